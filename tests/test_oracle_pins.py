@@ -1,0 +1,223 @@
+"""Pins of the CPU oracle to facts that do not come from the oracle itself:
+hand-worked examples, the published SplitMix64 outputs, exact-arithmetic brute
+force, set identities of the union over grids, permutation equivariance, and
+the all-in-one-cell reduction to brute force."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1409_8112_amd import workloads
+from tests.exact import check_csr, exact_pairs_within, pair_set
+
+
+def _load(golden_dir, name):
+    with open(os.path.join(golden_dir, name)) as f:
+        return json.load(f)
+
+
+# --- random numbers --------------------------------------------------------
+
+def test_splitmix64_published_outputs(golden_dir):
+    g = _load(golden_dir, "splitmix64.json")
+    for vec in g["vectors"]:
+        s = oracle.SplitMix64(vec["seed"])
+        got = [s.next() for _ in vec["outputs"]]
+        assert got == [int(x, 0) for x in vec["outputs"]]
+
+
+def test_uniform01_range_and_distribution():
+    from scipy import stats
+    s = oracle.SplitMix64(7)
+    x = np.array([s.uniform01() for _ in range(20000)])
+    assert np.all((x >= 0.0) & (x < 1.0))
+    assert stats.kstest(x, "uniform").pvalue > 1e-3
+    # 53-bit resolution: every value is an integer multiple of 2^-53
+    assert np.all(np.ldexp(x, 53) == np.floor(np.ldexp(x, 53)))
+
+
+def test_gaussian_pairs_are_standard_normal():
+    from scipy import stats
+    s = oracle.SplitMix64(11)
+    g = np.array([s.gaussian_pair() for _ in range(10000)])
+    assert stats.kstest(g[:, 0], "norm").pvalue > 1e-3
+    assert stats.kstest(g[:, 1], "norm").pvalue > 1e-3
+    assert abs(np.corrcoef(g[:, 0], g[:, 1])[0, 1]) < 0.05
+
+
+# --- transforms --------------------------------------------------------------
+
+@pytest.mark.parametrize("d", [1, 2, 3, 6, 9, 12, 33, 64])
+def test_rotations_orthonormal_and_shifts_in_unit_cube(d):
+    R, u = oracle.make_transforms(123, 4, d)
+    for t in range(4):
+        assert np.abs(R[t] @ R[t].T - np.eye(d)).max() <= 1e-13
+    assert np.all((u >= 0.0) & (u < 1.0))
+
+
+def test_transforms_deterministic_prefix_stable_and_shift_shared():
+    R5, u5 = oracle.make_transforms(99, 5, 6)
+    R3, u3 = oracle.make_transforms(99, 3, 6)
+    Rb, ub = oracle.make_transforms(99, 5, 6)
+    assert np.array_equal(R5, Rb) and np.array_equal(u5, ub)
+    assert np.array_equal(R5[:3], R3) and np.array_equal(u5[:3], u3)
+    Ri, ui = oracle.make_transforms(99, 5, 6, oracle.NO_ROTATE)
+    assert np.array_equal(ui, u5)  # the shift is drawn first, so both variants share it
+    assert np.array_equal(Ri, np.broadcast_to(np.eye(6), (5, 6, 6)))
+    R6, _ = oracle.make_transforms(100, 5, 6)
+    assert not np.array_equal(R6, R5)
+
+
+def test_rotation_first_row_uniform_on_sphere_d3():
+    """Haar orientation: each row of R is uniform on the sphere; for d = 3 a
+    coordinate of a uniform point on S^2 is uniform on [-1, 1] (Archimedes)."""
+    from scipy import stats
+    R, _ = oracle.make_transforms(2024, 3000, 3)
+    assert stats.kstest(R[:, 0, 0], stats.uniform(loc=-1, scale=2).cdf).pvalue > 1e-3
+    assert stats.kstest(R[:, 2, 1], stats.uniform(loc=-1, scale=2).cdf).pvalue > 1e-3
+    dets = np.linalg.det(R)
+    assert np.allclose(np.abs(dets), 1.0)
+    assert 0.4 < np.mean(dets > 0) < 0.6
+
+
+# --- hand-worked examples ----------------------------------------------------
+
+def test_hand_examples(golden_dir):
+    g = _load(golden_dir, "hand_examples.json")
+    for case in g["cases"]:
+        p = np.array(case["points"], dtype=np.float32)
+        R = np.array(case["R"], dtype=np.float64)
+        u = np.array(case["u"], dtype=np.float64)
+        c = case["alpha"] * case["r"]
+        kap = oracle.cell_coords(p, R, u, 1.0 / c)
+        assert kap.tolist() == case["kappa"], case["name"]
+        pairs = oracle.transform_pairs(p, case["r"], case["alpha"], R, u)
+        assert pairs.tolist() == case["pairs"], case["name"]
+        csr = oracle.rtg_with_transforms(p, case["r"], case["alpha"], R[None], u[None])
+        assert csr.upper_pairs().tolist() == case["pairs"], case["name"]
+        bf = oracle.bruteforce(p, case["r"]).upper_pairs()
+        assert bf.tolist() == case["bruteforce"], case["name"]
+
+
+# --- brute force -------------------------------------------------------------
+
+@pytest.mark.parametrize("d,n,r", [(1, 60, 0.05), (2, 120, 0.1), (3, 150, 0.2), (6, 120, 0.5),
+                                   (12, 80, 0.9)])
+def test_bruteforce_equals_exact_enumeration(d, n, r):
+    p = workloads.uniform_points(n, d, seed=d)
+    bf = oracle.bruteforce(p, r)
+    check_csr(bf.row_ptr, bf.col, n)
+    assert pair_set(bf.upper_pairs()) == exact_pairs_within(p, r)
+
+
+# --- one grid equals brute force over same-cell pairs ------------------------
+
+@pytest.mark.parametrize("d,n,r,alpha,rotate", [(1, 200, 0.05, 2.0, False), (2, 300, 0.08, 1.5, True),
+                                                (3, 300, 0.15, 2.0, True), (6, 200, 0.5, 1.2, True),
+                                                (12, 150, 1.0, 1.4, False), (12, 150, 1.0, 2.0, True)])
+def test_single_grid_equals_same_cell_bruteforce(d, n, r, alpha, rotate):
+    p = workloads.uniform_points(n, d, seed=100 + d)
+    R, u = oracle.make_transforms(5, 1, d, 0 if rotate else oracle.NO_ROTATE)
+    kap = oracle.cell_coords(p, R[0], u[0], 1.0 / (alpha * r))
+    within = exact_pairs_within(p, r)
+    expect = {(i, j) for (i, j) in within if np.array_equal(kap[i], kap[j])}
+    got = pair_set(oracle.transform_pairs(p, r, alpha, R[0], u[0]))
+    assert got == expect
+    assert len(expect) > 0
+
+
+# --- the union over grids ------------------------------------------------------
+
+def test_rtg_invariants_union_and_prefix():
+    n, d, r, k, alpha = 400, 3, 0.12, 5, 1.5
+    p = workloads.uniform_points(n, d, seed=3)
+    R, u = oracle.make_transforms(77, k + 1, d)
+    full = oracle.rtg_with_transforms(p, r, alpha, R[:k], u[:k])
+    check_csr(full.row_ptr, full.col, n)
+    S = pair_set(full.upper_pairs())
+    # precision 1: every reported pair is within r, in exact arithmetic
+    assert S <= exact_pairs_within(p, r)
+    # the union of the single grids
+    union = set()
+    for t in range(k):
+        union |= pair_set(oracle.transform_pairs(p, r, alpha, R[t], u[t]))
+    assert S == union
+    # one more grid never loses a pair
+    S1 = pair_set(oracle.rtg_with_transforms(p, r, alpha, R, u).upper_pairs())
+    assert S <= S1
+    # the seeded entry point draws the same transforms
+    seeded = oracle.rtg(p, r, k, alpha, 77)
+    assert np.array_equal(seeded.row_ptr, full.row_ptr) and np.array_equal(seeded.col, full.col)
+
+
+def test_upper_only_is_upper_triangle():
+    p = workloads.uniform_points(300, 2, seed=8)
+    sym = oracle.rtg(p, 0.1, 3, 2.0, 1)
+    up = oracle.rtg(p, 0.1, 3, 2.0, 1, oracle.UPPER_ONLY)
+    check_csr(up.row_ptr, up.col, 300, symmetric=False)
+    assert np.array_equal(up.upper_pairs(), sym.upper_pairs())
+    assert len(up.col) * 2 == len(sym.col)
+
+
+def test_permutation_equivariance():
+    n, d, r = 300, 3, 0.15
+    p = workloads.uniform_points(n, d, seed=4)
+    perm = np.random.default_rng(0).permutation(n)
+    a = pair_set(oracle.rtg(p, r, 4, 2.0, 9).upper_pairs())
+    b = pair_set(oracle.rtg(p[perm], r, 4, 2.0, 9).upper_pairs())
+    relabel = {tuple(sorted((int(perm[i]), int(perm[j])))) for i, j in b}
+    assert a == relabel
+
+
+def test_one_huge_cell_reduces_to_bruteforce():
+    """With c far larger than the point set and every shift away from a cell
+    face, all points share one cell, so one grid reports exactly the brute
+    force set."""
+    n, d, r = 250, 3, 0.2
+    p = workloads.uniform_points(n, d, seed=6)
+    R, u = oracle.make_transforms(0, 64, d)
+    t = next(t for t in range(64) if np.all((u[t] > 0.01) & (u[t] < 0.99)))
+    alpha = 1e4  # c = 2000: |R p| / c < 1e-3 for p in the unit cube
+    got = oracle.rtg_with_transforms(p, r, alpha, R[t:t + 1], u[t:t + 1])
+    bf = oracle.bruteforce(p, r)
+    assert np.array_equal(got.row_ptr, bf.row_ptr) and np.array_equal(got.col, bf.col)
+
+
+def test_coincident_points_are_reported_but_never_self_pairs():
+    p = np.array([[0.3, 0.3], [0.3, 0.3], [0.3, 0.3], [0.9, 0.9]], dtype=np.float32)
+    res = oracle.rtg(p, 0.01, 2, 2.0, 0)
+    assert pair_set(res.upper_pairs()) == {(0, 1), (0, 2), (1, 2)}
+    check_csr(res.row_ptr, res.col, 4)
+
+
+# --- argument handling -------------------------------------------------------
+
+def test_empty_and_single_point():
+    for n in (0, 1):
+        res = oracle.rtg(np.zeros((n, 3), np.float32), 0.1, 2, 2.0, 0)
+        assert res.row_ptr.tolist() == [0] * (n + 1) and len(res.col) == 0
+
+
+@pytest.mark.parametrize("bad", [
+    dict(d=0), dict(d=65), dict(k=0), dict(r=0.0), dict(r=-1.0), dict(r=float("nan")),
+    dict(r=float("inf")), dict(alpha=0.0), dict(alpha=float("nan")), dict(nanpoint=True),
+    dict(infpoint=True)])
+def test_invalid_arguments(bad):
+    d = bad.get("d", 3)
+    p = workloads.uniform_points(10, max(d, 1), seed=0)[:, :d] if d > 0 else np.zeros((10, 0), np.float32)
+    if bad.get("nanpoint"):
+        p[3, 1] = np.nan
+    if bad.get("infpoint"):
+        p[4, 0] = np.inf
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.rtg(p, bad.get("r", 0.1), bad.get("k", 2), bad.get("alpha", 2.0), 0)
+    assert e.value.code == oracle.EINVAL
+
+
+def test_out_of_range_cells():
+    p = np.array([[0.0, 0.0], [3e8, 0.0]], dtype=np.float32)  # y ~ 3e8 / 0.1 > 2^31
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.rtg(p, 0.05, 1, 2.0, 0, oracle.NO_ROTATE)
+    assert e.value.code == oracle.ERANGE
