@@ -1,0 +1,186 @@
+/*
+ * rtg.h -- all-pairs r-nearest-neighbours by randomly transformed grids (RTG)
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Kleinbort, Salzman & Halperin, "Efficient high-quality
+ * motion planning by fast all-pairs r-nearest-neighbors"):
+ *   given n points P in R^d and a radius r, report pairs p,q of P with
+ *   ||p - q|| <= r (the all-pairs r-NN query, Sec. I).  RTG answers it
+ *   approximately (Sec. III, Alg. "Randomly Shifted Grids" and its
+ *   random-orientation variant): for each of k grids of cell side alpha * r,
+ *   with a random orientation R_t and a uniform random shift u_t, every point
+ *   goes to the cell floor((R_t p) / (alpha r) + u_t); every pair of points in
+ *   a common cell is tested and reported when its distance is at most r; the
+ *   union over the k grids is reported once per pair (Sec. III-B).  The
+ *   paper's m is k here and its cell-size factor c~ is alpha.
+ *
+ * Exactness contract.  For given transforms the reported pair set is a
+ * deterministic function of the inputs and equals, bit for bit, the set that
+ * the FP64 definition gives: cells from FP64 arithmetic in a fixed order with
+ * no FMA, and the test s <= r*r where s sums ((double)p_l - (double)q_l)^2 in
+ * axis order.  The GPU screens pairs in FP32 and re-tests in that FP64 order
+ * every pair whose FP32 squared distance lies within a relative 2^-16 of r^2,
+ * so no decision differs from the FP64 one.
+ *
+ * Output.  A CSR neighbour list in device memory: row_ptr[n+1] (int64) and
+ * col[nnz] (int32); row i lists its neighbours in ascending order.  By default
+ * every pair is stored in both rows (the layout that answers multiple r-NN
+ * queries, Sec. III-B); with RTG_UPPER_ONLY row i holds only j > i.
+ *
+ * Conventions.  Every call returns an rtg_status.  Out-parameters are written
+ * only on RTG_OK.  Nothing throws across this interface.  Inputs stay owned by
+ * the caller.  Results are owned by the context until rtg_release (or
+ * rtg_destroy).  A context belongs to one device and one host thread, except
+ * that rtg_submit / rtg_poll / rtg_release may be called from any thread.
+ */
+#ifndef RTG_H
+#define RTG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rtg_status {
+  RTG_OK = 0,
+  RTG_EAGAIN = 1,   /* submitted request not finished yet                      */
+  RTG_EINVAL = -1,  /* bad argument (see each call)                            */
+  RTG_ENOMEM = -2,  /* the work does not fit the context's device-memory budget */
+  RTG_ERANGE = -3,  /* a cell coordinate |y| >= 2^31, r*r outside            */
+                    /* [2^-100, 2^120], or too few key bits for this alpha, d  */
+  RTG_EDEVICE = -4, /* a HIP call failed; the context is unusable             */
+  RTG_ENOENT = -5   /* unknown ticket or result handle                        */
+} rtg_status;
+
+enum {
+  RTG_NO_ROTATE = 1u, /* shift-only grids (the paper's first algorithm)         */
+  RTG_UPPER_ONLY = 2u /* store each pair once, in the row of its smaller index */
+};
+
+typedef struct rtg_ctx rtg_ctx;
+
+/* A device-resident neighbour list.  row_ptr and col point into the
+ * context's device memory and stay valid until rtg_release(handle). */
+typedef struct rtg_csr {
+  int64_t n;        /* rows                                         */
+  int64_t nnz;      /* entries in col                               */
+  int64_t *row_ptr; /* device, n+1 entries, row_ptr[0] = 0         */
+  int32_t *col;     /* device, nnz entries (NULL when nnz = 0)     */
+  uint64_t handle;  /* pass to rtg_release                          */
+  int64_t pairs;    /* unordered pairs reported (nnz/2 symmetric)  */
+} rtg_csr;
+
+/* One all-pairs query, for the batched and the request-loop entry points. */
+typedef struct rtg_query {
+  const float *points; /* device, row-major [n][d] FP32                */
+  int64_t n;
+  int32_t d;
+  double r;
+  int32_t k;
+  double alpha;
+  uint64_t seed;
+  uint32_t flags;
+} rtg_query;
+
+/* Counters of the last completed call on a context (for measurement). */
+typedef struct rtg_stats {
+  int64_t n, d, k;
+  int64_t point_transforms;  /* n * k                                          */
+  int64_t cells;             /* cells holding >= 2 points, summed over grids   */
+  int64_t tests;             /* same-cell pairs tested, summed over grids      */
+  int64_t candidates;        /* pairs within r before de-duplication           */
+  int64_t band_rechecks;     /* pairs re-tested in FP64                        */
+  int64_t unique_pairs;      /* unordered pairs reported                       */
+  int32_t key_bits;          /* bits of the sorted cell key                    */
+  int32_t key_passes;        /* radix passes over the cell keys                */
+  int32_t pair_bits;         /* bits of a packed (i,j) pair                    */
+  int32_t transforms_per_sort; /* grids grouped in one sort                    */
+  /* Device time per phase in milliseconds (0 unless timing is on). */
+  double ms_stage, ms_keys, ms_key_sort, ms_cells, ms_pairs, ms_pair_sort, ms_unique, ms_csr,
+      ms_total;
+} rtg_stats;
+
+/* Create a context on HIP device `device`.
+ *   arena / arena_bytes: device memory the context sub-allocates for scratch
+ *     and results.  If arena is NULL the context allocates arena_bytes itself
+ *     (hipMalloc) and frees them in rtg_destroy; otherwise the caller keeps
+ *     ownership and must keep the memory alive until rtg_destroy.
+ *     arena_bytes is the context's device-memory budget (RTG_ENOMEM beyond).
+ *   hip_stream: the hipStream_t all work is ordered on (NULL: the null stream).
+ * Errors: RTG_EINVAL (ctx NULL, arena_bytes < 1 MiB, bad device),
+ *         RTG_EDEVICE (HIP failure). */
+int rtg_create(rtg_ctx **ctx, int device, void *arena, size_t arena_bytes, void *hip_stream);
+
+/* Destroy a context: waits for outstanding work and frees every result. */
+int rtg_destroy(rtg_ctx *ctx);
+
+/* Blocking all-pairs r-NN by RTG (the paper's problem statement, Sec. I, with
+ * the grids of Sec. III).
+ *   points: device pointer, row-major [n][d] FP32, 4-byte aligned.
+ *   n in [0, 2^31); d in [1, 64]; r > 0 finite; k >= 1; alpha > 0 finite.
+ *   seed selects the k transforms (see rtg_make_transforms).
+ *   flags: RTG_NO_ROTATE, RTG_UPPER_ONLY.
+ * n <= 1 gives an empty list.  Errors: RTG_EINVAL (also for NaN/Inf
+ * coordinates), RTG_ERANGE, RTG_ENOMEM, RTG_EDEVICE. */
+int rtg_all_pairs(rtg_ctx *ctx, const float *points, int64_t n, int32_t d, double r, int32_t k,
+                  double alpha, uint64_t seed, uint32_t flags, rtg_csr *out);
+
+/* As rtg_all_pairs with caller-given transforms: R is host [k][d][d] FP64
+ * (row j maps p to (R p)_j), u is host [k][d] FP64 shifts in cell units.
+ * RTG_NO_ROTATE is ignored here (R is used as given). */
+int rtg_all_pairs_with_transforms(rtg_ctx *ctx, const float *points, int64_t n, int32_t d,
+                                  double r, int32_t k, double alpha, const double *R,
+                                  const double *u, uint32_t flags, rtg_csr *out);
+
+/* Many independent queries in one pass of the pipeline: every (query, grid)
+ * pair is one segment of a shared key space, so each kernel launch covers all
+ * queries.  outs[q] receives query q's list, identical to what rtg_all_pairs
+ * returns for it alone.  On error no result is kept.  Errors as
+ * rtg_all_pairs, for any query. */
+int rtg_all_pairs_batched(rtg_ctx *ctx, const rtg_query *queries, int32_t nq, rtg_csr *outs);
+
+/* Request loop (continuous batching).  rtg_submit copies the query's points
+ * into the context before it returns (the caller may reuse its buffer) and
+ * hands back a ticket; a scheduler thread admits requests while their device
+ * memory fits the budget and runs every admitted request in the next pass of
+ * the batched pipeline.  rtg_poll returns RTG_OK with the result once done
+ * (the result then belongs to the caller's handle), RTG_EAGAIN while pending,
+ * or the request's error.  Errors: RTG_EINVAL, RTG_ENOMEM (larger than the
+ * whole budget), RTG_ENOENT (unknown ticket). */
+int rtg_submit(rtg_ctx *ctx, const rtg_query *query, uint64_t *ticket);
+int rtg_poll(rtg_ctx *ctx, uint64_t ticket, rtg_csr *out);
+
+/* Free a result's device memory.  Errors: RTG_ENOENT. */
+int rtg_release(rtg_ctx *ctx, uint64_t handle);
+
+/* The k seeded transforms, on the host: R [k][d][d] FP64 with orthonormal rows
+ * (identity with RTG_NO_ROTATE), u [k][d] FP64 in [0,1).  Transform t draws
+ * from the SplitMix64 stream (Steele, Lea & Flood 2014) started at the
+ * (t+1)-th output of `seed`: first the d shifts (top 53 bits / 2^53), then
+ * d*d standard normals in row-major pairs (Marsaglia's polar method) whose
+ * rows are orthonormalised in index order by modified Gram-Schmidt applied
+ * twice.  A Gaussian matrix orthonormalised so is Haar distributed on O(d),
+ * the "random orientation" of Sec. III.  Errors: RTG_EINVAL. */
+int rtg_make_transforms(uint64_t seed, int32_t k, int32_t d, uint32_t flags, double *R, double *u);
+
+/* Turn per-phase device timing (HIP events on the context's stream) on or off. */
+int rtg_set_timing(rtg_ctx *ctx, int on);
+
+/* Counters of the last completed rtg_all_pairs* call. */
+int rtg_get_stats(const rtg_ctx *ctx, rtg_stats *out);
+
+/* Stage check: the integer cell coordinates floor((R_t p)/(alpha r) + u_t)
+ * computed by the key kernel for transform t, written to host kappa
+ * [n][d] (int64).  R [d][d], u [d] host FP64.  Same errors as rtg_all_pairs. */
+int rtg_debug_cell_coords(rtg_ctx *ctx, const float *points, int64_t n, int32_t d, double r,
+                          double alpha, const double *R, const double *u, int64_t *kappa);
+
+const char *rtg_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTG_H */

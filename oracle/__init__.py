@@ -65,6 +65,9 @@ def lib() -> ctypes.CDLL:
         L.oracle_rtg.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
                                  ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
                                  ctypes.c_uint32, resp]
+        L.oracle_rtg_rows.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
+                                      ctypes.c_int32, ctypes.c_double, f64p, f64p, i64p,
+                                      ctypes.c_int64, resp]
         L.oracle_bruteforce.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
                                         ctypes.c_uint32, resp]
         L.oracle_result_free.argtypes = [ctypes.POINTER(_Result)]
@@ -72,7 +75,8 @@ def lib() -> ctypes.CDLL:
         L.oracle_free.argtypes = [ctypes.c_void_p]
         L.oracle_free.restype = None
         for name in ("oracle_make_transforms", "oracle_cell_coords", "oracle_transform_pairs",
-                     "oracle_rtg_with_transforms", "oracle_rtg", "oracle_bruteforce"):
+                     "oracle_rtg_with_transforms", "oracle_rtg", "oracle_rtg_rows",
+                     "oracle_bruteforce"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -207,6 +211,27 @@ def rtg(points, r: float, k: int, alpha: float, seed: int, flags: int = 0) -> CS
     if rc != OK:
         raise OracleError(rc, "oracle_rtg")
     return _take_result(res)
+
+
+def rtg_rows(points, r: float, alpha: float, R, u, rows) -> list[np.ndarray]:
+    """Neighbour lists (ascending int32) of the given rows of the symmetric RTG
+    output, each computed on its own."""
+    p = _points(points)
+    n, d = p.shape
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    k = R.shape[0]
+    if R.shape != (k, d, d) or u.shape != (k, d):
+        raise ValueError("R must be [k,d,d] and u [k,d]")
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    res = ctypes.POINTER(_Result)()
+    rc = lib().oracle_rtg_rows(_ptr(p, ctypes.c_float), n, d, float(r), k, float(alpha),
+                               _ptr(R, ctypes.c_double), _ptr(u, ctypes.c_double),
+                               _ptr(rows, ctypes.c_int64), len(rows), ctypes.byref(res))
+    if rc != OK:
+        raise OracleError(rc, "oracle_rtg_rows")
+    csr = _take_result(res)
+    return [csr.col[csr.row_ptr[s]:csr.row_ptr[s + 1]] for s in range(len(rows))]
 
 
 def bruteforce(points, r: float, flags: int = 0) -> CSR:

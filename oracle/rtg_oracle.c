@@ -407,6 +407,49 @@ int oracle_rtg(const float *points, int64_t n, int32_t d, double r, int32_t k,
   return rc;
 }
 
+int oracle_rtg_rows(const float *points, int64_t n, int32_t d, double r,
+                    int32_t k, double alpha, const double *R, const double *u,
+                    const int64_t *rows, int64_t nrows, oracle_result **out) {
+  pair_vec pv = {NULL, 0, 0};
+  int64_t *kappa = NULL;
+  int64_t q, s;
+  int32_t t;
+  int rc = check_points(points, n, d);
+  if (rc == ORACLE_OK) rc = check_radius(r);
+  if (rc == ORACLE_OK && (k < 1 || !(isfinite(alpha) && alpha > 0.0) || nrows < 0))
+    rc = ORACLE_EINVAL;
+  for (s = 0; rc == ORACLE_OK && s < nrows; ++s)
+    if (rows[s] < 0 || rows[s] >= n) rc = ORACLE_EINVAL;
+  if (rc != ORACLE_OK) return rc;
+  if (n >= 2 && nrows > 0) {
+    double r2 = r * r;
+    double inv_c = 1.0 / (alpha * r);
+    kappa = (int64_t *)malloc(sizeof(int64_t) * (size_t)n * (size_t)d);
+    if (kappa == NULL) return ORACLE_ENOMEM;
+    for (t = 0; t < k; ++t) {
+      rc = oracle_cell_coords(points, n, d, R + (size_t)t * d * d,
+                              u + (size_t)t * d, inv_c, kappa);
+      if (rc != ORACLE_OK) goto fail;
+      for (s = 0; s < nrows; ++s)
+        for (q = 0; q < n; ++q)
+          if (q != rows[s] && same_cell(kappa, d, rows[s], q) &&
+              within_r(points, d, rows[s], q, r2)) {
+            rc = pv_push(&pv, s, q); /* (output row, neighbour) */
+            if (rc != ORACLE_OK) goto fail;
+          }
+    }
+  }
+  sort_unique(&pv); /* a neighbour found by several grids is kept once */
+  rc = make_csr(&pv, nrows, ORACLE_UPPER_ONLY, out);
+  free(kappa);
+  free(pv.v);
+  return rc;
+fail:
+  free(kappa);
+  free(pv.v);
+  return rc;
+}
+
 int oracle_bruteforce(const float *points, int64_t n, int32_t d, double r,
                       uint32_t flags, oracle_result **out) {
   pair_vec pv = {NULL, 0, 0};

@@ -112,6 +112,14 @@ int oracle_rtg(const float *points, int64_t n, int32_t d, double r, int32_t k,
                double alpha, uint64_t seed, uint32_t flags,
                oracle_result **out);
 
+/* The rows `rows[0..nrows)` of the symmetric RTG neighbour list, computed one
+ * by one: q is a neighbour of row s iff q != s, some transform puts q and s
+ * in the same cell, and ||q - s|| <= r.  Same transforms as
+ * oracle_rtg_with_transforms; result rows follow the order of `rows`. */
+int oracle_rtg_rows(const float *points, int64_t n, int32_t d, double r,
+                    int32_t k, double alpha, const double *R, const double *u,
+                    const int64_t *rows, int64_t nrows, oracle_result **out);
+
 /* Exact all-pairs r-NN by testing every pair (the set RTG approximates). */
 int oracle_bruteforce(const float *points, int64_t n, int32_t d, double r,
                       uint32_t flags, oracle_result **out);

@@ -1,0 +1,846 @@
+// rtg_host.cpp -- host side of the RTG library: C-ABI, context, device-memory
+// arena, transform generator, key-packing plan and the pipeline that drives
+// the gfx950 kernels (rtg_kernels.hip).
+#include "../../include/rtg.h"
+#include "rtg_internal.h"
+#include "rtg_runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using namespace rtgk;
+
+namespace rtg {
+
+// ---------------------------------------------------------------------------
+// transforms: SplitMix64 (Steele, Lea & Flood 2014) streams, uniform shifts,
+// Gaussian rows by Marsaglia's polar method, rows orthonormalised by modified
+// Gram-Schmidt applied twice.
+
+namespace {
+
+struct SplitMix64 {
+  uint64_t state;
+  uint64_t next() {
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  double unit() { return (double)(next() >> 11) * 0x1p-53; }
+};
+
+void polar_normals(SplitMix64& g, double* out2) {
+  for (;;) {
+    const double a = 2.0 * g.unit() - 1.0;
+    const double b = 2.0 * g.unit() - 1.0;
+    const double s = a * a + b * b;
+    if (s < 1.0 && s != 0.0) {
+      const double f = std::sqrt(-2.0 * std::log(s) / s);
+      out2[0] = a * f;
+      out2[1] = b * f;
+      return;
+    }
+  }
+}
+
+}  // namespace
+
+int make_transforms(uint64_t seed, int32_t k, int32_t d, uint32_t flags, double* R, double* u) {
+  if (k < 1 || d < 1 || d > kMaxDim || !R || !u) return RTG_EINVAL;
+  std::vector<double> gauss((size_t)d * d + 1);
+  SplitMix64 parent{seed};
+  for (int32_t t = 0; t < k; ++t) {
+    SplitMix64 g{parent.next()};  // stream t starts at the (t+1)-th output of seed
+    double* ut = u + (size_t)t * d;
+    double* Rt = R + (size_t)t * d * d;
+    for (int32_t j = 0; j < d; ++j) ut[j] = g.unit();
+    if (flags & RTG_NO_ROTATE) {
+      for (int32_t a = 0; a < d; ++a)
+        for (int32_t b = 0; b < d; ++b) Rt[(size_t)a * d + b] = (a == b) ? 1.0 : 0.0;
+      continue;
+    }
+    const int32_t dd = d * d;
+    for (int32_t e = 0; e < dd; e += 2) polar_normals(g, &gauss[e]);
+    for (int32_t row = 0; row < d; ++row) {
+      double* v = &gauss[(size_t)row * d];
+      for (int sweep = 0; sweep < 2; ++sweep) {
+        for (int32_t prev = 0; prev < row; ++prev) {
+          const double* q = Rt + (size_t)prev * d;
+          double dot = 0.0;
+          for (int32_t l = 0; l < d; ++l) dot = dot + v[l] * q[l];
+          for (int32_t l = 0; l < d; ++l) v[l] = v[l] - dot * q[l];
+        }
+      }
+      double nrm2 = 0.0;
+      for (int32_t l = 0; l < d; ++l) nrm2 = nrm2 + v[l] * v[l];
+      const double nrm = std::sqrt(nrm2);
+      if (!(nrm > 0.0)) return RTG_ERANGE;
+      for (int32_t l = 0; l < d; ++l) Rt[(size_t)row * d + l] = v[l] / nrm;
+    }
+  }
+  return RTG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// arena
+
+Arena::Arena(char* base, size_t bytes) {
+  const uintptr_t b = reinterpret_cast<uintptr_t>(base);
+  const uintptr_t a = (b + kAlign - 1) & ~(uintptr_t)(kAlign - 1);
+  base_ = reinterpret_cast<char*>(a);
+  size_ = bytes > (a - b) ? (bytes - (a - b)) & ~(size_t)(kAlign - 1) : 0;
+  if (size_) free_[0] = size_;
+}
+
+void* Arena::alloc(size_t bytes) {
+  bytes = std::max<size_t>(bytes, 1);
+  bytes = (bytes + kAlign - 1) & ~(size_t)(kAlign - 1);
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second < bytes) continue;
+    const size_t off = it->first, rem = it->second - bytes;
+    free_.erase(it);
+    if (rem) free_[off + bytes] = rem;
+    used_[off] = bytes;
+    in_use_ += bytes;
+    peak_ = std::max(peak_, in_use_);
+    return base_ + off;
+  }
+  return nullptr;
+}
+
+void Arena::release(void* p) {
+  if (!p) return;
+  const size_t off = (size_t)(static_cast<char*>(p) - base_);
+  auto u = used_.find(off);
+  if (u == used_.end()) return;
+  size_t start = off, len = u->second;
+  in_use_ -= len;
+  used_.erase(u);
+  auto next = free_.lower_bound(start);
+  if (next != free_.end() && start + len == next->first) {
+    len += next->second;
+    free_.erase(next);
+  }
+  auto prev = free_.lower_bound(start);
+  if (prev != free_.begin()) {
+    --prev;
+    if (prev->first + prev->second == start) {
+      start = prev->first;
+      len += prev->second;
+      free_.erase(prev);
+    }
+  }
+  free_[start] = len;
+}
+
+size_t Arena::largest_free() const {
+  size_t m = 0;
+  for (auto& f : free_) m = std::max(m, f.second);
+  return m;
+}
+
+// ---------------------------------------------------------------------------
+// helpers
+
+namespace {
+
+int ceil_log2(uint64_t x) {
+  int b = 0;
+  while (b < 64 && (1ull << b) < x) ++b;
+  return b;
+}
+
+// FP32 thresholds of the screen: lo <= r2 (1 - 2^-16) <= r2 (1 + 2^-16) <= hi.
+// The FP32 sum of d <= 64 squared FP32 differences is within a relative
+// (d + 2) 2^-24 < 2^-17.9 of the exact value, and the FP64 sum within
+// (d + 2) 2^-53, so a value at or below lo is within r in FP64 and a value
+// above hi is not; only the band between is re-tested in FP64.
+PairTest make_pair_test(double r2, int pair_bits) {
+  PairTest t;
+  const double lo_d = r2 * (1.0 - 0x1p-16);
+  float lo = (float)lo_d;
+  if ((double)lo > lo_d) lo = std::nextafter(lo, -INFINITY);
+  const double hi_d = r2 * (1.0 + 0x1p-16);
+  float hi = (float)hi_d;
+  if ((double)hi < hi_d) hi = std::nextafter(hi, INFINITY);
+  t.lo = lo;
+  t.hi = hi;
+  t.r2 = r2;
+  t.pair_bits = pair_bits;
+  return t;
+}
+
+float decode_order(uint32_t e) {
+  const uint32_t b = (e & 0x80000000u) ? (e & 0x7FFFFFFFu) : ~e;
+  float f;
+  std::memcpy(&f, &b, 4);
+  return f;
+}
+
+}  // namespace
+
+// Smallest field width b >= 1 such that two points whose cells coincide in
+// the low b bits of some axis but differ on that axis are more than r apart:
+// they differ by >= 2^b cells, so ||p - q|| >= (2^b - 1 - eps) alpha r with
+// eps < 1e-3 covering FP64 rounding of y for |y| < 2^31; (2^b - 1.001) alpha
+// >= 1.001 then puts them beyond r with margin, and such pairs are rejected.
+int min_field_bits(double alpha) {
+  for (int b = 1; b <= 32; ++b)
+    if ((std::ldexp(1.0, b) - 1.001) * alpha >= 1.001) return b;
+  return 33;
+}
+
+int plan_packing(int d, int k, const double* R, const double* u, double inv_c, double alpha,
+                 const float* lo, const float* hi, int64_t n, size_t budget_bytes, Packing& P) {
+  std::vector<int> need(d, 1);
+  P.klo.assign((size_t)k * d, 0);
+  for (int t = 0; t < k; ++t) {
+    for (int j = 0; j < d; ++j) {
+      const double* Rj = R + ((size_t)t * d + j) * d;
+      double zlo = 0.0, zhi = 0.0;
+      for (int l = 0; l < d; ++l) {
+        const double a = Rj[l] * (double)lo[l], b = Rj[l] * (double)hi[l];
+        zlo += std::min(a, b);
+        zhi += std::max(a, b);
+      }
+      const double ylo = zlo * inv_c + u[(size_t)t * d + j];
+      const double yhi = zhi * inv_c + u[(size_t)t * d + j];
+      int bits = 32;
+      int64_t klo = 0;
+      if (std::fabs(ylo) < 0x1p31 && std::fabs(yhi) < 0x1p31) {
+        // one cell of slack on each side covers the rounding of y
+        klo = (int64_t)std::floor(ylo) - 1;
+        const int64_t khi = (int64_t)std::floor(yhi) + 1;
+        bits = std::max(1, ceil_log2((uint64_t)(khi - klo + 1)));
+      }
+      P.klo[(size_t)t * d + j] = klo;
+      need[j] = std::max(need[j], std::min(bits, 32));
+    }
+  }
+  const int bmin = min_field_bits(alpha);
+  if (bmin > 32) return RTG_ERANGE;
+  for (int j = 0; j < d; ++j) need[j] = std::max(need[j], bmin);
+
+  // Grids per sort: as many as the key bits, the 32-bit element index of
+  // the sort and the memory budget allow.
+  int tb = k;
+  for (;;) {
+    const int seg_bits = tb > 1 ? ceil_log2((uint64_t)tb) : 0;
+    const int avail = 64 - seg_bits;
+    std::vector<int> b = need;
+    int total = 0;
+    for (int j = 0; j < d; ++j) total += b[j];
+    // Narrow the widest fields first, never below bmin.
+    while (total > avail) {
+      int jw = -1;
+      for (int j = 0; j < d; ++j)
+        if (b[j] > bmin && (jw < 0 || b[j] > b[jw])) jw = j;
+      if (jw < 0) break;
+      --b[jw];
+      --total;
+    }
+    const uint64_t elems = (uint64_t)n * (uint64_t)tb;
+    const size_t bytes = (size_t)elems * 28;  // two key/value buffers + cells
+    const bool fits = total <= avail && elems < (1ull << 32) && (bytes <= budget_bytes || tb == 1);
+    if (fits) {
+      P.tb = tb;
+      P.seg_bits = seg_bits;
+      P.layout.d = d;
+      P.layout.cell_bits = total;
+      int sh = 0;
+      P.truncated = false;
+      for (int j = 0; j < d; ++j) {
+        P.layout.shift[j] = (uint8_t)sh;
+        P.layout.bits[j] = (uint8_t)b[j];
+        if (b[j] < need[j]) P.truncated = true;
+        sh += b[j];
+      }
+      P.key_bits = total + seg_bits;
+      return RTG_OK;
+    }
+    if (tb == 1) return total > avail ? RTG_ERANGE : RTG_ENOMEM;
+    tb = (tb + 1) / 2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// context
+
+Ctx::Ctx(int dev, hipStream_t s) : device(dev), stream(s) {}
+
+Ctx::~Ctx() {
+  if (host_stage) (void)hipHostFree(host_stage);
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (own_arena && arena_mem) (void)hipFree(arena_mem);
+}
+
+int Ctx::hip_fail(hipError_t e, const char* what) {
+  if (e == hipSuccess) return RTG_OK;
+  std::fprintf(stderr, "rtg: %s failed: %s\n", what, hipGetErrorString(e));
+  poisoned = true;
+  return RTG_EDEVICE;
+}
+
+void* Ctx::dalloc(size_t bytes) { return arena->alloc(bytes); }
+void Ctx::dfree(void* p) { arena->release(p); }
+
+int Ctx::sync() { return hip_fail(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
+
+int Ctx::read_back(const void* dev, size_t bytes, void* host) {
+  hipError_t e = hipMemcpyAsync(host_stage, dev, bytes, hipMemcpyDeviceToHost, stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync D2H");
+  int rc = sync();
+  if (rc) return rc;
+  std::memcpy(host, host_stage, bytes);
+  return RTG_OK;
+}
+
+int Ctx::upload(void* dev, const void* host, size_t bytes) {
+  return hip_fail(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, stream),
+                  "hipMemcpyAsync H2D");
+}
+
+void Ctx::mark(int phase) {
+  if (timing) (void)hipEventRecord(ev[phase], stream);
+}
+
+uint64_t Ctx::keep_result(void* mem, int64_t n, int64_t nnz, int64_t* row_ptr, int32_t* col) {
+  const uint64_t h = next_handle++;
+  results[h] = Result{mem, n, nnz, row_ptr, col};
+  return h;
+}
+
+int Ctx::release(uint64_t h) {
+  auto it = results.find(h);
+  if (it == results.end()) return RTG_ENOENT;
+  dfree(it->second.mem);
+  results.erase(it);
+  return RTG_OK;
+}
+
+// Device-side validity of a caller pointer: it must be device memory (or
+// memory the device can address) of this context's device.
+int check_device_pointer(const void* p, int device) {
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return RTG_EINVAL;
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged) return RTG_EINVAL;
+  if (attr.type == hipMemoryTypeDevice && attr.device != device) return RTG_EINVAL;
+  return RTG_OK;
+}
+
+int validate_query(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha) {
+  if (d < 1 || d > kMaxDim || k < 1 || n < 0 || n >= (int64_t(1) << 31)) return RTG_EINVAL;
+  if (!std::isfinite(r) || !(r > 0.0) || !std::isfinite(alpha) || !(alpha > 0.0)) return RTG_EINVAL;
+  if (n > 0 && (!points || (reinterpret_cast<uintptr_t>(points) & 3u))) return RTG_EINVAL;
+  return RTG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the plain pipeline
+
+namespace {
+
+// Frees every arena block taken through it when it goes out of scope.
+struct Scratch {
+  Ctx& c;
+  std::vector<void*> held;
+  explicit Scratch(Ctx& ctx) : c(ctx) {}
+  ~Scratch() {
+    for (void* p : held) c.dfree(p);
+  }
+  template <class T>
+  T* get(size_t count) {
+    void* p = c.dalloc(std::max<size_t>(count, 1) * sizeof(T));
+    if (p) held.push_back(p);
+    return static_cast<T*>(p);
+  }
+  void drop(void* p) {
+    auto it = std::find(held.begin(), held.end(), p);
+    if (it != held.end()) {
+      c.dfree(p);
+      held.erase(it);
+    }
+  }
+};
+
+}  // namespace
+
+int Ctx::make_empty_result(int64_t n, rtg_csr* out) {
+  void* mem = dalloc(sizeof(int64_t) * (size_t)(n + 1));
+  if (!mem) return RTG_ENOMEM;
+  launch_fill_u64(static_cast<uint64_t*>(mem), 0ull, (size_t)(n + 1), stream);
+  int rc = sync();
+  if (rc) {
+    dfree(mem);
+    return rc;
+  }
+  out->n = n;
+  out->nnz = 0;
+  out->row_ptr = static_cast<int64_t*>(mem);
+  out->col = nullptr;
+  out->pairs = 0;
+  out->handle = keep_result(mem, n, 0, out->row_ptr, nullptr);
+  return RTG_OK;
+}
+
+int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha,
+                   const double* R, const double* u, uint32_t flags, rtg_csr* out) {
+  if (poisoned) return RTG_EDEVICE;
+  int rc = validate_query(points, n, d, r, k, alpha);
+  if (rc) return rc;
+  if (n > 0 && check_device_pointer(points, device)) return RTG_EINVAL;
+  const double r2 = r * r;
+  if (!(r2 >= 0x1p-100 && r2 <= 0x1p120)) return RTG_ERANGE;
+
+  rtg_stats st{};
+  st.n = n;
+  st.d = d;
+  st.k = k;
+  st.point_transforms = n * k;
+  if (n <= 1) {
+    // Still reject non-finite coordinates, as for any other n.
+    if (n == 1) {
+      std::vector<float> h(d);
+      if (hip_fail(hipMemcpy(h.data(), points, sizeof(float) * d, hipMemcpyDeviceToHost), "copy"))
+        return RTG_EDEVICE;
+      for (float v : h)
+        if (!std::isfinite(v)) return RTG_EINVAL;
+    }
+    rc = make_empty_result(n, out);
+    if (!rc) stats = st;
+    return rc;
+  }
+
+  Scratch S(*this);
+  const double c = alpha * r;
+  const double inv_c = 1.0 / c;
+  const int pair_bits = std::max(1, ceil_log2((uint64_t)n));
+  const PairTest ptest = make_pair_test(r2, pair_bits);
+
+  mark(0);
+  // --- stage ---------------------------------------------------------------
+  float* soa = S.get<float>((size_t)n * d);
+  uint32_t* flags_dev = S.get<uint32_t>(2 + 2 * kMaxDim);  // [0] bad, [1] err, bbox
+  double* Rd = S.get<double>((size_t)k * d * d);
+  double* ud = S.get<double>((size_t)k * d);
+  unsigned long long* counters = S.get<unsigned long long>(4);  // cand, rechecks, next item
+  if (!soa || !flags_dev || !Rd || !ud || !counters) return RTG_ENOMEM;
+  uint32_t* bad = flags_dev;
+  uint32_t* err = flags_dev + 1;
+  uint32_t* bbox = flags_dev + 2;
+  if ((rc = upload(Rd, R, sizeof(double) * (size_t)k * d * d))) return rc;
+  if ((rc = upload(ud, u, sizeof(double) * (size_t)k * d))) return rc;
+  launch_stage_init(bad, bbox, d, stream);
+  launch_fill_u32(err, 0u, 1, stream);
+  launch_fill_u64(reinterpret_cast<uint64_t*>(counters), 0ull, 4, stream);
+  launch_stage(points, n, d, soa, bad, bbox, stream);
+  mark(1);
+  std::vector<uint32_t> hb(2 + 2 * kMaxDim);
+  if ((rc = read_back(flags_dev, sizeof(uint32_t) * (2 + 2 * d), hb.data()))) return rc;
+  if (hb[0]) return RTG_EINVAL;
+  std::vector<float> lo(d), hi(d);
+  for (int j = 0; j < d; ++j) {
+    lo[j] = decode_order(hb[2 + 2 * j]);
+    hi[j] = decode_order(hb[3 + 2 * j]);
+  }
+
+  Packing P;
+  rc = plan_packing(d, k, R, u, inv_c, alpha, lo.data(), hi.data(), n, arena->largest_free() / 2,
+                    P);
+  if (rc) return rc;
+  st.key_bits = P.key_bits;
+  st.key_passes = (P.key_bits + kRadixBits - 1) / kRadixBits;
+  st.pair_bits = 2 * pair_bits;
+  st.transforms_per_sort = P.tb;
+
+  KeyLayout* layout_d = S.get<KeyLayout>(1);
+  int64_t* klo_d = S.get<int64_t>((size_t)k * d);
+  if (!layout_d || !klo_d) return RTG_ENOMEM;
+  if ((rc = upload(layout_d, &P.layout, sizeof(KeyLayout)))) return rc;
+  if ((rc = upload(klo_d, P.klo.data(), sizeof(int64_t) * (size_t)k * d))) return rc;
+
+  // --- per group of grids: keys, sort, cells, pairs ---------------------------
+  const size_t NB = (size_t)n * (size_t)P.tb;
+  uint64_t* keys = S.get<uint64_t>(NB);
+  uint64_t* keys_alt = S.get<uint64_t>(NB);
+  uint32_t* vals = S.get<uint32_t>(NB);
+  uint32_t* vals_alt = S.get<uint32_t>(NB);
+  const size_t ntiles = (NB + kTile - 1) / kTile;
+  uint32_t* radix_scr = S.get<uint32_t>(std::max(radix_scratch_elems(NB), 4 * ntiles + 8));
+  const size_t max_cells = NB / 2 + 1;
+  uint32_t* cstart = S.get<uint32_t>(max_cells);
+  uint32_t* cend = S.get<uint32_t>(max_cells);
+  uint64_t* items = S.get<uint64_t>(max_cells);
+  uint64_t* tests = S.get<uint64_t>(max_cells);
+  uint64_t* scan64 = S.get<uint64_t>(scan_scratch_elems(max_cells) + 4);
+  if (!keys || !keys_alt || !vals || !vals_alt || !radix_scr || !cstart || !cend || !items ||
+      !tests || !scan64)
+    return RTG_ENOMEM;
+
+  uint64_t cap = 0;
+  uint64_t* cand = nullptr;
+  uint64_t cand_total = 0;  // exact number of candidates so far
+
+  for (int t0 = 0; t0 < k; t0 += P.tb) {
+    const int tb = std::min(P.tb, k - t0);
+    const size_t N = (size_t)n * tb;
+    launch_keys(soa, n, d, t0, tb, Rd, ud, inv_c, klo_d, layout_d, keys, vals, err, stream);
+    mark(2);
+    const int where = radix_sort(keys, vals, keys_alt, vals_alt, N, 0, P.key_bits, radix_scr,
+                                 stream);
+    const uint64_t* skeys = where ? keys_alt : keys;
+    const uint32_t* sidx = where ? vals_alt : vals;
+    mark(3);
+    // cells with >= 2 points
+    const size_t nt = (N + kTile - 1) / kTile;
+    uint32_t* hcnt = radix_scr;
+    uint32_t* tcnt = radix_scr + nt;
+    uint32_t* tot = radix_scr + 2 * nt;  // [0] heads, [1] tails
+    uint32_t* sscr = radix_scr + 2 * nt + 2;
+    launch_run_count(skeys, N, hcnt, tcnt, stream);
+    scan_exclusive_u32(hcnt, hcnt, nt, tot, sscr, stream);
+    scan_exclusive_u32(tcnt, tcnt, nt, tot + 1, sscr, stream);
+    launch_run_write(skeys, N, hcnt, tcnt, cstart, cend, stream);
+    uint32_t ncells_h = 0, errh0 = 0;
+    if ((rc = read_back(tot, sizeof(uint32_t), &ncells_h))) return rc;
+    // A cell coordinate out of range makes the grouping meaningless: stop
+    // before the pair kernel sees it.
+    if ((rc = read_back(err, sizeof(uint32_t), &errh0))) return rc;
+    if (errh0) return RTG_ERANGE;
+    uint64_t totals[2] = {0, 0};  // items, tests
+    if (ncells_h) {
+      launch_cell_work(cstart, cend, tot, items, tests, ncells_h, stream);
+      scan_exclusive_u64(items, items, ncells_h, scan64 + scan_scratch_elems(max_cells), scan64,
+                         stream);
+      scan_exclusive_u64(tests, tests, ncells_h, scan64 + scan_scratch_elems(max_cells) + 1,
+                         scan64, stream);
+      if ((rc = read_back(scan64 + scan_scratch_elems(max_cells), sizeof(totals), totals)))
+        return rc;
+    }
+    mark(4);
+    st.cells += ncells_h;
+    st.tests += (int64_t)totals[1];
+    if (totals[0] == 0) continue;
+
+    // Room for this group's pairs: a guess first, the exact count on overflow.
+    uint64_t want = cand_total + std::min<uint64_t>(totals[1], std::max<uint64_t>(1u << 20, totals[1] / 16));
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      if (want > cap) {
+        uint64_t* grown = static_cast<uint64_t*>(dalloc(sizeof(uint64_t) * want));
+        if (!grown) return RTG_ENOMEM;
+        if (cand && cand_total)
+          if ((rc = hip_fail(hipMemcpyAsync(grown, cand, sizeof(uint64_t) * cand_total,
+                                            hipMemcpyDeviceToDevice, stream),
+                             "grow candidates")))
+            return rc;
+        if (cand) S.drop(cand);
+        S.held.push_back(grown);
+        cand = grown;
+        cap = want;
+      }
+      launch_fill_u64(reinterpret_cast<uint64_t*>(counters), cand_total, 1, stream);
+      launch_cell_pairs(points, d, sidx, cstart, cend, items, tot, totals[0], ptest, cand, cap,
+                        counters, counters + 1, counters + 2, stream);
+      unsigned long long now = 0;
+      if ((rc = read_back(counters, sizeof(now), &now))) return rc;
+      if (now <= cap) {
+        cand_total = now;
+        break;
+      }
+      want = now;
+      if (attempt == 1) return RTG_ENOMEM;
+    }
+    mark(5);
+  }
+  uint32_t errh = 0;
+  unsigned long long rech = 0;
+  if ((rc = read_back(err, sizeof(errh), &errh))) return rc;
+  if (errh) return RTG_ERANGE;
+  if ((rc = read_back(counters + 1, sizeof(rech), &rech))) return rc;
+  st.band_rechecks = (int64_t)rech;
+  st.candidates = (int64_t)cand_total;
+
+  // Key buffers are no longer needed.
+  S.drop(keys);
+  S.drop(keys_alt);
+  S.drop(vals);
+  S.drop(vals_alt);
+  S.drop(cstart);
+  S.drop(cend);
+  S.drop(items);
+  S.drop(tests);
+
+  // --- union: sort the packed pairs and drop repeats -------------------------
+  const size_t C = cand_total;
+  uint64_t* uniq = nullptr;
+  size_t U = 0;
+  if (C > 0) {
+    if (C >= (1ull << 32)) return RTG_ENOMEM;
+    uint64_t* cand_alt = S.get<uint64_t>(C);
+    uint32_t* scr = S.get<uint32_t>(radix_scratch_elems(C) + 16);
+    if (!cand_alt || !scr) return RTG_ENOMEM;
+    const int where = radix_sort(cand, nullptr, cand_alt, nullptr, C, 0, 2 * pair_bits, scr, stream);
+    const uint64_t* sc = where ? cand_alt : cand;
+    uint64_t* dst = where ? cand : cand_alt;
+    mark(6);
+    const size_t nt = (C + kTile - 1) / kTile;
+    uint32_t* tc = scr;
+    uint32_t* tot = scr + nt;
+    launch_unique_count(sc, C, tc, stream);
+    scan_exclusive_u32(tc, tc, nt, tot, tot + 1, stream);
+    launch_unique_write(sc, C, tc, dst, stream);
+    uint32_t uh = 0;
+    if ((rc = read_back(tot, sizeof(uh), &uh))) return rc;
+    U = uh;
+    uniq = dst;
+    mark(7);
+  } else {
+    mark(6);
+    mark(7);
+  }
+  st.unique_pairs = (int64_t)U;
+
+  // --- CSR ----------------------------------------------------------------------
+  const bool both = !(flags & RTG_UPPER_ONLY);
+  const size_t nnz = both ? 2 * U : U;
+  const size_t rp_bytes = sizeof(int64_t) * (size_t)(n + 1);
+  const size_t res_bytes = ((rp_bytes + Arena::kAlign - 1) & ~(size_t)(Arena::kAlign - 1)) +
+                           sizeof(int32_t) * std::max<size_t>(nnz, 1);
+  void* res = dalloc(res_bytes);
+  if (!res) return RTG_ENOMEM;
+  int64_t* row_ptr = static_cast<int64_t*>(res);
+  int32_t* col = reinterpret_cast<int32_t*>(static_cast<char*>(res) +
+                                            ((rp_bytes + Arena::kAlign - 1) & ~(size_t)(Arena::kAlign - 1)));
+  {
+    uint32_t* up_s = S.get<uint32_t>((size_t)n);
+    uint32_t* up_e = S.get<uint32_t>((size_t)n);
+    uint32_t* lo_s = both ? S.get<uint32_t>((size_t)n) : nullptr;
+    uint32_t* lo_e = both ? S.get<uint32_t>((size_t)n) : nullptr;
+    uint64_t* deg = S.get<uint64_t>((size_t)n);
+    uint64_t* dscr = S.get<uint64_t>(scan_scratch_elems((size_t)n));
+    if (!up_s || !up_e || (both && (!lo_s || !lo_e)) || !deg || !dscr) {
+      dfree(res);
+      return RTG_ENOMEM;
+    }
+    launch_fill_u32(up_s, 0u, (size_t)n, stream);
+    launch_fill_u32(up_e, 0u, (size_t)n, stream);
+    if (both) {
+      launch_fill_u32(lo_s, 0u, (size_t)n, stream);
+      launch_fill_u32(lo_e, 0u, (size_t)n, stream);
+    }
+    const uint64_t* lower = nullptr;
+    if (U > 0) {
+      launch_row_runs(uniq, U, pair_bits, up_s, up_e, stream);
+      if (both) {
+        uint64_t* sw = S.get<uint64_t>(U);
+        uint64_t* sw_alt = S.get<uint64_t>(U);
+        uint32_t* scr = S.get<uint32_t>(radix_scratch_elems(U));
+        if (!sw || !sw_alt || !scr) {
+          dfree(res);
+          return RTG_ENOMEM;
+        }
+        launch_swap_pairs(uniq, U, pair_bits, sw, stream);
+        const int where = radix_sort(sw, nullptr, sw_alt, nullptr, U, 0, 2 * pair_bits, scr, stream);
+        lower = where ? sw_alt : sw;
+        launch_row_runs(lower, U, pair_bits, lo_s, lo_e, stream);
+      }
+    }
+    launch_row_degree(lo_s, lo_e, up_s, up_e, n, deg, stream);
+    scan_exclusive_u64(deg, reinterpret_cast<uint64_t*>(row_ptr), (size_t)n,
+                       reinterpret_cast<uint64_t*>(row_ptr) + n, dscr, stream);
+    if (U > 0) {
+      launch_csr_fill_upper(uniq, U, pair_bits, row_ptr, lo_s, lo_e, up_s, col, stream);
+      if (both) launch_csr_fill_lower(lower, U, pair_bits, row_ptr, lo_s, col, stream);
+    }
+    mark(8);
+    if ((rc = sync())) {
+      dfree(res);
+      return rc;
+    }
+  }
+  if ((rc = hip_fail(hipGetLastError(), "kernel launch"))) {
+    dfree(res);
+    return rc;
+  }
+  if (timing) {
+    float ms[8] = {0};
+    for (int q = 0; q < 8; ++q) (void)hipEventElapsedTime(&ms[q], ev[q], ev[q + 1]);
+    st.ms_stage = ms[0];
+    st.ms_keys = 0;  // recorded per group below when timing a single group
+    st.ms_key_sort = 0;
+    st.ms_cells = 0;
+    st.ms_pairs = 0;
+    if (P.tb == k) {
+      st.ms_keys = ms[1];
+      st.ms_key_sort = ms[2];
+      st.ms_cells = ms[3];
+      st.ms_pairs = ms[4];
+    }
+    st.ms_pair_sort = ms[5];
+    st.ms_unique = ms[6];
+    st.ms_csr = ms[7];
+    float tot_ms = 0;
+    (void)hipEventElapsedTime(&tot_ms, ev[0], ev[8]);
+    st.ms_total = tot_ms;
+  }
+  out->n = n;
+  out->nnz = (int64_t)nnz;
+  out->row_ptr = row_ptr;
+  out->col = nnz ? col : nullptr;
+  out->pairs = (int64_t)U;
+  out->handle = keep_result(res, n, (int64_t)nnz, row_ptr, col);
+  stats = st;
+  return RTG_OK;
+}
+
+int Ctx::debug_cell_coords(const float* points, int64_t n, int32_t d, double r, double alpha,
+                           const double* R, const double* u, int64_t* kappa_host) {
+  if (poisoned) return RTG_EDEVICE;
+  int rc = validate_query(points, n, d, r, 1, alpha);
+  if (rc) return rc;
+  if (n == 0) return RTG_OK;
+  if (check_device_pointer(points, device)) return RTG_EINVAL;
+  Scratch S(*this);
+  float* soa = S.get<float>((size_t)n * d);
+  uint32_t* flags_dev = S.get<uint32_t>(2 + 2 * kMaxDim);
+  double* Rd = S.get<double>((size_t)d * d);
+  double* ud = S.get<double>((size_t)d);
+  int64_t* kap = S.get<int64_t>((size_t)n * d);
+  if (!soa || !flags_dev || !Rd || !ud || !kap) return RTG_ENOMEM;
+  if ((rc = upload(Rd, R, sizeof(double) * d * d)) || (rc = upload(ud, u, sizeof(double) * d)))
+    return rc;
+  launch_stage_init(flags_dev, flags_dev + 2, d, stream);
+  launch_fill_u32(flags_dev + 1, 0u, 1, stream);
+  launch_stage(points, n, d, soa, flags_dev, flags_dev + 2, stream);
+  launch_cell_coords(soa, n, d, Rd, ud, 1.0 / (alpha * r), kap, flags_dev + 1, stream);
+  uint32_t fl[2];
+  if ((rc = read_back(flags_dev, sizeof(fl), fl))) return rc;
+  if (fl[0]) return RTG_EINVAL;
+  if (fl[1]) return RTG_ERANGE;
+  return hip_fail(hipMemcpy(kappa_host, kap, sizeof(int64_t) * (size_t)n * d,
+                            hipMemcpyDeviceToHost),
+                  "copy kappa");
+}
+
+}  // namespace rtg
+
+// ===========================================================================
+// C-ABI
+
+using rtg::Ctx;
+
+extern "C" {
+
+int rtg_create(rtg_ctx** out, int device, void* arena, size_t arena_bytes, void* hip_stream) {
+  if (!out || arena_bytes < (1u << 20)) return RTG_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return RTG_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return RTG_EDEVICE;
+  Ctx* c = new (std::nothrow) Ctx(device, static_cast<hipStream_t>(hip_stream));
+  if (!c) return RTG_ENOMEM;
+  if (!arena) {
+    if (hipMalloc(&c->arena_mem, arena_bytes) != hipSuccess) {
+      delete c;
+      return RTG_ENOMEM;
+    }
+    c->own_arena = true;
+    arena = c->arena_mem;
+  }
+  c->arena.reset(new rtg::Arena(static_cast<char*>(arena), arena_bytes));
+  if (hipHostMalloc(&c->host_stage, 4096) != hipSuccess) {
+    delete c;
+    return RTG_EDEVICE;
+  }
+  for (auto& e : c->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete c;
+      return RTG_EDEVICE;
+    }
+  *out = reinterpret_cast<rtg_ctx*>(c);
+  return RTG_OK;
+}
+
+int rtg_destroy(rtg_ctx* ctx) {
+  if (!ctx) return RTG_EINVAL;
+  Ctx* c = reinterpret_cast<Ctx*>(ctx);
+  c->stop_server();
+  (void)hipStreamSynchronize(c->stream);
+  delete c;
+  return RTG_OK;
+}
+
+int rtg_all_pairs(rtg_ctx* ctx, const float* points, int64_t n, int32_t d, double r, int32_t k,
+                  double alpha, uint64_t seed, uint32_t flags, rtg_csr* out) {
+  if (!ctx || !out) return RTG_EINVAL;
+  int rc = rtg::validate_query(points, n, d, r, k, alpha);
+  if (rc) return rc;
+  std::vector<double> R((size_t)k * d * d), u((size_t)k * d);
+  if ((rc = rtg::make_transforms(seed, k, d, flags, R.data(), u.data()))) return rc;
+  Ctx* c = reinterpret_cast<Ctx*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  return c->all_pairs(points, n, d, r, k, alpha, R.data(), u.data(), flags, out);
+}
+
+int rtg_all_pairs_with_transforms(rtg_ctx* ctx, const float* points, int64_t n, int32_t d, double r,
+                                  int32_t k, double alpha, const double* R, const double* u,
+                                  uint32_t flags, rtg_csr* out) {
+  if (!ctx || !out || !R || !u) return RTG_EINVAL;
+  Ctx* c = reinterpret_cast<Ctx*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  return c->all_pairs(points, n, d, r, k, alpha, R, u, flags, out);
+}
+
+int rtg_release(rtg_ctx* ctx, uint64_t handle) {
+  if (!ctx) return RTG_EINVAL;
+  Ctx* c = reinterpret_cast<Ctx*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  return c->release(handle);
+}
+
+int rtg_make_transforms(uint64_t seed, int32_t k, int32_t d, uint32_t flags, double* R, double* u) {
+  return rtg::make_transforms(seed, k, d, flags, R, u);
+}
+
+int rtg_set_timing(rtg_ctx* ctx, int on) {
+  if (!ctx) return RTG_EINVAL;
+  reinterpret_cast<Ctx*>(ctx)->timing = on != 0;
+  return RTG_OK;
+}
+
+int rtg_get_stats(const rtg_ctx* ctx, rtg_stats* out) {
+  if (!ctx || !out) return RTG_EINVAL;
+  *out = reinterpret_cast<const Ctx*>(ctx)->stats;
+  return RTG_OK;
+}
+
+int rtg_debug_cell_coords(rtg_ctx* ctx, const float* points, int64_t n, int32_t d, double r,
+                          double alpha, const double* R, const double* u, int64_t* kappa) {
+  if (!ctx || !R || !u || (n > 0 && !kappa)) return RTG_EINVAL;
+  Ctx* c = reinterpret_cast<Ctx*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  return c->debug_cell_coords(points, n, d, r, alpha, R, u, kappa);
+}
+
+const char* rtg_strerror(int status) {
+  switch (status) {
+    case RTG_OK: return "ok";
+    case RTG_EAGAIN: return "request not finished";
+    case RTG_EINVAL: return "invalid argument";
+    case RTG_ENOMEM: return "does not fit the device-memory budget";
+    case RTG_ERANGE: return "out of range (cell coordinate, radius, or key bits)";
+    case RTG_EDEVICE: return "device error";
+    case RTG_ENOENT: return "unknown ticket or handle";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// rtg_internal.h -- launchers of the gfx950 kernels, shared by the host
+// pipeline (rtg_host.cpp) and the kernels (rtg_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtgk {
+
+constexpr int kBlock = 256;          // threads per block: four 64-wide waves
+constexpr int kWaves = kBlock / 64;  // waves per block
+constexpr int kKeysPerThread = 16;   // radix-sort / scan elements per thread
+constexpr int kTile = kBlock * kKeysPerThread;  // 4096 elements per tile
+constexpr int kPairTile = 64;        // points per tile in the cell-pair kernel
+constexpr int kRadixBits = 8;        // digit width of one radix pass
+constexpr int kMaxDim = 64;
+
+// Where each axis of a cell vector sits in the packed 64-bit key.
+struct KeyLayout {
+  int32_t d;
+  int32_t cell_bits;           // sum of bits[] (segment id sits above)
+  uint8_t shift[kMaxDim];      // bit offset of axis j
+  uint8_t bits[kMaxDim];       // width of axis j
+};
+
+// Tests of a squared distance against r^2: FP32 screen plus FP64 band.
+struct PairTest {
+  float lo;      // accept if d2_f32 <= lo  (lo <= r2 (1 - 2^-16))
+  float hi;      // reject if d2_f32 >  hi  (hi >= r2 (1 + 2^-16))
+  double r2;     // FP64 decision in between: s <= r2
+  int32_t pair_bits;  // bits of one index in a packed (i,j) pair
+};
+
+// --- staging --------------------------------------------------------------
+// AoS [n][d] -> SoA [d][n]; flags non-finite values; per-axis min/max as
+// order-preserving uint32 encodings (bbox[2j] = min, bbox[2j+1] = max).
+void launch_stage(const float* pts, int64_t n, int d, float* soa, uint32_t* bad,
+                  uint32_t* bbox, hipStream_t s);
+void launch_stage_init(uint32_t* bad, uint32_t* bbox, int d, hipStream_t s);
+
+// --- cell keys ------------------------------------------------------------
+// keys[(t - t0) * n + i] = packed cell of point i under transform t, and
+// vals[...] = i, for t in [t0, t0 + tb).  R [k][d][d], u [k][d] FP64;
+// klo [k][d] int64 origin of the packed range.  err |= 1 if |y| >= 2^31.
+void launch_keys(const float* soa, int64_t n, int d, int t0, int tb, const double* R,
+                 const double* u, double inv_c, const int64_t* klo, const KeyLayout* layout,
+                 uint64_t* keys, uint32_t* vals, uint32_t* err, hipStream_t s);
+// kappa [n][d] = floor(y) for one transform (stage check).
+void launch_cell_coords(const float* soa, int64_t n, int d, const double* R, const double* u,
+                        double inv_c, int64_t* kappa, uint32_t* err, hipStream_t s);
+
+// --- generic helpers ------------------------------------------------------
+void launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s);
+void launch_fill_u64(uint64_t* p, uint64_t v, size_t count, hipStream_t s);
+
+// Exclusive prefix sum of count elements; total (device, optional) receives
+// the sum.  scratch must hold scan_scratch_elems(count) elements.
+size_t scan_scratch_elems(size_t count);
+void scan_exclusive_u32(const uint32_t* in, uint32_t* out, size_t count, uint32_t* total,
+                        uint32_t* scratch, hipStream_t s);
+void scan_exclusive_u64(const uint64_t* in, uint64_t* out, size_t count, uint64_t* total,
+                        uint64_t* scratch, hipStream_t s);
+
+// --- radix sort -----------------------------------------------------------
+// Stable LSD sort of count 64-bit keys (and optional u32 values) on bits
+// [begin_bit, end_bit).  Ping-pongs between (keys, vals) and (keys_alt,
+// vals_alt); returns 0 if the result ends in keys/vals, 1 if in the *_alt.
+// scratch must hold radix_scratch_elems(count) u32.
+size_t radix_scratch_elems(size_t count);
+int radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+               size_t count, int begin_bit, int end_bit, uint32_t* scratch, hipStream_t s);
+
+// --- cells ----------------------------------------------------------------
+// Runs of equal keys with length >= 2 in a sorted key array: per tile counts
+// of run heads and run tails (u32 each, ntiles entries).
+void launch_run_count(const uint64_t* keys, size_t count, uint32_t* head_cnt,
+                      uint32_t* tail_cnt, hipStream_t s);
+// Writes start[c] / end[c] of run c (ordered by position) given the scanned
+// per-tile offsets.
+void launch_run_write(const uint64_t* keys, size_t count, const uint32_t* head_off,
+                      const uint32_t* tail_off, uint32_t* start, uint32_t* end, hipStream_t s);
+// items[c] = number of 64x64 tile pairs of run c; tests[c] = L(L-1)/2.
+void launch_cell_work(const uint32_t* start, const uint32_t* end, const uint32_t* ncells,
+                      uint64_t* items, uint64_t* tests, size_t max_cells, hipStream_t s);
+
+// --- cell pairs -----------------------------------------------------------
+// One 64-wide wave per (cell, tile a, tile b) item; emits packed pairs
+// (min << pair_bits | max) for same-cell pairs within r.  cand_count is the
+// running total (may exceed cap: then the overflow is only counted);
+// rechecks counts FP64 band re-tests; next_item is the launch's work counter
+// (reset by the launcher).
+void launch_cell_pairs(const float* pts, int d, const uint32_t* sidx, const uint32_t* start,
+                       const uint32_t* end, const uint64_t* item_off, const uint32_t* ncells,
+                       uint64_t total_items, PairTest test, uint64_t* cand, uint64_t cap,
+                       unsigned long long* cand_count, unsigned long long* rechecks,
+                       unsigned long long* next_item, hipStream_t s);
+
+// --- unique + CSR -----------------------------------------------------------
+void launch_unique_count(const uint64_t* keys, size_t count, uint32_t* tile_cnt, hipStream_t s);
+void launch_unique_write(const uint64_t* keys, size_t count, const uint32_t* tile_off,
+                         uint64_t* out, hipStream_t s);
+// swapped[p] = (j << b) | i for pairs[p] = (i << b) | j.
+void launch_swap_pairs(const uint64_t* pairs, size_t count, int pair_bits, uint64_t* swapped,
+                       hipStream_t s);
+// For a key array sorted by row (row = key >> pair_bits): rstart[row] = first
+// position, rend[row] = one past the last (untouched rows keep their value).
+void launch_row_runs(const uint64_t* keys, size_t count, int pair_bits, uint32_t* rstart,
+                     uint32_t* rend, hipStream_t s);
+// deg[i] = (lo_end - lo_start) + (up_end - up_start); lo_* may be null.
+void launch_row_degree(const uint32_t* lo_start, const uint32_t* lo_end, const uint32_t* up_start,
+                       const uint32_t* up_end, int64_t n, uint64_t* deg, hipStream_t s);
+// col[row_ptr[i] + lo_cnt(i) + (p - up_start[i])] = j for upper entries, and
+// col[row_ptr[j] + (q - lo_start[j])] = i for the swapped entries.
+void launch_csr_fill_upper(const uint64_t* up, size_t count, int pair_bits, const int64_t* row_ptr,
+                           const uint32_t* lo_start, const uint32_t* lo_end,
+                           const uint32_t* up_start, int32_t* col, hipStream_t s);
+void launch_csr_fill_lower(const uint64_t* lo, size_t count, int pair_bits, const int64_t* row_ptr,
+                           const uint32_t* lo_start, int32_t* col, hipStream_t s);
+
+}  // namespace rtgk

@@ -1,0 +1,992 @@
+// rtg_kernels.hip -- gfx950 kernels of the RTG all-pairs r-NN pipeline.
+//
+// Steps (Sec. III, Alg. "Randomly Shifted Grids" with random orientations):
+//   stage      AoS -> SoA copy of the points, finiteness check, bounding box
+//   keys       cell of every (point, grid) in FP64, packed into a 64-bit key
+//   sort       stable LSD radix sort of (key, point) -- groups equal cells
+//   cells      runs of equal keys with >= 2 points and their 64x64 tile pairs
+//   pairs      one wave per tile pair: FP32 screen, FP64 band re-test,
+//              ballot-compacted output of pairs within r
+//   unique     sort of packed pairs and removal of repeats (Sec. III-B)
+//   csr        symmetric neighbour lists (Sec. III-B)
+//
+// The whole file is compiled with FMA contraction off: the cell coordinate
+// y = (R p) / c + u and the FP64 re-test must round every product and sum on
+// its own, in the order written, to match the FP64 definition bit for bit.
+// Where a fused multiply-add is wanted (the FP32 screen) it is written out.
+#pragma clang fp contract(off)
+
+#include "rtg_internal.h"
+
+#include <math.h>
+
+namespace rtgk {
+namespace {
+
+__device__ __forceinline__ uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// Number of set bits of m below this lane.
+__device__ __forceinline__ uint32_t rank_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Orders the LDS traffic of one wave: every lane's earlier LDS writes are
+// seen by every lane's later LDS reads, and no access moves across.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    T t = __shfl_up(v, o, 64);
+    if (lane >= (uint32_t)o) v += t;
+  }
+  return v;
+}
+
+// Exclusive scan of one value per thread over a 256-thread block.  wsum
+// must be a __shared__ array of kWaves elements; total receives the sum.
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* wsum, T& total) {
+  const uint32_t lane = lane_id();
+  const int w = threadIdx.x >> 6;
+  T inc = wave_inclusive_scan(v);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  T before = 0, all = 0;
+#pragma unroll
+  for (int q = 0; q < kWaves; ++q) {
+    T x = wsum[q];
+    if (q < w) before += x;
+    all += x;
+  }
+  __syncthreads();
+  total = all;
+  return before + inc - v;
+}
+
+// Order-preserving encoding of a finite float as uint32.
+__device__ __forceinline__ uint32_t float_order(float f) {
+  uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// ---------------------------------------------------------------------------
+// fill
+
+template <typename T>
+__global__ void k_fill(T* p, T v, size_t count) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// stage: one thread per point.
+
+__global__ void k_stage_init(uint32_t* bad, uint32_t* bbox, int d) {
+  int t = threadIdx.x;
+  if (t == 0) *bad = 0u;
+  if (t < d) {
+    bbox[2 * t] = 0xFFFFFFFFu;
+    bbox[2 * t + 1] = 0u;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_stage(const float* __restrict__ pts, int64_t n, int d,
+                                                  float* __restrict__ soa, uint32_t* bad,
+                                                  uint32_t* bbox) {
+  __shared__ uint32_t smin[kMaxDim], smax[kMaxDim];
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool live = i < n;
+  if (threadIdx.x < (unsigned)d) {
+    smin[threadIdx.x] = 0xFFFFFFFFu;
+    smax[threadIdx.x] = 0u;
+  }
+  __syncthreads();
+  bool nonfinite = false;
+  for (int l = 0; l < d; ++l) {
+    float v = live ? pts[i * d + l] : 0.0f;
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    if (live) {
+      soa[(int64_t)l * n + i] = v;
+      if (!isfinite(v)) nonfinite = true;
+      else lo = hi = float_order(v);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
+      hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
+    }
+    if (lane_id() == 0) {
+      atomicMin(&smin[l], lo);
+      atomicMax(&smax[l], hi);
+    }
+  }
+  if (nonfinite) atomicOr(bad, 1u);
+  __syncthreads();
+  if (threadIdx.x < (unsigned)d) {
+    atomicMin(&bbox[2 * threadIdx.x], smin[threadIdx.x]);
+    atomicMax(&bbox[2 * threadIdx.x + 1], smax[threadIdx.x]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// keys: y_j = ((R_j0 p_0 + R_j1 p_1) + ...) * inv_c + u_j, each operation
+// rounded on its own (contraction is off), kappa_j = floor(y_j).
+
+template <int D>
+__device__ __forceinline__ double cell_y(const double* __restrict__ Rj, const float* p_reg,
+                                         const float* __restrict__ soa, int64_t n, int64_t i,
+                                         int d, double inv_c, double uj) {
+  double z;
+  if (D > 0) {
+    z = Rj[0] * (double)p_reg[0];
+#pragma unroll
+    for (int l = 1; l < D; ++l) z = z + Rj[l] * (double)p_reg[l];
+  } else {
+    z = Rj[0] * (double)soa[i];
+    for (int l = 1; l < d; ++l) z = z + Rj[l] * (double)soa[(int64_t)l * n + i];
+  }
+  return z * inv_c + uj;
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_keys(const float* __restrict__ soa, int64_t n, int d_rt,
+                                                 int t0, int tb, const double* __restrict__ R,
+                                                 const double* __restrict__ u, double inv_c,
+                                                 const int64_t* __restrict__ klo,
+                                                 const KeyLayout* __restrict__ layout,
+                                                 uint64_t* __restrict__ keys,
+                                                 uint32_t* __restrict__ vals, uint32_t* err) {
+  const int d = D > 0 ? D : d_rt;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  float p[D > 0 ? D : 1];
+  if (D > 0) {
+#pragma unroll
+    for (int l = 0; l < (D > 0 ? D : 1); ++l) p[l] = soa[(int64_t)l * n + i];
+  }
+  const int cell_bits = layout->cell_bits;
+  bool bad = false;
+  for (int tt = 0; tt < tb; ++tt) {
+    const int t = t0 + tt;
+    const double* Rt = R + (size_t)t * d * d;
+    const double* ut = u + (size_t)t * d;
+    const int64_t* kl = klo + (size_t)t * d;
+    uint64_t key = (cell_bits < 64) ? ((uint64_t)tt << cell_bits) : 0ull;
+    for (int j = 0; j < d; ++j) {
+      double y = cell_y<D>(Rt + (size_t)j * d, p, soa, n, i, d, inv_c, ut[j]);
+      bool ok = fabs(y) < 2147483648.0;
+      bad |= !ok;
+      int64_t kap = ok ? (int64_t)floor(y) : 0;
+      uint64_t mask = (1ull << layout->bits[j]) - 1ull;
+      key |= ((uint64_t)(kap - kl[j]) & mask) << layout->shift[j];
+    }
+    keys[(int64_t)tt * n + i] = key;
+    vals[(int64_t)tt * n + i] = (uint32_t)i;
+  }
+  if (bad) atomicOr(err, 1u);
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_cell_coords(const float* __restrict__ soa, int64_t n,
+                                                        int d_rt, const double* __restrict__ R,
+                                                        const double* __restrict__ u, double inv_c,
+                                                        int64_t* __restrict__ kappa,
+                                                        uint32_t* err) {
+  const int d = D > 0 ? D : d_rt;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  float p[D > 0 ? D : 1];
+  if (D > 0) {
+#pragma unroll
+    for (int l = 0; l < (D > 0 ? D : 1); ++l) p[l] = soa[(int64_t)l * n + i];
+  }
+  bool bad = false;
+  for (int j = 0; j < d; ++j) {
+    double y = cell_y<D>(R + (size_t)j * d, p, soa, n, i, d, inv_c, u[j]);
+    bool ok = fabs(y) < 2147483648.0;
+    bad |= !ok;
+    kappa[i * d + j] = ok ? (int64_t)floor(y) : 0;
+  }
+  if (bad) atomicOr(err, 1u);
+}
+
+// ---------------------------------------------------------------------------
+// scan: 256 threads x 8 consecutive elements per block.
+
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const T* __restrict__ in, size_t count,
+                                                        T* __restrict__ sums) {
+  __shared__ T wsum[kWaves];
+  const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
+  T s = 0;
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q)
+    if (base + q < count) s += in[base + q];
+  T total;
+  block_exclusive_scan<T>(s, wsum, total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const T* in, T* out, size_t count,
+                                                       const T* __restrict__ offsets, T* total) {
+  __shared__ T wsum[kWaves];
+  const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
+  T v[kScanItems];
+  T s = 0;
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) {
+    v[q] = (base + q < count) ? in[base + q] : (T)0;
+    s += v[q];
+  }
+  T tile_total;
+  T run = block_exclusive_scan<T>(s, wsum, tile_total);
+  const T off = offsets ? offsets[blockIdx.x] : (T)0;
+  run += off;
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) {
+    if (base + q < count) out[base + q] = run;
+    run += v[q];
+  }
+  if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = off + tile_total;
+}
+
+// ---------------------------------------------------------------------------
+// radix sort: tiles of 4096 elements; element e of a tile is held by wave
+// e / 1024, round (e % 1024) / 64, lane e % 64, so every load is one
+// contiguous 64-element run.
+
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t* __restrict__ keys,
+                                                       size_t count, int shift, int nbits,
+                                                       uint32_t* __restrict__ tile_hist,
+                                                       uint32_t ntiles) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0u;
+  __syncthreads();
+  const uint32_t mask = (1u << nbits) - 1u;
+  const size_t base = (size_t)blockIdx.x * kTile;
+#pragma unroll 4
+  for (int q = 0; q < kKeysPerThread; ++q) {
+    size_t e = base + (size_t)q * kBlock + threadIdx.x;
+    if (e < count) atomicAdd(&h[(uint32_t)(keys[e] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  tile_hist[(size_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+template <bool HAS_VAL>
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(
+    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, size_t count, int shift, int nbits,
+    const uint32_t* __restrict__ tile_off, uint32_t ntiles) {
+  __shared__ uint64_t skey[kTile];
+  __shared__ uint32_t sval[HAS_VAL ? kTile : 1];
+  __shared__ uint32_t wcnt[kWaves][256];
+  __shared__ uint32_t dstart[256];
+  __shared__ uint32_t goff[256];
+  __shared__ uint32_t wsum[kWaves];
+
+  const uint32_t lane = lane_id();
+  const int w = threadIdx.x >> 6;
+  const uint32_t mask = (1u << nbits) - 1u;
+#pragma unroll
+  for (int q = 0; q < kWaves; ++q) wcnt[q][threadIdx.x] = 0u;
+  __syncthreads();
+
+  const size_t tile_base = (size_t)blockIdx.x * kTile;
+  const size_t wave_base = tile_base + (size_t)w * (kTile / kWaves);
+  const uint64_t lt = (1ull << lane) - 1ull;
+
+  uint64_t k_[kKeysPerThread];
+  uint32_t v_[kKeysPerThread];
+  uint32_t r_[kKeysPerThread];
+#pragma unroll
+  for (int q = 0; q < kKeysPerThread; ++q) {
+    const size_t e = wave_base + (size_t)q * 64 + lane;
+    const bool valid = e < count;
+    const uint64_t key = valid ? kin[e] : ~0ull;
+    k_[q] = key;
+    if (HAS_VAL) v_[q] = valid ? vin[e] : 0u;
+    const uint32_t dg = (uint32_t)(key >> shift) & mask;
+    uint64_t peers = ballot(valid);
+    for (int b = 0; b < nbits; ++b) {
+      const bool bit = (dg >> b) & 1u;
+      const uint64_t m = ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    uint32_t before = 0;
+    if (valid) before = wcnt[w][dg];
+    r_[q] = before + (uint32_t)__popcll(peers & lt);
+    wave_lds_sync();
+    if (valid && (peers & lt) == 0ull) wcnt[w][dg] = before + (uint32_t)__popcll(peers);
+    wave_lds_sync();
+  }
+  __syncthreads();
+
+  // Digit d = threadIdx.x: where its run starts in the tile, and each wave's
+  // first position inside that run.
+  {
+    const uint32_t dg = threadIdx.x;
+    uint32_t c[kWaves];
+    uint32_t tot = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) {
+      c[q] = wcnt[q][dg];
+      tot += c[q];
+    }
+    uint32_t all;
+    const uint32_t start = block_exclusive_scan<uint32_t>(tot, wsum, all);
+    dstart[dg] = start;
+    uint32_t run = start;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) {
+      wcnt[q][dg] = run;
+      run += c[q];
+    }
+    goff[dg] = tile_off[(size_t)dg * ntiles + blockIdx.x];
+  }
+  __syncthreads();
+
+#pragma unroll
+  for (int q = 0; q < kKeysPerThread; ++q) {
+    const size_t e = wave_base + (size_t)q * 64 + lane;
+    if (e < count) {
+      const uint32_t dg = (uint32_t)(k_[q] >> shift) & mask;
+      const uint32_t pos = wcnt[w][dg] + r_[q];
+      skey[pos] = k_[q];
+      if (HAS_VAL) sval[pos] = v_[q];
+    }
+  }
+  __syncthreads();
+
+  const size_t rem = count - tile_base;
+  const uint32_t tile_count = rem < (size_t)kTile ? (uint32_t)rem : (uint32_t)kTile;
+#pragma unroll 4
+  for (int q = 0; q < kKeysPerThread; ++q) {
+    const uint32_t s = (uint32_t)q * kBlock + threadIdx.x;
+    if (s < tile_count) {
+      const uint64_t key = skey[s];
+      const uint32_t dg = (uint32_t)(key >> shift) & mask;
+      const size_t g = (size_t)goff[dg] + (s - dstart[dg]);
+      kout[g] = key;
+      if (HAS_VAL) vout[g] = sval[s];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// runs of equal keys (cells with >= 2 points), unique keys.
+
+__device__ __forceinline__ void run_flags(const uint64_t* __restrict__ keys, size_t count, size_t e,
+                                          bool& head, bool& tail) {
+  head = tail = false;
+  if (e >= count) return;
+  const uint64_t k = keys[e];
+  const bool prev_same = e > 0 && keys[e - 1] == k;
+  const bool next_same = e + 1 < count && keys[e + 1] == k;
+  head = !prev_same && next_same;
+  tail = prev_same && !next_same;
+}
+
+__global__ __launch_bounds__(kBlock) void k_run_count(const uint64_t* __restrict__ keys,
+                                                      size_t count, uint32_t* head_cnt,
+                                                      uint32_t* tail_cnt) {
+  __shared__ uint32_t sh[kWaves], st[kWaves];
+  const uint32_t lane = lane_id();
+  const int w = threadIdx.x >> 6;
+  const size_t wave_base = (size_t)blockIdx.x * kTile + (size_t)w * (kTile / kWaves);
+  uint32_t hc = 0, tc = 0;
+  for (int q = 0; q < kKeysPerThread; ++q) {
+    bool h, t;
+    run_flags(keys, count, wave_base + (size_t)q * 64 + lane, h, t);
+    hc += (uint32_t)__popcll(ballot(h));
+    tc += (uint32_t)__popcll(ballot(t));
+  }
+  if (lane == 0) {
+    sh[w] = hc;
+    st[w] = tc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t a = 0, b = 0;
+    for (int q = 0; q < kWaves; ++q) {
+      a += sh[q];
+      b += st[q];
+    }
+    head_cnt[blockIdx.x] = a;
+    tail_cnt[blockIdx.x] = b;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_run_write(const uint64_t* __restrict__ keys,
+                                                      size_t count,
+                                                      const uint32_t* __restrict__ head_off,
+                                                      const uint32_t* __restrict__ tail_off,
+                                                      uint32_t* __restrict__ start,
+                                                      uint32_t* __restrict__ end) {
+  __shared__ uint32_t sh[kWaves], st[kWaves];
+  const uint32_t lane = lane_id();
+  const int w = threadIdx.x >> 6;
+  const size_t wave_base = (size_t)blockIdx.x * kTile + (size_t)w * (kTile / kWaves);
+  uint32_t hmask = 0, tmask = 0, hc = 0, tc = 0;
+  for (int q = 0; q < kKeysPerThread; ++q) {
+    bool h, t;
+    run_flags(keys, count, wave_base + (size_t)q * 64 + lane, h, t);
+    hmask |= (uint32_t)h << q;
+    tmask |= (uint32_t)t << q;
+    hc += (uint32_t)__popcll(ballot(h));
+    tc += (uint32_t)__popcll(ballot(t));
+  }
+  if (lane == 0) {
+    sh[w] = hc;
+    st[w] = tc;
+  }
+  __syncthreads();
+  uint32_t hbase = head_off[blockIdx.x], tbase = tail_off[blockIdx.x];
+  for (int q = 0; q < w; ++q) {
+    hbase += sh[q];
+    tbase += st[q];
+  }
+  for (int q = 0; q < kKeysPerThread; ++q) {
+    const size_t e = wave_base + (size_t)q * 64 + lane;
+    const bool h = (hmask >> q) & 1u, t = (tmask >> q) & 1u;
+    const uint64_t hb = ballot(h), tbm = ballot(t);
+    if (h) start[hbase + rank_below(hb)] = (uint32_t)e;
+    if (t) end[tbase + rank_below(tbm)] = (uint32_t)(e + 1);
+    hbase += (uint32_t)__popcll(hb);
+    tbase += (uint32_t)__popcll(tbm);
+  }
+}
+
+__global__ void k_cell_work(const uint32_t* __restrict__ start, const uint32_t* __restrict__ end,
+                            const uint32_t* __restrict__ ncells, uint64_t* __restrict__ items,
+                            uint64_t* __restrict__ tests, size_t max_cells) {
+  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= max_cells) return;
+  uint64_t it = 0, te = 0;
+  if (c < *ncells) {
+    const uint64_t L = end[c] - start[c];
+    const uint64_t nt = (L + kPairTile - 1) / kPairTile;
+    it = nt * (nt + 1) / 2;
+    te = L * (L - 1) / 2;
+  }
+  items[c] = it;
+  tests[c] = te;
+}
+
+__global__ __launch_bounds__(kBlock) void k_unique_count(const uint64_t* __restrict__ keys,
+                                                         size_t count, uint32_t* tile_cnt) {
+  __shared__ uint32_t sh[kWaves];
+  const uint32_t lane = lane_id();
+  const int w = threadIdx.x >> 6;
+  const size_t wave_base = (size_t)blockIdx.x * kTile + (size_t)w * (kTile / kWaves);
+  uint32_t c = 0;
+  for (int q = 0; q < kKeysPerThread; ++q) {
+    const size_t e = wave_base + (size_t)q * 64 + lane;
+    const bool f = e < count && (e == 0 || keys[e] != keys[e - 1]);
+    c += (uint32_t)__popcll(ballot(f));
+  }
+  if (lane == 0) sh[w] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t a = 0;
+    for (int q = 0; q < kWaves; ++q) a += sh[q];
+    tile_cnt[blockIdx.x] = a;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_unique_write(const uint64_t* __restrict__ keys,
+                                                         size_t count,
+                                                         const uint32_t* __restrict__ tile_off,
+                                                         uint64_t* __restrict__ out) {
+  __shared__ uint32_t sh[kWaves];
+  const uint32_t lane = lane_id();
+  const int w = threadIdx.x >> 6;
+  const size_t wave_base = (size_t)blockIdx.x * kTile + (size_t)w * (kTile / kWaves);
+  uint32_t fmask = 0, c = 0;
+  for (int q = 0; q < kKeysPerThread; ++q) {
+    const size_t e = wave_base + (size_t)q * 64 + lane;
+    const bool f = e < count && (e == 0 || keys[e] != keys[e - 1]);
+    fmask |= (uint32_t)f << q;
+    c += (uint32_t)__popcll(ballot(f));
+  }
+  if (lane == 0) sh[w] = c;
+  __syncthreads();
+  uint32_t base = tile_off[blockIdx.x];
+  for (int q = 0; q < w; ++q) base += sh[q];
+  for (int q = 0; q < kKeysPerThread; ++q) {
+    const size_t e = wave_base + (size_t)q * 64 + lane;
+    const bool f = (fmask >> q) & 1u;
+    const uint64_t m = ballot(f);
+    if (f) out[base + rank_below(m)] = keys[e];
+    base += (uint32_t)__popcll(m);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// cell pairs.  One wave per item = (cell, tile a <= tile b) of 64 points
+// each; lane l holds point a_l in registers, tile b sits in LDS and is read
+// by broadcast.  Pairs within r are staged in a per-wave LDS buffer and
+// flushed with one global atomic per flush.
+
+constexpr int kOutBuf = 512;
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_cell_pairs(
+    const float* __restrict__ pts, int d_rt, const uint32_t* __restrict__ sidx,
+    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend,
+    const uint64_t* __restrict__ item_off, const uint32_t* __restrict__ ncells_p,
+    uint64_t total_items, PairTest T, uint64_t* __restrict__ cand, uint64_t cap,
+    unsigned long long* cand_count, unsigned long long* rechecks,
+    unsigned long long* next_item) {
+  constexpr int DD = D > 0 ? D : kMaxDim;
+  const int d = D > 0 ? D : d_rt;
+  __shared__ float sB[kWaves][DD][kPairTile];
+  __shared__ uint32_t sBi[kWaves][kPairTile];
+  __shared__ uint64_t sOut[kWaves][kOutBuf];
+
+  const uint32_t lane = lane_id();
+  const int w = threadIdx.x >> 6;
+  const uint32_t ncells = *ncells_p;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  uint32_t outn = 0;
+  unsigned long long nre = 0;
+
+  auto flush = [&]() {
+    wave_lds_sync();
+    if (outn) {
+      unsigned long long base = 0;
+      if (lane == 0) base = atomicAdd(cand_count, (unsigned long long)outn);
+      base = __shfl(base, 0, 64);
+      for (uint32_t e = lane; e < outn; e += 64) {
+        const uint64_t g = base + e;
+        if (g < cap) cand[g] = sOut[w][e];
+      }
+      outn = 0;
+    }
+    wave_lds_sync();
+  };
+
+  for (;;) {
+    unsigned long long item = 0;
+    if (lane == 0) item = atomicAdd(next_item, 1ull);
+    item = __shfl(item, 0, 64);
+    if (item >= total_items) break;
+
+    // The cell whose items cover this one: largest c with item_off[c] <= item.
+    uint32_t lo = 0, hi = ncells;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (item_off[mid] <= item) lo = mid;
+      else hi = mid;
+    }
+    const uint32_t s0 = cstart[lo];
+    const uint32_t L = cend[lo] - s0;
+    const uint32_t nt = (L + kPairTile - 1) / kPairTile;
+    uint64_t q = item - item_off[lo];
+    uint32_t ta = 0;
+    while (q >= (uint64_t)(nt - ta)) {
+      q -= nt - ta;
+      ++ta;
+    }
+    const uint32_t tb = ta + (uint32_t)q;
+    const uint32_t nA = min((uint32_t)kPairTile, L - ta * kPairTile);
+    const uint32_t nB = min((uint32_t)kPairTile, L - tb * kPairTile);
+
+    wave_lds_sync();
+    if (lane < nB) {
+      const uint32_t g = sidx[s0 + tb * kPairTile + lane];
+      sBi[w][lane] = g;
+      for (int l = 0; l < d; ++l) sB[w][l][lane] = pts[(size_t)g * d + l];
+    }
+    float a[DD];
+    uint32_t ai = 0;
+    if (lane < nA) {
+      ai = sidx[s0 + ta * kPairTile + lane];
+      for (int l = 0; l < d; ++l) a[l] = pts[(size_t)ai * d + l];
+    } else {
+      for (int l = 0; l < d; ++l) a[l] = 0.0f;
+    }
+    wave_lds_sync();
+
+    const bool diag = ta == tb;
+    for (uint32_t j = 0; j < nB; ++j) {
+      const bool act = lane < nA && (!diag || lane < j);
+      float d2 = 0.0f;
+      if (D > 0) {
+#pragma unroll
+        for (int l = 0; l < DD; ++l) {
+          const float df = a[l] - sB[w][l][j];
+          d2 = __builtin_fmaf(df, df, d2);
+        }
+      } else {
+        for (int l = 0; l < d; ++l) {
+          const float df = a[l] - sB[w][l][j];
+          d2 = __builtin_fmaf(df, df, d2);
+        }
+      }
+      bool acc = act && d2 <= T.lo;
+      if (act && !acc && d2 <= T.hi) {
+        // Band: decide in FP64 exactly as the definition does.
+        double s = 0.0;
+        for (int l = 0; l < d; ++l) {
+          const double dl = (double)a[l] - (double)sB[w][l][j];
+          s = s + dl * dl;
+        }
+        acc = s <= T.r2;
+        ++nre;
+      }
+      const uint64_t m = ballot(acc);
+      if (m) {
+        if (acc) {
+          const uint32_t bj = sBi[w][j];
+          const uint64_t pi = min(ai, bj), pj = max(ai, bj);
+          sOut[w][outn + (uint32_t)__popcll(m & lt)] = (pi << T.pair_bits) | pj;
+        }
+        outn += (uint32_t)__popcll(m);
+        if (outn > kOutBuf - 64) flush();
+      }
+    }
+  }
+  flush();
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) nre += __shfl_xor(nre, o, 64);
+  if (lane == 0 && nre) atomicAdd(rechecks, nre);
+}
+
+// ---------------------------------------------------------------------------
+// CSR
+
+__global__ void k_swap_pairs(const uint64_t* __restrict__ pairs, size_t count, int pb,
+                             uint64_t* __restrict__ out) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+  const uint64_t k = pairs[p];
+  const uint64_t mask = (1ull << pb) - 1ull;
+  out[p] = ((k & mask) << pb) | (k >> pb);
+}
+
+__global__ void k_row_runs(const uint64_t* __restrict__ keys, size_t count, int pb,
+                           uint32_t* __restrict__ rstart, uint32_t* __restrict__ rend) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+  const uint64_t row = keys[p] >> pb;
+  if (p == 0 || (keys[p - 1] >> pb) != row) rstart[row] = (uint32_t)p;
+  if (p + 1 == count || (keys[p + 1] >> pb) != row) rend[row] = (uint32_t)(p + 1);
+}
+
+__global__ void k_row_degree(const uint32_t* __restrict__ lo_start, const uint32_t* __restrict__ lo_end,
+                             const uint32_t* __restrict__ up_start, const uint32_t* __restrict__ up_end,
+                             int64_t n, uint64_t* __restrict__ deg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t c = (uint64_t)(up_end[i] - up_start[i]);
+  if (lo_start) c += (uint64_t)(lo_end[i] - lo_start[i]);
+  deg[i] = c;
+}
+
+__global__ void k_csr_fill_upper(const uint64_t* __restrict__ up, size_t count, int pb,
+                                 const int64_t* __restrict__ row_ptr,
+                                 const uint32_t* __restrict__ lo_start,
+                                 const uint32_t* __restrict__ lo_end,
+                                 const uint32_t* __restrict__ up_start, int32_t* __restrict__ col) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+  const uint64_t k = up[p];
+  const uint64_t i = k >> pb, j = k & ((1ull << pb) - 1ull);
+  int64_t pos = row_ptr[i] + (int64_t)(p - up_start[i]);
+  if (lo_start) pos += (int64_t)(lo_end[i] - lo_start[i]);
+  col[pos] = (int32_t)j;
+}
+
+__global__ void k_csr_fill_lower(const uint64_t* __restrict__ lo, size_t count, int pb,
+                                 const int64_t* __restrict__ row_ptr,
+                                 const uint32_t* __restrict__ lo_start, int32_t* __restrict__ col) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  const uint64_t k = lo[q];
+  const uint64_t j = k >> pb, i = k & ((1ull << pb) - 1ull);
+  col[row_ptr[j] + (int64_t)(q - lo_start[j])] = (int32_t)i;
+}
+
+inline unsigned grid_for(size_t count, unsigned block = kBlock) {
+  size_t g = (count + block - 1) / block;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+inline unsigned tiles_for(size_t count) { return (unsigned)((count + kTile - 1) / kTile); }
+
+}  // namespace
+
+// ===========================================================================
+// launchers
+
+void launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s) {
+  if (!count) return;
+  size_t g = (count + kBlock - 1) / kBlock;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_fill<uint32_t>, dim3((unsigned)g), dim3(kBlock), 0, s, p, v, count);
+}
+
+void launch_fill_u64(uint64_t* p, uint64_t v, size_t count, hipStream_t s) {
+  if (!count) return;
+  size_t g = (count + kBlock - 1) / kBlock;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_fill<uint64_t>, dim3((unsigned)g), dim3(kBlock), 0, s, p, v, count);
+}
+
+void launch_stage_init(uint32_t* bad, uint32_t* bbox, int d, hipStream_t s) {
+  hipLaunchKernelGGL(k_stage_init, dim3(1), dim3(kMaxDim), 0, s, bad, bbox, d);
+}
+
+void launch_stage(const float* pts, int64_t n, int d, float* soa, uint32_t* bad, uint32_t* bbox,
+                  hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_stage, dim3(grid_for((size_t)n)), dim3(kBlock), 0, s, pts, n, d, soa, bad,
+                     bbox);
+}
+
+template <int D>
+static void keys_dispatch(const float* soa, int64_t n, int d, int t0, int tb, const double* R,
+                          const double* u, double inv_c, const int64_t* klo,
+                          const KeyLayout* layout, uint64_t* keys, uint32_t* vals, uint32_t* err,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_keys<D>, dim3(grid_for((size_t)n)), dim3(kBlock), 0, s, soa, n, d, t0, tb, R,
+                     u, inv_c, klo, layout, keys, vals, err);
+}
+
+void launch_keys(const float* soa, int64_t n, int d, int t0, int tb, const double* R,
+                 const double* u, double inv_c, const int64_t* klo, const KeyLayout* layout,
+                 uint64_t* keys, uint32_t* vals, uint32_t* err, hipStream_t s) {
+  if (n <= 0) return;
+#define RTG_KEYS_CASE(DV) \
+  case DV: keys_dispatch<DV>(soa, n, d, t0, tb, R, u, inv_c, klo, layout, keys, vals, err, s); break;
+  switch (d) {
+    RTG_KEYS_CASE(1) RTG_KEYS_CASE(2) RTG_KEYS_CASE(3) RTG_KEYS_CASE(4) RTG_KEYS_CASE(5)
+    RTG_KEYS_CASE(6) RTG_KEYS_CASE(7) RTG_KEYS_CASE(8) RTG_KEYS_CASE(9) RTG_KEYS_CASE(10)
+    RTG_KEYS_CASE(11) RTG_KEYS_CASE(12) RTG_KEYS_CASE(13) RTG_KEYS_CASE(14) RTG_KEYS_CASE(15)
+    RTG_KEYS_CASE(16)
+    default: keys_dispatch<0>(soa, n, d, t0, tb, R, u, inv_c, klo, layout, keys, vals, err, s);
+  }
+#undef RTG_KEYS_CASE
+}
+
+template <int D>
+static void coords_dispatch(const float* soa, int64_t n, int d, const double* R, const double* u,
+                            double inv_c, int64_t* kappa, uint32_t* err, hipStream_t s) {
+  hipLaunchKernelGGL(k_cell_coords<D>, dim3(grid_for((size_t)n)), dim3(kBlock), 0, s, soa, n, d, R,
+                     u, inv_c, kappa, err);
+}
+
+void launch_cell_coords(const float* soa, int64_t n, int d, const double* R, const double* u,
+                        double inv_c, int64_t* kappa, uint32_t* err, hipStream_t s) {
+  if (n <= 0) return;
+#define RTG_COORDS_CASE(DV) \
+  case DV: coords_dispatch<DV>(soa, n, d, R, u, inv_c, kappa, err, s); break;
+  switch (d) {
+    RTG_COORDS_CASE(1) RTG_COORDS_CASE(2) RTG_COORDS_CASE(3) RTG_COORDS_CASE(4)
+    RTG_COORDS_CASE(5) RTG_COORDS_CASE(6) RTG_COORDS_CASE(7) RTG_COORDS_CASE(8)
+    RTG_COORDS_CASE(9) RTG_COORDS_CASE(10) RTG_COORDS_CASE(11) RTG_COORDS_CASE(12)
+    RTG_COORDS_CASE(13) RTG_COORDS_CASE(14) RTG_COORDS_CASE(15) RTG_COORDS_CASE(16)
+    default: coords_dispatch<0>(soa, n, d, R, u, inv_c, kappa, err, s);
+  }
+#undef RTG_COORDS_CASE
+}
+
+size_t scan_scratch_elems(size_t count) {
+  size_t total = 0;
+  while (count > (size_t)kScanTile) {
+    count = (count + kScanTile - 1) / kScanTile;
+    total += count;
+  }
+  return total + 1;
+}
+
+template <typename T>
+static void scan_rec(const T* in, T* out, size_t count, T* total, T* scratch, hipStream_t s) {
+  if (count == 0) {
+    if (total) hipLaunchKernelGGL(k_fill<T>, dim3(1), dim3(64), 0, s, total, (T)0, (size_t)1);
+    return;
+  }
+  if (count <= (size_t)kScanTile) {
+    hipLaunchKernelGGL(k_scan_apply<T>, dim3(1), dim3(kBlock), 0, s, in, out, count,
+                       (const T*)nullptr, total);
+    return;
+  }
+  const size_t nb = (count + kScanTile - 1) / kScanTile;
+  T* sums = scratch;
+  hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(kBlock), 0, s, in, count, sums);
+  scan_rec<T>(sums, sums, nb, (T*)nullptr, scratch + nb, s);
+  hipLaunchKernelGGL(k_scan_apply<T>, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, count,
+                     (const T*)sums, total);
+}
+
+void scan_exclusive_u32(const uint32_t* in, uint32_t* out, size_t count, uint32_t* total,
+                        uint32_t* scratch, hipStream_t s) {
+  scan_rec<uint32_t>(in, out, count, total, scratch, s);
+}
+
+void scan_exclusive_u64(const uint64_t* in, uint64_t* out, size_t count, uint64_t* total,
+                        uint64_t* scratch, hipStream_t s) {
+  scan_rec<uint64_t>(in, out, count, total, scratch, s);
+}
+
+size_t radix_scratch_elems(size_t count) {
+  const size_t h = (size_t)256 * tiles_for(count);
+  return h + scan_scratch_elems(h);
+}
+
+int radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+               size_t count, int begin_bit, int end_bit, uint32_t* scratch, hipStream_t s) {
+  if (count <= 1 || end_bit <= begin_bit) return 0;
+  const unsigned ntiles = tiles_for(count);
+  uint32_t* hist = scratch;
+  uint32_t* sscr = scratch + (size_t)256 * ntiles;
+  uint64_t *kin = keys, *kout = keys_alt;
+  uint32_t *vin = vals, *vout = vals_alt;
+  int where = 0;
+  for (int b = begin_bit; b < end_bit; b += kRadixBits) {
+    const int nbits = (end_bit - b) < kRadixBits ? (end_bit - b) : kRadixBits;
+    hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kBlock), 0, s, kin, count, b, nbits, hist,
+                       ntiles);
+    scan_rec<uint32_t>(hist, hist, (size_t)256 * ntiles, (uint32_t*)nullptr, sscr, s);
+    if (vals)
+      hipLaunchKernelGGL(k_radix_scatter<true>, dim3(ntiles), dim3(kBlock), 0, s, kin, vin, kout,
+                         vout, count, b, nbits, hist, ntiles);
+    else
+      hipLaunchKernelGGL(k_radix_scatter<false>, dim3(ntiles), dim3(kBlock), 0, s, kin,
+                         (const uint32_t*)nullptr, kout, (uint32_t*)nullptr, count, b, nbits, hist,
+                         ntiles);
+    uint64_t* tk = kin; kin = kout; kout = tk;
+    uint32_t* tv = vin; vin = vout; vout = tv;
+    where ^= 1;
+  }
+  return where;
+}
+
+void launch_run_count(const uint64_t* keys, size_t count, uint32_t* head_cnt, uint32_t* tail_cnt,
+                      hipStream_t s) {
+  if (!count) return;
+  hipLaunchKernelGGL(k_run_count, dim3(tiles_for(count)), dim3(kBlock), 0, s, keys, count, head_cnt,
+                     tail_cnt);
+}
+
+void launch_run_write(const uint64_t* keys, size_t count, const uint32_t* head_off,
+                      const uint32_t* tail_off, uint32_t* start, uint32_t* end, hipStream_t s) {
+  if (!count) return;
+  hipLaunchKernelGGL(k_run_write, dim3(tiles_for(count)), dim3(kBlock), 0, s, keys, count, head_off,
+                     tail_off, start, end);
+}
+
+void launch_cell_work(const uint32_t* start, const uint32_t* end, const uint32_t* ncells,
+                      uint64_t* items, uint64_t* tests, size_t max_cells, hipStream_t s) {
+  if (!max_cells) return;
+  hipLaunchKernelGGL(k_cell_work, dim3(grid_for(max_cells)), dim3(kBlock), 0, s, start, end, ncells,
+                     items, tests, max_cells);
+}
+
+template <int D>
+static void pairs_dispatch(const float* pts, int d, const uint32_t* sidx, const uint32_t* start,
+                           const uint32_t* end, const uint64_t* item_off, const uint32_t* ncells,
+                           uint64_t total_items, PairTest test, uint64_t* cand, uint64_t cap,
+                           unsigned long long* cand_count, unsigned long long* rechecks,
+                           unsigned long long* next_item, hipStream_t s) {
+  uint64_t blocks = (total_items + kWaves - 1) / kWaves;
+  const uint64_t max_blocks = 256ull * 8ull;  // 256 CUs, several resident blocks each
+  if (blocks > max_blocks) blocks = max_blocks;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_cell_pairs<D>, dim3((unsigned)blocks), dim3(kBlock), 0, s, pts, d, sidx,
+                     start, end, item_off, ncells, total_items, test, cand, cap, cand_count,
+                     rechecks, next_item);
+}
+
+void launch_cell_pairs(const float* pts, int d, const uint32_t* sidx, const uint32_t* start,
+                       const uint32_t* end, const uint64_t* item_off, const uint32_t* ncells,
+                       uint64_t total_items, PairTest test, uint64_t* cand, uint64_t cap,
+                       unsigned long long* cand_count, unsigned long long* rechecks,
+                       unsigned long long* next_item, hipStream_t s) {
+  if (!total_items) return;
+  hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, next_item, 0ull,
+                     (size_t)1);
+#define RTG_PAIRS_CASE(DV)                                                                    \
+  case DV:                                                                                    \
+    pairs_dispatch<DV>(pts, d, sidx, start, end, item_off, ncells, total_items, test, cand, \
+                       cap, cand_count, rechecks, next_item, s);                            \
+    break;
+  switch (d) {
+    RTG_PAIRS_CASE(1) RTG_PAIRS_CASE(2) RTG_PAIRS_CASE(3) RTG_PAIRS_CASE(4) RTG_PAIRS_CASE(5)
+    RTG_PAIRS_CASE(6) RTG_PAIRS_CASE(7) RTG_PAIRS_CASE(8) RTG_PAIRS_CASE(9) RTG_PAIRS_CASE(10)
+    RTG_PAIRS_CASE(11) RTG_PAIRS_CASE(12) RTG_PAIRS_CASE(13) RTG_PAIRS_CASE(14)
+    RTG_PAIRS_CASE(15) RTG_PAIRS_CASE(16)
+    default:
+      pairs_dispatch<0>(pts, d, sidx, start, end, item_off, ncells, total_items, test, cand, cap,
+                        cand_count, rechecks, next_item, s);
+  }
+#undef RTG_PAIRS_CASE
+}
+
+void launch_unique_count(const uint64_t* keys, size_t count, uint32_t* tile_cnt, hipStream_t s) {
+  if (!count) return;
+  hipLaunchKernelGGL(k_unique_count, dim3(tiles_for(count)), dim3(kBlock), 0, s, keys, count,
+                     tile_cnt);
+}
+
+void launch_unique_write(const uint64_t* keys, size_t count, const uint32_t* tile_off,
+                         uint64_t* out, hipStream_t s) {
+  if (!count) return;
+  hipLaunchKernelGGL(k_unique_write, dim3(tiles_for(count)), dim3(kBlock), 0, s, keys, count,
+                     tile_off, out);
+}
+
+void launch_swap_pairs(const uint64_t* pairs, size_t count, int pair_bits, uint64_t* swapped,
+                       hipStream_t s) {
+  if (!count) return;
+  hipLaunchKernelGGL(k_swap_pairs, dim3(grid_for(count)), dim3(kBlock), 0, s, pairs, count,
+                     pair_bits, swapped);
+}
+
+void launch_row_runs(const uint64_t* keys, size_t count, int pair_bits, uint32_t* rstart,
+                     uint32_t* rend, hipStream_t s) {
+  if (!count) return;
+  hipLaunchKernelGGL(k_row_runs, dim3(grid_for(count)), dim3(kBlock), 0, s, keys, count, pair_bits,
+                     rstart, rend);
+}
+
+void launch_row_degree(const uint32_t* lo_start, const uint32_t* lo_end, const uint32_t* up_start,
+                       const uint32_t* up_end, int64_t n, uint64_t* deg, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_row_degree, dim3(grid_for((size_t)n)), dim3(kBlock), 0, s, lo_start, lo_end,
+                     up_start, up_end, n, deg);
+}
+
+void launch_csr_fill_upper(const uint64_t* up, size_t count, int pair_bits, const int64_t* row_ptr,
+                           const uint32_t* lo_start, const uint32_t* lo_end,
+                           const uint32_t* up_start, int32_t* col, hipStream_t s) {
+  if (!count) return;
+  hipLaunchKernelGGL(k_csr_fill_upper, dim3(grid_for(count)), dim3(kBlock), 0, s, up, count,
+                     pair_bits, row_ptr, lo_start, lo_end, up_start, col);
+}
+
+void launch_csr_fill_lower(const uint64_t* lo, size_t count, int pair_bits, const int64_t* row_ptr,
+                           const uint32_t* lo_start, int32_t* col, hipStream_t s) {
+  if (!count) return;
+  hipLaunchKernelGGL(k_csr_fill_lower, dim3(grid_for(count)), dim3(kBlock), 0, s, lo, count,
+                     pair_bits, row_ptr, lo_start, col);
+}
+
+}  // namespace rtgk

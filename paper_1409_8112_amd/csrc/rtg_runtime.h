@@ -1,0 +1,103 @@
+// rtg_runtime.h -- host runtime of the RTG library: device-memory arena,
+// context, key-packing plan.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "../../include/rtg.h"
+#include "rtg_internal.h"
+
+namespace rtg {
+
+// First-fit sub-allocator over one device buffer (the context's memory
+// budget).  Host-side bookkeeping only; blocks are 256-byte aligned.
+class Arena {
+ public:
+  static constexpr size_t kAlign = 256;
+  Arena(char* base, size_t bytes);
+  void* alloc(size_t bytes);  // nullptr when no free block is large enough
+  void release(void* p);
+  size_t largest_free() const;
+  size_t size() const { return size_; }
+  size_t in_use() const { return in_use_; }
+  size_t peak() const { return peak_; }
+
+ private:
+  char* base_ = nullptr;
+  size_t size_ = 0, in_use_ = 0, peak_ = 0;
+  std::map<size_t, size_t> free_;  // offset -> length
+  std::map<size_t, size_t> used_;  // offset -> length
+};
+
+// How cell vectors are packed into the sort key for one query.
+struct Packing {
+  rtgk::KeyLayout layout{};
+  std::vector<int64_t> klo;  // [k][d] origin of each packed field
+  int tb = 1;                // grids per sort
+  int seg_bits = 0;          // bits of the grid id above the cell fields
+  int key_bits = 0;          // seg_bits + cell_bits
+  bool truncated = false;    // some field narrower than its span (aliasing)
+};
+
+int make_transforms(uint64_t seed, int32_t k, int32_t d, uint32_t flags, double* R, double* u);
+int min_field_bits(double alpha);
+int plan_packing(int d, int k, const double* R, const double* u, double inv_c, double alpha,
+                 const float* lo, const float* hi, int64_t n, size_t budget_bytes, Packing& P);
+int validate_query(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha);
+int check_device_pointer(const void* p, int device);
+
+struct Result {
+  void* mem;
+  int64_t n, nnz;
+  int64_t* row_ptr;
+  int32_t* col;
+};
+
+struct Ctx {
+  Ctx(int dev, hipStream_t s);
+  ~Ctx();
+
+  int device;
+  hipStream_t stream;
+  bool own_arena = false;
+  void* arena_mem = nullptr;
+  std::unique_ptr<Arena> arena;
+  void* host_stage = nullptr;  // pinned staging for scalar read-backs
+  bool poisoned = false;
+  bool timing = false;
+  hipEvent_t ev[9] = {};
+  rtg_stats stats{};
+  std::mutex mu;  // one pipeline call at a time
+  std::map<uint64_t, Result> results;
+  uint64_t next_handle = 1;
+
+  int hip_fail(hipError_t e, const char* what);
+  void* dalloc(size_t bytes);
+  void dfree(void* p);
+  int sync();
+  int read_back(const void* dev, size_t bytes, void* host);
+  int upload(void* dev, const void* host, size_t bytes);
+  void mark(int phase);
+  uint64_t keep_result(void* mem, int64_t n, int64_t nnz, int64_t* row_ptr, int32_t* col);
+  int release(uint64_t handle);
+  int make_empty_result(int64_t n, rtg_csr* out);
+
+  int all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha,
+                const double* R, const double* u, uint32_t flags, rtg_csr* out);
+  int debug_cell_coords(const float* points, int64_t n, int32_t d, double r, double alpha,
+                        const double* R, const double* u, int64_t* kappa_host);
+
+  // request loop (rtg_server.cpp)
+  void stop_server() {}
+};
+
+}  // namespace rtg

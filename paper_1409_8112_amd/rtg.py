@@ -1,0 +1,291 @@
+"""Thin Python binding of the RTG library (include/rtg.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of librtg.so.  PyTorch supplies device memory (the context's arena is
+one torch tensor) and the HIP stream; results come back as zero-copy torch
+views into that arena, valid until released.
+
+The library must be built (``paper_1409_8112_amd/build.py``); if it is
+missing it is built on first use.  There is no CPU fallback: without the
+library or a GPU every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import build as _build
+
+OK, EAGAIN, EINVAL, ENOMEM, ERANGE, EDEVICE, ENOENT = 0, 1, -1, -2, -3, -4, -5
+NO_ROTATE, UPPER_ONLY = 1, 2
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+class RTGError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+class rtg_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("handle", ctypes.c_uint64), ("pairs", ctypes.c_int64)]
+
+
+class rtg_query(ctypes.Structure):
+    _fields_ = [("points", ctypes.c_void_p), ("n", ctypes.c_int64), ("d", ctypes.c_int32),
+                ("r", ctypes.c_double), ("k", ctypes.c_int32), ("alpha", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32)]
+
+
+class rtg_stats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "n", "d", "k", "point_transforms", "cells", "tests", "candidates", "band_rechecks",
+        "unique_pairs")] + [(name, ctypes.c_int32) for name in (
+            "key_bits", "key_passes", "pair_bits", "transforms_per_sort")] + [
+        (name, ctypes.c_double) for name in (
+            "ms_stage", "ms_keys", "ms_key_sort", "ms_cells", "ms_pairs", "ms_pair_sort",
+            "ms_unique", "ms_csr", "ms_total")]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+def lib() -> ctypes.CDLL:
+    """Load librtg.so (building it if it has not been built)."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(_build.LIB_PATH):
+                _build.build()
+            L = ctypes.CDLL(_build.LIB_PATH)
+            vp, i64, i32, u64, u32, f64 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                           ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double)
+            sig = {
+                "rtg_create": [ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.c_size_t, vp],
+                "rtg_destroy": [vp],
+                "rtg_all_pairs": [vp, vp, i64, i32, f64, i32, f64, u64, u32,
+                                  ctypes.POINTER(rtg_csr)],
+                "rtg_all_pairs_with_transforms": [vp, vp, i64, i32, f64, i32, f64, vp, vp, u32,
+                                                  ctypes.POINTER(rtg_csr)],
+                "rtg_all_pairs_batched": [vp, ctypes.POINTER(rtg_query), i32,
+                                          ctypes.POINTER(rtg_csr)],
+                "rtg_submit": [vp, ctypes.POINTER(rtg_query), ctypes.POINTER(u64)],
+                "rtg_poll": [vp, u64, ctypes.POINTER(rtg_csr)],
+                "rtg_release": [vp, u64],
+                "rtg_make_transforms": [u64, i32, i32, u32, vp, vp],
+                "rtg_set_timing": [vp, ctypes.c_int],
+                "rtg_get_stats": [vp, ctypes.POINTER(rtg_stats)],
+                "rtg_debug_cell_coords": [vp, vp, i64, i32, f64, f64, vp, vp, vp],
+            }
+            for name, args in sig.items():
+                fn = getattr(L, name)
+                fn.argtypes = args
+                fn.restype = ctypes.c_int
+            L.rtg_strerror.argtypes = [ctypes.c_int]
+            L.rtg_strerror.restype = ctypes.c_char_p
+            _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().rtg_strerror(code).decode()
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != OK:
+        raise RTGError(rc, what)
+
+
+def rtg_make_transforms(seed: int, k: int, d: int, flags: int = 0):
+    """(R [k,d,d], u [k,d]) float64, the library's seeded transforms."""
+    R = np.zeros((k, d, d), dtype=np.float64)
+    u = np.zeros((k, d), dtype=np.float64)
+    _check(lib().rtg_make_transforms(seed & (2**64 - 1), k, d, flags, R.ctypes.data,
+                                     u.ctypes.data), "rtg_make_transforms")
+    return R, u
+
+
+make_transforms = rtg_make_transforms
+
+
+@dataclass
+class Result:
+    """A device-resident neighbour list (views into the context's arena)."""
+    ctx: "Context"
+    handle: int
+    n: int
+    nnz: int
+    pairs: int
+    row_ptr: "object"  # torch.int64 [n+1], cuda
+    col: "object"      # torch.int32 [nnz], cuda
+    released: bool = False
+
+    def to_numpy(self):
+        return self.row_ptr.cpu().numpy().copy(), self.col.cpu().numpy().copy()
+
+    def release(self) -> None:
+        if not self.released:
+            self.ctx.rtg_release(self.handle)
+            self.released = True
+
+
+class Context:
+    """An RTG context on one GPU: an arena of `arena_bytes` device memory from
+    torch and torch's current HIP stream."""
+
+    def __init__(self, device: int = 0, arena_bytes: int | None = None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("RTG needs a ROCm GPU; none is visible")
+        self.torch = torch
+        self.device = device
+        with torch.cuda.device(device):
+            if arena_bytes is None:
+                free, _ = torch.cuda.mem_get_info(device)
+                arena_bytes = int(min(64 << 30, free * 0.6))
+            self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=f"cuda:{device}")
+            self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.arena_base = self.arena.data_ptr()
+        self.arena_bytes = arena_bytes
+        h = ctypes.c_void_p()
+        _check(lib().rtg_create(ctypes.byref(h), device, ctypes.c_void_p(self.arena_base),
+                                arena_bytes, ctypes.c_void_p(self.stream.cuda_stream)),
+               "rtg_create")
+        self.h = h
+
+    # -- lifetime --------------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "h", None) and self.h.value:
+            lib().rtg_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- results -----------------------------------------------------------------
+    def _view(self, ptr: int, count: int, dtype):
+        t = self.torch
+        if count == 0:
+            return t.empty(0, dtype=dtype, device=self.arena.device)
+        off = ptr - self.arena_base
+        nbytes = count * t.empty(0, dtype=dtype).element_size()
+        if off < 0 or off + nbytes > self.arena_bytes:
+            raise RuntimeError("result outside the arena")
+        return self.arena[off:off + nbytes].view(dtype)
+
+    def _result(self, c: rtg_csr) -> Result:
+        t = self.torch
+        return Result(self, int(c.handle), int(c.n), int(c.nnz), int(c.pairs),
+                      self._view(c.row_ptr, int(c.n) + 1, t.int64),
+                      self._view(c.col or 0, int(c.nnz), t.int32))
+
+    def _points(self, points):
+        if points.dtype != self.torch.float32:
+            raise TypeError("points must be a float32 tensor")
+        if points.dim() != 2 or not points.is_cuda or not points.is_contiguous():
+            raise ValueError("points must be a contiguous [n, d] CUDA tensor")
+        return points
+
+    # -- calls -------------------------------------------------------------------
+    def rtg_all_pairs(self, points, r: float, k: int, alpha: float, seed: int,
+                      flags: int = 0) -> Result:
+        p = self._points(points)
+        out = rtg_csr()
+        _check(lib().rtg_all_pairs(self.h, p.data_ptr(), p.shape[0], p.shape[1], float(r), int(k),
+                                   float(alpha), seed & (2**64 - 1), flags, ctypes.byref(out)),
+               "rtg_all_pairs")
+        return self._result(out)
+
+    def rtg_all_pairs_with_transforms(self, points, r: float, alpha: float, R, u,
+                                      flags: int = 0) -> Result:
+        p = self._points(points)
+        R = np.ascontiguousarray(R, dtype=np.float64)
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        k, d = R.shape[0], p.shape[1]
+        if R.shape != (k, d, d) or u.shape != (k, d):
+            raise ValueError("R must be [k,d,d] and u [k,d]")
+        out = rtg_csr()
+        _check(lib().rtg_all_pairs_with_transforms(self.h, p.data_ptr(), p.shape[0], d, float(r), k,
+                                                   float(alpha), R.ctypes.data, u.ctypes.data,
+                                                   flags, ctypes.byref(out)),
+               "rtg_all_pairs_with_transforms")
+        return self._result(out)
+
+    def rtg_all_pairs_batched(self, queries) -> list[Result]:
+        """queries: list of dicts with points, r, k, alpha, seed, flags."""
+        nq = len(queries)
+        qs = (rtg_query * max(nq, 1))()
+        for i, q in enumerate(queries):
+            p = self._points(q["points"])
+            qs[i] = rtg_query(p.data_ptr(), p.shape[0], p.shape[1], float(q["r"]), int(q["k"]),
+                              float(q["alpha"]), q.get("seed", 0) & (2**64 - 1), q.get("flags", 0))
+        outs = (rtg_csr * max(nq, 1))()
+        _check(lib().rtg_all_pairs_batched(self.h, qs, nq, outs), "rtg_all_pairs_batched")
+        return [self._result(outs[i]) for i in range(nq)]
+
+    def rtg_submit(self, points, r: float, k: int, alpha: float, seed: int, flags: int = 0) -> int:
+        p = self._points(points)
+        q = rtg_query(p.data_ptr(), p.shape[0], p.shape[1], float(r), int(k), float(alpha),
+                      seed & (2**64 - 1), flags)
+        t = ctypes.c_uint64()
+        _check(lib().rtg_submit(self.h, ctypes.byref(q), ctypes.byref(t)), "rtg_submit")
+        return int(t.value)
+
+    def rtg_poll(self, ticket: int):
+        """The Result when done, None while pending; raises on the request's error."""
+        out = rtg_csr()
+        rc = lib().rtg_poll(self.h, ticket, ctypes.byref(out))
+        if rc == EAGAIN:
+            return None
+        _check(rc, "rtg_poll")
+        return self._result(out)
+
+    def rtg_release(self, handle: int) -> None:
+        _check(lib().rtg_release(self.h, handle), "rtg_release")
+
+    def rtg_set_timing(self, on: bool) -> None:
+        _check(lib().rtg_set_timing(self.h, 1 if on else 0), "rtg_set_timing")
+
+    def rtg_get_stats(self) -> dict:
+        s = rtg_stats()
+        _check(lib().rtg_get_stats(self.h, ctypes.byref(s)), "rtg_get_stats")
+        return s.as_dict()
+
+    def rtg_debug_cell_coords(self, points, r: float, alpha: float, R_t, u_t) -> np.ndarray:
+        p = self._points(points)
+        n, d = p.shape
+        R_t = np.ascontiguousarray(R_t, dtype=np.float64)
+        u_t = np.ascontiguousarray(u_t, dtype=np.float64)
+        kap = np.zeros((n, d), dtype=np.int64)
+        _check(lib().rtg_debug_cell_coords(self.h, p.data_ptr(), n, d, float(r), float(alpha),
+                                           R_t.ctypes.data, u_t.ctypes.data, kap.ctypes.data),
+               "rtg_debug_cell_coords")
+        return kap
+
+    # short aliases
+    all_pairs = rtg_all_pairs
+    all_pairs_with_transforms = rtg_all_pairs_with_transforms
+    all_pairs_batched = rtg_all_pairs_batched
+    submit = rtg_submit
+    poll = rtg_poll
+    release = rtg_release
+    set_timing = rtg_set_timing
+    stats = rtg_get_stats
+    debug_cell_coords = rtg_debug_cell_coords

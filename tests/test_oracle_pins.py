@@ -221,3 +221,16 @@ def test_out_of_range_cells():
     with pytest.raises(oracle.OracleError) as e:
         oracle.rtg(p, 0.05, 1, 2.0, 0, oracle.NO_ROTATE)
     assert e.value.code == oracle.ERANGE
+
+
+def test_rows_oracle_matches_full_rows():
+    """The one-row-at-a-time oracle used for sampled checks at large sizes
+    returns exactly the rows of the full symmetric output."""
+    n, d, r, k, alpha = 500, 4, 0.25, 3, 1.7
+    p = workloads.uniform_points(n, d, seed=12)
+    R, u = oracle.make_transforms(5, k, d)
+    full = oracle.rtg_with_transforms(p, r, alpha, R, u)
+    rows = np.array([0, 7, 99, 250, 499, 7])
+    got = oracle.rtg_rows(p, r, alpha, R, u, rows)
+    for s, row in enumerate(rows):
+        assert np.array_equal(got[s], full.col[full.row_ptr[row]:full.row_ptr[row + 1]])
