@@ -84,6 +84,24 @@ typedef struct rtg_query {
   uint32_t flags;
 } rtg_query;
 
+/* Kernels (or kernel groups) whose launches the stats count and, when
+ * timing is on for them, time with HIP events on the context's stream. */
+enum {
+  RTG_K_STAGE = 0,         /* AoS -> SoA copy, finiteness, bounding box      */
+  RTG_K_KEYS = 1,          /* FP64 cell keys                                */
+  RTG_K_KEY_HIST = 2,      /* digit histogram, one launch per key-sort pass  */
+  RTG_K_KEY_SCATTER = 3,   /* LDS-staged scatter, one launch per pass        */
+  RTG_K_CELLS = 4,         /* runs of equal keys, tile-pair counts           */
+  RTG_K_PAIRS = 5,         /* same-cell pair tests and output                */
+  RTG_K_PAIR_HIST = 6,     /* digit histogram of the pair sort               */
+  RTG_K_PAIR_SCATTER = 7,  /* scatter of the pair sort                       */
+  RTG_K_UNIQUE = 8,        /* removal of repeated pairs                      */
+  RTG_K_CSR = 9,           /* neighbour-list build (incl. transposed sort)   */
+  RTG_K_SCAN = 10,         /* prefix sums                                    */
+  RTG_NKERNELS = 11
+};
+#define RTG_TIME_PHASES (1u << 31) /* rtg_set_timing: per-phase events too */
+
 /* Counters of the last completed call on a context (for measurement). */
 typedef struct rtg_stats {
   int64_t n, d, k;
@@ -100,6 +118,12 @@ typedef struct rtg_stats {
   /* Device time per phase in milliseconds (0 unless timing is on). */
   double ms_stage, ms_keys, ms_key_sort, ms_cells, ms_pairs, ms_pair_sort, ms_unique, ms_csr,
       ms_total;
+  /* Per kernel id (RTG_K_*): launches, algorithmic bytes moved (the data the
+   * method must read and write, summed over launches) and device time in
+   * milliseconds summed over launches (0 unless timed). */
+  int64_t kernel_launches[RTG_NKERNELS];
+  double kernel_bytes[RTG_NKERNELS];
+  double kernel_ms[RTG_NKERNELS];
 } rtg_stats;
 
 /* Create a context on HIP device `device`.
@@ -165,8 +189,11 @@ int rtg_release(rtg_ctx *ctx, uint64_t handle);
  * the "random orientation" of Sec. III.  Errors: RTG_EINVAL. */
 int rtg_make_transforms(uint64_t seed, int32_t k, int32_t d, uint32_t flags, double *R, double *u);
 
-/* Turn per-phase device timing (HIP events on the context's stream) on or off. */
-int rtg_set_timing(rtg_ctx *ctx, int on);
+/* Device timing with HIP events on the context's stream: bit i of `mask`
+ * times every launch of kernel id i (RTG_K_*), RTG_TIME_PHASES times the
+ * pipeline phases; 0 turns timing off.  Events add a few microseconds per
+ * timed launch. */
+int rtg_set_timing(rtg_ctx *ctx, uint32_t mask);
 
 /* Counters of the last completed rtg_all_pairs* call. */
 int rtg_get_stats(const rtg_ctx *ctx, rtg_stats *out);

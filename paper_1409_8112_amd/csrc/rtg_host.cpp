@@ -307,7 +307,53 @@ int Ctx::upload(void* dev, const void* host, size_t bytes) {
 }
 
 void Ctx::mark(int phase) {
-  if (timing) (void)hipEventRecord(ev[phase], stream);
+  if (timing_mask & RTG_TIME_PHASES) (void)hipEventRecord(ev[phase], stream);
+}
+
+void Ctx::kbegin(int kid) {
+  if (!(timing_mask & (1u << kid))) return;
+  const size_t pair = kpending.size();
+  while (kev.size() < 2 * (pair + 1)) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    kev.push_back(e);
+  }
+  (void)hipEventRecord(kev[2 * pair], stream);
+  kpending.emplace_back(kid, (int)pair);
+}
+
+void Ctx::kend(int kid, double bytes) {
+  if (kstats) {
+    kstats->kernel_launches[kid] += 1;
+    kstats->kernel_bytes[kid] += bytes;
+  }
+  if (!(timing_mask & (1u << kid)) || kpending.empty()) return;
+  const auto& last = kpending.back();
+  if (last.first != kid) return;
+  (void)hipEventRecord(kev[2 * last.second + 1], stream);
+}
+
+void Ctx::kfinish() {
+  for (const auto& pk : kpending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, kev[2 * pk.second], kev[2 * pk.second + 1]) == hipSuccess &&
+        kstats)
+      kstats->kernel_ms[pk.first] += ms;
+  }
+  kpending.clear();
+}
+
+static void timer_begin(void* self, int kid) { static_cast<Ctx*>(self)->kbegin(kid); }
+static void timer_end(void* self, int kid, double bytes) {
+  static_cast<Ctx*>(self)->kend(kid, bytes);
+}
+
+rtgk::LaunchTimer Ctx::timer() {
+  rtgk::LaunchTimer t;
+  t.self = this;
+  t.begin = timer_begin;
+  t.end = timer_end;
+  return t;
 }
 
 uint64_t Ctx::keep_result(void* mem, int64_t n, int64_t nnz, int64_t* row_ptr, int32_t* col) {
@@ -406,6 +452,16 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
   st.d = d;
   st.k = k;
   st.point_transforms = n * k;
+  kstats = &st;
+  kpending.clear();
+  struct Detach {
+    Ctx& c;
+    ~Detach() {
+      c.kpending.clear();
+      c.kstats = nullptr;
+    }
+  } detach{*this};
+  const LaunchTimer tm = timer();
   if (n <= 1) {
     // Still reject non-finite coordinates, as for any other n.
     if (n == 1) {
@@ -442,7 +498,9 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
   launch_stage_init(bad, bbox, d, stream);
   launch_fill_u32(err, 0u, 1, stream);
   launch_fill_u64(reinterpret_cast<uint64_t*>(counters), 0ull, 4, stream);
+  kbegin(RTG_K_STAGE);
   launch_stage(points, n, d, soa, bad, bbox, stream);
+  kend(RTG_K_STAGE, 8.0 * (double)n * d);
   mark(1);
   std::vector<uint32_t> hb(2 + 2 * kMaxDim);
   if ((rc = read_back(flags_dev, sizeof(uint32_t) * (2 + 2 * d), hb.data()))) return rc;
@@ -493,10 +551,12 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
   for (int t0 = 0; t0 < k; t0 += P.tb) {
     const int tb = std::min(P.tb, k - t0);
     const size_t N = (size_t)n * tb;
+    kbegin(RTG_K_KEYS);
     launch_keys(soa, n, d, t0, tb, Rd, ud, inv_c, klo_d, layout_d, keys, vals, err, stream);
+    kend(RTG_K_KEYS, 4.0 * (double)n * d + 12.0 * (double)N);
     mark(2);
     const int where = radix_sort(keys, vals, keys_alt, vals_alt, N, 0, P.key_bits, radix_scr,
-                                 stream);
+                                 stream, &tm, RTG_K_KEY_HIST, RTG_K_KEY_SCATTER);
     const uint64_t* skeys = where ? keys_alt : keys;
     const uint32_t* sidx = where ? vals_alt : vals;
     mark(3);
@@ -506,10 +566,12 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
     uint32_t* tcnt = radix_scr + nt;
     uint32_t* tot = radix_scr + 2 * nt;  // [0] heads, [1] tails
     uint32_t* sscr = radix_scr + 2 * nt + 2;
+    kbegin(RTG_K_CELLS);
     launch_run_count(skeys, N, hcnt, tcnt, stream);
     scan_exclusive_u32(hcnt, hcnt, nt, tot, sscr, stream);
     scan_exclusive_u32(tcnt, tcnt, nt, tot + 1, sscr, stream);
     launch_run_write(skeys, N, hcnt, tcnt, cstart, cend, stream);
+    kend(RTG_K_CELLS, 16.0 * (double)N);
     uint32_t ncells_h = 0, errh0 = 0;
     if ((rc = read_back(tot, sizeof(uint32_t), &ncells_h))) return rc;
     // A cell coordinate out of range makes the grouping meaningless: stop
@@ -518,11 +580,13 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
     if (errh0) return RTG_ERANGE;
     uint64_t totals[2] = {0, 0};  // items, tests
     if (ncells_h) {
-      launch_cell_work(cstart, cend, tot, items, tests, ncells_h, stream);
+      kbegin(RTG_K_CELLS);
+      launch_cell_work(cstart, cend, tot, items, tests, ncells_h, counters + 3, stream);
       scan_exclusive_u64(items, items, ncells_h, scan64 + scan_scratch_elems(max_cells), scan64,
                          stream);
       scan_exclusive_u64(tests, tests, ncells_h, scan64 + scan_scratch_elems(max_cells) + 1,
                          scan64, stream);
+      kend(RTG_K_CELLS, 8.0 * (double)ncells_h + 32.0 * (double)ncells_h);
       if ((rc = read_back(scan64 + scan_scratch_elems(max_cells), sizeof(totals), totals)))
         return rc;
     }
@@ -548,10 +612,17 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
         cap = want;
       }
       launch_fill_u64(reinterpret_cast<uint64_t*>(counters), cand_total, 1, stream);
+      kbegin(RTG_K_PAIRS);
       launch_cell_pairs(points, d, sidx, cstart, cend, items, tot, totals[0], ptest, cand, cap,
                         counters, counters + 1, counters + 2, stream);
-      unsigned long long now = 0;
-      if ((rc = read_back(counters, sizeof(now), &now))) return rc;
+      unsigned long long cnt[4] = {0, 0, 0, 0};
+      // bytes: every member of a cell read once (index + coordinates), every
+      // pair within r written once
+      kend(RTG_K_PAIRS, 0.0);
+      if ((rc = read_back(counters, sizeof(cnt), cnt))) return rc;
+      const unsigned long long now = cnt[0];
+      st.kernel_bytes[RTG_K_PAIRS] +=
+          (4.0 + 4.0 * d) * (double)cnt[3] + 8.0 * (double)(now - cand_total);
       if (now <= cap) {
         cand_total = now;
         break;
@@ -588,19 +659,23 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
     uint64_t* cand_alt = S.get<uint64_t>(C);
     uint32_t* scr = S.get<uint32_t>(radix_scratch_elems(C) + 16);
     if (!cand_alt || !scr) return RTG_ENOMEM;
-    const int where = radix_sort(cand, nullptr, cand_alt, nullptr, C, 0, 2 * pair_bits, scr, stream);
+    const int where = radix_sort(cand, nullptr, cand_alt, nullptr, C, 0, 2 * pair_bits, scr, stream,
+                                 &tm, RTG_K_PAIR_HIST, RTG_K_PAIR_SCATTER);
     const uint64_t* sc = where ? cand_alt : cand;
     uint64_t* dst = where ? cand : cand_alt;
     mark(6);
     const size_t nt = (C + kTile - 1) / kTile;
     uint32_t* tc = scr;
     uint32_t* tot = scr + nt;
+    kbegin(RTG_K_UNIQUE);
     launch_unique_count(sc, C, tc, stream);
     scan_exclusive_u32(tc, tc, nt, tot, tot + 1, stream);
     launch_unique_write(sc, C, tc, dst, stream);
+    kend(RTG_K_UNIQUE, 16.0 * (double)C);
     uint32_t uh = 0;
     if ((rc = read_back(tot, sizeof(uh), &uh))) return rc;
     U = uh;
+    st.kernel_bytes[RTG_K_UNIQUE] += 8.0 * (double)U;
     uniq = dst;
     mark(7);
   } else {
@@ -631,6 +706,7 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
       dfree(res);
       return RTG_ENOMEM;
     }
+    kbegin(RTG_K_CSR);
     launch_fill_u32(up_s, 0u, (size_t)n, stream);
     launch_fill_u32(up_e, 0u, (size_t)n, stream);
     if (both) {
@@ -650,6 +726,7 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
         }
         launch_swap_pairs(uniq, U, pair_bits, sw, stream);
         const int where = radix_sort(sw, nullptr, sw_alt, nullptr, U, 0, 2 * pair_bits, scr, stream);
+        // (its launches count inside the CSR group)
         lower = where ? sw_alt : sw;
         launch_row_runs(lower, U, pair_bits, lo_s, lo_e, stream);
       }
@@ -661,6 +738,8 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
       launch_csr_fill_upper(uniq, U, pair_bits, row_ptr, lo_s, lo_e, up_s, col, stream);
       if (both) launch_csr_fill_lower(lower, U, pair_bits, row_ptr, lo_s, col, stream);
     }
+    // read the pairs (twice when both rows), write row_ptr and col
+    kend(RTG_K_CSR, (both ? 16.0 : 8.0) * (double)U + 8.0 * (double)(n + 1) + 4.0 * (double)nnz);
     mark(8);
     if ((rc = sync())) {
       dfree(res);
@@ -671,7 +750,8 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
     dfree(res);
     return rc;
   }
-  if (timing) {
+  kfinish();
+  if (timing_mask & RTG_TIME_PHASES) {
     float ms[8] = {0};
     for (int q = 0; q < 8; ++q) (void)hipEventElapsedTime(&ms[q], ev[q], ev[q + 1]);
     st.ms_stage = ms[0];
@@ -810,9 +890,11 @@ int rtg_make_transforms(uint64_t seed, int32_t k, int32_t d, uint32_t flags, dou
   return rtg::make_transforms(seed, k, d, flags, R, u);
 }
 
-int rtg_set_timing(rtg_ctx* ctx, int on) {
+int rtg_set_timing(rtg_ctx* ctx, uint32_t mask) {
   if (!ctx) return RTG_EINVAL;
-  reinterpret_cast<Ctx*>(ctx)->timing = on != 0;
+  Ctx* c = reinterpret_cast<Ctx*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->timing_mask = mask;
   return RTG_OK;
 }
 

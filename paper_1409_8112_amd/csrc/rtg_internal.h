@@ -31,6 +31,19 @@ struct PairTest {
   int32_t pair_bits;  // bits of one index in a packed (i,j) pair
 };
 
+// Optional hook around kernel launches (HIP-event timing, byte accounting).
+struct LaunchTimer {
+  void* self = nullptr;
+  void (*begin)(void* self, int kid) = nullptr;
+  void (*end)(void* self, int kid, double bytes) = nullptr;
+  void on_begin(int kid) const {
+    if (begin) begin(self, kid);
+  }
+  void on_end(int kid, double bytes) const {
+    if (end) end(self, kid, bytes);
+  }
+};
+
 // --- staging --------------------------------------------------------------
 // AoS [n][d] -> SoA [d][n]; flags non-finite values; per-axis min/max as
 // order-preserving uint32 encodings (bbox[2j] = min, bbox[2j+1] = max).
@@ -67,8 +80,11 @@ void scan_exclusive_u64(const uint64_t* in, uint64_t* out, size_t count, uint64_
 // vals_alt); returns 0 if the result ends in keys/vals, 1 if in the *_alt.
 // scratch must hold radix_scratch_elems(count) u32.
 size_t radix_scratch_elems(size_t count);
+// timer (optional) sees each histogram launch as kid_hist and each scatter
+// launch as kid_scatter.
 int radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
-               size_t count, int begin_bit, int end_bit, uint32_t* scratch, hipStream_t s);
+               size_t count, int begin_bit, int end_bit, uint32_t* scratch, hipStream_t s,
+               const LaunchTimer* timer = nullptr, int kid_hist = 0, int kid_scatter = 0);
 
 // --- cells ----------------------------------------------------------------
 // Runs of equal keys with length >= 2 in a sorted key array: per tile counts
@@ -79,9 +95,11 @@ void launch_run_count(const uint64_t* keys, size_t count, uint32_t* head_cnt,
 // per-tile offsets.
 void launch_run_write(const uint64_t* keys, size_t count, const uint32_t* head_off,
                       const uint32_t* tail_off, uint32_t* start, uint32_t* end, hipStream_t s);
-// items[c] = number of 64x64 tile pairs of run c; tests[c] = L(L-1)/2.
+// items[c] = number of 64x64 tile pairs of run c; tests[c] = L(L-1)/2;
+// *members += sum of L.
 void launch_cell_work(const uint32_t* start, const uint32_t* end, const uint32_t* ncells,
-                      uint64_t* items, uint64_t* tests, size_t max_cells, hipStream_t s);
+                      uint64_t* items, uint64_t* tests, size_t max_cells,
+                      unsigned long long* members, hipStream_t s);
 
 // --- cell pairs -----------------------------------------------------------
 // One 64-wide wave per (cell, tile a, tile b) item; emits packed pairs

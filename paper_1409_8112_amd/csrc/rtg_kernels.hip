@@ -473,20 +473,29 @@ __global__ __launch_bounds__(kBlock) void k_run_write(const uint64_t* __restrict
   }
 }
 
-__global__ void k_cell_work(const uint32_t* __restrict__ start, const uint32_t* __restrict__ end,
-                            const uint32_t* __restrict__ ncells, uint64_t* __restrict__ items,
-                            uint64_t* __restrict__ tests, size_t max_cells) {
+__global__ __launch_bounds__(kBlock) void k_cell_work(const uint32_t* __restrict__ start,
+                                                      const uint32_t* __restrict__ end,
+                                                      const uint32_t* __restrict__ ncells,
+                                                      uint64_t* __restrict__ items,
+                                                      uint64_t* __restrict__ tests,
+                                                      size_t max_cells,
+                                                      unsigned long long* members) {
   const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= max_cells) return;
-  uint64_t it = 0, te = 0;
-  if (c < *ncells) {
-    const uint64_t L = end[c] - start[c];
+  uint64_t it = 0, te = 0, L = 0;
+  if (c < max_cells && c < *ncells) {
+    L = end[c] - start[c];
     const uint64_t nt = (L + kPairTile - 1) / kPairTile;
     it = nt * (nt + 1) / 2;
     te = L * (L - 1) / 2;
   }
-  items[c] = it;
-  tests[c] = te;
+  if (c < max_cells) {
+    items[c] = it;
+    tests[c] = te;
+  }
+  unsigned long long m = L;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m += __shfl_xor(m, o, 64);
+  if (lane_id() == 0 && m) atomicAdd(members, m);
 }
 
 __global__ __launch_bounds__(kBlock) void k_unique_count(const uint64_t* __restrict__ keys,
@@ -852,7 +861,11 @@ size_t radix_scratch_elems(size_t count) {
 }
 
 int radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
-               size_t count, int begin_bit, int end_bit, uint32_t* scratch, hipStream_t s) {
+               size_t count, int begin_bit, int end_bit, uint32_t* scratch, hipStream_t s,
+               const LaunchTimer* timer, int kid_hist, int kid_scatter) {
+  const LaunchTimer none;
+  const LaunchTimer& tm = timer ? *timer : none;
+  const double elem = vals ? 12.0 : 8.0;
   if (count <= 1 || end_bit <= begin_bit) return 0;
   const unsigned ntiles = tiles_for(count);
   uint32_t* hist = scratch;
@@ -862,9 +875,12 @@ int radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* val
   int where = 0;
   for (int b = begin_bit; b < end_bit; b += kRadixBits) {
     const int nbits = (end_bit - b) < kRadixBits ? (end_bit - b) : kRadixBits;
+    tm.on_begin(kid_hist);
     hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kBlock), 0, s, kin, count, b, nbits, hist,
                        ntiles);
+    tm.on_end(kid_hist, 8.0 * (double)count);
     scan_rec<uint32_t>(hist, hist, (size_t)256 * ntiles, (uint32_t*)nullptr, sscr, s);
+    tm.on_begin(kid_scatter);
     if (vals)
       hipLaunchKernelGGL(k_radix_scatter<true>, dim3(ntiles), dim3(kBlock), 0, s, kin, vin, kout,
                          vout, count, b, nbits, hist, ntiles);
@@ -872,6 +888,7 @@ int radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* val
       hipLaunchKernelGGL(k_radix_scatter<false>, dim3(ntiles), dim3(kBlock), 0, s, kin,
                          (const uint32_t*)nullptr, kout, (uint32_t*)nullptr, count, b, nbits, hist,
                          ntiles);
+    tm.on_end(kid_scatter, 2.0 * elem * (double)count);
     uint64_t* tk = kin; kin = kout; kout = tk;
     uint32_t* tv = vin; vin = vout; vout = tv;
     where ^= 1;
@@ -894,10 +911,11 @@ void launch_run_write(const uint64_t* keys, size_t count, const uint32_t* head_o
 }
 
 void launch_cell_work(const uint32_t* start, const uint32_t* end, const uint32_t* ncells,
-                      uint64_t* items, uint64_t* tests, size_t max_cells, hipStream_t s) {
+                      uint64_t* items, uint64_t* tests, size_t max_cells,
+                      unsigned long long* members, hipStream_t s) {
   if (!max_cells) return;
   hipLaunchKernelGGL(k_cell_work, dim3(grid_for(max_cells)), dim3(kBlock), 0, s, start, end, ncells,
-                     items, tests, max_cells);
+                     items, tests, max_cells, members);
 }
 
 template <int D>

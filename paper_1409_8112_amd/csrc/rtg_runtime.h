@@ -73,9 +73,13 @@ struct Ctx {
   std::unique_ptr<Arena> arena;
   void* host_stage = nullptr;  // pinned staging for scalar read-backs
   bool poisoned = false;
-  bool timing = false;
+  uint32_t timing_mask = 0;  // bit i: time kernel id i; RTG_TIME_PHASES: phases
   hipEvent_t ev[9] = {};
   rtg_stats stats{};
+  // per-launch timing: a pool of event pairs and the launches of this call
+  std::vector<hipEvent_t> kev;
+  std::vector<std::pair<int, int>> kpending;  // (kernel id, event pair)
+  rtg_stats* kstats = nullptr;                // stats of the call in flight
   std::mutex mu;  // one pipeline call at a time
   std::map<uint64_t, Result> results;
   uint64_t next_handle = 1;
@@ -87,6 +91,10 @@ struct Ctx {
   int read_back(const void* dev, size_t bytes, void* host);
   int upload(void* dev, const void* host, size_t bytes);
   void mark(int phase);
+  void kbegin(int kid);
+  void kend(int kid, double bytes);
+  void kfinish();  // after a sync: add the timed launches to *kstats
+  rtgk::LaunchTimer timer();
   uint64_t keep_result(void* mem, int64_t n, int64_t nnz, int64_t* row_ptr, int32_t* col);
   int release(uint64_t handle);
   int make_empty_result(int64_t n, rtg_csr* out);

@@ -22,6 +22,11 @@ from . import build as _build
 
 OK, EAGAIN, EINVAL, ENOMEM, ERANGE, EDEVICE, ENOENT = 0, 1, -1, -2, -3, -4, -5
 NO_ROTATE, UPPER_ONLY = 1, 2
+# kernel ids of rtg_stats.kernel_* (RTG_K_* in rtg.h)
+KERNELS = ["stage", "keys", "key_hist", "key_scatter", "cells", "pairs", "pair_hist",
+           "pair_scatter", "unique", "csr", "scan"]
+NKERNELS = len(KERNELS)
+TIME_PHASES = 1 << 31
 
 _lib = None
 _lib_lock = threading.Lock()
@@ -52,10 +57,17 @@ class rtg_stats(ctypes.Structure):
             "key_bits", "key_passes", "pair_bits", "transforms_per_sort")] + [
         (name, ctypes.c_double) for name in (
             "ms_stage", "ms_keys", "ms_key_sort", "ms_cells", "ms_pairs", "ms_pair_sort",
-            "ms_unique", "ms_csr", "ms_total")]
+            "ms_unique", "ms_csr", "ms_total")] + [
+        ("kernel_launches", ctypes.c_int64 * NKERNELS),
+        ("kernel_bytes", ctypes.c_double * NKERNELS),
+        ("kernel_ms", ctypes.c_double * NKERNELS)]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if name.startswith("kernel_") else v
+        return out
 
 
 def lib() -> ctypes.CDLL:
@@ -81,7 +93,7 @@ def lib() -> ctypes.CDLL:
                 "rtg_poll": [vp, u64, ctypes.POINTER(rtg_csr)],
                 "rtg_release": [vp, u64],
                 "rtg_make_transforms": [u64, i32, i32, u32, vp, vp],
-                "rtg_set_timing": [vp, ctypes.c_int],
+                "rtg_set_timing": [vp, u32],
                 "rtg_get_stats": [vp, ctypes.POINTER(rtg_stats)],
                 "rtg_debug_cell_coords": [vp, vp, i64, i32, f64, f64, vp, vp, vp],
             }
@@ -260,8 +272,9 @@ class Context:
     def rtg_release(self, handle: int) -> None:
         _check(lib().rtg_release(self.h, handle), "rtg_release")
 
-    def rtg_set_timing(self, on: bool) -> None:
-        _check(lib().rtg_set_timing(self.h, 1 if on else 0), "rtg_set_timing")
+    def rtg_set_timing(self, mask: int) -> None:
+        """Bit i times kernel id i (KERNELS[i]); TIME_PHASES times the phases."""
+        _check(lib().rtg_set_timing(self.h, int(mask) & 0xFFFFFFFF), "rtg_set_timing")
 
     def rtg_get_stats(self) -> dict:
         s = rtg_stats()
