@@ -55,8 +55,11 @@ typedef enum rtg_status {
 } rtg_status;
 
 enum {
-  RTG_NO_ROTATE = 1u, /* shift-only grids (the paper's first algorithm)         */
-  RTG_UPPER_ONLY = 2u /* store each pair once, in the row of its smaller index */
+  RTG_NO_ROTATE = 1u,  /* shift-only grids (the paper's first algorithm)        */
+  RTG_UPPER_ONLY = 2u, /* store each pair once, in the row of its smaller index */
+  RTG_DEDUP_SORT = 4u  /* remove repeats by sorting all candidates (every grid's */
+                       /* pairs) and dropping equal neighbours, instead of the  */
+                       /* default first-owner rule; same result                 */
 };
 
 typedef struct rtg_ctx rtg_ctx;

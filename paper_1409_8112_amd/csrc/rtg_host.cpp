@@ -535,14 +535,30 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
   const size_t ntiles = (NB + kTile - 1) / kTile;
   uint32_t* radix_scr = S.get<uint32_t>(std::max(radix_scratch_elems(NB), 4 * ntiles + 8));
   const size_t max_cells = NB / 2 + 1;
+  const size_t max_units = max_cells + NB / kPairTile + 1;
   uint32_t* cstart = S.get<uint32_t>(max_cells);
   uint32_t* cend = S.get<uint32_t>(max_cells);
-  uint64_t* items = S.get<uint64_t>(max_cells);
+  uint32_t* units = S.get<uint32_t>(max_cells);
+  uint32_t* unit_cell = S.get<uint32_t>(max_units);
   uint64_t* tests = S.get<uint64_t>(max_cells);
-  uint64_t* scan64 = S.get<uint64_t>(scan_scratch_elems(max_cells) + 4);
-  if (!keys || !keys_alt || !vals || !vals_alt || !radix_scr || !cstart || !cend || !items ||
-      !tests || !scan64)
+  const size_t s64 = scan_scratch_elems(max_cells);
+  uint64_t* scan64 = S.get<uint64_t>(s64 + 4);
+  uint32_t* scan32 = S.get<uint32_t>(scan_scratch_elems(max_cells) + 4);
+  if (!keys || !keys_alt || !vals || !vals_alt || !radix_scr || !cstart || !cend || !units ||
+      !unit_cell || !tests || !scan64 || !scan32)
     return RTG_ENOMEM;
+
+  // First-owner filter (default): each pair is emitted only by the first grid
+  // whose cell holds both points, so the union needs no de-duplication.  It
+  // needs every point's packed cell key under every grid.
+  const bool first_owner = !(flags & RTG_DEDUP_SORT);
+  const int sig64 = P.layout.cell_bits > 32 ? 1 : 0;
+  void* sig = nullptr;
+  if (first_owner) {
+    sig = dalloc((size_t)n * k * (sig64 ? 8 : 4));
+    if (!sig) return RTG_ENOMEM;
+    S.held.push_back(sig);
+  }
 
   uint64_t cap = 0;
   uint64_t* cand = nullptr;
@@ -552,8 +568,10 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
     const int tb = std::min(P.tb, k - t0);
     const size_t N = (size_t)n * tb;
     kbegin(RTG_K_KEYS);
-    launch_keys(soa, n, d, t0, tb, Rd, ud, inv_c, klo_d, layout_d, keys, vals, err, stream);
-    kend(RTG_K_KEYS, 4.0 * (double)n * d + 12.0 * (double)N);
+    launch_keys(soa, n, d, t0, tb, Rd, ud, inv_c, klo_d, layout_d, keys, vals, err, sig, sig64, k,
+                stream);
+    kend(RTG_K_KEYS,
+         4.0 * (double)n * d + 12.0 * (double)N + (sig ? (sig64 ? 8.0 : 4.0) * (double)N : 0.0));
     mark(2);
     const int where = radix_sort(keys, vals, keys_alt, vals_alt, N, 0, P.key_bits, radix_scr,
                                  stream, &tm, RTG_K_KEY_HIST, RTG_K_KEY_SCATTER);
@@ -578,25 +596,35 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
     // before the pair kernel sees it.
     if ((rc = read_back(err, sizeof(uint32_t), &errh0))) return rc;
     if (errh0) return RTG_ERANGE;
-    uint64_t totals[2] = {0, 0};  // items, tests
+    uint64_t tests_total = 0;
+    uint32_t units_total = 0;
     if (ncells_h) {
       kbegin(RTG_K_CELLS);
-      launch_cell_work(cstart, cend, tot, items, tests, ncells_h, counters + 3, stream);
-      scan_exclusive_u64(items, items, ncells_h, scan64 + scan_scratch_elems(max_cells), scan64,
-                         stream);
-      scan_exclusive_u64(tests, tests, ncells_h, scan64 + scan_scratch_elems(max_cells) + 1,
-                         scan64, stream);
-      kend(RTG_K_CELLS, 8.0 * (double)ncells_h + 32.0 * (double)ncells_h);
-      if ((rc = read_back(scan64 + scan_scratch_elems(max_cells), sizeof(totals), totals)))
-        return rc;
+      launch_cell_work(cstart, cend, ncells_h, units, tests, counters + 3, stream);
+      scan_exclusive_u32(units, units, ncells_h, scan32 + s64, scan32, stream);
+      scan_exclusive_u64(tests, tests, ncells_h, scan64 + s64, scan64, stream);
+      launch_unit_fill(cstart, cend, units, ncells_h, unit_cell, stream);
+      kend(RTG_K_CELLS, 8.0 * (double)ncells_h + 16.0 * (double)ncells_h);
+      if ((rc = read_back(scan64 + s64, sizeof(tests_total), &tests_total))) return rc;
+      if ((rc = read_back(scan32 + s64, sizeof(units_total), &units_total))) return rc;
     }
     mark(4);
     st.cells += ncells_h;
-    st.tests += (int64_t)totals[1];
-    if (totals[0] == 0) continue;
+    st.tests += (int64_t)tests_total;
+    if (units_total == 0) continue;
+    PairFilter filt;
+    if (first_owner) {
+      filt.sig = sig;
+      filt.k = k;
+      filt.sig64 = sig64;
+      filt.skeys = skeys;
+      filt.cell_bits = P.seg_bits > 0 ? P.layout.cell_bits : 64;
+      filt.t0 = t0;
+    }
 
     // Room for this group's pairs: a guess first, the exact count on overflow.
-    uint64_t want = cand_total + std::min<uint64_t>(totals[1], std::max<uint64_t>(1u << 20, totals[1] / 16));
+    uint64_t want =
+        cand_total + std::min<uint64_t>(tests_total, std::max<uint64_t>(1u << 20, tests_total / 16));
     for (int attempt = 0; attempt < 2; ++attempt) {
       if (want > cap) {
         uint64_t* grown = static_cast<uint64_t*>(dalloc(sizeof(uint64_t) * want));
@@ -613,8 +641,8 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
       }
       launch_fill_u64(reinterpret_cast<uint64_t*>(counters), cand_total, 1, stream);
       kbegin(RTG_K_PAIRS);
-      launch_cell_pairs(points, d, sidx, cstart, cend, items, tot, totals[0], ptest, cand, cap,
-                        counters, counters + 1, counters + 2, stream);
+      launch_cell_pairs(points, d, sidx, cstart, cend, unit_cell, units, units_total, ptest, filt,
+                        cand, cap, counters, counters + 1, counters + 2, stream);
       unsigned long long cnt[4] = {0, 0, 0, 0};
       // bytes: every member of a cell read once (index + coordinates), every
       // pair within r written once
@@ -647,8 +675,10 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
   S.drop(vals_alt);
   S.drop(cstart);
   S.drop(cend);
-  S.drop(items);
+  S.drop(units);
+  S.drop(unit_cell);
   S.drop(tests);
+  if (sig) S.drop(sig);
 
   // --- union: sort the packed pairs and drop repeats -------------------------
   const size_t C = cand_total;
@@ -664,6 +694,12 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
     const uint64_t* sc = where ? cand_alt : cand;
     uint64_t* dst = where ? cand : cand_alt;
     mark(6);
+    if (first_owner) {
+      // every pair was emitted by exactly one grid: nothing to remove
+      U = C;
+      uniq = const_cast<uint64_t*>(sc);
+      mark(7);
+    } else {
     const size_t nt = (C + kTile - 1) / kTile;
     uint32_t* tc = scr;
     uint32_t* tot = scr + nt;
@@ -678,6 +714,7 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
     st.kernel_bytes[RTG_K_UNIQUE] += 8.0 * (double)U;
     uniq = dst;
     mark(7);
+    }
   } else {
     mark(6);
     mark(7);

@@ -55,9 +55,12 @@ void launch_stage_init(uint32_t* bad, uint32_t* bbox, int d, hipStream_t s);
 // keys[(t - t0) * n + i] = packed cell of point i under transform t, and
 // vals[...] = i, for t in [t0, t0 + tb).  R [k][d][d], u [k][d] FP64;
 // klo [k][d] int64 origin of the packed range.  err |= 1 if |y| >= 2^31.
+// If sig is not null, also sig[i * k + t] = the packed cell key (u64 if
+// sig64, else u32) of point i under grid t.
 void launch_keys(const float* soa, int64_t n, int d, int t0, int tb, const double* R,
                  const double* u, double inv_c, const int64_t* klo, const KeyLayout* layout,
-                 uint64_t* keys, uint32_t* vals, uint32_t* err, hipStream_t s);
+                 uint64_t* keys, uint32_t* vals, uint32_t* err, void* sig, int sig64, int k,
+                 hipStream_t s);
 // kappa [n][d] = floor(y) for one transform (stage check).
 void launch_cell_coords(const float* soa, int64_t n, int d, const double* R, const double* u,
                         double inv_c, int64_t* kappa, uint32_t* err, hipStream_t s);
@@ -95,23 +98,39 @@ void launch_run_count(const uint64_t* keys, size_t count, uint32_t* head_cnt,
 // per-tile offsets.
 void launch_run_write(const uint64_t* keys, size_t count, const uint32_t* head_off,
                       const uint32_t* tail_off, uint32_t* start, uint32_t* end, hipStream_t s);
-// items[c] = number of 64x64 tile pairs of run c; tests[c] = L(L-1)/2;
-// *members += sum of L.
-void launch_cell_work(const uint32_t* start, const uint32_t* end, const uint32_t* ncells,
-                      uint64_t* items, uint64_t* tests, size_t max_cells,
-                      unsigned long long* members, hipStream_t s);
+// units[c] = tiles of 64 points in run c, tests[c] = L(L-1)/2, and
+// *members += sum of L, for c < ncells.
+void launch_cell_work(const uint32_t* start, const uint32_t* end, uint32_t ncells,
+                      uint32_t* units, uint64_t* tests, unsigned long long* members,
+                      hipStream_t s);
+// unit_cell[unit_off[c] + q] = c for q < tiles of cell c.
+void launch_unit_fill(const uint32_t* start, const uint32_t* end, const uint32_t* unit_off,
+                      uint32_t ncells, uint32_t* unit_cell, hipStream_t s);
 
 // --- cell pairs -----------------------------------------------------------
-// One 64-wide wave per (cell, tile a, tile b) item; emits packed pairs
+// First-owner filter: keep a pair found under grid t only if no grid t' < t
+// put both points in one cell.  sig[i * k + t] is point i's packed cell key
+// under grid t (u32 or u64); null sig turns the filter off.
+struct PairFilter {
+  const void* sig = nullptr;
+  int32_t k = 0;
+  int32_t sig64 = 0;
+  const uint64_t* skeys = nullptr;  // sorted keys; grid id sits above cell_bits
+  int32_t cell_bits = 64;
+  int32_t t0 = 0;                   // first grid of this sort
+};
+
+// One 64-wide wave per unit = (cell, tile a); emits packed pairs
 // (min << pair_bits | max) for same-cell pairs within r.  cand_count is the
 // running total (may exceed cap: then the overflow is only counted);
-// rechecks counts FP64 band re-tests; next_item is the launch's work counter
+// rechecks counts FP64 band re-tests; next_unit is the launch's work counter
 // (reset by the launcher).
 void launch_cell_pairs(const float* pts, int d, const uint32_t* sidx, const uint32_t* start,
-                       const uint32_t* end, const uint64_t* item_off, const uint32_t* ncells,
-                       uint64_t total_items, PairTest test, uint64_t* cand, uint64_t cap,
-                       unsigned long long* cand_count, unsigned long long* rechecks,
-                       unsigned long long* next_item, hipStream_t s);
+                       const uint32_t* end, const uint32_t* unit_cell, const uint32_t* unit_off,
+                       uint32_t total_units, PairTest test, PairFilter filter, uint64_t* cand,
+                       uint64_t cap, unsigned long long* cand_count,
+                       unsigned long long* rechecks, unsigned long long* next_unit,
+                       hipStream_t s);
 
 // --- unique + CSR -----------------------------------------------------------
 void launch_unique_count(const uint64_t* keys, size_t count, uint32_t* tile_cnt, hipStream_t s);

@@ -20,6 +20,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace rtgk {
 namespace {
 
@@ -167,7 +169,8 @@ __global__ __launch_bounds__(kBlock) void k_keys(const float* __restrict__ soa, 
                                                  const int64_t* __restrict__ klo,
                                                  const KeyLayout* __restrict__ layout,
                                                  uint64_t* __restrict__ keys,
-                                                 uint32_t* __restrict__ vals, uint32_t* err) {
+                                                 uint32_t* __restrict__ vals, uint32_t* err,
+                                                 void* __restrict__ sig, int sig64, int k) {
   const int d = D > 0 ? D : d_rt;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
@@ -183,15 +186,20 @@ __global__ __launch_bounds__(kBlock) void k_keys(const float* __restrict__ soa, 
     const double* Rt = R + (size_t)t * d * d;
     const double* ut = u + (size_t)t * d;
     const int64_t* kl = klo + (size_t)t * d;
-    uint64_t key = (cell_bits < 64) ? ((uint64_t)tt << cell_bits) : 0ull;
+    uint64_t cell = 0;
     for (int j = 0; j < d; ++j) {
       double y = cell_y<D>(Rt + (size_t)j * d, p, soa, n, i, d, inv_c, ut[j]);
       bool ok = fabs(y) < 2147483648.0;
       bad |= !ok;
       int64_t kap = ok ? (int64_t)floor(y) : 0;
       uint64_t mask = (1ull << layout->bits[j]) - 1ull;
-      key |= ((uint64_t)(kap - kl[j]) & mask) << layout->shift[j];
+      cell |= ((uint64_t)(kap - kl[j]) & mask) << layout->shift[j];
     }
+    if (sig) {
+      if (sig64) static_cast<uint64_t*>(sig)[(size_t)i * k + t] = cell;
+      else static_cast<uint32_t*>(sig)[(size_t)i * k + t] = (uint32_t)cell;
+    }
+    const uint64_t key = (cell_bits < 64) ? (((uint64_t)tt << cell_bits) | cell) : cell;
     keys[(int64_t)tt * n + i] = key;
     vals[(int64_t)tt * n + i] = (uint32_t)i;
   }
@@ -475,22 +483,15 @@ __global__ __launch_bounds__(kBlock) void k_run_write(const uint64_t* __restrict
 
 __global__ __launch_bounds__(kBlock) void k_cell_work(const uint32_t* __restrict__ start,
                                                       const uint32_t* __restrict__ end,
-                                                      const uint32_t* __restrict__ ncells,
-                                                      uint64_t* __restrict__ items,
+                                                      uint32_t ncells, uint32_t* __restrict__ units,
                                                       uint64_t* __restrict__ tests,
-                                                      size_t max_cells,
                                                       unsigned long long* members) {
-  const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint64_t it = 0, te = 0, L = 0;
-  if (c < max_cells && c < *ncells) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t L = 0;
+  if (c < ncells) {
     L = end[c] - start[c];
-    const uint64_t nt = (L + kPairTile - 1) / kPairTile;
-    it = nt * (nt + 1) / 2;
-    te = L * (L - 1) / 2;
-  }
-  if (c < max_cells) {
-    items[c] = it;
-    tests[c] = te;
+    units[c] = (uint32_t)((L + kPairTile - 1) / kPairTile);
+    tests[c] = L * (L - 1) / 2;
   }
   unsigned long long m = L;
 #pragma unroll
@@ -548,34 +549,49 @@ __global__ __launch_bounds__(kBlock) void k_unique_write(const uint64_t* __restr
 }
 
 // ---------------------------------------------------------------------------
-// cell pairs.  One wave per item = (cell, tile a <= tile b) of 64 points
-// each; lane l holds point a_l in registers, tile b sits in LDS and is read
-// by broadcast.  Pairs within r are staged in a per-wave LDS buffer and
-// flushed with one global atomic per flush.
+// cell pairs.  A work unit is (cell, tile a) with tiles of 64 points; its
+// wave holds the 64 points of tile a in registers (one per lane) and walks
+// the tiles b >= a of the same cell, staging each in LDS (padded rows, read
+// by broadcast).  Lane l tests (a_l, b_j) for every j, keeping accepted j in
+// a bit mask and the j whose FP32 squared distance lies in the band around
+// r^2 in a second mask; the band is then re-tested in FP64.  With the
+// first-owner filter a pair is kept only if no earlier grid put both points
+// in one cell (that grid reported it already); the earlier cell keys are
+// compared in chunks of kSigChunk grids, tile a's in registers and tile b's
+// in LDS.  Kept pairs are written as (min << b) | max.
 
-constexpr int kOutBuf = 512;
+constexpr int kSigChunk = 8;
+constexpr int kOutBuf = 512;  // staged pairs per wave
 
-template <int D>
+template <typename T>
+__device__ __forceinline__ T uniform(T v) {
+  return (T)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+template <int D, bool SIG64>
 __global__ __launch_bounds__(kBlock) void k_cell_pairs(
-    const float* __restrict__ pts, int d_rt, const uint32_t* __restrict__ sidx,
+    const float* __restrict__ pts, int d, const uint32_t* __restrict__ sidx,
     const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend,
-    const uint64_t* __restrict__ item_off, const uint32_t* __restrict__ ncells_p,
-    uint64_t total_items, PairTest T, uint64_t* __restrict__ cand, uint64_t cap,
+    const uint32_t* __restrict__ unit_cell, const uint32_t* __restrict__ unit_off,
+    uint32_t total_units, PairTest T, PairFilter F, uint64_t* __restrict__ cand, uint64_t cap,
     unsigned long long* cand_count, unsigned long long* rechecks,
-    unsigned long long* next_item) {
-  constexpr int DD = D > 0 ? D : kMaxDim;
-  const int d = D > 0 ? D : d_rt;
-  __shared__ float sB[kWaves][DD][kPairTile];
+    unsigned long long* next_unit) {
+  using Sig = typename std::conditional<SIG64, uint64_t, uint32_t>::type;
+  // LDS row stride: rows of 4 floats read with 128-bit loads
+  constexpr int DP = D <= 2 ? D : ((D + 3) / 4) * 4;
+  __shared__ __attribute__((aligned(16))) float sB[kWaves][kPairTile][DP];
   __shared__ uint32_t sBi[kWaves][kPairTile];
+  __shared__ __attribute__((aligned(16))) Sig sBs[kWaves][kPairTile][kSigChunk];
   __shared__ uint64_t sOut[kWaves][kOutBuf];
 
   const uint32_t lane = lane_id();
   const int w = threadIdx.x >> 6;
-  const uint32_t ncells = *ncells_p;
-  const uint64_t lt = (1ull << lane) - 1ull;
-  uint32_t outn = 0;
+  const Sig* sig = static_cast<const Sig*>(F.sig);
   unsigned long long nre = 0;
+  uint32_t outn = 0;  // pairs staged in sOut[w] (wave-uniform)
 
+  // Staged pairs go out with one global atomic per flush: a device-wide
+  // counter is shared by every XCD, so per-tile atomics would serialise.
   auto flush = [&]() {
     wave_lds_sync();
     if (outn) {
@@ -591,84 +607,150 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs(
     wave_lds_sync();
   };
 
-  for (;;) {
-    unsigned long long item = 0;
-    if (lane == 0) item = atomicAdd(next_item, 1ull);
-    item = __shfl(item, 0, 64);
-    if (item >= total_items) break;
+  // Units are dealt to waves round-robin (no shared work counter).
+  const uint32_t wave_id = blockIdx.x * kWaves + w;
+  const uint32_t nwaves = gridDim.x * kWaves;
+  for (uint32_t u = wave_id; u < total_units; u += nwaves) {
 
-    // The cell whose items cover this one: largest c with item_off[c] <= item.
-    uint32_t lo = 0, hi = ncells;
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (item_off[mid] <= item) lo = mid;
-      else hi = mid;
-    }
-    const uint32_t s0 = cstart[lo];
-    const uint32_t L = cend[lo] - s0;
+    const uint32_t c = uniform(unit_cell[u]);
+    const uint32_t ta = u - uniform(unit_off[c]);
+    const uint32_t s0 = uniform(cstart[c]);
+    const uint32_t L = uniform(cend[c]) - s0;
     const uint32_t nt = (L + kPairTile - 1) / kPairTile;
-    uint64_t q = item - item_off[lo];
-    uint32_t ta = 0;
-    while (q >= (uint64_t)(nt - ta)) {
-      q -= nt - ta;
-      ++ta;
-    }
-    const uint32_t tb = ta + (uint32_t)q;
     const uint32_t nA = min((uint32_t)kPairTile, L - ta * kPairTile);
-    const uint32_t nB = min((uint32_t)kPairTile, L - tb * kPairTile);
+    int tcell = 0;
+    if (sig) tcell = F.t0 + (F.cell_bits >= 64 ? 0 : (int)uniform((uint32_t)(F.skeys[s0] >> F.cell_bits)));
 
-    wave_lds_sync();
-    if (lane < nB) {
-      const uint32_t g = sidx[s0 + tb * kPairTile + lane];
-      sBi[w][lane] = g;
-      for (int l = 0; l < d; ++l) sB[w][l][lane] = pts[(size_t)g * d + l];
-    }
-    float a[DD];
+    float a[D];
     uint32_t ai = 0;
-    if (lane < nA) {
-      ai = sidx[s0 + ta * kPairTile + lane];
-      for (int l = 0; l < d; ++l) a[l] = pts[(size_t)ai * d + l];
-    } else {
-      for (int l = 0; l < d; ++l) a[l] = 0.0f;
-    }
-    wave_lds_sync();
-
-    const bool diag = ta == tb;
-    for (uint32_t j = 0; j < nB; ++j) {
-      const bool act = lane < nA && (!diag || lane < j);
-      float d2 = 0.0f;
-      if (D > 0) {
+    const bool rowok = lane < nA;
+    if (rowok) ai = sidx[s0 + ta * kPairTile + lane];
 #pragma unroll
-        for (int l = 0; l < DD; ++l) {
-          const float df = a[l] - sB[w][l][j];
-          d2 = __builtin_fmaf(df, df, d2);
-        }
-      } else {
-        for (int l = 0; l < d; ++l) {
-          const float df = a[l] - sB[w][l][j];
-          d2 = __builtin_fmaf(df, df, d2);
-        }
+    for (int l = 0; l < D; ++l) a[l] = (rowok && l < d) ? pts[(size_t)ai * d + l] : 0.0f;
+
+    for (uint32_t tb = ta; tb < nt; ++tb) {
+      const uint32_t nB = min((uint32_t)kPairTile, L - tb * kPairTile);
+      wave_lds_sync();
+      uint32_t bi = 0;
+      if (lane < nB) {
+        bi = sidx[s0 + tb * kPairTile + lane];
+        sBi[w][lane] = bi;
+#pragma unroll
+        for (int l = 0; l < DP; ++l) sB[w][lane][l] = (l < d) ? pts[(size_t)bi * d + l] : 0.0f;
       }
-      bool acc = act && d2 <= T.lo;
-      if (act && !acc && d2 <= T.hi) {
-        // Band: decide in FP64 exactly as the definition does.
+      wave_lds_sync();
+
+      // lane l tests j only when j > lim: every pair once in a diagonal tile
+      const int lim = rowok ? (ta == tb ? (int)lane : -1) : 64;
+      uint32_t accw[2] = {0u, 0u}, bandw[2] = {0u, 0u};
+      auto test = [&](int j, int q, uint32_t& am, uint32_t& bm) {
+        float b[DP];
+#pragma unroll
+        for (int l = 0; l < DP; ++l) b[l] = sB[w][j][l];
+        float d2 = 0.0f;
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+          const float df = a[l] - b[l];
+          d2 = __builtin_fmaf(df, df, d2);
+        }
+        // bitwise, not short-circuit: every lane computes every test, so
+        // the loop stays free of branches and its LDS reads can run ahead
+        const uint32_t ok = (uint32_t)(j > lim);
+        const uint32_t in_lo = (uint32_t)(d2 <= T.lo);
+        const uint32_t in_hi = (uint32_t)(d2 <= T.hi);
+        am |= (ok & in_lo) << q;
+        bm |= (ok & in_hi & (in_lo ^ 1u)) << q;
+      };
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int jb = h * 32;
+        const int jn = min((int)nB - jb, 32);
+        if (jn <= 0) break;
+        uint32_t am = 0u, bm = 0u;
+        if (jn == 32) {
+#pragma unroll 8
+          for (int q = 0; q < 32; ++q) test(jb + q, q, am, bm);
+        } else {
+          for (int q = 0; q < jn; ++q) test(jb + q, q, am, bm);
+        }
+        accw[h] = am;
+        bandw[h] = bm;
+      }
+      uint64_t acc = ((uint64_t)accw[1] << 32) | accw[0];
+      uint64_t band = ((uint64_t)bandw[1] << 32) | bandw[0];
+
+      // Band: decide in FP64 exactly as the definition does.  Padding
+      // coordinates are zero on both sides and add nothing.
+      while (band) {
+        const int j = __builtin_ctzll(band);
+        band &= band - 1;
         double s = 0.0;
-        for (int l = 0; l < d; ++l) {
-          const double dl = (double)a[l] - (double)sB[w][l][j];
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+          const double dl = (double)a[l] - (double)sB[w][j][l];
           s = s + dl * dl;
         }
-        acc = s <= T.r2;
+        if (s <= T.r2) acc |= 1ull << j;
         ++nre;
       }
-      const uint64_t m = ballot(acc);
-      if (m) {
-        if (acc) {
-          const uint32_t bj = sBi[w][j];
-          const uint64_t pi = min(ai, bj), pj = max(ai, bj);
-          sOut[w][outn + (uint32_t)__popcll(m & lt)] = (pi << T.pair_bits) | pj;
+
+      // First owner: drop a pair that an earlier grid put in one cell.
+      if (sig && tcell > 0 && ballot(acc != 0ull)) {
+        for (int q0 = 0; q0 < tcell; q0 += kSigChunk) {
+          const int qn = min(kSigChunk, tcell - q0);
+          Sig sa[kSigChunk];
+#pragma unroll
+          for (int q = 0; q < kSigChunk; ++q)
+            sa[q] = (rowok && q < qn) ? sig[(size_t)ai * F.k + q0 + q] : (Sig)0;
+          wave_lds_sync();
+          if (lane < nB) {
+#pragma unroll
+            for (int q = 0; q < kSigChunk; ++q)
+              sBs[w][lane][q] = (q < qn) ? sig[(size_t)bi * F.k + q0 + q] : (Sig)0;
+          }
+          wave_lds_sync();
+          uint64_t m = acc;
+          while (m) {
+            const int j = __builtin_ctzll(m);
+            m &= m - 1;
+            bool same = false;
+#pragma unroll
+            for (int q = 0; q < kSigChunk; ++q) same |= (q < qn) && sa[q] == sBs[w][j][q];
+            if (same) acc &= ~(1ull << j);
+          }
         }
-        outn += (uint32_t)__popcll(m);
-        if (outn > kOutBuf - 64) flush();
+      }
+
+      const uint32_t cnt = (uint32_t)__popcll(acc);
+      const uint32_t incl = wave_inclusive_scan(cnt);
+      const uint32_t total = uniform(__shfl(incl, 63, 64));
+      if (total) {
+        if (outn + total > (uint32_t)kOutBuf) flush();
+        if (total > (uint32_t)kOutBuf) {
+          // more than the buffer holds (at most 64 x 64): straight out
+          unsigned long long base = 0;
+          if (lane == 0) base = atomicAdd(cand_count, (unsigned long long)total);
+          base = __shfl(base, 0, 64);
+          uint64_t pos = base + incl - cnt;
+          while (acc) {
+            const int j = __builtin_ctzll(acc);
+            acc &= acc - 1;
+            const uint64_t bj = sBi[w][j];
+            const uint64_t lo = min((uint64_t)ai, bj), hi = max((uint64_t)ai, bj);
+            if (pos < cap) cand[pos] = (lo << T.pair_bits) | hi;
+            ++pos;
+          }
+        } else {
+          uint32_t pos = outn + incl - cnt;
+          while (acc) {
+            const int j = __builtin_ctzll(acc);
+            acc &= acc - 1;
+            const uint64_t bj = sBi[w][j];
+            const uint64_t lo = min((uint64_t)ai, bj), hi = max((uint64_t)ai, bj);
+            sOut[w][pos++] = (lo << T.pair_bits) | hi;
+          }
+          outn += total;
+        }
       }
     }
   }
@@ -676,6 +758,17 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs(
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) nre += __shfl_xor(nre, o, 64);
   if (lane == 0 && nre) atomicAdd(rechecks, nre);
+}
+
+// unit_cell[unit_off[c] + q] = c for the tiles q of cell c.
+__global__ void k_unit_fill(const uint32_t* __restrict__ start, const uint32_t* __restrict__ end,
+                            const uint32_t* __restrict__ unit_off, uint32_t ncells,
+                            uint32_t* __restrict__ unit_cell) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  const uint32_t nt = (end[c] - start[c] + kPairTile - 1) / kPairTile;
+  const uint32_t o = unit_off[c];
+  for (uint32_t q = 0; q < nt; ++q) unit_cell[o + q] = c;
 }
 
 // ---------------------------------------------------------------------------
@@ -774,23 +867,29 @@ template <int D>
 static void keys_dispatch(const float* soa, int64_t n, int d, int t0, int tb, const double* R,
                           const double* u, double inv_c, const int64_t* klo,
                           const KeyLayout* layout, uint64_t* keys, uint32_t* vals, uint32_t* err,
-                          hipStream_t s) {
+                          void* sig, int sig64, int k, hipStream_t s) {
   hipLaunchKernelGGL(k_keys<D>, dim3(grid_for((size_t)n)), dim3(kBlock), 0, s, soa, n, d, t0, tb, R,
-                     u, inv_c, klo, layout, keys, vals, err);
+                     u, inv_c, klo, layout, keys, vals, err, sig, sig64, k);
 }
 
 void launch_keys(const float* soa, int64_t n, int d, int t0, int tb, const double* R,
                  const double* u, double inv_c, const int64_t* klo, const KeyLayout* layout,
-                 uint64_t* keys, uint32_t* vals, uint32_t* err, hipStream_t s) {
+                 uint64_t* keys, uint32_t* vals, uint32_t* err, void* sig, int sig64, int k,
+                 hipStream_t s) {
   if (n <= 0) return;
-#define RTG_KEYS_CASE(DV) \
-  case DV: keys_dispatch<DV>(soa, n, d, t0, tb, R, u, inv_c, klo, layout, keys, vals, err, s); break;
+#define RTG_KEYS_CASE(DV)                                                                       \
+  case DV:                                                                                      \
+    keys_dispatch<DV>(soa, n, d, t0, tb, R, u, inv_c, klo, layout, keys, vals, err, sig, sig64, \
+                      k, s);                                                                    \
+    break;
   switch (d) {
     RTG_KEYS_CASE(1) RTG_KEYS_CASE(2) RTG_KEYS_CASE(3) RTG_KEYS_CASE(4) RTG_KEYS_CASE(5)
     RTG_KEYS_CASE(6) RTG_KEYS_CASE(7) RTG_KEYS_CASE(8) RTG_KEYS_CASE(9) RTG_KEYS_CASE(10)
     RTG_KEYS_CASE(11) RTG_KEYS_CASE(12) RTG_KEYS_CASE(13) RTG_KEYS_CASE(14) RTG_KEYS_CASE(15)
     RTG_KEYS_CASE(16)
-    default: keys_dispatch<0>(soa, n, d, t0, tb, R, u, inv_c, klo, layout, keys, vals, err, s);
+    default:
+      keys_dispatch<0>(soa, n, d, t0, tb, R, u, inv_c, klo, layout, keys, vals, err, sig, sig64, k,
+                       s);
   }
 #undef RTG_KEYS_CASE
 }
@@ -910,52 +1009,77 @@ void launch_run_write(const uint64_t* keys, size_t count, const uint32_t* head_o
                      tail_off, start, end);
 }
 
-void launch_cell_work(const uint32_t* start, const uint32_t* end, const uint32_t* ncells,
-                      uint64_t* items, uint64_t* tests, size_t max_cells,
-                      unsigned long long* members, hipStream_t s) {
-  if (!max_cells) return;
-  hipLaunchKernelGGL(k_cell_work, dim3(grid_for(max_cells)), dim3(kBlock), 0, s, start, end, ncells,
-                     items, tests, max_cells, members);
+void launch_cell_work(const uint32_t* start, const uint32_t* end, uint32_t ncells,
+                      uint32_t* units, uint64_t* tests, unsigned long long* members,
+                      hipStream_t s) {
+  if (!ncells) return;
+  hipLaunchKernelGGL(k_cell_work, dim3(grid_for(ncells)), dim3(kBlock), 0, s, start, end, ncells,
+                     units, tests, members);
+}
+
+void launch_unit_fill(const uint32_t* start, const uint32_t* end, const uint32_t* unit_off,
+                      uint32_t ncells, uint32_t* unit_cell, hipStream_t s) {
+  if (!ncells) return;
+  hipLaunchKernelGGL(k_unit_fill, dim3(grid_for(ncells)), dim3(kBlock), 0, s, start, end, unit_off,
+                     ncells, unit_cell);
 }
 
 template <int D>
 static void pairs_dispatch(const float* pts, int d, const uint32_t* sidx, const uint32_t* start,
-                           const uint32_t* end, const uint64_t* item_off, const uint32_t* ncells,
-                           uint64_t total_items, PairTest test, uint64_t* cand, uint64_t cap,
+                           const uint32_t* end, const uint32_t* unit_cell,
+                           const uint32_t* unit_off, uint32_t total_units, PairTest test,
+                           PairFilter filter, uint64_t* cand, uint64_t cap,
                            unsigned long long* cand_count, unsigned long long* rechecks,
-                           unsigned long long* next_item, hipStream_t s) {
-  uint64_t blocks = (total_items + kWaves - 1) / kWaves;
+                           unsigned long long* next_unit, hipStream_t s) {
+  uint64_t blocks = ((uint64_t)total_units + kWaves - 1) / kWaves;
   const uint64_t max_blocks = 256ull * 8ull;  // 256 CUs, several resident blocks each
   if (blocks > max_blocks) blocks = max_blocks;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_cell_pairs<D>, dim3((unsigned)blocks), dim3(kBlock), 0, s, pts, d, sidx,
-                     start, end, item_off, ncells, total_items, test, cand, cap, cand_count,
-                     rechecks, next_item);
+  if (filter.sig64)
+    hipLaunchKernelGGL((k_cell_pairs<D, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, pts, d,
+                       sidx, start, end, unit_cell, unit_off, total_units, test, filter, cand, cap,
+                       cand_count, rechecks, next_unit);
+  else
+    hipLaunchKernelGGL((k_cell_pairs<D, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, pts, d,
+                       sidx, start, end, unit_cell, unit_off, total_units, test, filter, cand, cap,
+                       cand_count, rechecks, next_unit);
 }
 
 void launch_cell_pairs(const float* pts, int d, const uint32_t* sidx, const uint32_t* start,
-                       const uint32_t* end, const uint64_t* item_off, const uint32_t* ncells,
-                       uint64_t total_items, PairTest test, uint64_t* cand, uint64_t cap,
-                       unsigned long long* cand_count, unsigned long long* rechecks,
-                       unsigned long long* next_item, hipStream_t s) {
-  if (!total_items) return;
-  hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, next_item, 0ull,
-                     (size_t)1);
-#define RTG_PAIRS_CASE(DV)                                                                    \
-  case DV:                                                                                    \
-    pairs_dispatch<DV>(pts, d, sidx, start, end, item_off, ncells, total_items, test, cand, \
-                       cap, cand_count, rechecks, next_item, s);                            \
-    break;
+                       const uint32_t* end, const uint32_t* unit_cell, const uint32_t* unit_off,
+                       uint32_t total_units, PairTest test, PairFilter filter, uint64_t* cand,
+                       uint64_t cap, unsigned long long* cand_count,
+                       unsigned long long* rechecks, unsigned long long* next_unit,
+                       hipStream_t s) {
+  if (!total_units) return;
+#define RTG_PAIRS_ARGS pts, d, sidx, start, end, unit_cell, unit_off, total_units, test, filter, \
+                       cand, cap, cand_count, rechecks, next_unit, s
+  // Instantiations for d <= 16 exactly; larger d run the next wider one with
+  // zero padding, which adds exact zeros to both sums.
   switch (d) {
-    RTG_PAIRS_CASE(1) RTG_PAIRS_CASE(2) RTG_PAIRS_CASE(3) RTG_PAIRS_CASE(4) RTG_PAIRS_CASE(5)
-    RTG_PAIRS_CASE(6) RTG_PAIRS_CASE(7) RTG_PAIRS_CASE(8) RTG_PAIRS_CASE(9) RTG_PAIRS_CASE(10)
-    RTG_PAIRS_CASE(11) RTG_PAIRS_CASE(12) RTG_PAIRS_CASE(13) RTG_PAIRS_CASE(14)
-    RTG_PAIRS_CASE(15) RTG_PAIRS_CASE(16)
+    case 1: pairs_dispatch<1>(RTG_PAIRS_ARGS); break;
+    case 2: pairs_dispatch<2>(RTG_PAIRS_ARGS); break;
+    case 3: pairs_dispatch<3>(RTG_PAIRS_ARGS); break;
+    case 4: pairs_dispatch<4>(RTG_PAIRS_ARGS); break;
+    case 5: pairs_dispatch<5>(RTG_PAIRS_ARGS); break;
+    case 6: pairs_dispatch<6>(RTG_PAIRS_ARGS); break;
+    case 7: pairs_dispatch<7>(RTG_PAIRS_ARGS); break;
+    case 8: pairs_dispatch<8>(RTG_PAIRS_ARGS); break;
+    case 9: pairs_dispatch<9>(RTG_PAIRS_ARGS); break;
+    case 10: pairs_dispatch<10>(RTG_PAIRS_ARGS); break;
+    case 11: pairs_dispatch<11>(RTG_PAIRS_ARGS); break;
+    case 12: pairs_dispatch<12>(RTG_PAIRS_ARGS); break;
+    case 13: pairs_dispatch<13>(RTG_PAIRS_ARGS); break;
+    case 14: pairs_dispatch<14>(RTG_PAIRS_ARGS); break;
+    case 15: pairs_dispatch<15>(RTG_PAIRS_ARGS); break;
+    case 16: pairs_dispatch<16>(RTG_PAIRS_ARGS); break;
     default:
-      pairs_dispatch<0>(pts, d, sidx, start, end, item_off, ncells, total_items, test, cand, cap,
-                        cand_count, rechecks, next_item, s);
+      if (d <= 24) pairs_dispatch<24>(RTG_PAIRS_ARGS);
+      else if (d <= 32) pairs_dispatch<32>(RTG_PAIRS_ARGS);
+      else if (d <= 48) pairs_dispatch<48>(RTG_PAIRS_ARGS);
+      else pairs_dispatch<64>(RTG_PAIRS_ARGS);
   }
-#undef RTG_PAIRS_CASE
+#undef RTG_PAIRS_ARGS
 }
 
 void launch_unique_count(const uint64_t* keys, size_t count, uint32_t* tile_cnt, hipStream_t s) {

@@ -97,10 +97,12 @@ def test_small_uniform_d3_bit_exact(ctx):
     wl = workloads.small_uniform_d3()
     _say(f"workload {wl.name}")
     p = wl.points()
+    from paper_1409_8112_amd import rtg
     for flags in (0, oracle.NO_ROTATE, oracle.UPPER_ONLY):
-        rp, col = _gpu(ctx, p, wl.r, wl.k, wl.alpha, wl.seed, flags)
         ref = oracle.rtg(p, wl.r, wl.k, wl.alpha, wl.seed, flags)
-        _assert_same(rp, col, ref)
+        for dedup in (0, rtg.DEDUP_SORT):
+            rp, col = _gpu(ctx, p, wl.r, wl.k, wl.alpha, wl.seed, flags | dedup)
+            _assert_same(rp, col, ref)
     bf = oracle.bruteforce(p, wl.r)
     recall = len(ref.col) / max(1, len(bf.col) // 2)
     _say(f"recall vs brute force {recall:.4f}")
@@ -133,9 +135,27 @@ def test_clustered_d12_small(ctx):
     _say("clustered d=12 n=20000")
     p = workloads.clustered_points(20000, 12, seed=5)
     r = 0.04
-    rp, col = _gpu(ctx, p, r, 8, 2.0, 0)
     ref = oracle.rtg(p, r, 8, 2.0, 0)
-    _assert_same(rp, col, ref)
+    from paper_1409_8112_amd import rtg
+    for dedup in (0, rtg.DEDUP_SORT):
+        rp, col = _gpu(ctx, p, r, 8, 2.0, 0, dedup)
+        _assert_same(rp, col, ref)
+
+
+def test_grids_in_several_sorts(ctx):
+    """d = 31 with alpha = 0.6 needs two key bits per axis (62 bits), so the
+    six grids are split over several sorts; the first-owner rule must look
+    back across sorts."""
+    from paper_1409_8112_amd import rtg
+    d, n = 31, 4000
+    p = workloads.clustered_points(n, d, seed=2, n_clusters=8, sigma=0.03)
+    r = 0.3
+    ref = oracle.rtg(p, r, 6, 0.6, 4)
+    for dedup in (0, rtg.DEDUP_SORT):
+        rp, col = _gpu(ctx, p, r, 6, 0.6, 4, dedup)
+        _assert_same(rp, col, ref)
+        assert ctx.stats()["transforms_per_sort"] < 6
+    assert len(ref.col) > 0
 
 
 def test_one_huge_cell_many_tiles(ctx):
