@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -272,7 +273,21 @@ int plan_packing(int d, int k, const double* R, const double* u, double inv_c, d
 // ---------------------------------------------------------------------------
 // context
 
-Ctx::Ctx(int dev, hipStream_t s) : device(dev), stream(s) {}
+Ctx::Ctx(int dev, hipStream_t s) : device(dev), stream(s) {
+  // Reduce-then-scan is the default radix sort: on MI355X its per-pass
+  // histogram + scan + scatter beat onesweep, whose look-back reads cross
+  // the XCDs' L2s.  RTG_SORT=onesweep selects onesweep.
+  const char* e = std::getenv("RTG_SORT");
+  sort_algo = (e && std::strcmp(e, "onesweep") == 0) ? kSortOnesweep : kSortReduceScan;
+  // RTG_BUCKET_CAP lowers the entries a neighbour-list bucket may hold in
+  // LDS (tests use it to send buckets down the global-sort fallback).
+  const char* bc = std::getenv("RTG_BUCKET_CAP");
+  bucket_cap = kBucketMaxEntries;
+  if (bc) {
+    const long v = std::strtol(bc, nullptr, 10);
+    if (v >= 1 && v < kBucketMaxEntries) bucket_cap = (uint32_t)v;
+  }
+}
 
 Ctx::~Ctx() {
   if (host_stage) (void)hipHostFree(host_stage);
@@ -418,6 +433,140 @@ struct Scratch {
   }
 };
 
+// Result block: row_ptr (n+1 int64) then col (nnz int32), one arena block.
+int alloc_result(Ctx& c, int64_t n, size_t nnz, void** res, int64_t** row_ptr, int32_t** col) {
+  const size_t rp = ((sizeof(int64_t) * (size_t)(n + 1)) + Arena::kAlign - 1) &
+                    ~(size_t)(Arena::kAlign - 1);
+  *res = c.dalloc(rp + sizeof(int32_t) * std::max<size_t>(nnz, 1));
+  if (!*res) return RTG_ENOMEM;
+  *row_ptr = static_cast<int64_t*>(*res);
+  *col = reinterpret_cast<int32_t*>(static_cast<char*>(*res) + rp);
+  return RTG_OK;
+}
+
+// Neighbour lists by row buckets (see the bucket kernels): partition the
+// directed entries of the unique pairs into buckets of 2^rb rows, then put
+// each bucket in (row, col) order in LDS and write col and row_ptr; buckets
+// too large for LDS go through the global radix sort.
+int csr_by_buckets(Ctx& c, Scratch& S, const uint64_t* pairs, size_t count, int64_t n, int pb,
+                   bool both, uint32_t* err, const LaunchTimer* tm, void** res, int64_t** row_ptr,
+                   int32_t** col, size_t* nnz_out) {
+  hipStream_t s = c.stream;
+  int rc;
+  const size_t E = both ? 2 * count : count;
+  // at most 2^14 buckets of at most 2^11 rows; about 12k entries per
+  // bucket, well inside what one block holds in LDS, so that each
+  // partition block writes runs of entries per bucket
+  int rb = std::max(0, ceil_log2((uint64_t)n) - 14);
+  const double per_row = (double)E / (double)n;
+  while (rb < 11 && rb + 1 + pb <= 32 && per_row * (double)(1u << (rb + 1)) <= 12288.0) ++rb;
+  const uint32_t nbuckets = (uint32_t)((n + ((int64_t)1 << rb) - 1) >> rb);
+  const uint32_t nblocks = (uint32_t)std::min<size_t>(256, (count + 4095) / 4096);
+  const uint32_t chunk = (uint32_t)((count + nblocks - 1) / nblocks);
+  const size_t np = (size_t)nbuckets * nblocks;
+  uint32_t* part = S.get<uint32_t>(np + 1);
+  uint32_t* pscr = S.get<uint32_t>(scan_scratch_elems(np) + 1);
+  uint32_t* entries = S.get<uint32_t>(E);
+  uint32_t* over = S.get<uint32_t>((size_t)nbuckets + 1);  // [0] count, then bucket ids
+  if (!part || !pscr || !entries || !over) return RTG_ENOMEM;
+  if ((rc = alloc_result(c, n, E, res, row_ptr, col))) return rc;
+  if (tm) tm->on_begin(RTG_K_CSR);
+  launch_bucket_hist(pairs, count, pb, rb, both ? 1 : 0, nbuckets, chunk, nblocks, part, s);
+  scan_exclusive_u32(part, part, np, part + np, pscr, s);
+  launch_bucket_scatter(pairs, count, pb, rb, both ? 1 : 0, nbuckets, chunk, nblocks, part, entries,
+                        s);
+  launch_fill_u32(over, 0u, 1, s);
+  launch_bucket_csr(entries, part, nbuckets, nblocks, part + np, over + 1, over, c.bucket_cap, pb,
+                    rb, n, *row_ptr, *col, s);
+  launch_fill_u64(reinterpret_cast<uint64_t*>(*row_ptr + n), (uint64_t)E, 1, s);
+  // read the pairs twice, write and read the entries, write col and row_ptr
+  if (tm) tm->on_end(RTG_K_CSR, 16.0 * (double)count + 8.0 * (double)E + 4.0 * (double)E +
+                                    8.0 * (double)(n + 1));
+  uint32_t nover = 0;
+  if ((rc = c.read_back(over, sizeof(nover), &nover))) {
+    c.dfree(*res);
+    return rc;
+  }
+  if (nover) {
+    // Rare: buckets beyond LDS capacity go through the global radix sort.
+    std::vector<uint32_t> ids(nover);
+    rc = c.hip_fail(hipMemcpy(ids.data(), over + 1, sizeof(uint32_t) * nover,
+                              hipMemcpyDeviceToHost), "copy oversized list");
+    for (size_t q = 0; !rc && q < ids.size(); ++q) {
+      const uint32_t b = ids[q];
+      uint32_t lim[2];
+      const size_t nxt = (b + 1 < nbuckets) ? (size_t)(b + 1) * nblocks : np;
+      if ((rc = c.read_back(part + (size_t)b * nblocks, sizeof(uint32_t), &lim[0]))) break;
+      if ((rc = c.read_back(part + nxt, sizeof(uint32_t), &lim[1]))) break;
+      const size_t cnt = lim[1] - lim[0];
+      uint64_t* w = S.get<uint64_t>(cnt);
+      uint64_t* w_alt = S.get<uint64_t>(cnt);
+      void* scr = S.get<char>(radix_scratch_bytes(cnt, 0, rb + pb));
+      if (!w || !w_alt || !scr) {
+        rc = RTG_ENOMEM;
+        break;
+      }
+      launch_widen(entries + lim[0], cnt, w, s);
+      const int where = radix_sort(w, nullptr, w_alt, nullptr, cnt, 0, rb + pb, scr, err, s);
+      launch_bucket_emit_sorted(where ? w_alt : w, (uint32_t)cnt, lim[0], b, pb, rb, n, *row_ptr,
+                                *col, s);
+      if ((rc = c.sync())) break;
+      S.drop(w);
+      S.drop(w_alt);
+      S.drop(scr);
+    }
+    if (rc) {
+      c.dfree(*res);
+      return rc;
+    }
+  }
+  *nnz_out = E;
+  return RTG_OK;
+}
+
+// Neighbour lists from pairs sorted by (i, j): upper rows are runs of the
+// sorted list; lower rows come from a second sort of the swapped pairs.
+int csr_from_sorted(Ctx& c, Scratch& S, const uint64_t* uniq, size_t U, int64_t n, int pb,
+                    bool both, uint32_t* err, int64_t* row_ptr, int32_t* col) {
+  hipStream_t s = c.stream;
+  uint32_t* up_s = S.get<uint32_t>((size_t)n);
+  uint32_t* up_e = S.get<uint32_t>((size_t)n);
+  uint32_t* lo_s = both ? S.get<uint32_t>((size_t)n) : nullptr;
+  uint32_t* lo_e = both ? S.get<uint32_t>((size_t)n) : nullptr;
+  uint64_t* deg = S.get<uint64_t>((size_t)n);
+  uint64_t* dscr = S.get<uint64_t>(scan_scratch_elems((size_t)n));
+  if (!up_s || !up_e || (both && (!lo_s || !lo_e)) || !deg || !dscr) return RTG_ENOMEM;
+  c.kbegin(RTG_K_CSR);
+  launch_fill_u32(up_s, 0u, (size_t)n, s);
+  launch_fill_u32(up_e, 0u, (size_t)n, s);
+  if (both) {
+    launch_fill_u32(lo_s, 0u, (size_t)n, s);
+    launch_fill_u32(lo_e, 0u, (size_t)n, s);
+  }
+  const uint64_t* lower = nullptr;
+  launch_row_runs(uniq, U, pb, up_s, up_e, s);
+  if (both) {
+    uint64_t* sw = S.get<uint64_t>(U);
+    uint64_t* sw_alt = S.get<uint64_t>(U);
+    void* scr = S.get<char>(radix_scratch_bytes(U, 0, 2 * pb));
+    if (!sw || !sw_alt || !scr) return RTG_ENOMEM;
+    launch_swap_pairs(uniq, U, pb, sw, s);
+    const int where = radix_sort(sw, nullptr, sw_alt, nullptr, U, 0, 2 * pb, scr, err, s, nullptr,
+                                 0, 0, c.sort_algo);
+    lower = where ? sw_alt : sw;
+    launch_row_runs(lower, U, pb, lo_s, lo_e, s);
+  }
+  launch_row_degree(lo_s, lo_e, up_s, up_e, n, deg, s);
+  scan_exclusive_u64(deg, reinterpret_cast<uint64_t*>(row_ptr), (size_t)n,
+                     reinterpret_cast<uint64_t*>(row_ptr) + n, dscr, s);
+  launch_csr_fill_upper(uniq, U, pb, row_ptr, lo_s, lo_e, up_s, col, s);
+  if (both) launch_csr_fill_lower(lower, U, pb, row_ptr, lo_s, col, s);
+  const size_t nnz = both ? 2 * U : U;
+  c.kend(RTG_K_CSR, (both ? 16.0 : 8.0) * (double)U + 8.0 * (double)(n + 1) + 4.0 * (double)nnz);
+  return RTG_OK;
+}
+
+
 }  // namespace
 
 int Ctx::make_empty_result(int64_t n, rtg_csr* out) {
@@ -533,7 +682,8 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
   uint32_t* vals = S.get<uint32_t>(NB);
   uint32_t* vals_alt = S.get<uint32_t>(NB);
   const size_t ntiles = (NB + kTile - 1) / kTile;
-  uint32_t* radix_scr = S.get<uint32_t>(std::max(radix_scratch_elems(NB), 4 * ntiles + 8));
+  void* sort_scr = S.get<char>(radix_scratch_bytes(NB, 0, P.key_bits));
+  uint32_t* radix_scr = S.get<uint32_t>(2 * ntiles + 8 + scan_scratch_elems(ntiles));
   const size_t max_cells = NB / 2 + 1;
   const size_t max_units = max_cells + NB / kPairTile + 1;
   uint32_t* cstart = S.get<uint32_t>(max_cells);
@@ -544,7 +694,7 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
   const size_t s64 = scan_scratch_elems(max_cells);
   uint64_t* scan64 = S.get<uint64_t>(s64 + 4);
   uint32_t* scan32 = S.get<uint32_t>(scan_scratch_elems(max_cells) + 4);
-  if (!keys || !keys_alt || !vals || !vals_alt || !radix_scr || !cstart || !cend || !units ||
+  if (!keys || !keys_alt || !vals || !vals_alt || !sort_scr || !radix_scr || !cstart || !cend || !units ||
       !unit_cell || !tests || !scan64 || !scan32)
     return RTG_ENOMEM;
 
@@ -573,8 +723,8 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
     kend(RTG_K_KEYS,
          4.0 * (double)n * d + 12.0 * (double)N + (sig ? (sig64 ? 8.0 : 4.0) * (double)N : 0.0));
     mark(2);
-    const int where = radix_sort(keys, vals, keys_alt, vals_alt, N, 0, P.key_bits, radix_scr,
-                                 stream, &tm, RTG_K_KEY_HIST, RTG_K_KEY_SCATTER);
+    const int where = radix_sort(keys, vals, keys_alt, vals_alt, N, 0, P.key_bits, sort_scr, err,
+                                 stream, &tm, RTG_K_KEY_HIST, RTG_K_KEY_SCATTER, sort_algo);
     const uint64_t* skeys = where ? keys_alt : keys;
     const uint32_t* sidx = where ? vals_alt : vals;
     mark(3);
@@ -595,7 +745,8 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
     // A cell coordinate out of range makes the grouping meaningless: stop
     // before the pair kernel sees it.
     if ((rc = read_back(err, sizeof(uint32_t), &errh0))) return rc;
-    if (errh0) return RTG_ERANGE;
+    if (errh0 & 1u) return RTG_ERANGE;
+    if (errh0) return hip_fail(hipErrorUnknown, "radix sort look-back");
     uint64_t tests_total = 0;
     uint32_t units_total = 0;
     if (ncells_h) {
@@ -663,7 +814,8 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
   uint32_t errh = 0;
   unsigned long long rech = 0;
   if ((rc = read_back(err, sizeof(errh), &errh))) return rc;
-  if (errh) return RTG_ERANGE;
+  if (errh & 1u) return RTG_ERANGE;
+  if (errh) return hip_fail(hipErrorUnknown, "radix sort look-back");
   if ((rc = read_back(counters + 1, sizeof(rech), &rech))) return rc;
   st.band_rechecks = (int64_t)rech;
   st.candidates = (int64_t)cand_total;
@@ -680,112 +832,89 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
   S.drop(tests);
   if (sig) S.drop(sig);
 
-  // --- union: sort the packed pairs and drop repeats -------------------------
+  // --- union and neighbour lists ------------------------------------------------
+  const bool both = !(flags & RTG_UPPER_ONLY);
   const size_t C = cand_total;
-  uint64_t* uniq = nullptr;
-  size_t U = 0;
-  if (C > 0) {
-    if (C >= (1ull << 32)) return RTG_ENOMEM;
+  if (C >= (1ull << 32)) return RTG_ENOMEM;
+  // Row buckets need a 32-bit local entry (rb <= 8 row bits + pair_bits) and
+  // at most 2^14 buckets; larger inputs take the sorted-pair build below.
+  const bool bucket_ok = pair_bits <= 24 && ceil_log2((uint64_t)n) <= 22 &&
+                         ceil_log2((uint64_t)n) - 14 + pair_bits <= 32 &&
+                         (both ? 2 * C : C) < (1ull << 32);
+  const uint64_t* pairs = cand;  // pairs for the neighbour-list build
+  size_t npairs = C;
+  if (C > 0 && (!first_owner || !bucket_ok)) {
+    // Global sort of the packed pairs; with RTG_DEDUP_SORT also drop repeats
+    // (sort-unique over every grid's candidates).
     uint64_t* cand_alt = S.get<uint64_t>(C);
-    uint32_t* scr = S.get<uint32_t>(radix_scratch_elems(C) + 16);
+    uint32_t* scr = static_cast<uint32_t*>(
+        static_cast<void*>(S.get<char>(radix_scratch_bytes(C, 0, 2 * pair_bits))));
     if (!cand_alt || !scr) return RTG_ENOMEM;
-    const int where = radix_sort(cand, nullptr, cand_alt, nullptr, C, 0, 2 * pair_bits, scr, stream,
-                                 &tm, RTG_K_PAIR_HIST, RTG_K_PAIR_SCATTER);
+    const int where = radix_sort(cand, nullptr, cand_alt, nullptr, C, 0, 2 * pair_bits, scr, err,
+                                 stream, &tm, RTG_K_PAIR_HIST, RTG_K_PAIR_SCATTER, sort_algo);
     const uint64_t* sc = where ? cand_alt : cand;
     uint64_t* dst = where ? cand : cand_alt;
     mark(6);
     if (first_owner) {
-      // every pair was emitted by exactly one grid: nothing to remove
-      U = C;
-      uniq = const_cast<uint64_t*>(sc);
-      mark(7);
+      pairs = sc;  // every pair was emitted by exactly one grid
     } else {
-    const size_t nt = (C + kTile - 1) / kTile;
-    uint32_t* tc = scr;
-    uint32_t* tot = scr + nt;
-    kbegin(RTG_K_UNIQUE);
-    launch_unique_count(sc, C, tc, stream);
-    scan_exclusive_u32(tc, tc, nt, tot, tot + 1, stream);
-    launch_unique_write(sc, C, tc, dst, stream);
-    kend(RTG_K_UNIQUE, 16.0 * (double)C);
-    uint32_t uh = 0;
-    if ((rc = read_back(tot, sizeof(uh), &uh))) return rc;
-    U = uh;
-    st.kernel_bytes[RTG_K_UNIQUE] += 8.0 * (double)U;
-    uniq = dst;
-    mark(7);
+      const size_t nt = (C + kTile - 1) / kTile;
+      uint32_t* tc = scr;
+      uint32_t* tot = scr + nt;
+      kbegin(RTG_K_UNIQUE);
+      launch_unique_count(sc, C, tc, stream);
+      scan_exclusive_u32(tc, tc, nt, tot, tot + 1, stream);
+      launch_unique_write(sc, C, tc, dst, stream);
+      kend(RTG_K_UNIQUE, 16.0 * (double)C);
+      uint32_t uh = 0;
+      if ((rc = read_back(tot, sizeof(uh), &uh))) return rc;
+      st.kernel_bytes[RTG_K_UNIQUE] += 8.0 * (double)uh;
+      pairs = dst;
+      npairs = uh;
     }
+    mark(7);
   } else {
     mark(6);
     mark(7);
   }
-  st.unique_pairs = (int64_t)U;
 
-  // --- CSR ----------------------------------------------------------------------
-  const bool both = !(flags & RTG_UPPER_ONLY);
-  const size_t nnz = both ? 2 * U : U;
-  const size_t rp_bytes = sizeof(int64_t) * (size_t)(n + 1);
-  const size_t res_bytes = ((rp_bytes + Arena::kAlign - 1) & ~(size_t)(Arena::kAlign - 1)) +
-                           sizeof(int32_t) * std::max<size_t>(nnz, 1);
-  void* res = dalloc(res_bytes);
-  if (!res) return RTG_ENOMEM;
-  int64_t* row_ptr = static_cast<int64_t*>(res);
-  int32_t* col = reinterpret_cast<int32_t*>(static_cast<char*>(res) +
-                                            ((rp_bytes + Arena::kAlign - 1) & ~(size_t)(Arena::kAlign - 1)));
-  {
-    uint32_t* up_s = S.get<uint32_t>((size_t)n);
-    uint32_t* up_e = S.get<uint32_t>((size_t)n);
-    uint32_t* lo_s = both ? S.get<uint32_t>((size_t)n) : nullptr;
-    uint32_t* lo_e = both ? S.get<uint32_t>((size_t)n) : nullptr;
-    uint64_t* deg = S.get<uint64_t>((size_t)n);
-    uint64_t* dscr = S.get<uint64_t>(scan_scratch_elems((size_t)n));
-    if (!up_s || !up_e || (both && (!lo_s || !lo_e)) || !deg || !dscr) {
-      dfree(res);
-      return RTG_ENOMEM;
-    }
-    kbegin(RTG_K_CSR);
-    launch_fill_u32(up_s, 0u, (size_t)n, stream);
-    launch_fill_u32(up_e, 0u, (size_t)n, stream);
-    if (both) {
-      launch_fill_u32(lo_s, 0u, (size_t)n, stream);
-      launch_fill_u32(lo_e, 0u, (size_t)n, stream);
-    }
-    const uint64_t* lower = nullptr;
-    if (U > 0) {
-      launch_row_runs(uniq, U, pair_bits, up_s, up_e, stream);
-      if (both) {
-        uint64_t* sw = S.get<uint64_t>(U);
-        uint64_t* sw_alt = S.get<uint64_t>(U);
-        uint32_t* scr = S.get<uint32_t>(radix_scratch_elems(U));
-        if (!sw || !sw_alt || !scr) {
-          dfree(res);
-          return RTG_ENOMEM;
-        }
-        launch_swap_pairs(uniq, U, pair_bits, sw, stream);
-        const int where = radix_sort(sw, nullptr, sw_alt, nullptr, U, 0, 2 * pair_bits, scr, stream);
-        // (its launches count inside the CSR group)
-        lower = where ? sw_alt : sw;
-        launch_row_runs(lower, U, pair_bits, lo_s, lo_e, stream);
-      }
-    }
-    launch_row_degree(lo_s, lo_e, up_s, up_e, n, deg, stream);
-    scan_exclusive_u64(deg, reinterpret_cast<uint64_t*>(row_ptr), (size_t)n,
-                       reinterpret_cast<uint64_t*>(row_ptr) + n, dscr, stream);
-    if (U > 0) {
-      launch_csr_fill_upper(uniq, U, pair_bits, row_ptr, lo_s, lo_e, up_s, col, stream);
-      if (both) launch_csr_fill_lower(lower, U, pair_bits, row_ptr, lo_s, col, stream);
-    }
-    // read the pairs (twice when both rows), write row_ptr and col
-    kend(RTG_K_CSR, (both ? 16.0 : 8.0) * (double)U + 8.0 * (double)(n + 1) + 4.0 * (double)nnz);
-    mark(8);
-    if ((rc = sync())) {
+  void* res = nullptr;
+  int64_t* row_ptr = nullptr;
+  int32_t* col = nullptr;
+  size_t nnz = 0;
+  if (npairs == 0) {
+    if ((rc = alloc_result(*this, n, 0, &res, &row_ptr, &col))) return rc;
+    launch_fill_u64(reinterpret_cast<uint64_t*>(row_ptr), 0ull, (size_t)(n + 1), stream);
+  } else if (bucket_ok) {
+    rc = csr_by_buckets(*this, S, pairs, npairs, n, pair_bits, both, err, &tm, &res, &row_ptr, &col,
+                        &nnz);
+    if (rc) return rc;
+  } else {
+    nnz = both ? 2 * npairs : npairs;
+    if ((rc = alloc_result(*this, n, nnz, &res, &row_ptr, &col))) return rc;
+    rc = csr_from_sorted(*this, S, pairs, npairs, n, pair_bits, both, err, row_ptr, col);
+    if (rc) {
       dfree(res);
       return rc;
     }
   }
+  const size_t U = both ? nnz / 2 : nnz;
+  st.unique_pairs = (int64_t)U;
+  mark(8);
+  if ((rc = sync())) {
+    dfree(res);
+    return rc;
+  }
   if ((rc = hip_fail(hipGetLastError(), "kernel launch"))) {
     dfree(res);
     return rc;
+  }
+  {
+    uint32_t errh2 = 0;
+    if ((rc = read_back(err, sizeof(errh2), &errh2)) || errh2) {
+      dfree(res);
+      return rc ? rc : hip_fail(hipErrorUnknown, "radix sort look-back");
+    }
   }
   kfinish();
   if (timing_mask & RTG_TIME_PHASES) {

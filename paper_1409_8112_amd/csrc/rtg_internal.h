@@ -79,15 +79,18 @@ void scan_exclusive_u64(const uint64_t* in, uint64_t* out, size_t count, uint64_
 
 // --- radix sort -----------------------------------------------------------
 // Stable LSD sort of count 64-bit keys (and optional u32 values) on bits
-// [begin_bit, end_bit).  Ping-pongs between (keys, vals) and (keys_alt,
-// vals_alt); returns 0 if the result ends in keys/vals, 1 if in the *_alt.
-// scratch must hold radix_scratch_elems(count) u32.
-size_t radix_scratch_elems(size_t count);
-// timer (optional) sees each histogram launch as kid_hist and each scatter
-// launch as kid_scatter.
+// [begin_bit, end_bit), 8-bit digits.  Ping-pongs between (keys, vals) and
+// (keys_alt, vals_alt); returns 0 if the result ends in keys/vals, 1 if in
+// the *_alt.  scratch must hold radix_scratch_bytes(count, ...) bytes (any
+// algorithm).  *err |= 2 if a look-back wait gave up (the output is then
+// wrong but every write stays in bounds).  timer (optional) sees the
+// histogram launches as kid_hist and each digit pass as kid_scatter.
+enum { kSortOnesweep = 0, kSortReduceScan = 1 };
+size_t radix_scratch_bytes(size_t count, int begin_bit, int end_bit);
 int radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
-               size_t count, int begin_bit, int end_bit, uint32_t* scratch, hipStream_t s,
-               const LaunchTimer* timer = nullptr, int kid_hist = 0, int kid_scatter = 0);
+               size_t count, int begin_bit, int end_bit, void* scratch, uint32_t* err,
+               hipStream_t s, const LaunchTimer* timer = nullptr, int kid_hist = 0,
+               int kid_scatter = 0, int algo = kSortOnesweep);
 
 // --- cells ----------------------------------------------------------------
 // Runs of equal keys with length >= 2 in a sorted key array: per tile counts
@@ -153,5 +156,35 @@ void launch_csr_fill_upper(const uint64_t* up, size_t count, int pair_bits, cons
                            const uint32_t* up_start, int32_t* col, hipStream_t s);
 void launch_csr_fill_lower(const uint64_t* lo, size_t count, int pair_bits, const int64_t* row_ptr,
                            const uint32_t* lo_start, int32_t* col, hipStream_t s);
+
+// --- neighbour lists by row buckets -------------------------------------------
+// Directed entries of the pairs (both orientations when both != 0) go to
+// buckets of 2^rb rows (rb <= 11) as 32-bit keys (row mod 2^rb) << pb | col
+// (needs rb + pb <= 32).  Blocks take `chunk` pairs each; part / offs are
+// [nbuckets][nblocks] counts / their exclusive scan (bucket-major).
+constexpr int kBucketMaxEntries = 28672;  // entries one block holds in LDS
+constexpr int kBucketMaxRows = 2048;      // rows per bucket (rb <= 11)
+void launch_bucket_hist(const uint64_t* pairs, size_t count, int pb, int rb, int both,
+                        uint32_t nbuckets, uint32_t chunk, uint32_t nblocks, uint32_t* part,
+                        hipStream_t s);
+void launch_bucket_scatter(const uint64_t* pairs, size_t count, int pb, int rb, int both,
+                           uint32_t nbuckets, uint32_t chunk, uint32_t nblocks,
+                           const uint32_t* offs, uint32_t* entries, hipStream_t s);
+// Writes col and row_ptr (all but row_ptr[n]) for every bucket of at most
+// cap (<= kBucketMaxEntries) entries: entries of unique pairs, so a bucket's
+// start in the entry array is its start in col.  Larger buckets, and
+// buckets with a row of more than 1024 entries, are listed in oversized[]
+// (count in *n_oversized) for the caller.
+void launch_bucket_csr(const uint32_t* entries, const uint32_t* offs, uint32_t nbuckets,
+                       uint32_t nblocks, const uint32_t* total, uint32_t* oversized,
+                       uint32_t* n_oversized, uint32_t cap, int pb, int rb, int64_t n,
+                       int64_t* row_ptr, int32_t* col, hipStream_t s);
+// col / row_ptr of one bucket from its (row mod 2^rb, col) keys sorted
+// ascending (cnt of them, starting at entry start).
+void launch_bucket_emit_sorted(const uint64_t* keys, uint32_t cnt, uint32_t start, uint32_t b,
+                               int pb, int rb, int64_t n, int64_t* row_ptr, int32_t* col,
+                               hipStream_t s);
+void launch_widen(const uint32_t* src, size_t count, uint64_t* dst, hipStream_t s);
+void launch_u32_to_u64(const uint32_t* src, size_t count, uint64_t* dst, hipStream_t s);
 
 }  // namespace rtgk

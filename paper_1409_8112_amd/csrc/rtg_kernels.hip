@@ -20,7 +20,9 @@
 
 #include <math.h>
 
+#include <algorithm>
 #include <type_traits>
+#include <utility>
 
 namespace rtgk {
 namespace {
@@ -277,7 +279,129 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const T* in, T* out, size
 // ---------------------------------------------------------------------------
 // radix sort: tiles of 4096 elements; element e of a tile is held by wave
 // e / 1024, round (e % 1024) / 64, lane e % 64, so every load is one
-// contiguous 64-element run.
+// contiguous 64-element run.  Two drivers share the tile code:
+//   onesweep (default): one histogram read for all digit passes, then per
+//     pass one kernel in which each tile takes the next tile id, publishes
+//     its digit counts and looks back over earlier tiles' published counts
+//     (decoupled look-back) to find where its digits start;
+//   reduce-then-scan: per pass, tile histograms, a device-wide scan, then
+//     the scatter (one more read of the keys per pass).
+
+// LDS of one tile: staged keys/values and the per-wave digit counters.
+template <bool HAS_VAL>
+struct TileLds {
+  uint64_t key[kTile];
+  uint32_t val[HAS_VAL ? kTile : 1];
+  uint32_t wcnt[kWaves][256];
+  uint32_t dstart[256];
+  uint64_t goff[256];
+  uint32_t wsum[kWaves];
+};
+
+// Loads tile `tile` and ranks every element among the elements of its wave
+// with the same digit (stable: wave order, then round, then lane).  After
+// the call wcnt[w][dg] holds wave w's count of digit dg.
+template <bool HAS_VAL>
+__device__ __forceinline__ void tile_rank(TileLds<HAS_VAL>& S, const uint64_t* __restrict__ kin,
+                                          const uint32_t* __restrict__ vin, size_t count,
+                                          size_t tile, int shift, int nbits, uint64_t* k_,
+                                          uint32_t* v_, uint32_t* r_) {
+  const uint32_t lane = lane_id();
+  const int w = threadIdx.x >> 6;
+  const uint32_t mask = (1u << nbits) - 1u;
+#pragma unroll
+  for (int q = 0; q < kWaves; ++q) S.wcnt[q][threadIdx.x] = 0u;
+  __syncthreads();
+  const size_t wave_base = tile * kTile + (size_t)w * (kTile / kWaves);
+  const uint64_t lt = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int q = 0; q < kKeysPerThread; ++q) {
+    const size_t e = wave_base + (size_t)q * 64 + lane;
+    const bool valid = e < count;
+    const uint64_t key = valid ? kin[e] : ~0ull;
+    k_[q] = key;
+    if (HAS_VAL) v_[q] = valid ? vin[e] : 0u;
+    const uint32_t dg = (uint32_t)(key >> shift) & mask;
+    uint64_t peers = ballot(valid);
+    for (int b = 0; b < nbits; ++b) {
+      const bool bit = (dg >> b) & 1u;
+      const uint64_t m = ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    uint32_t before = 0;
+    if (valid) before = S.wcnt[w][dg];
+    r_[q] = before + (uint32_t)__popcll(peers & lt);
+    wave_lds_sync();
+    if (valid && (peers & lt) == 0ull) S.wcnt[w][dg] = before + (uint32_t)__popcll(peers);
+    wave_lds_sync();
+  }
+  __syncthreads();
+}
+
+// Thread dg: the tile's count of digit dg; sets dstart[dg] (its first
+// position in the tile) and turns wcnt[w][dg] into wave w's first position.
+template <bool HAS_VAL>
+__device__ __forceinline__ uint32_t tile_layout(TileLds<HAS_VAL>& S) {
+  const uint32_t dg = threadIdx.x;
+  uint32_t c[kWaves];
+  uint32_t tot = 0;
+#pragma unroll
+  for (int q = 0; q < kWaves; ++q) {
+    c[q] = S.wcnt[q][dg];
+    tot += c[q];
+  }
+  uint32_t all;
+  const uint32_t start = block_exclusive_scan<uint32_t>(tot, S.wsum, all);
+  S.dstart[dg] = start;
+  uint32_t run = start;
+#pragma unroll
+  for (int q = 0; q < kWaves; ++q) {
+    S.wcnt[q][dg] = run;
+    run += c[q];
+  }
+  return tot;
+}
+
+// Sorts the tile into LDS and writes it out at goff[dg] + rank in digit.
+template <bool HAS_VAL>
+__device__ __forceinline__ void tile_scatter(TileLds<HAS_VAL>& S, uint64_t* __restrict__ kout,
+                                             uint32_t* __restrict__ vout, size_t count,
+                                             size_t tile, int shift, int nbits, const uint64_t* k_,
+                                             const uint32_t* v_, const uint32_t* r_) {
+  const uint32_t lane = lane_id();
+  const int w = threadIdx.x >> 6;
+  const uint32_t mask = (1u << nbits) - 1u;
+  const size_t tile_base = tile * kTile;
+  const size_t wave_base = tile_base + (size_t)w * (kTile / kWaves);
+#pragma unroll
+  for (int q = 0; q < kKeysPerThread; ++q) {
+    const size_t e = wave_base + (size_t)q * 64 + lane;
+    if (e < count) {
+      const uint32_t dg = (uint32_t)(k_[q] >> shift) & mask;
+      const uint32_t pos = S.wcnt[w][dg] + r_[q];
+      S.key[pos] = k_[q];
+      if (HAS_VAL) S.val[pos] = v_[q];
+    }
+  }
+  __syncthreads();
+  const size_t rem = count - tile_base;
+  const uint32_t tile_count = rem < (size_t)kTile ? (uint32_t)rem : (uint32_t)kTile;
+#pragma unroll 4
+  for (int q = 0; q < kKeysPerThread; ++q) {
+    const uint32_t s = (uint32_t)q * kBlock + threadIdx.x;
+    if (s < tile_count) {
+      const uint64_t key = S.key[s];
+      const uint32_t dg = (uint32_t)(key >> shift) & mask;
+      const uint64_t g = S.goff[dg] + (s - S.dstart[dg]);
+      if (g < count) {  // always true when the offsets are right
+        kout[g] = key;
+        if (HAS_VAL) vout[g] = S.val[s];
+      }
+    }
+  }
+}
+
+// --- reduce-then-scan ---------------------------------------------------------
 
 __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t* __restrict__ keys,
                                                        size_t count, int shift, int nbits,
@@ -302,99 +426,115 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
     uint32_t* __restrict__ vout, size_t count, int shift, int nbits,
     const uint32_t* __restrict__ tile_off, uint32_t ntiles) {
-  __shared__ uint64_t skey[kTile];
-  __shared__ uint32_t sval[HAS_VAL ? kTile : 1];
-  __shared__ uint32_t wcnt[kWaves][256];
-  __shared__ uint32_t dstart[256];
-  __shared__ uint32_t goff[256];
-  __shared__ uint32_t wsum[kWaves];
-
-  const uint32_t lane = lane_id();
-  const int w = threadIdx.x >> 6;
-  const uint32_t mask = (1u << nbits) - 1u;
-#pragma unroll
-  for (int q = 0; q < kWaves; ++q) wcnt[q][threadIdx.x] = 0u;
-  __syncthreads();
-
-  const size_t tile_base = (size_t)blockIdx.x * kTile;
-  const size_t wave_base = tile_base + (size_t)w * (kTile / kWaves);
-  const uint64_t lt = (1ull << lane) - 1ull;
-
+  __shared__ TileLds<HAS_VAL> S;
   uint64_t k_[kKeysPerThread];
   uint32_t v_[kKeysPerThread];
   uint32_t r_[kKeysPerThread];
-#pragma unroll
-  for (int q = 0; q < kKeysPerThread; ++q) {
-    const size_t e = wave_base + (size_t)q * 64 + lane;
-    const bool valid = e < count;
-    const uint64_t key = valid ? kin[e] : ~0ull;
-    k_[q] = key;
-    if (HAS_VAL) v_[q] = valid ? vin[e] : 0u;
-    const uint32_t dg = (uint32_t)(key >> shift) & mask;
-    uint64_t peers = ballot(valid);
-    for (int b = 0; b < nbits; ++b) {
-      const bool bit = (dg >> b) & 1u;
-      const uint64_t m = ballot(bit);
-      peers &= bit ? m : ~m;
-    }
-    uint32_t before = 0;
-    if (valid) before = wcnt[w][dg];
-    r_[q] = before + (uint32_t)__popcll(peers & lt);
-    wave_lds_sync();
-    if (valid && (peers & lt) == 0ull) wcnt[w][dg] = before + (uint32_t)__popcll(peers);
-    wave_lds_sync();
-  }
+  tile_rank<HAS_VAL>(S, kin, vin, count, blockIdx.x, shift, nbits, k_, v_, r_);
+  tile_layout<HAS_VAL>(S);
+  S.goff[threadIdx.x] = tile_off[(size_t)threadIdx.x * ntiles + blockIdx.x];
   __syncthreads();
+  tile_scatter<HAS_VAL>(S, kout, vout, count, blockIdx.x, shift, nbits, k_, v_, r_);
+}
 
-  // Digit d = threadIdx.x: where its run starts in the tile, and each wave's
-  // first position inside that run.
-  {
-    const uint32_t dg = threadIdx.x;
-    uint32_t c[kWaves];
-    uint32_t tot = 0;
+// --- onesweep -------------------------------------------------------------------
+
+constexpr int kHistBlockTiles = 4;  // tiles per block of the all-pass histogram
+constexpr int kMaxPasses = 8;
+
+// part[block][p][dg]: this block's count of digit dg in pass p.
+__global__ __launch_bounds__(kBlock) void k_hist_all(const uint64_t* __restrict__ keys,
+                                                     size_t count, int begin_bit, int end_bit,
+                                                     uint32_t* __restrict__ part) {
+  __shared__ uint32_t h[kWaves][kMaxPasses][256];
+  const int w = threadIdx.x >> 6;
+  const int npass = (end_bit - begin_bit + kRadixBits - 1) / kRadixBits;
+  for (int p = 0; p < npass; ++p)
 #pragma unroll
-    for (int q = 0; q < kWaves; ++q) {
-      c[q] = wcnt[q][dg];
-      tot += c[q];
-    }
-    uint32_t all;
-    const uint32_t start = block_exclusive_scan<uint32_t>(tot, wsum, all);
-    dstart[dg] = start;
-    uint32_t run = start;
-#pragma unroll
-    for (int q = 0; q < kWaves; ++q) {
-      wcnt[q][dg] = run;
-      run += c[q];
-    }
-    goff[dg] = tile_off[(size_t)dg * ntiles + blockIdx.x];
-  }
+    for (int q = 0; q < kWaves; ++q) h[q][p][threadIdx.x] = 0u;
   __syncthreads();
-
-#pragma unroll
-  for (int q = 0; q < kKeysPerThread; ++q) {
-    const size_t e = wave_base + (size_t)q * 64 + lane;
-    if (e < count) {
-      const uint32_t dg = (uint32_t)(k_[q] >> shift) & mask;
-      const uint32_t pos = wcnt[w][dg] + r_[q];
-      skey[pos] = k_[q];
-      if (HAS_VAL) sval[pos] = v_[q];
+  const size_t base = (size_t)blockIdx.x * kHistBlockTiles * kTile;
+  for (int q = 0; q < kHistBlockTiles * kKeysPerThread; ++q) {
+    const size_t e = base + (size_t)q * kBlock + threadIdx.x;
+    if (e >= count) break;
+    const uint64_t key = keys[e];
+    for (int p = 0; p < npass; ++p) {
+      const int b = begin_bit + p * kRadixBits;
+      const int nb = min(kRadixBits, end_bit - b);
+      atomicAdd(&h[w][p][(uint32_t)(key >> b) & ((1u << nb) - 1u)], 1u);
     }
   }
   __syncthreads();
-
-  const size_t rem = count - tile_base;
-  const uint32_t tile_count = rem < (size_t)kTile ? (uint32_t)rem : (uint32_t)kTile;
-#pragma unroll 4
-  for (int q = 0; q < kKeysPerThread; ++q) {
-    const uint32_t s = (uint32_t)q * kBlock + threadIdx.x;
-    if (s < tile_count) {
-      const uint64_t key = skey[s];
-      const uint32_t dg = (uint32_t)(key >> shift) & mask;
-      const size_t g = (size_t)goff[dg] + (s - dstart[dg]);
-      kout[g] = key;
-      if (HAS_VAL) vout[g] = sval[s];
-    }
+  for (int p = 0; p < npass; ++p) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) s += h[q][p][threadIdx.x];
+    part[((size_t)blockIdx.x * npass + p) * 256 + threadIdx.x] = s;
   }
+}
+
+// One block per pass: digit_off[p][dg] = number of keys with a smaller digit.
+__global__ __launch_bounds__(kBlock) void k_hist_scan(const uint32_t* __restrict__ part,
+                                                      uint32_t nblocks, int npass,
+                                                      uint64_t* __restrict__ digit_off) {
+  __shared__ uint64_t wsum[kWaves];
+  const int p = blockIdx.x;
+  uint64_t s = 0;
+  for (uint32_t b = 0; b < nblocks; ++b) s += part[((size_t)b * npass + p) * 256 + threadIdx.x];
+  uint64_t all;
+  digit_off[p * 256 + threadIdx.x] = block_exclusive_scan<uint64_t>(s, wsum, all);
+}
+
+// Status word of (tile, digit): flag in the top two bits (0 not yet
+// published, 1 this tile's count, 2 count of this and all earlier tiles).
+constexpr uint64_t kStAggregate = 1ull << 62;
+constexpr uint64_t kStInclusive = 2ull << 62;
+constexpr uint64_t kStValue = (1ull << 62) - 1ull;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+template <bool HAS_VAL>
+__global__ __launch_bounds__(kBlock) void k_onesweep(
+    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, size_t count, int shift, int nbits,
+    const uint64_t* __restrict__ digit_off, unsigned long long* status, unsigned int* tile_counter,
+    unsigned int* err) {
+  __shared__ TileLds<HAS_VAL> S;
+  __shared__ uint32_t s_tile;
+  // Tile ids in the order blocks start: every earlier tile is already
+  // running, so each look-back wait ends.
+  if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
+  __syncthreads();
+  const size_t tile = s_tile;
+  uint64_t k_[kKeysPerThread];
+  uint32_t v_[kKeysPerThread];
+  uint32_t r_[kKeysPerThread];
+  tile_rank<HAS_VAL>(S, kin, vin, count, tile, shift, nbits, k_, v_, r_);
+  const uint32_t tot = tile_layout<HAS_VAL>(S);
+  const uint32_t dg = threadIdx.x;
+  if (dg < (1u << nbits)) {
+    unsigned long long* mine = status + tile * 256 + dg;
+    __hip_atomic_store(mine, kStAggregate | (uint64_t)tot, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t excl = 0;
+    for (size_t p = tile; p-- > 0;) {
+      uint64_t st;
+      uint32_t spins = 0;
+      do {
+        st = __hip_atomic_load(status + p * 256 + dg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } while ((st >> 62) == 0 && ++spins < kSpinLimit);
+      if ((st >> 62) == 0) {  // never published: give up, report, keep writes in bounds
+        atomicOr(err, 2u);
+        break;
+      }
+      excl += st & kStValue;
+      if ((st >> 62) == 2) break;
+    }
+    __hip_atomic_store(mine, kStInclusive | (excl + tot), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    S.goff[dg] = digit_off[dg] + excl;
+  }
+  __syncthreads();
+  tile_scatter<HAS_VAL>(S, kout, vout, count, tile, shift, nbits, k_, v_, r_);
 }
 
 // ---------------------------------------------------------------------------
@@ -826,6 +966,226 @@ __global__ void k_csr_fill_lower(const uint64_t* __restrict__ lo, size_t count, 
   col[row_ptr[j] + (int64_t)(q - lo_start[j])] = (int32_t)i;
 }
 
+// ---------------------------------------------------------------------------
+// Neighbour lists by row buckets.  Directed entries (row, col) -- both
+// orientations of every pair, or only (i, j) for upper-only lists -- are
+// partitioned into buckets of 2^rb consecutive rows: per-block bucket counts,
+// one device-wide scan in bucket-major order, and a scatter in which each
+// block places its entries through LDS cursors.  An entry is stored as the
+// 32-bit local key (row mod 2^rb) << pb | col.  Each bucket is then sorted in
+// LDS (bitonic) with repeats removed, and the emit step writes col and the
+// bucket's slice of row_ptr.  The order of entries inside a bucket before the
+// local sort does not matter: the sort makes it canonical.
+
+__global__ __launch_bounds__(kBlock) void k_bucket_hist(const uint64_t* __restrict__ pairs,
+                                                        size_t count, int pb, int rb, int both,
+                                                        uint32_t nbuckets, uint32_t chunk,
+                                                        uint32_t nblocks,
+                                                        uint32_t* __restrict__ part) {
+  extern __shared__ uint32_t h[];
+  for (uint32_t b = threadIdx.x; b < nbuckets; b += kBlock) h[b] = 0u;
+  __syncthreads();
+  const size_t base = (size_t)blockIdx.x * chunk;
+  const size_t end = min(count, base + chunk);
+  const uint64_t cmask = (1ull << pb) - 1ull;
+  // eight loads in flight per thread, then their atomics
+  for (size_t q0 = base; q0 < end; q0 += 8 * kBlock) {
+    uint64_t k8[8];
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+      const size_t q = q0 + (size_t)x * kBlock + threadIdx.x;
+      k8[x] = q < end ? pairs[q] : ~0ull;
+    }
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+      if (k8[x] == ~0ull) continue;
+      atomicAdd(&h[(uint32_t)((k8[x] >> pb) >> rb)], 1u);
+      if (both) atomicAdd(&h[(uint32_t)((k8[x] & cmask) >> rb)], 1u);
+    }
+  }
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < nbuckets; b += kBlock)
+    part[(size_t)b * nblocks + blockIdx.x] = h[b];
+}
+
+__global__ __launch_bounds__(kBlock) void k_bucket_scatter(const uint64_t* __restrict__ pairs,
+                                                           size_t count, int pb, int rb, int both,
+                                                           uint32_t nbuckets, uint32_t chunk,
+                                                           uint32_t nblocks,
+                                                           const uint32_t* __restrict__ offs,
+                                                           uint32_t* __restrict__ entries) {
+  extern __shared__ uint32_t cur[];
+  for (uint32_t b = threadIdx.x; b < nbuckets; b += kBlock)
+    cur[b] = offs[(size_t)b * nblocks + blockIdx.x];
+  __syncthreads();
+  const size_t base = (size_t)blockIdx.x * chunk;
+  const size_t end = min(count, base + chunk);
+  const uint64_t cmask = (1ull << pb) - 1ull;
+  const uint32_t rmask = (1u << rb) - 1u;
+  for (size_t q0 = base; q0 < end; q0 += 8 * kBlock) {
+    uint64_t k8[8];
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+      const size_t q = q0 + (size_t)x * kBlock + threadIdx.x;
+      k8[x] = q < end ? pairs[q] : ~0ull;
+    }
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+      if (k8[x] == ~0ull) continue;
+      const uint32_t i = (uint32_t)(k8[x] >> pb), j = (uint32_t)(k8[x] & cmask);
+      entries[atomicAdd(&cur[i >> rb], 1u)] = ((i & rmask) << pb) | j;
+      if (both) entries[atomicAdd(&cur[j >> rb], 1u)] = ((j & rmask) << pb) | i;
+    }
+  }
+}
+
+__device__ __forceinline__ void bucket_range(const uint32_t* __restrict__ offs, uint32_t b,
+                                             uint32_t nbuckets, uint32_t nblocks, uint32_t total,
+                                             uint32_t& start, uint32_t& cnt) {
+  start = offs[(size_t)b * nblocks];
+  const uint32_t stop = (b + 1 < nbuckets) ? offs[(size_t)(b + 1) * nblocks] : total;
+  cnt = stop - start;
+}
+
+// One block per bucket: put the bucket's entries in row order and write
+// them out as the bucket's part of col and row_ptr.  The input pairs are
+// unique, so every entry is kept, the bucket's start in the entry array is
+// its start in col, and the columns of a row are distinct.  The block's
+// 1024 threads load the whole bucket into registers at once, count rows
+// (LDS histogram), scatter the entries by row into LDS, and give each entry
+// its place in its row as the number of smaller columns in the row.
+// Buckets larger than cap or with a row longer than kLongRow are listed in
+// oversized for the caller.
+constexpr uint32_t kLongRow = 1024;
+constexpr int kCsrThreads = 1024;
+constexpr int kCsrWaves = kCsrThreads / 64;
+constexpr int kCsrItems = kBucketMaxEntries / kCsrThreads;
+
+__device__ __forceinline__ uint32_t csr_block_exclusive_scan(uint32_t v, uint32_t* wsum,
+                                                             uint32_t& total) {
+  const uint32_t lane = lane_id();
+  const int w = threadIdx.x >> 6;
+  const uint32_t inc = wave_inclusive_scan(v);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (int q = 0; q < kCsrWaves; ++q) {
+    const uint32_t x = wsum[q];
+    if (q < w) before += x;
+    all += x;
+  }
+  __syncthreads();
+  total = all;
+  return before + inc - v;
+}
+
+__global__ __launch_bounds__(kCsrThreads) void k_bucket_csr(
+    const uint32_t* __restrict__ entries, const uint32_t* __restrict__ offs, uint32_t nbuckets,
+    uint32_t nblocks, const uint32_t* __restrict__ total_p, uint32_t* __restrict__ oversized,
+    uint32_t* __restrict__ n_oversized, uint32_t cap, int pb, int rb, int64_t n,
+    int64_t* __restrict__ row_ptr, int32_t* __restrict__ col) {
+  __shared__ uint32_t s[kBucketMaxEntries];
+  __shared__ uint32_t rstart[kBucketMaxRows], rcur[kBucketMaxRows];
+  __shared__ uint32_t wsum[kCsrWaves];
+  __shared__ uint32_t s_long;
+  const uint32_t b = blockIdx.x;
+  uint32_t start, cnt;
+  bucket_range(offs, b, nbuckets, nblocks, *total_p, start, cnt);
+  if (cnt > cap) {
+    if (threadIdx.x == 0) oversized[atomicAdd(n_oversized, 1u)] = b;
+    return;
+  }
+  const uint32_t nrows = 1u << rb;
+  const uint32_t cmask = (1u << pb) - 1u;
+  uint32_t e_[kCsrItems];
+#pragma unroll
+  for (int q = 0; q < kCsrItems; ++q) {
+    const uint32_t i = threadIdx.x + (uint32_t)q * kCsrThreads;
+    e_[q] = i < cnt ? entries[start + i] : 0u;
+  }
+  for (uint32_t r = threadIdx.x; r < nrows; r += kCsrThreads) rcur[r] = 0u;
+  if (threadIdx.x == 0) s_long = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kCsrItems; ++q)
+    if (threadIdx.x + (uint32_t)q * kCsrThreads < cnt) atomicAdd(&rcur[e_[q] >> pb], 1u);
+  __syncthreads();
+  // row starts: each thread scans a contiguous run of rows
+  const uint32_t per = (nrows + kCsrThreads - 1) / kCsrThreads;
+  const uint32_t r0 = threadIdx.x * per;
+  uint32_t mine = 0;
+  for (uint32_t r = r0; r < r0 + per && r < nrows; ++r) {
+    mine += rcur[r];
+    if (rcur[r] > kLongRow) s_long = 1u;
+  }
+  uint32_t all;
+  uint32_t run = csr_block_exclusive_scan(mine, wsum, all);
+  for (uint32_t r = r0; r < r0 + per && r < nrows; ++r) {
+    rstart[r] = run;
+    const int64_t row = ((int64_t)b << rb) + r;
+    if (row < n) row_ptr[row] = (int64_t)start + run;
+    run += rcur[r];
+  }
+  __syncthreads();
+  if (s_long) {
+    if (threadIdx.x == 0) oversized[atomicAdd(n_oversized, 1u)] = b;
+    return;
+  }
+  for (uint32_t r = threadIdx.x; r < nrows; r += kCsrThreads) rcur[r] = rstart[r];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kCsrItems; ++q)
+    if (threadIdx.x + (uint32_t)q * kCsrThreads < cnt) s[atomicAdd(&rcur[e_[q] >> pb], 1u)] = e_[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kCsrItems; ++q) {
+    if (threadIdx.x + (uint32_t)q * kCsrThreads < cnt) {
+      const uint32_t r = e_[q] >> pb;
+      const uint32_t c = e_[q] & cmask;
+      const uint32_t lo = rstart[r], hi = rcur[r];
+      uint32_t rank = 0;
+      for (uint32_t x = lo; x < hi; ++x) rank += (s[x] & cmask) < c ? 1u : 0u;
+      col[(size_t)start + lo + rank] = (int32_t)c;
+    }
+  }
+}
+
+// col / row_ptr of one bucket whose (row, col) keys are already sorted in
+// keys[0..cnt): the caller's path for buckets too large for LDS.
+__global__ void k_bucket_emit_sorted(const uint64_t* __restrict__ keys, uint32_t cnt,
+                                     uint32_t start, uint32_t b, int pb, int rb, int64_t n,
+                                     int64_t* __restrict__ row_ptr, int32_t* __restrict__ col) {
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t cmask = (1ull << pb) - 1ull;
+  if (q < cnt) {
+    col[(size_t)start + q] = (int32_t)(keys[q] & cmask);
+    // first entry of each row (and every empty row before it) sets row_ptr
+    const uint32_t r = (uint32_t)(keys[q] >> pb);
+    const uint32_t rprev = q == 0 ? 0u : (uint32_t)(keys[q - 1] >> pb) + 1u;
+    if (q == 0 || (uint32_t)(keys[q - 1] >> pb) != r)
+      for (uint32_t rr = rprev; rr <= r; ++rr) {
+        const int64_t row = ((int64_t)b << rb) + rr;
+        if (row < n) row_ptr[row] = (int64_t)start + q;
+      }
+  }
+  if (q == 0) {
+    // rows after the last entry (all rows if the bucket is empty)
+    const uint32_t rlast = cnt ? (uint32_t)(keys[cnt - 1] >> pb) + 1u : 0u;
+    for (uint32_t rr = rlast; rr < (1u << rb); ++rr) {
+      const int64_t row = ((int64_t)b << rb) + rr;
+      if (row < n) row_ptr[row] = (int64_t)start + cnt;
+    }
+  }
+}
+
+// Widens the entries of one oversized bucket to 64-bit keys for the global
+// sort.
+__global__ void k_widen(const uint32_t* __restrict__ src, size_t count, uint64_t* __restrict__ dst) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < count) dst[q] = src[q];
+}
+
 inline unsigned grid_for(size_t count, unsigned block = kBlock) {
   size_t g = (count + block - 1) / block;
   return (unsigned)(g < 1 ? 1 : g);
@@ -954,24 +1314,70 @@ void scan_exclusive_u64(const uint64_t* in, uint64_t* out, size_t count, uint64_
   scan_rec<uint64_t>(in, out, count, total, scratch, s);
 }
 
-size_t radix_scratch_elems(size_t count) {
-  const size_t h = (size_t)256 * tiles_for(count);
-  return h + scan_scratch_elems(h);
+size_t radix_scratch_bytes(size_t count, int begin_bit, int end_bit) {
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t ntiles = tiles_for(count);
+  const int npass = std::max(1, (end_bit - begin_bit + kRadixBits - 1) / kRadixBits);
+  const size_t nbh = (count + (size_t)kHistBlockTiles * kTile - 1) / ((size_t)kHistBlockTiles * kTile);
+  const size_t onesweep = up(nbh * npass * 256 * 4) + up((size_t)npass * 256 * 8) +
+                          up(ntiles * 256 * 8) + up((size_t)npass * 4);
+  const size_t h = (size_t)256 * ntiles;
+  const size_t rts = up(4 * (h + scan_scratch_elems(h)));
+  return std::max(onesweep, rts) + 256;
 }
 
 int radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
-               size_t count, int begin_bit, int end_bit, uint32_t* scratch, hipStream_t s,
-               const LaunchTimer* timer, int kid_hist, int kid_scatter) {
+               size_t count, int begin_bit, int end_bit, void* scratch, uint32_t* err,
+               hipStream_t s, const LaunchTimer* timer, int kid_hist, int kid_scatter, int algo) {
   const LaunchTimer none;
   const LaunchTimer& tm = timer ? *timer : none;
   const double elem = vals ? 12.0 : 8.0;
   if (count <= 1 || end_bit <= begin_bit) return 0;
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const unsigned ntiles = tiles_for(count);
-  uint32_t* hist = scratch;
-  uint32_t* sscr = scratch + (size_t)256 * ntiles;
+  char* base = static_cast<char*>(scratch);
   uint64_t *kin = keys, *kout = keys_alt;
   uint32_t *vin = vals, *vout = vals_alt;
   int where = 0;
+  if (algo == kSortOnesweep) {
+    const int npass = (end_bit - begin_bit + kRadixBits - 1) / kRadixBits;
+    const size_t nbh =
+        (count + (size_t)kHistBlockTiles * kTile - 1) / ((size_t)kHistBlockTiles * kTile);
+    uint32_t* part = reinterpret_cast<uint32_t*>(base);
+    base += up(nbh * npass * 256 * 4);
+    uint64_t* digit_off = reinterpret_cast<uint64_t*>(base);
+    base += up((size_t)npass * 256 * 8);
+    unsigned long long* status = reinterpret_cast<unsigned long long*>(base);
+    base += up((size_t)ntiles * 256 * 8);
+    unsigned int* counters = reinterpret_cast<unsigned int*>(base);
+    tm.on_begin(kid_hist);
+    hipLaunchKernelGGL(k_hist_all, dim3((unsigned)nbh), dim3(kBlock), 0, s, kin, count, begin_bit,
+                       end_bit, part);
+    hipLaunchKernelGGL(k_hist_scan, dim3(npass), dim3(kBlock), 0, s, part, (uint32_t)nbh, npass,
+                       digit_off);
+    tm.on_end(kid_hist, 8.0 * (double)count);
+    hipLaunchKernelGGL(k_fill<unsigned int>, dim3(1), dim3(64), 0, s, counters, 0u, (size_t)npass);
+    for (int p = 0; p < npass; ++p) {
+      const int b = begin_bit + p * kRadixBits;
+      const int nbits = std::min(kRadixBits, end_bit - b);
+      launch_fill_u64(reinterpret_cast<uint64_t*>(status), 0ull, (size_t)ntiles * 256, s);
+      tm.on_begin(kid_scatter);
+      if (vals)
+        hipLaunchKernelGGL(k_onesweep<true>, dim3(ntiles), dim3(kBlock), 0, s, kin, vin, kout, vout,
+                           count, b, nbits, digit_off + (size_t)p * 256, status, counters + p, err);
+      else
+        hipLaunchKernelGGL(k_onesweep<false>, dim3(ntiles), dim3(kBlock), 0, s, kin,
+                           (const uint32_t*)nullptr, kout, (uint32_t*)nullptr, count, b, nbits,
+                           digit_off + (size_t)p * 256, status, counters + p, err);
+      tm.on_end(kid_scatter, 2.0 * elem * (double)count);
+      std::swap(kin, kout);
+      std::swap(vin, vout);
+      where ^= 1;
+    }
+    return where;
+  }
+  uint32_t* hist = reinterpret_cast<uint32_t*>(base);
+  uint32_t* sscr = hist + (size_t)256 * ntiles;
   for (int b = begin_bit; b < end_bit; b += kRadixBits) {
     const int nbits = (end_bit - b) < kRadixBits ? (end_bit - b) : kRadixBits;
     tm.on_begin(kid_hist);
@@ -988,8 +1394,8 @@ int radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* val
                          (const uint32_t*)nullptr, kout, (uint32_t*)nullptr, count, b, nbits, hist,
                          ntiles);
     tm.on_end(kid_scatter, 2.0 * elem * (double)count);
-    uint64_t* tk = kin; kin = kout; kout = tk;
-    uint32_t* tv = vin; vin = vout; vout = tv;
+    std::swap(kin, kout);
+    std::swap(vin, vout);
     where ^= 1;
   }
   return where;
@@ -1129,6 +1535,50 @@ void launch_csr_fill_lower(const uint64_t* lo, size_t count, int pair_bits, cons
   if (!count) return;
   hipLaunchKernelGGL(k_csr_fill_lower, dim3(grid_for(count)), dim3(kBlock), 0, s, lo, count,
                      pair_bits, row_ptr, lo_start, col);
+}
+
+// --- row buckets ------------------------------------------------------------
+
+void launch_bucket_hist(const uint64_t* pairs, size_t count, int pb, int rb, int both,
+                        uint32_t nbuckets, uint32_t chunk, uint32_t nblocks, uint32_t* part,
+                        hipStream_t s) {
+  if (!nblocks) return;
+  hipLaunchKernelGGL(k_bucket_hist, dim3(nblocks), dim3(kBlock), nbuckets * sizeof(uint32_t), s,
+                     pairs, count, pb, rb, both, nbuckets, chunk, nblocks, part);
+}
+
+void launch_bucket_scatter(const uint64_t* pairs, size_t count, int pb, int rb, int both,
+                           uint32_t nbuckets, uint32_t chunk, uint32_t nblocks,
+                           const uint32_t* offs, uint32_t* entries, hipStream_t s) {
+  if (!nblocks) return;
+  hipLaunchKernelGGL(k_bucket_scatter, dim3(nblocks), dim3(kBlock), nbuckets * sizeof(uint32_t), s,
+                     pairs, count, pb, rb, both, nbuckets, chunk, nblocks, offs, entries);
+}
+
+void launch_bucket_csr(const uint32_t* entries, const uint32_t* offs, uint32_t nbuckets,
+                       uint32_t nblocks, const uint32_t* total, uint32_t* oversized,
+                       uint32_t* n_oversized, uint32_t cap, int pb, int rb, int64_t n,
+                       int64_t* row_ptr, int32_t* col, hipStream_t s) {
+  if (!nbuckets) return;
+  if (cap > (uint32_t)kBucketMaxEntries) cap = kBucketMaxEntries;
+  hipLaunchKernelGGL(k_bucket_csr, dim3(nbuckets), dim3(kCsrThreads), 0, s, entries, offs,
+                     nbuckets, nblocks, total, oversized, n_oversized, cap, pb, rb, n, row_ptr, col);
+}
+
+void launch_bucket_emit_sorted(const uint64_t* keys, uint32_t cnt, uint32_t start, uint32_t b,
+                               int pb, int rb, int64_t n, int64_t* row_ptr, int32_t* col,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_bucket_emit_sorted, dim3(grid_for(cnt ? cnt : 1)), dim3(kBlock), 0, s, keys,
+                     cnt, start, b, pb, rb, n, row_ptr, col);
+}
+
+void launch_widen(const uint32_t* src, size_t count, uint64_t* dst, hipStream_t s) {
+  if (!count) return;
+  hipLaunchKernelGGL(k_widen, dim3(grid_for(count)), dim3(kBlock), 0, s, src, count, dst);
+}
+
+void launch_u32_to_u64(const uint32_t* src, size_t count, uint64_t* dst, hipStream_t s) {
+  launch_widen(src, count, dst, s);
 }
 
 }  // namespace rtgk

@@ -74,6 +74,8 @@ struct Ctx {
   void* host_stage = nullptr;  // pinned staging for scalar read-backs
   bool poisoned = false;
   uint32_t timing_mask = 0;  // bit i: time kernel id i; RTG_TIME_PHASES: phases
+  int sort_algo = 0;         // rtgk::kSortOnesweep or rtgk::kSortReduceScan
+  uint32_t bucket_cap = rtgk::kBucketMaxEntries;  // entries per LDS-sorted bucket
   hipEvent_t ev[9] = {};
   rtg_stats stats{};
   // per-launch timing: a pool of event pairs and the launches of this call

@@ -277,6 +277,46 @@ def test_invalid_arguments(ctx):
     _assert_same(rp, col, oracle.rtg(p, 0.2, 2, 2.0, 0))
 
 
+def test_onesweep_sort_matches(ctx):
+    """The onesweep radix sort (RTG_SORT=onesweep) gives the same lists as the
+    default reduce-then-scan sort."""
+    from paper_1409_8112_amd import rtg
+    os.environ["RTG_SORT"] = "onesweep"
+    try:
+        other = rtg.Context(0, arena_bytes=4 << 30)
+    finally:
+        del os.environ["RTG_SORT"]
+    try:
+        for n, d, r in [(5000, 3, 0.06), (20000, 6, 0.3)]:
+            p = workloads.uniform_points(n, d, seed=n + d)
+            res = other.all_pairs(_dev(p), r, 4, 2.0, 1)
+            rp, col = res.to_numpy()
+            res.release()
+            _assert_same(rp, col, oracle.rtg(p, r, 4, 2.0, 1))
+    finally:
+        other.close()
+
+
+def test_oversized_buckets_take_the_global_sort(ctx):
+    """Neighbour-list buckets too large for LDS are sorted by the global radix
+    sort; a context with a tiny bucket capacity sends most buckets there."""
+    from paper_1409_8112_amd import rtg
+    os.environ["RTG_BUCKET_CAP"] = "40"
+    try:
+        other = rtg.Context(0, arena_bytes=4 << 30)
+    finally:
+        del os.environ["RTG_BUCKET_CAP"]
+    try:
+        p = workloads.uniform_points(6000, 3, seed=77)
+        for flags in (0, oracle.UPPER_ONLY, rtg.DEDUP_SORT):
+            res = other.all_pairs(_dev(p), 0.08, 4, 2.0, 5, flags)
+            rp, col = res.to_numpy()
+            res.release()
+            _assert_same(rp, col, oracle.rtg(p, 0.08, 4, 2.0, 5, flags & ~rtg.DEDUP_SORT))
+    finally:
+        other.close()
+
+
 def test_release_and_determinism(ctx):
     from paper_1409_8112_amd import rtg
     p = workloads.uniform_points(20000, 4, seed=2)
