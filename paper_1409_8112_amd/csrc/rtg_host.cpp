@@ -316,6 +316,11 @@ int Ctx::read_back(const void* dev, size_t bytes, void* host) {
   return RTG_OK;
 }
 
+int Ctx::gather_back(const rtgk::Gather& g, uint64_t* host) {
+  rtgk::launch_gather(g, static_cast<uint64_t*>(gather_dev), stream);
+  return read_back(gather_dev, sizeof(uint64_t) * g.count, host);
+}
+
 int Ctx::upload(void* dev, const void* host, size_t bytes) {
   return hip_fail(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, stream),
                   "hipMemcpyAsync H2D");
@@ -644,11 +649,12 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
   uint32_t* bbox = flags_dev + 2;
   if ((rc = upload(Rd, R, sizeof(double) * (size_t)k * d * d))) return rc;
   if ((rc = upload(ud, u, sizeof(double) * (size_t)k * d))) return rc;
-  launch_stage_init(bad, bbox, d, stream);
+  uint32_t* stage_part = S.get<uint32_t>(stage_scratch_elems(n, d));
+  if (!stage_part) return RTG_ENOMEM;
   launch_fill_u32(err, 0u, 1, stream);
   launch_fill_u64(reinterpret_cast<uint64_t*>(counters), 0ull, 4, stream);
   kbegin(RTG_K_STAGE);
-  launch_stage(points, n, d, soa, bad, bbox, stream);
+  launch_stage(points, n, d, soa, bad, bbox, stage_part, stream);
   kend(RTG_K_STAGE, 8.0 * (double)n * d);
   mark(1);
   std::vector<uint32_t> hb(2 + 2 * kMaxDim);
@@ -677,12 +683,15 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
 
   // --- per group of grids: keys, sort, cells, pairs ---------------------------
   const size_t NB = (size_t)n * (size_t)P.tb;
+  // The point index rides in the low bits of the key when both fit in 64
+  // bits: the sort then moves 8 bytes per element instead of 12.
+  const int idx_bits = (P.key_bits + pair_bits <= 64) ? pair_bits : 0;
   uint64_t* keys = S.get<uint64_t>(NB);
   uint64_t* keys_alt = S.get<uint64_t>(NB);
-  uint32_t* vals = S.get<uint32_t>(NB);
-  uint32_t* vals_alt = S.get<uint32_t>(NB);
+  uint32_t* vals = idx_bits ? nullptr : S.get<uint32_t>(NB);
+  uint32_t* vals_alt = idx_bits ? nullptr : S.get<uint32_t>(NB);
   const size_t ntiles = (NB + kTile - 1) / kTile;
-  void* sort_scr = S.get<char>(radix_scratch_bytes(NB, 0, P.key_bits));
+  void* sort_scr = S.get<char>(radix_scratch_bytes(NB, 0, P.key_bits));  // passes as for 0..key_bits
   uint32_t* radix_scr = S.get<uint32_t>(2 * ntiles + 8 + scan_scratch_elems(ntiles));
   const size_t max_cells = NB / 2 + 1;
   const size_t max_units = max_cells + NB / kPairTile + 1;
@@ -694,7 +703,8 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
   const size_t s64 = scan_scratch_elems(max_cells);
   uint64_t* scan64 = S.get<uint64_t>(s64 + 4);
   uint32_t* scan32 = S.get<uint32_t>(scan_scratch_elems(max_cells) + 4);
-  if (!keys || !keys_alt || !vals || !vals_alt || !sort_scr || !radix_scr || !cstart || !cend || !units ||
+  if (!keys || !keys_alt || (!idx_bits && (!vals || !vals_alt)) || !sort_scr || !radix_scr ||
+      !cstart || !cend || !units ||
       !unit_cell || !tests || !scan64 || !scan32)
     return RTG_ENOMEM;
 
@@ -719,14 +729,15 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
     const size_t N = (size_t)n * tb;
     kbegin(RTG_K_KEYS);
     launch_keys(soa, n, d, t0, tb, Rd, ud, inv_c, klo_d, layout_d, keys, vals, err, sig, sig64, k,
-                stream);
-    kend(RTG_K_KEYS,
-         4.0 * (double)n * d + 12.0 * (double)N + (sig ? (sig64 ? 8.0 : 4.0) * (double)N : 0.0));
+                idx_bits, stream);
+    kend(RTG_K_KEYS, 4.0 * (double)n * d + (idx_bits ? 8.0 : 12.0) * (double)N +
+                         (sig ? (sig64 ? 8.0 : 4.0) * (double)N : 0.0));
     mark(2);
-    const int where = radix_sort(keys, vals, keys_alt, vals_alt, N, 0, P.key_bits, sort_scr, err,
-                                 stream, &tm, RTG_K_KEY_HIST, RTG_K_KEY_SCATTER, sort_algo);
+    const int where = radix_sort(keys, vals, keys_alt, vals_alt, N, idx_bits, idx_bits + P.key_bits,
+                                 sort_scr, err, stream, &tm, RTG_K_KEY_HIST, RTG_K_KEY_SCATTER,
+                                 sort_algo);
     const uint64_t* skeys = where ? keys_alt : keys;
-    const uint32_t* sidx = where ? vals_alt : vals;
+    const uint32_t* sidx = idx_bits ? nullptr : (where ? vals_alt : vals);
     mark(3);
     // cells with >= 2 points
     const size_t nt = (N + kTile - 1) / kTile;
@@ -735,16 +746,19 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
     uint32_t* tot = radix_scr + 2 * nt;  // [0] heads, [1] tails
     uint32_t* sscr = radix_scr + 2 * nt + 2;
     kbegin(RTG_K_CELLS);
-    launch_run_count(skeys, N, hcnt, tcnt, stream);
+    launch_run_count(skeys, N, idx_bits, hcnt, tcnt, stream);
     scan_exclusive_u32(hcnt, hcnt, nt, tot, sscr, stream);
     scan_exclusive_u32(tcnt, tcnt, nt, tot + 1, sscr, stream);
-    launch_run_write(skeys, N, hcnt, tcnt, cstart, cend, stream);
+    launch_run_write(skeys, N, idx_bits, hcnt, tcnt, cstart, cend, stream);
     kend(RTG_K_CELLS, 16.0 * (double)N);
-    uint32_t ncells_h = 0, errh0 = 0;
-    if ((rc = read_back(tot, sizeof(uint32_t), &ncells_h))) return rc;
+    uint64_t got[8];
+    Gather g1;
+    g1.add(tot, 4);
+    g1.add(err, 4);
+    if ((rc = gather_back(g1, got))) return rc;
+    const uint32_t ncells_h = (uint32_t)got[0], errh0 = (uint32_t)got[1];
     // A cell coordinate out of range makes the grouping meaningless: stop
     // before the pair kernel sees it.
-    if ((rc = read_back(err, sizeof(uint32_t), &errh0))) return rc;
     if (errh0 & 1u) return RTG_ERANGE;
     if (errh0) return hip_fail(hipErrorUnknown, "radix sort look-back");
     uint64_t tests_total = 0;
@@ -756,21 +770,26 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
       scan_exclusive_u64(tests, tests, ncells_h, scan64 + s64, scan64, stream);
       launch_unit_fill(cstart, cend, units, ncells_h, unit_cell, stream);
       kend(RTG_K_CELLS, 8.0 * (double)ncells_h + 16.0 * (double)ncells_h);
-      if ((rc = read_back(scan64 + s64, sizeof(tests_total), &tests_total))) return rc;
-      if ((rc = read_back(scan32 + s64, sizeof(units_total), &units_total))) return rc;
+      Gather g2;
+      g2.add(scan64 + s64, 8);
+      g2.add(scan32 + s64, 4);
+      if ((rc = gather_back(g2, got))) return rc;
+      tests_total = got[0];
+      units_total = (uint32_t)got[1];
     }
     mark(4);
     st.cells += ncells_h;
     st.tests += (int64_t)tests_total;
     if (units_total == 0) continue;
     PairFilter filt;
+    filt.skeys = skeys;
+    filt.idx_bits = idx_bits;
+    filt.cell_bits = P.seg_bits > 0 ? P.layout.cell_bits : 64;
+    filt.t0 = t0;
     if (first_owner) {
       filt.sig = sig;
       filt.k = k;
       filt.sig64 = sig64;
-      filt.skeys = skeys;
-      filt.cell_bits = P.seg_bits > 0 ? P.layout.cell_bits : 64;
-      filt.t0 = t0;
     }
 
     // Room for this group's pairs: a guess first, the exact count on overflow.
@@ -811,12 +830,15 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
     }
     mark(5);
   }
-  uint32_t errh = 0;
-  unsigned long long rech = 0;
-  if ((rc = read_back(err, sizeof(errh), &errh))) return rc;
+  uint64_t fin[8];
+  Gather g3;
+  g3.add(err, 4);
+  g3.add(counters + 1, 8);
+  if ((rc = gather_back(g3, fin))) return rc;
+  const uint32_t errh = (uint32_t)fin[0];
+  const unsigned long long rech = fin[1];
   if (errh & 1u) return RTG_ERANGE;
   if (errh) return hip_fail(hipErrorUnknown, "radix sort look-back");
-  if ((rc = read_back(counters + 1, sizeof(rech), &rech))) return rc;
   st.band_rechecks = (int64_t)rech;
   st.candidates = (int64_t)cand_total;
 
@@ -964,9 +986,10 @@ int Ctx::debug_cell_coords(const float* points, int64_t n, int32_t d, double r, 
   if (!soa || !flags_dev || !Rd || !ud || !kap) return RTG_ENOMEM;
   if ((rc = upload(Rd, R, sizeof(double) * d * d)) || (rc = upload(ud, u, sizeof(double) * d)))
     return rc;
-  launch_stage_init(flags_dev, flags_dev + 2, d, stream);
+  uint32_t* stage_part = S.get<uint32_t>(stage_scratch_elems(n, d));
+  if (!stage_part) return RTG_ENOMEM;
   launch_fill_u32(flags_dev + 1, 0u, 1, stream);
-  launch_stage(points, n, d, soa, flags_dev, flags_dev + 2, stream);
+  launch_stage(points, n, d, soa, flags_dev, flags_dev + 2, stage_part, stream);
   launch_cell_coords(soa, n, d, Rd, ud, 1.0 / (alpha * r), kap, flags_dev + 1, stream);
   uint32_t fl[2];
   if ((rc = read_back(flags_dev, sizeof(fl), fl))) return rc;
@@ -1005,6 +1028,11 @@ int rtg_create(rtg_ctx** out, int device, void* arena, size_t arena_bytes, void*
   if (hipHostMalloc(&c->host_stage, 4096) != hipSuccess) {
     delete c;
     return RTG_EDEVICE;
+  }
+  c->gather_dev = c->arena->alloc(64);
+  if (!c->gather_dev) {
+    delete c;
+    return RTG_ENOMEM;
   }
   for (auto& e : c->ev)
     if (hipEventCreate(&e) != hipSuccess) {

@@ -44,23 +44,38 @@ struct LaunchTimer {
   }
 };
 
+// Device scalars to bring back with one copy (launch_gather).
+struct Gather {
+  const void* src[8] = {};
+  int bytes[8] = {};
+  int count = 0;
+  void add(const void* p, int nbytes) {
+    src[count] = p;
+    bytes[count] = nbytes;
+    ++count;
+  }
+};
+void launch_gather(const Gather& g, uint64_t* dst, hipStream_t s);
+
 // --- staging --------------------------------------------------------------
-// AoS [n][d] -> SoA [d][n]; flags non-finite values; per-axis min/max as
-// order-preserving uint32 encodings (bbox[2j] = min, bbox[2j+1] = max).
+// AoS [n][d] -> SoA [d][n]; *bad = 1 if a value is not finite (else 0);
+// per-axis min/max as order-preserving uint32 encodings (bbox[2j] = min,
+// bbox[2j+1] = max).  part: stage_scratch_elems(n, d) elements.
+size_t stage_scratch_elems(int64_t n, int d);
 void launch_stage(const float* pts, int64_t n, int d, float* soa, uint32_t* bad,
-                  uint32_t* bbox, hipStream_t s);
-void launch_stage_init(uint32_t* bad, uint32_t* bbox, int d, hipStream_t s);
+                  uint32_t* bbox, uint32_t* part, hipStream_t s);
 
 // --- cell keys ------------------------------------------------------------
 // keys[(t - t0) * n + i] = packed cell of point i under transform t, and
 // vals[...] = i, for t in [t0, t0 + tb).  R [k][d][d], u [k][d] FP64;
 // klo [k][d] int64 origin of the packed range.  err |= 1 if |y| >= 2^31.
 // If sig is not null, also sig[i * k + t] = the packed cell key (u64 if
-// sig64, else u32) of point i under grid t.
+// sig64, else u32) of point i under grid t.  With idx_bits > 0 the point
+// index rides in the key's low bits (key << idx_bits | i) and vals is unused.
 void launch_keys(const float* soa, int64_t n, int d, int t0, int tb, const double* R,
                  const double* u, double inv_c, const int64_t* klo, const KeyLayout* layout,
                  uint64_t* keys, uint32_t* vals, uint32_t* err, void* sig, int sig64, int k,
-                 hipStream_t s);
+                 int idx_bits, hipStream_t s);
 // kappa [n][d] = floor(y) for one transform (stage check).
 void launch_cell_coords(const float* soa, int64_t n, int d, const double* R, const double* u,
                         double inv_c, int64_t* kappa, uint32_t* err, hipStream_t s);
@@ -93,13 +108,13 @@ int radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* val
                int kid_scatter = 0, int algo = kSortOnesweep);
 
 // --- cells ----------------------------------------------------------------
-// Runs of equal keys with length >= 2 in a sorted key array: per tile counts
-// of run heads and run tails (u32 each, ntiles entries).
-void launch_run_count(const uint64_t* keys, size_t count, uint32_t* head_cnt,
+// Runs of equal keys >> shift with length >= 2 in a sorted key array: per
+// tile counts of run heads and run tails (u32 each, ntiles entries).
+void launch_run_count(const uint64_t* keys, size_t count, int shift, uint32_t* head_cnt,
                       uint32_t* tail_cnt, hipStream_t s);
 // Writes start[c] / end[c] of run c (ordered by position) given the scanned
 // per-tile offsets.
-void launch_run_write(const uint64_t* keys, size_t count, const uint32_t* head_off,
+void launch_run_write(const uint64_t* keys, size_t count, int shift, const uint32_t* head_off,
                       const uint32_t* tail_off, uint32_t* start, uint32_t* end, hipStream_t s);
 // units[c] = tiles of 64 points in run c, tests[c] = L(L-1)/2, and
 // *members += sum of L, for c < ncells.
@@ -111,9 +126,10 @@ void launch_unit_fill(const uint32_t* start, const uint32_t* end, const uint32_t
                       uint32_t ncells, uint32_t* unit_cell, hipStream_t s);
 
 // --- cell pairs -----------------------------------------------------------
-// First-owner filter: keep a pair found under grid t only if no grid t' < t
-// put both points in one cell.  sig[i * k + t] is point i's packed cell key
-// under grid t (u32 or u64); null sig turns the filter off.
+// Sorted keys and first-owner filter.  The filter keeps a pair found under
+// grid t only if no grid t' < t put both points in one cell;
+// sig[i * k + t] is point i's packed cell key under grid t (u32 or u64);
+// null sig turns the filter off.  skeys / idx_bits are always set.
 struct PairFilter {
   const void* sig = nullptr;
   int32_t k = 0;
@@ -121,6 +137,7 @@ struct PairFilter {
   const uint64_t* skeys = nullptr;  // sorted keys; grid id sits above cell_bits
   int32_t cell_bits = 64;
   int32_t t0 = 0;                   // first grid of this sort
+  int32_t idx_bits = 0;             // > 0: point index in the low bits of skeys
 };
 
 // One 64-wide wave per unit = (cell, tile a); emits packed pairs

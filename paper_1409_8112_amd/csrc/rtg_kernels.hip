@@ -97,26 +97,16 @@ __global__ void k_fill(T* p, T v, size_t count) {
 // ---------------------------------------------------------------------------
 // stage: one thread per point.
 
-__global__ void k_stage_init(uint32_t* bad, uint32_t* bbox, int d) {
-  int t = threadIdx.x;
-  if (t == 0) *bad = 0u;
-  if (t < d) {
-    bbox[2 * t] = 0xFFFFFFFFu;
-    bbox[2 * t + 1] = 0u;
-  }
-}
-
+// Each block writes its own per-axis min/max (order-preserving encodings)
+// to part[block][2d]; k_bbox_reduce folds them.  (Per-block atomics on the
+// 2d words of one bounding box would all meet at one address per axis.)
 __global__ __launch_bounds__(kBlock) void k_stage(const float* __restrict__ pts, int64_t n, int d,
                                                   float* __restrict__ soa, uint32_t* bad,
-                                                  uint32_t* bbox) {
-  __shared__ uint32_t smin[kMaxDim], smax[kMaxDim];
+                                                  uint32_t* __restrict__ part) {
+  __shared__ uint32_t smin[kWaves][kMaxDim], smax[kWaves][kMaxDim];
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool live = i < n;
-  if (threadIdx.x < (unsigned)d) {
-    smin[threadIdx.x] = 0xFFFFFFFFu;
-    smax[threadIdx.x] = 0u;
-  }
-  __syncthreads();
+  const int w = threadIdx.x >> 6;
   bool nonfinite = false;
   for (int l = 0; l < d; ++l) {
     float v = live ? pts[i * d + l] : 0.0f;
@@ -132,15 +122,45 @@ __global__ __launch_bounds__(kBlock) void k_stage(const float* __restrict__ pts,
       hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
     }
     if (lane_id() == 0) {
-      atomicMin(&smin[l], lo);
-      atomicMax(&smax[l], hi);
+      smin[w][l] = lo;
+      smax[w][l] = hi;
     }
   }
-  if (nonfinite) atomicOr(bad, 1u);
+  if (ballot(nonfinite) && lane_id() == 0) atomicOr(bad, 1u);
   __syncthreads();
   if (threadIdx.x < (unsigned)d) {
-    atomicMin(&bbox[2 * threadIdx.x], smin[threadIdx.x]);
-    atomicMax(&bbox[2 * threadIdx.x + 1], smax[threadIdx.x]);
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) {
+      lo = min(lo, smin[q][threadIdx.x]);
+      hi = max(hi, smax[q][threadIdx.x]);
+    }
+    part[(size_t)blockIdx.x * 2 * d + 2 * threadIdx.x] = lo;
+    part[(size_t)blockIdx.x * 2 * d + 2 * threadIdx.x + 1] = hi;
+  }
+}
+
+// bbox[2j] = min over blocks, bbox[2j+1] = max, one wave per axis.
+__global__ __launch_bounds__(kBlock) void k_bbox_reduce(const uint32_t* __restrict__ part,
+                                                        uint32_t nblocks, int d,
+                                                        uint32_t* __restrict__ bbox) {
+  const int w = threadIdx.x >> 6;
+  const uint32_t lane = lane_id();
+  for (int l = w; l < d; l += kWaves) {
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    for (uint32_t b = lane; b < nblocks; b += 64) {
+      lo = min(lo, part[(size_t)b * 2 * d + 2 * l]);
+      hi = max(hi, part[(size_t)b * 2 * d + 2 * l + 1]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
+      hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
+    }
+    if (lane == 0) {
+      bbox[2 * l] = lo;
+      bbox[2 * l + 1] = hi;
+    }
   }
 }
 
@@ -172,7 +192,8 @@ __global__ __launch_bounds__(kBlock) void k_keys(const float* __restrict__ soa, 
                                                  const KeyLayout* __restrict__ layout,
                                                  uint64_t* __restrict__ keys,
                                                  uint32_t* __restrict__ vals, uint32_t* err,
-                                                 void* __restrict__ sig, int sig64, int k) {
+                                                 void* __restrict__ sig, int sig64, int k,
+                                                 int idx_bits) {
   const int d = D > 0 ? D : d_rt;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
@@ -202,8 +223,12 @@ __global__ __launch_bounds__(kBlock) void k_keys(const float* __restrict__ soa, 
       else static_cast<uint32_t*>(sig)[(size_t)i * k + t] = (uint32_t)cell;
     }
     const uint64_t key = (cell_bits < 64) ? (((uint64_t)tt << cell_bits) | cell) : cell;
-    keys[(int64_t)tt * n + i] = key;
-    vals[(int64_t)tt * n + i] = (uint32_t)i;
+    if (idx_bits) {
+      keys[(int64_t)tt * n + i] = (key << idx_bits) | (uint64_t)i;
+    } else {
+      keys[(int64_t)tt * n + i] = key;
+      vals[(int64_t)tt * n + i] = (uint32_t)i;
+    }
   }
   if (bad) atomicOr(err, 1u);
 }
@@ -541,18 +566,18 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(
 // runs of equal keys (cells with >= 2 points), unique keys.
 
 __device__ __forceinline__ void run_flags(const uint64_t* __restrict__ keys, size_t count, size_t e,
-                                          bool& head, bool& tail) {
+                                          int shift, bool& head, bool& tail) {
   head = tail = false;
   if (e >= count) return;
-  const uint64_t k = keys[e];
-  const bool prev_same = e > 0 && keys[e - 1] == k;
-  const bool next_same = e + 1 < count && keys[e + 1] == k;
+  const uint64_t k = keys[e] >> shift;
+  const bool prev_same = e > 0 && (keys[e - 1] >> shift) == k;
+  const bool next_same = e + 1 < count && (keys[e + 1] >> shift) == k;
   head = !prev_same && next_same;
   tail = prev_same && !next_same;
 }
 
 __global__ __launch_bounds__(kBlock) void k_run_count(const uint64_t* __restrict__ keys,
-                                                      size_t count, uint32_t* head_cnt,
+                                                      size_t count, int shift, uint32_t* head_cnt,
                                                       uint32_t* tail_cnt) {
   __shared__ uint32_t sh[kWaves], st[kWaves];
   const uint32_t lane = lane_id();
@@ -561,7 +586,7 @@ __global__ __launch_bounds__(kBlock) void k_run_count(const uint64_t* __restrict
   uint32_t hc = 0, tc = 0;
   for (int q = 0; q < kKeysPerThread; ++q) {
     bool h, t;
-    run_flags(keys, count, wave_base + (size_t)q * 64 + lane, h, t);
+    run_flags(keys, count, wave_base + (size_t)q * 64 + lane, shift, h, t);
     hc += (uint32_t)__popcll(ballot(h));
     tc += (uint32_t)__popcll(ballot(t));
   }
@@ -582,7 +607,7 @@ __global__ __launch_bounds__(kBlock) void k_run_count(const uint64_t* __restrict
 }
 
 __global__ __launch_bounds__(kBlock) void k_run_write(const uint64_t* __restrict__ keys,
-                                                      size_t count,
+                                                      size_t count, int shift,
                                                       const uint32_t* __restrict__ head_off,
                                                       const uint32_t* __restrict__ tail_off,
                                                       uint32_t* __restrict__ start,
@@ -594,7 +619,7 @@ __global__ __launch_bounds__(kBlock) void k_run_write(const uint64_t* __restrict
   uint32_t hmask = 0, tmask = 0, hc = 0, tc = 0;
   for (int q = 0; q < kKeysPerThread; ++q) {
     bool h, t;
-    run_flags(keys, count, wave_base + (size_t)q * 64 + lane, h, t);
+    run_flags(keys, count, wave_base + (size_t)q * 64 + lane, shift, h, t);
     hmask |= (uint32_t)h << q;
     tmask |= (uint32_t)t << q;
     hc += (uint32_t)__popcll(ballot(h));
@@ -703,6 +728,13 @@ __global__ __launch_bounds__(kBlock) void k_unique_write(const uint64_t* __restr
 constexpr int kSigChunk = 8;
 constexpr int kOutBuf = 512;  // staged pairs per wave
 
+// Point index at sorted position p: the low idx_bits of the sorted key
+// when keys carry it, else the separate index array.
+__device__ __forceinline__ uint32_t point_at(const uint32_t* __restrict__ sidx,
+                                             const PairFilter& F, uint32_t p) {
+  return F.idx_bits ? (uint32_t)(F.skeys[p] & ((1ull << F.idx_bits) - 1ull)) : sidx[p];
+}
+
 template <typename T>
 __device__ __forceinline__ T uniform(T v) {
   return (T)__builtin_amdgcn_readfirstlane((int)v);
@@ -759,12 +791,15 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs(
     const uint32_t nt = (L + kPairTile - 1) / kPairTile;
     const uint32_t nA = min((uint32_t)kPairTile, L - ta * kPairTile);
     int tcell = 0;
-    if (sig) tcell = F.t0 + (F.cell_bits >= 64 ? 0 : (int)uniform((uint32_t)(F.skeys[s0] >> F.cell_bits)));
+    if (sig)
+      tcell = F.t0 + (F.cell_bits >= 64 ? 0
+                                        : (int)uniform((uint32_t)((F.skeys[s0] >> F.idx_bits) >>
+                                                                  F.cell_bits)));
 
     float a[D];
     uint32_t ai = 0;
     const bool rowok = lane < nA;
-    if (rowok) ai = sidx[s0 + ta * kPairTile + lane];
+    if (rowok) ai = point_at(sidx, F, s0 + ta * kPairTile + lane);
 #pragma unroll
     for (int l = 0; l < D; ++l) a[l] = (rowok && l < d) ? pts[(size_t)ai * d + l] : 0.0f;
 
@@ -773,7 +808,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs(
       wave_lds_sync();
       uint32_t bi = 0;
       if (lane < nB) {
-        bi = sidx[s0 + tb * kPairTile + lane];
+        bi = point_at(sidx, F, s0 + tb * kPairTile + lane);
         sBi[w][lane] = bi;
 #pragma unroll
         for (int l = 0; l < DP; ++l) sB[w][lane][l] = (l < d) ? pts[(size_t)bi * d + l] : 0.0f;
@@ -1186,6 +1221,15 @@ __global__ void k_widen(const uint32_t* __restrict__ src, size_t count, uint64_t
   if (q < count) dst[q] = src[q];
 }
 
+// dst[q] = the 4- or 8-byte device scalar at src[q], zero-extended: several
+// scalars come back to the host with one copy.
+__global__ void k_gather(Gather g, uint64_t* __restrict__ dst) {
+  const int q = threadIdx.x;
+  if (q >= g.count) return;
+  dst[q] = g.bytes[q] == 8 ? *static_cast<const uint64_t*>(g.src[q])
+                           : (uint64_t)*static_cast<const uint32_t*>(g.src[q]);
+}
+
 inline unsigned grid_for(size_t count, unsigned block = kBlock) {
   size_t g = (count + block - 1) / block;
   return (unsigned)(g < 1 ? 1 : g);
@@ -1212,35 +1256,35 @@ void launch_fill_u64(uint64_t* p, uint64_t v, size_t count, hipStream_t s) {
   hipLaunchKernelGGL(k_fill<uint64_t>, dim3((unsigned)g), dim3(kBlock), 0, s, p, v, count);
 }
 
-void launch_stage_init(uint32_t* bad, uint32_t* bbox, int d, hipStream_t s) {
-  hipLaunchKernelGGL(k_stage_init, dim3(1), dim3(kMaxDim), 0, s, bad, bbox, d);
-}
+size_t stage_scratch_elems(int64_t n, int d) { return (size_t)grid_for((size_t)n) * 2 * d; }
 
 void launch_stage(const float* pts, int64_t n, int d, float* soa, uint32_t* bad, uint32_t* bbox,
-                  hipStream_t s) {
+                  uint32_t* part, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_stage, dim3(grid_for((size_t)n)), dim3(kBlock), 0, s, pts, n, d, soa, bad,
-                     bbox);
+  const unsigned nb = grid_for((size_t)n);
+  hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(64), 0, s, bad, 0u, (size_t)1);
+  hipLaunchKernelGGL(k_stage, dim3(nb), dim3(kBlock), 0, s, pts, n, d, soa, bad, part);
+  hipLaunchKernelGGL(k_bbox_reduce, dim3(1), dim3(kBlock), 0, s, part, nb, d, bbox);
 }
 
 template <int D>
 static void keys_dispatch(const float* soa, int64_t n, int d, int t0, int tb, const double* R,
                           const double* u, double inv_c, const int64_t* klo,
                           const KeyLayout* layout, uint64_t* keys, uint32_t* vals, uint32_t* err,
-                          void* sig, int sig64, int k, hipStream_t s) {
+                          void* sig, int sig64, int k, int idx_bits, hipStream_t s) {
   hipLaunchKernelGGL(k_keys<D>, dim3(grid_for((size_t)n)), dim3(kBlock), 0, s, soa, n, d, t0, tb, R,
-                     u, inv_c, klo, layout, keys, vals, err, sig, sig64, k);
+                     u, inv_c, klo, layout, keys, vals, err, sig, sig64, k, idx_bits);
 }
 
 void launch_keys(const float* soa, int64_t n, int d, int t0, int tb, const double* R,
                  const double* u, double inv_c, const int64_t* klo, const KeyLayout* layout,
                  uint64_t* keys, uint32_t* vals, uint32_t* err, void* sig, int sig64, int k,
-                 hipStream_t s) {
+                 int idx_bits, hipStream_t s) {
   if (n <= 0) return;
 #define RTG_KEYS_CASE(DV)                                                                       \
   case DV:                                                                                      \
     keys_dispatch<DV>(soa, n, d, t0, tb, R, u, inv_c, klo, layout, keys, vals, err, sig, sig64, \
-                      k, s);                                                                    \
+                      k, idx_bits, s);                                                          \
     break;
   switch (d) {
     RTG_KEYS_CASE(1) RTG_KEYS_CASE(2) RTG_KEYS_CASE(3) RTG_KEYS_CASE(4) RTG_KEYS_CASE(5)
@@ -1249,7 +1293,7 @@ void launch_keys(const float* soa, int64_t n, int d, int t0, int tb, const doubl
     RTG_KEYS_CASE(16)
     default:
       keys_dispatch<0>(soa, n, d, t0, tb, R, u, inv_c, klo, layout, keys, vals, err, sig, sig64, k,
-                       s);
+                       idx_bits, s);
   }
 #undef RTG_KEYS_CASE
 }
@@ -1401,18 +1445,18 @@ int radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* val
   return where;
 }
 
-void launch_run_count(const uint64_t* keys, size_t count, uint32_t* head_cnt, uint32_t* tail_cnt,
-                      hipStream_t s) {
+void launch_run_count(const uint64_t* keys, size_t count, int shift, uint32_t* head_cnt,
+                      uint32_t* tail_cnt, hipStream_t s) {
   if (!count) return;
-  hipLaunchKernelGGL(k_run_count, dim3(tiles_for(count)), dim3(kBlock), 0, s, keys, count, head_cnt,
-                     tail_cnt);
+  hipLaunchKernelGGL(k_run_count, dim3(tiles_for(count)), dim3(kBlock), 0, s, keys, count, shift,
+                     head_cnt, tail_cnt);
 }
 
-void launch_run_write(const uint64_t* keys, size_t count, const uint32_t* head_off,
+void launch_run_write(const uint64_t* keys, size_t count, int shift, const uint32_t* head_off,
                       const uint32_t* tail_off, uint32_t* start, uint32_t* end, hipStream_t s) {
   if (!count) return;
-  hipLaunchKernelGGL(k_run_write, dim3(tiles_for(count)), dim3(kBlock), 0, s, keys, count, head_off,
-                     tail_off, start, end);
+  hipLaunchKernelGGL(k_run_write, dim3(tiles_for(count)), dim3(kBlock), 0, s, keys, count, shift,
+                     head_off, tail_off, start, end);
 }
 
 void launch_cell_work(const uint32_t* start, const uint32_t* end, uint32_t ncells,
@@ -1579,6 +1623,11 @@ void launch_widen(const uint32_t* src, size_t count, uint64_t* dst, hipStream_t 
 
 void launch_u32_to_u64(const uint32_t* src, size_t count, uint64_t* dst, hipStream_t s) {
   launch_widen(src, count, dst, s);
+}
+
+void launch_gather(const Gather& g, uint64_t* dst, hipStream_t s) {
+  if (g.count <= 0) return;
+  hipLaunchKernelGGL(k_gather, dim3(1), dim3(64), 0, s, g, dst);
 }
 
 }  // namespace rtgk

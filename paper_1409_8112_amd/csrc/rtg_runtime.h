@@ -72,6 +72,7 @@ struct Ctx {
   void* arena_mem = nullptr;
   std::unique_ptr<Arena> arena;
   void* host_stage = nullptr;  // pinned staging for scalar read-backs
+  void* gather_dev = nullptr;  // 8 device u64 that gather_back fills
   bool poisoned = false;
   uint32_t timing_mask = 0;  // bit i: time kernel id i; RTG_TIME_PHASES: phases
   int sort_algo = 0;         // rtgk::kSortOnesweep or rtgk::kSortReduceScan
@@ -91,6 +92,8 @@ struct Ctx {
   void dfree(void* p);
   int sync();
   int read_back(const void* dev, size_t bytes, void* host);
+  // Several device scalars in one copy (one sync).
+  int gather_back(const rtgk::Gather& g, uint64_t* host);
   int upload(void* dev, const void* host, size_t bytes);
   void mark(int phase);
   void kbegin(int kid);
