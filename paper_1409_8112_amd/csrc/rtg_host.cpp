@@ -197,40 +197,53 @@ int min_field_bits(double alpha) {
   return 33;
 }
 
-int plan_packing(int d, int k, const double* R, const double* u, double inv_c, double alpha,
-                 const float* lo, const float* hi, int64_t n, size_t budget_bytes, Packing& P) {
+int plan_batch(int d, uint32_t m, const int64_t* k, const int64_t* n, const double* R,
+               const double* u, const double* inv_c, const double* alpha, const float* lo,
+               const float* hi, size_t budget_bytes, Packing& P) {
+  int64_t S_total = 0, nmax = 0, elems_all = 0;
+  for (uint32_t q = 0; q < m; ++q) {
+    S_total += k[q];
+    nmax = std::max(nmax, n[q]);
+    elems_all += n[q] * k[q];
+  }
   std::vector<int> need(d, 1);
-  P.klo.assign((size_t)k * d, 0);
-  for (int t = 0; t < k; ++t) {
-    for (int j = 0; j < d; ++j) {
-      const double* Rj = R + ((size_t)t * d + j) * d;
-      double zlo = 0.0, zhi = 0.0;
-      for (int l = 0; l < d; ++l) {
-        const double a = Rj[l] * (double)lo[l], b = Rj[l] * (double)hi[l];
-        zlo += std::min(a, b);
-        zhi += std::max(a, b);
+  P.klo.assign((size_t)S_total * d, 0);
+  int bmin = 1;
+  int64_t tr = 0;
+  for (uint32_t q = 0; q < m; ++q) {
+    bmin = std::max(bmin, min_field_bits(alpha[q]));
+    const float* lq = lo + (size_t)q * d;
+    const float* hq = hi + (size_t)q * d;
+    for (int64_t t = 0; t < k[q]; ++t, ++tr) {
+      for (int j = 0; j < d; ++j) {
+        const double* Rj = R + ((size_t)tr * d + j) * d;
+        double zlo = 0.0, zhi = 0.0;
+        for (int l = 0; l < d; ++l) {
+          const double a = Rj[l] * (double)lq[l], b = Rj[l] * (double)hq[l];
+          zlo += std::min(a, b);
+          zhi += std::max(a, b);
+        }
+        const double ylo = zlo * inv_c[q] + u[(size_t)tr * d + j];
+        const double yhi = zhi * inv_c[q] + u[(size_t)tr * d + j];
+        int bits = 32;
+        int64_t klo = 0;
+        if (std::fabs(ylo) < 0x1p31 && std::fabs(yhi) < 0x1p31) {
+          // one cell of slack on each side covers the rounding of y
+          klo = (int64_t)std::floor(ylo) - 1;
+          const int64_t khi = (int64_t)std::floor(yhi) + 1;
+          bits = std::max(1, ceil_log2((uint64_t)(khi - klo + 1)));
+        }
+        P.klo[(size_t)tr * d + j] = klo;
+        need[j] = std::max(need[j], std::min(bits, 32));
       }
-      const double ylo = zlo * inv_c + u[(size_t)t * d + j];
-      const double yhi = zhi * inv_c + u[(size_t)t * d + j];
-      int bits = 32;
-      int64_t klo = 0;
-      if (std::fabs(ylo) < 0x1p31 && std::fabs(yhi) < 0x1p31) {
-        // one cell of slack on each side covers the rounding of y
-        klo = (int64_t)std::floor(ylo) - 1;
-        const int64_t khi = (int64_t)std::floor(yhi) + 1;
-        bits = std::max(1, ceil_log2((uint64_t)(khi - klo + 1)));
-      }
-      P.klo[(size_t)t * d + j] = klo;
-      need[j] = std::max(need[j], std::min(bits, 32));
     }
   }
-  const int bmin = min_field_bits(alpha);
   if (bmin > 32) return RTG_ERANGE;
   for (int j = 0; j < d; ++j) need[j] = std::max(need[j], bmin);
 
-  // Grids per sort: as many as the key bits, the 32-bit element index of
+  // Segments per pass: as many as the key bits, the 32-bit element index of
   // the sort and the memory budget allow.
-  int tb = k;
+  int64_t tb = S_total;
   for (;;) {
     const int seg_bits = tb > 1 ? ceil_log2((uint64_t)tb) : 0;
     const int avail = 64 - seg_bits;
@@ -246,11 +259,11 @@ int plan_packing(int d, int k, const double* R, const double* u, double inv_c, d
       --b[jw];
       --total;
     }
-    const uint64_t elems = (uint64_t)n * (uint64_t)tb;
+    const uint64_t elems = (uint64_t)std::min<int64_t>(elems_all, tb * nmax);
     const size_t bytes = (size_t)elems * 28;  // two key/value buffers + cells
     const bool fits = total <= avail && elems < (1ull << 32) && (bytes <= budget_bytes || tb == 1);
     if (fits) {
-      P.tb = tb;
+      P.tb = (int)tb;
       P.seg_bits = seg_bits;
       P.layout.d = d;
       P.layout.cell_bits = total;
@@ -281,6 +294,14 @@ Ctx::Ctx(int dev, hipStream_t s) : device(dev), stream(s) {
   sort_algo = (e && std::strcmp(e, "onesweep") == 0) ? kSortOnesweep : kSortReduceScan;
   // RTG_BUCKET_CAP lowers the entries a neighbour-list bucket may hold in
   // LDS (tests use it to send buckets down the global-sort fallback).
+  // RTG_BATCH_POINTS lowers the points per batch of rtg_all_pairs_batched
+  // (tests use it to split small batches).
+  const char* bp = std::getenv("RTG_BATCH_POINTS");
+  batch_points = kBatchPoints;
+  if (bp) {
+    const long long v = std::strtoll(bp, nullptr, 10);
+    if (v >= 2 && v < kBatchPoints) batch_points = v;
+  }
   const char* bc = std::getenv("RTG_BUCKET_CAP");
   bucket_cap = kBucketMaxEntries;
   if (bc) {
@@ -592,20 +613,64 @@ int Ctx::make_empty_result(int64_t n, rtg_csr* out) {
   return RTG_OK;
 }
 
-int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha,
-                   const double* R, const double* u, uint32_t flags, rtg_csr* out) {
-  if (poisoned) return RTG_EDEVICE;
+// Argument checks of one query that need no device work beyond a pointer
+// query: the shared rules, a device pointer of this context's device, and
+// r*r inside the range where the FP32 screen's band is sound.
+int Ctx::check_query(const float* points, int64_t n, int32_t d, double r, int32_t k,
+                     double alpha) {
   int rc = validate_query(points, n, d, r, k, alpha);
   if (rc) return rc;
   if (n > 0 && check_device_pointer(points, device)) return RTG_EINVAL;
   const double r2 = r * r;
   if (!(r2 >= 0x1p-100 && r2 <= 0x1p120)) return RTG_ERANGE;
+  return RTG_OK;
+}
 
+// Lists for a query of n <= 1 points: empty, after the finiteness check.
+int Ctx::tiny_query(const float* points, int64_t n, int32_t d, rtg_csr* out) {
+  if (n == 1) {
+    std::vector<float> h(d);
+    if (hip_fail(hipMemcpy(h.data(), points, sizeof(float) * d, hipMemcpyDeviceToHost), "copy"))
+      return RTG_EDEVICE;
+    for (float v : h)
+      if (!std::isfinite(v)) return RTG_EINVAL;
+  }
+  return make_empty_result(n, out);
+}
+
+int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha,
+                   const double* R, const double* u, uint32_t flags, rtg_csr* out) {
+  if (poisoned) return RTG_EDEVICE;
+  int rc = check_query(points, n, d, r, k, alpha);
+  if (rc) return rc;
   rtg_stats st{};
   st.n = n;
   st.d = d;
   st.k = k;
   st.point_transforms = n * k;
+  if (n <= 1) {
+    rc = tiny_query(points, n, d, out);
+    if (!rc) stats = st;
+    return rc;
+  }
+  Job job{points, n, d, r, alpha, k, flags, R, u, out};
+  std::vector<Job*> jobs{&job};
+  rc = run_batch(jobs, st);
+  if (!rc) stats = st;
+  return rc;
+}
+
+// One pass of the pipeline over a batch of instances of one dimension d
+// sharing the RTG_UPPER_ONLY / RTG_DEDUP_SORT flags (every instance has
+// n >= 2 and passed check_query).  On success each job's out is filled.
+int Ctx::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
+  const uint32_t m = (uint32_t)jobs.size();
+  const int d = jobs[0]->d;
+  const uint32_t flags = jobs[0]->flags;
+  const bool both = !(flags & RTG_UPPER_ONLY);
+  const bool first_owner = !(flags & RTG_DEDUP_SORT);
+  int rc;
+
   kstats = &st;
   kpending.clear();
   struct Detach {
@@ -616,73 +681,124 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
     }
   } detach{*this};
   const LaunchTimer tm = timer();
-  if (n <= 1) {
-    // Still reject non-finite coordinates, as for any other n.
-    if (n == 1) {
-      std::vector<float> h(d);
-      if (hip_fail(hipMemcpy(h.data(), points, sizeof(float) * d, hipMemcpyDeviceToHost), "copy"))
-        return RTG_EDEVICE;
-      for (float v : h)
-        if (!std::isfinite(v)) return RTG_EINVAL;
-    }
-    rc = make_empty_result(n, out);
-    if (!rc) stats = st;
-    return rc;
+  Scratch S(*this);
+  mark(0);
+
+  // --- the batch's instances and segments (host) -----------------------------
+  std::vector<InstDesc> inst(m);
+  int64_t npts = 0;
+  uint32_t nblk = 0;
+  int32_t S_total = 0, kmax = 0;
+  for (uint32_t q = 0; q < m; ++q) {
+    const Job& j = *jobs[q];
+    inst[q].pts = j.pts;
+    inst[q].pt_off = npts;
+    inst[q].n = j.n;
+    inst[q].inv_c = 1.0 / (j.alpha * j.r);
+    inst[q].k = j.k;
+    inst[q].tr_off = S_total;
+    inst[q].seg_first = S_total;
+    inst[q].blk_first = (int32_t)nblk;
+    npts += j.n;
+    nblk += (uint32_t)((j.n + kBlock - 1) / kBlock);
+    S_total += j.k;
+    kmax = std::max(kmax, j.k);
+  }
+  if (npts >= (int64_t(1) << 31)) return RTG_ENOMEM;
+  const int pair_bits = std::max(1, ceil_log2((uint64_t)npts));
+  std::vector<PairTest> tests(m);
+  std::vector<double> Rh((size_t)S_total * d * d), uh((size_t)S_total * d);
+  for (uint32_t q = 0; q < m; ++q) {
+    const Job& j = *jobs[q];
+    tests[q] = make_pair_test(j.r * j.r, pair_bits);
+    std::memcpy(&Rh[(size_t)inst[q].tr_off * d * d], j.R, sizeof(double) * (size_t)j.k * d * d);
+    std::memcpy(&uh[(size_t)inst[q].tr_off * d], j.u, sizeof(double) * (size_t)j.k * d);
   }
 
-  Scratch S(*this);
-  const double c = alpha * r;
-  const double inv_c = 1.0 / c;
-  const int pair_bits = std::max(1, ceil_log2((uint64_t)n));
-  const PairTest ptest = make_pair_test(r2, pair_bits);
-
-  mark(0);
-  // --- stage ---------------------------------------------------------------
-  float* soa = S.get<float>((size_t)n * d);
-  uint32_t* flags_dev = S.get<uint32_t>(2 + 2 * kMaxDim);  // [0] bad, [1] err, bbox
-  double* Rd = S.get<double>((size_t)k * d * d);
-  double* ud = S.get<double>((size_t)k * d);
-  unsigned long long* counters = S.get<unsigned long long>(4);  // cand, rechecks, next item
-  if (!soa || !flags_dev || !Rd || !ud || !counters) return RTG_ENOMEM;
-  uint32_t* bad = flags_dev;
-  uint32_t* err = flags_dev + 1;
-  uint32_t* bbox = flags_dev + 2;
-  if ((rc = upload(Rd, R, sizeof(double) * (size_t)k * d * d))) return rc;
-  if ((rc = upload(ud, u, sizeof(double) * (size_t)k * d))) return rc;
-  uint32_t* stage_part = S.get<uint32_t>(stage_scratch_elems(n, d));
-  if (!stage_part) return RTG_ENOMEM;
+  InstDesc* inst_d = S.get<InstDesc>(m);
+  PairTest* tests_d = S.get<PairTest>(m);
+  double* Rd = S.get<double>(Rh.size());
+  double* ud = S.get<double>(uh.size());
+  float* soa = S.get<float>((size_t)npts * d);
+  float* aos = m > 1 ? S.get<float>((size_t)npts * d) : nullptr;
+  uint32_t* part = S.get<uint32_t>((size_t)nblk * 2 * d);
+  uint32_t* bbox = S.get<uint32_t>((size_t)m * 2 * d + 2);  // + [bad, err]
+  unsigned long long* counters = S.get<unsigned long long>(4);  // cand, rechecks, -, members
+  if (!inst_d || !tests_d || !Rd || !ud || !soa || (m > 1 && !aos) || !part || !bbox || !counters)
+    return RTG_ENOMEM;
+  uint32_t* bad = bbox + (size_t)m * 2 * d;
+  uint32_t* err = bad + 1;
+  if ((rc = upload(inst_d, inst.data(), sizeof(InstDesc) * m))) return rc;
+  if ((rc = upload(tests_d, tests.data(), sizeof(PairTest) * m))) return rc;
+  if ((rc = upload(Rd, Rh.data(), sizeof(double) * Rh.size()))) return rc;
+  if ((rc = upload(ud, uh.data(), sizeof(double) * uh.size()))) return rc;
   launch_fill_u32(err, 0u, 1, stream);
   launch_fill_u64(reinterpret_cast<uint64_t*>(counters), 0ull, 4, stream);
-  kbegin(RTG_K_STAGE);
-  launch_stage(points, n, d, soa, bad, bbox, stage_part, stream);
-  kend(RTG_K_STAGE, 8.0 * (double)n * d);
-  mark(1);
-  std::vector<uint32_t> hb(2 + 2 * kMaxDim);
-  if ((rc = read_back(flags_dev, sizeof(uint32_t) * (2 + 2 * d), hb.data()))) return rc;
-  if (hb[0]) return RTG_EINVAL;
-  std::vector<float> lo(d), hi(d);
-  for (int j = 0; j < d; ++j) {
-    lo[j] = decode_order(hb[2 + 2 * j]);
-    hi[j] = decode_order(hb[3 + 2 * j]);
-  }
 
+  // --- stage: SoA copy (+ concatenated rows), finiteness, bounding boxes -------
+  kbegin(RTG_K_STAGE);
+  launch_stage(inst_d, m, nblk, d, npts, soa, aos, bad, bbox, part, stream);
+  kend(RTG_K_STAGE, (aos ? 12.0 : 8.0) * (double)npts * d);
+  mark(1);
+  std::vector<uint32_t> hb((size_t)m * 2 * d + 1);
+  if ((rc = sync())) return rc;
+  if ((rc = hip_fail(hipMemcpy(hb.data(), bbox, sizeof(uint32_t) * hb.size(),
+                               hipMemcpyDeviceToHost), "copy bounding boxes")))
+    return rc;
+  if (hb[(size_t)m * 2 * d]) return RTG_EINVAL;
+  const float* pts_rows = aos ? aos : jobs[0]->pts;
+
+  // --- key layout shared by the batch ---------------------------------------------
   Packing P;
-  rc = plan_packing(d, k, R, u, inv_c, alpha, lo.data(), hi.data(), n, arena->largest_free() / 2,
-                    P);
-  if (rc) return rc;
-  st.key_bits = P.key_bits;
-  st.key_passes = (P.key_bits + kRadixBits - 1) / kRadixBits;
+  {
+    std::vector<float> lo((size_t)m * d), hi((size_t)m * d);
+    for (size_t e = 0; e < (size_t)m * d; ++e) {
+      lo[e] = decode_order(hb[2 * e]);
+      hi[e] = decode_order(hb[2 * e + 1]);
+    }
+    std::vector<double> alphas(m), inv_cs(m);
+    std::vector<int64_t> ns(m), ks(m);
+    for (uint32_t q = 0; q < m; ++q) {
+      alphas[q] = jobs[q]->alpha;
+      inv_cs[q] = inst[q].inv_c;
+      ns[q] = jobs[q]->n;
+      ks[q] = jobs[q]->k;
+    }
+    rc = plan_batch(d, m, ks.data(), ns.data(), Rh.data(), uh.data(), inv_cs.data(),
+                    alphas.data(), lo.data(), hi.data(), arena->largest_free() / 2, P);
+    if (rc) return rc;
+  }
+  st.key_bits = std::max(st.key_bits, P.key_bits);
+  st.key_passes = std::max(st.key_passes, (P.key_bits + kRadixBits - 1) / kRadixBits);
   st.pair_bits = 2 * pair_bits;
   st.transforms_per_sort = P.tb;
 
   KeyLayout* layout_d = S.get<KeyLayout>(1);
-  int64_t* klo_d = S.get<int64_t>((size_t)k * d);
-  if (!layout_d || !klo_d) return RTG_ENOMEM;
+  int64_t* klo_d = S.get<int64_t>(P.klo.size());
+  SegDesc* segs_d = S.get<SegDesc>((size_t)S_total);
+  if (!layout_d || !klo_d || !segs_d) return RTG_ENOMEM;
   if ((rc = upload(layout_d, &P.layout, sizeof(KeyLayout)))) return rc;
-  if ((rc = upload(klo_d, P.klo.data(), sizeof(int64_t) * (size_t)k * d))) return rc;
+  if ((rc = upload(klo_d, P.klo.data(), sizeof(int64_t) * P.klo.size()))) return rc;
 
-  // --- per group of grids: keys, sort, cells, pairs ---------------------------
-  const size_t NB = (size_t)n * (size_t)P.tb;
+  // Passes: consecutive ranges of P.tb segments; key offsets restart per pass.
+  std::vector<SegDesc> segs((size_t)S_total);
+  size_t NB = 0;
+  for (int32_t sa = 0; sa < S_total; sa += P.tb) {
+    const int32_t sb = std::min(S_total, sa + P.tb);
+    int64_t off = 0;
+    for (uint32_t q = 0; q < m; ++q)
+      for (int32_t t = 0; t < jobs[q]->k; ++t) {
+        const int32_t s = inst[q].seg_first + t;
+        if (s < sa || s >= sb) continue;
+        segs[s].key_off = off;
+        segs[s].inst = (int32_t)q;
+        segs[s].t = t;
+        off += jobs[q]->n;
+      }
+    NB = std::max(NB, (size_t)off);
+  }
+  if ((rc = upload(segs_d, segs.data(), sizeof(SegDesc) * segs.size()))) return rc;
+
   // The point index rides in the low bits of the key when both fit in 64
   // bits: the sort then moves 8 bytes per element instead of 12.
   const int idx_bits = (P.key_bits + pair_bits <= 64) ? pair_bits : 0;
@@ -691,49 +807,53 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
   uint32_t* vals = idx_bits ? nullptr : S.get<uint32_t>(NB);
   uint32_t* vals_alt = idx_bits ? nullptr : S.get<uint32_t>(NB);
   const size_t ntiles = (NB + kTile - 1) / kTile;
-  void* sort_scr = S.get<char>(radix_scratch_bytes(NB, 0, P.key_bits));  // passes as for 0..key_bits
-  uint32_t* radix_scr = S.get<uint32_t>(2 * ntiles + 8 + scan_scratch_elems(ntiles));
+  void* sort_scr = S.get<char>(radix_scratch_bytes(NB, 0, P.key_bits));
+  uint32_t* run_scr = S.get<uint32_t>(2 * ntiles + 8 + scan_scratch_elems(ntiles));
   const size_t max_cells = NB / 2 + 1;
   const size_t max_units = max_cells + NB / kPairTile + 1;
   uint32_t* cstart = S.get<uint32_t>(max_cells);
   uint32_t* cend = S.get<uint32_t>(max_cells);
   uint32_t* units = S.get<uint32_t>(max_cells);
   uint32_t* unit_cell = S.get<uint32_t>(max_units);
-  uint64_t* tests = S.get<uint64_t>(max_cells);
+  uint64_t* tests_c = S.get<uint64_t>(max_cells);
   const size_t s64 = scan_scratch_elems(max_cells);
   uint64_t* scan64 = S.get<uint64_t>(s64 + 4);
-  uint32_t* scan32 = S.get<uint32_t>(scan_scratch_elems(max_cells) + 4);
-  if (!keys || !keys_alt || (!idx_bits && (!vals || !vals_alt)) || !sort_scr || !radix_scr ||
-      !cstart || !cend || !units ||
-      !unit_cell || !tests || !scan64 || !scan32)
+  uint32_t* scan32 = S.get<uint32_t>(s64 + 4);
+  if (!keys || !keys_alt || (!idx_bits && (!vals || !vals_alt)) || !sort_scr || !run_scr ||
+      !cstart || !cend || !units || !unit_cell || !tests_c || !scan64 || !scan32)
     return RTG_ENOMEM;
 
   // First-owner filter (default): each pair is emitted only by the first grid
   // whose cell holds both points, so the union needs no de-duplication.  It
   // needs every point's packed cell key under every grid.
-  const bool first_owner = !(flags & RTG_DEDUP_SORT);
   const int sig64 = P.layout.cell_bits > 32 ? 1 : 0;
   void* sig = nullptr;
   if (first_owner) {
-    sig = dalloc((size_t)n * k * (sig64 ? 8 : 4));
+    sig = S.get<char>((size_t)npts * kmax * (sig64 ? 8 : 4));
     if (!sig) return RTG_ENOMEM;
-    S.held.push_back(sig);
   }
 
   uint64_t cap = 0;
   uint64_t* cand = nullptr;
   uint64_t cand_total = 0;  // exact number of candidates so far
 
-  for (int t0 = 0; t0 < k; t0 += P.tb) {
-    const int tb = std::min(P.tb, k - t0);
-    const size_t N = (size_t)n * tb;
+  for (int32_t sa = 0; sa < S_total; sa += P.tb) {
+    const int32_t sb = std::min(S_total, sa + P.tb);
+    size_t N = 0, pass_pts = 0;
+    for (int32_t s = sa; s < sb; ++s) {
+      N += (size_t)jobs[segs[s].inst]->n;
+      if (s == sa || segs[s].inst != segs[s - 1].inst) pass_pts += (size_t)jobs[segs[s].inst]->n;
+    }
+    const int seg_bits = (sb - sa) > 1 ? ceil_log2((uint64_t)(sb - sa)) : 0;
+    const int key_bits = seg_bits + P.layout.cell_bits;
+    KeysArgs ka{inst_d, m, nblk, d, npts, soa, sa, sb, segs_d, Rd, ud, klo_d, layout_d,
+                keys, vals, err, sig, sig64, kmax, idx_bits};
     kbegin(RTG_K_KEYS);
-    launch_keys(soa, n, d, t0, tb, Rd, ud, inv_c, klo_d, layout_d, keys, vals, err, sig, sig64, k,
-                idx_bits, stream);
-    kend(RTG_K_KEYS, 4.0 * (double)n * d + (idx_bits ? 8.0 : 12.0) * (double)N +
+    launch_keys(ka, stream);
+    kend(RTG_K_KEYS, 4.0 * (double)pass_pts * d + (idx_bits ? 8.0 : 12.0) * (double)N +
                          (sig ? (sig64 ? 8.0 : 4.0) * (double)N : 0.0));
     mark(2);
-    const int where = radix_sort(keys, vals, keys_alt, vals_alt, N, idx_bits, idx_bits + P.key_bits,
+    const int where = radix_sort(keys, vals, keys_alt, vals_alt, N, idx_bits, idx_bits + key_bits,
                                  sort_scr, err, stream, &tm, RTG_K_KEY_HIST, RTG_K_KEY_SCATTER,
                                  sort_algo);
     const uint64_t* skeys = where ? keys_alt : keys;
@@ -741,10 +861,10 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
     mark(3);
     // cells with >= 2 points
     const size_t nt = (N + kTile - 1) / kTile;
-    uint32_t* hcnt = radix_scr;
-    uint32_t* tcnt = radix_scr + nt;
-    uint32_t* tot = radix_scr + 2 * nt;  // [0] heads, [1] tails
-    uint32_t* sscr = radix_scr + 2 * nt + 2;
+    uint32_t* hcnt = run_scr;
+    uint32_t* tcnt = run_scr + nt;
+    uint32_t* tot = run_scr + 2 * nt;  // [0] heads, [1] tails
+    uint32_t* sscr = run_scr + 2 * nt + 2;
     kbegin(RTG_K_CELLS);
     launch_run_count(skeys, N, idx_bits, hcnt, tcnt, stream);
     scan_exclusive_u32(hcnt, hcnt, nt, tot, sscr, stream);
@@ -765,11 +885,12 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
     uint32_t units_total = 0;
     if (ncells_h) {
       kbegin(RTG_K_CELLS);
-      launch_cell_work(cstart, cend, ncells_h, units, tests, counters + 3, stream);
+      launch_fill_u64(reinterpret_cast<uint64_t*>(counters) + 3, 0ull, 1, stream);
+      launch_cell_work(cstart, cend, ncells_h, units, tests_c, counters + 3, stream);
       scan_exclusive_u32(units, units, ncells_h, scan32 + s64, scan32, stream);
-      scan_exclusive_u64(tests, tests, ncells_h, scan64 + s64, scan64, stream);
+      scan_exclusive_u64(tests_c, tests_c, ncells_h, scan64 + s64, scan64, stream);
       launch_unit_fill(cstart, cend, units, ncells_h, unit_cell, stream);
-      kend(RTG_K_CELLS, 8.0 * (double)ncells_h + 16.0 * (double)ncells_h);
+      kend(RTG_K_CELLS, 24.0 * (double)ncells_h);
       Gather g2;
       g2.add(scan64 + s64, 8);
       g2.add(scan32 + s64, 4);
@@ -784,17 +905,15 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
     PairFilter filt;
     filt.skeys = skeys;
     filt.idx_bits = idx_bits;
-    filt.cell_bits = P.seg_bits > 0 ? P.layout.cell_bits : 64;
-    filt.t0 = t0;
     if (first_owner) {
       filt.sig = sig;
-      filt.k = k;
+      filt.k = kmax;
       filt.sig64 = sig64;
     }
 
-    // Room for this group's pairs: a guess first, the exact count on overflow.
-    uint64_t want =
-        cand_total + std::min<uint64_t>(tests_total, std::max<uint64_t>(1u << 20, tests_total / 16));
+    // Room for this pass's pairs: a guess first, the exact count on overflow.
+    uint64_t want = cand_total + std::min<uint64_t>(tests_total,
+                                                    std::max<uint64_t>(1u << 20, tests_total / 16));
     for (int attempt = 0; attempt < 2; ++attempt) {
       if (want > cap) {
         uint64_t* grown = static_cast<uint64_t*>(dalloc(sizeof(uint64_t) * want));
@@ -810,15 +929,18 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
         cap = want;
       }
       launch_fill_u64(reinterpret_cast<uint64_t*>(counters), cand_total, 1, stream);
+      PairsArgs pa{pts_rows, d, sidx, cstart, cend, unit_cell, units, units_total, tests_d,
+                   segs_d, sa, seg_bits > 0 ? idx_bits + P.layout.cell_bits : 64, filt, cand, cap,
+                   counters, counters + 1};
       kbegin(RTG_K_PAIRS);
-      launch_cell_pairs(points, d, sidx, cstart, cend, unit_cell, units, units_total, ptest, filt,
-                        cand, cap, counters, counters + 1, counters + 2, stream);
-      unsigned long long cnt[4] = {0, 0, 0, 0};
-      // bytes: every member of a cell read once (index + coordinates), every
-      // pair within r written once
+      launch_cell_pairs(pa, stream);
       kend(RTG_K_PAIRS, 0.0);
+      unsigned long long cnt[4] = {0, 0, 0, 0};
       if ((rc = read_back(counters, sizeof(cnt), cnt))) return rc;
       const unsigned long long now = cnt[0];
+      // every member of a multi-point cell read once (index + coordinates;
+      // counters[3] = members, summed by the cell-work kernel of this pass),
+      // every pair within r written once
       st.kernel_bytes[RTG_K_PAIRS] +=
           (4.0 + 4.0 * d) * (double)cnt[3] + 8.0 * (double)(now - cand_total);
       if (now <= cap) {
@@ -830,38 +952,30 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
     }
     mark(5);
   }
-  uint64_t fin[8];
-  Gather g3;
-  g3.add(err, 4);
-  g3.add(counters + 1, 8);
-  if ((rc = gather_back(g3, fin))) return rc;
-  const uint32_t errh = (uint32_t)fin[0];
-  const unsigned long long rech = fin[1];
-  if (errh & 1u) return RTG_ERANGE;
-  if (errh) return hip_fail(hipErrorUnknown, "radix sort look-back");
-  st.band_rechecks = (int64_t)rech;
-  st.candidates = (int64_t)cand_total;
+  {
+    uint64_t fin[8];
+    Gather g3;
+    g3.add(err, 4);
+    g3.add(counters + 1, 8);
+    if ((rc = gather_back(g3, fin))) return rc;
+    if (fin[0] & 1u) return RTG_ERANGE;
+    if (fin[0]) return hip_fail(hipErrorUnknown, "radix sort look-back");
+    st.band_rechecks += (int64_t)fin[1];
+  }
+  st.candidates += (int64_t)cand_total;
 
   // Key buffers are no longer needed.
-  S.drop(keys);
-  S.drop(keys_alt);
-  S.drop(vals);
-  S.drop(vals_alt);
-  S.drop(cstart);
-  S.drop(cend);
-  S.drop(units);
-  S.drop(unit_cell);
-  S.drop(tests);
-  if (sig) S.drop(sig);
+  for (void* p : {(void*)keys, (void*)keys_alt, (void*)vals, (void*)vals_alt, (void*)cstart,
+                  (void*)cend, (void*)units, (void*)unit_cell, (void*)tests_c, sig})
+    S.drop(p);
 
   // --- union and neighbour lists ------------------------------------------------
-  const bool both = !(flags & RTG_UPPER_ONLY);
   const size_t C = cand_total;
   if (C >= (1ull << 32)) return RTG_ENOMEM;
-  // Row buckets need a 32-bit local entry (rb <= 8 row bits + pair_bits) and
-  // at most 2^14 buckets; larger inputs take the sorted-pair build below.
-  const bool bucket_ok = pair_bits <= 24 && ceil_log2((uint64_t)n) <= 22 &&
-                         ceil_log2((uint64_t)n) - 14 + pair_bits <= 32 &&
+  // Row buckets need a 32-bit local entry (rb row bits + pair_bits) and at
+  // most 2^14 buckets; larger batches take the sorted-pair build below.
+  const bool bucket_ok = pair_bits <= 24 && ceil_log2((uint64_t)npts) <= 22 &&
+                         ceil_log2((uint64_t)npts) - 14 + pair_bits <= 32 &&
                          (both ? 2 * C : C) < (1ull << 32);
   const uint64_t* pairs = cand;  // pairs for the neighbour-list build
   size_t npairs = C;
@@ -905,36 +1019,88 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
   int32_t* col = nullptr;
   size_t nnz = 0;
   if (npairs == 0) {
-    if ((rc = alloc_result(*this, n, 0, &res, &row_ptr, &col))) return rc;
-    launch_fill_u64(reinterpret_cast<uint64_t*>(row_ptr), 0ull, (size_t)(n + 1), stream);
+    if ((rc = alloc_result(*this, npts, 0, &res, &row_ptr, &col))) return rc;
+    launch_fill_u64(reinterpret_cast<uint64_t*>(row_ptr), 0ull, (size_t)(npts + 1), stream);
   } else if (bucket_ok) {
-    rc = csr_by_buckets(*this, S, pairs, npairs, n, pair_bits, both, err, &tm, &res, &row_ptr, &col,
-                        &nnz);
+    rc = csr_by_buckets(*this, S, pairs, npairs, npts, pair_bits, both, err, &tm, &res, &row_ptr,
+                        &col, &nnz);
     if (rc) return rc;
   } else {
     nnz = both ? 2 * npairs : npairs;
-    if ((rc = alloc_result(*this, n, nnz, &res, &row_ptr, &col))) return rc;
-    rc = csr_from_sorted(*this, S, pairs, npairs, n, pair_bits, both, err, row_ptr, col);
+    if ((rc = alloc_result(*this, npts, nnz, &res, &row_ptr, &col))) return rc;
+    rc = csr_from_sorted(*this, S, pairs, npairs, npts, pair_bits, both, err, row_ptr, col);
     if (rc) {
       dfree(res);
       return rc;
     }
   }
-  const size_t U = both ? nnz / 2 : nnz;
-  st.unique_pairs = (int64_t)U;
+  st.unique_pairs += (int64_t)(both ? nnz / 2 : nnz);
+
+  // --- per-instance lists ------------------------------------------------------------
+  if (m == 1) {
+    Job& j = *jobs[0];
+    j.out->n = j.n;
+    j.out->nnz = (int64_t)nnz;
+    j.out->row_ptr = row_ptr;
+    j.out->col = nnz ? col : nullptr;
+    j.out->pairs = (int64_t)(both ? nnz / 2 : nnz);
+  } else {
+    std::vector<int64_t> at(m + 1);
+    int64_t* at_d = S.get<int64_t>(m + 1);
+    int64_t** rp_tab = S.get<int64_t*>(m);
+    int32_t** col_tab = S.get<int32_t*>(m);
+    if (!at_d || !rp_tab || !col_tab) {
+      dfree(res);
+      return RTG_ENOMEM;
+    }
+    launch_rowptr_at(inst_d, m, row_ptr, npts, at_d, stream);
+    if ((rc = sync()) || (rc = hip_fail(hipMemcpy(at.data(), at_d, sizeof(int64_t) * (m + 1),
+                                                  hipMemcpyDeviceToHost), "copy row offsets"))) {
+      dfree(res);
+      return rc;
+    }
+    std::vector<void*> mem(m, nullptr);
+    std::vector<int64_t*> rps(m);
+    std::vector<int32_t*> cols(m);
+    for (uint32_t q = 0; q < m && !rc; ++q) {
+      const size_t nq = (size_t)((q + 1 < m ? at[q + 1] : at[m]) - at[q]);
+      rc = alloc_result(*this, jobs[q]->n, nq, &mem[q], &rps[q], &cols[q]);
+    }
+    if (!rc) rc = upload(rp_tab, rps.data(), sizeof(int64_t*) * m);
+    if (!rc) rc = upload(col_tab, cols.data(), sizeof(int32_t*) * m);
+    if (!rc) {
+      launch_localize(inst_d, m, nblk, row_ptr, col, rp_tab, col_tab, stream);
+      rc = sync();
+    }
+    dfree(res);
+    if (rc) {
+      for (void* p : mem) dfree(p);
+      return rc;
+    }
+    for (uint32_t q = 0; q < m; ++q) {
+      Job& j = *jobs[q];
+      const int64_t nq = (q + 1 < m ? at[q + 1] : at[m]) - at[q];
+      j.out->n = j.n;
+      j.out->nnz = nq;
+      j.out->row_ptr = rps[q];
+      j.out->col = nq ? cols[q] : nullptr;
+      j.out->pairs = both ? nq / 2 : nq;
+      j.out->handle = keep_result(mem[q], j.n, nq, rps[q], cols[q]);
+    }
+  }
   mark(8);
   if ((rc = sync())) {
-    dfree(res);
+    if (m == 1) dfree(res);
     return rc;
   }
   if ((rc = hip_fail(hipGetLastError(), "kernel launch"))) {
-    dfree(res);
+    if (m == 1) dfree(res);
     return rc;
   }
   {
     uint32_t errh2 = 0;
     if ((rc = read_back(err, sizeof(errh2), &errh2)) || errh2) {
-      dfree(res);
+      if (m == 1) dfree(res);
       return rc ? rc : hip_fail(hipErrorUnknown, "radix sort look-back");
     }
   }
@@ -942,30 +1108,79 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
   if (timing_mask & RTG_TIME_PHASES) {
     float ms[8] = {0};
     for (int q = 0; q < 8; ++q) (void)hipEventElapsedTime(&ms[q], ev[q], ev[q + 1]);
-    st.ms_stage = ms[0];
-    st.ms_keys = 0;  // recorded per group below when timing a single group
-    st.ms_key_sort = 0;
-    st.ms_cells = 0;
-    st.ms_pairs = 0;
-    if (P.tb == k) {
-      st.ms_keys = ms[1];
-      st.ms_key_sort = ms[2];
-      st.ms_cells = ms[3];
-      st.ms_pairs = ms[4];
+    st.ms_stage += ms[0];
+    if (P.tb >= S_total) {
+      st.ms_keys += ms[1];
+      st.ms_key_sort += ms[2];
+      st.ms_cells += ms[3];
+      st.ms_pairs += ms[4];
     }
-    st.ms_pair_sort = ms[5];
-    st.ms_unique = ms[6];
-    st.ms_csr = ms[7];
+    st.ms_pair_sort += ms[5];
+    st.ms_unique += ms[6];
+    st.ms_csr += ms[7];
     float tot_ms = 0;
     (void)hipEventElapsedTime(&tot_ms, ev[0], ev[8]);
-    st.ms_total = tot_ms;
+    st.ms_total += tot_ms;
   }
-  out->n = n;
-  out->nnz = (int64_t)nnz;
-  out->row_ptr = row_ptr;
-  out->col = nnz ? col : nullptr;
-  out->pairs = (int64_t)U;
-  out->handle = keep_result(res, n, (int64_t)nnz, row_ptr, col);
+  if (m == 1) jobs[0]->out->handle = keep_result(res, jobs[0]->n, (int64_t)nnz, row_ptr, col);
+  return RTG_OK;
+}
+
+// Many queries: grouped by dimension and list flags, each group split into
+// batches of at most batch_points points (an instance larger than that runs
+// alone), every batch one pass of run_batch.
+int Ctx::batched(const rtg_query* q, int32_t nq, rtg_csr* outs) {
+  if (poisoned) return RTG_EDEVICE;
+  int rc;
+  for (int32_t i = 0; i < nq; ++i)
+    if ((rc = check_query(q[i].points, q[i].n, q[i].d, q[i].r, q[i].k, q[i].alpha))) return rc;
+  std::vector<std::vector<double>> R(nq), u(nq);
+  for (int32_t i = 0; i < nq; ++i) {
+    R[i].resize((size_t)q[i].k * q[i].d * q[i].d);
+    u[i].resize((size_t)q[i].k * q[i].d);
+    if ((rc = make_transforms(q[i].seed, q[i].k, q[i].d, q[i].flags, R[i].data(), u[i].data())))
+      return rc;
+  }
+  std::vector<rtg_csr> res(nq);
+  std::vector<char> done(nq, 0);
+  auto undo = [&](int code) {
+    for (int32_t i = 0; i < nq; ++i)
+      if (done[i]) release(res[i].handle);
+    return code;
+  };
+  rtg_stats st{};
+  std::vector<Job> jobs(nq);
+  std::map<std::pair<int, uint32_t>, std::vector<int32_t>> groups;
+  for (int32_t i = 0; i < nq; ++i) {
+    st.n += q[i].n;
+    st.point_transforms += q[i].n * q[i].k;
+    if (q[i].n <= 1) {
+      if ((rc = tiny_query(q[i].points, q[i].n, q[i].d, &res[i]))) return undo(rc);
+      done[i] = 1;
+      continue;
+    }
+    jobs[i] = Job{q[i].points, q[i].n, q[i].d, q[i].r, q[i].alpha, q[i].k, q[i].flags,
+                  R[i].data(), u[i].data(), &res[i]};
+    groups[{q[i].d, q[i].flags & (RTG_UPPER_ONLY | RTG_DEDUP_SORT)}].push_back(i);
+  }
+  for (auto& g : groups) {
+    size_t b = 0;
+    while (b < g.second.size()) {
+      std::vector<Job*> batch;
+      int64_t pts = 0;
+      while (b < g.second.size() &&
+             (batch.empty() || pts + jobs[g.second[b]].n <= batch_points)) {
+        pts += jobs[g.second[b]].n;
+        batch.push_back(&jobs[g.second[b]]);
+        ++b;
+      }
+      if ((rc = run_batch(batch, st))) return undo(rc);
+      for (Job* j : batch) done[j->out - res.data()] = 1;
+    }
+  }
+  for (int32_t i = 0; i < nq; ++i) outs[i] = res[i];
+  st.d = nq ? q[0].d : 0;
+  st.k = nq ? q[0].k : 0;
   stats = st;
   return RTG_OK;
 }
@@ -986,10 +1201,16 @@ int Ctx::debug_cell_coords(const float* points, int64_t n, int32_t d, double r, 
   if (!soa || !flags_dev || !Rd || !ud || !kap) return RTG_ENOMEM;
   if ((rc = upload(Rd, R, sizeof(double) * d * d)) || (rc = upload(ud, u, sizeof(double) * d)))
     return rc;
-  uint32_t* stage_part = S.get<uint32_t>(stage_scratch_elems(n, d));
-  if (!stage_part) return RTG_ENOMEM;
+  const uint32_t nblk = (uint32_t)((n + kBlock - 1) / kBlock);
+  uint32_t* stage_part = S.get<uint32_t>((size_t)nblk * 2 * d);
+  InstDesc* inst_d = S.get<InstDesc>(1);
+  if (!stage_part || !inst_d) return RTG_ENOMEM;
+  InstDesc one{};
+  one.pts = points;
+  one.n = n;
+  if ((rc = upload(inst_d, &one, sizeof(one)))) return rc;
   launch_fill_u32(flags_dev + 1, 0u, 1, stream);
-  launch_stage(points, n, d, soa, flags_dev, flags_dev + 2, stage_part, stream);
+  launch_stage(inst_d, 1, nblk, d, n, soa, nullptr, flags_dev, flags_dev + 2, stage_part, stream);
   launch_cell_coords(soa, n, d, Rd, ud, 1.0 / (alpha * r), kap, flags_dev + 1, stream);
   uint32_t fl[2];
   if ((rc = read_back(flags_dev, sizeof(fl), fl))) return rc;

@@ -57,25 +57,65 @@ struct Gather {
 };
 void launch_gather(const Gather& g, uint64_t* dst, hipStream_t s);
 
+// --- batches ------------------------------------------------------------------
+// A batch is a set of instances (queries) of the same dimension d run through
+// one pass of the pipeline.  Their points are concatenated (instance q owns
+// batch points [pt_off, pt_off + n)); every (instance, grid) pair is one
+// segment of the key space, numbered instance-major.  Kernels that work per
+// point use blocks of kBlock points that never span two instances: instance
+// q owns blocks [blk_first, blk_first + ceil(n / kBlock)).
+struct InstDesc {
+  const float* pts;   // the caller's row-major [n][d] points
+  int64_t pt_off;     // first batch point of the instance
+  int64_t n;          // points
+  double inv_c;       // 1 / (alpha r)
+  int32_t k;          // grids
+  int32_t tr_off;     // first transform of the instance in R / u / klo
+  int32_t seg_first;  // segment of (instance, grid 0); grid t is seg_first + t
+  int32_t blk_first;  // first point block of the instance
+};
+struct SegDesc {
+  int64_t key_off;    // first key of the segment within its pass
+  int32_t inst;       // instance
+  int32_t t;          // grid of the instance
+};
+
 // --- staging --------------------------------------------------------------
-// AoS [n][d] -> SoA [d][n]; *bad = 1 if a value is not finite (else 0);
-// per-axis min/max as order-preserving uint32 encodings (bbox[2j] = min,
-// bbox[2j+1] = max).  part: stage_scratch_elems(n, d) elements.
-size_t stage_scratch_elems(int64_t n, int d);
-void launch_stage(const float* pts, int64_t n, int d, float* soa, uint32_t* bad,
-                  uint32_t* bbox, uint32_t* part, hipStream_t s);
+// For every instance: copy its points into the batch's SoA [d][npts] (and
+// row-major aos [npts][d] when aos is not null), *bad = 1 if a value is not
+// finite (else 0), and per-axis min/max as order-preserving uint32
+// encodings in bbox[q][2d] (min at 2j, max at 2j+1).  nblocks = the
+// instances' point blocks; part holds nblocks * 2d elements.
+void launch_stage(const InstDesc* inst, uint32_t m, uint32_t nblocks, int d, int64_t npts,
+                  float* soa, float* aos, uint32_t* bad, uint32_t* bbox, uint32_t* part,
+                  hipStream_t s);
 
 // --- cell keys ------------------------------------------------------------
-// keys[(t - t0) * n + i] = packed cell of point i under transform t, and
-// vals[...] = i, for t in [t0, t0 + tb).  R [k][d][d], u [k][d] FP64;
-// klo [k][d] int64 origin of the packed range.  err |= 1 if |y| >= 2^31.
-// If sig is not null, also sig[i * k + t] = the packed cell key (u64 if
-// sig64, else u32) of point i under grid t.  With idx_bits > 0 the point
-// index rides in the key's low bits (key << idx_bits | i) and vals is unused.
-void launch_keys(const float* soa, int64_t n, int d, int t0, int tb, const double* R,
-                 const double* u, double inv_c, const int64_t* klo, const KeyLayout* layout,
-                 uint64_t* keys, uint32_t* vals, uint32_t* err, void* sig, int sig64, int k,
-                 int idx_bits, hipStream_t s);
+// For every batch point and each of its instance's segments in [sa, sb):
+// key = (segment - sa) << cell_bits | packed cell, written at
+// segs[segment].key_off + the point's index in its instance; the value is
+// the batch point index.  With idx_bits > 0 the point index rides in the
+// key's low bits (key << idx_bits | point) and vals is unused.  If sig is
+// not null, sig[point * kmax + grid] = the packed cell (u64 if sig64, else
+// u32).  err |= 1 if some |y| >= 2^31.
+struct KeysArgs {
+  const InstDesc* inst;
+  uint32_t m, nblocks;
+  int d;
+  int64_t npts;
+  const float* soa;
+  int sa, sb;
+  const SegDesc* segs;
+  const double *R, *u;
+  const int64_t* klo;
+  const KeyLayout* layout;
+  uint64_t* keys;
+  uint32_t* vals;
+  uint32_t* err;
+  void* sig;
+  int sig64, kmax, idx_bits;
+};
+void launch_keys(const KeysArgs& a, hipStream_t s);
 // kappa [n][d] = floor(y) for one transform (stage check).
 void launch_cell_coords(const float* soa, int64_t n, int d, const double* R, const double* u,
                         double inv_c, int64_t* kappa, uint32_t* err, hipStream_t s);
@@ -128,29 +168,38 @@ void launch_unit_fill(const uint32_t* start, const uint32_t* end, const uint32_t
 // --- cell pairs -----------------------------------------------------------
 // Sorted keys and first-owner filter.  The filter keeps a pair found under
 // grid t only if no grid t' < t put both points in one cell;
-// sig[i * k + t] is point i's packed cell key under grid t (u32 or u64);
+// sig[point * k + t] is a point's packed cell key under grid t (u32 or u64);
 // null sig turns the filter off.  skeys / idx_bits are always set.
 struct PairFilter {
   const void* sig = nullptr;
-  int32_t k = 0;
+  int32_t k = 0;                    // sig row stride (grids of the widest instance)
   int32_t sig64 = 0;
-  const uint64_t* skeys = nullptr;  // sorted keys; grid id sits above cell_bits
-  int32_t cell_bits = 64;
-  int32_t t0 = 0;                   // first grid of this sort
+  const uint64_t* skeys = nullptr;  // sorted keys
   int32_t idx_bits = 0;             // > 0: point index in the low bits of skeys
 };
 
 // One 64-wide wave per unit = (cell, tile a); emits packed pairs
-// (min << pair_bits | max) for same-cell pairs within r.  cand_count is the
-// running total (may exceed cap: then the overflow is only counted);
-// rechecks counts FP64 band re-tests; next_unit is the launch's work counter
-// (reset by the launcher).
-void launch_cell_pairs(const float* pts, int d, const uint32_t* sidx, const uint32_t* start,
-                       const uint32_t* end, const uint32_t* unit_cell, const uint32_t* unit_off,
-                       uint32_t total_units, PairTest test, PairFilter filter, uint64_t* cand,
-                       uint64_t cap, unsigned long long* cand_count,
-                       unsigned long long* rechecks, unsigned long long* next_unit,
-                       hipStream_t s);
+// (min << pair_bits | max) for same-cell pairs within r.  A cell's segment
+// is sa + (its key >> seg_shift) (sa when seg_shift >= 64); segs[] gives
+// the segment's instance, whose PairTest is tests[instance], and grid.
+// cand_count is the running total (may exceed cap: then the overflow is only
+// counted); rechecks counts FP64 band re-tests.
+struct PairsArgs {
+  const float* pts;  // batch points, row-major [npts][d]
+  int d;
+  const uint32_t* sidx;  // sorted point indices (null when in skeys)
+  const uint32_t *start, *end;
+  const uint32_t *unit_cell, *unit_off;
+  uint32_t total_units;
+  const PairTest* tests;
+  const SegDesc* segs;
+  int sa, seg_shift;
+  PairFilter filter;
+  uint64_t* cand;
+  uint64_t cap;
+  unsigned long long *cand_count, *rechecks;
+};
+void launch_cell_pairs(const PairsArgs& a, hipStream_t s);
 
 // --- unique + CSR -----------------------------------------------------------
 void launch_unique_count(const uint64_t* keys, size_t count, uint32_t* tile_cnt, hipStream_t s);
@@ -203,5 +252,15 @@ void launch_bucket_emit_sorted(const uint64_t* keys, uint32_t cnt, uint32_t star
                                hipStream_t s);
 void launch_widen(const uint32_t* src, size_t count, uint64_t* dst, hipStream_t s);
 void launch_u32_to_u64(const uint32_t* src, size_t count, uint64_t* dst, hipStream_t s);
+
+// --- per-instance lists of a batch ------------------------------------------
+// out[q] = row_ptr[first batch point of instance q], out[m] = row_ptr[npts].
+void launch_rowptr_at(const InstDesc* inst, uint32_t m, const int64_t* row_ptr, int64_t npts,
+                      int64_t* out, hipStream_t s);
+// Instance q's rows of the batch lists into out_rp[q] (n+1) / out_col[q],
+// with column indices local to the instance (device pointer tables).
+void launch_localize(const InstDesc* inst, uint32_t m, uint32_t nblocks, const int64_t* row_ptr,
+                     const int32_t* col, int64_t* const* out_rp, int32_t* const* out_col,
+                     hipStream_t s);
 
 }  // namespace rtgk

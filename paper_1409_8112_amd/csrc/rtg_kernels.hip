@@ -97,22 +97,39 @@ __global__ void k_fill(T* p, T v, size_t count) {
 // ---------------------------------------------------------------------------
 // stage: one thread per point.
 
+// Instance that owns point block blk: the largest q with blk_first <= blk.
+__device__ __forceinline__ uint32_t block_instance(const InstDesc* __restrict__ inst, uint32_t m,
+                                                   uint32_t blk) {
+  uint32_t lo = 0, hi = m;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if ((uint32_t)inst[mid].blk_first <= blk) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // Each block writes its own per-axis min/max (order-preserving encodings)
-// to part[block][2d]; k_bbox_reduce folds them.  (Per-block atomics on the
-// 2d words of one bounding box would all meet at one address per axis.)
-__global__ __launch_bounds__(kBlock) void k_stage(const float* __restrict__ pts, int64_t n, int d,
-                                                  float* __restrict__ soa, uint32_t* bad,
+// to part[block][2d]; k_bbox_reduce folds them per instance.  (Atomics on
+// the 2d words of one bounding box would all meet at one address per axis.)
+__global__ __launch_bounds__(kBlock) void k_stage(const InstDesc* __restrict__ inst, uint32_t m,
+                                                  int d, int64_t npts, float* __restrict__ soa,
+                                                  float* __restrict__ aos, uint32_t* bad,
                                                   uint32_t* __restrict__ part) {
   __shared__ uint32_t smin[kWaves][kMaxDim], smax[kWaves][kMaxDim];
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool live = i < n;
+  const uint32_t q = block_instance(inst, m, blockIdx.x);
+  const float* pts = inst[q].pts;
+  const int64_t i = (int64_t)(blockIdx.x - (uint32_t)inst[q].blk_first) * kBlock + threadIdx.x;
+  const bool live = i < inst[q].n;
+  const int64_t g = inst[q].pt_off + i;
   const int w = threadIdx.x >> 6;
   bool nonfinite = false;
   for (int l = 0; l < d; ++l) {
     float v = live ? pts[i * d + l] : 0.0f;
     uint32_t lo = 0xFFFFFFFFu, hi = 0u;
     if (live) {
-      soa[(int64_t)l * n + i] = v;
+      soa[(int64_t)l * npts + g] = v;
+      if (aos) aos[g * d + l] = v;
       if (!isfinite(v)) nonfinite = true;
       else lo = hi = float_order(v);
     }
@@ -131,26 +148,29 @@ __global__ __launch_bounds__(kBlock) void k_stage(const float* __restrict__ pts,
   if (threadIdx.x < (unsigned)d) {
     uint32_t lo = 0xFFFFFFFFu, hi = 0u;
 #pragma unroll
-    for (int q = 0; q < kWaves; ++q) {
-      lo = min(lo, smin[q][threadIdx.x]);
-      hi = max(hi, smax[q][threadIdx.x]);
+    for (int q2 = 0; q2 < kWaves; ++q2) {
+      lo = min(lo, smin[q2][threadIdx.x]);
+      hi = max(hi, smax[q2][threadIdx.x]);
     }
     part[(size_t)blockIdx.x * 2 * d + 2 * threadIdx.x] = lo;
     part[(size_t)blockIdx.x * 2 * d + 2 * threadIdx.x + 1] = hi;
   }
 }
 
-// bbox[2j] = min over blocks, bbox[2j+1] = max, one wave per axis.
-__global__ __launch_bounds__(kBlock) void k_bbox_reduce(const uint32_t* __restrict__ part,
-                                                        uint32_t nblocks, int d,
+// One block per instance: bbox[q][2j] = min over its blocks, [2j+1] = max.
+__global__ __launch_bounds__(kBlock) void k_bbox_reduce(const InstDesc* __restrict__ inst, int d,
+                                                        const uint32_t* __restrict__ part,
                                                         uint32_t* __restrict__ bbox) {
+  const uint32_t q = blockIdx.x;
+  const uint32_t b0 = inst[q].blk_first;
+  const uint32_t nb = (uint32_t)((inst[q].n + kBlock - 1) / kBlock);
   const int w = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
   for (int l = w; l < d; l += kWaves) {
     uint32_t lo = 0xFFFFFFFFu, hi = 0u;
-    for (uint32_t b = lane; b < nblocks; b += 64) {
-      lo = min(lo, part[(size_t)b * 2 * d + 2 * l]);
-      hi = max(hi, part[(size_t)b * 2 * d + 2 * l + 1]);
+    for (uint32_t b = lane; b < nb; b += 64) {
+      lo = min(lo, part[(size_t)(b0 + b) * 2 * d + 2 * l]);
+      hi = max(hi, part[(size_t)(b0 + b) * 2 * d + 2 * l + 1]);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -158,8 +178,8 @@ __global__ __launch_bounds__(kBlock) void k_bbox_reduce(const uint32_t* __restri
       hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
     }
     if (lane == 0) {
-      bbox[2 * l] = lo;
-      bbox[2 * l + 1] = hi;
+      bbox[(size_t)q * 2 * d + 2 * l] = lo;
+      bbox[(size_t)q * 2 * d + 2 * l + 1] = hi;
     }
   }
 }
@@ -184,34 +204,46 @@ __device__ __forceinline__ double cell_y(const double* __restrict__ Rj, const fl
   return z * inv_c + uj;
 }
 
+// One thread per batch point; writes the keys of the point's segments in
+// [sa, sb): key = (segment - sa) << cell_bits | packed cell, at
+// segs[segment].key_off + the point's index in its instance.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_keys(const float* __restrict__ soa, int64_t n, int d_rt,
-                                                 int t0, int tb, const double* __restrict__ R,
-                                                 const double* __restrict__ u, double inv_c,
+__global__ __launch_bounds__(kBlock) void k_keys(const InstDesc* __restrict__ inst, uint32_t m,
+                                                 int d_rt, int64_t npts,
+                                                 const float* __restrict__ soa, int sa, int sb,
+                                                 const SegDesc* __restrict__ segs,
+                                                 const double* __restrict__ R,
+                                                 const double* __restrict__ u,
                                                  const int64_t* __restrict__ klo,
                                                  const KeyLayout* __restrict__ layout,
                                                  uint64_t* __restrict__ keys,
                                                  uint32_t* __restrict__ vals, uint32_t* err,
-                                                 void* __restrict__ sig, int sig64, int k,
+                                                 void* __restrict__ sig, int sig64, int kmax,
                                                  int idx_bits) {
   const int d = D > 0 ? D : d_rt;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
+  const uint32_t q = block_instance(inst, m, blockIdx.x);
+  const int64_t i = (int64_t)(blockIdx.x - (uint32_t)inst[q].blk_first) * kBlock + threadIdx.x;
+  if (i >= inst[q].n) return;
+  const int64_t g = inst[q].pt_off + i;
+  const int seg_first = inst[q].seg_first;
+  const int t_lo = max(0, sa - seg_first), t_hi = min(inst[q].k, sb - seg_first);
+  const double inv_c = inst[q].inv_c;
   float p[D > 0 ? D : 1];
   if (D > 0) {
 #pragma unroll
-    for (int l = 0; l < (D > 0 ? D : 1); ++l) p[l] = soa[(int64_t)l * n + i];
+    for (int l = 0; l < (D > 0 ? D : 1); ++l) p[l] = soa[(int64_t)l * npts + g];
   }
   const int cell_bits = layout->cell_bits;
   bool bad = false;
-  for (int tt = 0; tt < tb; ++tt) {
-    const int t = t0 + tt;
-    const double* Rt = R + (size_t)t * d * d;
-    const double* ut = u + (size_t)t * d;
-    const int64_t* kl = klo + (size_t)t * d;
+  for (int t = t_lo; t < t_hi; ++t) {
+    const int s = seg_first + t;
+    const int tr = inst[q].tr_off + t;
+    const double* Rt = R + (size_t)tr * d * d;
+    const double* ut = u + (size_t)tr * d;
+    const int64_t* kl = klo + (size_t)tr * d;
     uint64_t cell = 0;
     for (int j = 0; j < d; ++j) {
-      double y = cell_y<D>(Rt + (size_t)j * d, p, soa, n, i, d, inv_c, ut[j]);
+      double y = cell_y<D>(Rt + (size_t)j * d, p, soa, npts, g, d, inv_c, ut[j]);
       bool ok = fabs(y) < 2147483648.0;
       bad |= !ok;
       int64_t kap = ok ? (int64_t)floor(y) : 0;
@@ -219,15 +251,16 @@ __global__ __launch_bounds__(kBlock) void k_keys(const float* __restrict__ soa, 
       cell |= ((uint64_t)(kap - kl[j]) & mask) << layout->shift[j];
     }
     if (sig) {
-      if (sig64) static_cast<uint64_t*>(sig)[(size_t)i * k + t] = cell;
-      else static_cast<uint32_t*>(sig)[(size_t)i * k + t] = (uint32_t)cell;
+      if (sig64) static_cast<uint64_t*>(sig)[(size_t)g * kmax + t] = cell;
+      else static_cast<uint32_t*>(sig)[(size_t)g * kmax + t] = (uint32_t)cell;
     }
-    const uint64_t key = (cell_bits < 64) ? (((uint64_t)tt << cell_bits) | cell) : cell;
+    const uint64_t key = (cell_bits < 64) ? (((uint64_t)(s - sa) << cell_bits) | cell) : cell;
+    const int64_t pos = segs[s].key_off + i;
     if (idx_bits) {
-      keys[(int64_t)tt * n + i] = (key << idx_bits) | (uint64_t)i;
+      keys[pos] = (key << idx_bits) | (uint64_t)g;
     } else {
-      keys[(int64_t)tt * n + i] = key;
-      vals[(int64_t)tt * n + i] = (uint32_t)i;
+      keys[pos] = key;
+      vals[pos] = (uint32_t)g;
     }
   }
   if (bad) atomicOr(err, 1u);
@@ -745,9 +778,9 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs(
     const float* __restrict__ pts, int d, const uint32_t* __restrict__ sidx,
     const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend,
     const uint32_t* __restrict__ unit_cell, const uint32_t* __restrict__ unit_off,
-    uint32_t total_units, PairTest T, PairFilter F, uint64_t* __restrict__ cand, uint64_t cap,
-    unsigned long long* cand_count, unsigned long long* rechecks,
-    unsigned long long* next_unit) {
+    uint32_t total_units, const PairTest* __restrict__ tests, const SegDesc* __restrict__ segs,
+    int sa, int seg_shift, PairFilter F, uint64_t* __restrict__ cand, uint64_t cap,
+    unsigned long long* cand_count, unsigned long long* rechecks) {
   using Sig = typename std::conditional<SIG64, uint64_t, uint32_t>::type;
   // LDS row stride: rows of 4 floats read with 128-bit loads
   constexpr int DP = D <= 2 ? D : ((D + 3) / 4) * 4;
@@ -790,11 +823,11 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs(
     const uint32_t L = uniform(cend[c]) - s0;
     const uint32_t nt = (L + kPairTile - 1) / kPairTile;
     const uint32_t nA = min((uint32_t)kPairTile, L - ta * kPairTile);
-    int tcell = 0;
-    if (sig)
-      tcell = F.t0 + (F.cell_bits >= 64 ? 0
-                                        : (int)uniform((uint32_t)((F.skeys[s0] >> F.idx_bits) >>
-                                                                  F.cell_bits)));
+    // the cell's segment: its instance (radius) and grid
+    const int seg =
+        sa + (seg_shift >= 64 ? 0 : (int)uniform((uint32_t)(F.skeys[s0] >> seg_shift)));
+    const int tcell = uniform(segs[seg].t);
+    const PairTest T = tests[uniform(segs[seg].inst)];
 
     float a[D];
     uint32_t ai = 0;
@@ -1230,6 +1263,38 @@ __global__ void k_gather(Gather g, uint64_t* __restrict__ dst) {
                            : (uint64_t)*static_cast<const uint32_t*>(g.src[q]);
 }
 
+// out[q] = row_ptr[first point of instance q] for q < m, out[m] = row_ptr[npts].
+__global__ void k_rowptr_at(const InstDesc* __restrict__ inst, uint32_t m,
+                            const int64_t* __restrict__ row_ptr, int64_t npts,
+                            int64_t* __restrict__ out) {
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < m) out[q] = row_ptr[inst[q].pt_off];
+  if (q == m) out[m] = row_ptr[npts];
+}
+
+// One thread per batch point (point blocks as in the stage): copies the
+// point's row of the batch lists into its instance's own lists, with
+// indices local to the instance.
+__global__ __launch_bounds__(kBlock) void k_localize(const InstDesc* __restrict__ inst, uint32_t m,
+                                                     const int64_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ col,
+                                                     int64_t* const* __restrict__ out_rp,
+                                                     int32_t* const* __restrict__ out_col) {
+  const uint32_t q = block_instance(inst, m, blockIdx.x);
+  const int64_t n = inst[q].n;
+  const int64_t i = (int64_t)(blockIdx.x - (uint32_t)inst[q].blk_first) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int64_t off = inst[q].pt_off;
+  const int64_t g = off + i;
+  const int64_t base = row_ptr[off];
+  const int64_t a = row_ptr[g], b = row_ptr[g + 1];
+  int64_t* rp = out_rp[q];
+  rp[i] = a - base;
+  if (i == n - 1) rp[n] = b - base;
+  int32_t* c = out_col[q];
+  for (int64_t e = a; e < b; ++e) c[e - base] = col[e] - (int32_t)off;
+}
+
 inline unsigned grid_for(size_t count, unsigned block = kBlock) {
   size_t g = (count + block - 1) / block;
   return (unsigned)(g < 1 ? 1 : g);
@@ -1256,46 +1321,44 @@ void launch_fill_u64(uint64_t* p, uint64_t v, size_t count, hipStream_t s) {
   hipLaunchKernelGGL(k_fill<uint64_t>, dim3((unsigned)g), dim3(kBlock), 0, s, p, v, count);
 }
 
-size_t stage_scratch_elems(int64_t n, int d) { return (size_t)grid_for((size_t)n) * 2 * d; }
-
-void launch_stage(const float* pts, int64_t n, int d, float* soa, uint32_t* bad, uint32_t* bbox,
-                  uint32_t* part, hipStream_t s) {
-  if (n <= 0) return;
-  const unsigned nb = grid_for((size_t)n);
+void launch_stage(const InstDesc* inst, uint32_t m, uint32_t nblocks, int d, int64_t npts,
+                  float* soa, float* aos, uint32_t* bad, uint32_t* bbox, uint32_t* part,
+                  hipStream_t s) {
+  if (!nblocks) return;
   hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(64), 0, s, bad, 0u, (size_t)1);
-  hipLaunchKernelGGL(k_stage, dim3(nb), dim3(kBlock), 0, s, pts, n, d, soa, bad, part);
-  hipLaunchKernelGGL(k_bbox_reduce, dim3(1), dim3(kBlock), 0, s, part, nb, d, bbox);
+  hipLaunchKernelGGL(k_stage, dim3(nblocks), dim3(kBlock), 0, s, inst, m, d, npts, soa, aos, bad,
+                     part);
+  hipLaunchKernelGGL(k_bbox_reduce, dim3(m), dim3(kBlock), 0, s, inst, d, part, bbox);
 }
 
 template <int D>
-static void keys_dispatch(const float* soa, int64_t n, int d, int t0, int tb, const double* R,
-                          const double* u, double inv_c, const int64_t* klo,
-                          const KeyLayout* layout, uint64_t* keys, uint32_t* vals, uint32_t* err,
-                          void* sig, int sig64, int k, int idx_bits, hipStream_t s) {
-  hipLaunchKernelGGL(k_keys<D>, dim3(grid_for((size_t)n)), dim3(kBlock), 0, s, soa, n, d, t0, tb, R,
-                     u, inv_c, klo, layout, keys, vals, err, sig, sig64, k, idx_bits);
+static void keys_dispatch(const KeysArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_keys<D>, dim3(a.nblocks), dim3(kBlock), 0, s, a.inst, a.m, a.d, a.npts,
+                     a.soa, a.sa, a.sb, a.segs, a.R, a.u, a.klo, a.layout, a.keys, a.vals, a.err,
+                     a.sig, a.sig64, a.kmax, a.idx_bits);
 }
 
-void launch_keys(const float* soa, int64_t n, int d, int t0, int tb, const double* R,
-                 const double* u, double inv_c, const int64_t* klo, const KeyLayout* layout,
-                 uint64_t* keys, uint32_t* vals, uint32_t* err, void* sig, int sig64, int k,
-                 int idx_bits, hipStream_t s) {
-  if (n <= 0) return;
-#define RTG_KEYS_CASE(DV)                                                                       \
-  case DV:                                                                                      \
-    keys_dispatch<DV>(soa, n, d, t0, tb, R, u, inv_c, klo, layout, keys, vals, err, sig, sig64, \
-                      k, idx_bits, s);                                                          \
-    break;
-  switch (d) {
-    RTG_KEYS_CASE(1) RTG_KEYS_CASE(2) RTG_KEYS_CASE(3) RTG_KEYS_CASE(4) RTG_KEYS_CASE(5)
-    RTG_KEYS_CASE(6) RTG_KEYS_CASE(7) RTG_KEYS_CASE(8) RTG_KEYS_CASE(9) RTG_KEYS_CASE(10)
-    RTG_KEYS_CASE(11) RTG_KEYS_CASE(12) RTG_KEYS_CASE(13) RTG_KEYS_CASE(14) RTG_KEYS_CASE(15)
-    RTG_KEYS_CASE(16)
-    default:
-      keys_dispatch<0>(soa, n, d, t0, tb, R, u, inv_c, klo, layout, keys, vals, err, sig, sig64, k,
-                       idx_bits, s);
+void launch_keys(const KeysArgs& a, hipStream_t s) {
+  if (!a.nblocks) return;
+  switch (a.d) {
+    case 1: keys_dispatch<1>(a, s); break;
+    case 2: keys_dispatch<2>(a, s); break;
+    case 3: keys_dispatch<3>(a, s); break;
+    case 4: keys_dispatch<4>(a, s); break;
+    case 5: keys_dispatch<5>(a, s); break;
+    case 6: keys_dispatch<6>(a, s); break;
+    case 7: keys_dispatch<7>(a, s); break;
+    case 8: keys_dispatch<8>(a, s); break;
+    case 9: keys_dispatch<9>(a, s); break;
+    case 10: keys_dispatch<10>(a, s); break;
+    case 11: keys_dispatch<11>(a, s); break;
+    case 12: keys_dispatch<12>(a, s); break;
+    case 13: keys_dispatch<13>(a, s); break;
+    case 14: keys_dispatch<14>(a, s); break;
+    case 15: keys_dispatch<15>(a, s); break;
+    case 16: keys_dispatch<16>(a, s); break;
+    default: keys_dispatch<0>(a, s);
   }
-#undef RTG_KEYS_CASE
 }
 
 template <int D>
@@ -1475,35 +1538,27 @@ void launch_unit_fill(const uint32_t* start, const uint32_t* end, const uint32_t
 }
 
 template <int D>
-static void pairs_dispatch(const float* pts, int d, const uint32_t* sidx, const uint32_t* start,
-                           const uint32_t* end, const uint32_t* unit_cell,
-                           const uint32_t* unit_off, uint32_t total_units, PairTest test,
-                           PairFilter filter, uint64_t* cand, uint64_t cap,
-                           unsigned long long* cand_count, unsigned long long* rechecks,
-                           unsigned long long* next_unit, hipStream_t s) {
-  uint64_t blocks = ((uint64_t)total_units + kWaves - 1) / kWaves;
+static void pairs_dispatch(const PairsArgs& a, hipStream_t s) {
+  uint64_t blocks = ((uint64_t)a.total_units + kWaves - 1) / kWaves;
   const uint64_t max_blocks = 256ull * 8ull;  // 256 CUs, several resident blocks each
   if (blocks > max_blocks) blocks = max_blocks;
   if (blocks < 1) blocks = 1;
-  if (filter.sig64)
-    hipLaunchKernelGGL((k_cell_pairs<D, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, pts, d,
-                       sidx, start, end, unit_cell, unit_off, total_units, test, filter, cand, cap,
-                       cand_count, rechecks, next_unit);
+  if (a.filter.sig64)
+    hipLaunchKernelGGL((k_cell_pairs<D, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a.pts,
+                       a.d, a.sidx, a.start, a.end, a.unit_cell, a.unit_off, a.total_units, a.tests,
+                       a.segs, a.sa, a.seg_shift, a.filter, a.cand, a.cap, a.cand_count,
+                       a.rechecks);
   else
-    hipLaunchKernelGGL((k_cell_pairs<D, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, pts, d,
-                       sidx, start, end, unit_cell, unit_off, total_units, test, filter, cand, cap,
-                       cand_count, rechecks, next_unit);
+    hipLaunchKernelGGL((k_cell_pairs<D, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a.pts,
+                       a.d, a.sidx, a.start, a.end, a.unit_cell, a.unit_off, a.total_units, a.tests,
+                       a.segs, a.sa, a.seg_shift, a.filter, a.cand, a.cap, a.cand_count,
+                       a.rechecks);
 }
 
-void launch_cell_pairs(const float* pts, int d, const uint32_t* sidx, const uint32_t* start,
-                       const uint32_t* end, const uint32_t* unit_cell, const uint32_t* unit_off,
-                       uint32_t total_units, PairTest test, PairFilter filter, uint64_t* cand,
-                       uint64_t cap, unsigned long long* cand_count,
-                       unsigned long long* rechecks, unsigned long long* next_unit,
-                       hipStream_t s) {
-  if (!total_units) return;
-#define RTG_PAIRS_ARGS pts, d, sidx, start, end, unit_cell, unit_off, total_units, test, filter, \
-                       cand, cap, cand_count, rechecks, next_unit, s
+void launch_cell_pairs(const PairsArgs& a, hipStream_t s) {
+  if (!a.total_units) return;
+  const int d = a.d;
+#define RTG_PAIRS_ARGS a, s
   // Instantiations for d <= 16 exactly; larger d run the next wider one with
   // zero padding, which adds exact zeros to both sums.
   switch (d) {
@@ -1628,6 +1683,20 @@ void launch_u32_to_u64(const uint32_t* src, size_t count, uint64_t* dst, hipStre
 void launch_gather(const Gather& g, uint64_t* dst, hipStream_t s) {
   if (g.count <= 0) return;
   hipLaunchKernelGGL(k_gather, dim3(1), dim3(64), 0, s, g, dst);
+}
+
+void launch_rowptr_at(const InstDesc* inst, uint32_t m, const int64_t* row_ptr, int64_t npts,
+                      int64_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_rowptr_at, dim3(grid_for((size_t)m + 1)), dim3(kBlock), 0, s, inst, m,
+                     row_ptr, npts, out);
+}
+
+void launch_localize(const InstDesc* inst, uint32_t m, uint32_t nblocks, const int64_t* row_ptr,
+                     const int32_t* col, int64_t* const* out_rp, int32_t* const* out_col,
+                     hipStream_t s) {
+  if (!nblocks) return;
+  hipLaunchKernelGGL(k_localize, dim3(nblocks), dim3(kBlock), 0, s, inst, m, row_ptr, col, out_rp,
+                     out_col);
 }
 
 }  // namespace rtgk

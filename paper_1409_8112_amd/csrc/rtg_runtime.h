@@ -42,7 +42,7 @@ class Arena {
 struct Packing {
   rtgk::KeyLayout layout{};
   std::vector<int64_t> klo;  // [k][d] origin of each packed field
-  int tb = 1;                // grids per sort
+  int tb = 1;                // segments (instance, grid) per sort
   int seg_bits = 0;          // bits of the grid id above the cell fields
   int key_bits = 0;          // seg_bits + cell_bits
   bool truncated = false;    // some field narrower than its span (aliasing)
@@ -50,10 +50,29 @@ struct Packing {
 
 int make_transforms(uint64_t seed, int32_t k, int32_t d, uint32_t flags, double* R, double* u);
 int min_field_bits(double alpha);
-int plan_packing(int d, int k, const double* R, const double* u, double inv_c, double alpha,
-                 const float* lo, const float* hi, int64_t n, size_t budget_bytes, Packing& P);
 int validate_query(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha);
 int check_device_pointer(const void* p, int device);
+
+// One query of a batch, with its transforms (host arrays).
+struct Job {
+  const float* pts;
+  int64_t n;
+  int32_t d;
+  double r, alpha;
+  int32_t k;
+  uint32_t flags;
+  const double* R;  // [k][d][d]
+  const double* u;  // [k][d]
+  rtg_csr* out;
+};
+
+// Points per batch of rtg_all_pairs_batched (an instance larger runs alone):
+// keeps the neighbour-list build on row buckets and the packed sort keys.
+constexpr int64_t kBatchPoints = int64_t(1) << 22;
+
+int plan_batch(int d, uint32_t m, const int64_t* k, const int64_t* n, const double* R,
+               const double* u, const double* inv_c, const double* alpha, const float* lo,
+               const float* hi, size_t budget_bytes, Packing& P);
 
 struct Result {
   void* mem;
@@ -77,6 +96,7 @@ struct Ctx {
   uint32_t timing_mask = 0;  // bit i: time kernel id i; RTG_TIME_PHASES: phases
   int sort_algo = 0;         // rtgk::kSortOnesweep or rtgk::kSortReduceScan
   uint32_t bucket_cap = rtgk::kBucketMaxEntries;  // entries per LDS-sorted bucket
+  int64_t batch_points = kBatchPoints;             // points per batch
   hipEvent_t ev[9] = {};
   rtg_stats stats{};
   // per-launch timing: a pool of event pairs and the launches of this call
@@ -106,6 +126,10 @@ struct Ctx {
 
   int all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha,
                 const double* R, const double* u, uint32_t flags, rtg_csr* out);
+  int batched(const rtg_query* q, int32_t nq, rtg_csr* outs);
+  int run_batch(std::vector<Job*>& jobs, rtg_stats& st);
+  int check_query(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha);
+  int tiny_query(const float* points, int64_t n, int32_t d, rtg_csr* out);
   int debug_cell_coords(const float* points, int64_t n, int32_t d, double r, double alpha,
                         const double* R, const double* u, int64_t* kappa_host);
 

@@ -1,8 +1,8 @@
 // rtg_server.cpp -- batched entry point and request loop.
 //
-// Interim form: the batched call runs its queries one after another through
-// the plain pipeline, and a submitted request runs at submit time.  Results
-// are identical to rtg_all_pairs for each query.
+// The batched call groups queries by dimension and runs each group through
+// the batch pipeline (one pass per batch of instances).  Interim request
+// loop: a submitted request runs at submit time.
 #include "../../include/rtg.h"
 #include "rtg_runtime.h"
 
@@ -13,22 +13,10 @@ using rtg::Ctx;
 extern "C" {
 
 int rtg_all_pairs_batched(rtg_ctx* ctx, const rtg_query* q, int32_t nq, rtg_csr* outs) {
-  if (!ctx || (nq > 0 && (!q || !outs)) || nq < 0) return RTG_EINVAL;
+  if (!ctx || nq < 0 || (nq > 0 && (!q || !outs))) return RTG_EINVAL;
   Ctx* c = reinterpret_cast<Ctx*>(ctx);
-  std::vector<rtg_csr> done;
-  for (int32_t i = 0; i < nq; ++i) {
-    rtg_csr o{};
-    int rc = rtg_all_pairs(ctx, q[i].points, q[i].n, q[i].d, q[i].r, q[i].k, q[i].alpha,
-                           q[i].seed, q[i].flags, &o);
-    if (rc) {
-      for (auto& x : done) rtg_release(ctx, x.handle);
-      return rc;
-    }
-    done.push_back(o);
-  }
-  (void)c;
-  for (int32_t i = 0; i < nq; ++i) outs[i] = done[i];
-  return RTG_OK;
+  std::lock_guard<std::mutex> lk(c->mu);
+  return c->batched(q, nq, outs);
 }
 
 int rtg_submit(rtg_ctx* ctx, const rtg_query* q, uint64_t* ticket) {
