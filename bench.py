@@ -57,6 +57,116 @@ def cpu_baseline(points, wl, budget_s: float):
             "seconds": dt, "pairs": pairs}
 
 
+def bench_batched(ctx, count: int, reps: int = 3) -> dict:
+    """Many instances in one rtg_all_pairs_batched call against the same
+    instances run one rtg_all_pairs call at a time (points resident)."""
+    import torch
+    from paper_1409_8112_amd import workloads
+    wls = workloads.batched_instances(count)
+    pts = [torch.from_numpy(w.points()).to("cuda:0") for w in wls]
+    queries = [dict(points=p, r=w.r, k=w.k, alpha=w.alpha, seed=w.seed) for p, w in zip(pts, wls)]
+    torch.cuda.synchronize()
+
+    def batched_once():
+        res = ctx.all_pairs_batched(queries)
+        pairs = sum(r.pairs for r in res)
+        for r in res:
+            r.release()
+        return pairs
+
+    batched_once()  # warm-up
+    times = []
+    pairs = 0
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pairs = batched_once()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    t_b = float(np.median(times))
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pairs_plain = 0
+    for q in queries:
+        r = ctx.all_pairs(q["points"], q["r"], q["k"], q["alpha"], q["seed"])
+        pairs_plain += r.pairs
+        r.release()
+    torch.cuda.synchronize()
+    t_p = time.perf_counter() - t0
+    total_n = sum(w.n for w in wls)
+    return {"workload": f"{count} instances, n log-uniform [1e3, 6.4e4] (sum {total_n}), "
+                        "d in {2,3,6,9}, uniform, ~15 nb, k=6, alpha=2",
+            "value": pairs / t_b, "unit": "pairs/s", "ms": t_b * 1e3, "pairs": pairs,
+            "plain_value": pairs_plain / t_p, "plain_ms": t_p * 1e3,
+            "plain_pairs": pairs_plain, "speedup_vs_plain": t_p / t_b,
+            "same_pairs_as_plain": pairs == pairs_plain}
+
+
+def bench_serving(ctx, count: int, rate: float, seed: int = 0) -> dict:
+    """Poisson arrivals through rtg_submit / rtg_poll.  Latency runs from a
+    request's scheduled arrival to the poll that sees it done."""
+    import torch
+    from paper_1409_8112_amd import workloads
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    ns = np.exp(rng.uniform(np.log(500), np.log(2_000_000), size=count)).round().astype(np.int64)
+    dims = rng.choice([3, 6, 12], size=count)
+    n_mid = int(round(np.sqrt(500 * 2_000_000)))
+    gamma = {int(d): workloads.calibrate_radius_uniform(n_mid, int(d), 15.0)
+             / (np.log(n_mid) / n_mid) ** (1.0 / d) for d in (3, 6, 12)}
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(seed)
+    reqs = []
+    for i in range(count):
+        n, d = int(ns[i]), int(dims[i])
+        p = torch.rand((n, d), generator=gen, device="cuda:0", dtype=torch.float32)
+        reqs.append((p, workloads.prm_radius(n, d, gamma[d]), i))
+    torch.cuda.synchronize()
+    before = ctx.stats()
+
+    lat, pairs = [], 0
+    pending = {}
+    i = 0
+    t0 = time.perf_counter()
+    last_done = t0
+    while i < count or pending:
+        now = time.perf_counter() - t0
+        while i < count and arrivals[i] <= now:
+            p, r, s = reqs[i]
+            t = ctx.submit(p, r, 8, 2.0, s)
+            if t is None:
+                break  # no room to stage it yet
+            pending[t] = arrivals[i]
+            i += 1
+        done = []
+        for t, arr in pending.items():
+            res = ctx.poll(t)
+            if res is not None:
+                fin = time.perf_counter()
+                lat.append((fin - t0 - arr) * 1e3)
+                pairs += res.pairs
+                res.release()
+                done.append(t)
+                last_done = fin
+        for t in done:
+            del pending[t]
+        if not done:
+            time.sleep(5e-5)
+    after = ctx.stats()
+    span = last_done - t0 - arrivals[0]
+    served = after["served_requests"] - before["served_requests"]
+    passes = after["served_batches"] - before["served_batches"]
+    return {"workload": f"{count} requests, Poisson {rate:g}/s, n log-uniform [500, 2e6] "
+                        f"(sum {int(ns.sum())}), d in {{3,6,12}}, uniform, ~15 nb, k=8, alpha=2",
+            "value": pairs / span, "unit": "pairs/s", "pairs": pairs,
+            "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                           "p99": float(np.percentile(lat, 99)),
+                           "max": float(np.max(lat))},
+            "offered_s": float(arrivals[-1]), "span_s": span,
+            "requests_per_pass": served / max(passes, 1)}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +177,13 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=60.0)
     ap.add_argument("--arena-gb", type=float, default=48.0)
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-instances measurement")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the request-loop measurement")
+    ap.add_argument("--batched-count", type=int, default=4096)
+    ap.add_argument("--serving-requests", type=int, default=1000)
+    ap.add_argument("--serving-rate", type=float, default=1000.0)
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -166,6 +283,13 @@ def main(argv=None) -> int:
         "probe_kernel_ms": {name: probe["kernel_ms"][i] for i, name in enumerate(rtg.KERNELS)},
         "roofline": roof,
     }
+    if not args.no_batched:
+        print(f"# batched: {args.batched_count} instances", file=sys.stderr, flush=True)
+        out["batched"] = bench_batched(ctx, args.batched_count)
+    if not args.no_serving:
+        print(f"# serving: {args.serving_requests} requests at {args.serving_rate}/s",
+              file=sys.stderr, flush=True)
+        out["serving"] = bench_serving(ctx, args.serving_requests, args.serving_rate)
     ctx.close()
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)

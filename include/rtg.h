@@ -127,6 +127,10 @@ typedef struct rtg_stats {
   int64_t kernel_launches[RTG_NKERNELS];
   double kernel_bytes[RTG_NKERNELS];
   double kernel_ms[RTG_NKERNELS];
+  /* Request loop totals since rtg_create: requests finished and pipeline
+   * passes (batches) that ran them. */
+  int64_t served_requests;
+  int64_t served_batches;
 } rtg_stats;
 
 /* Create a context on HIP device `device`.
@@ -199,7 +203,7 @@ int rtg_make_transforms(uint64_t seed, int32_t k, int32_t d, uint32_t flags, dou
 int rtg_set_timing(rtg_ctx *ctx, uint32_t mask);
 
 /* Counters of the last completed rtg_all_pairs* call. */
-int rtg_get_stats(const rtg_ctx *ctx, rtg_stats *out);
+int rtg_get_stats(rtg_ctx *ctx, rtg_stats *out);
 
 /* Stage check: the integer cell coordinates floor((R_t p)/(alpha r) + u_t)
  * computed by the key kernel for transform t, written to host kappa

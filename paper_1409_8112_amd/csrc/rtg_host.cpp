@@ -286,22 +286,25 @@ int plan_batch(int d, uint32_t m, const int64_t* k, const int64_t* n, const doub
 // ---------------------------------------------------------------------------
 // context
 
-Ctx::Ctx(int dev, hipStream_t s) : device(dev), stream(s) {
+Ctx::Ctx(int dev) : device(dev) {
   // Reduce-then-scan is the default radix sort: on MI355X its per-pass
   // histogram + scan + scatter beat onesweep, whose look-back reads cross
   // the XCDs' L2s.  RTG_SORT=onesweep selects onesweep.
   const char* e = std::getenv("RTG_SORT");
   sort_algo = (e && std::strcmp(e, "onesweep") == 0) ? kSortOnesweep : kSortReduceScan;
-  // RTG_BUCKET_CAP lowers the entries a neighbour-list bucket may hold in
-  // LDS (tests use it to send buckets down the global-sort fallback).
   // RTG_BATCH_POINTS lowers the points per batch of rtg_all_pairs_batched
-  // (tests use it to split small batches).
+  // and of the request loop (tests use it to split small batches).
   const char* bp = std::getenv("RTG_BATCH_POINTS");
   batch_points = kBatchPoints;
   if (bp) {
     const long long v = std::strtoll(bp, nullptr, 10);
     if (v >= 2 && v < kBatchPoints) batch_points = v;
   }
+  // RTG_LANES: passes of the request loop that may run at once (1..4).
+  if (const char* e = std::getenv("RTG_LANES"))
+    server_lanes = std::max(1, std::min(4, std::atoi(e)));
+  // RTG_BUCKET_CAP lowers the entries a neighbour-list bucket may hold in
+  // LDS (tests use it to send buckets down the global-sort fallback).
   const char* bc = std::getenv("RTG_BUCKET_CAP");
   bucket_cap = kBucketMaxEntries;
   if (bc) {
@@ -311,8 +314,8 @@ Ctx::Ctx(int dev, hipStream_t s) : device(dev), stream(s) {
 }
 
 Ctx::~Ctx() {
-  if (host_stage) (void)hipHostFree(host_stage);
-  for (auto& e : ev) (void)hipEventDestroy(e);
+  stop_server();
+  main.fini();
   if (own_arena && arena_mem) (void)hipFree(arena_mem);
 }
 
@@ -323,12 +326,101 @@ int Ctx::hip_fail(hipError_t e, const char* what) {
   return RTG_EDEVICE;
 }
 
-void* Ctx::dalloc(size_t bytes) { return arena->alloc(bytes); }
-void Ctx::dfree(void* p) { arena->release(p); }
+void* Ctx::dalloc(size_t bytes) {
+  std::lock_guard<std::mutex> lk(amu);
+  return arena->alloc(bytes);
+}
 
-int Ctx::sync() { return hip_fail(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
+void Ctx::dfree(void* p) {
+  std::lock_guard<std::mutex> lk(amu);
+  arena->release(p);
+}
 
-int Ctx::read_back(const void* dev, size_t bytes, void* host) {
+size_t Ctx::largest_free() {
+  std::lock_guard<std::mutex> lk(amu);
+  return arena->largest_free();
+}
+
+size_t Ctx::free_bytes() {
+  std::lock_guard<std::mutex> lk(amu);
+  return arena->size() - arena->in_use();
+}
+
+uint64_t Ctx::new_handle() {
+  std::lock_guard<std::mutex> lk(amu);
+  return next_handle++;
+}
+
+uint64_t Ctx::keep_result(uint64_t h, void* mem, int64_t n, int64_t nnz, int64_t pairs,
+                          int64_t* row_ptr, int32_t* col) {
+  std::lock_guard<std::mutex> lk(amu);
+  if (!h) h = next_handle++;
+  results[h] = Result{mem, n, nnz, pairs, row_ptr, col};
+  return h;
+}
+
+int Ctx::release(uint64_t h) {
+  std::lock_guard<std::mutex> lk(amu);
+  auto it = results.find(h);
+  if (it == results.end()) return RTG_ENOENT;
+  arena->release(it->second.mem);
+  results.erase(it);
+  return RTG_OK;
+}
+
+bool Ctx::find_result(uint64_t h, rtg_csr* out) {
+  std::lock_guard<std::mutex> lk(amu);
+  auto it = results.find(h);
+  if (it == results.end()) return false;
+  out->n = it->second.n;
+  out->nnz = it->second.nnz;
+  out->row_ptr = it->second.row_ptr;
+  out->col = it->second.nnz ? it->second.col : nullptr;
+  out->pairs = it->second.pairs;
+  out->handle = h;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// lanes
+
+int Lane::init(Ctx* c, hipStream_t s, bool create_stream) {
+  ctx = c;
+  stream = s;
+  if (create_stream) {
+    // default priority (streams of different priorities are avoided)
+    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) return RTG_EDEVICE;
+    own_stream = true;
+  }
+  if (hipHostMalloc(&host_stage, 4096) != hipSuccess) return RTG_EDEVICE;
+  gather_dev = c->dalloc(64);
+  if (!gather_dev) return RTG_ENOMEM;
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) return RTG_EDEVICE;
+  return RTG_OK;
+}
+
+void Lane::fini() {
+  if (stream || own_stream) (void)hipStreamSynchronize(stream);
+  if (host_stage) (void)hipHostFree(host_stage);
+  host_stage = nullptr;
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : kev) (void)hipEventDestroy(e);
+  kev.clear();
+  if (gather_dev && ctx) ctx->dfree(gather_dev);
+  gather_dev = nullptr;
+  if (own_stream) (void)hipStreamDestroy(stream);
+  own_stream = false;
+}
+
+int Lane::hip_fail(hipError_t e, const char* what) { return ctx->hip_fail(e, what); }
+void* Lane::dalloc(size_t bytes) { return ctx->dalloc(bytes); }
+void Lane::dfree(void* p) { ctx->dfree(p); }
+
+int Lane::sync() { return hip_fail(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
+
+int Lane::read_back(const void* dev, size_t bytes, void* host) {
   hipError_t e = hipMemcpyAsync(host_stage, dev, bytes, hipMemcpyDeviceToHost, stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync D2H");
   int rc = sync();
@@ -337,21 +429,28 @@ int Ctx::read_back(const void* dev, size_t bytes, void* host) {
   return RTG_OK;
 }
 
-int Ctx::gather_back(const rtgk::Gather& g, uint64_t* host) {
+int Lane::gather_back(const rtgk::Gather& g, uint64_t* host) {
   rtgk::launch_gather(g, static_cast<uint64_t*>(gather_dev), stream);
   return read_back(gather_dev, sizeof(uint64_t) * g.count, host);
 }
 
-int Ctx::upload(void* dev, const void* host, size_t bytes) {
+int Lane::download(void* host, const void* dev, size_t bytes) {
+  if (bytes == 0) return RTG_OK;
+  hipError_t e = hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync D2H");
+  return sync();
+}
+
+int Lane::upload(void* dev, const void* host, size_t bytes) {
   return hip_fail(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, stream),
                   "hipMemcpyAsync H2D");
 }
 
-void Ctx::mark(int phase) {
+void Lane::mark(int phase) {
   if (timing_mask & RTG_TIME_PHASES) (void)hipEventRecord(ev[phase], stream);
 }
 
-void Ctx::kbegin(int kid) {
+void Lane::kbegin(int kid) {
   if (!(timing_mask & (1u << kid))) return;
   const size_t pair = kpending.size();
   while (kev.size() < 2 * (pair + 1)) {
@@ -363,7 +462,7 @@ void Ctx::kbegin(int kid) {
   kpending.emplace_back(kid, (int)pair);
 }
 
-void Ctx::kend(int kid, double bytes) {
+void Lane::kend(int kid, double bytes) {
   if (kstats) {
     kstats->kernel_launches[kid] += 1;
     kstats->kernel_bytes[kid] += bytes;
@@ -374,7 +473,7 @@ void Ctx::kend(int kid, double bytes) {
   (void)hipEventRecord(kev[2 * last.second + 1], stream);
 }
 
-void Ctx::kfinish() {
+void Lane::kfinish() {
   for (const auto& pk : kpending) {
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, kev[2 * pk.second], kev[2 * pk.second + 1]) == hipSuccess &&
@@ -384,31 +483,17 @@ void Ctx::kfinish() {
   kpending.clear();
 }
 
-static void timer_begin(void* self, int kid) { static_cast<Ctx*>(self)->kbegin(kid); }
+static void timer_begin(void* self, int kid) { static_cast<Lane*>(self)->kbegin(kid); }
 static void timer_end(void* self, int kid, double bytes) {
-  static_cast<Ctx*>(self)->kend(kid, bytes);
+  static_cast<Lane*>(self)->kend(kid, bytes);
 }
 
-rtgk::LaunchTimer Ctx::timer() {
+rtgk::LaunchTimer Lane::timer() {
   rtgk::LaunchTimer t;
   t.self = this;
   t.begin = timer_begin;
   t.end = timer_end;
   return t;
-}
-
-uint64_t Ctx::keep_result(void* mem, int64_t n, int64_t nnz, int64_t* row_ptr, int32_t* col) {
-  const uint64_t h = next_handle++;
-  results[h] = Result{mem, n, nnz, row_ptr, col};
-  return h;
-}
-
-int Ctx::release(uint64_t h) {
-  auto it = results.find(h);
-  if (it == results.end()) return RTG_ENOENT;
-  dfree(it->second.mem);
-  results.erase(it);
-  return RTG_OK;
 }
 
 // Device-side validity of a caller pointer: it must be device memory (or
@@ -437,11 +522,15 @@ int validate_query(const float* points, int64_t n, int32_t d, double r, int32_t 
 namespace {
 
 // Frees every arena block taken through it when it goes out of scope.
+// Blocks are returned only after the lane's stream has drained, so that
+// another lane cannot reuse memory a kernel of this one still touches.
 struct Scratch {
-  Ctx& c;
+  Lane& c;
   std::vector<void*> held;
-  explicit Scratch(Ctx& ctx) : c(ctx) {}
+  explicit Scratch(Lane& lane) : c(lane) {}
   ~Scratch() {
+    if (held.empty()) return;
+    (void)hipStreamSynchronize(c.stream);
     for (void* p : held) c.dfree(p);
   }
   template <class T>
@@ -453,6 +542,7 @@ struct Scratch {
   void drop(void* p) {
     auto it = std::find(held.begin(), held.end(), p);
     if (it != held.end()) {
+      (void)hipStreamSynchronize(c.stream);
       c.dfree(p);
       held.erase(it);
     }
@@ -460,7 +550,7 @@ struct Scratch {
 };
 
 // Result block: row_ptr (n+1 int64) then col (nnz int32), one arena block.
-int alloc_result(Ctx& c, int64_t n, size_t nnz, void** res, int64_t** row_ptr, int32_t** col) {
+int alloc_result(Lane& c, int64_t n, size_t nnz, void** res, int64_t** row_ptr, int32_t** col) {
   const size_t rp = ((sizeof(int64_t) * (size_t)(n + 1)) + Arena::kAlign - 1) &
                     ~(size_t)(Arena::kAlign - 1);
   *res = c.dalloc(rp + sizeof(int32_t) * std::max<size_t>(nnz, 1));
@@ -474,7 +564,7 @@ int alloc_result(Ctx& c, int64_t n, size_t nnz, void** res, int64_t** row_ptr, i
 // directed entries of the unique pairs into buckets of 2^rb rows, then put
 // each bucket in (row, col) order in LDS and write col and row_ptr; buckets
 // too large for LDS go through the global radix sort.
-int csr_by_buckets(Ctx& c, Scratch& S, const uint64_t* pairs, size_t count, int64_t n, int pb,
+int csr_by_buckets(Lane& c, Scratch& S, const uint64_t* pairs, size_t count, int64_t n, int pb,
                    bool both, uint32_t* err, const LaunchTimer* tm, void** res, int64_t** row_ptr,
                    int32_t** col, size_t* nnz_out) {
   hipStream_t s = c.stream;
@@ -502,7 +592,7 @@ int csr_by_buckets(Ctx& c, Scratch& S, const uint64_t* pairs, size_t count, int6
   launch_bucket_scatter(pairs, count, pb, rb, both ? 1 : 0, nbuckets, chunk, nblocks, part, entries,
                         s);
   launch_fill_u32(over, 0u, 1, s);
-  launch_bucket_csr(entries, part, nbuckets, nblocks, part + np, over + 1, over, c.bucket_cap, pb,
+  launch_bucket_csr(entries, part, nbuckets, nblocks, part + np, over + 1, over, c.ctx->bucket_cap, pb,
                     rb, n, *row_ptr, *col, s);
   launch_fill_u64(reinterpret_cast<uint64_t*>(*row_ptr + n), (uint64_t)E, 1, s);
   // read the pairs twice, write and read the entries, write col and row_ptr
@@ -516,8 +606,7 @@ int csr_by_buckets(Ctx& c, Scratch& S, const uint64_t* pairs, size_t count, int6
   if (nover) {
     // Rare: buckets beyond LDS capacity go through the global radix sort.
     std::vector<uint32_t> ids(nover);
-    rc = c.hip_fail(hipMemcpy(ids.data(), over + 1, sizeof(uint32_t) * nover,
-                              hipMemcpyDeviceToHost), "copy oversized list");
+    rc = c.download(ids.data(), over + 1, sizeof(uint32_t) * nover);
     for (size_t q = 0; !rc && q < ids.size(); ++q) {
       const uint32_t b = ids[q];
       uint32_t lim[2];
@@ -552,7 +641,7 @@ int csr_by_buckets(Ctx& c, Scratch& S, const uint64_t* pairs, size_t count, int6
 
 // Neighbour lists from pairs sorted by (i, j): upper rows are runs of the
 // sorted list; lower rows come from a second sort of the swapped pairs.
-int csr_from_sorted(Ctx& c, Scratch& S, const uint64_t* uniq, size_t U, int64_t n, int pb,
+int csr_from_sorted(Lane& c, Scratch& S, const uint64_t* uniq, size_t U, int64_t n, int pb,
                     bool both, uint32_t* err, int64_t* row_ptr, int32_t* col) {
   hipStream_t s = c.stream;
   uint32_t* up_s = S.get<uint32_t>((size_t)n);
@@ -578,7 +667,7 @@ int csr_from_sorted(Ctx& c, Scratch& S, const uint64_t* uniq, size_t U, int64_t 
     if (!sw || !sw_alt || !scr) return RTG_ENOMEM;
     launch_swap_pairs(uniq, U, pb, sw, s);
     const int where = radix_sort(sw, nullptr, sw_alt, nullptr, U, 0, 2 * pb, scr, err, s, nullptr,
-                                 0, 0, c.sort_algo);
+                                 0, 0, c.ctx->sort_algo);
     lower = where ? sw_alt : sw;
     launch_row_runs(lower, U, pb, lo_s, lo_e, s);
   }
@@ -595,7 +684,7 @@ int csr_from_sorted(Ctx& c, Scratch& S, const uint64_t* uniq, size_t U, int64_t 
 
 }  // namespace
 
-int Ctx::make_empty_result(int64_t n, rtg_csr* out) {
+int Lane::make_empty_result(int64_t n, rtg_csr* out, uint64_t handle) {
   void* mem = dalloc(sizeof(int64_t) * (size_t)(n + 1));
   if (!mem) return RTG_ENOMEM;
   launch_fill_u64(static_cast<uint64_t*>(mem), 0ull, (size_t)(n + 1), stream);
@@ -609,7 +698,7 @@ int Ctx::make_empty_result(int64_t n, rtg_csr* out) {
   out->row_ptr = static_cast<int64_t*>(mem);
   out->col = nullptr;
   out->pairs = 0;
-  out->handle = keep_result(mem, n, 0, out->row_ptr, nullptr);
+  out->handle = ctx->keep_result(handle, mem, n, 0, 0, out->row_ptr, nullptr);
   return RTG_OK;
 }
 
@@ -627,15 +716,14 @@ int Ctx::check_query(const float* points, int64_t n, int32_t d, double r, int32_
 }
 
 // Lists for a query of n <= 1 points: empty, after the finiteness check.
-int Ctx::tiny_query(const float* points, int64_t n, int32_t d, rtg_csr* out) {
+int Lane::tiny_query(const float* points, int64_t n, int32_t d, rtg_csr* out, uint64_t handle) {
   if (n == 1) {
     std::vector<float> h(d);
-    if (hip_fail(hipMemcpy(h.data(), points, sizeof(float) * d, hipMemcpyDeviceToHost), "copy"))
-      return RTG_EDEVICE;
+    if (download(h.data(), points, sizeof(float) * d)) return RTG_EDEVICE;
     for (float v : h)
       if (!std::isfinite(v)) return RTG_EINVAL;
   }
-  return make_empty_result(n, out);
+  return make_empty_result(n, out, handle);
 }
 
 int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha,
@@ -649,13 +737,13 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
   st.k = k;
   st.point_transforms = n * k;
   if (n <= 1) {
-    rc = tiny_query(points, n, d, out);
+    rc = main.tiny_query(points, n, d, out, 0);
     if (!rc) stats = st;
     return rc;
   }
   Job job{points, n, d, r, alpha, k, flags, R, u, out};
   std::vector<Job*> jobs{&job};
-  rc = run_batch(jobs, st);
+  rc = main.run_batch(jobs, st);
   if (!rc) stats = st;
   return rc;
 }
@@ -663,7 +751,7 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
 // One pass of the pipeline over a batch of instances of one dimension d
 // sharing the RTG_UPPER_ONLY / RTG_DEDUP_SORT flags (every instance has
 // n >= 2 and passed check_query).  On success each job's out is filled.
-int Ctx::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
+int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   const uint32_t m = (uint32_t)jobs.size();
   const int d = jobs[0]->d;
   const uint32_t flags = jobs[0]->flags;
@@ -674,7 +762,7 @@ int Ctx::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   kstats = &st;
   kpending.clear();
   struct Detach {
-    Ctx& c;
+    Lane& c;
     ~Detach() {
       c.kpending.clear();
       c.kstats = nullptr;
@@ -742,9 +830,7 @@ int Ctx::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   mark(1);
   std::vector<uint32_t> hb((size_t)m * 2 * d + 1);
   if ((rc = sync())) return rc;
-  if ((rc = hip_fail(hipMemcpy(hb.data(), bbox, sizeof(uint32_t) * hb.size(),
-                               hipMemcpyDeviceToHost), "copy bounding boxes")))
-    return rc;
+  if ((rc = download(hb.data(), bbox, sizeof(uint32_t) * hb.size()))) return rc;
   if (hb[(size_t)m * 2 * d]) return RTG_EINVAL;
   const float* pts_rows = aos ? aos : jobs[0]->pts;
 
@@ -765,7 +851,7 @@ int Ctx::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
       ks[q] = jobs[q]->k;
     }
     rc = plan_batch(d, m, ks.data(), ns.data(), Rh.data(), uh.data(), inv_cs.data(),
-                    alphas.data(), lo.data(), hi.data(), arena->largest_free() / 2, P);
+                    alphas.data(), lo.data(), hi.data(), ctx->largest_free() / 2, P);
     if (rc) return rc;
   }
   st.key_bits = std::max(st.key_bits, P.key_bits);
@@ -855,7 +941,7 @@ int Ctx::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     mark(2);
     const int where = radix_sort(keys, vals, keys_alt, vals_alt, N, idx_bits, idx_bits + key_bits,
                                  sort_scr, err, stream, &tm, RTG_K_KEY_HIST, RTG_K_KEY_SCATTER,
-                                 sort_algo);
+                                 ctx->sort_algo);
     const uint64_t* skeys = where ? keys_alt : keys;
     const uint32_t* sidx = idx_bits ? nullptr : (where ? vals_alt : vals);
     mark(3);
@@ -987,7 +1073,7 @@ int Ctx::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
         static_cast<void*>(S.get<char>(radix_scratch_bytes(C, 0, 2 * pair_bits))));
     if (!cand_alt || !scr) return RTG_ENOMEM;
     const int where = radix_sort(cand, nullptr, cand_alt, nullptr, C, 0, 2 * pair_bits, scr, err,
-                                 stream, &tm, RTG_K_PAIR_HIST, RTG_K_PAIR_SCATTER, sort_algo);
+                                 stream, &tm, RTG_K_PAIR_HIST, RTG_K_PAIR_SCATTER, ctx->sort_algo);
     const uint64_t* sc = where ? cand_alt : cand;
     uint64_t* dst = where ? cand : cand_alt;
     mark(6);
@@ -1054,8 +1140,7 @@ int Ctx::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
       return RTG_ENOMEM;
     }
     launch_rowptr_at(inst_d, m, row_ptr, npts, at_d, stream);
-    if ((rc = sync()) || (rc = hip_fail(hipMemcpy(at.data(), at_d, sizeof(int64_t) * (m + 1),
-                                                  hipMemcpyDeviceToHost), "copy row offsets"))) {
+    if ((rc = download(at.data(), at_d, sizeof(int64_t) * (m + 1)))) {
       dfree(res);
       return rc;
     }
@@ -1085,7 +1170,7 @@ int Ctx::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
       j.out->row_ptr = rps[q];
       j.out->col = nq ? cols[q] : nullptr;
       j.out->pairs = both ? nq / 2 : nq;
-      j.out->handle = keep_result(mem[q], j.n, nq, rps[q], cols[q]);
+      j.out->handle = ctx->keep_result(j.handle, mem[q], j.n, nq, j.out->pairs, rps[q], cols[q]);
     }
   }
   mark(8);
@@ -1122,7 +1207,10 @@ int Ctx::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     (void)hipEventElapsedTime(&tot_ms, ev[0], ev[8]);
     st.ms_total += tot_ms;
   }
-  if (m == 1) jobs[0]->out->handle = keep_result(res, jobs[0]->n, (int64_t)nnz, row_ptr, col);
+  if (m == 1)
+    jobs[0]->out->handle =
+        ctx->keep_result(jobs[0]->handle, res, jobs[0]->n, (int64_t)nnz, jobs[0]->out->pairs,
+                         row_ptr, col);
   return RTG_OK;
 }
 
@@ -1155,12 +1243,12 @@ int Ctx::batched(const rtg_query* q, int32_t nq, rtg_csr* outs) {
     st.n += q[i].n;
     st.point_transforms += q[i].n * q[i].k;
     if (q[i].n <= 1) {
-      if ((rc = tiny_query(q[i].points, q[i].n, q[i].d, &res[i]))) return undo(rc);
+      if ((rc = main.tiny_query(q[i].points, q[i].n, q[i].d, &res[i], 0))) return undo(rc);
       done[i] = 1;
       continue;
     }
     jobs[i] = Job{q[i].points, q[i].n, q[i].d, q[i].r, q[i].alpha, q[i].k, q[i].flags,
-                  R[i].data(), u[i].data(), &res[i]};
+                  R[i].data(), u[i].data(), &res[i], 0};
     groups[{q[i].d, q[i].flags & (RTG_UPPER_ONLY | RTG_DEDUP_SORT)}].push_back(i);
   }
   for (auto& g : groups) {
@@ -1174,7 +1262,7 @@ int Ctx::batched(const rtg_query* q, int32_t nq, rtg_csr* outs) {
         batch.push_back(&jobs[g.second[b]]);
         ++b;
       }
-      if ((rc = run_batch(batch, st))) return undo(rc);
+      if ((rc = main.run_batch(batch, st))) return undo(rc);
       for (Job* j : batch) done[j->out - res.data()] = 1;
     }
   }
@@ -1192,14 +1280,15 @@ int Ctx::debug_cell_coords(const float* points, int64_t n, int32_t d, double r, 
   if (rc) return rc;
   if (n == 0) return RTG_OK;
   if (check_device_pointer(points, device)) return RTG_EINVAL;
-  Scratch S(*this);
+  Lane& L = main;
+  Scratch S(L);
   float* soa = S.get<float>((size_t)n * d);
   uint32_t* flags_dev = S.get<uint32_t>(2 + 2 * kMaxDim);
   double* Rd = S.get<double>((size_t)d * d);
   double* ud = S.get<double>((size_t)d);
   int64_t* kap = S.get<int64_t>((size_t)n * d);
   if (!soa || !flags_dev || !Rd || !ud || !kap) return RTG_ENOMEM;
-  if ((rc = upload(Rd, R, sizeof(double) * d * d)) || (rc = upload(ud, u, sizeof(double) * d)))
+  if ((rc = L.upload(Rd, R, sizeof(double) * d * d)) || (rc = L.upload(ud, u, sizeof(double) * d)))
     return rc;
   const uint32_t nblk = (uint32_t)((n + kBlock - 1) / kBlock);
   uint32_t* stage_part = S.get<uint32_t>((size_t)nblk * 2 * d);
@@ -1208,17 +1297,15 @@ int Ctx::debug_cell_coords(const float* points, int64_t n, int32_t d, double r, 
   InstDesc one{};
   one.pts = points;
   one.n = n;
-  if ((rc = upload(inst_d, &one, sizeof(one)))) return rc;
-  launch_fill_u32(flags_dev + 1, 0u, 1, stream);
-  launch_stage(inst_d, 1, nblk, d, n, soa, nullptr, flags_dev, flags_dev + 2, stage_part, stream);
-  launch_cell_coords(soa, n, d, Rd, ud, 1.0 / (alpha * r), kap, flags_dev + 1, stream);
+  if ((rc = L.upload(inst_d, &one, sizeof(one)))) return rc;
+  launch_fill_u32(flags_dev + 1, 0u, 1, L.stream);
+  launch_stage(inst_d, 1, nblk, d, n, soa, nullptr, flags_dev, flags_dev + 2, stage_part, L.stream);
+  launch_cell_coords(soa, n, d, Rd, ud, 1.0 / (alpha * r), kap, flags_dev + 1, L.stream);
   uint32_t fl[2];
-  if ((rc = read_back(flags_dev, sizeof(fl), fl))) return rc;
+  if ((rc = L.read_back(flags_dev, sizeof(fl), fl))) return rc;
   if (fl[0]) return RTG_EINVAL;
   if (fl[1]) return RTG_ERANGE;
-  return hip_fail(hipMemcpy(kappa_host, kap, sizeof(int64_t) * (size_t)n * d,
-                            hipMemcpyDeviceToHost),
-                  "copy kappa");
+  return L.download(kappa_host, kap, sizeof(int64_t) * (size_t)n * d);
 }
 
 }  // namespace rtg
@@ -1235,7 +1322,7 @@ int rtg_create(rtg_ctx** out, int device, void* arena, size_t arena_bytes, void*
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return RTG_EINVAL;
   if (hipSetDevice(device) != hipSuccess) return RTG_EDEVICE;
-  Ctx* c = new (std::nothrow) Ctx(device, static_cast<hipStream_t>(hip_stream));
+  Ctx* c = new (std::nothrow) Ctx(device);
   if (!c) return RTG_ENOMEM;
   if (!arena) {
     if (hipMalloc(&c->arena_mem, arena_bytes) != hipSuccess) {
@@ -1246,20 +1333,11 @@ int rtg_create(rtg_ctx** out, int device, void* arena, size_t arena_bytes, void*
     arena = c->arena_mem;
   }
   c->arena.reset(new rtg::Arena(static_cast<char*>(arena), arena_bytes));
-  if (hipHostMalloc(&c->host_stage, 4096) != hipSuccess) {
+  const int rc = c->main.init(c, static_cast<hipStream_t>(hip_stream), false);
+  if (rc) {
     delete c;
-    return RTG_EDEVICE;
+    return rc;
   }
-  c->gather_dev = c->arena->alloc(64);
-  if (!c->gather_dev) {
-    delete c;
-    return RTG_ENOMEM;
-  }
-  for (auto& e : c->ev)
-    if (hipEventCreate(&e) != hipSuccess) {
-      delete c;
-      return RTG_EDEVICE;
-    }
   *out = reinterpret_cast<rtg_ctx*>(c);
   return RTG_OK;
 }
@@ -1268,7 +1346,7 @@ int rtg_destroy(rtg_ctx* ctx) {
   if (!ctx) return RTG_EINVAL;
   Ctx* c = reinterpret_cast<Ctx*>(ctx);
   c->stop_server();
-  (void)hipStreamSynchronize(c->stream);
+  (void)hipStreamSynchronize(c->main.stream);
   delete c;
   return RTG_OK;
 }
@@ -1296,9 +1374,7 @@ int rtg_all_pairs_with_transforms(rtg_ctx* ctx, const float* points, int64_t n, 
 
 int rtg_release(rtg_ctx* ctx, uint64_t handle) {
   if (!ctx) return RTG_EINVAL;
-  Ctx* c = reinterpret_cast<Ctx*>(ctx);
-  std::lock_guard<std::mutex> lk(c->mu);
-  return c->release(handle);
+  return reinterpret_cast<Ctx*>(ctx)->release(handle);
 }
 
 int rtg_make_transforms(uint64_t seed, int32_t k, int32_t d, uint32_t flags, double* R, double* u) {
@@ -1309,13 +1385,19 @@ int rtg_set_timing(rtg_ctx* ctx, uint32_t mask) {
   if (!ctx) return RTG_EINVAL;
   Ctx* c = reinterpret_cast<Ctx*>(ctx);
   std::lock_guard<std::mutex> lk(c->mu);
-  c->timing_mask = mask;
+  c->main.timing_mask = mask;
   return RTG_OK;
 }
 
-int rtg_get_stats(const rtg_ctx* ctx, rtg_stats* out) {
+int rtg_get_stats(rtg_ctx* ctx, rtg_stats* out) {
   if (!ctx || !out) return RTG_EINVAL;
-  *out = reinterpret_cast<const Ctx*>(ctx)->stats;
+  Ctx* c = reinterpret_cast<Ctx*>(ctx);
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    *out = c->stats;
+  }
+  out->served_requests = c->served_requests;
+  out->served_batches = c->served_batches;
   return RTG_OK;
 }
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -64,6 +65,7 @@ struct Job {
   const double* R;  // [k][d][d]
   const double* u;  // [k][d]
   rtg_csr* out;
+  uint64_t handle = 0;  // result handle to use (0: a new one)
 };
 
 // Points per batch of rtg_all_pairs_batched (an instance larger runs alone):
@@ -76,37 +78,32 @@ int plan_batch(int d, uint32_t m, const int64_t* k, const int64_t* n, const doub
 
 struct Result {
   void* mem;
-  int64_t n, nnz;
+  int64_t n, nnz, pairs;
   int64_t* row_ptr;
   int32_t* col;
 };
 
-struct Ctx {
-  Ctx(int dev, hipStream_t s);
-  ~Ctx();
+struct Ctx;
+struct Server;
 
-  int device;
-  hipStream_t stream;
-  bool own_arena = false;
-  void* arena_mem = nullptr;
-  std::unique_ptr<Arena> arena;
-  void* host_stage = nullptr;  // pinned staging for scalar read-backs
+// An execution lane: one HIP stream with its own staging buffers and timing
+// state.  A pass of the pipeline runs on one lane and is ordered on its
+// stream; passes on different lanes run concurrently and share the
+// context's arena and results.
+struct Lane {
+  Ctx* ctx = nullptr;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  void* host_stage = nullptr;  // pinned staging for scalar read-backs (4 KB)
   void* gather_dev = nullptr;  // 8 device u64 that gather_back fills
-  bool poisoned = false;
-  uint32_t timing_mask = 0;  // bit i: time kernel id i; RTG_TIME_PHASES: phases
-  int sort_algo = 0;         // rtgk::kSortOnesweep or rtgk::kSortReduceScan
-  uint32_t bucket_cap = rtgk::kBucketMaxEntries;  // entries per LDS-sorted bucket
-  int64_t batch_points = kBatchPoints;             // points per batch
+  uint32_t timing_mask = 0;    // bit i: time kernel id i; RTG_TIME_PHASES: phases
   hipEvent_t ev[9] = {};
-  rtg_stats stats{};
-  // per-launch timing: a pool of event pairs and the launches of this call
-  std::vector<hipEvent_t> kev;
-  std::vector<std::pair<int, int>> kpending;  // (kernel id, event pair)
-  rtg_stats* kstats = nullptr;                // stats of the call in flight
-  std::mutex mu;  // one pipeline call at a time
-  std::map<uint64_t, Result> results;
-  uint64_t next_handle = 1;
+  std::vector<hipEvent_t> kev;                // pool of event pairs
+  std::vector<std::pair<int, int>> kpending;  // (kernel id, event pair) of this pass
+  rtg_stats* kstats = nullptr;                // stats of the pass in flight
 
+  int init(Ctx* c, hipStream_t s, bool create_stream);
+  void fini();
   int hip_fail(hipError_t e, const char* what);
   void* dalloc(size_t bytes);
   void dfree(void* p);
@@ -115,26 +112,64 @@ struct Ctx {
   // Several device scalars in one copy (one sync).
   int gather_back(const rtgk::Gather& g, uint64_t* host);
   int upload(void* dev, const void* host, size_t bytes);
+  int download(void* host, const void* dev, size_t bytes);  // ordered on the stream, waits
   void mark(int phase);
   void kbegin(int kid);
   void kend(int kid, double bytes);
   void kfinish();  // after a sync: add the timed launches to *kstats
   rtgk::LaunchTimer timer();
-  uint64_t keep_result(void* mem, int64_t n, int64_t nnz, int64_t* row_ptr, int32_t* col);
+
+  int make_empty_result(int64_t n, rtg_csr* out, uint64_t handle);
+  int tiny_query(const float* points, int64_t n, int32_t d, rtg_csr* out, uint64_t handle);
+  // One pass of the pipeline over a batch of instances of one dimension.
+  int run_batch(std::vector<Job*>& jobs, rtg_stats& st);
+};
+
+struct Ctx {
+  explicit Ctx(int dev);
+  ~Ctx();
+
+  int device;
+  bool own_arena = false;
+  void* arena_mem = nullptr;
+  std::unique_ptr<Arena> arena;
+  std::atomic<bool> poisoned{false};
+  int sort_algo = 0;  // rtgk::kSortOnesweep or rtgk::kSortReduceScan
+  uint32_t bucket_cap = rtgk::kBucketMaxEntries;  // entries per LDS-sorted bucket
+  int64_t batch_points = kBatchPoints;             // points per batch
+  int server_lanes = 2;  // passes of the request loop that may run at once
+  Lane main;          // the caller's stream: blocking calls
+  rtg_stats stats{};  // of the last blocking call
+  std::mutex mu;      // one blocking call at a time
+  std::mutex amu;     // arena, results, handles
+  std::map<uint64_t, Result> results;
+  uint64_t next_handle = 1;
+  Server* server = nullptr;  // request loop, started by the first rtg_submit
+  std::mutex server_mu;      // guards the server pointer
+
+  int hip_fail(hipError_t e, const char* what);
+  void* dalloc(size_t bytes);
+  void dfree(void* p);
+  size_t largest_free();
+  size_t free_bytes();
+  uint64_t new_handle();
+  uint64_t keep_result(uint64_t h, void* mem, int64_t n, int64_t nnz, int64_t pairs,
+                       int64_t* row_ptr, int32_t* col);
   int release(uint64_t handle);
-  int make_empty_result(int64_t n, rtg_csr* out);
+  bool find_result(uint64_t handle, rtg_csr* out);
 
   int all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha,
                 const double* R, const double* u, uint32_t flags, rtg_csr* out);
   int batched(const rtg_query* q, int32_t nq, rtg_csr* outs);
-  int run_batch(std::vector<Job*>& jobs, rtg_stats& st);
   int check_query(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha);
-  int tiny_query(const float* points, int64_t n, int32_t d, rtg_csr* out);
   int debug_cell_coords(const float* points, int64_t n, int32_t d, double r, double alpha,
                         const double* R, const double* u, int64_t* kappa_host);
 
   // request loop (rtg_server.cpp)
-  void stop_server() {}
+  int submit(const rtg_query& q, uint64_t* ticket);
+  int poll(uint64_t ticket, rtg_csr* out);
+  void stop_server();
+  std::atomic<int64_t> served_requests{0}, served_batches{0};
 };
 
 }  // namespace rtg

@@ -60,7 +60,8 @@ class rtg_stats(ctypes.Structure):
             "ms_unique", "ms_csr", "ms_total")] + [
         ("kernel_launches", ctypes.c_int64 * NKERNELS),
         ("kernel_bytes", ctypes.c_double * NKERNELS),
-        ("kernel_ms", ctypes.c_double * NKERNELS)]
+        ("kernel_ms", ctypes.c_double * NKERNELS),
+        ("served_requests", ctypes.c_int64), ("served_batches", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         out = {}
@@ -252,12 +253,18 @@ class Context:
         _check(lib().rtg_all_pairs_batched(self.h, qs, nq, outs), "rtg_all_pairs_batched")
         return [self._result(outs[i]) for i in range(nq)]
 
-    def rtg_submit(self, points, r: float, k: int, alpha: float, seed: int, flags: int = 0) -> int:
+    def rtg_submit(self, points, r: float, k: int, alpha: float, seed: int,
+                   flags: int = 0) -> int | None:
+        """A ticket, or None when the points cannot be staged yet (retry later).
+        The points are copied before this returns."""
         p = self._points(points)
         q = rtg_query(p.data_ptr(), p.shape[0], p.shape[1], float(r), int(k), float(alpha),
                       seed & (2**64 - 1), flags)
         t = ctypes.c_uint64()
-        _check(lib().rtg_submit(self.h, ctypes.byref(q), ctypes.byref(t)), "rtg_submit")
+        rc = lib().rtg_submit(self.h, ctypes.byref(q), ctypes.byref(t))
+        if rc == EAGAIN:
+            return None
+        _check(rc, "rtg_submit")
         return int(t.value)
 
     def rtg_poll(self, ticket: int):
@@ -268,6 +275,18 @@ class Context:
             return None
         _check(rc, "rtg_poll")
         return self._result(out)
+
+    def wait(self, ticket: int, timeout_s: float = 60.0, sleep_s: float = 1e-4):
+        """Poll until the request is done (raises TimeoutError after timeout_s)."""
+        import time
+        t_end = time.monotonic() + timeout_s
+        while True:
+            res = self.rtg_poll(ticket)
+            if res is not None:
+                return res
+            if time.monotonic() > t_end:
+                raise TimeoutError(f"request {ticket} not done after {timeout_s} s")
+            time.sleep(sleep_s)
 
     def rtg_release(self, handle: int) -> None:
         _check(lib().rtg_release(self.h, handle), "rtg_release")
