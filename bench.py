@@ -181,6 +181,9 @@ def main(argv=None) -> int:
                     help="skip the batched-instances measurement")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the request-loop measurement")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device copy of this many MiB first (a known-size "
+                         "kernel for scaling hardware byte counters)")
     ap.add_argument("--batched-count", type=int, default=4096)
     ap.add_argument("--serving-requests", type=int, default=1000)
     ap.add_argument("--serving-rate", type=float, default=1000.0)
@@ -200,6 +203,14 @@ def main(argv=None) -> int:
     ctx = rtg.Context(0, arena_bytes=int(args.arena_gb * (1 << 30)))
     pts = torch.from_numpy(pts_host).to("cuda:0")
     torch.cuda.synchronize()
+    if args.copy_calibration_mib > 0:
+        # reads and writes exactly copy_calibration_mib MiB each
+        src = torch.ones(args.copy_calibration_mib << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         res = ctx.all_pairs(pts, wl.r, wl.k, wl.alpha, wl.seed)

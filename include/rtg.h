@@ -131,6 +131,9 @@ typedef struct rtg_stats {
    * passes (batches) that ran them. */
   int64_t served_requests;
   int64_t served_batches;
+  /* Pair-kernel launches of the last call that screened on the matrix cores
+   * (the rest used the vector screen). */
+  int64_t matrix_screen_launches;
 } rtg_stats;
 
 /* Create a context on HIP device `device`.

@@ -177,6 +177,17 @@ PairTest make_pair_test(double r2, int pair_bits) {
   return t;
 }
 
+// Whether the matrix-core pair screen suits an instance: its band, relative
+// to r^2, is about (2K + d + 8) * 1.5 * 2^-24 * 2 d alpha^2 for cells of side
+// alpha r (K = d + 2 rounded up to even); up to 2^-8 it sends few pairs to
+// FP64.  Wider bands stay exact but slow, so they take the vector screen.
+bool gram_suits(int d, double alpha) {
+  if (d > 16) return false;
+  const int K = (d + 3) & ~1;
+  const double band = 1.5 * (2.0 * K + d + 8) * 0x1p-24 * 2.0 * d * alpha * alpha;
+  return band <= 0x1p-8;
+}
+
 float decode_order(uint32_t e) {
   const uint32_t b = (e & 0x80000000u) ? (e & 0x7FFFFFFFu) : ~e;
   float f;
@@ -299,6 +310,12 @@ Ctx::Ctx(int dev) : device(dev) {
   if (bp) {
     const long long v = std::strtoll(bp, nullptr, 10);
     if (v >= 2 && v < kBatchPoints) batch_points = v;
+  }
+  // RTG_PAIRS: "vector" forces the vector pair screen, "matrix" the
+  // matrix-core one wherever d <= 16 (default: matrix cores where they suit).
+  if (const char* e = std::getenv("RTG_PAIRS")) {
+    if (std::strcmp(e, "vector") == 0) pair_screen = 1;
+    if (std::strcmp(e, "matrix") == 0) pair_screen = 2;
   }
   // RTG_LANES: passes of the request loop that may run at once (1..4).
   if (const char* e = std::getenv("RTG_LANES"))
@@ -756,7 +773,6 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   const int d = jobs[0]->d;
   const uint32_t flags = jobs[0]->flags;
   const bool both = !(flags & RTG_UPPER_ONLY);
-  const bool first_owner = !(flags & RTG_DEDUP_SORT);
   int rc;
 
   kstats = &st;
@@ -911,17 +927,30 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
 
   // First-owner filter (default): each pair is emitted only by the first grid
   // whose cell holds both points, so the union needs no de-duplication.  It
-  // needs every point's packed cell key under every grid.
-  const int sig64 = P.layout.cell_bits > 32 ? 1 : 0;
-  void* sig = nullptr;
+  // compares neighbourhood signatures: per grid the low sig_b bits of every
+  // axis field, sig_b the widest minimum field width of the batch.  Groups
+  // wider than a word (small alpha at high d) take sort-unique instead.
+  int sig_b = 1;
+  for (uint32_t q = 0; q < m; ++q) sig_b = std::max(sig_b, min_field_bits(jobs[q]->alpha));
+  const int sig_g = d * sig_b;
+  const bool first_owner = !(flags & RTG_DEDUP_SORT) && sig_g <= 64;
+  const int sig_gpw = sig_g <= 64 ? 64 / sig_g : 1;
+  const int sig_W = (kmax + sig_gpw - 1) / sig_gpw;
+  uint64_t* sig = nullptr;
   if (first_owner) {
-    sig = S.get<char>((size_t)npts * kmax * (sig64 ? 8 : 4));
+    sig = S.get<uint64_t>((size_t)npts * sig_W);
     if (!sig) return RTG_ENOMEM;
+    launch_fill_u64(sig, 0ull, (size_t)npts * sig_W, stream);
   }
 
   uint64_t cap = 0;
   uint64_t* cand = nullptr;
   uint64_t cand_total = 0;  // exact number of candidates so far
+
+  // Pair screen: matrix cores when every instance suits them.
+  bool use_gram = ctx->pair_screen != 1;
+  for (uint32_t q = 0; q < m && use_gram; ++q) use_gram = gram_suits(d, jobs[q]->alpha);
+  if (ctx->pair_screen == 2) use_gram = d <= 16;
 
   for (int32_t sa = 0; sa < S_total; sa += P.tb) {
     const int32_t sb = std::min(S_total, sa + P.tb);
@@ -933,11 +962,11 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     const int seg_bits = (sb - sa) > 1 ? ceil_log2((uint64_t)(sb - sa)) : 0;
     const int key_bits = seg_bits + P.layout.cell_bits;
     KeysArgs ka{inst_d, m, nblk, d, npts, soa, sa, sb, segs_d, Rd, ud, klo_d, layout_d,
-                keys, vals, err, sig, sig64, kmax, idx_bits};
+                keys, vals, err, sig, sig_W, sig_b, sig_gpw, idx_bits};
     kbegin(RTG_K_KEYS);
     launch_keys(ka, stream);
     kend(RTG_K_KEYS, 4.0 * (double)pass_pts * d + (idx_bits ? 8.0 : 12.0) * (double)N +
-                         (sig ? (sig64 ? 8.0 : 4.0) * (double)N : 0.0));
+                         (sig ? 16.0 * (double)pass_pts * sig_W : 0.0));
     mark(2);
     const int where = radix_sort(keys, vals, keys_alt, vals_alt, N, idx_bits, idx_bits + key_bits,
                                  sort_scr, err, stream, &tm, RTG_K_KEY_HIST, RTG_K_KEY_SCATTER,
@@ -993,8 +1022,10 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     filt.idx_bits = idx_bits;
     if (first_owner) {
       filt.sig = sig;
-      filt.k = kmax;
-      filt.sig64 = sig64;
+      filt.W = sig_W;
+      filt.g = sig_g;
+      filt.gpw = sig_gpw;
+      filt.gmask = sig_g >= 64 ? ~0ull : ((1ull << sig_g) - 1ull);
     }
 
     // Room for this pass's pairs: a guess first, the exact count on overflow.
@@ -1018,8 +1049,10 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
       PairsArgs pa{pts_rows, d, sidx, cstart, cend, unit_cell, units, units_total, tests_d,
                    segs_d, sa, seg_bits > 0 ? idx_bits + P.layout.cell_bits : 64, filt, cand, cap,
                    counters, counters + 1};
+      pa.gram = use_gram ? 1 : 0;
       kbegin(RTG_K_PAIRS);
       launch_cell_pairs(pa, stream);
+      if (use_gram) st.matrix_screen_launches += 1;
       kend(RTG_K_PAIRS, 0.0);
       unsigned long long cnt[4] = {0, 0, 0, 0};
       if ((rc = read_back(counters, sizeof(cnt), cnt))) return rc;
@@ -1052,7 +1085,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
 
   // Key buffers are no longer needed.
   for (void* p : {(void*)keys, (void*)keys_alt, (void*)vals, (void*)vals_alt, (void*)cstart,
-                  (void*)cend, (void*)units, (void*)unit_cell, (void*)tests_c, sig})
+                  (void*)cend, (void*)units, (void*)unit_cell, (void*)tests_c, (void*)sig})
     S.drop(p);
 
   // --- union and neighbour lists ------------------------------------------------

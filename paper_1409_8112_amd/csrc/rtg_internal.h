@@ -112,8 +112,9 @@ struct KeysArgs {
   uint64_t* keys;
   uint32_t* vals;
   uint32_t* err;
-  void* sig;
-  int sig64, kmax, idx_bits;
+  uint64_t* sig;     // neighbourhood signatures (see PairFilter), or null
+  int sig_W, sig_b, sig_gpw;
+  int idx_bits;
 };
 void launch_keys(const KeysArgs& a, hipStream_t s);
 // kappa [n][d] = floor(y) for one transform (stage check).
@@ -170,10 +171,17 @@ void launch_unit_fill(const uint32_t* start, const uint32_t* end, const uint32_t
 // grid t only if no grid t' < t put both points in one cell;
 // sig[point * k + t] is a point's packed cell key under grid t (u32 or u64);
 // null sig turns the filter off.  skeys / idx_bits are always set.
+// Neighbourhood signatures for the first-owner rule.  Under grid t a point's
+// group holds the low b bits of each axis field (kappa_j - origin_j), g = d b
+// bits, at bit (t % gpw) g of word t / gpw of the point's W-word row.  For two
+// points within r every axis differs by at most 2^b - 1 cells (b is at least
+// the key packing's minimum field width), so equal groups mean equal cells.
 struct PairFilter {
-  const void* sig = nullptr;
-  int32_t k = 0;                    // sig row stride (grids of the widest instance)
-  int32_t sig64 = 0;
+  const uint64_t* sig = nullptr;    // [npts][W]; null: no first-owner rule
+  int32_t W = 0;                    // words per point
+  int32_t g = 0;                    // bits per grid (<= 64)
+  int32_t gpw = 1;                  // grids per word
+  uint64_t gmask = 0;               // (1 << g) - 1
   const uint64_t* skeys = nullptr;  // sorted keys
   int32_t idx_bits = 0;             // > 0: point index in the low bits of skeys
 };
@@ -198,6 +206,7 @@ struct PairsArgs {
   uint64_t* cand;
   uint64_t cap;
   unsigned long long *cand_count, *rechecks;
+  int gram = 0;  // 1: matrix-core screen (d <= 16), 0: vector screen
 };
 void launch_cell_pairs(const PairsArgs& a, hipStream_t s);
 

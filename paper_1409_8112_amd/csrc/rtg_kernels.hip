@@ -218,8 +218,8 @@ __global__ __launch_bounds__(kBlock) void k_keys(const InstDesc* __restrict__ in
                                                  const KeyLayout* __restrict__ layout,
                                                  uint64_t* __restrict__ keys,
                                                  uint32_t* __restrict__ vals, uint32_t* err,
-                                                 void* __restrict__ sig, int sig64, int kmax,
-                                                 int idx_bits) {
+                                                 uint64_t* __restrict__ sig, int sig_W,
+                                                 int sig_b, int sig_gpw, int idx_bits) {
   const int d = D > 0 ? D : d_rt;
   const uint32_t q = block_instance(inst, m, blockIdx.x);
   const int64_t i = (int64_t)(blockIdx.x - (uint32_t)inst[q].blk_first) * kBlock + threadIdx.x;
@@ -234,6 +234,10 @@ __global__ __launch_bounds__(kBlock) void k_keys(const InstDesc* __restrict__ in
     for (int l = 0; l < (D > 0 ? D : 1); ++l) p[l] = soa[(int64_t)l * npts + g];
   }
   const int cell_bits = layout->cell_bits;
+  const uint64_t bmask = (1ull << sig_b) - 1ull;
+  const int gbits = d * sig_b;
+  uint64_t sword = 0;  // signature word being filled
+  int sw = -1;         // its index
   bool bad = false;
   for (int t = t_lo; t < t_hi; ++t) {
     const int s = seg_first + t;
@@ -241,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(const InstDesc* __restrict__ in
     const double* Rt = R + (size_t)tr * d * d;
     const double* ut = u + (size_t)tr * d;
     const int64_t* kl = klo + (size_t)tr * d;
-    uint64_t cell = 0;
+    uint64_t cell = 0, grp = 0;
     for (int j = 0; j < d; ++j) {
       double y = cell_y<D>(Rt + (size_t)j * d, p, soa, npts, g, d, inv_c, ut[j]);
       bool ok = fabs(y) < 2147483648.0;
@@ -249,10 +253,17 @@ __global__ __launch_bounds__(kBlock) void k_keys(const InstDesc* __restrict__ in
       int64_t kap = ok ? (int64_t)floor(y) : 0;
       uint64_t mask = (1ull << layout->bits[j]) - 1ull;
       cell |= ((uint64_t)(kap - kl[j]) & mask) << layout->shift[j];
+      grp |= ((uint64_t)(kap - kl[j]) & bmask) << (j * sig_b);
     }
     if (sig) {
-      if (sig64) static_cast<uint64_t*>(sig)[(size_t)g * kmax + t] = cell;
-      else static_cast<uint32_t*>(sig)[(size_t)g * kmax + t] = (uint32_t)cell;
+      // the point owns its row: earlier passes' bits are read back and kept
+      const int w = t / sig_gpw;
+      if (w != sw) {
+        if (sw >= 0) sig[(size_t)g * sig_W + sw] |= sword;
+        sword = 0;
+        sw = w;
+      }
+      sword |= grp << ((t - w * sig_gpw) * gbits);
     }
     const uint64_t key = (cell_bits < 64) ? (((uint64_t)(s - sa) << cell_bits) | cell) : cell;
     const int64_t pos = segs[s].key_off + i;
@@ -263,6 +274,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(const InstDesc* __restrict__ in
       vals[pos] = (uint32_t)g;
     }
   }
+  if (sig && sw >= 0) sig[(size_t)g * sig_W + sw] |= sword;
   if (bad) atomicOr(err, 1u);
 }
 
@@ -758,8 +770,24 @@ __global__ __launch_bounds__(kBlock) void k_unique_write(const uint64_t* __restr
 // compared in chunks of kSigChunk grids, tile a's in registers and tile b's
 // in LDS.  Kept pairs are written as (min << b) | max.
 
-constexpr int kSigChunk = 8;
-constexpr int kOutBuf = 512;  // staged pairs per wave
+constexpr int kSigWords = 4;  // signature words staged per chunk
+constexpr int kOutBuf = 256;  // staged pairs per wave
+
+// Whether two points within r shared a cell under some grid t < tcell whose
+// signature group lies in the staged words w0 .. w0 + wn - 1 (a[q], b[q]).
+__device__ __forceinline__ bool shared_earlier_cell(const uint64_t* a, const uint64_t* b, int w0,
+                                                    int wn, int tcell, const PairFilter& F) {
+  bool same = false;
+#pragma unroll
+  for (int q = 0; q < kSigWords; ++q) {
+    if (q < wn) {
+      const uint64_t x = a[q] ^ b[q];
+      const int tn = min(F.gpw, tcell - (w0 + q) * F.gpw);
+      for (int z = 0; z < tn; ++z) same |= ((x >> (z * F.g)) & F.gmask) == 0ull;
+    }
+  }
+  return same;
+}
 
 // Point index at sorted position p: the low idx_bits of the sorted key
 // when keys carry it, else the separate index array.
@@ -773,7 +801,7 @@ __device__ __forceinline__ T uniform(T v) {
   return (T)__builtin_amdgcn_readfirstlane((int)v);
 }
 
-template <int D, bool SIG64>
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_cell_pairs(
     const float* __restrict__ pts, int d, const uint32_t* __restrict__ sidx,
     const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend,
@@ -781,17 +809,16 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs(
     uint32_t total_units, const PairTest* __restrict__ tests, const SegDesc* __restrict__ segs,
     int sa, int seg_shift, PairFilter F, uint64_t* __restrict__ cand, uint64_t cap,
     unsigned long long* cand_count, unsigned long long* rechecks) {
-  using Sig = typename std::conditional<SIG64, uint64_t, uint32_t>::type;
   // LDS row stride: rows of 4 floats read with 128-bit loads
   constexpr int DP = D <= 2 ? D : ((D + 3) / 4) * 4;
   __shared__ __attribute__((aligned(16))) float sB[kWaves][kPairTile][DP];
   __shared__ uint32_t sBi[kWaves][kPairTile];
-  __shared__ __attribute__((aligned(16))) Sig sBs[kWaves][kPairTile][kSigChunk];
+  __shared__ uint64_t sBw[kWaves][kSigWords][kPairTile];
   __shared__ uint64_t sOut[kWaves][kOutBuf];
 
   const uint32_t lane = lane_id();
   const int w = threadIdx.x >> 6;
-  const Sig* sig = static_cast<const Sig*>(F.sig);
+  const uint64_t* sig = F.sig;
   unsigned long long nre = 0;
   uint32_t outn = 0;  // pairs staged in sOut[w] (wave-uniform)
 
@@ -904,27 +931,28 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs(
 
       // First owner: drop a pair that an earlier grid put in one cell.
       if (sig && tcell > 0 && ballot(acc != 0ull)) {
-        for (int q0 = 0; q0 < tcell; q0 += kSigChunk) {
-          const int qn = min(kSigChunk, tcell - q0);
-          Sig sa[kSigChunk];
+        const int nw = (tcell - 1) / F.gpw + 1;  // words holding grids < tcell
+        for (int w0 = 0; w0 < nw; w0 += kSigWords) {
+          const int wn = min(kSigWords, nw - w0);
+          uint64_t aw[kSigWords];
 #pragma unroll
-          for (int q = 0; q < kSigChunk; ++q)
-            sa[q] = (rowok && q < qn) ? sig[(size_t)ai * F.k + q0 + q] : (Sig)0;
+          for (int q = 0; q < kSigWords; ++q)
+            aw[q] = (rowok && q < wn) ? sig[(size_t)ai * F.W + w0 + q] : 0ull;
           wave_lds_sync();
           if (lane < nB) {
 #pragma unroll
-            for (int q = 0; q < kSigChunk; ++q)
-              sBs[w][lane][q] = (q < qn) ? sig[(size_t)bi * F.k + q0 + q] : (Sig)0;
+            for (int q = 0; q < kSigWords; ++q)
+              sBw[w][q][lane] = (q < wn) ? sig[(size_t)bi * F.W + w0 + q] : 0ull;
           }
           wave_lds_sync();
           uint64_t m = acc;
           while (m) {
             const int j = __builtin_ctzll(m);
             m &= m - 1;
-            bool same = false;
+            uint64_t bw[kSigWords];
 #pragma unroll
-            for (int q = 0; q < kSigChunk; ++q) same |= (q < qn) && sa[q] == sBs[w][j][q];
-            if (same) acc &= ~(1ull << j);
+            for (int q = 0; q < kSigWords; ++q) bw[q] = sBw[w][q][j];
+            if (shared_earlier_cell(aw, bw, w0, wn, tcell, F)) acc &= ~(1ull << j);
           }
         }
       }
@@ -956,6 +984,319 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs(
             const uint64_t bj = sBi[w][j];
             const uint64_t lo = min((uint64_t)ai, bj), hi = max((uint64_t)ai, bj);
             sOut[w][pos++] = (lo << T.pair_bits) | hi;
+          }
+          outn += total;
+        }
+      }
+    }
+  }
+  flush();
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) nre += __shfl_xor(nre, o, 64);
+  if (lane == 0 && nre) atomicAdd(rechecks, nre);
+}
+
+// ---------------------------------------------------------------------------
+// cell pairs on the matrix cores.  Same units, filter and output as
+// k_cell_pairs, but the squared distances of a 64 x 64 tile pair come from
+// Gram blocks.  With the cell's first point o as origin, a' = a - o and
+// b' = b - o in FP32; the rows [a', |a'|^2, 1] and [-2 b', 1, |b'|^2] have
+// dot product |a'|^2 + |b'|^2 - 2 a'.b' = |a' - b'|^2, and
+// v_mfma_f32_32x32x2f32 accumulates 32 x 32 of them over K/2 steps.
+//
+// The screen accepts v <= lo and rejects v > hi, lo and hi = r^2 -/+ E,
+// where E bounds |v - s| for s the FP64 squared distance of the definition:
+// recursive-summation bounds for the K products and sums of the expansion
+// and for the norms, the rounding of a - o and of r^2 to FP32, all
+// proportional to S = max |a'|^2 + max |b'|^2 over the tile pair, with a
+// factor 1.5 to spare.  E is set per tile pair, so it widens by itself when
+// a cell's points lie far apart (aliased keys, very large cells): the screen
+// stays exact and only sends more pairs to FP64.  Pairs with v in between
+// (or NaN) are decided in FP64 from the original coordinates.
+
+// v_mfma_f32_32x32x2f32 lane layout: lane l supplies A[l % 32][l / 32] and
+// B[l / 32][l % 32]; result register i of lane l holds D[row][l % 32] with
+// row = 8 (i / 4) + 4 (l / 32) + i % 4.
+__device__ __forceinline__ uint32_t mfma32_row(uint32_t i, uint32_t lane) {
+  return 8u * (i >> 2) + 4u * (lane >> 5) + (i & 3u);
+}
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_cell_pairs_gram(
+    const float* __restrict__ pts, const uint32_t* __restrict__ sidx,
+    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend,
+    const uint32_t* __restrict__ unit_cell, const uint32_t* __restrict__ unit_off,
+    uint32_t total_units, const PairTest* __restrict__ tests, const SegDesc* __restrict__ segs,
+    int sa, int seg_shift, PairFilter F, uint64_t* __restrict__ cand, uint64_t cap,
+    unsigned long long* cand_count, unsigned long long* rechecks) {
+  constexpr int KA = (D + 3) & ~1;  // augmented row length, even
+  constexpr int KS = KA / 2;        // MFMA steps per block
+  constexpr int KP = KA + 1;        // LDS row stride, odd: conflict-free column reads
+  constexpr float kU = 0x1p-24f;
+  constexpr float kGain = 1.5f * (float)(2 * KA + D + 8) * kU;
+  // A tile rows, then (once they are in registers) A signature words; the
+  // same for B.
+  constexpr int kRegion = (kPairTile * KP > 2 * kSigWords * kPairTile) ? kPairTile * KP
+                                                                       : 2 * kSigWords * kPairTile;
+  __shared__ __attribute__((aligned(16))) float sAreg[kWaves][kRegion];
+  __shared__ __attribute__((aligned(16))) float sBreg[kWaves][kRegion];
+  __shared__ uint32_t sAi[kWaves][kPairTile];
+  __shared__ uint32_t sBi[kWaves][kPairTile];
+  __shared__ uint64_t sOut[kWaves][kOutBuf];
+
+  const uint32_t lane = lane_id();
+  const uint32_t l32 = lane & 31u, h = lane >> 5;
+  const int w = threadIdx.x >> 6;
+  const uint64_t* sig = F.sig;
+  float (*sA)[KP] = reinterpret_cast<float (*)[KP]>(sAreg[w]);
+  float (*sB)[KP] = reinterpret_cast<float (*)[KP]>(sBreg[w]);
+  uint64_t (*sAw)[kPairTile] = reinterpret_cast<uint64_t (*)[kPairTile]>(sAreg[w]);
+  uint64_t (*sBw)[kPairTile] = reinterpret_cast<uint64_t (*)[kPairTile]>(sBreg[w]);
+  unsigned long long nre = 0;
+  uint32_t outn = 0;
+
+  auto flush = [&]() {
+    wave_lds_sync();
+    if (outn) {
+      unsigned long long base = 0;
+      if (lane == 0) base = atomicAdd(cand_count, (unsigned long long)outn);
+      base = __shfl(base, 0, 64);
+      for (uint32_t e = lane; e < outn; e += 64) {
+        const uint64_t g = base + e;
+        if (g < cap) cand[g] = sOut[w][e];
+      }
+      outn = 0;
+    }
+    wave_lds_sync();
+  };
+
+  const uint32_t wave_id = blockIdx.x * kWaves + w;
+  const uint32_t nwaves = gridDim.x * kWaves;
+  for (uint32_t u = wave_id; u < total_units; u += nwaves) {
+    const uint32_t c = uniform(unit_cell[u]);
+    const uint32_t ta = u - uniform(unit_off[c]);
+    const uint32_t s0 = uniform(cstart[c]);
+    const uint32_t L = uniform(cend[c]) - s0;
+    const uint32_t nt = (L + kPairTile - 1) / kPairTile;
+    const uint32_t nA = min((uint32_t)kPairTile, L - ta * kPairTile);
+    const int seg =
+        sa + (seg_shift >= 64 ? 0 : (int)uniform((uint32_t)(F.skeys[s0] >> seg_shift)));
+    const int tcell = uniform(segs[seg].t);
+    const PairTest T = tests[uniform(segs[seg].inst)];
+    const float r2f = (float)T.r2;
+
+    // origin: the cell's first point
+    const uint32_t oi = uniform(point_at(sidx, F, s0));
+    float o[D];
+#pragma unroll
+    for (int l = 0; l < D; ++l) o[l] = pts[(size_t)oi * D + l];
+
+    // tile a: centred rows, norms; invalid rows get a huge norm (rejected)
+    wave_lds_sync();
+    float na = 0.0f;
+    {
+      uint32_t ai = 0;
+      float row[KA];
+      if (lane < nA) {
+        ai = point_at(sidx, F, s0 + ta * kPairTile + lane);
+        float n2 = 0.0f;
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+          const float v = pts[(size_t)ai * D + l] - o[l];
+          row[l] = v;
+          n2 = __builtin_fmaf(v, v, n2);
+        }
+        row[D] = n2;
+        na = n2;
+      } else {
+#pragma unroll
+        for (int l = 0; l < D; ++l) row[l] = 0.0f;
+        row[D] = 1e30f;
+      }
+      row[D + 1] = 1.0f;
+#pragma unroll
+      for (int l = D + 2; l < KA; ++l) row[l] = 0.0f;
+      sAi[w][lane] = ai;
+#pragma unroll
+      for (int l = 0; l < KA; ++l) sA[lane][l] = row[l];
+    }
+    const float amax = wave_max_f(na);
+    wave_lds_sync();
+    float areg[2][KS];
+#pragma unroll
+    for (int R = 0; R < 2; ++R)
+#pragma unroll
+      for (int q = 0; q < KS; ++q) areg[R][q] = sA[32 * R + l32][2 * q + h];
+
+    for (uint32_t tb = ta; tb < nt; ++tb) {
+      const uint32_t nB = min((uint32_t)kPairTile, L - tb * kPairTile);
+      wave_lds_sync();
+      float nb = 0.0f;
+      {
+        uint32_t bi = 0;
+        float row[KA];
+        if (lane < nB) {
+          bi = point_at(sidx, F, s0 + tb * kPairTile + lane);
+          float n2 = 0.0f;
+#pragma unroll
+          for (int l = 0; l < D; ++l) {
+            const float v = pts[(size_t)bi * D + l] - o[l];
+            row[l] = -2.0f * v;
+            n2 = __builtin_fmaf(v, v, n2);
+          }
+          row[D + 1] = n2;
+          nb = n2;
+        } else {
+#pragma unroll
+          for (int l = 0; l < D; ++l) row[l] = 0.0f;
+          row[D + 1] = 1e30f;
+        }
+        row[D] = 1.0f;
+#pragma unroll
+        for (int l = D + 2; l < KA; ++l) row[l] = 0.0f;
+        sBi[w][lane] = bi;
+#pragma unroll
+        for (int l = 0; l < KA; ++l) sB[lane][l] = row[l];
+      }
+      const float bmax = wave_max_f(nb);
+      wave_lds_sync();
+
+      // the tile pair's band
+      const float E = (amax + bmax) * kGain + r2f * (4.0f * kU) + 1e-36f;
+      const float lo = (E < r2f) ? (r2f - E) * (1.0f - 0x1p-20f) : -INFINITY;
+      const float hi = (r2f + E) * (1.0f + 0x1p-20f);
+
+      float breg[2][KS];
+#pragma unroll
+      for (int C = 0; C < 2; ++C)
+#pragma unroll
+        for (int q = 0; q < KS; ++q) breg[C][q] = sB[32 * C + l32][2 * q + h];
+
+      const bool diag = (ta == tb);
+      uint64_t acc = 0ull, band = 0ull;
+#pragma unroll
+      for (int R = 0; R < 2; ++R) {
+        if (R == 1 && nA <= 32u) break;
+#pragma unroll
+        for (int C = 0; C < 2; ++C) {
+          if (C == 1 && nB <= 32u) break;
+          floatx16 v = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f,
+                        0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+          for (int q = 0; q < KS; ++q)
+            v = __builtin_amdgcn_mfma_f32_32x32x2f32(areg[R][q], breg[C][q], v, 0, 0, 0);
+          uint32_t am = 0u, rm = 0u;
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            am |= (uint32_t)(v[i] <= lo) << i;
+            rm |= (uint32_t)(v[i] > hi) << i;
+          }
+          uint32_t valid = 0xFFFFu;
+          if (diag) {
+            // row < col: a prefix of the 16 registers (rows rise with i)
+            const int x = (int)(32 * C + l32) - 32 * R - 4 * (int)h;
+            int cnt = 0;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) cnt += min(max(x - 8 * g, 0), 4);
+            valid = (1u << cnt) - 1u;
+          }
+          const int sh = (R * 2 + C) * 16;
+          acc |= (uint64_t)(am & valid) << sh;
+          band |= (uint64_t)(~(am | rm) & valid) << sh;
+        }
+      }
+
+      // Band: decide in FP64 exactly as the definition does.
+      while (band) {
+        const int b = __builtin_ctzll(band);
+        band &= band - 1;
+        const uint32_t row = 32u * ((uint32_t)b >> 5) + mfma32_row((uint32_t)b & 15u, lane);
+        const uint32_t col = 32u * (((uint32_t)b >> 4) & 1u) + l32;
+        const uint32_t pa = sAi[w][row], pb = sBi[w][col];
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+          const double dl = (double)pts[(size_t)pa * D + l] - (double)pts[(size_t)pb * D + l];
+          s = s + dl * dl;
+        }
+        if (s <= T.r2) acc |= 1ull << b;
+        ++nre;
+      }
+
+      // First owner: drop a pair that an earlier grid put in one cell.  The
+      // tile rows in LDS are in registers by now; their space takes the
+      // signature words.
+      if (sig && tcell > 0 && ballot(acc != 0ull)) {
+        const int nw = (tcell - 1) / F.gpw + 1;  // words holding grids < tcell
+        for (int w0 = 0; w0 < nw; w0 += kSigWords) {
+          const int wn = min(kSigWords, nw - w0);
+          wave_lds_sync();
+          if (lane < nA) {
+            const size_t ra = (size_t)sAi[w][lane] * F.W + w0;
+#pragma unroll
+            for (int q = 0; q < kSigWords; ++q) sAw[q][lane] = (q < wn) ? sig[ra + q] : 0ull;
+          }
+          if (lane < nB) {
+            const size_t rb = (size_t)sBi[w][lane] * F.W + w0;
+#pragma unroll
+            for (int q = 0; q < kSigWords; ++q) sBw[q][lane] = (q < wn) ? sig[rb + q] : 0ull;
+          }
+          wave_lds_sync();
+          uint64_t m = acc;
+          while (m) {
+            const int b = __builtin_ctzll(m);
+            m &= m - 1;
+            const uint32_t row = 32u * ((uint32_t)b >> 5) + mfma32_row((uint32_t)b & 15u, lane);
+            const uint32_t col = 32u * (((uint32_t)b >> 4) & 1u) + l32;
+            uint64_t aw[kSigWords], bw[kSigWords];
+#pragma unroll
+            for (int q = 0; q < kSigWords; ++q) {
+              aw[q] = sAw[q][row];
+              bw[q] = sBw[q][col];
+            }
+            if (shared_earlier_cell(aw, bw, w0, wn, tcell, F)) acc &= ~(1ull << b);
+          }
+        }
+      }
+
+      const uint32_t cnt = (uint32_t)__popcll(acc);
+      const uint32_t incl = wave_inclusive_scan(cnt);
+      const uint32_t total = uniform(__shfl(incl, 63, 64));
+      if (total) {
+        if (outn + total > (uint32_t)kOutBuf) flush();
+        if (total > (uint32_t)kOutBuf) {
+          unsigned long long base = 0;
+          if (lane == 0) base = atomicAdd(cand_count, (unsigned long long)total);
+          base = __shfl(base, 0, 64);
+          uint64_t pos = base + incl - cnt;
+          while (acc) {
+            const int b = __builtin_ctzll(acc);
+            acc &= acc - 1;
+            const uint32_t row = 32u * ((uint32_t)b >> 5) + mfma32_row((uint32_t)b & 15u, lane);
+            const uint32_t col = 32u * (((uint32_t)b >> 4) & 1u) + l32;
+            const uint64_t x = sAi[w][row], y = sBi[w][col];
+            const uint64_t lo_i = min(x, y), hi_i = max(x, y);
+            if (pos < cap) cand[pos] = (lo_i << T.pair_bits) | hi_i;
+            ++pos;
+          }
+        } else {
+          uint32_t pos = outn + incl - cnt;
+          while (acc) {
+            const int b = __builtin_ctzll(acc);
+            acc &= acc - 1;
+            const uint32_t row = 32u * ((uint32_t)b >> 5) + mfma32_row((uint32_t)b & 15u, lane);
+            const uint32_t col = 32u * (((uint32_t)b >> 4) & 1u) + l32;
+            const uint64_t x = sAi[w][row], y = sBi[w][col];
+            const uint64_t lo_i = min(x, y), hi_i = max(x, y);
+            sOut[w][pos++] = (lo_i << T.pair_bits) | hi_i;
           }
           outn += total;
         }
@@ -1335,7 +1676,7 @@ template <int D>
 static void keys_dispatch(const KeysArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_keys<D>, dim3(a.nblocks), dim3(kBlock), 0, s, a.inst, a.m, a.d, a.npts,
                      a.soa, a.sa, a.sb, a.segs, a.R, a.u, a.klo, a.layout, a.keys, a.vals, a.err,
-                     a.sig, a.sig64, a.kmax, a.idx_bits);
+                     a.sig, a.sig_W, a.sig_b, a.sig_gpw, a.idx_bits);
 }
 
 void launch_keys(const KeysArgs& a, hipStream_t s) {
@@ -1543,16 +1884,19 @@ static void pairs_dispatch(const PairsArgs& a, hipStream_t s) {
   const uint64_t max_blocks = 256ull * 8ull;  // 256 CUs, several resident blocks each
   if (blocks > max_blocks) blocks = max_blocks;
   if (blocks < 1) blocks = 1;
-  if (a.filter.sig64)
-    hipLaunchKernelGGL((k_cell_pairs<D, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a.pts,
-                       a.d, a.sidx, a.start, a.end, a.unit_cell, a.unit_off, a.total_units, a.tests,
-                       a.segs, a.sa, a.seg_shift, a.filter, a.cand, a.cap, a.cand_count,
-                       a.rechecks);
-  else
-    hipLaunchKernelGGL((k_cell_pairs<D, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a.pts,
-                       a.d, a.sidx, a.start, a.end, a.unit_cell, a.unit_off, a.total_units, a.tests,
-                       a.segs, a.sa, a.seg_shift, a.filter, a.cand, a.cap, a.cand_count,
-                       a.rechecks);
+  if constexpr (D <= 16) {
+    if (a.gram && a.d == D) {
+      hipLaunchKernelGGL((k_cell_pairs_gram<D>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                         a.pts, a.sidx, a.start, a.end, a.unit_cell, a.unit_off, a.total_units,
+                         a.tests, a.segs, a.sa, a.seg_shift, a.filter, a.cand, a.cap,
+                         a.cand_count, a.rechecks);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_cell_pairs<D>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a.pts, a.d,
+                     a.sidx, a.start, a.end, a.unit_cell, a.unit_off, a.total_units, a.tests,
+                     a.segs, a.sa, a.seg_shift, a.filter, a.cand, a.cap, a.cand_count,
+                     a.rechecks);
 }
 
 void launch_cell_pairs(const PairsArgs& a, hipStream_t s) {

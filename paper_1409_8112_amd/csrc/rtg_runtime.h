@@ -138,6 +138,7 @@ struct Ctx {
   uint32_t bucket_cap = rtgk::kBucketMaxEntries;  // entries per LDS-sorted bucket
   int64_t batch_points = kBatchPoints;             // points per batch
   int server_lanes = 2;  // passes of the request loop that may run at once
+  int pair_screen = 0;   // 0 auto, 1 vector, 2 matrix cores (d <= 16)
   Lane main;          // the caller's stream: blocking calls
   rtg_stats stats{};  // of the last blocking call
   std::mutex mu;      // one blocking call at a time

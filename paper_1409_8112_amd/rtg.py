@@ -61,7 +61,8 @@ class rtg_stats(ctypes.Structure):
         ("kernel_launches", ctypes.c_int64 * NKERNELS),
         ("kernel_bytes", ctypes.c_double * NKERNELS),
         ("kernel_ms", ctypes.c_double * NKERNELS),
-        ("served_requests", ctypes.c_int64), ("served_batches", ctypes.c_int64)]
+        ("served_requests", ctypes.c_int64), ("served_batches", ctypes.c_int64),
+        ("matrix_screen_launches", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         out = {}

@@ -69,3 +69,36 @@ def test_binding_refuses_to_run_without_a_gpu():
         pytest.skip("a GPU is visible")
     with pytest.raises(RuntimeError):
         rtg.Context()
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of rtg_csr, rtg_query and rtg_stats have the C
+    layout of include/rtg.h (sizes and field offsets, compiled with gcc)."""
+    import shutil
+    import subprocess
+    from paper_1409_8112_amd import rtg
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    fields = {"rtg_csr": [f for f, _ in rtg.rtg_csr._fields_],
+              "rtg_query": [f for f, _ in rtg.rtg_query._fields_],
+              "rtg_stats": [f for f, _ in rtg.rtg_stats._fields_]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rtg.h"', "int main(void) {"]
+    for st, fs in fields.items():
+        lines.append(f'  printf("{st} %zu\\n", sizeof({st}));')
+        for f in fs:
+            lines.append(f'  printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(root, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True,
+                                                        capture_output=True,
+                                                        text=True).stdout.splitlines())
+    for st, fs in fields.items():
+        cls = getattr(rtg, st)
+        assert int(got[st]) == ctypes.sizeof(cls), st
+        for f in fs:
+            assert int(got[f"{st}.{f}"]) == getattr(cls, f).offset, f"{st}.{f}"

@@ -374,3 +374,27 @@ def test_full_size_uniform_d6_sampled(ctx):
 
 def test_full_size_clustered_d12_sampled(ctx):
     _check_full(ctx, workloads.skewed_clustered_d12(), 48)
+
+
+def test_too_few_key_bits_is_out_of_range(ctx):
+    """d = 40 with alpha = 0.6 needs 2 bits per axis to keep aliased cells
+    apart (80 > 64 bits): the library refuses with RTG_ERANGE, as declared,
+    rather than report pairs from keys that could not separate cells."""
+    from paper_1409_8112_amd import rtg
+    _say("too few key bits d=40 alpha=0.6")
+    p = workloads.clustered_points(3000, 40, seed=12, n_clusters=6, sigma=0.04)
+    with pytest.raises(rtg.RTGError) as e:
+        _gpu(ctx, p, 0.35, 5, 0.6, 2)
+    assert e.value.code == rtg.ERANGE
+
+
+@pytest.mark.parametrize("alpha", [0.8, 1.0, 1.02, 3.0])
+def test_signature_widths(ctx, alpha):
+    """alpha below ~1 needs 2 signature bits per axis, above 1.01 one bit."""
+    _say(f"signature widths alpha={alpha}")
+    d, n = 5, 4000
+    p = workloads.uniform_points(n, d, seed=int(alpha * 100))
+    r = workloads.calibrate_radius_uniform(n, d, 12.0)
+    ref = oracle.rtg(p, r, 7, alpha, 9)
+    rp, col = _gpu(ctx, p, r, 7, alpha, 9)
+    _assert_same(rp, col, ref)

@@ -1,0 +1,142 @@
+"""Both pair screens, forced: the vector screen (FP32 differences on the
+vector units) and the matrix-core screen (FP32 Gram blocks with a per-tile
+error band), each bit-exact to the oracle on the cases that stress them:
+ragged tiles, every d it serves, one huge cell, coincident points, pairs
+at r exactly and one ulp either side, aliased keys, clustered cells."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1409_8112_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["vector", "matrix"]
+
+
+@pytest.fixture(scope="module", params=MODES)
+def screen(request):
+    import torch
+    from paper_1409_8112_amd import rtg
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    old = os.environ.get("RTG_PAIRS")
+    os.environ["RTG_PAIRS"] = request.param
+    try:
+        c = rtg.Context(0, arena_bytes=8 << 30)
+    finally:
+        if old is None:
+            del os.environ["RTG_PAIRS"]
+        else:
+            os.environ["RTG_PAIRS"] = old
+    yield request.param, c
+    c.close()
+
+
+def _dev(p):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(p, dtype=np.float32)).cuda()
+
+
+def _check(mode, ctx, res, ref):
+    rp, col = res.to_numpy()
+    res.release()
+    assert np.array_equal(rp, ref.row_ptr) and np.array_equal(col, ref.col)
+    st = ctx.stats()
+    if st["tests"] > 0 and st["d"] <= 16:
+        used = st["matrix_screen_launches"] > 0
+        assert used == (mode == "matrix"), st["matrix_screen_launches"]
+
+
+def _run(screen, p, r, k, alpha, seed, flags=0):
+    mode, ctx = screen
+    print(f"screen {mode}: n={len(p)} d={p.shape[1]} r={r} k={k} alpha={alpha}", flush=True)
+    res = ctx.all_pairs(_dev(p), r, k, alpha, seed, flags)
+    _check(mode, ctx, res, oracle.rtg(p, r, k, alpha, seed, flags & 3))
+
+
+def test_small_uniform_d3_all_flags(screen):
+    from paper_1409_8112_amd import rtg
+    wl = workloads.small_uniform_d3()
+    p = wl.points()
+    for flags in (0, rtg.NO_ROTATE, rtg.UPPER_ONLY, rtg.DEDUP_SORT):
+        _run(screen, p, wl.r, wl.k, wl.alpha, wl.seed, flags)
+
+
+@pytest.mark.parametrize("n", [2, 31, 32, 33, 64, 65, 97, 130, 4097])
+def test_ragged_tiles(screen, n):
+    p = workloads.uniform_points(n, 5, seed=n)
+    _run(screen, p, 0.9 * (8.0 / max(n, 8)) ** (1 / 5), 3, 2.0, n)
+
+
+@pytest.mark.parametrize("d", list(range(1, 17)))
+def test_dimensions(screen, d):
+    n = 2500
+    p = workloads.uniform_points(n, d, seed=300 + d)
+    _run(screen, p, workloads.calibrate_radius_uniform(n, d, 12.0), 4, 2.0, d)
+
+
+def test_clustered_cells(screen):
+    p = workloads.clustered_points(12000, 12, seed=6)
+    _run(screen, p, 0.04, 6, 2.0, 1)
+
+
+def test_one_huge_cell(screen):
+    mode, ctx = screen
+    n, d, r = 1500, 3, 0.08
+    p = workloads.uniform_points(n, d, seed=19)
+    R, u = oracle.make_transforms(0, 64, d)
+    t = next(t for t in range(64) if np.all((u[t] > 0.01) & (u[t] < 0.99)))
+    res = ctx.all_pairs_with_transforms(_dev(p), r, 1e4, R[t:t + 1], u[t:t + 1])
+    _check(mode, ctx, res, oracle.bruteforce(p, r))
+
+
+def test_coincident_points(screen):
+    p = np.repeat(workloads.uniform_points(40, 4, seed=2), 9, axis=0)
+    _run(screen, p, 0.05, 3, 2.0, 5)
+
+
+def test_pairs_at_r_and_one_ulp_either_side(screen):
+    mode, ctx = screen
+    rng = np.random.default_rng(17)
+    r = 0.3125
+    gx, gy = np.meshgrid(np.arange(16), np.arange(16))
+    base = np.stack([gx.ravel(), gy.ravel()], axis=1).astype(np.float32)
+    q = base + np.array([3 * 0.0625, 4 * 0.0625], dtype=np.float32)
+    steps = rng.integers(-1, 2, size=q.shape)
+    q = np.where(steps > 0, np.nextafter(q, np.float32(np.inf)),
+                 np.where(steps < 0, np.nextafter(q, np.float32(-np.inf)), q)).astype(np.float32)
+    p = np.concatenate([base, q]).astype(np.float32)
+    R, u = oracle.make_transforms(11, 4, 2, oracle.NO_ROTATE)
+    # alpha 3: every (base, q) pair shares a cell under some grid
+    res = ctx.all_pairs_with_transforms(_dev(p), r, 3.0, R, u)
+    ref = oracle.rtg_with_transforms(p, r, 3.0, R, u)
+    assert len(ref.col) > 0
+    _check(mode, ctx, res, ref)
+    assert ctx.stats()["band_rechecks"] > 0
+
+
+def test_aliased_keys(screen):
+    mode, ctx = screen
+    d, n, r, alpha = 12, 5000, 0.5, 2.0
+    rng = np.random.default_rng(4)
+    p = (rng.random((n, d)) * 400.0).astype(np.float32)
+    twins = p[:200].copy()
+    twins[:, 0] += np.float32(32 * alpha * r)
+    near = p[:300].copy()
+    near[:, 3] += np.float32(0.3 * r)
+    p = np.concatenate([p, twins, near]).astype(np.float32)
+    R, u = oracle.make_transforms(8, 4, d, oracle.NO_ROTATE)
+    res = ctx.all_pairs_with_transforms(_dev(p), r, alpha, R, u)
+    ref = oracle.rtg_with_transforms(p, r, alpha, R, u)
+    assert len(ref.col) > 0
+    _check(mode, ctx, res, ref)
+
+
+def test_far_from_origin(screen):
+    """Coordinates near 1e4 with r ~ 1e-2: the centred Gram form must not
+    lose the small differences to the large absolute values."""
+    p = (1e4 + workloads.uniform_points(3000, 6, seed=8)).astype(np.float32)
+    _run(screen, p, 0.25, 4, 2.0, 3)
