@@ -21,8 +21,10 @@ HEADERS = [os.path.join(CSRC, f) for f in ("rtg_internal.h", "rtg_runtime.h")] +
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall",
-         "-Wno-unused-result", "-pthread"]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # matrix-core results straight into VGPRs (no accumulator-register reads)
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1",
+         "-Wall", "-Wno-unused-result", "-Wno-pass-failed", "-pthread"]
 
 
 def build(verbose: bool = False) -> str:

@@ -947,10 +947,16 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   uint64_t* cand = nullptr;
   uint64_t cand_total = 0;  // exact number of candidates so far
 
-  // Pair screen: matrix cores when every instance suits them.
-  bool use_gram = ctx->pair_screen != 1;
+  // Pair screen: matrix cores when every instance suits them.  Their Gram
+  // form squares and sums coordinates, so it needs |coordinate| <= 2^60
+  // (no FP32 overflow for d <= 16); the vector screen takes the rest.
+  bool coords_small = true;
+  for (size_t e = 0; e < (size_t)m * d; ++e)
+    coords_small = coords_small && std::fabs(decode_order(hb[2 * e])) <= 0x1p60f &&
+                   std::fabs(decode_order(hb[2 * e + 1])) <= 0x1p60f;
+  bool use_gram = ctx->pair_screen != 1 && coords_small;
   for (uint32_t q = 0; q < m && use_gram; ++q) use_gram = gram_suits(d, jobs[q]->alpha);
-  if (ctx->pair_screen == 2) use_gram = d <= 16;
+  if (ctx->pair_screen == 2) use_gram = d <= 16 && coords_small;
 
   for (int32_t sa = 0; sa < S_total; sa += P.tb) {
     const int32_t sb = std::min(S_total, sa + P.tb);
@@ -1025,7 +1031,10 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
       filt.W = sig_W;
       filt.g = sig_g;
       filt.gpw = sig_gpw;
-      filt.gmask = sig_g >= 64 ? ~0ull : ((1ull << sig_g) - 1ull);
+      for (int z = 0; z < sig_gpw; ++z) {
+        filt.lows |= 1ull << (z * sig_g);
+        filt.highs |= 1ull << (z * sig_g + sig_g - 1);
+      }
     }
 
     // Room for this pass's pairs: a guess first, the exact count on overflow.

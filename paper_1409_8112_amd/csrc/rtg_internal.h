@@ -181,7 +181,7 @@ struct PairFilter {
   int32_t W = 0;                    // words per point
   int32_t g = 0;                    // bits per grid (<= 64)
   int32_t gpw = 1;                  // grids per word
-  uint64_t gmask = 0;               // (1 << g) - 1
+  uint64_t lows = 0, highs = 0;     // lowest and highest bit of each group
   const uint64_t* skeys = nullptr;  // sorted keys
   int32_t idx_bits = 0;             // > 0: point index in the low bits of skeys
 };

@@ -774,7 +774,11 @@ constexpr int kSigWords = 4;  // signature words staged per chunk
 constexpr int kOutBuf = 256;  // staged pairs per wave
 
 // Whether two points within r shared a cell under some grid t < tcell whose
-// signature group lies in the staged words w0 .. w0 + wn - 1 (a[q], b[q]).
+// signature group lies in the staged words w0 .. w0 + wn - 1 (a[q], b[q]):
+// whether x = a ^ b has an all-zero group among those grids.  With L the
+// lowest and H the highest bit of every group, (x - L) & ~x & H is nonzero
+// exactly when some group of x is zero; a borrow only runs upward, out of a
+// zero group, so masking to the first n groups keeps the test exact.
 __device__ __forceinline__ bool shared_earlier_cell(const uint64_t* a, const uint64_t* b, int w0,
                                                     int wn, int tcell, const PairFilter& F) {
   bool same = false;
@@ -782,8 +786,9 @@ __device__ __forceinline__ bool shared_earlier_cell(const uint64_t* a, const uin
   for (int q = 0; q < kSigWords; ++q) {
     if (q < wn) {
       const uint64_t x = a[q] ^ b[q];
-      const int tn = min(F.gpw, tcell - (w0 + q) * F.gpw);
-      for (int z = 0; z < tn; ++z) same |= ((x >> (z * F.g)) & F.gmask) == 0ull;
+      const int n = min(F.gpw, tcell - (w0 + q) * F.gpw);  // grids of this word, >= 1
+      const uint64_t keep = (n * F.g >= 64) ? ~0ull : ((1ull << (n * F.g)) - 1ull);
+      same |= (((x - F.lows) & ~x & F.highs) & keep) != 0ull;
     }
   }
   return same;
@@ -1023,6 +1028,14 @@ __device__ __forceinline__ uint32_t mfma32_row(uint32_t i, uint32_t lane) {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
+// The least float above x (x not NaN; +inf stays +inf).
+__device__ __forceinline__ float next_up(float x) {
+  const uint32_t b = __float_as_uint(x);
+  if (x == 0.0f) return __uint_as_float(1u);
+  if (b & 0x80000000u) return __uint_as_float(b - 1u);
+  return (x == INFINITY) ? x : __uint_as_float(b + 1u);
+}
+
 __device__ __forceinline__ float wave_max_f(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
@@ -1030,7 +1043,7 @@ __device__ __forceinline__ float wave_max_f(float v) {
 }
 
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_cell_pairs_gram(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_cell_pairs_gram(
     const float* __restrict__ pts, const uint32_t* __restrict__ sidx,
     const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend,
     const uint32_t* __restrict__ unit_cell, const uint32_t* __restrict__ unit_off,
@@ -1173,6 +1186,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs_gram(
       const float E = (amax + bmax) * kGain + r2f * (4.0f * kU) + 1e-36f;
       const float lo = (E < r2f) ? (r2f - E) * (1.0f - 0x1p-20f) : -INFINITY;
       const float hi = (r2f + E) * (1.0f + 0x1p-20f);
+      const float lo1 = next_up(lo);  // v <= lo  <=>  v - lo1 < 0
+      const float hi1 = next_up(hi);
 
       float breg[2][KS];
 #pragma unroll
@@ -1193,24 +1208,28 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs_gram(
 #pragma unroll
           for (int q = 0; q < KS; ++q)
             v = __builtin_amdgcn_mfma_f32_32x32x2f32(areg[R][q], breg[C][q], v, 0, 0, 0);
-          uint32_t am = 0u, rm = 0u;
+          // Bit 15 - i of am: v[i] <= lo, of cm: v[i] <= hi; each is the
+          // sign of v - (threshold's successor), shifted in from the right
+          // (v is finite: the host keeps coordinates small enough).
+          uint32_t am = 0u, cm = 0u;
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
-            am |= (uint32_t)(v[i] <= lo) << i;
-            rm |= (uint32_t)(v[i] > hi) << i;
+            am = __builtin_amdgcn_alignbit(am, __float_as_uint(v[i] - lo1), 31);
+            cm = __builtin_amdgcn_alignbit(cm, __float_as_uint(v[i] - hi1), 31);
           }
           uint32_t valid = 0xFFFFu;
           if (diag) {
-            // row < col: a prefix of the 16 registers (rows rise with i)
+            // row < col holds for registers i < cnt (rows rise with i)
             const int x = (int)(32 * C + l32) - 32 * R - 4 * (int)h;
             int cnt = 0;
 #pragma unroll
             for (int g = 0; g < 4; ++g) cnt += min(max(x - 8 * g, 0), 4);
-            valid = (1u << cnt) - 1u;
+            valid = (0xFFFFu << (16 - cnt)) & 0xFFFFu;
           }
           const int sh = (R * 2 + C) * 16;
-          acc |= (uint64_t)(am & valid) << sh;
-          band |= (uint64_t)(~(am | rm) & valid) << sh;
+          am &= valid;
+          acc |= (uint64_t)am << sh;
+          band |= (uint64_t)(cm & valid & ~am) << sh;
         }
       }
 
@@ -1218,7 +1237,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs_gram(
       while (band) {
         const int b = __builtin_ctzll(band);
         band &= band - 1;
-        const uint32_t row = 32u * ((uint32_t)b >> 5) + mfma32_row((uint32_t)b & 15u, lane);
+        const uint32_t row = 32u * ((uint32_t)b >> 5) + mfma32_row(15u - ((uint32_t)b & 15u), lane);
         const uint32_t col = 32u * (((uint32_t)b >> 4) & 1u) + l32;
         const uint32_t pa = sAi[w][row], pb = sBi[w][col];
         double s = 0.0;
@@ -1254,7 +1273,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs_gram(
           while (m) {
             const int b = __builtin_ctzll(m);
             m &= m - 1;
-            const uint32_t row = 32u * ((uint32_t)b >> 5) + mfma32_row((uint32_t)b & 15u, lane);
+            const uint32_t row = 32u * ((uint32_t)b >> 5) + mfma32_row(15u - ((uint32_t)b & 15u), lane);
             const uint32_t col = 32u * (((uint32_t)b >> 4) & 1u) + l32;
             uint64_t aw[kSigWords], bw[kSigWords];
 #pragma unroll
@@ -1280,7 +1299,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs_gram(
           while (acc) {
             const int b = __builtin_ctzll(acc);
             acc &= acc - 1;
-            const uint32_t row = 32u * ((uint32_t)b >> 5) + mfma32_row((uint32_t)b & 15u, lane);
+            const uint32_t row = 32u * ((uint32_t)b >> 5) + mfma32_row(15u - ((uint32_t)b & 15u), lane);
             const uint32_t col = 32u * (((uint32_t)b >> 4) & 1u) + l32;
             const uint64_t x = sAi[w][row], y = sBi[w][col];
             const uint64_t lo_i = min(x, y), hi_i = max(x, y);
@@ -1292,7 +1311,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs_gram(
           while (acc) {
             const int b = __builtin_ctzll(acc);
             acc &= acc - 1;
-            const uint32_t row = 32u * ((uint32_t)b >> 5) + mfma32_row((uint32_t)b & 15u, lane);
+            const uint32_t row = 32u * ((uint32_t)b >> 5) + mfma32_row(15u - ((uint32_t)b & 15u), lane);
             const uint32_t col = 32u * (((uint32_t)b >> 4) & 1u) + l32;
             const uint64_t x = sAi[w][row], y = sBi[w][col];
             const uint64_t lo_i = min(x, y), hi_i = max(x, y);
