@@ -35,7 +35,8 @@ FP32_VEC_PEAK_TFLOPS = 157.3
 # kernel ids whose launches are single kernels (candidates for the roofline)
 SINGLE_KERNELS = {"keys": "k_keys", "key_hist": "k_radix_hist", "key_scatter": "k_radix_scatter<true>",
                   "pairs": "k_cell_pairs", "pair_hist": "k_radix_hist",
-                  "pair_scatter": "k_radix_scatter<false>", "stage": "k_stage"}
+                  "pair_scatter": "k_radix_scatter<false>", "stage": "k_stage",
+                  "gather": "k_gather_units"}
 
 
 def workload_by_name(name):

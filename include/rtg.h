@@ -101,7 +101,8 @@ enum {
   RTG_K_UNIQUE = 8,        /* removal of repeated pairs                      */
   RTG_K_CSR = 9,           /* neighbour-list build (incl. transposed sort)   */
   RTG_K_SCAN = 10,         /* prefix sums                                    */
-  RTG_NKERNELS = 11
+  RTG_K_GATHER = 11,       /* cell members' coordinates by sorted position   */
+  RTG_NKERNELS = 12
 };
 #define RTG_TIME_PHASES (1u << 31) /* rtg_set_timing: per-phase events too */
 

@@ -317,6 +317,16 @@ Ctx::Ctx(int dev) : device(dev) {
     if (std::strcmp(e, "vector") == 0) pair_screen = 1;
     if (std::strcmp(e, "matrix") == 0) pair_screen = 2;
   }
+  // RTG_GATHER: "sorted" makes the pair kernels read a copy of the cell
+  // members' rows gathered in sorted order instead of the rows by index.
+  if (const char* e = std::getenv("RTG_GATHER")) gather_direct = std::strcmp(e, "sorted") != 0;
+  // RTG_UNIT_TILES: cells of at most this many 64-point tiles are one work
+  // unit of the pair kernels (larger cells: one unit per tile).
+  if (const char* e = std::getenv("RTG_UNIT_TILES"))
+    cell_unit_tiles = (uint32_t)std::max(1, std::min(64, std::atoi(e)));
+  // RTG_PAIR_BLOCKS: grid size cap of the pair kernels (default 2048).
+  if (const char* e = std::getenv("RTG_PAIR_BLOCKS"))
+    pair_blocks = (uint32_t)std::max(1, std::min(1 << 20, std::atoi(e)));
   // RTG_LANES: passes of the request loop that may run at once (1..4).
   if (const char* e = std::getenv("RTG_LANES"))
     server_lanes = std::max(1, std::min(4, std::atoi(e)));
@@ -916,13 +926,14 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   uint32_t* cstart = S.get<uint32_t>(max_cells);
   uint32_t* cend = S.get<uint32_t>(max_cells);
   uint32_t* units = S.get<uint32_t>(max_cells);
-  uint32_t* unit_cell = S.get<uint32_t>(max_units);
+  UnitDesc* udesc = S.get<UnitDesc>(max_units);
+  float* spts = S.get<float>((size_t)d * NB);  // unit points by sorted position
   uint64_t* tests_c = S.get<uint64_t>(max_cells);
   const size_t s64 = scan_scratch_elems(max_cells);
   uint64_t* scan64 = S.get<uint64_t>(s64 + 4);
   uint32_t* scan32 = S.get<uint32_t>(s64 + 4);
   if (!keys || !keys_alt || (!idx_bits && (!vals || !vals_alt)) || !sort_scr || !run_scr ||
-      !cstart || !cend || !units || !unit_cell || !tests_c || !scan64 || !scan32)
+      !cstart || !cend || !units || !udesc || !spts || !tests_c || !scan64 || !scan32)
     return RTG_ENOMEM;
 
   // First-owner filter (default): each pair is emitted only by the first grid
@@ -936,10 +947,12 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   const bool first_owner = !(flags & RTG_DEDUP_SORT) && sig_g <= 64;
   const int sig_gpw = sig_g <= 64 ? 64 / sig_g : 1;
   const int sig_W = (kmax + sig_gpw - 1) / sig_gpw;
-  uint64_t* sig = nullptr;
+  uint64_t* sig = nullptr;   // [npts][W]
+  uint64_t* ssig = nullptr;  // [W][NB] by sorted position
   if (first_owner) {
     sig = S.get<uint64_t>((size_t)npts * sig_W);
-    if (!sig) return RTG_ENOMEM;
+    ssig = S.get<uint64_t>((size_t)sig_W * NB);
+    if (!sig || !ssig) return RTG_ENOMEM;
     launch_fill_u64(sig, 0ull, (size_t)npts * sig_W, stream);
   }
 
@@ -1007,10 +1020,13 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     if (ncells_h) {
       kbegin(RTG_K_CELLS);
       launch_fill_u64(reinterpret_cast<uint64_t*>(counters) + 3, 0ull, 1, stream);
-      launch_cell_work(cstart, cend, ncells_h, units, tests_c, counters + 3, stream);
+      launch_cell_work(cstart, cend, ncells_h, ctx->cell_unit_tiles, units, tests_c,
+                       counters + 3, stream);
       scan_exclusive_u32(units, units, ncells_h, scan32 + s64, scan32, stream);
       scan_exclusive_u64(tests_c, tests_c, ncells_h, scan64 + s64, scan64, stream);
-      launch_unit_fill(cstart, cend, units, ncells_h, unit_cell, stream);
+      launch_unit_fill(cstart, cend, units, ncells_h, ctx->cell_unit_tiles, skeys,
+                       seg_bits > 0 ? idx_bits + P.layout.cell_bits : 64, sa, segs_d, udesc,
+                       stream);
       kend(RTG_K_CELLS, 24.0 * (double)ncells_h);
       Gather g2;
       g2.add(scan64 + s64, 8);
@@ -1023,18 +1039,36 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     st.cells += ncells_h;
     st.tests += (int64_t)tests_total;
     if (units_total == 0) continue;
-    PairFilter filt;
-    filt.skeys = skeys;
-    filt.idx_bits = idx_bits;
+    PairsArgs pa{};
+    pa.units = udesc;
+    pa.total_units = units_total;
+    pa.spts = spts;
+    pa.ssig = first_owner ? ssig : nullptr;
+    pa.N = NB;
+    pa.direct = ctx->gather_direct ? 1 : 0;
+    pa.max_blocks = ctx->pair_blocks;
+    pa.sigp = first_owner ? sig : nullptr;
+    pa.skeys = skeys;
+    pa.sidx = sidx;
+    pa.idx_bits = idx_bits;
+    pa.pts = pts_rows;
+    pa.d = d;
+    pa.tests = tests_d;
+    pa.gram = use_gram ? 1 : 0;
     if (first_owner) {
-      filt.sig = sig;
-      filt.W = sig_W;
-      filt.g = sig_g;
-      filt.gpw = sig_gpw;
+      pa.W = sig_W;
+      pa.g = sig_g;
+      pa.gpw = sig_gpw;
       for (int z = 0; z < sig_gpw; ++z) {
-        filt.lows |= 1ull << (z * sig_g);
-        filt.highs |= 1ull << (z * sig_g + sig_g - 1);
+        pa.lows |= 1ull << (z * sig_g);
+        pa.highs |= 1ull << (z * sig_g + sig_g - 1);
       }
+    }
+    // the unit points' coordinates and signature words by sorted position
+    if (!pa.direct) {
+      kbegin(RTG_K_GATHER);
+      launch_gather_units(pa, first_owner ? sig : nullptr, spts, ssig, stream);
+      kend(RTG_K_GATHER, 0.0);
     }
 
     // Room for this pass's pairs: a guess first, the exact count on overflow.
@@ -1055,10 +1089,10 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
         cap = want;
       }
       launch_fill_u64(reinterpret_cast<uint64_t*>(counters), cand_total, 1, stream);
-      PairsArgs pa{pts_rows, d, sidx, cstart, cend, unit_cell, units, units_total, tests_d,
-                   segs_d, sa, seg_bits > 0 ? idx_bits + P.layout.cell_bits : 64, filt, cand, cap,
-                   counters, counters + 1};
-      pa.gram = use_gram ? 1 : 0;
+      pa.cand = cand;
+      pa.cap = cap;
+      pa.cand_count = counters;
+      pa.rechecks = counters + 1;
       kbegin(RTG_K_PAIRS);
       launch_cell_pairs(pa, stream);
       if (use_gram) st.matrix_screen_launches += 1;
@@ -1071,6 +1105,9 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
       // every pair within r written once
       st.kernel_bytes[RTG_K_PAIRS] +=
           (4.0 + 4.0 * d) * (double)cnt[3] + 8.0 * (double)(now - cand_total);
+      if (attempt == 0 && !pa.direct)  // the gather: index, row, words in; row, words out
+        st.kernel_bytes[RTG_K_GATHER] +=
+            (8.0 + 8.0 * d + (first_owner ? 16.0 * sig_W : 0.0)) * (double)cnt[3];
       if (now <= cap) {
         cand_total = now;
         break;
@@ -1094,7 +1131,8 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
 
   // Key buffers are no longer needed.
   for (void* p : {(void*)keys, (void*)keys_alt, (void*)vals, (void*)vals_alt, (void*)cstart,
-                  (void*)cend, (void*)units, (void*)unit_cell, (void*)tests_c, (void*)sig})
+                  (void*)cend, (void*)units, (void*)udesc, (void*)spts, (void*)tests_c,
+                  (void*)sig, (void*)ssig})
     S.drop(p);
 
   // --- union and neighbour lists ------------------------------------------------

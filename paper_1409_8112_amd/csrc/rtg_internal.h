@@ -157,57 +157,71 @@ void launch_run_count(const uint64_t* keys, size_t count, int shift, uint32_t* h
 // per-tile offsets.
 void launch_run_write(const uint64_t* keys, size_t count, int shift, const uint32_t* head_off,
                       const uint32_t* tail_off, uint32_t* start, uint32_t* end, hipStream_t s);
-// units[c] = tiles of 64 points in run c, tests[c] = L(L-1)/2, and
+// units[c] = work units of run c (see UnitDesc), tests[c] = L(L-1)/2, and
 // *members += sum of L, for c < ncells.
 void launch_cell_work(const uint32_t* start, const uint32_t* end, uint32_t ncells,
-                      uint32_t* units, uint64_t* tests, unsigned long long* members,
-                      hipStream_t s);
-// unit_cell[unit_off[c] + q] = c for q < tiles of cell c.
+                      uint32_t cell_unit_tiles, uint32_t* units, uint64_t* tests,
+                      unsigned long long* members, hipStream_t s);
+// A work unit of the pair kernels: the 64-point tiles ta in [ta_begin,
+// ta_end) of a cell, each tested against the cell's tiles tb >= ta.  A cell
+// of at most cell_unit_tiles tiles is one unit; a larger cell has one unit
+// per tile.
+struct UnitDesc {
+  uint32_t s0;        // first sorted position of the cell
+  uint32_t len;       // points in the cell
+  uint32_t ta_begin;  // the unit's first A tile
+  uint32_t ta_end;    // one past its last A tile
+  uint32_t t;         // grid of the cell
+  uint32_t inst;      // instance of the cell
+  uint32_t pad[2];
+};
+// desc[unit_off[c] + q] for the units q of cell c; a cell's segment is
+// sa + (its key >> seg_shift) (sa when seg_shift >= 64).
 void launch_unit_fill(const uint32_t* start, const uint32_t* end, const uint32_t* unit_off,
-                      uint32_t ncells, uint32_t* unit_cell, hipStream_t s);
+                      uint32_t ncells, uint32_t cell_unit_tiles, const uint64_t* skeys,
+                      int seg_shift, int sa, const SegDesc* segs, UnitDesc* desc, hipStream_t s);
 
 // --- cell pairs -----------------------------------------------------------
-// Sorted keys and first-owner filter.  The filter keeps a pair found under
-// grid t only if no grid t' < t put both points in one cell;
-// sig[point * k + t] is a point's packed cell key under grid t (u32 or u64);
-// null sig turns the filter off.  skeys / idx_bits are always set.
-// Neighbourhood signatures for the first-owner rule.  Under grid t a point's
-// group holds the low b bits of each axis field (kappa_j - origin_j), g = d b
-// bits, at bit (t % gpw) g of word t / gpw of the point's W-word row.  For two
-// points within r every axis differs by at most 2^b - 1 cells (b is at least
-// the key packing's minimum field width), so equal groups mean equal cells.
-struct PairFilter {
-  const uint64_t* sig = nullptr;    // [npts][W]; null: no first-owner rule
-  int32_t W = 0;                    // words per point
-  int32_t g = 0;                    // bits per grid (<= 64)
-  int32_t gpw = 1;                  // grids per word
-  uint64_t lows = 0, highs = 0;     // lowest and highest bit of each group
-  const uint64_t* skeys = nullptr;  // sorted keys
-  int32_t idx_bits = 0;             // > 0: point index in the low bits of skeys
-};
-
-// One 64-wide wave per unit = (cell, tile a); emits packed pairs
-// (min << pair_bits | max) for same-cell pairs within r.  A cell's segment
-// is sa + (its key >> seg_shift) (sa when seg_shift >= 64); segs[] gives
-// the segment's instance, whose PairTest is tests[instance], and grid.
-// cand_count is the running total (may exceed cap: then the overflow is only
-// counted); rechecks counts FP64 band re-tests.
+// Neighbourhood signatures for the first-owner rule, which keeps a pair
+// found under grid t only if no grid t' < t put both points in one cell.
+// Under grid t a point's group holds the low b bits of each axis field
+// (kappa_j - origin_j), g = d b bits, at bit (t % gpw) g of word t / gpw of
+// the point's W-word row.  For two points within r every axis differs by at
+// most 2^b - 1 cells (b is at least the key packing's minimum field width),
+// so equal groups mean equal cells.
+//
+// The pair kernels read every unit's points by sorted position: their
+// coordinates spts[l][p] and signature words ssig[w][p], gathered once by
+// launch_gather_units.  One 64-wide wave per unit emits packed pairs
+// (min << pair_bits | max) for same-cell pairs within r; cand_count is the
+// running total (it may exceed cap: then the overflow is only counted);
+// rechecks counts FP64 band re-tests.
 struct PairsArgs {
-  const float* pts;  // batch points, row-major [npts][d]
-  int d;
-  const uint32_t* sidx;  // sorted point indices (null when in skeys)
-  const uint32_t *start, *end;
-  const uint32_t *unit_cell, *unit_off;
+  const UnitDesc* units;
   uint32_t total_units;
-  const PairTest* tests;
-  const SegDesc* segs;
-  int sa, seg_shift;
-  PairFilter filter;
+  const float* spts;       // [d][N] unit points' coordinates by sorted position
+  const uint64_t* ssig;    // [W][N] their signature words (null: no first-owner rule)
+  size_t N;                // plane stride of spts / ssig
+  int direct;              // 1: read rows by point index from pts / sigp instead
+  const uint64_t* sigp;    // [npts][W] signature words by point (direct reads)
+  const uint64_t* skeys;   // sorted keys
+  const uint32_t* sidx;    // sorted point indices (null when in skeys)
+  int idx_bits;            // > 0: point index in the low idx_bits of skeys
+  const float* pts;        // batch points, row-major [npts][d] (FP64 band re-test)
+  int d;
+  const PairTest* tests;   // per instance
+  int W, g, gpw;           // signature layout
+  uint64_t lows, highs;    // lowest and highest bit of each signature group
   uint64_t* cand;
   uint64_t cap;
   unsigned long long *cand_count, *rechecks;
-  int gram = 0;  // 1: matrix-core screen (d <= 16), 0: vector screen
+  int gram;                // 1: matrix-core screen (d <= 16), 0: vector screen
+  uint32_t max_blocks;     // grid size cap (0: default)
 };
+// spts / ssig for the positions of every unit, from the batch rows and the
+// per-point signatures sig [npts][W] (ssig untouched when sig is null).
+void launch_gather_units(const PairsArgs& a, const uint64_t* sig, float* spts, uint64_t* ssig,
+                         hipStream_t s);
 void launch_cell_pairs(const PairsArgs& a, hipStream_t s);
 
 // --- unique + CSR -----------------------------------------------------------

@@ -693,14 +693,16 @@ __global__ __launch_bounds__(kBlock) void k_run_write(const uint64_t* __restrict
 
 __global__ __launch_bounds__(kBlock) void k_cell_work(const uint32_t* __restrict__ start,
                                                       const uint32_t* __restrict__ end,
-                                                      uint32_t ncells, uint32_t* __restrict__ units,
+                                                      uint32_t ncells, uint32_t cell_unit_tiles,
+                                                      uint32_t* __restrict__ units,
                                                       uint64_t* __restrict__ tests,
                                                       unsigned long long* members) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t L = 0;
   if (c < ncells) {
     L = end[c] - start[c];
-    units[c] = (uint32_t)((L + kPairTile - 1) / kPairTile);
+    const uint32_t nt = (uint32_t)((L + kPairTile - 1) / kPairTile);
+    units[c] = nt <= cell_unit_tiles ? 1u : nt;
     tests[c] = L * (L - 1) / 2;
   }
   unsigned long long m = L;
@@ -759,46 +761,55 @@ __global__ __launch_bounds__(kBlock) void k_unique_write(const uint64_t* __restr
 }
 
 // ---------------------------------------------------------------------------
-// cell pairs.  A work unit is (cell, tile a) with tiles of 64 points; its
-// wave holds the 64 points of tile a in registers (one per lane) and walks
-// the tiles b >= a of the same cell, staging each in LDS (padded rows, read
-// by broadcast).  Lane l tests (a_l, b_j) for every j, keeping accepted j in
-// a bit mask and the j whose FP32 squared distance lies in the band around
-// r^2 in a second mask; the band is then re-tested in FP64.  With the
-// first-owner filter a pair is kept only if no earlier grid put both points
-// in one cell (that grid reported it already); the earlier cell keys are
-// compared in chunks of kSigChunk grids, tile a's in registers and tile b's
-// in LDS.  Kept pairs are written as (min << b) | max.
+// cell pairs.  A work unit is (cell, tile a) with tiles of 64 points; its wave
+// tests tile a against the tiles b >= a of the same cell.  Unit points are
+// read by sorted position from spts / ssig (gathered once), so every tile
+// load is a direct, coalesced read; the next B tile is loaded while the
+// current one is tested.  Accepted pairs go through the first-owner filter
+// (a pair is kept only if no earlier grid put both points in one cell: the
+// signature words of the two points are compared) and are written as
+// (min << pair_bits) | max.
 
-constexpr int kSigWords = 4;  // signature words staged per chunk
+constexpr int kSigWords = 2;  // signature words kept per point (more: read on demand)
 constexpr int kOutBuf = 256;  // staged pairs per wave
 
-// Whether two points within r shared a cell under some grid t < tcell whose
-// signature group lies in the staged words w0 .. w0 + wn - 1 (a[q], b[q]):
-// whether x = a ^ b has an all-zero group among those grids.  With L the
-// lowest and H the highest bit of every group, (x - L) & ~x & H is nonzero
-// exactly when some group of x is zero; a borrow only runs upward, out of a
-// zero group, so masking to the first n groups keeps the test exact.
-__device__ __forceinline__ bool shared_earlier_cell(const uint64_t* a, const uint64_t* b, int w0,
-                                                    int wn, int tcell, const PairFilter& F) {
+// Whether x = a ^ b (signature words of two points within r) has an all-zero
+// group among the first n groups: with L the lowest and H the highest bit of
+// every group, (x - L) & ~x & H is nonzero exactly when some group of x is
+// zero; a borrow only runs upward, out of a zero group, so masking to the
+// first n groups keeps the test exact.
+__device__ __forceinline__ bool zero_group(uint64_t x, int n, const PairsArgs& P) {
+  const uint64_t keep = (n * P.g >= 64) ? ~0ull : ((1ull << (n * P.g)) - 1ull);
+  return (((x - P.lows) & ~x & P.highs) & keep) != 0ull;
+}
+
+// Signature word q of the point at sorted position p with index i.
+__device__ __forceinline__ uint64_t sig_word(const PairsArgs& P, int q, uint32_t p, uint32_t i) {
+  return P.direct ? P.sigp[(size_t)i * P.W + q] : P.ssig[(size_t)q * P.N + p];
+}
+
+// Whether two points within r shared a cell under a grid t < tcell; word q of
+// their signatures is aq / bq for q < kSigWords, and is read on demand (the
+// points at sorted positions pa, pb with indices ia, ib) beyond that.
+__device__ __forceinline__ bool shared_earlier_cell(const uint64_t* aq, const uint64_t* bq,
+                                                    int tcell, uint32_t pa, uint32_t ia,
+                                                    uint32_t pb, uint32_t ib,
+                                                    const PairsArgs& P) {
+  const int nw = (tcell - 1) / P.gpw + 1;
   bool same = false;
 #pragma unroll
-  for (int q = 0; q < kSigWords; ++q) {
-    if (q < wn) {
-      const uint64_t x = a[q] ^ b[q];
-      const int n = min(F.gpw, tcell - (w0 + q) * F.gpw);  // grids of this word, >= 1
-      const uint64_t keep = (n * F.g >= 64) ? ~0ull : ((1ull << (n * F.g)) - 1ull);
-      same |= (((x - F.lows) & ~x & F.highs) & keep) != 0ull;
-    }
-  }
+  for (int q = 0; q < kSigWords; ++q)
+    if (q < nw) same |= zero_group(aq[q] ^ bq[q], min(P.gpw, tcell - q * P.gpw), P);
+  for (int q = kSigWords; q < nw && !same; ++q)
+    same = zero_group(sig_word(P, q, pa, ia) ^ sig_word(P, q, pb, ib),
+                      min(P.gpw, tcell - q * P.gpw), P);
   return same;
 }
 
-// Point index at sorted position p: the low idx_bits of the sorted key
-// when keys carry it, else the separate index array.
-__device__ __forceinline__ uint32_t point_at(const uint32_t* __restrict__ sidx,
-                                             const PairFilter& F, uint32_t p) {
-  return F.idx_bits ? (uint32_t)(F.skeys[p] & ((1ull << F.idx_bits) - 1ull)) : sidx[p];
+// Point index at sorted position p: the low idx_bits of the sorted key when
+// keys carry it, else the separate index array.
+__device__ __forceinline__ uint32_t point_at(const PairsArgs& P, uint32_t p) {
+  return P.idx_bits ? (uint32_t)(P.skeys[p] & ((1ull << P.idx_bits) - 1ull)) : P.sidx[p];
 }
 
 template <typename T>
@@ -806,14 +817,158 @@ __device__ __forceinline__ T uniform(T v) {
   return (T)__builtin_amdgcn_readfirstlane((int)v);
 }
 
+// One tile's data for this lane (lane < n): coordinates, point index and the
+// first signature words.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_cell_pairs(
-    const float* __restrict__ pts, int d, const uint32_t* __restrict__ sidx,
-    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend,
-    const uint32_t* __restrict__ unit_cell, const uint32_t* __restrict__ unit_off,
-    uint32_t total_units, const PairTest* __restrict__ tests, const SegDesc* __restrict__ segs,
-    int sa, int seg_shift, PairFilter F, uint64_t* __restrict__ cand, uint64_t cap,
-    unsigned long long* cand_count, unsigned long long* rechecks) {
+struct TileRegs {
+  float c[D];
+  uint32_t idx;
+  uint64_t sw[kSigWords];
+};
+
+template <int D>
+__device__ __forceinline__ void load_tile(const PairsArgs& P, uint32_t p0, uint32_t n, int nw,
+                                          uint32_t lane, TileRegs<D>& R) {
+  const bool ok = lane < n;
+  const uint32_t p = p0 + lane;
+  R.idx = ok ? point_at(P, p) : 0u;
+  if (P.direct) {
+    const float* row = P.pts + (size_t)R.idx * P.d;
+#pragma unroll
+    for (int l = 0; l < D; ++l) R.c[l] = (ok && l < P.d) ? row[l] : 0.0f;
+#pragma unroll
+    for (int q = 0; q < kSigWords; ++q)
+      R.sw[q] = (ok && q < nw) ? P.sigp[(size_t)R.idx * P.W + q] : 0ull;
+  } else {
+#pragma unroll
+    for (int l = 0; l < D; ++l) R.c[l] = (ok && l < P.d) ? P.spts[(size_t)l * P.N + p] : 0.0f;
+#pragma unroll
+    for (int q = 0; q < kSigWords; ++q)
+      R.sw[q] = (ok && q < nw) ? P.ssig[(size_t)q * P.N + p] : 0ull;
+  }
+}
+
+// A unit's fields, uniform across the wave (ok = false past the last unit).
+struct UnitView {
+  uint32_t s0, L, ta_begin, ta_end, nt, inst;
+  int tcell, nw;  // grid; signature words to compare (0: no filtering)
+  bool ok;
+};
+
+__device__ __forceinline__ UnitView unit_view(const PairsArgs& P, uint32_t u) {
+  UnitView v;
+  v.ok = u < P.total_units;
+  if (!v.ok) {
+    v.s0 = v.L = v.ta_begin = v.ta_end = v.nt = v.inst = 0u;
+    v.tcell = v.nw = 0;
+    return v;
+  }
+  const UnitDesc U = P.units[u];
+  v.s0 = uniform(U.s0);
+  v.L = uniform(U.len);
+  v.ta_begin = uniform(U.ta_begin);
+  v.ta_end = uniform(U.ta_end);
+  v.tcell = (int)uniform(U.t);
+  v.inst = uniform(U.inst);
+  v.nt = (v.L + kPairTile - 1) / kPairTile;
+  v.nw = (P.ssig && v.tcell > 0) ? (v.tcell - 1) / P.gpw + 1 : 0;
+  return v;
+}
+
+__device__ __forceinline__ uint32_t tile_len(const UnitView& V, uint32_t t) {
+  return min((uint32_t)kPairTile, V.L - t * kPairTile);
+}
+
+// Loads the tile after (ta, tb) in the wave's stream of tile pairs: the next
+// B tile of the row, else the next row's diagonal tile, else the first tile
+// of the next unit Vn (nothing when the stream ends).
+template <int D>
+__device__ __forceinline__ void load_next(const PairsArgs& P, const UnitView& V,
+                                          const UnitView& Vn, uint32_t ta, uint32_t tb,
+                                          uint32_t lane, TileRegs<D>& R) {
+  uint32_t p0 = 0, n = 0;
+  int nw = 0;
+  if (tb + 1 < V.nt) {
+    p0 = V.s0 + (tb + 1) * kPairTile;
+    n = tile_len(V, tb + 1);
+    nw = V.nw;
+  } else if (ta + 1 < V.ta_end) {
+    p0 = V.s0 + (ta + 1) * kPairTile;
+    n = tile_len(V, ta + 1);
+    nw = V.nw;
+  } else if (Vn.ok) {
+    p0 = Vn.s0 + Vn.ta_begin * kPairTile;
+    n = tile_len(Vn, Vn.ta_begin);
+    nw = Vn.nw;
+  }
+  if (n) load_tile<D>(P, p0, n, nw, lane, R);
+}
+
+// Appends this lane's pairs (ai, partner(j)) for the bits j of acc to the
+// wave's staging buffer, flushing it to cand as needed.
+struct OutStage {
+  uint64_t* buf;  // kOutBuf entries of this wave
+  uint32_t n = 0;
+};
+
+__device__ __forceinline__ void flush_out(const PairsArgs& P, OutStage& O, uint32_t lane) {
+  wave_lds_sync();
+  if (O.n) {
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(P.cand_count, (unsigned long long)O.n);
+    base = __shfl(base, 0, 64);
+    for (uint32_t e = lane; e < O.n; e += 64) {
+      const uint64_t g = base + e;
+      if (g < P.cap) P.cand[g] = O.buf[e];
+    }
+    O.n = 0;
+  }
+  wave_lds_sync();
+}
+
+// Writes the pairs of acc; pair_of(bit) gives the packed pair of a bit.
+template <typename PairOf>
+__device__ __forceinline__ void emit_pairs(const PairsArgs& P, OutStage& O, uint32_t lane,
+                                           uint64_t acc, PairOf pair_of) {
+  const uint32_t cnt = (uint32_t)__popcll(acc);
+  const uint32_t incl = wave_inclusive_scan(cnt);
+  const uint32_t total = uniform(__shfl(incl, 63, 64));
+  if (!total) return;
+  if (O.n + total > (uint32_t)kOutBuf) flush_out(P, O, lane);
+  if (total > (uint32_t)kOutBuf) {
+    // more than the buffer holds: straight out
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(P.cand_count, (unsigned long long)total);
+    base = __shfl(base, 0, 64);
+    uint64_t pos = base + incl - cnt;
+    while (acc) {
+      const int b = __builtin_ctzll(acc);
+      acc &= acc - 1;
+      if (pos < P.cap) P.cand[pos] = pair_of(b);
+      ++pos;
+    }
+  } else {
+    uint32_t pos = O.n + incl - cnt;
+    while (acc) {
+      const int b = __builtin_ctzll(acc);
+      acc &= acc - 1;
+      O.buf[pos++] = pair_of(b);
+    }
+    O.n += total;
+  }
+}
+
+__device__ __forceinline__ uint64_t pack_pair(uint64_t x, uint64_t y, int pair_bits) {
+  return (min(x, y) << pair_bits) | max(x, y);
+}
+
+// --- vector screen --------------------------------------------------------
+// Lane l holds point a_l of tile a in registers and tests it against every
+// point b_j of tile b, read from LDS by broadcast: FP32 squared differences
+// summed with FMA; accepted j in one bit mask, j whose FP32 value lies in the
+// band around r^2 in a second mask, re-tested in FP64.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_cell_pairs(const PairsArgs P) {
   // LDS row stride: rows of 4 floats read with 128-bit loads
   constexpr int DP = D <= 2 ? D : ((D + 3) / 4) * 4;
   __shared__ __attribute__((aligned(16))) float sB[kWaves][kPairTile][DP];
@@ -823,62 +978,40 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs(
 
   const uint32_t lane = lane_id();
   const int w = threadIdx.x >> 6;
-  const uint64_t* sig = F.sig;
   unsigned long long nre = 0;
-  uint32_t outn = 0;  // pairs staged in sOut[w] (wave-uniform)
+  OutStage O;
+  O.buf = sOut[w];
 
-  // Staged pairs go out with one global atomic per flush: a device-wide
-  // counter is shared by every XCD, so per-tile atomics would serialise.
-  auto flush = [&]() {
-    wave_lds_sync();
-    if (outn) {
-      unsigned long long base = 0;
-      if (lane == 0) base = atomicAdd(cand_count, (unsigned long long)outn);
-      base = __shfl(base, 0, 64);
-      for (uint32_t e = lane; e < outn; e += 64) {
-        const uint64_t g = base + e;
-        if (g < cap) cand[g] = sOut[w][e];
-      }
-      outn = 0;
-    }
-    wave_lds_sync();
-  };
-
-  // Units are dealt to waves round-robin (no shared work counter).
   const uint32_t wave_id = blockIdx.x * kWaves + w;
   const uint32_t nwaves = gridDim.x * kWaves;
-  for (uint32_t u = wave_id; u < total_units; u += nwaves) {
-
-    const uint32_t c = uniform(unit_cell[u]);
-    const uint32_t ta = u - uniform(unit_off[c]);
-    const uint32_t s0 = uniform(cstart[c]);
-    const uint32_t L = uniform(cend[c]) - s0;
-    const uint32_t nt = (L + kPairTile - 1) / kPairTile;
-    const uint32_t nA = min((uint32_t)kPairTile, L - ta * kPairTile);
-    // the cell's segment: its instance (radius) and grid
-    const int seg =
-        sa + (seg_shift >= 64 ? 0 : (int)uniform((uint32_t)(F.skeys[s0] >> seg_shift)));
-    const int tcell = uniform(segs[seg].t);
-    const PairTest T = tests[uniform(segs[seg].inst)];
-
-    float a[D];
-    uint32_t ai = 0;
-    const bool rowok = lane < nA;
-    if (rowok) ai = point_at(sidx, F, s0 + ta * kPairTile + lane);
-#pragma unroll
-    for (int l = 0; l < D; ++l) a[l] = (rowok && l < d) ? pts[(size_t)ai * d + l] : 0.0f;
-
-    for (uint32_t tb = ta; tb < nt; ++tb) {
-      const uint32_t nB = min((uint32_t)kPairTile, L - tb * kPairTile);
+  // The wave's units form one stream of tiles, each loaded while the tile
+  // pair before it is tested.
+  uint32_t u = wave_id;
+  UnitView V = unit_view(P, u);
+  TileRegs<D> cur, nxt;
+  if (V.ok)
+    load_tile<D>(P, V.s0 + V.ta_begin * kPairTile, tile_len(V, V.ta_begin), V.nw, lane, cur);
+  while (V.ok) {
+    const UnitView Vn = unit_view(P, u + nwaves);
+    const PairTest T = P.tests[V.inst];
+    for (uint32_t ta = V.ta_begin; ta < V.ta_end; ++ta) {
+      const uint32_t nA = tile_len(V, ta);
+      const uint32_t pa0 = V.s0 + ta * kPairTile;
+      const bool rowok = lane < nA;
+      const TileRegs<D> A = cur;  // the row's tile, also its diagonal B tile
+      for (uint32_t tb = ta; tb < V.nt; ++tb) {
+      const uint32_t pb0 = V.s0 + tb * kPairTile;
+      const uint32_t nB = tile_len(V, tb);
       wave_lds_sync();
-      uint32_t bi = 0;
       if (lane < nB) {
-        bi = point_at(sidx, F, s0 + tb * kPairTile + lane);
-        sBi[w][lane] = bi;
+        sBi[w][lane] = cur.idx;
 #pragma unroll
-        for (int l = 0; l < DP; ++l) sB[w][lane][l] = (l < d) ? pts[(size_t)bi * d + l] : 0.0f;
+        for (int l = 0; l < DP; ++l) sB[w][lane][l] = (l < D) ? cur.c[l] : 0.0f;
+#pragma unroll
+        for (int q = 0; q < kSigWords; ++q) sBw[w][q][lane] = cur.sw[q];
       }
       wave_lds_sync();
+      load_next<D>(P, V, Vn, ta, tb, lane, nxt);
 
       // lane l tests j only when j > lim: every pair once in a diagonal tile
       const int lim = rowok ? (ta == tb ? (int)lane : -1) : 64;
@@ -890,7 +1023,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs(
         float d2 = 0.0f;
 #pragma unroll
         for (int l = 0; l < D; ++l) {
-          const float df = a[l] - b[l];
+          const float df = A.c[l] - b[l];
           d2 = __builtin_fmaf(df, df, d2);
         }
         // bitwise, not short-circuit: every lane computes every test, so
@@ -927,7 +1060,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs(
         double s = 0.0;
 #pragma unroll
         for (int l = 0; l < D; ++l) {
-          const double dl = (double)a[l] - (double)sB[w][j][l];
+          const double dl = (double)A.c[l] - (double)sB[w][j][l];
           s = s + dl * dl;
         }
         if (s <= T.r2) acc |= 1ull << j;
@@ -935,79 +1068,41 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs(
       }
 
       // First owner: drop a pair that an earlier grid put in one cell.
-      if (sig && tcell > 0 && ballot(acc != 0ull)) {
-        const int nw = (tcell - 1) / F.gpw + 1;  // words holding grids < tcell
-        for (int w0 = 0; w0 < nw; w0 += kSigWords) {
-          const int wn = min(kSigWords, nw - w0);
-          uint64_t aw[kSigWords];
+      if (V.nw && ballot(acc != 0ull)) {
+        uint64_t m = acc;
+        while (m) {
+          const int j = __builtin_ctzll(m);
+          m &= m - 1;
+          uint64_t bw[kSigWords];
 #pragma unroll
-          for (int q = 0; q < kSigWords; ++q)
-            aw[q] = (rowok && q < wn) ? sig[(size_t)ai * F.W + w0 + q] : 0ull;
-          wave_lds_sync();
-          if (lane < nB) {
-#pragma unroll
-            for (int q = 0; q < kSigWords; ++q)
-              sBw[w][q][lane] = (q < wn) ? sig[(size_t)bi * F.W + w0 + q] : 0ull;
-          }
-          wave_lds_sync();
-          uint64_t m = acc;
-          while (m) {
-            const int j = __builtin_ctzll(m);
-            m &= m - 1;
-            uint64_t bw[kSigWords];
-#pragma unroll
-            for (int q = 0; q < kSigWords; ++q) bw[q] = sBw[w][q][j];
-            if (shared_earlier_cell(aw, bw, w0, wn, tcell, F)) acc &= ~(1ull << j);
-          }
+          for (int q = 0; q < kSigWords; ++q) bw[q] = sBw[w][q][j];
+          if (shared_earlier_cell(A.sw, bw, V.tcell, pa0 + lane, A.idx, pb0 + (uint32_t)j,
+                                  sBi[w][j], P))
+            acc &= ~(1ull << j);
         }
       }
 
-      const uint32_t cnt = (uint32_t)__popcll(acc);
-      const uint32_t incl = wave_inclusive_scan(cnt);
-      const uint32_t total = uniform(__shfl(incl, 63, 64));
-      if (total) {
-        if (outn + total > (uint32_t)kOutBuf) flush();
-        if (total > (uint32_t)kOutBuf) {
-          // more than the buffer holds (at most 64 x 64): straight out
-          unsigned long long base = 0;
-          if (lane == 0) base = atomicAdd(cand_count, (unsigned long long)total);
-          base = __shfl(base, 0, 64);
-          uint64_t pos = base + incl - cnt;
-          while (acc) {
-            const int j = __builtin_ctzll(acc);
-            acc &= acc - 1;
-            const uint64_t bj = sBi[w][j];
-            const uint64_t lo = min((uint64_t)ai, bj), hi = max((uint64_t)ai, bj);
-            if (pos < cap) cand[pos] = (lo << T.pair_bits) | hi;
-            ++pos;
-          }
-        } else {
-          uint32_t pos = outn + incl - cnt;
-          while (acc) {
-            const int j = __builtin_ctzll(acc);
-            acc &= acc - 1;
-            const uint64_t bj = sBi[w][j];
-            const uint64_t lo = min((uint64_t)ai, bj), hi = max((uint64_t)ai, bj);
-            sOut[w][pos++] = (lo << T.pair_bits) | hi;
-          }
-          outn += total;
-        }
+      const uint64_t ai = A.idx;
+      emit_pairs(P, O, lane, acc,
+                 [&](int j) { return pack_pair(ai, sBi[w][j], T.pair_bits); });
+      cur = nxt;
       }
     }
+    u += nwaves;
+    V = Vn;
   }
-  flush();
+  flush_out(P, O, lane);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) nre += __shfl_xor(nre, o, 64);
-  if (lane == 0 && nre) atomicAdd(rechecks, nre);
+  if (lane == 0 && nre) atomicAdd(P.rechecks, nre);
 }
 
-// ---------------------------------------------------------------------------
-// cell pairs on the matrix cores.  Same units, filter and output as
-// k_cell_pairs, but the squared distances of a 64 x 64 tile pair come from
-// Gram blocks.  With the cell's first point o as origin, a' = a - o and
-// b' = b - o in FP32; the rows [a', |a'|^2, 1] and [-2 b', 1, |b'|^2] have
-// dot product |a'|^2 + |b'|^2 - 2 a'.b' = |a' - b'|^2, and
-// v_mfma_f32_32x32x2f32 accumulates 32 x 32 of them over K/2 steps.
+// --- matrix-core screen -----------------------------------------------------
+// The squared distances of a 64 x 64 tile pair come from Gram blocks.  With
+// the A tile's first point o as origin, a' = a - o and b' = b - o in FP32;
+// the rows [a', |a'|^2, 1] and [-2 b', 1, |b'|^2] have dot product
+// |a'|^2 + |b'|^2 - 2 a'.b' = |a' - b'|^2, and v_mfma_f32_32x32x2f32
+// accumulates 32 x 32 of them over K/2 steps.
 //
 // The screen accepts v <= lo and rejects v > hi, lo and hi = r^2 -/+ E,
 // where E bounds |v - s| for s the FP64 squared distance of the definition:
@@ -1017,7 +1112,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs(
 // factor 1.5 to spare.  E is set per tile pair, so it widens by itself when
 // a cell's points lie far apart (aliased keys, very large cells): the screen
 // stays exact and only sends more pairs to FP64.  Pairs with v in between
-// (or NaN) are decided in FP64 from the original coordinates.
+// are decided in FP64 from the original coordinates.
 
 // v_mfma_f32_32x32x2f32 lane layout: lane l supplies A[l % 32][l / 32] and
 // B[l / 32][l % 32]; result register i of lane l holds D[row][l % 32] with
@@ -1042,21 +1137,25 @@ __device__ __forceinline__ float wave_max_f(float v) {
   return v;
 }
 
+// Bits of a tile pair's 64-bit masks: bit 16 (2R + C) + 15 - i is register
+// i of block (R, C), i.e. row 32 R + mfma32_row(i, lane), column 32 C + l32.
+__device__ __forceinline__ uint32_t gram_row(int b, uint32_t lane) {
+  return 32u * ((uint32_t)b >> 5) + mfma32_row(15u - ((uint32_t)b & 15u), lane);
+}
+__device__ __forceinline__ uint32_t gram_col(int b, uint32_t lane) {
+  return 32u * (((uint32_t)b >> 4) & 1u) + (lane & 31u);
+}
+
 template <int D>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_cell_pairs_gram(
-    const float* __restrict__ pts, const uint32_t* __restrict__ sidx,
-    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ cend,
-    const uint32_t* __restrict__ unit_cell, const uint32_t* __restrict__ unit_off,
-    uint32_t total_units, const PairTest* __restrict__ tests, const SegDesc* __restrict__ segs,
-    int sa, int seg_shift, PairFilter F, uint64_t* __restrict__ cand, uint64_t cap,
-    unsigned long long* cand_count, unsigned long long* rechecks) {
+__global__ __launch_bounds__(kBlock) void k_cell_pairs_gram(
+    const PairsArgs P) {
   constexpr int KA = (D + 3) & ~1;  // augmented row length, even
   constexpr int KS = KA / 2;        // MFMA steps per block
   constexpr int KP = KA + 1;        // LDS row stride, odd: conflict-free column reads
   constexpr float kU = 0x1p-24f;
   constexpr float kGain = 1.5f * (float)(2 * KA + D + 8) * kU;
-  // A tile rows, then (once they are in registers) A signature words; the
-  // same for B.
+  // A tile rows, then (once they are in registers) the A signature words;
+  // the same for B.
   constexpr int kRegion = (kPairTile * KP > 2 * kSigWords * kPairTile) ? kPairTile * KP
                                                                        : 2 * kSigWords * kPairTile;
   __shared__ __attribute__((aligned(16))) float sAreg[kWaves][kRegion];
@@ -1068,62 +1167,45 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
   const uint32_t lane = lane_id();
   const uint32_t l32 = lane & 31u, h = lane >> 5;
   const int w = threadIdx.x >> 6;
-  const uint64_t* sig = F.sig;
   float (*sA)[KP] = reinterpret_cast<float (*)[KP]>(sAreg[w]);
   float (*sB)[KP] = reinterpret_cast<float (*)[KP]>(sBreg[w]);
   uint64_t (*sAw)[kPairTile] = reinterpret_cast<uint64_t (*)[kPairTile]>(sAreg[w]);
   uint64_t (*sBw)[kPairTile] = reinterpret_cast<uint64_t (*)[kPairTile]>(sBreg[w]);
   unsigned long long nre = 0;
-  uint32_t outn = 0;
-
-  auto flush = [&]() {
-    wave_lds_sync();
-    if (outn) {
-      unsigned long long base = 0;
-      if (lane == 0) base = atomicAdd(cand_count, (unsigned long long)outn);
-      base = __shfl(base, 0, 64);
-      for (uint32_t e = lane; e < outn; e += 64) {
-        const uint64_t g = base + e;
-        if (g < cap) cand[g] = sOut[w][e];
-      }
-      outn = 0;
-    }
-    wave_lds_sync();
-  };
+  OutStage O;
+  O.buf = sOut[w];
 
   const uint32_t wave_id = blockIdx.x * kWaves + w;
   const uint32_t nwaves = gridDim.x * kWaves;
-  for (uint32_t u = wave_id; u < total_units; u += nwaves) {
-    const uint32_t c = uniform(unit_cell[u]);
-    const uint32_t ta = u - uniform(unit_off[c]);
-    const uint32_t s0 = uniform(cstart[c]);
-    const uint32_t L = uniform(cend[c]) - s0;
-    const uint32_t nt = (L + kPairTile - 1) / kPairTile;
-    const uint32_t nA = min((uint32_t)kPairTile, L - ta * kPairTile);
-    const int seg =
-        sa + (seg_shift >= 64 ? 0 : (int)uniform((uint32_t)(F.skeys[s0] >> seg_shift)));
-    const int tcell = uniform(segs[seg].t);
-    const PairTest T = tests[uniform(segs[seg].inst)];
+  // The wave's units form one stream of tiles, each loaded while the tile
+  // pair before it is tested.
+  uint32_t u = wave_id;
+  UnitView V = unit_view(P, u);
+  TileRegs<D> cur, nxt;
+  if (V.ok)
+    load_tile<D>(P, V.s0 + V.ta_begin * kPairTile, tile_len(V, V.ta_begin), V.nw, lane, cur);
+  while (V.ok) {
+    const UnitView Vn = unit_view(P, u + nwaves);
+    const PairTest T = P.tests[V.inst];
     const float r2f = (float)T.r2;
-
-    // origin: the cell's first point
-    const uint32_t oi = uniform(point_at(sidx, F, s0));
+    // origin: the first point of the unit's first tile (lane 0; wave-uniform)
     float o[D];
 #pragma unroll
-    for (int l = 0; l < D; ++l) o[l] = pts[(size_t)oi * D + l];
-
+    for (int l = 0; l < D; ++l)
+      o[l] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(cur.c[l])));
+    for (uint32_t ta = V.ta_begin; ta < V.ta_end; ++ta) {
+    const uint32_t nA = tile_len(V, ta);
+    const uint32_t pa0 = V.s0 + ta * kPairTile;
     // tile a: centred rows, norms; invalid rows get a huge norm (rejected)
     wave_lds_sync();
     float na = 0.0f;
     {
-      uint32_t ai = 0;
       float row[KA];
       if (lane < nA) {
-        ai = point_at(sidx, F, s0 + ta * kPairTile + lane);
         float n2 = 0.0f;
 #pragma unroll
         for (int l = 0; l < D; ++l) {
-          const float v = pts[(size_t)ai * D + l] - o[l];
+          const float v = cur.c[l] - o[l];
           row[l] = v;
           n2 = __builtin_fmaf(v, v, n2);
         }
@@ -1137,7 +1219,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
       row[D + 1] = 1.0f;
 #pragma unroll
       for (int l = D + 2; l < KA; ++l) row[l] = 0.0f;
-      sAi[w][lane] = ai;
+      sAi[w][lane] = cur.idx;
 #pragma unroll
       for (int l = 0; l < KA; ++l) sA[lane][l] = row[l];
     }
@@ -1148,20 +1230,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     for (int R = 0; R < 2; ++R)
 #pragma unroll
       for (int q = 0; q < KS; ++q) areg[R][q] = sA[32 * R + l32][2 * q + h];
+    if (V.nw) {
+      // the A rows are in registers: their space takes the A signature words
+      wave_lds_sync();
+#pragma unroll
+      for (int q = 0; q < kSigWords; ++q) sAw[q][lane] = cur.sw[q];
+    }
 
-    for (uint32_t tb = ta; tb < nt; ++tb) {
-      const uint32_t nB = min((uint32_t)kPairTile, L - tb * kPairTile);
+    for (uint32_t tb = ta; tb < V.nt; ++tb) {
+      const uint32_t pb0 = V.s0 + tb * kPairTile;
+      const uint32_t nB = min((uint32_t)kPairTile, V.L - tb * kPairTile);
       wave_lds_sync();
       float nb = 0.0f;
+      uint64_t bsw[kSigWords];
       {
-        uint32_t bi = 0;
         float row[KA];
         if (lane < nB) {
-          bi = point_at(sidx, F, s0 + tb * kPairTile + lane);
           float n2 = 0.0f;
 #pragma unroll
           for (int l = 0; l < D; ++l) {
-            const float v = pts[(size_t)bi * D + l] - o[l];
+            const float v = cur.c[l] - o[l];
             row[l] = -2.0f * v;
             n2 = __builtin_fmaf(v, v, n2);
           }
@@ -1175,12 +1263,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
         row[D] = 1.0f;
 #pragma unroll
         for (int l = D + 2; l < KA; ++l) row[l] = 0.0f;
-        sBi[w][lane] = bi;
+        sBi[w][lane] = cur.idx;
 #pragma unroll
         for (int l = 0; l < KA; ++l) sB[lane][l] = row[l];
+#pragma unroll
+        for (int q = 0; q < kSigWords; ++q) bsw[q] = cur.sw[q];
       }
       const float bmax = wave_max_f(nb);
       wave_lds_sync();
+      load_next<D>(P, V, Vn, ta, tb, lane, nxt);
 
       // the tile pair's band
       const float E = (amax + bmax) * kGain + r2f * (4.0f * kU) + 1e-36f;
@@ -1203,6 +1294,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
 #pragma unroll
         for (int C = 0; C < 2; ++C) {
           if (C == 1 && nB <= 32u) break;
+          if (diag && R > C) continue;  // rows above the columns: no pairs
           floatx16 v = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f,
                         0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -1218,9 +1310,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
             cm = __builtin_amdgcn_alignbit(cm, __float_as_uint(v[i] - hi1), 31);
           }
           uint32_t valid = 0xFFFFu;
-          if (diag) {
+          if (diag && R == C) {
             // row < col holds for registers i < cnt (rows rise with i)
-            const int x = (int)(32 * C + l32) - 32 * R - 4 * (int)h;
+            const int x = (int)l32 - 4 * (int)h;
             int cnt = 0;
 #pragma unroll
             for (int g = 0; g < 4; ++g) cnt += min(max(x - 8 * g, 0), 4);
@@ -1230,6 +1322,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
           am &= valid;
           acc |= (uint64_t)am << sh;
           band |= (uint64_t)(cm & valid & ~am) << sh;
+          // one block's accumulators at a time
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
 
@@ -1237,13 +1331,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
       while (band) {
         const int b = __builtin_ctzll(band);
         band &= band - 1;
-        const uint32_t row = 32u * ((uint32_t)b >> 5) + mfma32_row(15u - ((uint32_t)b & 15u), lane);
-        const uint32_t col = 32u * (((uint32_t)b >> 4) & 1u) + l32;
-        const uint32_t pa = sAi[w][row], pb = sBi[w][col];
+        const uint32_t pa = sAi[w][gram_row(b, lane)], pb = sBi[w][gram_col(b, lane)];
         double s = 0.0;
 #pragma unroll
         for (int l = 0; l < D; ++l) {
-          const double dl = (double)pts[(size_t)pa * D + l] - (double)pts[(size_t)pb * D + l];
+          const double dl = (double)P.pts[(size_t)pa * D + l] - (double)P.pts[(size_t)pb * D + l];
           s = s + dl * dl;
         }
         if (s <= T.r2) acc |= 1ull << b;
@@ -1251,92 +1343,113 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
       }
 
       // First owner: drop a pair that an earlier grid put in one cell.  The
-      // tile rows in LDS are in registers by now; their space takes the
-      // signature words.
-      if (sig && tcell > 0 && ballot(acc != 0ull)) {
-        const int nw = (tcell - 1) / F.gpw + 1;  // words holding grids < tcell
-        for (int w0 = 0; w0 < nw; w0 += kSigWords) {
-          const int wn = min(kSigWords, nw - w0);
-          wave_lds_sync();
-          if (lane < nA) {
-            const size_t ra = (size_t)sAi[w][lane] * F.W + w0;
+      // B rows are in registers by now: their space takes the B words.
+      if (V.nw && ballot(acc != 0ull)) {
+        wave_lds_sync();
 #pragma unroll
-            for (int q = 0; q < kSigWords; ++q) sAw[q][lane] = (q < wn) ? sig[ra + q] : 0ull;
-          }
-          if (lane < nB) {
-            const size_t rb = (size_t)sBi[w][lane] * F.W + w0;
+        for (int q = 0; q < kSigWords; ++q) sBw[q][lane] = bsw[q];
+        wave_lds_sync();
+        uint64_t m = acc;
+        while (m) {
+          const int b = __builtin_ctzll(m);
+          m &= m - 1;
+          const uint32_t row = gram_row(b, lane), col = gram_col(b, lane);
+          uint64_t aq[kSigWords], bq[kSigWords];
 #pragma unroll
-            for (int q = 0; q < kSigWords; ++q) sBw[q][lane] = (q < wn) ? sig[rb + q] : 0ull;
+          for (int q = 0; q < kSigWords; ++q) {
+            aq[q] = sAw[q][row];
+            bq[q] = sBw[q][col];
           }
-          wave_lds_sync();
-          uint64_t m = acc;
-          while (m) {
-            const int b = __builtin_ctzll(m);
-            m &= m - 1;
-            const uint32_t row = 32u * ((uint32_t)b >> 5) + mfma32_row(15u - ((uint32_t)b & 15u), lane);
-            const uint32_t col = 32u * (((uint32_t)b >> 4) & 1u) + l32;
-            uint64_t aw[kSigWords], bw[kSigWords];
-#pragma unroll
-            for (int q = 0; q < kSigWords; ++q) {
-              aw[q] = sAw[q][row];
-              bw[q] = sBw[q][col];
-            }
-            if (shared_earlier_cell(aw, bw, w0, wn, tcell, F)) acc &= ~(1ull << b);
-          }
+          if (shared_earlier_cell(aq, bq, V.tcell, pa0 + row, sAi[w][row], pb0 + col,
+                                  sBi[w][col], P))
+            acc &= ~(1ull << b);
         }
       }
 
-      const uint32_t cnt = (uint32_t)__popcll(acc);
-      const uint32_t incl = wave_inclusive_scan(cnt);
-      const uint32_t total = uniform(__shfl(incl, 63, 64));
-      if (total) {
-        if (outn + total > (uint32_t)kOutBuf) flush();
-        if (total > (uint32_t)kOutBuf) {
-          unsigned long long base = 0;
-          if (lane == 0) base = atomicAdd(cand_count, (unsigned long long)total);
-          base = __shfl(base, 0, 64);
-          uint64_t pos = base + incl - cnt;
-          while (acc) {
-            const int b = __builtin_ctzll(acc);
-            acc &= acc - 1;
-            const uint32_t row = 32u * ((uint32_t)b >> 5) + mfma32_row(15u - ((uint32_t)b & 15u), lane);
-            const uint32_t col = 32u * (((uint32_t)b >> 4) & 1u) + l32;
-            const uint64_t x = sAi[w][row], y = sBi[w][col];
-            const uint64_t lo_i = min(x, y), hi_i = max(x, y);
-            if (pos < cap) cand[pos] = (lo_i << T.pair_bits) | hi_i;
-            ++pos;
-          }
-        } else {
-          uint32_t pos = outn + incl - cnt;
-          while (acc) {
-            const int b = __builtin_ctzll(acc);
-            acc &= acc - 1;
-            const uint32_t row = 32u * ((uint32_t)b >> 5) + mfma32_row(15u - ((uint32_t)b & 15u), lane);
-            const uint32_t col = 32u * (((uint32_t)b >> 4) & 1u) + l32;
-            const uint64_t x = sAi[w][row], y = sBi[w][col];
-            const uint64_t lo_i = min(x, y), hi_i = max(x, y);
-            sOut[w][pos++] = (lo_i << T.pair_bits) | hi_i;
-          }
-          outn += total;
-        }
-      }
+      emit_pairs(P, O, lane, acc, [&](int b) {
+        return pack_pair(sAi[w][gram_row(b, lane)], sBi[w][gram_col(b, lane)], T.pair_bits);
+      });
+      cur = nxt;
     }
+    }
+    u += nwaves;
+    V = Vn;
   }
-  flush();
+  flush_out(P, O, lane);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) nre += __shfl_xor(nre, o, 64);
-  if (lane == 0 && nre) atomicAdd(rechecks, nre);
+  if (lane == 0 && nre) atomicAdd(P.rechecks, nre);
 }
 
-// unit_cell[unit_off[c] + q] = c for the tiles q of cell c.
+// Unit descriptors of cell c: the whole cell, or one unit per tile.
 __global__ void k_unit_fill(const uint32_t* __restrict__ start, const uint32_t* __restrict__ end,
                             const uint32_t* __restrict__ unit_off, uint32_t ncells,
-                            uint32_t* __restrict__ unit_cell) {
+                            uint32_t cell_unit_tiles, const uint64_t* __restrict__ skeys,
+                            int seg_shift, int sa,
+                            const SegDesc* __restrict__ segs, UnitDesc* __restrict__ desc) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncells) return;
-  const uint32_t nt = (end[c] - start[c] + kPairTile - 1) / kPairTile;
+  const uint32_t s0 = start[c], L = end[c] - s0;
+  const uint32_t nt = (L + kPairTile - 1) / kPairTile;
+  const int seg = sa + (seg_shift >= 64 ? 0 : (int)(skeys[s0] >> seg_shift));
+  UnitDesc D;
+  D.s0 = s0;
+  D.len = L;
+  D.t = (uint32_t)segs[seg].t;
+  D.inst = (uint32_t)segs[seg].inst;
+  D.pad[0] = D.pad[1] = 0u;
   const uint32_t o = unit_off[c];
-  for (uint32_t q = 0; q < nt; ++q) unit_cell[o + q] = c;
+  if (nt <= cell_unit_tiles) {
+    D.ta_begin = 0;
+    D.ta_end = nt;
+    desc[o] = D;
+  } else {
+    for (uint32_t q = 0; q < nt; ++q) {
+      D.ta_begin = q;
+      D.ta_end = q + 1;
+      desc[o + q] = D;
+    }
+  }
+}
+
+// spts[l][p] and ssig[w][p] for the positions p of every unit (one wave per
+// unit, one lane per position).  All loads of a lane are issued before its
+// stores.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_gather_units(const PairsArgs P,
+                                                         const uint64_t* __restrict__ sig,
+                                                         float* __restrict__ spts,
+                                                         uint64_t* __restrict__ ssig) {
+  const uint32_t u = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (u >= P.total_units) return;
+  const UnitDesc U = P.units[u];
+  const uint32_t lane = lane_id();
+  for (uint32_t ta = U.ta_begin; ta < U.ta_end; ++ta) {
+  const uint32_t n = min((uint32_t)kPairTile, U.len - ta * kPairTile);
+  if (lane >= n) break;
+  const uint32_t p = U.s0 + ta * kPairTile + lane;
+  const uint32_t i = point_at(P, p);
+  const int d = D > 0 ? D : P.d;
+  const float* __restrict__ row = P.pts + (size_t)i * d;
+  if (D > 0) {
+    float c[D > 0 ? D : 1];
+#pragma unroll
+    for (int l = 0; l < (D > 0 ? D : 1); ++l) c[l] = row[l];
+    uint64_t w[kSigWords];
+#pragma unroll
+    for (int q = 0; q < kSigWords; ++q) w[q] = (sig && q < P.W) ? sig[(size_t)i * P.W + q] : 0ull;
+#pragma unroll
+    for (int l = 0; l < (D > 0 ? D : 1); ++l) spts[(size_t)l * P.N + p] = c[l];
+#pragma unroll
+    for (int q = 0; q < kSigWords; ++q)
+      if (sig && q < P.W) ssig[(size_t)q * P.N + p] = w[q];
+  } else {
+    for (int l = 0; l < d; ++l) spts[(size_t)l * P.N + p] = row[l];
+  }
+  if (sig)
+    for (int q = (D > 0 ? kSigWords : 0); q < P.W; ++q)
+      ssig[(size_t)q * P.N + p] = sig[(size_t)i * P.W + q];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1883,39 +1996,63 @@ void launch_run_write(const uint64_t* keys, size_t count, int shift, const uint3
 }
 
 void launch_cell_work(const uint32_t* start, const uint32_t* end, uint32_t ncells,
-                      uint32_t* units, uint64_t* tests, unsigned long long* members,
-                      hipStream_t s) {
+                      uint32_t cell_unit_tiles, uint32_t* units, uint64_t* tests,
+                      unsigned long long* members, hipStream_t s) {
   if (!ncells) return;
   hipLaunchKernelGGL(k_cell_work, dim3(grid_for(ncells)), dim3(kBlock), 0, s, start, end, ncells,
-                     units, tests, members);
+                     cell_unit_tiles, units, tests, members);
 }
 
 void launch_unit_fill(const uint32_t* start, const uint32_t* end, const uint32_t* unit_off,
-                      uint32_t ncells, uint32_t* unit_cell, hipStream_t s) {
+                      uint32_t ncells, uint32_t cell_unit_tiles, const uint64_t* skeys,
+                      int seg_shift, int sa, const SegDesc* segs, UnitDesc* desc, hipStream_t s) {
   if (!ncells) return;
   hipLaunchKernelGGL(k_unit_fill, dim3(grid_for(ncells)), dim3(kBlock), 0, s, start, end, unit_off,
-                     ncells, unit_cell);
+                     ncells, cell_unit_tiles, skeys, seg_shift, sa, segs, desc);
+}
+
+void launch_gather_units(const PairsArgs& a, const uint64_t* sig, float* spts, uint64_t* ssig,
+                         hipStream_t s) {
+  if (!a.total_units) return;
+  const unsigned blocks = (unsigned)(((uint64_t)a.total_units + kWaves - 1) / kWaves);
+#define RTG_GATHER(DD) \
+  hipLaunchKernelGGL(k_gather_units<DD>, dim3(blocks), dim3(kBlock), 0, s, a, sig, spts, ssig)
+  switch (a.d) {
+    case 1: RTG_GATHER(1); break;
+    case 2: RTG_GATHER(2); break;
+    case 3: RTG_GATHER(3); break;
+    case 4: RTG_GATHER(4); break;
+    case 5: RTG_GATHER(5); break;
+    case 6: RTG_GATHER(6); break;
+    case 7: RTG_GATHER(7); break;
+    case 8: RTG_GATHER(8); break;
+    case 9: RTG_GATHER(9); break;
+    case 10: RTG_GATHER(10); break;
+    case 11: RTG_GATHER(11); break;
+    case 12: RTG_GATHER(12); break;
+    case 13: RTG_GATHER(13); break;
+    case 14: RTG_GATHER(14); break;
+    case 15: RTG_GATHER(15); break;
+    case 16: RTG_GATHER(16); break;
+    default: RTG_GATHER(0); break;
+  }
+#undef RTG_GATHER
 }
 
 template <int D>
 static void pairs_dispatch(const PairsArgs& a, hipStream_t s) {
   uint64_t blocks = ((uint64_t)a.total_units + kWaves - 1) / kWaves;
-  const uint64_t max_blocks = 256ull * 8ull;  // 256 CUs, several resident blocks each
+  // 256 CUs, several resident blocks each
+  const uint64_t max_blocks = a.max_blocks ? a.max_blocks : 256ull * 8ull;
   if (blocks > max_blocks) blocks = max_blocks;
   if (blocks < 1) blocks = 1;
   if constexpr (D <= 16) {
     if (a.gram && a.d == D) {
-      hipLaunchKernelGGL((k_cell_pairs_gram<D>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                         a.pts, a.sidx, a.start, a.end, a.unit_cell, a.unit_off, a.total_units,
-                         a.tests, a.segs, a.sa, a.seg_shift, a.filter, a.cand, a.cap,
-                         a.cand_count, a.rechecks);
+      hipLaunchKernelGGL((k_cell_pairs_gram<D>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
       return;
     }
   }
-  hipLaunchKernelGGL((k_cell_pairs<D>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a.pts, a.d,
-                     a.sidx, a.start, a.end, a.unit_cell, a.unit_off, a.total_units, a.tests,
-                     a.segs, a.sa, a.seg_shift, a.filter, a.cand, a.cap, a.cand_count,
-                     a.rechecks);
+  hipLaunchKernelGGL((k_cell_pairs<D>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
 }
 
 void launch_cell_pairs(const PairsArgs& a, hipStream_t s) {

@@ -139,6 +139,9 @@ struct Ctx {
   int64_t batch_points = kBatchPoints;             // points per batch
   int server_lanes = 2;  // passes of the request loop that may run at once
   int pair_screen = 0;   // 0 auto, 1 vector, 2 matrix cores (d <= 16)
+  bool gather_direct = true;  // pair kernels read rows by point index
+  uint32_t cell_unit_tiles = 1;  // cells of at most this many tiles: one work unit
+  uint32_t pair_blocks = 0;      // pair-kernel grid cap (0: default)
   Lane main;          // the caller's stream: blocking calls
   rtg_stats stats{};  // of the last blocking call
   std::mutex mu;      // one blocking call at a time

@@ -24,7 +24,7 @@ OK, EAGAIN, EINVAL, ENOMEM, ERANGE, EDEVICE, ENOENT = 0, 1, -1, -2, -3, -4, -5
 NO_ROTATE, UPPER_ONLY, DEDUP_SORT = 1, 2, 4
 # kernel ids of rtg_stats.kernel_* (RTG_K_* in rtg.h)
 KERNELS = ["stage", "keys", "key_hist", "key_scatter", "cells", "pairs", "pair_hist",
-           "pair_scatter", "unique", "csr", "scan"]
+           "pair_scatter", "unique", "csr", "scan", "gather"]
 NKERNELS = len(KERNELS)
 TIME_PHASES = 1 << 31
 
