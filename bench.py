@@ -30,13 +30,34 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
-FP32_VEC_PEAK_TFLOPS = 157.3
+FP32_VEC_PEAK_TFLOPS = 157.3  # MI355X FP32 vector and FP32 matrix (dense) peak
 
 # kernel ids whose launches are single kernels (candidates for the roofline)
 SINGLE_KERNELS = {"keys": "k_keys", "key_hist": "k_radix_hist", "key_scatter": "k_radix_scatter<true>",
                   "pairs": "k_cell_pairs", "pair_hist": "k_radix_hist",
                   "pair_scatter": "k_radix_scatter<false>", "stage": "k_stage",
                   "gather": "k_gather_units"}
+
+
+def measured_traffic(kernel_name: str):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when it is missing, names another kernel, or the kernel
+    source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_cell_pairs_uniform_n1e6_d6_traffic.txt")
+    src = os.path.join(ROOT, "paper_1409_8112_amd", "csrc", "rtg_kernels.hip")
+    try:
+        kv = {}
+        for line in open(path):
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if kv.get("source_sha256") != sha or not kernel_name.startswith(kv.get("kernel", "?")[:12]):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def workload_by_name(name):
@@ -260,14 +281,21 @@ def main(argv=None) -> int:
         # ALU bound: FP32 flops of the screen, 3 per coordinate (sub, mul, add)
         flops = 3.0 * wl.d * st["tests"] * args.steps / max(k_launch, 1)
         achieved = flops / (avg_ms / 1e3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VEC_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP32_VEC_PEAK_TFLOPS, "traffic": None}
+        traffic = (measured_traffic("k_cell_pairs")
+                   if args.workload == "uniform_d6" and st["matrix_screen_launches"] else None)
+        # the matrix-core screen is an FP32 contraction (Gram blocks): its
+        # peak is the FP32 matrix rate, the same figure as FP32 vector
+        bound = "mfma" if st["matrix_screen_launches"] else "alu"
+        roof = {"bound": bound, "achieved": achieved, "peak": FP32_VEC_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP32_VEC_PEAK_TFLOPS, "traffic": traffic}
     else:
         per_launch = k_bytes / max(k_launch, 1)
         achieved = per_launch / (avg_ms / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None}
-    roof.update({"kernel": SINGLE_KERNELS[dominant], "kernel_id": dominant,
+    if dominant == "pairs" and st["matrix_screen_launches"]:
+        roof["kernel"] = "k_cell_pairs_gram"
+    roof.update({"kernel": roof.get("kernel", SINGLE_KERNELS[dominant]), "kernel_id": dominant,
                  "avg_launch_ms": avg_ms, "launches_per_step": k_launch / args.steps,
                  "algorithmic_bytes_per_launch": k_bytes / max(k_launch, 1)})
 

@@ -1593,11 +1593,51 @@ __device__ __forceinline__ void bucket_range(const uint32_t* __restrict__ offs, 
 // unique, so every entry is kept, the bucket's start in the entry array is
 // its start in col, and the columns of a row are distinct.  The block's
 // 1024 threads load the whole bucket into registers at once, count rows
-// (LDS histogram), scatter the entries by row into LDS, and give each entry
-// its place in its row as the number of smaller columns in the row.
-// Buckets larger than cap or with a row longer than kLongRow are listed in
+// (LDS histogram) and scatter the entries by row into LDS.  An entry of a
+// row of at most kShortRow entries takes its place in the row as the number
+// of smaller columns; a longer row is sorted in place by one wave.  Buckets
+// larger than cap or with a row longer than kLongRow are listed in
 // oversized for the caller.
 constexpr uint32_t kLongRow = 1024;
+constexpr uint32_t kShortRow = 64;
+constexpr uint32_t kMaxLongRows = 512;  // long rows per bucket handled in LDS
+
+// Ascending sort of v[0..len) in LDS by one wave (len <= 1024): a bitonic
+// network in its flip form, where every compare-exchange puts the smaller
+// key at the lower index, so the missing tail of the power-of-two size acts
+// as +infinity and the sort runs in place.
+__device__ __forceinline__ void wave_sort_lds(uint32_t* v, uint32_t len, uint32_t lane) {
+  uint32_t P = 1;
+  while (P < len) P <<= 1;
+  for (uint32_t size = 2; size <= P; size <<= 1) {
+    const uint32_t half = size >> 1;
+    for (uint32_t i = lane; i < (P >> 1); i += 64) {
+      const uint32_t blk = i / half, off = i % half;
+      const uint32_t a = blk * size + off, b = blk * size + size - 1 - off;
+      if (b < len) {
+        const uint32_t x = v[a], y = v[b];
+        if (y < x) {
+          v[a] = y;
+          v[b] = x;
+        }
+      }
+    }
+    wave_lds_sync();
+    for (uint32_t st = half >> 1; st >= 1; st >>= 1) {
+      for (uint32_t i = lane; i < (P >> 1); i += 64) {
+        const uint32_t a = 2 * st * (i / st) + (i % st), b = a + st;
+        if (b < len) {
+          const uint32_t x = v[a], y = v[b];
+          if (y < x) {
+            v[a] = y;
+            v[b] = x;
+          }
+        }
+      }
+      wave_lds_sync();
+    }
+  }
+}
 constexpr int kCsrThreads = 1024;
 constexpr int kCsrWaves = kCsrThreads / 64;
 constexpr int kCsrItems = kBucketMaxEntries / kCsrThreads;
@@ -1629,7 +1669,8 @@ __global__ __launch_bounds__(kCsrThreads) void k_bucket_csr(
   __shared__ uint32_t s[kBucketMaxEntries];
   __shared__ uint32_t rstart[kBucketMaxRows], rcur[kBucketMaxRows];
   __shared__ uint32_t wsum[kCsrWaves];
-  __shared__ uint32_t s_long;
+  __shared__ uint32_t s_long, s_nlong;
+  __shared__ uint32_t s_longrows[kMaxLongRows];
   const uint32_t b = blockIdx.x;
   uint32_t start, cnt;
   bucket_range(offs, b, nbuckets, nblocks, *total_p, start, cnt);
@@ -1646,7 +1687,10 @@ __global__ __launch_bounds__(kCsrThreads) void k_bucket_csr(
     e_[q] = i < cnt ? entries[start + i] : 0u;
   }
   for (uint32_t r = threadIdx.x; r < nrows; r += kCsrThreads) rcur[r] = 0u;
-  if (threadIdx.x == 0) s_long = 0u;
+  if (threadIdx.x == 0) {
+    s_long = 0u;
+    s_nlong = 0u;
+  }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < kCsrItems; ++q)
@@ -1659,6 +1703,11 @@ __global__ __launch_bounds__(kCsrThreads) void k_bucket_csr(
   for (uint32_t r = r0; r < r0 + per && r < nrows; ++r) {
     mine += rcur[r];
     if (rcur[r] > kLongRow) s_long = 1u;
+    if (rcur[r] > kShortRow) {
+      const uint32_t q = atomicAdd(&s_nlong, 1u);
+      if (q < kMaxLongRows) s_longrows[q] = r;
+      else s_long = 1u;  // too many long rows: the caller sorts the bucket
+    }
   }
   uint32_t all;
   uint32_t run = csr_block_exclusive_scan(mine, wsum, all);
@@ -1683,12 +1732,24 @@ __global__ __launch_bounds__(kCsrThreads) void k_bucket_csr(
   for (int q = 0; q < kCsrItems; ++q) {
     if (threadIdx.x + (uint32_t)q * kCsrThreads < cnt) {
       const uint32_t r = e_[q] >> pb;
-      const uint32_t c = e_[q] & cmask;
       const uint32_t lo = rstart[r], hi = rcur[r];
-      uint32_t rank = 0;
-      for (uint32_t x = lo; x < hi; ++x) rank += (s[x] & cmask) < c ? 1u : 0u;
-      col[(size_t)start + lo + rank] = (int32_t)c;
+      if (hi - lo <= kShortRow) {
+        const uint32_t c = e_[q] & cmask;
+        uint32_t rank = 0;
+        for (uint32_t x = lo; x < hi; ++x) rank += (s[x] & cmask) < c ? 1u : 0u;
+        col[(size_t)start + lo + rank] = (int32_t)c;
+      }
     }
+  }
+  // long rows: one wave sorts each in place (the row bits are equal, so the
+  // whole entries order as the columns)
+  const uint32_t nlong = s_nlong;
+  const uint32_t lane = lane_id();
+  for (uint32_t q = threadIdx.x >> 6; q < nlong; q += kCsrWaves) {
+    const uint32_t r = s_longrows[q];
+    const uint32_t lo = rstart[r], len = rcur[r] - lo;
+    wave_sort_lds(s + lo, len, lane);
+    for (uint32_t x = lane; x < len; x += 64) col[(size_t)start + lo + x] = (int32_t)(s[lo + x] & cmask);
   }
 }
 

@@ -398,3 +398,23 @@ def test_signature_widths(ctx, alpha):
     ref = oracle.rtg(p, r, 7, alpha, 9)
     rp, col = _gpu(ctx, p, r, 7, alpha, 9)
     _assert_same(rp, col, ref)
+
+
+def test_long_rows_in_lists(ctx):
+    """Tight clusters of 40, 150, 700 and 1500 points (every pair within r)
+    in a sparse background give neighbour rows of every length the list
+    build distinguishes: counted in place, sorted by one wave, and rows too
+    long for LDS (their bucket takes the global sort)."""
+    _say("long rows")
+    rng = np.random.default_rng(21)
+    d, r = 4, 0.05
+    parts = [rng.random((6000, d))]
+    for size in (40, 150, 700, 1500):
+        centre = rng.random(d) * 0.8 + 0.1
+        parts.append(centre + (rng.random((size, d)) - 0.5) * (0.6 * r / np.sqrt(d)))
+    p = np.concatenate(parts).astype(np.float32)
+    p = p[rng.permutation(len(p))]
+    ref = oracle.rtg(p, r, 3, 2.0, 5)
+    rp, col = _gpu(ctx, p, r, 3, 2.0, 5)
+    _assert_same(rp, col, ref)
+    assert np.diff(ref.row_ptr).max() >= 1499
