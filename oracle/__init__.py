@@ -70,6 +70,9 @@ def lib() -> ctypes.CDLL:
                                       ctypes.c_int64, resp]
         L.oracle_bruteforce.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
                                         ctypes.c_uint32, resp]
+        L.oracle_rtg_query.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, f32p, ctypes.c_int64,
+                                       ctypes.c_double, ctypes.c_int32, ctypes.c_double, f64p,
+                                       f64p, resp]
         L.oracle_result_free.argtypes = [ctypes.POINTER(_Result)]
         L.oracle_result_free.restype = None
         L.oracle_free.argtypes = [ctypes.c_void_p]
@@ -232,6 +235,28 @@ def rtg_rows(points, r: float, alpha: float, R, u, rows) -> list[np.ndarray]:
         raise OracleError(rc, "oracle_rtg_rows")
     csr = _take_result(res)
     return [csr.col[csr.row_ptr[s]:csr.row_ptr[s + 1]] for s in range(len(rows))]
+
+
+def rtg_query(points, queries, r: float, alpha: float, R, u) -> CSR:
+    """Query mode: row s lists the indexed points within r of queries[s] that
+    share a cell with it under some transform (ascending, once each)."""
+    p = _points(points)
+    q = _points(queries)
+    n, d = p.shape
+    if q.shape[1] != d:
+        raise ValueError("queries must have the points' dimension")
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    k = R.shape[0]
+    if R.shape != (k, d, d) or u.shape != (k, d):
+        raise ValueError("R must be [k,d,d] and u [k,d]")
+    res = ctypes.POINTER(_Result)()
+    rc = lib().oracle_rtg_query(_ptr(p, ctypes.c_float), n, d, _ptr(q, ctypes.c_float), len(q),
+                                float(r), k, float(alpha), _ptr(R, ctypes.c_double),
+                                _ptr(u, ctypes.c_double), ctypes.byref(res))
+    if rc != OK:
+        raise OracleError(rc, "oracle_rtg_query")
+    return _take_result(res)
 
 
 def bruteforce(points, r: float, flags: int = 0) -> CSR:

@@ -450,6 +450,70 @@ fail:
   return rc;
 }
 
+/* The pair test between a query row and a point row. */
+static int within_r_rows(const float *pa, const float *pb, int32_t d, double r2) {
+  double s = 0.0;
+  int32_t l;
+  for (l = 0; l < d; ++l) {
+    double delta = (double)pa[l] - (double)pb[l];
+    s = s + delta * delta;
+  }
+  return s <= r2;
+}
+
+int oracle_rtg_query(const float *points, int64_t n, int32_t d,
+                     const float *queries, int64_t m, double r, int32_t k,
+                     double alpha, const double *R, const double *u,
+                     oracle_result **out) {
+  pair_vec pv = {NULL, 0, 0};
+  int64_t *kp = NULL, *kq = NULL;
+  int64_t s, i;
+  int32_t t, j;
+  int rc = check_points(points, n, d);
+  if (rc == ORACLE_OK) rc = check_points(queries, m, d);
+  if (rc == ORACLE_OK) rc = check_radius(r);
+  if (rc == ORACLE_OK && (k < 1 || !(isfinite(alpha) && alpha > 0.0)))
+    rc = ORACLE_EINVAL;
+  if (rc != ORACLE_OK) return rc;
+  if (n >= 1 && m >= 1) {
+    double r2 = r * r;
+    double inv_c = 1.0 / (alpha * r);
+    kp = (int64_t *)malloc(sizeof(int64_t) * (size_t)n * (size_t)d);
+    kq = (int64_t *)malloc(sizeof(int64_t) * (size_t)m * (size_t)d);
+    if (kp == NULL || kq == NULL) {
+      rc = ORACLE_ENOMEM;
+      goto done;
+    }
+    for (t = 0; t < k; ++t) {
+      /* the cell of every point and of every query under transform t */
+      rc = oracle_cell_coords(points, n, d, R + (size_t)t * d * d,
+                              u + (size_t)t * d, inv_c, kp);
+      if (rc == ORACLE_OK)
+        rc = oracle_cell_coords(queries, m, d, R + (size_t)t * d * d,
+                                u + (size_t)t * d, inv_c, kq);
+      if (rc != ORACLE_OK) goto done;
+      for (s = 0; s < m; ++s)
+        for (i = 0; i < n; ++i) {
+          int same = 1;
+          for (j = 0; j < d && same; ++j)
+            same = kq[(size_t)s * d + j] == kp[(size_t)i * d + j];
+          if (same && within_r_rows(queries + (size_t)s * d,
+                                    points + (size_t)i * d, d, r2)) {
+            rc = pv_push(&pv, s, i); /* (query row, indexed point) */
+            if (rc != ORACLE_OK) goto done;
+          }
+        }
+    }
+  }
+  sort_unique(&pv); /* a point found by several grids is kept once */
+  rc = make_csr(&pv, m, ORACLE_UPPER_ONLY, out);
+done:
+  free(kp);
+  free(kq);
+  free(pv.v);
+  return rc;
+}
+
 int oracle_bruteforce(const float *points, int64_t n, int32_t d, double r,
                       uint32_t flags, oracle_result **out) {
   pair_vec pv = {NULL, 0, 0};

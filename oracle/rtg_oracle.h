@@ -120,6 +120,18 @@ int oracle_rtg_rows(const float *points, int64_t n, int32_t d, double r,
                     int32_t k, double alpha, const double *R, const double *u,
                     const int64_t *rows, int64_t nrows, oracle_result **out);
 
+/* Query mode: the same grids answer r-NN queries for new points.  Row s of
+ * the result lists, ascending and once each, the indexed points p_i with
+ * ||p_i - q_s|| <= r (FP64, axis order, as for pairs) that share a cell with
+ * q_s under some transform -- q_s takes the role of one more point of the
+ * set (a query equal to p_i reports i).  Transforms as in
+ * oracle_rtg_with_transforms.  ORACLE_ERANGE if a cell coordinate of a point
+ * or a query has |y| >= 2^31. */
+int oracle_rtg_query(const float *points, int64_t n, int32_t d,
+                     const float *queries, int64_t m, double r, int32_t k,
+                     double alpha, const double *R, const double *u,
+                     oracle_result **out);
+
 /* Exact all-pairs r-NN by testing every pair (the set RTG approximates). */
 int oracle_bruteforce(const float *points, int64_t n, int32_t d, double r,
                       uint32_t flags, oracle_result **out);

@@ -46,3 +46,10 @@ def check_csr(row_ptr: np.ndarray, col: np.ndarray, n: int, symmetric: bool = Tr
         assert all((c, r) in fwd for r, c in fwd), "not symmetric"
     else:
         assert np.all(col > rows)
+
+
+def exact_within(a, b, r: float) -> bool:
+    """||a - b|| <= r in exact rational arithmetic on the float32 inputs
+    and the double r (no rounding anywhere)."""
+    s = sum((Fraction(float(x)) - Fraction(float(y))) ** 2 for x, y in zip(a, b))
+    return s <= Fraction(float(r)) ** 2
