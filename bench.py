@@ -125,6 +125,35 @@ def bench_batched(ctx, count: int, reps: int = 3) -> dict:
             "same_pairs_as_plain": pairs == pairs_plain}
 
 
+def bench_query(ctx, pts, wl, m: int = 1_000_000, reps: int = 5) -> dict:
+    """Query mode: an index of the workload's points (its k sorted grids),
+    then m uniform query points per call."""
+    import torch
+    from paper_1409_8112_amd import workloads
+    q = torch.from_numpy(workloads.uniform_points(m, wl.d, seed=4242)).to("cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = ctx.index_build(pts, wl.r, wl.k, wl.alpha, wl.seed)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    res = ctx.index_query(h, q)  # warm-up
+    res.release()
+    times, found = [], 0
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx.index_query(h, q)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        found = res.nnz
+        res.release()
+    ctx.release(h)
+    t = float(np.median(times))
+    return {"workload": f"index of {wl.name}; {m} uniform query points per call",
+            "queries_per_s": m / t, "ms": t * 1e3, "neighbours": found,
+            "neighbours_per_s": found / t, "index_build_ms": build_ms}
+
+
 def bench_serving(ctx, count: int, rate: float, seed: int = 0) -> dict:
     """Poisson arrivals through rtg_submit / rtg_poll.  Latency runs from a
     request's scheduled arrival to the poll that sees it done."""
@@ -203,6 +232,7 @@ def main(argv=None) -> int:
                     help="skip the batched-instances measurement")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the request-loop measurement")
+    ap.add_argument("--no-query", action="store_true", help="skip the query-mode measurement")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (a known-size "
                          "kernel for scaling hardware byte counters)")
@@ -323,6 +353,9 @@ def main(argv=None) -> int:
         "probe_kernel_ms": {name: probe["kernel_ms"][i] for i, name in enumerate(rtg.KERNELS)},
         "roofline": roof,
     }
+    if not args.no_query and args.workload == "uniform_d6":
+        print("# query mode", file=sys.stderr, flush=True)
+        out["query"] = bench_query(ctx, pts, wl)
     if not args.no_batched:
         print(f"# batched: {args.batched_count} instances", file=sys.stderr, flush=True)
         out["batched"] = bench_batched(ctx, args.batched_count)

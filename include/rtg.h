@@ -187,8 +187,27 @@ int rtg_all_pairs_batched(rtg_ctx *ctx, const rtg_query *queries, int32_t nq, rt
 int rtg_submit(rtg_ctx *ctx, const rtg_query *query, uint64_t *ticket);
 int rtg_poll(rtg_ctx *ctx, uint64_t ticket, rtg_csr *out);
 
-/* Free a result's device memory.  Errors: RTG_ENOENT. */
+/* Free a result's or an index's device memory.  Errors: RTG_ENOENT. */
 int rtg_release(rtg_ctx *ctx, uint64_t handle);
+
+/* Query mode (an r-NN index of one point set; Sec. V suggests answering
+ * queries from the grids).  rtg_index_build sorts the k grids of `points`
+ * once -- the transforms, cell keys and sort of rtg_all_pairs -- and keeps
+ * them, a copy of the points and their signatures in the context under
+ * *index (free with rtg_release).  Arguments and errors as rtg_all_pairs;
+ * flags: RTG_NO_ROTATE.
+ *
+ * rtg_index_query answers m query points (device, row-major [m][d] FP32,
+ * the index's d): row s of the result lists, ascending and once each, the
+ * indexed points p_i with ||p_i - q_s|| <= r that share a cell with q_s
+ * under some grid of the index, decided exactly as the pairs of
+ * rtg_all_pairs (FP64 cell coordinates and distances).  A query equal to an
+ * indexed point reports that point.  Errors: RTG_EINVAL (also NaN/Inf
+ * coordinates), RTG_ERANGE, RTG_ENOMEM, RTG_ENOENT (unknown index). */
+int rtg_index_build(rtg_ctx *ctx, const float *points, int64_t n, int32_t d, double r, int32_t k,
+                    double alpha, uint64_t seed, uint32_t flags, uint64_t *index);
+int rtg_index_query(rtg_ctx *ctx, uint64_t index, const float *queries, int64_t m,
+                    rtg_csr *out);
 
 /* The k seeded transforms, on the host: R [k][d][d] FP64 with orthonormal rows
  * (identity with RTG_NO_ROTATE), u [k][d] FP64 in [0,1).  Transform t draws

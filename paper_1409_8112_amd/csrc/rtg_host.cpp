@@ -389,9 +389,15 @@ uint64_t Ctx::keep_result(uint64_t h, void* mem, int64_t n, int64_t nnz, int64_t
 int Ctx::release(uint64_t h) {
   std::lock_guard<std::mutex> lk(amu);
   auto it = results.find(h);
-  if (it == results.end()) return RTG_ENOENT;
-  arena->release(it->second.mem);
-  results.erase(it);
+  if (it != results.end()) {
+    arena->release(it->second.mem);
+    results.erase(it);
+    return RTG_OK;
+  }
+  auto ix = indexes.find(h);
+  if (ix == indexes.end()) return RTG_ENOENT;
+  for (void* p : ix->second->blocks) arena->release(p);
+  indexes.erase(ix);
   return RTG_OK;
 }
 
@@ -1388,6 +1394,259 @@ int Ctx::debug_cell_coords(const float* points, int64_t n, int32_t d, double r, 
   return L.download(kappa_host, kap, sizeof(int64_t) * (size_t)n * d);
 }
 
+// ---------------------------------------------------------------------------
+// query mode
+
+// The sorted grids of one point set (steps A1-A3 of the pipeline, single
+// instance), kept with a copy of the points and their signatures.
+int Lane::build_index(const float* points, int64_t n, int32_t d, double r, int32_t k,
+                      double alpha, const double* R, const double* u, Index& I) {
+  int rc;
+  I.n = n;
+  I.d = d;
+  I.k = k;
+  I.r = r;
+  I.alpha = alpha;
+  auto own = [&](size_t bytes) -> void* {
+    void* p = dalloc(std::max<size_t>(bytes, 1));
+    if (p) I.blocks.push_back(p);
+    return p;
+  };
+  I.R = static_cast<double*>(own(sizeof(double) * (size_t)k * d * d));
+  I.u = static_cast<double*>(own(sizeof(double) * (size_t)k * d));
+  I.grids = static_cast<QueryGrid*>(own(sizeof(QueryGrid) * (size_t)k));
+  I.layout = static_cast<KeyLayout*>(own(sizeof(KeyLayout)));
+  I.klo = static_cast<int64_t*>(own(sizeof(int64_t) * (size_t)k * d));
+  if (!I.R || !I.u || !I.grids || !I.layout || !I.klo) return RTG_ENOMEM;
+  if ((rc = upload(I.R, R, sizeof(double) * (size_t)k * d * d))) return rc;
+  if ((rc = upload(I.u, u, sizeof(double) * (size_t)k * d))) return rc;
+  if (n == 0) return sync();
+
+  Scratch S(*this);
+  I.pts = static_cast<float*>(own(sizeof(float) * (size_t)n * d));
+  if (!I.pts) return RTG_ENOMEM;
+  if ((rc = hip_fail(hipMemcpyAsync(I.pts, points, sizeof(float) * (size_t)n * d,
+                                    hipMemcpyDeviceToDevice, stream),
+                     "copy index points")))
+    return rc;
+
+  // stage: SoA copy, finiteness, bounding box
+  const uint32_t nblk = (uint32_t)((n + kBlock - 1) / kBlock);
+  InstDesc one{};
+  one.pts = I.pts;
+  one.n = n;
+  one.inv_c = 1.0 / (alpha * r);
+  one.k = k;
+  InstDesc* inst_d = S.get<InstDesc>(1);
+  float* soa = S.get<float>((size_t)n * d);
+  uint32_t* part = S.get<uint32_t>((size_t)nblk * 2 * d);
+  uint32_t* bbox = S.get<uint32_t>((size_t)2 * d + 2);
+  SegDesc* segs_d = S.get<SegDesc>((size_t)k);
+  if (!inst_d || !soa || !part || !bbox || !segs_d) return RTG_ENOMEM;
+  uint32_t* bad = bbox + 2 * d;
+  uint32_t* err = bad + 1;
+  if ((rc = upload(inst_d, &one, sizeof(one)))) return rc;
+  launch_fill_u32(err, 0u, 1, stream);
+  launch_stage(inst_d, 1, nblk, d, n, soa, nullptr, bad, bbox, part, stream);
+  std::vector<uint32_t> hb((size_t)2 * d + 1);
+  if ((rc = download(hb.data(), bbox, sizeof(uint32_t) * hb.size()))) return rc;
+  if (hb[(size_t)2 * d]) return RTG_EINVAL;
+  std::vector<float> lo(d), hi(d);
+  for (int j = 0; j < d; ++j) {
+    lo[j] = decode_order(hb[2 * j]);
+    hi[j] = decode_order(hb[2 * j + 1]);
+  }
+  const int64_t kk = k, nn = n;
+  if ((rc = plan_batch(d, 1, &kk, &nn, R, u, &one.inv_c, &alpha, lo.data(), hi.data(),
+                       ctx->largest_free() / 2, I.P)))
+    return rc;
+  if ((rc = upload(I.layout, &I.P.layout, sizeof(KeyLayout)))) return rc;
+  if ((rc = upload(I.klo, I.P.klo.data(), sizeof(int64_t) * I.P.klo.size()))) return rc;
+
+  // signatures of the first-owner rule (keys that fit imply groups that fit)
+  I.sig_b = min_field_bits(alpha);
+  I.sig_g = d * I.sig_b;
+  if (I.sig_g > 64) return RTG_ERANGE;
+  I.sig_gpw = 64 / I.sig_g;
+  I.sig_W = (k + I.sig_gpw - 1) / I.sig_gpw;
+  for (int z = 0; z < I.sig_gpw; ++z) {
+    I.lows |= 1ull << (z * I.sig_g);
+    I.highs |= 1ull << (z * I.sig_g + I.sig_g - 1);
+  }
+  I.sig = static_cast<uint64_t*>(own(sizeof(uint64_t) * (size_t)n * I.sig_W));
+  if (!I.sig) return RTG_ENOMEM;
+  launch_fill_u64(I.sig, 0ull, (size_t)n * I.sig_W, stream);
+
+  // keys and sort, pass by pass; each grid's n sorted keys are kept
+  std::vector<SegDesc> segs((size_t)k);
+  std::vector<QueryGrid> grids((size_t)k);
+  const int pair_bits = std::max(1, ceil_log2((uint64_t)n));
+  for (int32_t sa = 0; sa < k; sa += I.P.tb) {
+    const int32_t sb = std::min(k, sa + I.P.tb);
+    for (int32_t t = sa; t < sb; ++t) segs[t] = SegDesc{(int64_t)(t - sa) * n, 0, t};
+  }
+  if ((rc = upload(segs_d, segs.data(), sizeof(SegDesc) * segs.size()))) return rc;
+  for (int32_t sa = 0; sa < k; sa += I.P.tb) {
+    const int32_t sb = std::min(k, sa + I.P.tb);
+    const size_t N = (size_t)(sb - sa) * n;
+    const int seg_bits = (sb - sa) > 1 ? ceil_log2((uint64_t)(sb - sa)) : 0;
+    const int key_bits = seg_bits + I.P.layout.cell_bits;
+    const int idx_bits = (key_bits + pair_bits <= 64) ? pair_bits : 0;
+    uint64_t* keys = static_cast<uint64_t*>(own(sizeof(uint64_t) * N));
+    uint64_t* keys_alt = static_cast<uint64_t*>(own(sizeof(uint64_t) * N));
+    uint32_t* vals = idx_bits ? nullptr : static_cast<uint32_t*>(own(sizeof(uint32_t) * N));
+    uint32_t* vals_alt = idx_bits ? nullptr : static_cast<uint32_t*>(own(sizeof(uint32_t) * N));
+    void* scr = S.get<char>(radix_scratch_bytes(N, 0, key_bits));
+    if (!keys || !keys_alt || (!idx_bits && (!vals || !vals_alt)) || !scr) return RTG_ENOMEM;
+    KeysArgs ka{inst_d, 1, nblk, d, n, soa, sa, sb, segs_d, I.R, I.u, I.klo, I.layout,
+                keys, vals, err, I.sig, I.sig_W, I.sig_b, I.sig_gpw, idx_bits};
+    launch_keys(ka, stream);
+    const int where = radix_sort(keys, vals, keys_alt, vals_alt, N, idx_bits, idx_bits + key_bits,
+                                 scr, err, stream, nullptr, 0, 0, ctx->sort_algo);
+    uint64_t* sorted = where ? keys_alt : keys;
+    uint32_t* sorted_idx = idx_bits ? nullptr : (where ? vals_alt : vals);
+    if ((rc = sync())) return rc;  // the other buffers go back below
+    for (void* p : {(void*)(where ? keys : keys_alt), (void*)(where ? vals : vals_alt)}) {
+      if (!p) continue;
+      auto it = std::find(I.blocks.begin(), I.blocks.end(), p);
+      if (it != I.blocks.end()) I.blocks.erase(it);
+      dfree(p);
+    }
+    for (int32_t t = sa; t < sb; ++t)
+      grids[t] = QueryGrid{sorted + (size_t)(t - sa) * n,
+                           sorted_idx ? sorted_idx + (size_t)(t - sa) * n : nullptr,
+                           (uint64_t)(t - sa), idx_bits, 0};
+  }
+  if ((rc = upload(I.grids, grids.data(), sizeof(QueryGrid) * grids.size()))) return rc;
+  uint32_t errh = 0;
+  if ((rc = read_back(err, sizeof(errh), &errh))) return rc;
+  if (errh & 1u) return RTG_ERANGE;
+  if (errh) return hip_fail(hipErrorUnknown, "radix sort look-back");
+  return RTG_OK;
+}
+
+int Lane::query_index(const Index& I, const float* queries, int64_t m, rtg_stats& st,
+                      rtg_csr* out) {
+  int rc;
+  if (m == 0 || I.n == 0) return make_empty_result(m, out, 0);
+  kstats = &st;
+  kpending.clear();
+  struct Detach {
+    Lane& c;
+    ~Detach() {
+      c.kpending.clear();
+      c.kstats = nullptr;
+    }
+  } detach{*this};
+  Scratch S(*this);
+  const int k = I.k, d = I.d;
+  uint64_t* qkey = S.get<uint64_t>((size_t)m * k);
+  uint64_t* qsig = S.get<uint64_t>((size_t)m * I.sig_W);
+  uint32_t* err = S.get<uint32_t>(2);
+  unsigned long long* counter = S.get<unsigned long long>(1);
+  if (!qkey || !qsig || !err || !counter) return RTG_ENOMEM;
+  launch_fill_u32(err, 0u, 2, stream);
+  QueryArgs A{};
+  A.queries = queries;
+  A.m = m;
+  A.d = d;
+  A.k = k;
+  A.R = I.R;
+  A.u = I.u;
+  A.inv_c = 1.0 / (I.alpha * I.r);
+  A.r2 = I.r * I.r;
+  A.klo = I.klo;
+  A.layout = I.layout;
+  A.cell_bits = I.P.layout.cell_bits;
+  A.grids = I.grids;
+  A.n = I.n;
+  A.pts = I.pts;
+  A.sig = I.sig;
+  A.W = I.sig_W;
+  A.sig_b = I.sig_b;
+  A.g = I.sig_g;
+  A.gpw = I.sig_gpw;
+  A.lows = I.lows;
+  A.highs = I.highs;
+  A.qkey = qkey;
+  A.qsig = qsig;
+  A.err = err;
+  A.pb = std::max(1, ceil_log2((uint64_t)std::max<int64_t>(I.n, m)));
+  launch_query_keys(A, stream);
+  uint32_t errh = 0;
+  if ((rc = read_back(err, sizeof(errh), &errh))) return rc;
+  if (errh & 2u) return RTG_EINVAL;
+  if (errh & 1u) return RTG_ERANGE;
+
+  // pairs (query, point); room from a guess, the exact count on overflow
+  uint64_t cap = std::max<uint64_t>(1u << 20, (uint64_t)m * 32);
+  uint64_t* cand = nullptr;
+  uint64_t C = 0;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    if (cand) S.drop(cand);
+    cand = S.get<uint64_t>(cap);
+    if (!cand) return RTG_ENOMEM;
+    launch_fill_u64(reinterpret_cast<uint64_t*>(counter), 0ull, 1, stream);
+    A.cand = cand;
+    A.cap = cap;
+    A.cand_count = counter;
+    kbegin(RTG_K_PAIRS);
+    launch_query_pairs(A, stream);
+    kend(RTG_K_PAIRS, 0.0);
+    unsigned long long cnt = 0;
+    if ((rc = read_back(counter, sizeof(cnt), &cnt))) return rc;
+    C = cnt;
+    if (C <= cap) break;
+    if (attempt == 1) return RTG_ENOMEM;
+    cap = C;
+  }
+  st.candidates = (int64_t)C;
+  st.unique_pairs = (int64_t)C;
+
+  // lists: rows are the queries, one orientation
+  void* res = nullptr;
+  int64_t* row_ptr = nullptr;
+  int32_t* col = nullptr;
+  size_t nnz = 0;
+  const int pb = A.pb;
+  const bool bucket_ok = pb <= 24 && ceil_log2((uint64_t)m) <= 22 &&
+                         ceil_log2((uint64_t)m) - 14 + pb <= 32 && C < (1ull << 32);
+  if (C == 0) {
+    if ((rc = alloc_result(*this, m, 0, &res, &row_ptr, &col))) return rc;
+    launch_fill_u64(reinterpret_cast<uint64_t*>(row_ptr), 0ull, (size_t)(m + 1), stream);
+  } else if (bucket_ok) {
+    if ((rc = csr_by_buckets(*this, S, cand, C, m, pb, false, err + 1, nullptr, &res, &row_ptr,
+                             &col, &nnz)))
+      return rc;
+  } else {
+    uint64_t* alt = S.get<uint64_t>(C);
+    void* scr = S.get<char>(radix_scratch_bytes(C, 0, 2 * pb));
+    if (!alt || !scr) return RTG_ENOMEM;
+    launch_fill_u32(err + 1, 0u, 1, stream);
+    const int where = radix_sort(cand, nullptr, alt, nullptr, C, 0, 2 * pb, scr, err + 1, stream,
+                                 nullptr, 0, 0, ctx->sort_algo);
+    nnz = C;
+    if ((rc = alloc_result(*this, m, nnz, &res, &row_ptr, &col))) return rc;
+    if ((rc = csr_from_sorted(*this, S, where ? alt : cand, C, m, pb, false, err + 1, row_ptr,
+                              col))) {
+      dfree(res);
+      return rc;
+    }
+  }
+  if ((rc = sync())) {
+    dfree(res);
+    return rc;
+  }
+  out->n = m;
+  out->nnz = (int64_t)nnz;
+  out->row_ptr = row_ptr;
+  out->col = nnz ? col : nullptr;
+  out->pairs = (int64_t)nnz;
+  out->handle = ctx->keep_result(0, res, m, (int64_t)nnz, (int64_t)nnz, row_ptr, col);
+  kfinish();
+  return RTG_OK;
+}
+
 }  // namespace rtg
 
 // ===========================================================================
@@ -1455,6 +1714,59 @@ int rtg_all_pairs_with_transforms(rtg_ctx* ctx, const float* points, int64_t n, 
 int rtg_release(rtg_ctx* ctx, uint64_t handle) {
   if (!ctx) return RTG_EINVAL;
   return reinterpret_cast<Ctx*>(ctx)->release(handle);
+}
+
+int rtg_index_build(rtg_ctx* ctx, const float* points, int64_t n, int32_t d, double r, int32_t k,
+                    double alpha, uint64_t seed, uint32_t flags, uint64_t* index) {
+  if (!ctx || !index) return RTG_EINVAL;
+  Ctx* c = reinterpret_cast<Ctx*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->poisoned) return RTG_EDEVICE;
+  int rc = c->check_query(points, n, d, r, k, alpha);
+  if (rc) return rc;
+  std::vector<double> R((size_t)k * d * d), u((size_t)k * d);
+  if ((rc = rtg::make_transforms(seed, k, d, flags, R.data(), u.data()))) return rc;
+  std::unique_ptr<rtg::Index> I(new (std::nothrow) rtg::Index());
+  if (!I) return RTG_ENOMEM;
+  rc = c->main.build_index(points, n, d, r, k, alpha, R.data(), u.data(), *I);
+  if (rc) {
+    (void)hipStreamSynchronize(c->main.stream);
+    for (void* p : I->blocks) c->dfree(p);
+    return rc;
+  }
+  const uint64_t h = c->new_handle();
+  {
+    std::lock_guard<std::mutex> alk(c->amu);
+    c->indexes[h] = std::move(I);
+  }
+  *index = h;
+  return RTG_OK;
+}
+
+int rtg_index_query(rtg_ctx* ctx, uint64_t index, const float* queries, int64_t m,
+                    rtg_csr* out) {
+  if (!ctx || !out) return RTG_EINVAL;
+  Ctx* c = reinterpret_cast<Ctx*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->poisoned) return RTG_EDEVICE;
+  const rtg::Index* I = nullptr;
+  {
+    std::lock_guard<std::mutex> alk(c->amu);
+    auto it = c->indexes.find(index);
+    if (it == c->indexes.end()) return RTG_ENOENT;
+    I = it->second.get();
+  }
+  if (m < 0 || m >= (int64_t(1) << 31)) return RTG_EINVAL;
+  if (m > 0 && (!queries || (reinterpret_cast<uintptr_t>(queries) & 3u) ||
+                rtg::check_device_pointer(queries, c->device)))
+    return RTG_EINVAL;
+  rtg_stats st{};
+  st.n = m;
+  st.d = I->d;
+  st.k = I->k;
+  const int rc = c->main.query_index(*I, queries, m, st, out);
+  if (!rc) c->stats = st;
+  return rc;
 }
 
 int rtg_make_transforms(uint64_t seed, int32_t k, int32_t d, uint32_t flags, double* R, double* u) {

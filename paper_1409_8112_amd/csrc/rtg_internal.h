@@ -218,6 +218,42 @@ struct PairsArgs {
   int gram;                // 1: matrix-core screen (d <= 16), 0: vector screen
   uint32_t max_blocks;     // grid size cap (0: default)
 };
+// --- query mode -------------------------------------------------------------
+// One sorted grid of an index: its n sorted keys (cell prefix above the point
+// index when the keys carry it) and the grid's segment id within its sort.
+struct QueryGrid {
+  const uint64_t* keys;
+  const uint32_t* idx;  // point indices when the keys do not carry them
+  uint64_t seg;
+  int32_t idx_bits;     // > 0: the point index in the low idx_bits of the keys
+  int32_t pad;
+};
+struct QueryArgs {
+  const float* queries;     // [m][d] row-major
+  int64_t m;
+  int d, k;
+  const double *R, *u;      // [k][d][d], [k][d]
+  double inv_c, r2;
+  const int64_t* klo;       // [k][d] field origins
+  const KeyLayout* layout;
+  int cell_bits;            // packed cell bits of the index's keys
+  const QueryGrid* grids;   // [k]
+  int64_t n;                // indexed points
+  const float* pts;         // [n][d] indexed points
+  const uint64_t* sig;      // [n][W] their signatures (null: no first-owner rule)
+  int W, sig_b, g, gpw;
+  uint64_t lows, highs;
+  uint64_t* qkey;           // [m][k] cell prefix of each query under each grid
+  uint64_t* qsig;           // [m][W] signature words of each query
+  uint32_t* err;            // bit 0: a cell coordinate out of range, bit 1: not finite
+  int pb;                   // bits of an index in a packed (query, point) pair
+  uint64_t* cand;
+  uint64_t cap;
+  unsigned long long* cand_count;
+};
+void launch_query_keys(const QueryArgs& a, hipStream_t s);
+void launch_query_pairs(const QueryArgs& a, hipStream_t s);
+
 // spts / ssig for the positions of every unit, from the batch rows and the
 // per-point signatures sig [npts][W] (ssig untouched when sig is null).
 void launch_gather_units(const PairsArgs& a, const uint64_t* sig, float* spts, uint64_t* ssig,

@@ -1381,6 +1381,176 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs_gram(
   if (lane == 0 && nre) atomicAdd(P.rechecks, nre);
 }
 
+// ---------------------------------------------------------------------------
+// query mode.  A query point takes the role of one more point of the indexed
+// set: under grid t it falls in the cell floor((R_t q)/(alpha r) + u_t),
+// computed in FP64 in the same order as the points' cells, and is reported
+// with the indexed points of that cell within r, once (first-owner rule with
+// the query's own signature).
+
+// Cell prefix (segment and packed cell fields) of every query under every
+// grid, and the query's signature words.  One thread per query.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_query_keys(const QueryArgs A) {
+  const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= A.m) return;
+  const int d = D > 0 ? D : A.d;
+  float p[D > 0 ? D : 1];
+  bool finite = true;
+  if (D > 0) {
+#pragma unroll
+    for (int l = 0; l < (D > 0 ? D : 1); ++l) p[l] = A.queries[q * d + l];
+  }
+  for (int l = 0; l < d; ++l) finite = finite && isfinite(A.queries[q * d + l]);
+  if (!finite) {
+    atomicOr(A.err, 2u);
+    return;
+  }
+  const uint64_t bmask = (1ull << A.sig_b) - 1ull;
+  uint64_t sword = 0;
+  int sw = -1;
+  bool bad = false;
+  for (int t = 0; t < A.k; ++t) {
+    const double* Rt = A.R + (size_t)t * d * d;
+    const double* ut = A.u + (size_t)t * d;
+    const int64_t* kl = A.klo + (size_t)t * d;
+    uint64_t cell = 0, grp = 0;
+    for (int j = 0; j < d; ++j) {
+      // same operation order as the points' keys (the key kernel)
+      double z;
+      if (D > 0) {
+        z = Rt[(size_t)j * d] * (double)p[0];
+        for (int l = 1; l < d; ++l) z = z + Rt[(size_t)j * d + l] * (double)p[l];
+      } else {
+        z = Rt[(size_t)j * d] * (double)A.queries[q * d];
+        for (int l = 1; l < d; ++l) z = z + Rt[(size_t)j * d + l] * (double)A.queries[q * d + l];
+      }
+      const double y = z * A.inv_c + ut[j];
+      const bool ok = fabs(y) < 2147483648.0;
+      bad |= !ok;
+      const int64_t kap = ok ? (int64_t)floor(y) : 0;
+      const uint64_t mask = (1ull << A.layout->bits[j]) - 1ull;
+      cell |= ((uint64_t)(kap - kl[j]) & mask) << A.layout->shift[j];
+      grp |= ((uint64_t)(kap - kl[j]) & bmask) << (j * A.sig_b);
+    }
+    const uint64_t prefix = A.cell_bits < 64 ? ((A.grids[t].seg << A.cell_bits) | cell) : cell;
+    A.qkey[(size_t)q * A.k + t] = prefix;
+    if (A.sig) {
+      const int w = t / A.gpw;
+      if (w != sw) {
+        if (sw >= 0) A.qsig[(size_t)q * A.W + sw] = sword;
+        sword = 0;
+        sw = w;
+      }
+      sword |= grp << ((t - w * A.gpw) * A.g);
+    }
+  }
+  if (A.sig && sw >= 0) A.qsig[(size_t)q * A.W + sw] = sword;
+  if (bad) atomicOr(A.err, 1u);
+}
+
+// First position in keys[0..n) whose cell prefix is >= K.
+__device__ __forceinline__ uint32_t prefix_lower_bound(const uint64_t* keys, uint32_t n, int shift,
+                                                       uint64_t K) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if ((keys[mid] >> shift) < K) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Pairs (query, indexed point): one wave per query; lane t finds grid t's
+// cell by binary search, then the wave tests that cell's members.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_query_pairs(const QueryArgs A) {
+  __shared__ uint64_t sOut[kWaves][kOutBuf];
+  const uint32_t lane = lane_id();
+  const int w = threadIdx.x >> 6;
+  const int d = D > 0 ? D : A.d;
+  PairsArgs P{};  // output staging shares the pair kernels' machinery
+  P.cand = A.cand;
+  P.cap = A.cap;
+  P.cand_count = A.cand_count;
+  OutStage O;
+  O.buf = sOut[w];
+  const uint32_t n = (uint32_t)A.n;
+  const int64_t wave_id = (int64_t)blockIdx.x * kWaves + w;
+  const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+  for (int64_t q = wave_id; q < A.m; q += nwaves) {
+    double qc[D > 0 ? D : 1];
+    if (D > 0) {
+#pragma unroll
+      for (int l = 0; l < (D > 0 ? D : 1); ++l) qc[l] = (double)A.queries[q * d + l];
+    }
+    uint64_t qw[kSigWords] = {0ull, 0ull};
+    if (A.sig)
+#pragma unroll
+      for (int x = 0; x < kSigWords; ++x) qw[x] = x < A.W ? A.qsig[(size_t)q * A.W + x] : 0ull;
+    for (int t0 = 0; t0 < A.k; t0 += 64) {
+      // lane t: the range of grid t0 + t
+      uint32_t rlo = 0, rhi = 0;
+      const int tl = t0 + (int)lane;
+      if (tl < A.k) {
+        const uint64_t K = A.qkey[(size_t)q * A.k + tl];
+        const uint64_t* keys = A.grids[tl].keys;
+        const int sh = A.grids[tl].idx_bits;
+        rlo = prefix_lower_bound(keys, n, sh, K);
+        rhi = rlo;
+        while (rhi < n && (keys[rhi] >> sh) == K && rhi - rlo < 8u) ++rhi;
+        if (rhi < n && (keys[rhi] >> sh) == K)
+          rhi = K == ~0ull ? n : prefix_lower_bound(keys + rhi, n - rhi, sh, K + 1ull) + rhi;
+      }
+      const int tn = min(64, A.k - t0);
+      for (int tt = 0; tt < tn; ++tt) {
+        const int t = t0 + tt;
+        const uint32_t lo = (uint32_t)__shfl((int)rlo, tt, 64);
+        const uint32_t hi = (uint32_t)__shfl((int)rhi, tt, 64);
+        const QueryGrid G = A.grids[t];
+        const uint64_t imask = G.idx_bits ? ((1ull << G.idx_bits) - 1ull) : 0ull;
+        for (uint32_t base = lo; base < hi; base += 64) {
+          const uint32_t pos = base + lane;
+          bool hit = false;
+          uint32_t i = 0;
+          if (pos < hi) {
+            i = G.idx_bits ? (uint32_t)(G.keys[pos] & imask) : G.idx[pos];
+            const float* row = A.pts + (size_t)i * d;
+            double s2 = 0.0;
+            if (D > 0) {
+#pragma unroll
+              for (int l = 0; l < (D > 0 ? D : 1); ++l) {
+                const double dl = qc[l] - (double)row[l];
+                s2 = s2 + dl * dl;
+              }
+            } else {
+              for (int l = 0; l < d; ++l) {
+                const double dl = (double)A.queries[q * d + l] - (double)row[l];
+                s2 = s2 + dl * dl;
+              }
+            }
+            hit = s2 <= A.r2;
+            if (hit && A.sig && t > 0) {
+              // dropped if an earlier grid put the query and the point in one cell
+              const int nw = (t - 1) / A.gpw + 1;
+              for (int x = 0; x < nw && hit; ++x) {
+                const uint64_t xw =
+                    (x < kSigWords ? qw[x] : A.qsig[(size_t)q * A.W + x]) ^ A.sig[(size_t)i * A.W + x];
+                const int ng = min(A.gpw, t - x * A.gpw);
+                const uint64_t keep = (ng * A.g >= 64) ? ~0ull : ((1ull << (ng * A.g)) - 1ull);
+                hit = (((xw - A.lows) & ~xw & A.highs) & keep) == 0ull;
+              }
+            }
+          }
+          const uint64_t pair = ((uint64_t)q << A.pb) | i;
+          emit_pairs(P, O, lane, hit ? 1ull : 0ull, [&](int) { return pair; });
+        }
+      }
+    }
+  }
+  flush_out(P, O, lane);
+}
+
 // Unit descriptors of cell c: the whole cell, or one unit per tile.
 __global__ void k_unit_fill(const uint32_t* __restrict__ start, const uint32_t* __restrict__ end,
                             const uint32_t* __restrict__ unit_off, uint32_t ncells,
@@ -2098,6 +2268,53 @@ void launch_gather_units(const PairsArgs& a, const uint64_t* sig, float* spts, u
     default: RTG_GATHER(0); break;
   }
 #undef RTG_GATHER
+}
+
+void launch_query_keys(const QueryArgs& a, hipStream_t s) {
+  if (a.m <= 0) return;
+  const unsigned blocks = (unsigned)((a.m + kBlock - 1) / kBlock);
+#define RTG_QK(DD) hipLaunchKernelGGL(k_query_keys<DD>, dim3(blocks), dim3(kBlock), 0, s, a)
+  switch (a.d) {
+    case 1: RTG_QK(1); break;
+    case 2: RTG_QK(2); break;
+    case 3: RTG_QK(3); break;
+    case 4: RTG_QK(4); break;
+    case 5: RTG_QK(5); break;
+    case 6: RTG_QK(6); break;
+    case 7: RTG_QK(7); break;
+    case 8: RTG_QK(8); break;
+    case 9: RTG_QK(9); break;
+    case 10: RTG_QK(10); break;
+    case 11: RTG_QK(11); break;
+    case 12: RTG_QK(12); break;
+    case 16: RTG_QK(16); break;
+    default: RTG_QK(0); break;
+  }
+#undef RTG_QK
+}
+
+void launch_query_pairs(const QueryArgs& a, hipStream_t s) {
+  if (a.m <= 0 || a.n <= 0) return;
+  uint64_t blocks = ((uint64_t)a.m + kWaves - 1) / kWaves;
+  if (blocks > 4096) blocks = 4096;
+#define RTG_QP(DD) hipLaunchKernelGGL(k_query_pairs<DD>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a)
+  switch (a.d) {
+    case 1: RTG_QP(1); break;
+    case 2: RTG_QP(2); break;
+    case 3: RTG_QP(3); break;
+    case 4: RTG_QP(4); break;
+    case 5: RTG_QP(5); break;
+    case 6: RTG_QP(6); break;
+    case 7: RTG_QP(7); break;
+    case 8: RTG_QP(8); break;
+    case 9: RTG_QP(9); break;
+    case 10: RTG_QP(10); break;
+    case 11: RTG_QP(11); break;
+    case 12: RTG_QP(12); break;
+    case 16: RTG_QP(16); break;
+    default: RTG_QP(0); break;
+  }
+#undef RTG_QP
 }
 
 template <int D>

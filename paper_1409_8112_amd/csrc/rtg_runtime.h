@@ -83,6 +83,23 @@ struct Result {
   int32_t* col;
 };
 
+// Query mode: the sorted grids of one point set, kept on the device.
+struct Index {
+  int64_t n = 0;
+  int32_t d = 0, k = 0;
+  double r = 0.0, alpha = 0.0;
+  Packing P;
+  int sig_b = 0, sig_g = 0, sig_gpw = 1, sig_W = 0;
+  uint64_t lows = 0, highs = 0;
+  float* pts = nullptr;       // [n][d] copy of the points
+  uint64_t* sig = nullptr;    // [n][W] signatures
+  double *R = nullptr, *u = nullptr;
+  int64_t* klo = nullptr;
+  rtgk::KeyLayout* layout = nullptr;
+  rtgk::QueryGrid* grids = nullptr;  // device [k]
+  std::vector<void*> blocks;         // arena blocks the index owns
+};
+
 struct Ctx;
 struct Server;
 
@@ -120,6 +137,10 @@ struct Lane {
   rtgk::LaunchTimer timer();
 
   int make_empty_result(int64_t n, rtg_csr* out, uint64_t handle);
+  int build_index(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha,
+                  const double* R, const double* u, Index& I);
+  int query_index(const Index& I, const float* queries, int64_t m, rtg_stats& st,
+                  rtg_csr* out);
   int tiny_query(const float* points, int64_t n, int32_t d, rtg_csr* out, uint64_t handle);
   // One pass of the pipeline over a batch of instances of one dimension.
   int run_batch(std::vector<Job*>& jobs, rtg_stats& st);
@@ -147,6 +168,7 @@ struct Ctx {
   std::mutex mu;      // one blocking call at a time
   std::mutex amu;     // arena, results, handles
   std::map<uint64_t, Result> results;
+  std::map<uint64_t, std::unique_ptr<Index>> indexes;
   uint64_t next_handle = 1;
   Server* server = nullptr;  // request loop, started by the first rtg_submit
   std::mutex server_mu;      // guards the server pointer

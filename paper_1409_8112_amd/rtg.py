@@ -95,6 +95,9 @@ def lib() -> ctypes.CDLL:
                 "rtg_poll": [vp, u64, ctypes.POINTER(rtg_csr)],
                 "rtg_release": [vp, u64],
                 "rtg_make_transforms": [u64, i32, i32, u32, vp, vp],
+                "rtg_index_build": [vp, vp, i64, i32, f64, i32, f64, u64, u32,
+                                    ctypes.POINTER(u64)],
+                "rtg_index_query": [vp, u64, vp, i64, ctypes.POINTER(rtg_csr)],
                 "rtg_set_timing": [vp, u32],
                 "rtg_get_stats": [vp, ctypes.POINTER(rtg_stats)],
                 "rtg_debug_cell_coords": [vp, vp, i64, i32, f64, f64, vp, vp, vp],
@@ -292,6 +295,26 @@ class Context:
     def rtg_release(self, handle: int) -> None:
         _check(lib().rtg_release(self.h, handle), "rtg_release")
 
+    def rtg_index_build(self, points, r: float, k: int, alpha: float, seed: int,
+                        flags: int = 0) -> int:
+        """Sorts the k grids of `points` once and keeps them; returns the index
+        handle (free with release)."""
+        p = self._points(points)
+        h = ctypes.c_uint64()
+        _check(lib().rtg_index_build(self.h, p.data_ptr(), p.shape[0], p.shape[1], float(r),
+                                     int(k), float(alpha), seed & (2**64 - 1), flags,
+                                     ctypes.byref(h)), "rtg_index_build")
+        return int(h.value)
+
+    def rtg_index_query(self, index: int, queries) -> Result:
+        """Row s: the indexed points within r of queries[s] sharing a cell with it
+        under some grid (ascending)."""
+        q = self._points(queries)
+        out = rtg_csr()
+        _check(lib().rtg_index_query(self.h, index, q.data_ptr(), q.shape[0], ctypes.byref(out)),
+               "rtg_index_query")
+        return self._result(out)
+
     def rtg_set_timing(self, mask: int) -> None:
         """Bit i times kernel id i (KERNELS[i]); TIME_PHASES times the phases."""
         _check(lib().rtg_set_timing(self.h, int(mask) & 0xFFFFFFFF), "rtg_set_timing")
@@ -313,6 +336,8 @@ class Context:
         return kap
 
     # short aliases
+    index_build = rtg_index_build
+    index_query = rtg_index_query
     all_pairs = rtg_all_pairs
     all_pairs_with_transforms = rtg_all_pairs_with_transforms
     all_pairs_batched = rtg_all_pairs_batched
