@@ -125,6 +125,28 @@ def bench_batched(ctx, count: int, reps: int = 3) -> dict:
             "same_pairs_as_plain": pairs == pairs_plain}
 
 
+def bench_auto(ctx, pts, wl, target: float, mean_neighbours: float, reps: int = 10) -> dict:
+    """The workload with (k, alpha) chosen by the library for a target recall
+    (modelled), against its fixed parameters' modelled recall."""
+    import torch
+    from paper_1409_8112_amd import rtg
+    k, alpha, rec = rtg.choose_params(wl.d, target, mean_neighbours)
+    times, pairs = [], 0
+    for i in range(reps + 2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx.all_pairs(pts, wl.r, k, alpha, wl.seed)
+        pairs = res.pairs
+        res.release()
+        torch.cuda.synchronize()
+        if i >= 2:
+            times.append(time.perf_counter() - t0)
+    t = float(np.median(times))
+    return {"target_recall": target, "k": k, "alpha": alpha, "model_recall": rec,
+            "fixed_model_recall": rtg.model_recall(wl.d, wl.k, wl.alpha),
+            "ms": t * 1e3, "pairs": pairs, "pairs_per_s": pairs / t}
+
+
 def bench_query(ctx, pts, wl, m: int = 1_000_000, reps: int = 5) -> dict:
     """Query mode: an index of the workload's points (its k sorted grids),
     then m uniform query points per call."""
@@ -233,6 +255,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the request-loop measurement")
     ap.add_argument("--no-query", action="store_true", help="skip the query-mode measurement")
+    ap.add_argument("--no-auto", action="store_true",
+                    help="skip the run with parameters chosen for a target recall")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (a known-size "
                          "kernel for scaling hardware byte counters)")
@@ -353,6 +377,9 @@ def main(argv=None) -> int:
         "probe_kernel_ms": {name: probe["kernel_ms"][i] for i, name in enumerate(rtg.KERNELS)},
         "roofline": roof,
     }
+    if not args.no_auto and args.workload == "uniform_d6":
+        print("# parameters chosen for recall 0.98", file=sys.stderr, flush=True)
+        out["auto_params"] = bench_auto(ctx, pts, wl, 0.98, 20.0)
     if not args.no_query and args.workload == "uniform_d6":
         print("# query mode", file=sys.stderr, flush=True)
         out["query"] = bench_query(ctx, pts, wl)

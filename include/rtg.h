@@ -219,6 +219,32 @@ int rtg_index_query(rtg_ctx *ctx, uint64_t index, const float *queries, int64_t 
  * the "random orientation" of Sec. III.  Errors: RTG_EINVAL. */
 int rtg_make_transforms(uint64_t seed, int32_t k, int32_t d, uint32_t flags, double *R, double *u);
 
+/* Parameters for a target recall (Sec. III-A: the cell factor c~ = alpha
+ * and the number of grids m = k trade running time against the share of
+ * pairs found; Sec. V asks for choosing them automatically).
+ *
+ * Model: a pair at distance rho <= r, displaced along a direction u,
+ * shares a cell of side c = alpha r under one randomly shifted grid with
+ * probability prod_j (1 - rho |u_j| / c)_+; with random orientations that
+ * probability is averaged over directions and the k grids are independent.
+ * Neighbour pairs have locally uniform positions: rho has density
+ * d rho^(d-1) / r^d on [0, r] and u is uniform on the sphere.  Recall is
+ * E[1 - (1 - p)^k].  Cost, in units of one point under one grid, is
+ * k (1 + beta nu alpha^d / (2 zeta_d)), with nu the mean number of
+ * neighbours within r, zeta_d the unit-ball volume and beta the measured
+ * cost of one pair test relative to one point under one grid.
+ *
+ * Returns the (k, alpha) of least modelled cost whose modelled recall is at
+ * least target, alpha on a grid of step 1/32 in [0.5, 4]; *recall receives
+ * the modelled recall.  flags: RTG_NO_ROTATE (shift-only grids).  Host only.
+ * Errors: RTG_EINVAL (d outside [1, 64], target outside (0, 1),
+ * mean_neighbours <= 0), RTG_ERANGE (target not reached with k <= 1024). */
+int rtg_choose_params(int32_t d, double target_recall, double mean_neighbours, uint32_t flags,
+                      int32_t *k, double *alpha, double *recall);
+
+/* The modelled recall of (k, alpha) (see rtg_choose_params).  Host only. */
+int rtg_model_recall(int32_t d, int32_t k, double alpha, uint32_t flags, double *recall);
+
 /* Device timing with HIP events on the context's stream: bit i of `mask`
  * times every launch of kernel id i (RTG_K_*), RTG_TIME_PHASES times the
  * pipeline phases; 0 turns timing off.  Events add a few microseconds per

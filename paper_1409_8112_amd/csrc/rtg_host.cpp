@@ -1395,6 +1395,130 @@ int Ctx::debug_cell_coords(const float* points, int64_t n, int32_t d, double r, 
 }
 
 // ---------------------------------------------------------------------------
+// parameter choice
+
+namespace {
+
+// Quadrature of the recall model: radii at the midpoints of v in [0, 1]
+// with rho / r = v^(1/d) (which turns the density d x^(d-1) into a uniform
+// one), directions from a fixed SplitMix64 stream of Gaussian vectors.
+constexpr int kModelRadii = 48;
+constexpr int kModelDirs = 2048;
+constexpr int kModelDirsFixed = 512;  // directions kept per radius for shift-only grids
+
+struct RecallModel {
+  int d = 0;
+  std::vector<double> x;      // rho / r at the quadrature radii
+  std::vector<double> dirs;   // [kModelDirs][d] |u_j| of unit directions
+
+  explicit RecallModel(int dim) : d(dim) {
+    for (int i = 0; i < kModelRadii; ++i)
+      x.push_back(std::pow((i + 0.5) / kModelRadii, 1.0 / d));
+    SplitMix64 g{0x5EEDC0FFEEull + (uint64_t)d};
+    dirs.resize((size_t)kModelDirs * d);
+    for (int q = 0; q < kModelDirs; ++q) {
+      double nrm = 0.0;
+      for (int j = 0; j < d; j += 2) {
+        double pr[2];
+        polar_normals(g, pr);
+        for (int e = 0; e < 2 && j + e < d; ++e) {
+          dirs[(size_t)q * d + j + e] = pr[e];
+          nrm += pr[e] * pr[e];
+        }
+      }
+      nrm = std::sqrt(nrm);
+      for (int j = 0; j < d; ++j) dirs[(size_t)q * d + j] = std::fabs(dirs[(size_t)q * d + j]) / nrm;
+    }
+  }
+
+  // P(one grid holds the pair) for displacement x * r along direction q
+  double cocell(int q, double xr_over_c) const {
+    double p = 1.0;
+    for (int j = 0; j < d && p > 0.0; ++j) p *= std::max(0.0, 1.0 - xr_over_c * dirs[(size_t)q * d + j]);
+    return p;
+  }
+
+  // One-grid probabilities at the quadrature radii for cell factor alpha:
+  // averaged over directions (rotate), else per (radius, direction).
+  std::vector<double> probs(double alpha, bool rotate) const {
+    std::vector<double> p(rotate ? x.size() : x.size() * kModelDirsFixed, 0.0);
+    for (size_t i = 0; i < x.size(); ++i) {
+      const double s = x[i] / alpha;
+      if (rotate) {
+        for (int q = 0; q < kModelDirs; ++q) p[i] += cocell(q, s) / kModelDirs;
+      } else {
+        for (int q = 0; q < kModelDirsFixed; ++q) p[i * kModelDirsFixed + q] = cocell(q, s);
+      }
+    }
+    return p;
+  }
+
+  // E[1 - (1 - p)^k] over the quadrature (p from probs()).
+  static double recall_of(const std::vector<double>& p, int k, bool rotate) {
+    double acc = 0.0;
+    for (double pi : p) acc += 1.0 - std::pow(1.0 - pi, k);
+    return acc / (double)(rotate ? kModelRadii : (size_t)kModelRadii * kModelDirsFixed);
+  }
+
+  double recall(int k, double alpha, bool rotate) const {
+    return recall_of(probs(alpha, rotate), k, rotate);
+  }
+};
+
+// Relative cost of one pair test against one point under one grid, from the
+// measured time split of the uniform d6 benchmark (keys, sort, cells and
+// lists per point-grid against the pair screen per test).
+constexpr double kTestCost = 0.0134;
+
+double unit_ball_volume(int d) { return std::pow(M_PI, d / 2.0) / std::tgamma(d / 2.0 + 1.0); }
+
+}  // namespace
+
+int model_recall(int32_t d, int32_t k, double alpha, uint32_t flags, double* recall) {
+  if (d < 1 || d > kMaxDim || k < 1 || !(alpha > 0.0) || !std::isfinite(alpha) || !recall)
+    return RTG_EINVAL;
+  RecallModel M(d);
+  *recall = M.recall(k, alpha, !(flags & RTG_NO_ROTATE));
+  return RTG_OK;
+}
+
+int choose_params(int32_t d, double target, double nu, uint32_t flags, int32_t* k_out,
+                  double* alpha_out, double* recall_out) {
+  if (d < 1 || d > kMaxDim || !(target > 0.0 && target < 1.0) || !(nu > 0.0) ||
+      !std::isfinite(nu) || !k_out || !alpha_out || !recall_out)
+    return RTG_EINVAL;
+  const bool rotate = !(flags & RTG_NO_ROTATE);
+  RecallModel M(d);
+  const double zeta = unit_ball_volume(d);
+  double best = INFINITY, best_alpha = 0.0, best_recall = 0.0;
+  int best_k = 0;
+  for (int a = 32; a <= 256; a += 2) {
+    const double alpha = a / 64.0;
+    const std::vector<double> p = M.probs(alpha, rotate);
+    // least k reaching the target: recall rises with k (bisection)
+    int lo = 1, hi = 1024;
+    if (RecallModel::recall_of(p, hi, rotate) < target) continue;
+    while (lo < hi) {
+      const int mid = (lo + hi) / 2;
+      if (RecallModel::recall_of(p, mid, rotate) >= target) hi = mid;
+      else lo = mid + 1;
+    }
+    const double cost = lo * (1.0 + kTestCost * nu * std::pow(alpha, d) / (2.0 * zeta));
+    if (cost < best) {
+      best = cost;
+      best_k = lo;
+      best_alpha = alpha;
+      best_recall = RecallModel::recall_of(p, lo, rotate);
+    }
+  }
+  if (!best_k) return RTG_ERANGE;
+  *k_out = best_k;
+  *alpha_out = best_alpha;
+  *recall_out = best_recall;
+  return RTG_OK;
+}
+
+// ---------------------------------------------------------------------------
 // query mode
 
 // The sorted grids of one point set (steps A1-A3 of the pipeline, single
@@ -1767,6 +1891,15 @@ int rtg_index_query(rtg_ctx* ctx, uint64_t index, const float* queries, int64_t 
   const int rc = c->main.query_index(*I, queries, m, st, out);
   if (!rc) c->stats = st;
   return rc;
+}
+
+int rtg_choose_params(int32_t d, double target_recall, double mean_neighbours, uint32_t flags,
+                      int32_t* k, double* alpha, double* recall) {
+  return rtg::choose_params(d, target_recall, mean_neighbours, flags, k, alpha, recall);
+}
+
+int rtg_model_recall(int32_t d, int32_t k, double alpha, uint32_t flags, double* recall) {
+  return rtg::model_recall(d, k, alpha, flags, recall);
 }
 
 int rtg_make_transforms(uint64_t seed, int32_t k, int32_t d, uint32_t flags, double* R, double* u) {

@@ -50,6 +50,9 @@ struct Packing {
 };
 
 int make_transforms(uint64_t seed, int32_t k, int32_t d, uint32_t flags, double* R, double* u);
+int model_recall(int32_t d, int32_t k, double alpha, uint32_t flags, double* recall);
+int choose_params(int32_t d, double target, double nu, uint32_t flags, int32_t* k_out,
+                  double* alpha_out, double* recall_out);
 int min_field_bits(double alpha);
 int validate_query(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha);
 int check_device_pointer(const void* p, int device);

@@ -95,6 +95,9 @@ def lib() -> ctypes.CDLL:
                 "rtg_poll": [vp, u64, ctypes.POINTER(rtg_csr)],
                 "rtg_release": [vp, u64],
                 "rtg_make_transforms": [u64, i32, i32, u32, vp, vp],
+                "rtg_choose_params": [i32, f64, f64, u32, ctypes.POINTER(i32),
+                                      ctypes.POINTER(f64), ctypes.POINTER(f64)],
+                "rtg_model_recall": [i32, i32, f64, u32, ctypes.POINTER(f64)],
                 "rtg_index_build": [vp, vp, i64, i32, f64, i32, f64, u64, u32,
                                     ctypes.POINTER(u64)],
                 "rtg_index_query": [vp, u64, vp, i64, ctypes.POINTER(rtg_csr)],
@@ -131,6 +134,23 @@ def rtg_make_transforms(seed: int, k: int, d: int, flags: int = 0):
 
 
 make_transforms = rtg_make_transforms
+
+
+def choose_params(d: int, target_recall: float, mean_neighbours: float, flags: int = 0):
+    """(k, alpha, modelled recall) of least modelled cost reaching the target."""
+    k, a, rc = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().rtg_choose_params(int(d), float(target_recall), float(mean_neighbours), flags,
+                                   ctypes.byref(k), ctypes.byref(a), ctypes.byref(rc)),
+           "rtg_choose_params")
+    return int(k.value), float(a.value), float(rc.value)
+
+
+def model_recall(d: int, k: int, alpha: float, flags: int = 0) -> float:
+    """The modelled recall of k grids of cell factor alpha in dimension d."""
+    rc = ctypes.c_double()
+    _check(lib().rtg_model_recall(int(d), int(k), float(alpha), flags, ctypes.byref(rc)),
+           "rtg_model_recall")
+    return float(rc.value)
 
 
 @dataclass
