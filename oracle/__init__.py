@@ -18,6 +18,12 @@ from .build import LIB_PATH, build
 
 OK, EINVAL, ENOMEM, ERANGE = 0, -1, -2, -3
 NO_ROTATE, UPPER_ONLY = 1, 2
+ROBOTS_SHIFT = 8
+
+
+def robots(b: int) -> int:
+    """Flag bits selecting the MR-metric over b robots (Sec. IV-C)."""
+    return int(b) << ROBOTS_SHIFT
 
 _lib = None
 
@@ -38,7 +44,8 @@ def lib() -> ctypes.CDLL:
     """Load the oracle library, building it first if it has not been built."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        src = [os.path.join(os.path.dirname(LIB_PATH), f) for f in ("rtg_oracle.c", "rtg_oracle.h")]
+        if not os.path.exists(LIB_PATH) or max(map(os.path.getmtime, src)) > os.path.getmtime(LIB_PATH):
             build()
         L = ctypes.CDLL(LIB_PATH)
         f64p = ctypes.POINTER(ctypes.c_double)
@@ -66,20 +73,20 @@ def lib() -> ctypes.CDLL:
                                  ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
                                  ctypes.c_uint32, resp]
         L.oracle_rtg_rows.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
-                                      ctypes.c_int32, ctypes.c_double, f64p, f64p, i64p,
-                                      ctypes.c_int64, resp]
+                                      ctypes.c_int32, ctypes.c_double, f64p, f64p,
+                                      ctypes.c_uint32, i64p, ctypes.c_int64, resp]
         L.oracle_bruteforce.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
                                         ctypes.c_uint32, resp]
         L.oracle_rtg_query.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, f32p, ctypes.c_int64,
                                        ctypes.c_double, ctypes.c_int32, ctypes.c_double, f64p,
-                                       f64p, resp]
+                                       f64p, ctypes.c_uint32, resp]
         L.oracle_result_free.argtypes = [ctypes.POINTER(_Result)]
         L.oracle_result_free.restype = None
         L.oracle_free.argtypes = [ctypes.c_void_p]
         L.oracle_free.restype = None
         for name in ("oracle_make_transforms", "oracle_cell_coords", "oracle_transform_pairs",
                      "oracle_rtg_with_transforms", "oracle_rtg", "oracle_rtg_rows",
-                     "oracle_bruteforce"):
+                     "oracle_bruteforce", "oracle_rtg_query"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -216,9 +223,9 @@ def rtg(points, r: float, k: int, alpha: float, seed: int, flags: int = 0) -> CS
     return _take_result(res)
 
 
-def rtg_rows(points, r: float, alpha: float, R, u, rows) -> list[np.ndarray]:
+def rtg_rows(points, r: float, alpha: float, R, u, rows, flags: int = 0) -> list[np.ndarray]:
     """Neighbour lists (ascending int32) of the given rows of the symmetric RTG
-    output, each computed on its own."""
+    output, each computed on its own (flags: robots(b) for the MR-metric)."""
     p = _points(points)
     n, d = p.shape
     R = np.ascontiguousarray(R, dtype=np.float64)
@@ -229,7 +236,7 @@ def rtg_rows(points, r: float, alpha: float, R, u, rows) -> list[np.ndarray]:
     rows = np.ascontiguousarray(rows, dtype=np.int64)
     res = ctypes.POINTER(_Result)()
     rc = lib().oracle_rtg_rows(_ptr(p, ctypes.c_float), n, d, float(r), k, float(alpha),
-                               _ptr(R, ctypes.c_double), _ptr(u, ctypes.c_double),
+                               _ptr(R, ctypes.c_double), _ptr(u, ctypes.c_double), flags,
                                _ptr(rows, ctypes.c_int64), len(rows), ctypes.byref(res))
     if rc != OK:
         raise OracleError(rc, "oracle_rtg_rows")
@@ -237,9 +244,10 @@ def rtg_rows(points, r: float, alpha: float, R, u, rows) -> list[np.ndarray]:
     return [csr.col[csr.row_ptr[s]:csr.row_ptr[s + 1]] for s in range(len(rows))]
 
 
-def rtg_query(points, queries, r: float, alpha: float, R, u) -> CSR:
+def rtg_query(points, queries, r: float, alpha: float, R, u, flags: int = 0) -> CSR:
     """Query mode: row s lists the indexed points within r of queries[s] that
-    share a cell with it under some transform (ascending, once each)."""
+    share a cell with it under some transform (ascending, once each); flags:
+    robots(b) for the MR-metric."""
     p = _points(points)
     q = _points(queries)
     n, d = p.shape
@@ -253,7 +261,7 @@ def rtg_query(points, queries, r: float, alpha: float, R, u) -> CSR:
     res = ctypes.POINTER(_Result)()
     rc = lib().oracle_rtg_query(_ptr(p, ctypes.c_float), n, d, _ptr(q, ctypes.c_float), len(q),
                                 float(r), k, float(alpha), _ptr(R, ctypes.c_double),
-                                _ptr(u, ctypes.c_double), ctypes.byref(res))
+                                _ptr(u, ctypes.c_double), flags, ctypes.byref(res))
     if rc != OK:
         raise OracleError(rc, "oracle_rtg_query")
     return _take_result(res)

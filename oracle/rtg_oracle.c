@@ -144,19 +144,59 @@ int oracle_cell_coords(const float *points, int64_t n, int32_t d,
 }
 
 /* ------------------------------------------------------------------------ */
-/* The pair test: squared distance in FP64, axis order, reported iff <= r^2. */
+/* The pair test.
+ *   Euclidean metric (Sec. I): s = sum over axes, in axis order, of
+ *   ((double)p_l - (double)q_l)^2; the pair is within r iff s <= r*r.
+ *   MR-metric (Sec. IV-C, several robots moving at once): the configuration
+ *   holds `robots` robots of d / robots consecutive axes each, and the
+ *   distance is the sum, in robot order, of every robot's own Euclidean
+ *   displacement -- the FP64 square root of that robot's squared displacement,
+ *   summed in axis order as above; the pair is within r iff the sum <= r. */
+typedef struct {
+  double r, r2;
+  int32_t d;
+  int32_t sub; /* axes per robot; 0: the Euclidean metric */
+} pair_metric;
 
-static int within_r(const float *points, int32_t d, int64_t a, int64_t b,
-                    double r2) {
-  const float *pa = points + (size_t)a * d;
-  const float *pb = points + (size_t)b * d;
+/* The metric that `flags` selects (ORACLE_ROBOTS(b), b >= 2, dividing d). */
+static int make_metric(double r, int32_t d, uint32_t flags, pair_metric *mt) {
+  uint32_t robots = (flags & ORACLE_ROBOTS_MASK) >> ORACLE_ROBOTS_SHIFT;
+  mt->r = r;
+  mt->r2 = r * r;
+  mt->d = d;
+  mt->sub = 0;
+  if (robots <= 1) return ORACLE_OK;
+  if (robots > (uint32_t)d || d % (int32_t)robots != 0) return ORACLE_EINVAL;
+  mt->sub = d / (int32_t)robots;
+  return ORACLE_OK;
+}
+
+static int within_metric(const pair_metric *mt, const float *pa,
+                         const float *pb) {
   double s = 0.0;
-  int32_t l;
-  for (l = 0; l < d; ++l) {
-    double delta = (double)pa[l] - (double)pb[l];
-    s = s + delta * delta;
+  int32_t l, b;
+  if (mt->sub == 0) {
+    for (l = 0; l < mt->d; ++l) {
+      double delta = (double)pa[l] - (double)pb[l];
+      s = s + delta * delta;
+    }
+    return s <= mt->r2;
   }
-  return s <= r2;
+  for (b = 0; b < mt->d; b += mt->sub) {
+    double t = 0.0;
+    for (l = b; l < b + mt->sub; ++l) {
+      double delta = (double)pa[l] - (double)pb[l];
+      t = t + delta * delta;
+    }
+    s = s + sqrt(t);
+  }
+  return s <= mt->r;
+}
+
+static int within_r(const pair_metric *mt, const float *points, int64_t a,
+                    int64_t b) {
+  return within_metric(mt, points + (size_t)a * mt->d,
+                       points + (size_t)b * mt->d);
 }
 
 /* Growable array of (i,j) index pairs. */
@@ -229,9 +269,9 @@ static int same_cell(const int64_t *kappa, int32_t d, int64_t a, int64_t b) {
 
 /* One grid of Alg. Randomly Shifted Grids: cells of every point, then every
  * pair inside each non-empty cell; reported pairs are appended to pv. */
-static int one_grid(const float *points, int64_t n, int32_t d, double r2,
-                    double inv_c, const double *R, const double *u,
-                    pair_vec *pv) {
+static int one_grid(const float *points, int64_t n, int32_t d,
+                    const pair_metric *mt, double inv_c, const double *R,
+                    const double *u, pair_vec *pv) {
   int64_t *kappa, *order, g0, g1, a, b;
   cell_order co;
   int rc;
@@ -258,7 +298,7 @@ static int one_grid(const float *points, int64_t n, int32_t d, double r2,
     for (a = g0; a < g1; ++a)
       for (b = a + 1; b < g1; ++b) {
         int64_t i = order[a], j = order[b]; /* i < j: ties sorted by index */
-        if (within_r(points, d, i, j, r2)) {
+        if (within_r(mt, points, i, j)) {
           rc = pv_push(pv, i, j);
           if (rc != ORACLE_OK) goto done;
         }
@@ -340,7 +380,9 @@ int oracle_transform_pairs(const float *points, int64_t n, int32_t d, double r,
   if (rc != ORACLE_OK) return rc;
   if (n >= 2) {
     double c = alpha * r;
-    rc = one_grid(points, n, d, r * r, 1.0 / c, R, u, &pv);
+    pair_metric mt;
+    make_metric(r, d, 0u, &mt);
+    rc = one_grid(points, n, d, &mt, 1.0 / c, R, u, &pv);
     if (rc != ORACLE_OK) {
       free(pv.v);
       return rc;
@@ -357,18 +399,19 @@ int oracle_rtg_with_transforms(const float *points, int64_t n, int32_t d,
                                const double *R, const double *u, uint32_t flags,
                                oracle_result **out) {
   pair_vec pv = {NULL, 0, 0};
+  pair_metric mt;
   int32_t t;
   int rc = check_points(points, n, d);
   if (rc == ORACLE_OK) rc = check_radius(r);
   if (rc == ORACLE_OK && (k < 1 || !(isfinite(alpha) && alpha > 0.0)))
     rc = ORACLE_EINVAL;
+  if (rc == ORACLE_OK) rc = make_metric(r, d, flags, &mt);
   if (rc != ORACLE_OK) return rc;
   if (n >= 2) {
-    double r2 = r * r;
     double c = alpha * r;
     double inv_c = 1.0 / c;
     for (t = 0; t < k; ++t) {
-      rc = one_grid(points, n, d, r2, inv_c, R + (size_t)t * d * d,
+      rc = one_grid(points, n, d, &mt, inv_c, R + (size_t)t * d * d,
                     u + (size_t)t * d, &pv);
       if (rc != ORACLE_OK) {
         free(pv.v);
@@ -409,8 +452,10 @@ int oracle_rtg(const float *points, int64_t n, int32_t d, double r, int32_t k,
 
 int oracle_rtg_rows(const float *points, int64_t n, int32_t d, double r,
                     int32_t k, double alpha, const double *R, const double *u,
-                    const int64_t *rows, int64_t nrows, oracle_result **out) {
+                    uint32_t flags, const int64_t *rows, int64_t nrows,
+                    oracle_result **out) {
   pair_vec pv = {NULL, 0, 0};
+  pair_metric mt;
   int64_t *kappa = NULL;
   int64_t q, s;
   int32_t t;
@@ -418,11 +463,11 @@ int oracle_rtg_rows(const float *points, int64_t n, int32_t d, double r,
   if (rc == ORACLE_OK) rc = check_radius(r);
   if (rc == ORACLE_OK && (k < 1 || !(isfinite(alpha) && alpha > 0.0) || nrows < 0))
     rc = ORACLE_EINVAL;
+  if (rc == ORACLE_OK) rc = make_metric(r, d, flags, &mt);
   for (s = 0; rc == ORACLE_OK && s < nrows; ++s)
     if (rows[s] < 0 || rows[s] >= n) rc = ORACLE_EINVAL;
   if (rc != ORACLE_OK) return rc;
   if (n >= 2 && nrows > 0) {
-    double r2 = r * r;
     double inv_c = 1.0 / (alpha * r);
     kappa = (int64_t *)malloc(sizeof(int64_t) * (size_t)n * (size_t)d);
     if (kappa == NULL) return ORACLE_ENOMEM;
@@ -433,7 +478,7 @@ int oracle_rtg_rows(const float *points, int64_t n, int32_t d, double r,
       for (s = 0; s < nrows; ++s)
         for (q = 0; q < n; ++q)
           if (q != rows[s] && same_cell(kappa, d, rows[s], q) &&
-              within_r(points, d, rows[s], q, r2)) {
+              within_r(&mt, points, rows[s], q)) {
             rc = pv_push(&pv, s, q); /* (output row, neighbour) */
             if (rc != ORACLE_OK) goto fail;
           }
@@ -450,22 +495,12 @@ fail:
   return rc;
 }
 
-/* The pair test between a query row and a point row. */
-static int within_r_rows(const float *pa, const float *pb, int32_t d, double r2) {
-  double s = 0.0;
-  int32_t l;
-  for (l = 0; l < d; ++l) {
-    double delta = (double)pa[l] - (double)pb[l];
-    s = s + delta * delta;
-  }
-  return s <= r2;
-}
-
 int oracle_rtg_query(const float *points, int64_t n, int32_t d,
                      const float *queries, int64_t m, double r, int32_t k,
                      double alpha, const double *R, const double *u,
-                     oracle_result **out) {
+                     uint32_t flags, oracle_result **out) {
   pair_vec pv = {NULL, 0, 0};
+  pair_metric mt;
   int64_t *kp = NULL, *kq = NULL;
   int64_t s, i;
   int32_t t, j;
@@ -474,9 +509,9 @@ int oracle_rtg_query(const float *points, int64_t n, int32_t d,
   if (rc == ORACLE_OK) rc = check_radius(r);
   if (rc == ORACLE_OK && (k < 1 || !(isfinite(alpha) && alpha > 0.0)))
     rc = ORACLE_EINVAL;
+  if (rc == ORACLE_OK) rc = make_metric(r, d, flags, &mt);
   if (rc != ORACLE_OK) return rc;
   if (n >= 1 && m >= 1) {
-    double r2 = r * r;
     double inv_c = 1.0 / (alpha * r);
     kp = (int64_t *)malloc(sizeof(int64_t) * (size_t)n * (size_t)d);
     kq = (int64_t *)malloc(sizeof(int64_t) * (size_t)m * (size_t)d);
@@ -497,8 +532,8 @@ int oracle_rtg_query(const float *points, int64_t n, int32_t d,
           int same = 1;
           for (j = 0; j < d && same; ++j)
             same = kq[(size_t)s * d + j] == kp[(size_t)i * d + j];
-          if (same && within_r_rows(queries + (size_t)s * d,
-                                    points + (size_t)i * d, d, r2)) {
+          if (same && within_metric(&mt, queries + (size_t)s * d,
+                                    points + (size_t)i * d)) {
             rc = pv_push(&pv, s, i); /* (query row, indexed point) */
             if (rc != ORACLE_OK) goto done;
           }
@@ -517,13 +552,15 @@ done:
 int oracle_bruteforce(const float *points, int64_t n, int32_t d, double r,
                       uint32_t flags, oracle_result **out) {
   pair_vec pv = {NULL, 0, 0};
+  pair_metric mt;
   int64_t i, j;
   int rc = check_points(points, n, d);
   if (rc == ORACLE_OK) rc = check_radius(r);
+  if (rc == ORACLE_OK) rc = make_metric(r, d, flags, &mt);
   if (rc != ORACLE_OK) return rc;
   for (i = 0; i < n; ++i)
     for (j = i + 1; j < n; ++j)
-      if (within_r(points, d, i, j, r * r)) {
+      if (within_r(&mt, points, i, j)) {
         rc = pv_push(&pv, i, j);
         if (rc != ORACLE_OK) {
           free(pv.v);

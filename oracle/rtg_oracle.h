@@ -19,7 +19,9 @@
  *     a uniformly random orientation;
  *   - pairs reported by several grids are reported once (Sec. III-B), and
  *     every pair is stored in both orientations so that the per-point
- *     neighbour lists answer multiple r-NN queries (Sec. III-B).
+ *     neighbour lists answer multiple r-NN queries (Sec. III-B);
+ *   - the MR-metric of the multi-robot experiments (Sec. IV-C) as an
+ *     alternative pair test on the same Euclidean grids.
  *
  * Parameter names: the paper's m (number of grids) is `k` here and its
  * cell-size factor c~ is `alpha`; the grid cell side is alpha * r.
@@ -40,7 +42,10 @@
  *     whose rows are orthonormalised by modified Gram-Schmidt applied twice;
  *   - pairs are by index; coincident points are reported (distance 0) and a
  *     point is never paired with itself;
- *   - the output is a canonical CSR: rows ascending, columns ascending.
+ *   - the output is a canonical CSR: rows ascending, columns ascending;
+ *   - the MR-metric's robots are equal blocks of consecutive axes, and the
+ *     grids stay Euclidean: only the pair test changes (the paper names the
+ *     metric but not how the grids treat it).
  */
 #ifndef RTG_ORACLE_H
 #define RTG_ORACLE_H
@@ -62,6 +67,16 @@ enum {
   ORACLE_NO_ROTATE = 1u,  /* shift-only grids (the paper's first algorithm) */
   ORACLE_UPPER_ONLY = 2u  /* store (i,j) in row i only, j > i              */
 };
+
+/* The MR-metric of Sec. IV-C: ORACLE_ROBOTS(b) in flags, b in [2, d] dividing
+ * d, splits a configuration into b robots of d / b consecutive axes each and
+ * measures the distance of two configurations as the sum of the robots'
+ * Euclidean displacements (each an FP64 square root of the robot's squared
+ * displacement summed in axis order); a pair is within r iff that sum <= r.
+ * The grids stay those of the Euclidean method.  b = 0 or 1: Euclidean. */
+#define ORACLE_ROBOTS_SHIFT 8
+#define ORACLE_ROBOTS_MASK 0xFF00u
+#define ORACLE_ROBOTS(b) ((uint32_t)(b) << ORACLE_ROBOTS_SHIFT)
 
 /* A neighbour list in CSR form, owned by the oracle (free with
  * oracle_result_free).  row_ptr has n+1 entries, col has nnz entries. */
@@ -101,7 +116,8 @@ int oracle_transform_pairs(const float *points, int64_t n, int32_t d, double r,
                            double alpha, const double *R, const double *u,
                            int64_t **pairs, int64_t *npairs);
 
-/* Full RTG with caller-given transforms (R [k][d][d], u [k][d]). */
+/* Full RTG with caller-given transforms (R [k][d][d], u [k][d]).  flags:
+ * ORACLE_UPPER_ONLY, ORACLE_ROBOTS(b) (NO_ROTATE is not used: R is given). */
 int oracle_rtg_with_transforms(const float *points, int64_t n, int32_t d,
                                double r, int32_t k, double alpha,
                                const double *R, const double *u, uint32_t flags,
@@ -114,25 +130,29 @@ int oracle_rtg(const float *points, int64_t n, int32_t d, double r, int32_t k,
 
 /* The rows `rows[0..nrows)` of the symmetric RTG neighbour list, computed one
  * by one: q is a neighbour of row s iff q != s, some transform puts q and s
- * in the same cell, and ||q - s|| <= r.  Same transforms as
- * oracle_rtg_with_transforms; result rows follow the order of `rows`. */
+ * in the same cell, and q is within r of s (the metric of flags).  Same
+ * transforms as oracle_rtg_with_transforms; result rows follow the order of
+ * `rows`.  flags: ORACLE_ROBOTS(b). */
 int oracle_rtg_rows(const float *points, int64_t n, int32_t d, double r,
                     int32_t k, double alpha, const double *R, const double *u,
-                    const int64_t *rows, int64_t nrows, oracle_result **out);
+                    uint32_t flags, const int64_t *rows, int64_t nrows,
+                    oracle_result **out);
 
 /* Query mode: the same grids answer r-NN queries for new points.  Row s of
  * the result lists, ascending and once each, the indexed points p_i with
  * ||p_i - q_s|| <= r (FP64, axis order, as for pairs) that share a cell with
  * q_s under some transform -- q_s takes the role of one more point of the
  * set (a query equal to p_i reports i).  Transforms as in
- * oracle_rtg_with_transforms.  ORACLE_ERANGE if a cell coordinate of a point
- * or a query has |y| >= 2^31. */
+ * oracle_rtg_with_transforms; flags: ORACLE_ROBOTS(b) (the distance test is
+ * then the MR-metric's).  ORACLE_ERANGE if a cell coordinate of a point or a
+ * query has |y| >= 2^31. */
 int oracle_rtg_query(const float *points, int64_t n, int32_t d,
                      const float *queries, int64_t m, double r, int32_t k,
                      double alpha, const double *R, const double *u,
-                     oracle_result **out);
+                     uint32_t flags, oracle_result **out);
 
-/* Exact all-pairs r-NN by testing every pair (the set RTG approximates). */
+/* Exact all-pairs r-NN by testing every pair (the set RTG approximates).
+ * flags: ORACLE_UPPER_ONLY, ORACLE_ROBOTS(b). */
 int oracle_bruteforce(const float *points, int64_t n, int32_t d, double r,
                       uint32_t flags, oracle_result **out);
 

@@ -53,3 +53,21 @@ def exact_within(a, b, r: float) -> bool:
     and the double r (no rounding anywhere)."""
     s = sum((Fraction(float(x)) - Fraction(float(y))) ** 2 for x, y in zip(a, b))
     return s <= Fraction(float(r)) ** 2
+
+
+def mr_margin(a, b, r: float, robots: int) -> float:
+    """sum over robots of ||a_b - b_b|| minus r for the MR-metric (robots of
+    d / robots consecutive axes each), from the exact squared displacements
+    of the float32 inputs with 60-digit decimal square roots: its sign
+    decides the MR test unless it is within about 1e-55 of zero."""
+    from decimal import Decimal, localcontext
+    a = [Fraction(float(x)) for x in a]
+    b = [Fraction(float(x)) for x in b]
+    sub = len(a) // robots
+    with localcontext() as ctx:
+        ctx.prec = 60
+        total = Decimal(0)
+        for q in range(robots):
+            s = sum((x - y) ** 2 for x, y in zip(a[q * sub:(q + 1) * sub], b[q * sub:(q + 1) * sub]))
+            total += (Decimal(s.numerator) / Decimal(s.denominator)).sqrt()
+        return float(total - Decimal(float(r)))
