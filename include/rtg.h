@@ -20,7 +20,11 @@
  * no FMA, and the test s <= r*r where s sums ((double)p_l - (double)q_l)^2 in
  * axis order.  The GPU screens pairs in FP32 and re-tests in that FP64 order
  * every pair whose FP32 squared distance lies within a relative 2^-16 of r^2,
- * so no decision differs from the FP64 one.
+ * so no decision differs from the FP64 one.  Under the MR-metric
+ * (RTG_ROBOTS) the test is sum_b sqrt(s_b) <= r, s_b each robot's squared
+ * displacement summed as above, square roots correctly rounded, sum in robot
+ * order; the FP32 screen then only rejects pairs beyond r in the Euclidean
+ * sense, and every other pair is decided in FP64.
  *
  * Output.  A CSR neighbour list in device memory: row_ptr[n+1] (int64) and
  * col[nnz] (int32); row i lists its neighbours in ascending order.  By default
@@ -61,6 +65,18 @@ enum {
                        /* pairs) and dropping equal neighbours, instead of the  */
                        /* default first-owner rule; same result                 */
 };
+
+/* The MR-metric of the multi-robot experiments (Sec. IV-C): RTG_ROBOTS(b) in
+ * flags, b in [2, d] dividing d, reads each point as the configuration of b
+ * robots of d / b consecutive axes each, and the distance of two
+ * configurations as the sum of the distances the robots move (each robot's
+ * Euclidean displacement).  The grids are the Euclidean ones: since that sum
+ * is at least the Euclidean distance, every MR neighbour is a Euclidean
+ * neighbour, and only the pair test changes.  b = 0 or 1: Euclidean.  Any
+ * other b, or a flag bit this header does not define, is RTG_EINVAL. */
+#define RTG_ROBOTS_SHIFT 8
+#define RTG_ROBOTS_MASK 0xFF00u
+#define RTG_ROBOTS(b) ((uint32_t)(b) << RTG_ROBOTS_SHIFT)
 
 typedef struct rtg_ctx rtg_ctx;
 
@@ -156,7 +172,7 @@ int rtg_destroy(rtg_ctx *ctx);
  *   points: device pointer, row-major [n][d] FP32, 4-byte aligned.
  *   n in [0, 2^31); d in [1, 64]; r > 0 finite; k >= 1; alpha > 0 finite.
  *   seed selects the k transforms (see rtg_make_transforms).
- *   flags: RTG_NO_ROTATE, RTG_UPPER_ONLY.
+ *   flags: RTG_NO_ROTATE, RTG_UPPER_ONLY, RTG_DEDUP_SORT, RTG_ROBOTS(b).
  * n <= 1 gives an empty list.  Errors: RTG_EINVAL (also for NaN/Inf
  * coordinates), RTG_ERANGE, RTG_ENOMEM, RTG_EDEVICE. */
 int rtg_all_pairs(rtg_ctx *ctx, const float *points, int64_t n, int32_t d, double r, int32_t k,
@@ -195,7 +211,8 @@ int rtg_release(rtg_ctx *ctx, uint64_t handle);
  * once -- the transforms, cell keys and sort of rtg_all_pairs -- and keeps
  * them, a copy of the points and their signatures in the context under
  * *index (free with rtg_release).  Arguments and errors as rtg_all_pairs;
- * flags: RTG_NO_ROTATE.
+ * flags: RTG_NO_ROTATE, RTG_ROBOTS(b) (the queries' distance test is then
+ * the MR-metric's; list flags are ignored).
  *
  * rtg_index_query answers m query points (device, row-major [m][d] FP32,
  * the index's d): row s of the result lists, ascending and once each, the

@@ -177,6 +177,17 @@ PairTest make_pair_test(double r2, int pair_bits) {
   return t;
 }
 
+// The squared radius of the Euclidean test that finds the candidates of an
+// MR-metric query.  A pair within r under the MR-metric in FP64 has
+// Euclidean distance at most its exact MR distance (triangle inequality),
+// which is at most r (1 + (2 d + 4) 2^-53); its FP64 squared distance is then
+// at most r*r (1 + (5 d + 12) 2^-53) < r*r (1 + 2^-40) for d <= 64, so the
+// Euclidean test against this radius keeps every MR neighbour.
+double mr_screen_r2(double r) {
+  const double x = (r * r) * (1.0 + 0x1p-40);
+  return std::nextafter(x, INFINITY);
+}
+
 // Whether the matrix-core pair screen suits an instance: its band, relative
 // to r^2, is about (2K + d + 8) * 1.5 * 2^-24 * 2 d alpha^2 for cells of side
 // alpha r (K = d + 2 rounded up to even); up to 2^-8 it sends few pairs to
@@ -542,6 +553,15 @@ int check_device_pointer(const void* p, int device) {
   return RTG_OK;
 }
 
+int axes_per_robot(int32_t d, uint32_t flags) {
+  constexpr uint32_t known = RTG_NO_ROTATE | RTG_UPPER_ONLY | RTG_DEDUP_SORT | RTG_ROBOTS_MASK;
+  if (flags & ~known) return -1;
+  const int robots = (int)((flags & RTG_ROBOTS_MASK) >> RTG_ROBOTS_SHIFT);
+  if (robots <= 1) return 0;
+  if (d < 1 || robots > d || d % robots) return -1;
+  return d / robots;
+}
+
 int validate_query(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha) {
   if (d < 1 || d > kMaxDim || k < 1 || n < 0 || n >= (int64_t(1) << 31)) return RTG_EINVAL;
   if (!std::isfinite(r) || !(r > 0.0) || !std::isfinite(alpha) || !(alpha > 0.0)) return RTG_EINVAL;
@@ -739,9 +759,10 @@ int Lane::make_empty_result(int64_t n, rtg_csr* out, uint64_t handle) {
 // query: the shared rules, a device pointer of this context's device, and
 // r*r inside the range where the FP32 screen's band is sound.
 int Ctx::check_query(const float* points, int64_t n, int32_t d, double r, int32_t k,
-                     double alpha) {
+                     double alpha, uint32_t flags) {
   int rc = validate_query(points, n, d, r, k, alpha);
   if (rc) return rc;
+  if (axes_per_robot(d, flags) < 0) return RTG_EINVAL;
   if (n > 0 && check_device_pointer(points, device)) return RTG_EINVAL;
   const double r2 = r * r;
   if (!(r2 >= 0x1p-100 && r2 <= 0x1p120)) return RTG_ERANGE;
@@ -762,7 +783,7 @@ int Lane::tiny_query(const float* points, int64_t n, int32_t d, rtg_csr* out, ui
 int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha,
                    const double* R, const double* u, uint32_t flags, rtg_csr* out) {
   if (poisoned) return RTG_EDEVICE;
-  int rc = check_query(points, n, d, r, k, alpha);
+  int rc = check_query(points, n, d, r, k, alpha, flags);
   if (rc) return rc;
   rtg_stats st{};
   st.n = n;
@@ -827,10 +848,14 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   if (npts >= (int64_t(1) << 31)) return RTG_ENOMEM;
   const int pair_bits = std::max(1, ceil_log2((uint64_t)npts));
   std::vector<PairTest> tests(m);
+  std::vector<int> sub(m);  // MR-metric axes per robot (0: Euclidean)
+  bool any_mr = false;
   std::vector<double> Rh((size_t)S_total * d * d), uh((size_t)S_total * d);
   for (uint32_t q = 0; q < m; ++q) {
     const Job& j = *jobs[q];
-    tests[q] = make_pair_test(j.r * j.r, pair_bits);
+    sub[q] = axes_per_robot(d, j.flags);
+    tests[q] = make_pair_test(sub[q] ? mr_screen_r2(j.r) : j.r * j.r, pair_bits);
+    any_mr = any_mr || sub[q] > 0;
     std::memcpy(&Rh[(size_t)inst[q].tr_off * d * d], j.R, sizeof(double) * (size_t)j.k * d * d);
     std::memcpy(&uh[(size_t)inst[q].tr_off * d], j.u, sizeof(double) * (size_t)j.k * d);
   }
@@ -1133,13 +1158,36 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     if (fin[0]) return hip_fail(hipErrorUnknown, "radix sort look-back");
     st.band_rechecks += (int64_t)fin[1];
   }
-  st.candidates += (int64_t)cand_total;
 
   // Key buffers are no longer needed.
   for (void* p : {(void*)keys, (void*)keys_alt, (void*)vals, (void*)vals_alt, (void*)cstart,
                   (void*)cend, (void*)units, (void*)udesc, (void*)spts, (void*)tests_c,
                   (void*)sig, (void*)ssig})
     S.drop(p);
+
+  // --- MR-metric: keep the Euclidean candidates within r under the MR-metric -----
+  if (any_mr && cand_total > 0) {
+    std::vector<MrInst> mi(m);
+    for (uint32_t q = 0; q < m; ++q) mi[q] = MrInst{inst[q].pt_off, jobs[q]->r, sub[q], 0};
+    MrInst* mi_d = S.get<MrInst>(m);
+    uint64_t* kept = S.get<uint64_t>(cand_total);
+    if (!mi_d || !kept) return RTG_ENOMEM;
+    if ((rc = upload(mi_d, mi.data(), sizeof(MrInst) * m))) return rc;
+    launch_fill_u64(reinterpret_cast<uint64_t*>(counters) + 2, 0ull, 1, stream);
+    MrFilterArgs fa{cand, cand_total, pair_bits, d, pts_rows, pts_rows, mi_d, (int)m, kept,
+                    counters + 2};
+    kbegin(RTG_K_PAIRS);
+    launch_mr_filter(fa, stream);
+    kend(RTG_K_PAIRS, (8.0 + 8.0 * d) * (double)cand_total);  // pairs and both rows read
+    unsigned long long nk = 0;
+    if ((rc = read_back(counters + 2, sizeof(nk), &nk))) return rc;
+    st.kernel_bytes[RTG_K_PAIRS] += 8.0 * (double)nk;  // kept pairs written
+    st.band_rechecks += (int64_t)cand_total;
+    S.drop(cand);
+    cand = kept;
+    cand_total = nk;
+  }
+  st.candidates += (int64_t)cand_total;
 
   // --- union and neighbour lists ------------------------------------------------
   const size_t C = cand_total;
@@ -1307,7 +1355,8 @@ int Ctx::batched(const rtg_query* q, int32_t nq, rtg_csr* outs) {
   if (poisoned) return RTG_EDEVICE;
   int rc;
   for (int32_t i = 0; i < nq; ++i)
-    if ((rc = check_query(q[i].points, q[i].n, q[i].d, q[i].r, q[i].k, q[i].alpha))) return rc;
+    if ((rc = check_query(q[i].points, q[i].n, q[i].d, q[i].r, q[i].k, q[i].alpha, q[i].flags)))
+      return rc;
   std::vector<std::vector<double>> R(nq), u(nq);
   for (int32_t i = 0; i < nq; ++i) {
     R[i].resize((size_t)q[i].k * q[i].d * q[i].d);
@@ -1678,7 +1727,7 @@ int Lane::query_index(const Index& I, const float* queries, int64_t m, rtg_stats
   A.R = I.R;
   A.u = I.u;
   A.inv_c = 1.0 / (I.alpha * I.r);
-  A.r2 = I.r * I.r;
+  A.r2 = I.sub ? mr_screen_r2(I.r) : I.r * I.r;
   A.klo = I.klo;
   A.layout = I.layout;
   A.cell_bits = I.P.layout.cell_bits;
@@ -1723,6 +1772,26 @@ int Lane::query_index(const Index& I, const float* queries, int64_t m, rtg_stats
     if (C <= cap) break;
     if (attempt == 1) return RTG_ENOMEM;
     cap = C;
+  }
+  if (I.sub && C > 0) {
+    // MR-metric: keep the Euclidean candidates within r under the MR-metric
+    MrInst mi{0, I.r, I.sub, 0};
+    MrInst* mi_d = S.get<MrInst>(1);
+    uint64_t* kept = S.get<uint64_t>(C);
+    if (!mi_d || !kept) return RTG_ENOMEM;
+    if ((rc = upload(mi_d, &mi, sizeof(mi)))) return rc;
+    launch_fill_u64(reinterpret_cast<uint64_t*>(counter), 0ull, 1, stream);
+    MrFilterArgs fa{cand, C, A.pb, d, queries, I.pts, mi_d, 1, kept, counter};
+    kbegin(RTG_K_PAIRS);
+    launch_mr_filter(fa, stream);
+    kend(RTG_K_PAIRS, (8.0 + 8.0 * d) * (double)C);
+    unsigned long long nk = 0;
+    if ((rc = read_back(counter, sizeof(nk), &nk))) return rc;
+    st.kernel_bytes[RTG_K_PAIRS] += 8.0 * (double)nk;
+    st.band_rechecks = (int64_t)C;
+    S.drop(cand);
+    cand = kept;
+    C = nk;
   }
   st.candidates = (int64_t)C;
   st.unique_pairs = (int64_t)C;
@@ -1846,12 +1915,13 @@ int rtg_index_build(rtg_ctx* ctx, const float* points, int64_t n, int32_t d, dou
   Ctx* c = reinterpret_cast<Ctx*>(ctx);
   std::lock_guard<std::mutex> lk(c->mu);
   if (c->poisoned) return RTG_EDEVICE;
-  int rc = c->check_query(points, n, d, r, k, alpha);
+  int rc = c->check_query(points, n, d, r, k, alpha, flags);
   if (rc) return rc;
   std::vector<double> R((size_t)k * d * d), u((size_t)k * d);
   if ((rc = rtg::make_transforms(seed, k, d, flags, R.data(), u.data()))) return rc;
   std::unique_ptr<rtg::Index> I(new (std::nothrow) rtg::Index());
   if (!I) return RTG_ENOMEM;
+  I->sub = rtg::axes_per_robot(d, flags);
   rc = c->main.build_index(points, n, d, r, k, alpha, R.data(), u.data(), *I);
   if (rc) {
     (void)hipStreamSynchronize(c->main.stream);

@@ -218,6 +218,34 @@ struct PairsArgs {
   int gram;                // 1: matrix-core screen (d <= 16), 0: vector screen
   uint32_t max_blocks;     // grid size cap (0: default)
 };
+// --- MR-metric filter -----------------------------------------------------
+// Under the MR-metric (the sum of the robots' Euclidean displacements, each
+// robot a block of sub consecutive axes) the pair kernels run the Euclidean
+// test with a radius a little above r, which keeps every MR neighbour, and
+// this pass keeps the packed pairs (a << pair_bits | b) whose MR distance is
+// at most r.  The instance of a pair is the last one with pt_off <= a; pairs
+// of Euclidean instances (sub == 0) are kept as they are.  Kept pairs are
+// appended to out in no particular order; out_count must start at zero.
+struct MrInst {
+  int64_t pt_off;  // first row of the instance
+  double r;
+  int32_t sub;     // axes per robot; 0: Euclidean instance
+  int32_t pad;
+};
+struct MrFilterArgs {
+  const uint64_t* in;
+  uint64_t count;
+  int pair_bits;
+  int d;
+  const float* rows_a;  // row-major [.][d]: rows of the pairs' first indices
+  const float* rows_b;  // and of their second indices
+  const MrInst* inst;   // [m], pt_off ascending, inst[0].pt_off = 0
+  int m;
+  uint64_t* out;        // room for count pairs
+  unsigned long long* out_count;
+};
+void launch_mr_filter(const MrFilterArgs& a, hipStream_t s);
+
 // --- query mode -------------------------------------------------------------
 // One sorted grid of an index: its n sorted keys (cell prefix above the point
 // index when the keys carry it) and the grid's segment id within its sort.

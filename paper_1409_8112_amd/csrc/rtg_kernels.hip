@@ -1551,6 +1551,76 @@ __global__ __launch_bounds__(kBlock) void k_query_pairs(const QueryArgs A) {
   flush_out(P, O, lane);
 }
 
+// The MR-metric's FP64 decision for one candidate pair: the robots' squared
+// displacements summed in axis order, their square roots (correctly rounded)
+// added in robot order, the sum tested against r.
+__device__ __forceinline__ bool mr_keep(const MrFilterArgs& A, uint64_t v) {
+  const uint64_t a = v >> A.pair_bits, b = v & ((1ull << A.pair_bits) - 1ull);
+  int lo = 0, hi = A.m - 1;  // the last instance with pt_off <= a
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (A.inst[mid].pt_off <= (int64_t)a) lo = mid;
+    else hi = mid - 1;
+  }
+  const MrInst I = A.inst[lo];
+  if (I.sub <= 0) return true;
+  const float* ra = A.rows_a + (size_t)a * A.d;
+  const float* rb = A.rows_b + (size_t)b * A.d;
+  double s = 0.0;
+  for (int o = 0; o < A.d; o += I.sub) {
+    double t = 0.0;
+    for (int l = o; l < o + I.sub; ++l) {
+      const double dl = (double)ra[l] - (double)rb[l];
+      t = t + dl * dl;
+    }
+    s = s + __builtin_sqrt(t);
+  }
+  return s <= I.r;
+}
+
+// One block per tile of kBlock * kMrPer candidates (coalesced reads, one
+// lane per candidate and step); the block's kept pairs take one atomic.
+constexpr int kMrPer = 16;
+__global__ __launch_bounds__(kBlock) void k_mr_filter(const MrFilterArgs A) {
+  __shared__ uint32_t sWave[kWaves];
+  __shared__ unsigned long long sBase;
+  const uint32_t lane = lane_id();
+  const int w = threadIdx.x >> 6;
+  const uint64_t tile = (uint64_t)kBlock * kMrPer;
+  for (uint64_t t0 = (uint64_t)blockIdx.x * tile; t0 < A.count; t0 += (uint64_t)gridDim.x * tile) {
+    uint64_t v[kMrPer], km[kMrPer];
+    uint32_t tot = 0;
+#pragma unroll
+    for (int i = 0; i < kMrPer; ++i) {
+      const uint64_t p = t0 + (uint64_t)i * kBlock + threadIdx.x;
+      v[i] = p < A.count ? A.in[p] : 0ull;
+    }
+#pragma unroll
+    for (int i = 0; i < kMrPer; ++i) {
+      const uint64_t p = t0 + (uint64_t)i * kBlock + threadIdx.x;
+      km[i] = ballot(p < A.count && mr_keep(A, v[i]));
+      tot += (uint32_t)__popcll(km[i]);
+    }
+    if (lane == 0) sWave[w] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t all = 0;
+#pragma unroll
+      for (int x = 0; x < kWaves; ++x) all += sWave[x];
+      sBase = all ? atomicAdd(A.out_count, (unsigned long long)all) : 0ull;
+    }
+    __syncthreads();
+    unsigned long long at = sBase;
+    for (int x = 0; x < w; ++x) at += sWave[x];
+#pragma unroll
+    for (int i = 0; i < kMrPer; ++i) {
+      if ((km[i] >> lane) & 1ull) A.out[at + rank_below(km[i])] = v[i];
+      at += (uint32_t)__popcll(km[i]);
+    }
+    __syncthreads();  // sWave and sBase are rewritten by the next tile
+  }
+}
+
 // Unit descriptors of cell c: the whole cell, or one unit per tile.
 __global__ void k_unit_fill(const uint32_t* __restrict__ start, const uint32_t* __restrict__ end,
                             const uint32_t* __restrict__ unit_off, uint32_t ncells,
@@ -2291,6 +2361,14 @@ void launch_query_keys(const QueryArgs& a, hipStream_t s) {
     default: RTG_QK(0); break;
   }
 #undef RTG_QK
+}
+
+void launch_mr_filter(const MrFilterArgs& a, hipStream_t s) {
+  if (a.count == 0) return;
+  const uint64_t tile = (uint64_t)kBlock * kMrPer;
+  uint64_t blocks = (a.count + tile - 1) / tile;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_mr_filter, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
 }
 
 void launch_query_pairs(const QueryArgs& a, hipStream_t s) {

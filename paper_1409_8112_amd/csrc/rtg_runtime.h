@@ -55,6 +55,10 @@ int choose_params(int32_t d, double target, double nu, uint32_t flags, int32_t* 
                   double* alpha_out, double* recall_out);
 int min_field_bits(double alpha);
 int validate_query(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha);
+// Axes per robot of the MR-metric that flags select (0: Euclidean), or -1
+// for flags the library does not know or a robot count that does not
+// divide d.
+int axes_per_robot(int32_t d, uint32_t flags);
 int check_device_pointer(const void* p, int device);
 
 // One query of a batch, with its transforms (host arrays).
@@ -91,6 +95,7 @@ struct Index {
   int64_t n = 0;
   int32_t d = 0, k = 0;
   double r = 0.0, alpha = 0.0;
+  int32_t sub = 0;  // MR-metric: axes per robot; 0: Euclidean
   Packing P;
   int sig_b = 0, sig_g = 0, sig_gpw = 1, sig_W = 0;
   uint64_t lows = 0, highs = 0;
@@ -190,7 +195,8 @@ struct Ctx {
   int all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha,
                 const double* R, const double* u, uint32_t flags, rtg_csr* out);
   int batched(const rtg_query* q, int32_t nq, rtg_csr* outs);
-  int check_query(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha);
+  int check_query(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha,
+                  uint32_t flags);
   int debug_cell_coords(const float* points, int64_t n, int32_t d, double r, double alpha,
                         const double* R, const double* u, int64_t* kappa_host);
 

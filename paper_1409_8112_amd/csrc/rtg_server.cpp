@@ -276,7 +276,7 @@ void Server::work(int li) {
 
 int Ctx::submit(const rtg_query& q, uint64_t* ticket) {
   if (poisoned) return RTG_EDEVICE;
-  int rc = check_query(q.points, q.n, q.d, q.r, q.k, q.alpha);
+  int rc = check_query(q.points, q.n, q.d, q.r, q.k, q.alpha, q.flags);
   if (rc) return rc;
   Server* s = nullptr;
   {

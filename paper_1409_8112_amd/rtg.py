@@ -22,6 +22,12 @@ from . import build as _build
 
 OK, EAGAIN, EINVAL, ENOMEM, ERANGE, EDEVICE, ENOENT = 0, 1, -1, -2, -3, -4, -5
 NO_ROTATE, UPPER_ONLY, DEDUP_SORT = 1, 2, 4
+ROBOTS_SHIFT = 8
+
+
+def robots(b: int) -> int:
+    """Flag bits of the MR-metric over b robots (RTG_ROBOTS(b))."""
+    return int(b) << ROBOTS_SHIFT
 # kernel ids of rtg_stats.kernel_* (RTG_K_* in rtg.h)
 KERNELS = ["stage", "keys", "key_hist", "key_scatter", "cells", "pairs", "pair_hist",
            "pair_scatter", "unique", "csr", "scan", "gather"]
