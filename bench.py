@@ -147,6 +147,54 @@ def bench_auto(ctx, pts, wl, target: float, mean_neighbours: float, reps: int = 
             "ms": t * 1e3, "pairs": pairs, "pairs_per_s": pairs / t}
 
 
+def _median_call_ms(ctx, pts, r, k, alpha, seed, flags, reps):
+    import torch
+    times, pairs = [], 0
+    for i in range(reps + 2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx.all_pairs(pts, r, k, alpha, seed, flags)
+        pairs = res.pairs
+        res.release()
+        torch.cuda.synchronize()
+        if i >= 2:
+            times.append(time.perf_counter() - t0)
+    return float(np.median(times)) * 1e3, pairs
+
+
+def bench_variants(ctx, pts, wl, reps: int = 10) -> dict:
+    """The rules that remove repeated pairs -- first owner (default),
+    sort-unique and the pair bitmap -- on a small, a mid-size and the
+    workload's instance (the bitmap does not fit the last one and falls back
+    to the first owner), and the Euclidean metric against the MR-metric of
+    two robots (d = 6 as two robots in 3-D) on the workload."""
+    import torch
+    from paper_1409_8112_amd import rtg, workloads
+    rules = {"first_owner": 0, "sort_unique": rtg.DEDUP_SORT, "bitmap": rtg.DEDUP_BITMAP}
+    cases = [(workloads.small_uniform_d3(), None),
+             (workloads.Workload("uniform n=64000 d=6 k=8 alpha=2 (~20 nb)", 64000, 6,
+                                 workloads.calibrate_radius_uniform(64000, 6, 20.0), 8, 2.0, 0, 0),
+              None),
+             (wl, pts)]
+    dedup = {}
+    for w, dev in cases:
+        if dev is None:
+            dev = torch.from_numpy(w.points()).to("cuda:0")
+        row = {}
+        for name, fl in rules.items():
+            if name == "bitmap" and w.n * (w.n - 1) // 2 > 8 * (4 << 30):
+                continue  # larger than the bitmap limit: it would run the first-owner rule
+            ms, pairs = _median_call_ms(ctx, dev, w.r, w.k, w.alpha, w.seed, fl, reps)
+            row[name + "_ms"] = ms
+            row["pairs"] = pairs
+        dedup[w.name] = row
+    eu_ms, eu_pairs = _median_call_ms(ctx, pts, wl.r, wl.k, wl.alpha, wl.seed, 0, reps)
+    mr_ms, mr_pairs = _median_call_ms(ctx, pts, wl.r, wl.k, wl.alpha, wl.seed, rtg.robots(2), reps)
+    return {"dedup": dedup,
+            "metric": {"workload": wl.name, "euclidean_ms": eu_ms, "euclidean_pairs": eu_pairs,
+                       "mr_2_robots_ms": mr_ms, "mr_2_robots_pairs": mr_pairs}}
+
+
 def bench_query(ctx, pts, wl, m: int = 1_000_000, reps: int = 5) -> dict:
     """Query mode: an index of the workload's points (its k sorted grids),
     then m uniform query points per call."""
@@ -255,6 +303,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the request-loop measurement")
     ap.add_argument("--no-query", action="store_true", help="skip the query-mode measurement")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the dedup-rule and metric-variant measurements")
     ap.add_argument("--no-auto", action="store_true",
                     help="skip the run with parameters chosen for a target recall")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -383,6 +433,9 @@ def main(argv=None) -> int:
     if not args.no_query and args.workload == "uniform_d6":
         print("# query mode", file=sys.stderr, flush=True)
         out["query"] = bench_query(ctx, pts, wl)
+    if not args.no_variants and args.workload == "uniform_d6":
+        print("# dedup rules and metric variants", file=sys.stderr, flush=True)
+        out["variants"] = bench_variants(ctx, pts, wl)
     if not args.no_batched:
         print(f"# batched: {args.batched_count} instances", file=sys.stderr, flush=True)
         out["batched"] = bench_batched(ctx, args.batched_count)

@@ -61,9 +61,17 @@ typedef enum rtg_status {
 enum {
   RTG_NO_ROTATE = 1u,  /* shift-only grids (the paper's first algorithm)        */
   RTG_UPPER_ONLY = 2u, /* store each pair once, in the row of its smaller index */
-  RTG_DEDUP_SORT = 4u  /* remove repeats by sorting all candidates (every grid's */
-                       /* pairs) and dropping equal neighbours, instead of the  */
-                       /* default first-owner rule; same result                 */
+  RTG_DEDUP_SORT = 4u,   /* remove repeats by sorting all candidates (every    */
+                         /* grid's pairs) and dropping equal neighbours,        */
+                         /* instead of the default first-owner rule            */
+  RTG_DEDUP_BITMAP = 8u  /* remove repeats with one bit per unordered pair of  */
+                         /* each instance (the upper triangle, n(n-1)/2 bits;   */
+                         /* the paper's bitset of Sec. III-B): every grid's     */
+                         /* pairs set their bit, the first arrival is kept.     */
+                         /* When a pass's bitmaps exceed 4 GiB or a quarter of  */
+                         /* the free budget, the first-owner rule runs instead. */
+                         /* Every rule gives the same result; SORT and BITMAP   */
+                         /* together are RTG_EINVAL.                            */
 };
 
 /* The MR-metric of the multi-robot experiments (Sec. IV-C): RTG_ROBOTS(b) in
@@ -114,7 +122,7 @@ enum {
   RTG_K_PAIRS = 5,         /* same-cell pair tests and output                */
   RTG_K_PAIR_HIST = 6,     /* digit histogram of the pair sort               */
   RTG_K_PAIR_SCATTER = 7,  /* scatter of the pair sort                       */
-  RTG_K_UNIQUE = 8,        /* removal of repeated pairs                      */
+  RTG_K_UNIQUE = 8,        /* removal of repeated pairs (sort-unique, bitmap)  */
   RTG_K_CSR = 9,           /* neighbour-list build (incl. transposed sort)   */
   RTG_K_SCAN = 10,         /* prefix sums                                    */
   RTG_K_GATHER = 11,       /* cell members' coordinates by sorted position   */
@@ -172,7 +180,8 @@ int rtg_destroy(rtg_ctx *ctx);
  *   points: device pointer, row-major [n][d] FP32, 4-byte aligned.
  *   n in [0, 2^31); d in [1, 64]; r > 0 finite; k >= 1; alpha > 0 finite.
  *   seed selects the k transforms (see rtg_make_transforms).
- *   flags: RTG_NO_ROTATE, RTG_UPPER_ONLY, RTG_DEDUP_SORT, RTG_ROBOTS(b).
+ *   flags: RTG_NO_ROTATE, RTG_UPPER_ONLY, RTG_DEDUP_SORT or RTG_DEDUP_BITMAP,
+ *   RTG_ROBOTS(b).
  * n <= 1 gives an empty list.  Errors: RTG_EINVAL (also for NaN/Inf
  * coordinates), RTG_ERANGE, RTG_ENOMEM, RTG_EDEVICE. */
 int rtg_all_pairs(rtg_ctx *ctx, const float *points, int64_t n, int32_t d, double r, int32_t k,

@@ -554,8 +554,10 @@ int check_device_pointer(const void* p, int device) {
 }
 
 int axes_per_robot(int32_t d, uint32_t flags) {
-  constexpr uint32_t known = RTG_NO_ROTATE | RTG_UPPER_ONLY | RTG_DEDUP_SORT | RTG_ROBOTS_MASK;
+  constexpr uint32_t known =
+      RTG_NO_ROTATE | RTG_UPPER_ONLY | RTG_DEDUP_SORT | RTG_DEDUP_BITMAP | RTG_ROBOTS_MASK;
   if (flags & ~known) return -1;
+  if ((flags & RTG_DEDUP_SORT) && (flags & RTG_DEDUP_BITMAP)) return -1;
   const int robots = (int)((flags & RTG_ROBOTS_MASK) >> RTG_ROBOTS_SHIFT);
   if (robots <= 1) return 0;
   if (d < 1 || robots > d || d % robots) return -1;
@@ -975,7 +977,23 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   int sig_b = 1;
   for (uint32_t q = 0; q < m; ++q) sig_b = std::max(sig_b, min_field_bits(jobs[q]->alpha));
   const int sig_g = d * sig_b;
-  const bool first_owner = !(flags & RTG_DEDUP_SORT) && sig_g <= 64;
+  // Bitmaps of every instance's unordered pairs, when asked for and small
+  // enough; otherwise the first-owner rule where the signatures fit.
+  uint64_t bitmap_words = 0;
+  std::vector<BitmapInst> bmi;
+  if (flags & RTG_DEDUP_BITMAP) {
+    uint64_t bits = 0;
+    for (uint32_t q = 0; q < m; ++q) {
+      bmi.push_back(BitmapInst{inst[q].pt_off, (int64_t)bits});
+      const uint64_t nq = (uint64_t)inst[q].n;
+      bits += nq * (nq - 1) / 2;
+    }
+    const uint64_t words = (bits + 31) / 32;
+    const uint64_t limit = std::min<uint64_t>(kBitmapMaxBytes, ctx->largest_free() / 4);
+    if (4 * words <= limit) bitmap_words = std::max<uint64_t>(words, 1);
+  }
+  const bool bitmap = bitmap_words > 0;
+  const bool first_owner = !(flags & RTG_DEDUP_SORT) && !bitmap && sig_g <= 64;
   const int sig_gpw = sig_g <= 64 ? 64 / sig_g : 1;
   const int sig_W = (kmax + sig_gpw - 1) / sig_gpw;
   uint64_t* sig = nullptr;   // [npts][W]
@@ -1189,7 +1207,31 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   }
   st.candidates += (int64_t)cand_total;
 
+  // --- bitmap de-duplication: first arrival of each pair --------------------------
+  if (bitmap && cand_total > 0) {
+    BitmapInst* bmi_d = S.get<BitmapInst>(m);
+    uint32_t* bits = S.get<uint32_t>(bitmap_words);
+    uint64_t* uniq = S.get<uint64_t>(cand_total);
+    if (!bmi_d || !bits || !uniq) return RTG_ENOMEM;
+    if ((rc = upload(bmi_d, bmi.data(), sizeof(BitmapInst) * m))) return rc;
+    kbegin(RTG_K_UNIQUE);
+    launch_fill_u32(bits, 0u, bitmap_words, stream);
+    launch_fill_u64(reinterpret_cast<uint64_t*>(counters) + 2, 0ull, 1, stream);
+    BitmapArgs ba{cand, cand_total, pair_bits, (int)m, bmi_d, bits, uniq, counters + 2};
+    launch_bitmap_unique(ba, stream);
+    // the bitmap cleared, the candidates read, one word touched per candidate
+    kend(RTG_K_UNIQUE, 4.0 * (double)bitmap_words + 12.0 * (double)cand_total);
+    unsigned long long nu = 0;
+    if ((rc = read_back(counters + 2, sizeof(nu), &nu))) return rc;
+    st.kernel_bytes[RTG_K_UNIQUE] += 8.0 * (double)nu;  // unique pairs written
+    S.drop(bits);
+    S.drop(cand);
+    cand = uniq;
+    cand_total = nu;
+  }
+
   // --- union and neighbour lists ------------------------------------------------
+  const bool unique_pairs = first_owner || bitmap;  // no repeats among the candidates
   const size_t C = cand_total;
   if (C >= (1ull << 32)) return RTG_ENOMEM;
   // Row buckets need a 32-bit local entry (rb row bits + pair_bits) and at
@@ -1199,7 +1241,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
                          (both ? 2 * C : C) < (1ull << 32);
   const uint64_t* pairs = cand;  // pairs for the neighbour-list build
   size_t npairs = C;
-  if (C > 0 && (!first_owner || !bucket_ok)) {
+  if (C > 0 && (!unique_pairs || !bucket_ok)) {
     // Global sort of the packed pairs; with RTG_DEDUP_SORT also drop repeats
     // (sort-unique over every grid's candidates).
     uint64_t* cand_alt = S.get<uint64_t>(C);
@@ -1211,8 +1253,8 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     const uint64_t* sc = where ? cand_alt : cand;
     uint64_t* dst = where ? cand : cand_alt;
     mark(6);
-    if (first_owner) {
-      pairs = sc;  // every pair was emitted by exactly one grid
+    if (unique_pairs) {
+      pairs = sc;  // every pair is there once
     } else {
       const size_t nt = (C + kTile - 1) / kTile;
       uint32_t* tc = scr;
@@ -1384,7 +1426,7 @@ int Ctx::batched(const rtg_query* q, int32_t nq, rtg_csr* outs) {
     }
     jobs[i] = Job{q[i].points, q[i].n, q[i].d, q[i].r, q[i].alpha, q[i].k, q[i].flags,
                   R[i].data(), u[i].data(), &res[i], 0};
-    groups[{q[i].d, q[i].flags & (RTG_UPPER_ONLY | RTG_DEDUP_SORT)}].push_back(i);
+    groups[{q[i].d, q[i].flags & kListFlags}].push_back(i);
   }
   for (auto& g : groups) {
     size_t b = 0;

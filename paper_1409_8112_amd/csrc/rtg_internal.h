@@ -246,6 +246,28 @@ struct MrFilterArgs {
 };
 void launch_mr_filter(const MrFilterArgs& a, hipStream_t s);
 
+// --- bitmap de-duplication --------------------------------------------------
+// Keeps the first arrival of each packed pair (a << pair_bits | b, a < b, both
+// in the instance with the last pt_off <= a): instance q owns bits
+// [bit_off, bit_off + n (n - 1) / 2) of bits, the pair of local indices
+// a' < b' bit b'(b'-1)/2 + a'.  bits must start at zero; kept pairs are
+// appended to out in no particular order; out_count must start at zero.
+struct BitmapInst {
+  int64_t pt_off;
+  int64_t bit_off;
+};
+struct BitmapArgs {
+  const uint64_t* in;
+  uint64_t count;
+  int pair_bits;
+  int m;
+  const BitmapInst* inst;  // [m], pt_off ascending, inst[0].pt_off = 0
+  uint32_t* bits;
+  uint64_t* out;           // room for count pairs
+  unsigned long long* out_count;
+};
+void launch_bitmap_unique(const BitmapArgs& a, hipStream_t s);
+
 // --- query mode -------------------------------------------------------------
 // One sorted grid of an index: its n sorted keys (cell prefix above the point
 // index when the keys carry it) and the grid's segment id within its sort.

@@ -1578,27 +1578,32 @@ __device__ __forceinline__ bool mr_keep(const MrFilterArgs& A, uint64_t v) {
   return s <= I.r;
 }
 
-// One block per tile of kBlock * kMrPer candidates (coalesced reads, one
-// lane per candidate and step); the block's kept pairs take one atomic.
-constexpr int kMrPer = 16;
-__global__ __launch_bounds__(kBlock) void k_mr_filter(const MrFilterArgs A) {
+// Keeps the packed pairs v of in[0, count) with keep(v), appended to out in
+// no particular order.  One block per tile of kBlock * kCompactPer pairs
+// (coalesced reads, one lane per pair and step); a tile's kept pairs take
+// one atomic on out_count.  Every lane of a block runs the same tiles.
+constexpr int kCompactPer = 16;
+template <class Keep>
+__device__ __forceinline__ void compact_tiles(const uint64_t* __restrict__ in, uint64_t count,
+                                              uint64_t* __restrict__ out,
+                                              unsigned long long* out_count, Keep keep) {
   __shared__ uint32_t sWave[kWaves];
   __shared__ unsigned long long sBase;
   const uint32_t lane = lane_id();
   const int w = threadIdx.x >> 6;
-  const uint64_t tile = (uint64_t)kBlock * kMrPer;
-  for (uint64_t t0 = (uint64_t)blockIdx.x * tile; t0 < A.count; t0 += (uint64_t)gridDim.x * tile) {
-    uint64_t v[kMrPer], km[kMrPer];
+  const uint64_t tile = (uint64_t)kBlock * kCompactPer;
+  for (uint64_t t0 = (uint64_t)blockIdx.x * tile; t0 < count; t0 += (uint64_t)gridDim.x * tile) {
+    uint64_t v[kCompactPer], km[kCompactPer];
     uint32_t tot = 0;
 #pragma unroll
-    for (int i = 0; i < kMrPer; ++i) {
+    for (int i = 0; i < kCompactPer; ++i) {
       const uint64_t p = t0 + (uint64_t)i * kBlock + threadIdx.x;
-      v[i] = p < A.count ? A.in[p] : 0ull;
+      v[i] = p < count ? in[p] : 0ull;
     }
 #pragma unroll
-    for (int i = 0; i < kMrPer; ++i) {
+    for (int i = 0; i < kCompactPer; ++i) {
       const uint64_t p = t0 + (uint64_t)i * kBlock + threadIdx.x;
-      km[i] = ballot(p < A.count && mr_keep(A, v[i]));
+      km[i] = ballot(p < count && keep(v[i]));
       tot += (uint32_t)__popcll(km[i]);
     }
     if (lane == 0) sWave[w] = tot;
@@ -1607,18 +1612,45 @@ __global__ __launch_bounds__(kBlock) void k_mr_filter(const MrFilterArgs A) {
       uint32_t all = 0;
 #pragma unroll
       for (int x = 0; x < kWaves; ++x) all += sWave[x];
-      sBase = all ? atomicAdd(A.out_count, (unsigned long long)all) : 0ull;
+      sBase = all ? atomicAdd(out_count, (unsigned long long)all) : 0ull;
     }
     __syncthreads();
     unsigned long long at = sBase;
     for (int x = 0; x < w; ++x) at += sWave[x];
 #pragma unroll
-    for (int i = 0; i < kMrPer; ++i) {
-      if ((km[i] >> lane) & 1ull) A.out[at + rank_below(km[i])] = v[i];
+    for (int i = 0; i < kCompactPer; ++i) {
+      if ((km[i] >> lane) & 1ull) out[at + rank_below(km[i])] = v[i];
       at += (uint32_t)__popcll(km[i]);
     }
     __syncthreads();  // sWave and sBase are rewritten by the next tile
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mr_filter(const MrFilterArgs A) {
+  compact_tiles(A.in, A.count, A.out, A.out_count, [&](uint64_t v) { return mr_keep(A, v); });
+}
+
+// Repeats removed with one bit per unordered pair of an instance (the
+// upper triangle, a' < b' local indices, bit b'(b'-1)/2 + a'): the
+// candidate whose atomic OR sets the bit is kept, any later one is not.
+// Which of equal candidates survives does not matter: they are equal.
+__device__ __forceinline__ bool bitmap_first(const BitmapArgs& A, uint64_t v) {
+  const uint64_t a = v >> A.pair_bits, b = v & ((1ull << A.pair_bits) - 1ull);
+  int lo = 0, hi = A.m - 1;  // the last instance with pt_off <= a
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (A.inst[mid].pt_off <= (int64_t)a) lo = mid;
+    else hi = mid - 1;
+  }
+  const BitmapInst I = A.inst[lo];
+  const uint64_t la = a - (uint64_t)I.pt_off, lb = b - (uint64_t)I.pt_off;
+  const uint64_t bit = (uint64_t)I.bit_off + lb * (lb - 1) / 2 + la;
+  const uint32_t m = 1u << (bit & 31u);
+  return (atomicOr(A.bits + (bit >> 5), m) & m) == 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bitmap_unique(const BitmapArgs A) {
+  compact_tiles(A.in, A.count, A.out, A.out_count, [&](uint64_t v) { return bitmap_first(A, v); });
 }
 
 // Unit descriptors of cell c: the whole cell, or one unit per tile.
@@ -2363,12 +2395,20 @@ void launch_query_keys(const QueryArgs& a, hipStream_t s) {
 #undef RTG_QK
 }
 
+static unsigned compact_blocks(uint64_t count) {
+  const uint64_t tile = (uint64_t)kBlock * kCompactPer;
+  const uint64_t blocks = (count + tile - 1) / tile;
+  return (unsigned)(blocks > 4096 ? 4096 : blocks);
+}
+
 void launch_mr_filter(const MrFilterArgs& a, hipStream_t s) {
   if (a.count == 0) return;
-  const uint64_t tile = (uint64_t)kBlock * kMrPer;
-  uint64_t blocks = (a.count + tile - 1) / tile;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_mr_filter, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_mr_filter, dim3(compact_blocks(a.count)), dim3(kBlock), 0, s, a);
+}
+
+void launch_bitmap_unique(const BitmapArgs& a, hipStream_t s) {
+  if (a.count == 0) return;
+  hipLaunchKernelGGL(k_bitmap_unique, dim3(compact_blocks(a.count)), dim3(kBlock), 0, s, a);
 }
 
 void launch_query_pairs(const QueryArgs& a, hipStream_t s) {

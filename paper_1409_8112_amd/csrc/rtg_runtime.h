@@ -55,6 +55,12 @@ int choose_params(int32_t d, double target, double nu, uint32_t flags, int32_t* 
                   double* alpha_out, double* recall_out);
 int min_field_bits(double alpha);
 int validate_query(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha);
+// Flags that shape a pass's output (instances batched together share them).
+constexpr uint32_t kListFlags = RTG_UPPER_ONLY | RTG_DEDUP_SORT | RTG_DEDUP_BITMAP;
+// Largest pair bitmap of one pass (RTG_DEDUP_BITMAP): beyond it the pass
+// removes repeats by the first-owner rule instead.
+constexpr uint64_t kBitmapMaxBytes = uint64_t(4) << 30;
+
 // Axes per robot of the MR-metric that flags select (0: Euclidean), or -1
 // for flags the library does not know or a robot count that does not
 // divide d.

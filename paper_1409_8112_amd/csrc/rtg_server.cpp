@@ -52,7 +52,7 @@ struct Request {
 };
 
 uint32_t group_of(const rtg_query& q) {
-  return ((uint32_t)q.d << 8) | (q.flags & (RTG_UPPER_ONLY | RTG_DEDUP_SORT));
+  return ((uint32_t)q.d << 8) | (q.flags & kListFlags);
 }
 
 }  // namespace

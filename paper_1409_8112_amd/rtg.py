@@ -21,7 +21,7 @@ import numpy as np
 from . import build as _build
 
 OK, EAGAIN, EINVAL, ENOMEM, ERANGE, EDEVICE, ENOENT = 0, 1, -1, -2, -3, -4, -5
-NO_ROTATE, UPPER_ONLY, DEDUP_SORT = 1, 2, 4
+NO_ROTATE, UPPER_ONLY, DEDUP_SORT, DEDUP_BITMAP = 1, 2, 4, 8
 ROBOTS_SHIFT = 8
 
 

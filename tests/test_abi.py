@@ -88,8 +88,8 @@ def test_binding_structs_match_the_header(tmp_path):
         lines.append(f'  printf("{st} %zu\\n", sizeof({st}));')
         for f in fs:
             lines.append(f'  printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
-    lines.append('  printf("flags %u %u %u %u\\n", (unsigned)RTG_NO_ROTATE, (unsigned)RTG_UPPER_ONLY, '
-                 '(unsigned)RTG_DEDUP_SORT, (unsigned)RTG_ROBOTS(3));')
+    lines.append('  printf("flags %u %u %u %u %u\\n", (unsigned)RTG_NO_ROTATE, (unsigned)RTG_UPPER_ONLY, '
+                 '(unsigned)RTG_DEDUP_SORT, (unsigned)RTG_DEDUP_BITMAP, (unsigned)RTG_ROBOTS(3));')
     lines += ["  return 0;", "}"]
     src = tmp_path / "layout.c"
     src.write_text("\n".join(lines) + "\n")
@@ -98,7 +98,8 @@ def test_binding_structs_match_the_header(tmp_path):
                     str(exe)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines()
     flags = [ln for ln in out if ln.startswith("flags ")]
-    assert flags == [f"flags {rtg.NO_ROTATE} {rtg.UPPER_ONLY} {rtg.DEDUP_SORT} {rtg.robots(3)}"]
+    assert flags == [f"flags {rtg.NO_ROTATE} {rtg.UPPER_ONLY} {rtg.DEDUP_SORT} {rtg.DEDUP_BITMAP} "
+                     f"{rtg.robots(3)}"]
     got = dict(line.split() for line in out if not line.startswith("flags "))
     for st, fs in fields.items():
         cls = getattr(rtg, st)
