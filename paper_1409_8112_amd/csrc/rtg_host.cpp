@@ -659,31 +659,33 @@ int csr_by_buckets(Lane& c, Scratch& S, const uint64_t* pairs, size_t count, int
     return rc;
   }
   if (nover) {
-    // Rare: buckets beyond LDS capacity go through the global radix sort.
-    std::vector<uint32_t> ids(nover);
-    rc = c.download(ids.data(), over + 1, sizeof(uint32_t) * nover);
-    for (size_t q = 0; !rc && q < ids.size(); ++q) {
-      const uint32_t b = ids[q];
-      uint32_t lim[2];
-      const size_t nxt = (b + 1 < nbuckets) ? (size_t)(b + 1) * nblocks : np;
-      if ((rc = c.read_back(part + (size_t)b * nblocks, sizeof(uint32_t), &lim[0]))) break;
-      if ((rc = c.read_back(part + nxt, sizeof(uint32_t), &lim[1]))) break;
-      const size_t cnt = lim[1] - lim[0];
-      uint64_t* w = S.get<uint64_t>(cnt);
-      uint64_t* w_alt = S.get<uint64_t>(cnt);
-      void* scr = S.get<char>(radix_scratch_bytes(cnt, 0, rb + pb));
+    // Buckets beyond LDS capacity (heavy rows, or rows that cluster in index
+    // order), all in one global radix sort of their entries tagged with the
+    // bucket's place in the list.
+    uint32_t* ext = S.get<uint32_t>(3 * (size_t)nover + 1);  // start, cnt, off, total
+    uint32_t* escr = S.get<uint32_t>(scan_scratch_elems(nover) + 1);
+    uint32_t tot = 0;
+    rc = (!ext || !escr) ? RTG_ENOMEM : RTG_OK;
+    if (!rc) {
+      launch_over_extent(over + 1, nover, part, nblocks, nbuckets, np, ext, ext + nover, s);
+      scan_exclusive_u32(ext + nover, ext + 2 * (size_t)nover, nover, ext + 3 * (size_t)nover,
+                         escr, s);
+      rc = c.read_back(ext + 3 * (size_t)nover, sizeof(tot), &tot);
+    }
+    if (!rc && tot) {
+      const int sh = rb + pb;
+      const int bits = sh + std::max(1, ceil_log2((uint64_t)nover));
+      uint64_t* w = S.get<uint64_t>(tot);
+      uint64_t* w_alt = S.get<uint64_t>(tot);
+      void* scr = S.get<char>(radix_scratch_bytes(tot, 0, bits));
       if (!w || !w_alt || !scr) {
         rc = RTG_ENOMEM;
-        break;
+      } else {
+        launch_over_gather(entries, ext, ext + 2 * (size_t)nover, nover, tot, sh, w, s);
+        const int where = radix_sort(w, nullptr, w_alt, nullptr, tot, 0, bits, scr, err, s);
+        launch_over_emit(where ? w_alt : w, tot, over + 1, ext, ext + nover,
+                         ext + 2 * (size_t)nover, pb, rb, n, *row_ptr, *col, s);
       }
-      launch_widen(entries + lim[0], cnt, w, s);
-      const int where = radix_sort(w, nullptr, w_alt, nullptr, cnt, 0, rb + pb, scr, err, s);
-      launch_bucket_emit_sorted(where ? w_alt : w, (uint32_t)cnt, lim[0], b, pb, rb, n, *row_ptr,
-                                *col, s);
-      if ((rc = c.sync())) break;
-      S.drop(w);
-      S.drop(w_alt);
-      S.drop(scr);
     }
     if (rc) {
       c.dfree(*res);

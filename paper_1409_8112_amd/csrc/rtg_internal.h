@@ -354,12 +354,21 @@ void launch_bucket_csr(const uint32_t* entries, const uint32_t* offs, uint32_t n
                        uint32_t nblocks, const uint32_t* total, uint32_t* oversized,
                        uint32_t* n_oversized, uint32_t cap, int pb, int rb, int64_t n,
                        int64_t* row_ptr, int32_t* col, hipStream_t s);
-// col / row_ptr of one bucket from its (row mod 2^rb, col) keys sorted
-// ascending (cnt of them, starting at entry start).
-void launch_bucket_emit_sorted(const uint64_t* keys, uint32_t cnt, uint32_t start, uint32_t b,
-                               int pb, int rb, int64_t n, int64_t* row_ptr, int32_t* col,
-                               hipStream_t s);
-void launch_widen(const uint32_t* src, size_t count, uint64_t* dst, hipStream_t s);
+// Every oversized bucket at once: ids[q] (q < nover) are their bucket ids.
+// launch_over_extent gives each one's first entry and entry count (part is
+// the scanned partition table, part[np] its total); with off the exclusive
+// scan of cnt and tot its sum, launch_over_gather tags each entry with q
+// above bit sh = rb + pb, and launch_over_emit writes col and row_ptr from
+// those keys sorted on bits [0, sh + bits of q).
+void launch_over_extent(const uint32_t* ids, uint32_t nover, const uint32_t* part,
+                        uint32_t nblocks, uint32_t nbuckets, size_t np, uint32_t* start,
+                        uint32_t* cnt, hipStream_t s);
+void launch_over_gather(const uint32_t* entries, const uint32_t* start, const uint32_t* off,
+                        uint32_t nover, uint32_t tot, int sh, uint64_t* w, hipStream_t s);
+void launch_over_emit(const uint64_t* keys, uint32_t tot, const uint32_t* ids,
+                      const uint32_t* start, const uint32_t* cnt, const uint32_t* off, int pb,
+                      int rb, int64_t n, int64_t* row_ptr, int32_t* col, hipStream_t s);
+
 void launch_u32_to_u64(const uint32_t* src, size_t count, uint64_t* dst, hipStream_t s);
 
 // --- per-instance lists of a batch ------------------------------------------

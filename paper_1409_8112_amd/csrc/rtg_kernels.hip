@@ -2027,34 +2027,73 @@ __global__ __launch_bounds__(kCsrThreads) void k_bucket_csr(
 
 // col / row_ptr of one bucket whose (row, col) keys are already sorted in
 // keys[0..cnt): the caller's path for buckets too large for LDS.
-__global__ void k_bucket_emit_sorted(const uint64_t* __restrict__ keys, uint32_t cnt,
-                                     uint32_t start, uint32_t b, int pb, int rb, int64_t n,
-                                     int64_t* __restrict__ row_ptr, int32_t* __restrict__ col) {
+// Buckets beyond LDS capacity, all in one global sort.  Bucket ids[q] holds
+// entries [start[q], start[q] + cnt[q]) of the entry array (and of col).
+__global__ void k_over_extent(const uint32_t* __restrict__ ids, uint32_t nover,
+                              const uint32_t* __restrict__ part, uint32_t nblocks,
+                              uint32_t nbuckets, size_t np, uint32_t* __restrict__ start,
+                              uint32_t* __restrict__ cnt) {
   const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t cmask = (1ull << pb) - 1ull;
-  if (q < cnt) {
-    col[(size_t)start + q] = (int32_t)(keys[q] & cmask);
-    // first entry of each row (and every empty row before it) sets row_ptr
-    const uint32_t r = (uint32_t)(keys[q] >> pb);
-    const uint32_t rprev = q == 0 ? 0u : (uint32_t)(keys[q - 1] >> pb) + 1u;
-    if (q == 0 || (uint32_t)(keys[q - 1] >> pb) != r)
-      for (uint32_t rr = rprev; rr <= r; ++rr) {
-        const int64_t row = ((int64_t)b << rb) + rr;
-        if (row < n) row_ptr[row] = (int64_t)start + q;
-      }
-  }
-  if (q == 0) {
-    // rows after the last entry (all rows if the bucket is empty)
-    const uint32_t rlast = cnt ? (uint32_t)(keys[cnt - 1] >> pb) + 1u : 0u;
-    for (uint32_t rr = rlast; rr < (1u << rb); ++rr) {
-      const int64_t row = ((int64_t)b << rb) + rr;
-      if (row < n) row_ptr[row] = (int64_t)start + cnt;
-    }
-  }
+  if (q >= nover) return;
+  const uint32_t b = ids[q];
+  const uint32_t st = part[(size_t)b * nblocks];
+  const uint32_t nx = (b + 1 < nbuckets) ? part[(size_t)(b + 1) * nblocks] : part[np];
+  start[q] = st;
+  cnt[q] = nx - st;
 }
 
-// Widens the entries of one oversized bucket to 64-bit keys for the global
-// sort.
+// The largest q with off[q] <= i (off ascending, off[0] = 0).
+__device__ __forceinline__ uint32_t over_of(const uint32_t* __restrict__ off, uint32_t nover,
+                                            uint32_t i) {
+  uint32_t lo = 0, hi = nover - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// w[off[q] + e] = q << sh | entry e of oversized bucket q: one sort orders
+// every oversized bucket's entries, bucket by bucket.
+__global__ void k_over_gather(const uint32_t* __restrict__ entries,
+                              const uint32_t* __restrict__ start, const uint32_t* __restrict__ off,
+                              uint32_t nover, uint32_t tot, int sh, uint64_t* __restrict__ w) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= tot) return;
+  const uint32_t q = over_of(off, nover, i);
+  w[i] = ((uint64_t)q << sh) | entries[(size_t)start[q] + (i - off[q])];
+}
+
+// col and row_ptr of every oversized bucket from the sorted tagged entries.
+__global__ void k_over_emit(const uint64_t* __restrict__ keys, uint32_t tot,
+                            const uint32_t* __restrict__ ids, const uint32_t* __restrict__ start,
+                            const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ off,
+                            int pb, int rb, int64_t n, int64_t* __restrict__ row_ptr,
+                            int32_t* __restrict__ col) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= tot) return;
+  const int sh = rb + pb;
+  const uint64_t emask = (1ull << sh) - 1ull;
+  const uint64_t key = keys[i];
+  const uint32_t q = (uint32_t)(key >> sh);
+  const uint32_t e = (uint32_t)(key & emask);
+  const uint32_t rr = e >> pb;
+  const uint32_t local = i - off[q];
+  const int64_t base = (int64_t)ids[q] << rb;
+  const int64_t at = (int64_t)start[q] + local;
+  col[at] = (int32_t)(e & ((1u << pb) - 1u));
+  // the first entry of each row sets row_ptr for it and the empty rows before
+  const uint32_t from = local == 0 ? 0u : (uint32_t)((keys[i - 1] & emask) >> pb) + 1u;
+  for (uint32_t r = from; r <= rr; ++r)
+    if (base + r < n) row_ptr[base + r] = at;
+  // the bucket's last entry sets the empty rows after it
+  if (local + 1 == cnt[q])
+    for (uint32_t r = rr + 1; r < (1u << rb); ++r)
+      if (base + r < n) row_ptr[base + r] = (int64_t)start[q] + cnt[q];
+}
+
+// dst[q] = src[q], zero-extended.
 __global__ void k_widen(const uint32_t* __restrict__ src, size_t count, uint64_t* __restrict__ dst) {
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q < count) dst[q] = src[q];
@@ -2560,20 +2599,32 @@ void launch_bucket_csr(const uint32_t* entries, const uint32_t* offs, uint32_t n
                      nbuckets, nblocks, total, oversized, n_oversized, cap, pb, rb, n, row_ptr, col);
 }
 
-void launch_bucket_emit_sorted(const uint64_t* keys, uint32_t cnt, uint32_t start, uint32_t b,
-                               int pb, int rb, int64_t n, int64_t* row_ptr, int32_t* col,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(k_bucket_emit_sorted, dim3(grid_for(cnt ? cnt : 1)), dim3(kBlock), 0, s, keys,
-                     cnt, start, b, pb, rb, n, row_ptr, col);
+void launch_over_extent(const uint32_t* ids, uint32_t nover, const uint32_t* part,
+                        uint32_t nblocks, uint32_t nbuckets, size_t np, uint32_t* start,
+                        uint32_t* cnt, hipStream_t s) {
+  if (!nover) return;
+  hipLaunchKernelGGL(k_over_extent, dim3(grid_for(nover)), dim3(kBlock), 0, s, ids, nover, part,
+                     nblocks, nbuckets, np, start, cnt);
 }
 
-void launch_widen(const uint32_t* src, size_t count, uint64_t* dst, hipStream_t s) {
-  if (!count) return;
-  hipLaunchKernelGGL(k_widen, dim3(grid_for(count)), dim3(kBlock), 0, s, src, count, dst);
+void launch_over_gather(const uint32_t* entries, const uint32_t* start, const uint32_t* off,
+                        uint32_t nover, uint32_t tot, int sh, uint64_t* w, hipStream_t s) {
+  if (!nover || !tot) return;
+  hipLaunchKernelGGL(k_over_gather, dim3(grid_for(tot)), dim3(kBlock), 0, s, entries, start, off,
+                     nover, tot, sh, w);
+}
+
+void launch_over_emit(const uint64_t* keys, uint32_t tot, const uint32_t* ids,
+                      const uint32_t* start, const uint32_t* cnt, const uint32_t* off, int pb,
+                      int rb, int64_t n, int64_t* row_ptr, int32_t* col, hipStream_t s) {
+  if (!tot) return;
+  hipLaunchKernelGGL(k_over_emit, dim3(grid_for(tot)), dim3(kBlock), 0, s, keys, tot, ids, start,
+                     cnt, off, pb, rb, n, row_ptr, col);
 }
 
 void launch_u32_to_u64(const uint32_t* src, size_t count, uint64_t* dst, hipStream_t s) {
-  launch_widen(src, count, dst, s);
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_widen, dim3(grid_for(count)), dim3(kBlock), 0, s, src, count, dst);
 }
 
 void launch_gather(const Gather& g, uint64_t* dst, hipStream_t s) {

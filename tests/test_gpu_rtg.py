@@ -317,6 +317,33 @@ def test_oversized_buckets_take_the_global_sort(ctx):
         other.close()
 
 
+def test_dense_rows_contiguous_in_index_order(ctx):
+    """Clustered points ordered along one axis put the heavy rows side by
+    side, so several neighbour-list buckets overflow LDS at once; they share
+    one global sort.  Also with a bucket capacity that only some exceed."""
+    from paper_1409_8112_amd import rtg
+    p = workloads.clustered_points(12000, 3, seed=9, n_clusters=8, sigma=0.03)
+    p = p[np.argsort(p[:, 0], kind="stable")]
+    ref = oracle.rtg(p, 0.06, 4, 2.0, 1)
+    res = ctx.all_pairs(_dev(p), 0.06, 4, 2.0, 1)
+    rp, col = res.to_numpy()
+    res.release()
+    _assert_same(rp, col, ref)
+    os.environ["RTG_BUCKET_CAP"] = "3000"
+    try:
+        other = rtg.Context(0, arena_bytes=4 << 30)
+    finally:
+        del os.environ["RTG_BUCKET_CAP"]
+    try:
+        for flags in (0, oracle.UPPER_ONLY):
+            res = other.all_pairs(_dev(p), 0.06, 4, 2.0, 1, flags)
+            rp, col = res.to_numpy()
+            res.release()
+            _assert_same(rp, col, oracle.rtg(p, 0.06, 4, 2.0, 1, flags))
+    finally:
+        other.close()
+
+
 def test_release_and_determinism(ctx):
     from paper_1409_8112_amd import rtg
     p = workloads.uniform_points(20000, 4, seed=2)
