@@ -46,15 +46,48 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// v from another lane by a DPP pattern (row_mask / bank_mask select the
+// written rows and banks; lanes whose source falls outside the row, or that
+// are not written, get old).  Every lane of the wave must be active.
+template <int Ctrl, int RowMask = 0xf, int BankMask = 0xf>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t old, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, Ctrl, RowMask, BankMask, false);
+}
+
+// The value of lane l (a constant or wave-uniform l), in every lane.
+__device__ __forceinline__ uint32_t lane_value(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ unsigned long long lane_value(unsigned long long v, int l) {
+  const uint32_t lo = lane_value((uint32_t)v, l), hi = lane_value((uint32_t)(v >> 32), l);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// DPP controls: row_shr:n = 0x110 + n, row_mirror = 0x140,
+// row_half_mirror = 0x141, row_bcast:15 = 0x142, row_bcast:31 = 0x143;
+// quad_perm [1,0,3,2] = 0xB1, [2,3,0,1] = 0x4E.
 template <typename T>
 __device__ __forceinline__ T wave_inclusive_scan(T v) {
-  const uint32_t lane = lane_id();
+  if constexpr (sizeof(T) == 4) {
+    // within each row of 16 lanes (shifts 1, 2, 4, 8), then row 0's total
+    // into rows 1 and 3, then rows 0-1's total into rows 2 and 3
+    uint32_t x = (uint32_t)v;
+    x += dpp_u32<0x111>(0u, x);
+    x += dpp_u32<0x112>(0u, x);
+    x += dpp_u32<0x114>(0u, x);
+    x += dpp_u32<0x118>(0u, x);
+    x += dpp_u32<0x142, 0xa>(0u, x);
+    x += dpp_u32<0x143, 0xc>(0u, x);
+    return (T)x;
+  } else {
+    const uint32_t lane = lane_id();
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    T t = __shfl_up(v, o, 64);
-    if (lane >= (uint32_t)o) v += t;
+    for (int o = 1; o < 64; o <<= 1) {
+      T t = __shfl_up(v, o, 64);
+      if (lane >= (uint32_t)o) v += t;
+    }
+    return v;
   }
-  return v;
 }
 
 // Exclusive scan of one value per thread over a 256-thread block.  wsum
@@ -916,7 +949,7 @@ __device__ __forceinline__ void flush_out(const PairsArgs& P, OutStage& O, uint3
   if (O.n) {
     unsigned long long base = 0;
     if (lane == 0) base = atomicAdd(P.cand_count, (unsigned long long)O.n);
-    base = __shfl(base, 0, 64);
+    base = lane_value(base, 0);
     for (uint32_t e = lane; e < O.n; e += 64) {
       const uint64_t g = base + e;
       if (g < P.cap) P.cand[g] = O.buf[e];
@@ -932,14 +965,14 @@ __device__ __forceinline__ void emit_pairs(const PairsArgs& P, OutStage& O, uint
                                            uint64_t acc, PairOf pair_of) {
   const uint32_t cnt = (uint32_t)__popcll(acc);
   const uint32_t incl = wave_inclusive_scan(cnt);
-  const uint32_t total = uniform(__shfl(incl, 63, 64));
+  const uint32_t total = lane_value(incl, 63);
   if (!total) return;
   if (O.n + total > (uint32_t)kOutBuf) flush_out(P, O, lane);
   if (total > (uint32_t)kOutBuf) {
     // more than the buffer holds: straight out
     unsigned long long base = 0;
     if (lane == 0) base = atomicAdd(P.cand_count, (unsigned long long)total);
-    base = __shfl(base, 0, 64);
+    base = lane_value(base, 0);
     uint64_t pos = base + incl - cnt;
     while (acc) {
       const int b = __builtin_ctzll(acc);
@@ -1131,10 +1164,19 @@ __device__ __forceinline__ float next_up(float x) {
   return (x == INFINITY) ? x : __uint_as_float(b + 1u);
 }
 
+// The maximum over the wave, uniform: quads (xor 1, xor 2), half rows and
+// rows by mirroring, then the four rows' maxima read out.
 __device__ __forceinline__ float wave_max_f(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
+  auto step = [](float x, uint32_t y) { return fmaxf(x, __uint_as_float(y)); };
+  v = step(v, dpp_u32<0xB1>(__float_as_uint(v), __float_as_uint(v)));
+  v = step(v, dpp_u32<0x4E>(__float_as_uint(v), __float_as_uint(v)));
+  v = step(v, dpp_u32<0x141>(__float_as_uint(v), __float_as_uint(v)));
+  v = step(v, dpp_u32<0x140>(__float_as_uint(v), __float_as_uint(v)));
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+  return fmaxf(fmaxf(r0, r1), fmaxf(r2, r3));
 }
 
 // Bits of a tile pair's 64-bit masks: bit 16 (2R + C) + 15 - i is register
@@ -1243,42 +1285,43 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs_gram(
       wave_lds_sync();
       float nb = 0.0f;
       uint64_t bsw[kSigWords];
-      {
-        float row[KA];
-        if (lane < nB) {
-          float n2 = 0.0f;
+      float row[KA];
+      if (lane < nB) {
+        float n2 = 0.0f;
 #pragma unroll
-          for (int l = 0; l < D; ++l) {
-            const float v = cur.c[l] - o[l];
-            row[l] = -2.0f * v;
-            n2 = __builtin_fmaf(v, v, n2);
-          }
-          row[D + 1] = n2;
-          nb = n2;
-        } else {
-#pragma unroll
-          for (int l = 0; l < D; ++l) row[l] = 0.0f;
-          row[D + 1] = 1e30f;
+        for (int l = 0; l < D; ++l) {
+          const float v = cur.c[l] - o[l];
+          row[l] = -2.0f * v;
+          n2 = __builtin_fmaf(v, v, n2);
         }
-        row[D] = 1.0f;
+        nb = n2;
+      } else {
 #pragma unroll
-        for (int l = D + 2; l < KA; ++l) row[l] = 0.0f;
-        sBi[w][lane] = cur.idx;
-#pragma unroll
-        for (int l = 0; l < KA; ++l) sB[lane][l] = row[l];
-#pragma unroll
-        for (int q = 0; q < kSigWords; ++q) bsw[q] = cur.sw[q];
+        for (int l = 0; l < D; ++l) row[l] = 0.0f;
       }
+      row[D] = 1.0f;
+#pragma unroll
+      for (int l = D + 2; l < KA; ++l) row[l] = 0.0f;
+#pragma unroll
+      for (int q = 0; q < kSigWords; ++q) bsw[q] = cur.sw[q];
       const float bmax = wave_max_f(nb);
+
+      // The tile pair's band.  The products carry lo into the sums (the B
+      // rows hold |b'|^2 - lo), so each output is x = v - lo: x < 0 accepts,
+      // x > W rejects, anything between is decided in FP64.  E bounds the
+      // rounding of x, including the lo term; a pair whose band reaches 0
+      // (cells far wider than r) is decided in FP64 throughout.
+      const float E = (amax + bmax + r2f) * kGain + r2f * (4.0f * kU) + 1e-36f;
+      const bool all_fp64 = !(E < r2f);
+      const float lo = all_fp64 ? 0.0f : (r2f - E) * (1.0f - 0x1p-20f);
+      const float hi = (r2f + E) * (1.0f + 0x1p-20f);
+      const uint32_t Wu = __float_as_uint(next_up(hi - lo));  // x <= W, as bits (x >= 0)
+      row[D + 1] = lane < nB ? nb - lo : 1e30f;
+      sBi[w][lane] = cur.idx;
+#pragma unroll
+      for (int l = 0; l < KA; ++l) sB[lane][l] = row[l];
       wave_lds_sync();
       load_next<D>(P, V, Vn, ta, tb, lane, nxt);
-
-      // the tile pair's band
-      const float E = (amax + bmax) * kGain + r2f * (4.0f * kU) + 1e-36f;
-      const float lo = (E < r2f) ? (r2f - E) * (1.0f - 0x1p-20f) : -INFINITY;
-      const float hi = (r2f + E) * (1.0f + 0x1p-20f);
-      const float lo1 = next_up(lo);  // v <= lo  <=>  v - lo1 < 0
-      const float hi1 = next_up(hi);
 
       float breg[2][KS];
 #pragma unroll
@@ -1300,14 +1343,24 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs_gram(
 #pragma unroll
           for (int q = 0; q < KS; ++q)
             v = __builtin_amdgcn_mfma_f32_32x32x2f32(areg[R][q], breg[C][q], v, 0, 0, 0);
-          // Bit 15 - i of am: v[i] <= lo, of cm: v[i] <= hi; each is the
-          // sign of v - (threshold's successor), shifted in from the right
-          // (v is finite: the host keeps coordinates small enough).
-          uint32_t am = 0u, cm = 0u;
+          // Bit 15 - i of am: x[i] < 0, its sign shifted in from the right
+          // (x is finite: the host keeps coordinates small enough).  The
+          // least x >= 0 as bits (negative x are larger as unsigned) tells
+          // whether any x lies in the band; only then are its bits built:
+          // bit 15 - i of cm is x[i] <= W.
+          uint32_t am = 0u, mn = 0xFFFFFFFFu;
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
-            am = __builtin_amdgcn_alignbit(am, __float_as_uint(v[i] - lo1), 31);
-            cm = __builtin_amdgcn_alignbit(cm, __float_as_uint(v[i] - hi1), 31);
+            am = __builtin_amdgcn_alignbit(am, __float_as_uint(v[i]), 31);
+            mn = min(mn, __float_as_uint(v[i]));
+          }
+          uint32_t cm = 0u;
+          if (ballot(mn <= Wu) || all_fp64) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+              cm = __builtin_amdgcn_alignbit(cm, __float_as_uint(v[i]) - (Wu + 1u), 31);
+            cm = all_fp64 ? 0xFFFFu : cm;
+            am = all_fp64 ? 0u : am;
           }
           uint32_t valid = 0xFFFFu;
           if (diag && R == C) {
@@ -1505,8 +1558,8 @@ __global__ __launch_bounds__(kBlock) void k_query_pairs(const QueryArgs A) {
       const int tn = min(64, A.k - t0);
       for (int tt = 0; tt < tn; ++tt) {
         const int t = t0 + tt;
-        const uint32_t lo = (uint32_t)__shfl((int)rlo, tt, 64);
-        const uint32_t hi = (uint32_t)__shfl((int)rhi, tt, 64);
+        const uint32_t lo = lane_value(rlo, tt);
+        const uint32_t hi = lane_value(rhi, tt);
         const QueryGrid G = A.grids[t];
         const uint64_t imask = G.idx_bits ? ((1ull << G.idx_bits) - 1ull) : 0ull;
         for (uint32_t base = lo; base < hi; base += 64) {
