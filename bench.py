@@ -36,7 +36,7 @@ FP32_VEC_PEAK_TFLOPS = 157.3  # MI355X FP32 vector and FP32 matrix (dense) peak
 SINGLE_KERNELS = {"keys": "k_keys", "key_hist": "k_radix_hist", "key_scatter": "k_radix_scatter<true>",
                   "pairs": "k_cell_pairs", "pair_hist": "k_radix_hist",
                   "pair_scatter": "k_radix_scatter<false>", "stage": "k_stage",
-                  "gather": "k_gather_units"}
+                  "gather": "k_gather_units", "compact": "k_seg_compact"}
 
 
 def measured_traffic(kernel_name: str):

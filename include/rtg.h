@@ -126,7 +126,8 @@ enum {
   RTG_K_CSR = 9,           /* neighbour-list build (incl. transposed sort)   */
   RTG_K_SCAN = 10,         /* prefix sums                                    */
   RTG_K_GATHER = 11,       /* cell members' coordinates by sorted position   */
-  RTG_NKERNELS = 12
+  RTG_K_COMPACT = 12,      /* pair output made contiguous; MR-metric filter  */
+  RTG_NKERNELS = 13
 };
 #define RTG_TIME_PHASES (1u << 31) /* rtg_set_timing: per-phase events too */
 

@@ -872,7 +872,8 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   float* aos = m > 1 ? S.get<float>((size_t)npts * d) : nullptr;
   uint32_t* part = S.get<uint32_t>((size_t)nblk * 2 * d);
   uint32_t* bbox = S.get<uint32_t>((size_t)m * 2 * d + 2);  // + [bad, err]
-  unsigned long long* counters = S.get<unsigned long long>(4);  // cand, rechecks, -, members
+  // -, rechecks, filter count, members, then the pair-output segments' counts
+  unsigned long long* counters = S.get<unsigned long long>(4 + kCandSegments);
   if (!inst_d || !tests_d || !Rd || !ud || !soa || (m > 1 && !aos) || !part || !bbox || !counters)
     return RTG_ENOMEM;
   uint32_t* bad = bbox + (size_t)m * 2 * d;
@@ -1122,48 +1123,66 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
       kend(RTG_K_GATHER, 0.0);
     }
 
-    // Room for this pass's pairs: a guess first, the exact count on overflow.
-    uint64_t want = cand_total + std::min<uint64_t>(tests_total,
-                                                    std::max<uint64_t>(1u << 20, tests_total / 16));
+    // This pass's pairs go to kCandSegments output segments, room for them
+    // from a guess first and from the largest count on overflow; then one
+    // copy puts them after the earlier passes' pairs in cand.
+    const uint32_t nseg = kCandSegments;
+    unsigned long long* segcnt = counters + 4;
+    const uint64_t guess =
+        std::min<uint64_t>(tests_total, std::max<uint64_t>(1u << 20, tests_total / 16));
+    uint64_t seg_cap = guess / nseg + guess / (4 * nseg) + 1024;
     for (int attempt = 0; attempt < 2; ++attempt) {
-      if (want > cap) {
-        uint64_t* grown = static_cast<uint64_t*>(dalloc(sizeof(uint64_t) * want));
-        if (!grown) return RTG_ENOMEM;
-        if (cand && cand_total)
-          if ((rc = hip_fail(hipMemcpyAsync(grown, cand, sizeof(uint64_t) * cand_total,
-                                            hipMemcpyDeviceToDevice, stream),
-                             "grow candidates")))
-            return rc;
-        if (cand) S.drop(cand);
-        S.held.push_back(grown);
-        cand = grown;
-        cap = want;
-      }
-      launch_fill_u64(reinterpret_cast<uint64_t*>(counters), cand_total, 1, stream);
-      pa.cand = cand;
-      pa.cap = cap;
-      pa.cand_count = counters;
+      uint64_t* sbuf = S.get<uint64_t>((size_t)nseg * seg_cap);
+      if (!sbuf) return RTG_ENOMEM;
+      launch_fill_u64(reinterpret_cast<uint64_t*>(segcnt), 0ull, nseg, stream);
+      pa.cand = sbuf;
+      pa.cap = seg_cap;
+      pa.cand_count = segcnt;
+      pa.nseg = nseg;
       pa.rechecks = counters + 1;
       kbegin(RTG_K_PAIRS);
       launch_cell_pairs(pa, stream);
       if (use_gram) st.matrix_screen_launches += 1;
       kend(RTG_K_PAIRS, 0.0);
-      unsigned long long cnt[4] = {0, 0, 0, 0};
-      if ((rc = read_back(counters, sizeof(cnt), cnt))) return rc;
-      const unsigned long long now = cnt[0];
+      std::vector<unsigned long long> cnt(4 + (size_t)nseg);
+      if ((rc = read_back(counters, sizeof(unsigned long long) * cnt.size(), cnt.data())))
+        return rc;
+      uint64_t total = 0, most = 0;
+      for (uint32_t g = 0; g < nseg; ++g) {
+        total += cnt[4 + g];
+        most = std::max<uint64_t>(most, cnt[4 + g]);
+      }
       // every member of a multi-point cell read once (index + coordinates;
       // counters[3] = members, summed by the cell-work kernel of this pass),
       // every pair within r written once
-      st.kernel_bytes[RTG_K_PAIRS] +=
-          (4.0 + 4.0 * d) * (double)cnt[3] + 8.0 * (double)(now - cand_total);
+      st.kernel_bytes[RTG_K_PAIRS] += (4.0 + 4.0 * d) * (double)cnt[3] + 8.0 * (double)total;
       if (attempt == 0 && !pa.direct)  // the gather: index, row, words in; row, words out
         st.kernel_bytes[RTG_K_GATHER] +=
             (8.0 + 8.0 * d + (first_owner ? 16.0 * sig_W : 0.0)) * (double)cnt[3];
-      if (now <= cap) {
-        cand_total = now;
+      if (most <= seg_cap) {
+        if (cand_total + total > cap) {
+          const uint64_t want = cand_total + total;
+          uint64_t* grown = static_cast<uint64_t*>(dalloc(sizeof(uint64_t) * std::max<uint64_t>(want, 1)));
+          if (!grown) return RTG_ENOMEM;
+          if (cand && cand_total)
+            if ((rc = hip_fail(hipMemcpyAsync(grown, cand, sizeof(uint64_t) * cand_total,
+                                              hipMemcpyDeviceToDevice, stream),
+                               "grow candidates")))
+              return rc;
+          if (cand) S.drop(cand);
+          S.held.push_back(grown);
+          cand = grown;
+          cap = want;
+        }
+        kbegin(RTG_K_COMPACT);
+        launch_seg_compact(sbuf, seg_cap, segcnt, nseg, most, cand + cand_total, stream);
+        kend(RTG_K_COMPACT, 16.0 * (double)total);
+        cand_total += total;
+        S.drop(sbuf);
         break;
       }
-      want = now;
+      S.drop(sbuf);
+      seg_cap = most;
       if (attempt == 1) return RTG_ENOMEM;
     }
     mark(5);
@@ -1196,12 +1215,12 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     launch_fill_u64(reinterpret_cast<uint64_t*>(counters) + 2, 0ull, 1, stream);
     MrFilterArgs fa{cand, cand_total, pair_bits, d, pts_rows, pts_rows, mi_d, (int)m, kept,
                     counters + 2};
-    kbegin(RTG_K_PAIRS);
+    kbegin(RTG_K_COMPACT);
     launch_mr_filter(fa, stream);
-    kend(RTG_K_PAIRS, (8.0 + 8.0 * d) * (double)cand_total);  // pairs and both rows read
+    kend(RTG_K_COMPACT, (8.0 + 8.0 * d) * (double)cand_total);  // pairs and both rows read
     unsigned long long nk = 0;
     if ((rc = read_back(counters + 2, sizeof(nk), &nk))) return rc;
-    st.kernel_bytes[RTG_K_PAIRS] += 8.0 * (double)nk;  // kept pairs written
+    st.kernel_bytes[RTG_K_COMPACT] += 8.0 * (double)nk;  // kept pairs written
     st.band_rechecks += (int64_t)cand_total;
     S.drop(cand);
     cand = kept;
@@ -1826,12 +1845,12 @@ int Lane::query_index(const Index& I, const float* queries, int64_t m, rtg_stats
     if ((rc = upload(mi_d, &mi, sizeof(mi)))) return rc;
     launch_fill_u64(reinterpret_cast<uint64_t*>(counter), 0ull, 1, stream);
     MrFilterArgs fa{cand, C, A.pb, d, queries, I.pts, mi_d, 1, kept, counter};
-    kbegin(RTG_K_PAIRS);
+    kbegin(RTG_K_COMPACT);
     launch_mr_filter(fa, stream);
-    kend(RTG_K_PAIRS, (8.0 + 8.0 * d) * (double)C);
+    kend(RTG_K_COMPACT, (8.0 + 8.0 * d) * (double)C);
     unsigned long long nk = 0;
     if ((rc = read_back(counter, sizeof(nk), &nk))) return rc;
-    st.kernel_bytes[RTG_K_PAIRS] += 8.0 * (double)nk;
+    st.kernel_bytes[RTG_K_COMPACT] += 8.0 * (double)nk;
     st.band_rechecks = (int64_t)C;
     S.drop(cand);
     cand = kept;

@@ -193,9 +193,12 @@ void launch_unit_fill(const uint32_t* start, const uint32_t* end, const uint32_t
 // The pair kernels read every unit's points by sorted position: their
 // coordinates spts[l][p] and signature words ssig[w][p], gathered once by
 // launch_gather_units.  One 64-wide wave per unit emits packed pairs
-// (min << pair_bits | max) for same-cell pairs within r; cand_count is the
-// running total (it may exceed cap: then the overflow is only counted);
-// rechecks counts FP64 band re-tests.
+// (min << pair_bits | max) for same-cell pairs within r.  The output has
+// nseg segments of cap entries each (segment s at cand + s cap, taken by
+// blocks b with b % nseg == s, so that the segments' counters are not all
+// contended by every XCD); cand_count[s] is segment s's running total (it
+// may exceed cap: then the overflow is only counted).  rechecks counts FP64
+// band re-tests.
 struct PairsArgs {
   const UnitDesc* units;
   uint32_t total_units;
@@ -213,8 +216,9 @@ struct PairsArgs {
   int W, g, gpw;           // signature layout
   uint64_t lows, highs;    // lowest and highest bit of each signature group
   uint64_t* cand;
-  uint64_t cap;
-  unsigned long long *cand_count, *rechecks;
+  uint64_t cap;            // entries per segment
+  unsigned long long *cand_count, *rechecks;  // cand_count: [nseg]
+  uint32_t nseg;           // output segments (0 or 1: one)
   int gram;                // 1: matrix-core screen (d <= 16), 0: vector screen
   uint32_t max_blocks;     // grid size cap (0: default)
 };
@@ -309,6 +313,10 @@ void launch_query_pairs(const QueryArgs& a, hipStream_t s);
 void launch_gather_units(const PairsArgs& a, const uint64_t* sig, float* spts, uint64_t* ssig,
                          hipStream_t s);
 void launch_cell_pairs(const PairsArgs& a, hipStream_t s);
+// dst[0, sum cnt) = the segments' entries in segment order: segment s holds
+// src[s seg_cap, s seg_cap + cnt[s]).  dst must not overlap src.
+void launch_seg_compact(const uint64_t* src, uint64_t seg_cap, const unsigned long long* cnt,
+                        uint32_t nseg, uint64_t max_count, uint64_t* dst, hipStream_t s);
 
 // --- unique + CSR -----------------------------------------------------------
 void launch_unique_count(const uint64_t* keys, size_t count, uint32_t* tile_cnt, hipStream_t s);

@@ -942,17 +942,30 @@ __device__ __forceinline__ void load_next(const PairsArgs& P, const UnitView& V,
 struct OutStage {
   uint64_t* buf;  // kOutBuf entries of this wave
   uint32_t n = 0;
+  uint64_t* dst;               // this block's output segment
+  unsigned long long* count;   // and its running total
+  uint64_t cap;                // the segment's capacity
 };
+
+__device__ __forceinline__ OutStage out_stage(const PairsArgs& P, uint64_t* buf) {
+  OutStage O;
+  O.buf = buf;
+  const uint32_t seg = P.nseg > 1 ? blockIdx.x % P.nseg : 0u;
+  O.dst = P.cand + (size_t)seg * P.cap;
+  O.count = P.cand_count + seg;
+  O.cap = P.cap;
+  return O;
+}
 
 __device__ __forceinline__ void flush_out(const PairsArgs& P, OutStage& O, uint32_t lane) {
   wave_lds_sync();
   if (O.n) {
     unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(P.cand_count, (unsigned long long)O.n);
+    if (lane == 0) base = atomicAdd(O.count, (unsigned long long)O.n);
     base = lane_value(base, 0);
     for (uint32_t e = lane; e < O.n; e += 64) {
       const uint64_t g = base + e;
-      if (g < P.cap) P.cand[g] = O.buf[e];
+      if (g < O.cap) O.dst[g] = O.buf[e];
     }
     O.n = 0;
   }
@@ -971,13 +984,13 @@ __device__ __forceinline__ void emit_pairs(const PairsArgs& P, OutStage& O, uint
   if (total > (uint32_t)kOutBuf) {
     // more than the buffer holds: straight out
     unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(P.cand_count, (unsigned long long)total);
+    if (lane == 0) base = atomicAdd(O.count, (unsigned long long)total);
     base = lane_value(base, 0);
     uint64_t pos = base + incl - cnt;
     while (acc) {
       const int b = __builtin_ctzll(acc);
       acc &= acc - 1;
-      if (pos < P.cap) P.cand[pos] = pair_of(b);
+      if (pos < O.cap) O.dst[pos] = pair_of(b);
       ++pos;
     }
   } else {
@@ -1012,8 +1025,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs(const PairsArgs P) {
   const uint32_t lane = lane_id();
   const int w = threadIdx.x >> 6;
   unsigned long long nre = 0;
-  OutStage O;
-  O.buf = sOut[w];
+  OutStage O = out_stage(P, sOut[w]);
 
   const uint32_t wave_id = blockIdx.x * kWaves + w;
   const uint32_t nwaves = gridDim.x * kWaves;
@@ -1214,8 +1226,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs_gram(
   uint64_t (*sAw)[kPairTile] = reinterpret_cast<uint64_t (*)[kPairTile]>(sAreg[w]);
   uint64_t (*sBw)[kPairTile] = reinterpret_cast<uint64_t (*)[kPairTile]>(sBreg[w]);
   unsigned long long nre = 0;
-  OutStage O;
-  O.buf = sOut[w];
+  OutStage O = out_stage(P, sOut[w]);
 
   const uint32_t wave_id = blockIdx.x * kWaves + w;
   const uint32_t nwaves = gridDim.x * kWaves;
@@ -1526,8 +1537,7 @@ __global__ __launch_bounds__(kBlock) void k_query_pairs(const QueryArgs A) {
   P.cand = A.cand;
   P.cap = A.cap;
   P.cand_count = A.cand_count;
-  OutStage O;
-  O.buf = sOut[w];
+  OutStage O = out_stage(P, sOut[w]);
   const uint32_t n = (uint32_t)A.n;
   const int64_t wave_id = (int64_t)blockIdx.x * kWaves + w;
   const int64_t nwaves = (int64_t)gridDim.x * kWaves;
@@ -1704,6 +1714,21 @@ __device__ __forceinline__ bool bitmap_first(const BitmapArgs& A, uint64_t v) {
 
 __global__ __launch_bounds__(kBlock) void k_bitmap_unique(const BitmapArgs A) {
   compact_tiles(A.in, A.count, A.out, A.out_count, [&](uint64_t v) { return bitmap_first(A, v); });
+}
+
+// Segment blockIdx.y of the pair output to its place in dst.
+__global__ __launch_bounds__(kBlock) void k_seg_compact(const uint64_t* __restrict__ src,
+                                                        uint64_t seg_cap,
+                                                        const unsigned long long* __restrict__ cnt,
+                                                        uint64_t* __restrict__ dst) {
+  const uint32_t g = blockIdx.y;
+  uint64_t off = 0;
+  for (uint32_t h = 0; h < g; ++h) off += cnt[h];
+  const uint64_t n = cnt[g];
+  const uint64_t* s = src + (size_t)g * seg_cap;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * kBlock)
+    dst[off + i] = s[i];
 }
 
 // Unit descriptors of cell c: the whole cell, or one unit per tile.
@@ -2485,6 +2510,15 @@ void launch_query_keys(const QueryArgs& a, hipStream_t s) {
     default: RTG_QK(0); break;
   }
 #undef RTG_QK
+}
+
+void launch_seg_compact(const uint64_t* src, uint64_t seg_cap, const unsigned long long* cnt,
+                        uint32_t nseg, uint64_t max_count, uint64_t* dst, hipStream_t s) {
+  if (nseg == 0 || max_count == 0) return;
+  uint64_t bx = (max_count + kBlock * 4 - 1) / (kBlock * 4);
+  if (bx > 512) bx = 512;
+  hipLaunchKernelGGL(k_seg_compact, dim3((unsigned)bx, nseg), dim3(kBlock), 0, s, src, seg_cap,
+                     cnt, dst);
 }
 
 static unsigned compact_blocks(uint64_t count) {

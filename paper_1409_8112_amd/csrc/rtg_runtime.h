@@ -57,6 +57,8 @@ int min_field_bits(double alpha);
 int validate_query(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha);
 // Flags that shape a pass's output (instances batched together share them).
 constexpr uint32_t kListFlags = RTG_UPPER_ONLY | RTG_DEDUP_SORT | RTG_DEDUP_BITMAP;
+// Output segments of the pair kernels (each with its own counter).
+constexpr uint32_t kCandSegments = 32;
 // Largest pair bitmap of one pass (RTG_DEDUP_BITMAP): beyond it the pass
 // removes repeats by the first-owner rule instead.
 constexpr uint64_t kBitmapMaxBytes = uint64_t(4) << 30;

@@ -30,7 +30,7 @@ def robots(b: int) -> int:
     return int(b) << ROBOTS_SHIFT
 # kernel ids of rtg_stats.kernel_* (RTG_K_* in rtg.h)
 KERNELS = ["stage", "keys", "key_hist", "key_scatter", "cells", "pairs", "pair_hist",
-           "pair_scatter", "unique", "csr", "scan", "gather"]
+           "pair_scatter", "unique", "csr", "scan", "gather", "compact"]
 NKERNELS = len(KERNELS)
 TIME_PHASES = 1 << 31
 
