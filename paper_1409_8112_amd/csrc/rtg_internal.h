@@ -345,8 +345,8 @@ void launch_csr_fill_lower(const uint64_t* lo, size_t count, int pair_bits, cons
 // buckets of 2^rb rows (rb <= 11) as 32-bit keys (row mod 2^rb) << pb | col
 // (needs rb + pb <= 32).  Blocks take `chunk` pairs each; part / offs are
 // [nbuckets][nblocks] counts / their exclusive scan (bucket-major).
-constexpr int kBucketMaxEntries = 28672;  // entries one block holds in LDS
-constexpr int kBucketMaxRows = 2048;      // rows per bucket (rb <= 11)
+constexpr int kBucketMaxEntries = 16384;  // entries one block holds in LDS
+constexpr int kBucketMaxRows = 1024;      // rows per bucket (rb <= 10)
 void launch_bucket_hist(const uint64_t* pairs, size_t count, int pb, int rb, int both,
                         uint32_t nbuckets, uint32_t chunk, uint32_t nblocks, uint32_t* part,
                         hipStream_t s);

@@ -2103,8 +2103,6 @@ __global__ __launch_bounds__(kCsrThreads) void k_bucket_csr(
   }
 }
 
-// col / row_ptr of one bucket whose (row, col) keys are already sorted in
-// keys[0..cnt): the caller's path for buckets too large for LDS.
 // Buckets beyond LDS capacity, all in one global sort.  Bucket ids[q] holds
 // entries [start[q], start[q] + cnt[q]) of the entry array (and of col).
 __global__ void k_over_extent(const uint32_t* __restrict__ ids, uint32_t nover,
