@@ -437,6 +437,10 @@ int Lane::init(Ctx* c, hipStream_t s, bool create_stream) {
     own_stream = true;
   }
   if (hipHostMalloc(&host_stage, 4096) != hipSuccess) return RTG_EDEVICE;
+  host_stage_bytes = 4096;
+  if (hipHostMalloc(&host_up, 65536) != hipSuccess) return RTG_EDEVICE;
+  host_up_bytes = 65536;
+  if (hipEventCreateWithFlags(&up_done, hipEventDisableTiming) != hipSuccess) return RTG_EDEVICE;
   gather_dev = c->dalloc(64);
   if (!gather_dev) return RTG_ENOMEM;
   for (auto& e : ev)
@@ -448,6 +452,10 @@ void Lane::fini() {
   if (stream || own_stream) (void)hipStreamSynchronize(stream);
   if (host_stage) (void)hipHostFree(host_stage);
   host_stage = nullptr;
+  if (host_up) (void)hipHostFree(host_up);
+  host_up = nullptr;
+  if (up_done) (void)hipEventDestroy(up_done);
+  up_done = nullptr;
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& e : kev) (void)hipEventDestroy(e);
@@ -465,6 +473,15 @@ void Lane::dfree(void* p) { ctx->dfree(p); }
 int Lane::sync() { return hip_fail(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
 
 int Lane::read_back(const void* dev, size_t bytes, void* host) {
+  if (bytes > host_stage_bytes) {
+    // every earlier read-back has completed (each one waits)
+    const size_t grown = std::max(bytes, 2 * host_stage_bytes);
+    void* p = nullptr;
+    if (hipHostMalloc(&p, grown) != hipSuccess) return hip_fail(hipErrorOutOfMemory, "hipHostMalloc");
+    (void)hipHostFree(host_stage);
+    host_stage = p;
+    host_stage_bytes = grown;
+  }
   hipError_t e = hipMemcpyAsync(host_stage, dev, bytes, hipMemcpyDeviceToHost, stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync D2H");
   int rc = sync();
@@ -488,6 +505,22 @@ int Lane::download(void* host, const void* dev, size_t bytes) {
 int Lane::upload(void* dev, const void* host, size_t bytes) {
   return hip_fail(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, stream),
                   "hipMemcpyAsync H2D");
+}
+
+int Lane::up_room(size_t bytes) {
+  if (up_pending) {
+    if (hipEventSynchronize(up_done) != hipSuccess) return hip_fail(hipErrorUnknown, "upload wait");
+    up_pending = false;
+  }
+  if (bytes > host_up_bytes) {
+    const size_t grown = std::max(bytes, 2 * host_up_bytes);
+    void* p = nullptr;
+    if (hipHostMalloc(&p, grown) != hipSuccess) return hip_fail(hipErrorOutOfMemory, "hipHostMalloc");
+    (void)hipHostFree(host_up);
+    host_up = p;
+    host_up_bytes = grown;
+  }
+  return RTG_OK;
 }
 
 void Lane::mark(int phase) {
@@ -576,6 +609,44 @@ int validate_query(const float* points, int64_t n, int32_t d, double r, int32_t 
 
 namespace {
 
+// Host arrays bound for the device in one transfer: add() reserves a
+// 256-byte aligned slot and returns its offset; send() copies every slot
+// from the lane's pinned staging into one device block with one
+// hipMemcpyAsync, ordered on the lane's stream.
+class Uploads {
+ public:
+  explicit Uploads(Lane& lane) : L_(lane) {}
+  size_t add(const void* host, size_t bytes) {
+    const size_t off = total_;
+    parts_.push_back(Part{host, bytes, off});
+    total_ = (off + bytes + 255) & ~(size_t)255;
+    return off;
+  }
+  size_t total() const { return total_; }
+  int send(void* dev) {
+    if (!total_) return RTG_OK;
+    int rc = L_.up_room(total_);
+    if (rc) return rc;
+    for (const Part& p : parts_)
+      if (p.bytes) std::memcpy(static_cast<char*>(L_.host_up) + p.off, p.host, p.bytes);
+    rc = L_.hip_fail(hipMemcpyAsync(dev, L_.host_up, total_, hipMemcpyHostToDevice, L_.stream),
+                     "hipMemcpyAsync H2D");
+    if (rc) return rc;
+    rc = L_.hip_fail(hipEventRecord(L_.up_done, L_.stream), "hipEventRecord");
+    if (!rc) L_.up_pending = true;
+    return rc;
+  }
+
+ private:
+  struct Part {
+    const void* host;
+    size_t bytes, off;
+  };
+  Lane& L_;
+  std::vector<Part> parts_;
+  size_t total_ = 0;
+};
+
 // Frees every arena block taken through it when it goes out of scope.
 // Blocks are returned only after the lane's stream has drained, so that
 // another lane cannot reuse memory a kernel of this one still touches.
@@ -621,7 +692,9 @@ int alloc_result(Lane& c, int64_t n, size_t nnz, void** res, int64_t** row_ptr, 
 // too large for LDS go through the global radix sort.
 int csr_by_buckets(Lane& c, Scratch& S, const uint64_t* pairs, size_t count, int64_t n, int pb,
                    bool both, uint32_t* err, const LaunchTimer* tm, void** res, int64_t** row_ptr,
-                   int32_t** col, size_t* nnz_out) {
+                   int32_t** col, size_t* nnz_out, uint32_t* err_host = nullptr,
+                   bool* drained = nullptr) {
+  if (drained) *drained = false;
   hipStream_t s = c.stream;
   int rc;
   const size_t E = both ? 2 * count : count;
@@ -656,11 +729,18 @@ int csr_by_buckets(Lane& c, Scratch& S, const uint64_t* pairs, size_t count, int
   // read the pairs twice, write and read the entries, write col and row_ptr
   if (tm) tm->on_end(RTG_K_CSR, 16.0 * (double)count + 8.0 * (double)E + 4.0 * (double)E +
                                     8.0 * (double)(n + 1));
-  uint32_t nover = 0;
-  if ((rc = c.read_back(over, sizeof(nover), &nover))) {
+  // one read for the oversized count and the error bits of everything so far
+  uint64_t got[8];
+  Gather g;
+  g.add(over, 4);
+  g.add(err, 4);
+  if ((rc = c.gather_back(g, got))) {
     c.dfree(*res);
     return rc;
   }
+  const uint32_t nover = (uint32_t)got[0];
+  if (err_host) *err_host = (uint32_t)got[1];
+  if (drained) *drained = nover == 0;
   if (nover) {
     // Buckets beyond LDS capacity (heavy rows, or rows that cluster in index
     // order), all in one global radix sort of their entries tagged with the
@@ -867,26 +947,29 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     std::memcpy(&uh[(size_t)inst[q].tr_off * d], j.u, sizeof(double) * (size_t)j.k * d);
   }
 
-  InstDesc* inst_d = S.get<InstDesc>(m);
-  PairTest* tests_d = S.get<PairTest>(m);
-  double* Rd = S.get<double>(Rh.size());
-  double* ud = S.get<double>(uh.size());
+  Uploads U1(*this);
+  const size_t o_inst = U1.add(inst.data(), sizeof(InstDesc) * m);
+  const size_t o_tests = U1.add(tests.data(), sizeof(PairTest) * m);
+  const size_t o_R = U1.add(Rh.data(), sizeof(double) * Rh.size());
+  const size_t o_u = U1.add(uh.data(), sizeof(double) * uh.size());
+  char* up1 = S.get<char>(U1.total());
+  if (!up1) return RTG_ENOMEM;
+  InstDesc* inst_d = reinterpret_cast<InstDesc*>(up1 + o_inst);
+  PairTest* tests_d = reinterpret_cast<PairTest*>(up1 + o_tests);
+  double* Rd = reinterpret_cast<double*>(up1 + o_R);
+  double* ud = reinterpret_cast<double*>(up1 + o_u);
   float* soa = S.get<float>((size_t)npts * d);
   float* aos = m > 1 ? S.get<float>((size_t)npts * d) : nullptr;
   uint32_t* part = S.get<uint32_t>((size_t)nblk * 2 * d);
-  uint32_t* bbox = S.get<uint32_t>((size_t)m * 2 * d + 2);  // + [bad, err]
-  // -, rechecks, filter count, members, then the pair-output segments' counts
-  unsigned long long* counters = S.get<unsigned long long>(4 + kCandSegments);
-  if (!inst_d || !tests_d || !Rd || !ud || !soa || (m > 1 && !aos) || !part || !bbox || !counters)
-    return RTG_ENOMEM;
+  uint32_t* bbox = S.get<uint32_t>((size_t)m * 2 * d + 1);  // + [bad]
+  // -, rechecks, filter count, members, the pair-output segments' counts,
+  // then err (read back with them after each pass's pair kernel)
+  unsigned long long* counters = S.get<unsigned long long>(kCounterWords);
+  if (!soa || (m > 1 && !aos) || !part || !bbox || !counters) return RTG_ENOMEM;
   uint32_t* bad = bbox + (size_t)m * 2 * d;
-  uint32_t* err = bad + 1;
-  if ((rc = upload(inst_d, inst.data(), sizeof(InstDesc) * m))) return rc;
-  if ((rc = upload(tests_d, tests.data(), sizeof(PairTest) * m))) return rc;
-  if ((rc = upload(Rd, Rh.data(), sizeof(double) * Rh.size()))) return rc;
-  if ((rc = upload(ud, uh.data(), sizeof(double) * uh.size()))) return rc;
-  launch_fill_u32(err, 0u, 1, stream);
-  launch_fill_u64(reinterpret_cast<uint64_t*>(counters), 0ull, 4, stream);
+  uint32_t* err = reinterpret_cast<uint32_t*>(counters + kErrWord);
+  if ((rc = U1.send(up1))) return rc;
+  launch_fill_u64(reinterpret_cast<uint64_t*>(counters), 0ull, kCounterWords, stream);
 
   // --- stage: SoA copy (+ concatenated rows), finiteness, bounding boxes -------
   kbegin(RTG_K_STAGE);
@@ -894,8 +977,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   kend(RTG_K_STAGE, (aos ? 12.0 : 8.0) * (double)npts * d);
   mark(1);
   std::vector<uint32_t> hb((size_t)m * 2 * d + 1);
-  if ((rc = sync())) return rc;
-  if ((rc = download(hb.data(), bbox, sizeof(uint32_t) * hb.size()))) return rc;
+  if ((rc = read_back(bbox, sizeof(uint32_t) * hb.size(), hb.data()))) return rc;
   if (hb[(size_t)m * 2 * d]) return RTG_EINVAL;
   const float* pts_rows = aos ? aos : jobs[0]->pts;
 
@@ -924,12 +1006,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   st.pair_bits = 2 * pair_bits;
   st.transforms_per_sort = P.tb;
 
-  KeyLayout* layout_d = S.get<KeyLayout>(1);
-  int64_t* klo_d = S.get<int64_t>(P.klo.size());
-  SegDesc* segs_d = S.get<SegDesc>((size_t)S_total);
-  if (!layout_d || !klo_d || !segs_d) return RTG_ENOMEM;
-  if ((rc = upload(layout_d, &P.layout, sizeof(KeyLayout)))) return rc;
-  if ((rc = upload(klo_d, P.klo.data(), sizeof(int64_t) * P.klo.size()))) return rc;
+
 
   // Passes: consecutive ranges of P.tb segments; key offsets restart per pass.
   std::vector<SegDesc> segs((size_t)S_total);
@@ -948,7 +1025,16 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
       }
     NB = std::max(NB, (size_t)off);
   }
-  if ((rc = upload(segs_d, segs.data(), sizeof(SegDesc) * segs.size()))) return rc;
+  Uploads U2(*this);
+  const size_t o_layout = U2.add(&P.layout, sizeof(KeyLayout));
+  const size_t o_klo = U2.add(P.klo.data(), sizeof(int64_t) * P.klo.size());
+  const size_t o_segs = U2.add(segs.data(), sizeof(SegDesc) * segs.size());
+  char* up2 = S.get<char>(U2.total());
+  if (!up2) return RTG_ENOMEM;
+  KeyLayout* layout_d = reinterpret_cast<KeyLayout*>(up2 + o_layout);
+  int64_t* klo_d = reinterpret_cast<int64_t*>(up2 + o_klo);
+  SegDesc* segs_d = reinterpret_cast<SegDesc*>(up2 + o_segs);
+  if ((rc = U2.send(up2))) return rc;
 
   // The point index rides in the low bits of the key when both fit in 64
   // bits: the sort then moves 8 bytes per element instead of 12.
@@ -1014,6 +1100,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   uint64_t cap = 0;
   uint64_t* cand = nullptr;
   uint64_t cand_total = 0;  // exact number of candidates so far
+  uint64_t rechecks_seen = 0;
 
   // Pair screen: matrix cores when every instance suits them.  Their Gram
   // form squares and sums coordinates, so it needs |coordinate| <= 2^60
@@ -1150,6 +1237,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
       std::vector<unsigned long long> cnt(4 + (size_t)nseg);
       if ((rc = read_back(counters, sizeof(unsigned long long) * cnt.size(), cnt.data())))
         return rc;
+      rechecks_seen = cnt[1];  // FP64 re-tests so far (a running total)
       uint64_t total = 0, most = 0;
       for (uint32_t g = 0; g < nseg; ++g) {
         total += cnt[4 + g];
@@ -1190,16 +1278,8 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     }
     mark(5);
   }
-  {
-    uint64_t fin[8];
-    Gather g3;
-    g3.add(err, 4);
-    g3.add(counters + 1, 8);
-    if ((rc = gather_back(g3, fin))) return rc;
-    if (fin[0] & 1u) return RTG_ERANGE;
-    if (fin[0]) return hip_fail(hipErrorUnknown, "radix sort look-back");
-    st.band_rechecks += (int64_t)fin[1];
-  }
+  // (each pass checked err after its key sort; the pair kernels set none)
+  st.band_rechecks += (int64_t)rechecks_seen;
 
   // Key buffers are no longer needed.
   for (void* p : {(void*)keys, (void*)keys_alt, (void*)vals, (void*)vals_alt, (void*)cstart,
@@ -1304,12 +1384,15 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   int64_t* row_ptr = nullptr;
   int32_t* col = nullptr;
   size_t nnz = 0;
+  // drained: the list build read err after its last kernel and nothing ran since
+  bool drained = false;
+  uint32_t err_seen = 0;
   if (npairs == 0) {
     if ((rc = alloc_result(*this, npts, 0, &res, &row_ptr, &col))) return rc;
     launch_fill_u64(reinterpret_cast<uint64_t*>(row_ptr), 0ull, (size_t)(npts + 1), stream);
   } else if (bucket_ok) {
     rc = csr_by_buckets(*this, S, pairs, npairs, npts, pair_bits, both, err, &tm, &res, &row_ptr,
-                        &col, &nnz);
+                        &col, &nnz, &err_seen, &drained);
     if (rc) return rc;
   } else {
     nnz = both ? 2 * npairs : npairs;
@@ -1374,17 +1457,18 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     }
   }
   mark(8);
-  if ((rc = sync())) {
-    if (m == 1) dfree(res);
-    return rc;
-  }
   if ((rc = hip_fail(hipGetLastError(), "kernel launch"))) {
     if (m == 1) dfree(res);
     return rc;
   }
   {
-    uint32_t errh2 = 0;
-    if ((rc = read_back(err, sizeof(errh2), &errh2)) || errh2) {
+    // Wait for the pass (the read waits) and check the sorts' error bits,
+    // unless the list build already did after the last kernel (phase
+    // timing needs the final event, so it always waits).
+    uint32_t errh2 = err_seen;
+    if (!(m == 1 && drained) || (timing_mask & RTG_TIME_PHASES))
+      rc = read_back(err, sizeof(errh2), &errh2);
+    if (rc || errh2) {
       if (m == 1) dfree(res);
       return rc ? rc : hip_fail(hipErrorUnknown, "radix sort look-back");
     }

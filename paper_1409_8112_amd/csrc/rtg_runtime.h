@@ -59,6 +59,11 @@ int validate_query(const float* points, int64_t n, int32_t d, double r, int32_t 
 constexpr uint32_t kListFlags = RTG_UPPER_ONLY | RTG_DEDUP_SORT | RTG_DEDUP_BITMAP;
 // Output segments of the pair kernels (each with its own counter).
 constexpr uint32_t kCandSegments = 32;
+// The pass counters: [0] unused, [1] FP64 re-tests, [2] filter count,
+// [3] cell members, [4, 4 + kCandSegments) segment counts, then the
+// pipeline's error bits (a u32 in the low half of the last word).
+constexpr uint32_t kErrWord = 4 + kCandSegments;
+constexpr uint32_t kCounterWords = kErrWord + 1;
 // Largest pair bitmap of one pass (RTG_DEDUP_BITMAP): beyond it the pass
 // removes repeats by the first-owner rule instead.
 constexpr uint64_t kBitmapMaxBytes = uint64_t(4) << 30;
@@ -127,7 +132,12 @@ struct Lane {
   Ctx* ctx = nullptr;
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  void* host_stage = nullptr;  // pinned staging for scalar read-backs (4 KB)
+  void* host_stage = nullptr;  // pinned staging for read-backs
+  size_t host_stage_bytes = 0;
+  void* host_up = nullptr;     // pinned staging for batched uploads
+  size_t host_up_bytes = 0;
+  hipEvent_t up_done = nullptr;  // recorded after the last batched upload's copy
+  bool up_pending = false;
   void* gather_dev = nullptr;  // 8 device u64 that gather_back fills
   uint32_t timing_mask = 0;    // bit i: time kernel id i; RTG_TIME_PHASES: phases
   hipEvent_t ev[9] = {};
@@ -145,6 +155,9 @@ struct Lane {
   // Several device scalars in one copy (one sync).
   int gather_back(const rtgk::Gather& g, uint64_t* host);
   int upload(void* dev, const void* host, size_t bytes);
+  // Room for bytes in the pinned upload staging, once the previous batched
+  // upload has left it.
+  int up_room(size_t bytes);
   int download(void* host, const void* dev, size_t bytes);  // ordered on the stream, waits
   void mark(int phase);
   void kbegin(int kid);
