@@ -335,7 +335,7 @@ Ctx::Ctx(int dev) : device(dev) {
   // unit of the pair kernels (larger cells: one unit per tile).
   if (const char* e = std::getenv("RTG_UNIT_TILES"))
     cell_unit_tiles = (uint32_t)std::max(1, std::min(64, std::atoi(e)));
-  // RTG_PAIR_BLOCKS: grid size cap of the pair kernels (default 2048).
+  // RTG_PAIR_BLOCKS: grid size of the pair kernels (default: from the work).
   if (const char* e = std::getenv("RTG_PAIR_BLOCKS"))
     pair_blocks = (uint32_t)std::max(1, std::min(1 << 20, std::atoi(e)));
   // RTG_LANES: passes of the request loop that may run at once (1..4).
@@ -344,6 +344,8 @@ Ctx::Ctx(int dev) : device(dev) {
   // RTG_BUCKET_CAP lowers the entries a neighbour-list bucket may hold in
   // LDS (tests use it to send buckets down the global-sort fallback).
   const char* bc = std::getenv("RTG_BUCKET_CAP");
+  if (const char* e = std::getenv("RTG_UNITS"))
+    balanced_units = std::strcmp(e, "roundrobin") != 0;
   bucket_cap = kBucketMaxEntries;
   if (bc) {
     const long v = std::strtol(bc, nullptr, 10);
@@ -1057,8 +1059,16 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   const size_t s64 = scan_scratch_elems(max_cells);
   uint64_t* scan64 = S.get<uint64_t>(s64 + 4);
   uint32_t* scan32 = S.get<uint32_t>(s64 + 4);
+  // the units' tile pairs, their prefix, and each pair-kernel wave's run of units
+  const bool balanced = ctx->balanced_units;
+  const size_t su = scan_scratch_elems(max_units);
+  uint64_t* uwork = balanced ? S.get<uint64_t>(max_units) : nullptr;
+  uint64_t* uscan = balanced ? S.get<uint64_t>(su + 4) : nullptr;
+  const size_t max_waves = (size_t)std::max<uint32_t>(ctx->pair_blocks, kMaxPairBlocks) * kWaves;
+  uint32_t* wfirst = balanced ? S.get<uint32_t>(max_waves + 1) : nullptr;
   if (!keys || !keys_alt || (!idx_bits && (!vals || !vals_alt)) || !sort_scr || !run_scr ||
-      !cstart || !cend || !units || !udesc || !spts || !tests_c || !scan64 || !scan32)
+      !cstart || !cend || !units || !udesc || !spts || !tests_c || !scan64 || !scan32 ||
+      (balanced && (!uwork || !uscan || !wfirst)))
     return RTG_ENOMEM;
 
   // First-owner filter (default): each pair is emitted only by the first grid
@@ -1168,7 +1178,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
       scan_exclusive_u64(tests_c, tests_c, ncells_h, scan64 + s64, scan64, stream);
       launch_unit_fill(cstart, cend, units, ncells_h, ctx->cell_unit_tiles, skeys,
                        seg_bits > 0 ? idx_bits + P.layout.cell_bits : 64, sa, segs_d, udesc,
-                       stream);
+                       uwork, stream);
       kend(RTG_K_CELLS, 24.0 * (double)ncells_h);
       Gather g2;
       g2.add(scan64 + s64, 8);
@@ -1188,7 +1198,20 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     pa.ssig = first_owner ? ssig : nullptr;
     pa.N = NB;
     pa.direct = ctx->gather_direct ? 1 : 0;
-    pa.max_blocks = ctx->pair_blocks;
+    // about 90k pair tests per wave: enough work to hide a wave's start, and
+    // waves small enough that the last ones do not run alone for long
+    pa.max_blocks = ctx->pair_blocks
+                        ? ctx->pair_blocks
+                        : (uint32_t)std::min<uint64_t>(
+                              kMaxPairBlocks,
+                              std::max<uint64_t>(2048, tests_total / (90000ull * kWaves) + 1));
+    if (balanced) {
+      // each wave takes a contiguous run of units with an equal share of the
+      // tile pairs, so that no wave (and no block) runs far longer than the rest
+      scan_exclusive_u64(uwork, uwork, units_total, uscan + su, uscan, stream);
+      launch_wave_ranges(uwork, units_total, uscan + su, pair_waves(pa), wfirst, stream);
+      pa.wave_first = wfirst;
+    }
     pa.sigp = first_owner ? sig : nullptr;
     pa.skeys = skeys;
     pa.sidx = sidx;

@@ -177,9 +177,11 @@ struct UnitDesc {
 };
 // desc[unit_off[c] + q] for the units q of cell c; a cell's segment is
 // sa + (its key >> seg_shift) (sa when seg_shift >= 64).
+// work (optional) receives each unit's tile pairs.
 void launch_unit_fill(const uint32_t* start, const uint32_t* end, const uint32_t* unit_off,
                       uint32_t ncells, uint32_t cell_unit_tiles, const uint64_t* skeys,
-                      int seg_shift, int sa, const SegDesc* segs, UnitDesc* desc, hipStream_t s);
+                      int seg_shift, int sa, const SegDesc* segs, UnitDesc* desc, uint64_t* work,
+                      hipStream_t s);
 
 // --- cell pairs -----------------------------------------------------------
 // Neighbourhood signatures for the first-owner rule, which keeps a pair
@@ -221,7 +223,17 @@ struct PairsArgs {
   uint32_t nseg;           // output segments (0 or 1: one)
   int gram;                // 1: matrix-core screen (d <= 16), 0: vector screen
   uint32_t max_blocks;     // grid size cap (0: default)
+  // [pair_waves + 1]: wave w takes units [wave_first[w], wave_first[w + 1])
+  // (launch_wave_ranges); null: every pair_waves-th unit from its own index
+  const uint32_t* wave_first;
 };
+// Waves of the pair kernels' grid for these arguments.
+uint32_t pair_waves(const PairsArgs& a);
+// first[0..nwaves] from the exclusive prefix work_off of the units' tile
+// pairs (total their sum, on the device): contiguous runs of units with
+// about equal work.
+void launch_wave_ranges(const uint64_t* work_off, uint32_t nunits, const uint64_t* total,
+                        uint32_t nwaves, uint32_t* first, hipStream_t s);
 // --- MR-metric filter -----------------------------------------------------
 // Under the MR-metric (the sum of the robots' Euclidean displacements, each
 // robot a block of sub consecutive axes) the pair kernels run the Euclidean

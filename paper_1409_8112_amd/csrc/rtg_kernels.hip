@@ -888,9 +888,9 @@ struct UnitView {
   bool ok;
 };
 
-__device__ __forceinline__ UnitView unit_view(const PairsArgs& P, uint32_t u) {
+__device__ __forceinline__ UnitView unit_view(const PairsArgs& P, uint32_t u, uint32_t u_end) {
   UnitView v;
-  v.ok = u < P.total_units;
+  v.ok = u < u_end;
   if (!v.ok) {
     v.s0 = v.L = v.ta_begin = v.ta_end = v.nt = v.inst = 0u;
     v.tcell = v.nw = 0;
@@ -1031,13 +1031,20 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs(const PairsArgs P) {
   const uint32_t nwaves = gridDim.x * kWaves;
   // The wave's units form one stream of tiles, each loaded while the tile
   // pair before it is tested.
-  uint32_t u = wave_id;
-  UnitView V = unit_view(P, u);
+  // The wave's units: a contiguous run holding about an equal share of the
+  // tile pairs (wave_first), else every nwaves-th unit.
+  uint32_t u = wave_id, u_end = P.total_units, step = nwaves;
+  if (P.wave_first) {
+    u = uniform(P.wave_first[wave_id]);
+    u_end = uniform(P.wave_first[wave_id + 1]);
+    step = 1;
+  }
+  UnitView V = unit_view(P, u, u_end);
   TileRegs<D> cur, nxt;
   if (V.ok)
     load_tile<D>(P, V.s0 + V.ta_begin * kPairTile, tile_len(V, V.ta_begin), V.nw, lane, cur);
   while (V.ok) {
-    const UnitView Vn = unit_view(P, u + nwaves);
+    const UnitView Vn = unit_view(P, u + step, u_end);
     const PairTest T = P.tests[V.inst];
     for (uint32_t ta = V.ta_begin; ta < V.ta_end; ++ta) {
       const uint32_t nA = tile_len(V, ta);
@@ -1133,7 +1140,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs(const PairsArgs P) {
       cur = nxt;
       }
     }
-    u += nwaves;
+    u += step;
     V = Vn;
   }
   flush_out(P, O, lane);
@@ -1232,13 +1239,20 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs_gram(
   const uint32_t nwaves = gridDim.x * kWaves;
   // The wave's units form one stream of tiles, each loaded while the tile
   // pair before it is tested.
-  uint32_t u = wave_id;
-  UnitView V = unit_view(P, u);
+  // The wave's units: a contiguous run holding about an equal share of the
+  // tile pairs (wave_first), else every nwaves-th unit.
+  uint32_t u = wave_id, u_end = P.total_units, step = nwaves;
+  if (P.wave_first) {
+    u = uniform(P.wave_first[wave_id]);
+    u_end = uniform(P.wave_first[wave_id + 1]);
+    step = 1;
+  }
+  UnitView V = unit_view(P, u, u_end);
   TileRegs<D> cur, nxt;
   if (V.ok)
     load_tile<D>(P, V.s0 + V.ta_begin * kPairTile, tile_len(V, V.ta_begin), V.nw, lane, cur);
   while (V.ok) {
-    const UnitView Vn = unit_view(P, u + nwaves);
+    const UnitView Vn = unit_view(P, u + step, u_end);
     const PairTest T = P.tests[V.inst];
     const float r2f = (float)T.r2;
     // origin: the first point of the unit's first tile (lane 0; wave-uniform)
@@ -1436,7 +1450,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs_gram(
       cur = nxt;
     }
     }
-    u += nwaves;
+    u += step;
     V = Vn;
   }
   flush_out(P, O, lane);
@@ -1736,7 +1750,8 @@ __global__ void k_unit_fill(const uint32_t* __restrict__ start, const uint32_t* 
                             const uint32_t* __restrict__ unit_off, uint32_t ncells,
                             uint32_t cell_unit_tiles, const uint64_t* __restrict__ skeys,
                             int seg_shift, int sa,
-                            const SegDesc* __restrict__ segs, UnitDesc* __restrict__ desc) {
+                            const SegDesc* __restrict__ segs, UnitDesc* __restrict__ desc,
+                            uint64_t* __restrict__ work) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncells) return;
   const uint32_t s0 = start[c], L = end[c] - s0;
@@ -1753,13 +1768,35 @@ __global__ void k_unit_fill(const uint32_t* __restrict__ start, const uint32_t* 
     D.ta_begin = 0;
     D.ta_end = nt;
     desc[o] = D;
+    if (work) work[o] = (uint64_t)nt * (nt + 1) / 2;  // tile pairs of the unit
   } else {
     for (uint32_t q = 0; q < nt; ++q) {
       D.ta_begin = q;
       D.ta_end = q + 1;
       desc[o + q] = D;
+      if (work) work[o + q] = nt - q;
     }
   }
+}
+
+// first[w] = the first unit whose exclusive prefix of tile pairs reaches
+// w total / nwaves, for w <= nwaves: wave w takes units [first[w],
+// first[w + 1]), a contiguous run with about an equal share of the work.
+__global__ void k_wave_ranges(const uint64_t* __restrict__ work_off, uint32_t nunits,
+                              const uint64_t* __restrict__ total, uint32_t nwaves,
+                              uint32_t* __restrict__ first) {
+  const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w > nwaves) return;
+  // w total / nwaves without overflow: total < 2^56 (units x tile pairs)
+  const uint64_t T = *total;
+  const uint64_t target = (T / nwaves) * w + (T % nwaves) * w / nwaves;
+  uint32_t lo = 0, hi = nunits;  // first index with work_off >= target
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (work_off[mid] < target) lo = mid + 1;
+    else hi = mid;
+  }
+  first[w] = w == nwaves ? nunits : lo;
 }
 
 // spts[l][p] and ssig[w][p] for the positions p of every unit (one wave per
@@ -2453,10 +2490,25 @@ void launch_cell_work(const uint32_t* start, const uint32_t* end, uint32_t ncell
 
 void launch_unit_fill(const uint32_t* start, const uint32_t* end, const uint32_t* unit_off,
                       uint32_t ncells, uint32_t cell_unit_tiles, const uint64_t* skeys,
-                      int seg_shift, int sa, const SegDesc* segs, UnitDesc* desc, hipStream_t s) {
+                      int seg_shift, int sa, const SegDesc* segs, UnitDesc* desc, uint64_t* work,
+                      hipStream_t s) {
   if (!ncells) return;
   hipLaunchKernelGGL(k_unit_fill, dim3(grid_for(ncells)), dim3(kBlock), 0, s, start, end, unit_off,
-                     ncells, cell_unit_tiles, skeys, seg_shift, sa, segs, desc);
+                     ncells, cell_unit_tiles, skeys, seg_shift, sa, segs, desc, work);
+}
+
+uint32_t pair_waves(const PairsArgs& a) {
+  uint64_t blocks = ((uint64_t)a.total_units + kWaves - 1) / kWaves;
+  const uint64_t max_blocks = a.max_blocks ? a.max_blocks : 256ull * 8ull;
+  if (blocks > max_blocks) blocks = max_blocks;
+  if (blocks < 1) blocks = 1;
+  return (uint32_t)blocks * kWaves;
+}
+
+void launch_wave_ranges(const uint64_t* work_off, uint32_t nunits, const uint64_t* total,
+                        uint32_t nwaves, uint32_t* first, hipStream_t s) {
+  hipLaunchKernelGGL(k_wave_ranges, dim3(grid_for((size_t)nwaves + 1)), dim3(kBlock), 0, s,
+                     work_off, nunits, total, nwaves, first);
 }
 
 void launch_gather_units(const PairsArgs& a, const uint64_t* sig, float* spts, uint64_t* ssig,
@@ -2561,11 +2613,8 @@ void launch_query_pairs(const QueryArgs& a, hipStream_t s) {
 
 template <int D>
 static void pairs_dispatch(const PairsArgs& a, hipStream_t s) {
-  uint64_t blocks = ((uint64_t)a.total_units + kWaves - 1) / kWaves;
-  // 256 CUs, several resident blocks each
-  const uint64_t max_blocks = a.max_blocks ? a.max_blocks : 256ull * 8ull;
-  if (blocks > max_blocks) blocks = max_blocks;
-  if (blocks < 1) blocks = 1;
+  // 256 CUs, several resident blocks each (the grid wave_first was made for)
+  const uint64_t blocks = pair_waves(a) / kWaves;
   if constexpr (D <= 16) {
     if (a.gram && a.d == D) {
       hipLaunchKernelGGL((k_cell_pairs_gram<D>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);

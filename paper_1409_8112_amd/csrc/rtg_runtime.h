@@ -57,6 +57,8 @@ int min_field_bits(double alpha);
 int validate_query(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha);
 // Flags that shape a pass's output (instances batched together share them).
 constexpr uint32_t kListFlags = RTG_UPPER_ONLY | RTG_DEDUP_SORT | RTG_DEDUP_BITMAP;
+// Largest default grid of the pair kernels.
+constexpr uint32_t kMaxPairBlocks = 8192;
 // Output segments of the pair kernels (each with its own counter).
 constexpr uint32_t kCandSegments = 32;
 // The pass counters: [0] unused, [1] FP64 re-tests, [2] filter count,
@@ -192,6 +194,7 @@ struct Ctx {
   bool gather_direct = true;  // pair kernels read rows by point index
   uint32_t cell_unit_tiles = 1;  // cells of at most this many tiles: one work unit
   uint32_t pair_blocks = 0;      // pair-kernel grid cap (0: default)
+  bool balanced_units = true;    // pair-kernel waves take equal shares of the tile pairs
   Lane main;          // the caller's stream: blocking calls
   rtg_stats stats{};  // of the last blocking call
   std::mutex mu;      // one blocking call at a time
