@@ -344,6 +344,8 @@ Ctx::Ctx(int dev) : device(dev) {
   // RTG_BUCKET_CAP lowers the entries a neighbour-list bucket may hold in
   // LDS (tests use it to send buckets down the global-sort fallback).
   const char* bc = std::getenv("RTG_BUCKET_CAP");
+  if (const char* e = std::getenv("RTG_BUCKET_BLOCKS"))
+    bucket_blocks = (uint32_t)std::max(1, std::min(4096, std::atoi(e)));
   if (const char* e = std::getenv("RTG_UNITS"))
     balanced_units = std::strcmp(e, "roundrobin") != 0;
   bucket_cap = kBucketMaxEntries;
@@ -710,7 +712,8 @@ int csr_by_buckets(Lane& c, Scratch& S, const uint64_t* pairs, size_t count, int
          per_row * (double)(1u << (rb + 1)) <= 8192.0)
     ++rb;
   const uint32_t nbuckets = (uint32_t)((n + ((int64_t)1 << rb) - 1) >> rb);
-  const uint32_t nblocks = (uint32_t)std::min<size_t>(256, (count + 4095) / 4096);
+  const uint32_t nblocks =
+      (uint32_t)std::min<size_t>(c.ctx->bucket_blocks, (count + 4095) / 4096);
   const uint32_t chunk = (uint32_t)((count + nblocks - 1) / nblocks);
   const size_t np = (size_t)nbuckets * nblocks;
   uint32_t* part = S.get<uint32_t>(np + 1);

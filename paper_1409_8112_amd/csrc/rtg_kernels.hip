@@ -1008,6 +1008,22 @@ __device__ __forceinline__ uint64_t pack_pair(uint64_t x, uint64_t y, int pair_b
   return (min(x, y) << pair_bits) | max(x, y);
 }
 
+// Appends pair (when keep) to the wave's staging buffer: one slot per
+// keeping lane, in lane order, flushing first if they would not fit.
+__device__ __forceinline__ void append_pair(const PairsArgs& P, OutStage& O, uint32_t lane,
+                                            bool keep, uint64_t pair) {
+  const uint64_t kb = ballot(keep);
+  const uint32_t nk = (uint32_t)__popcll(kb);
+  if (!nk) return;
+  if (O.n + nk > (uint32_t)kOutBuf) flush_out(P, O, lane);
+  if (keep) O.buf[O.n + rank_below(kb)] = pair;
+  O.n += nk;
+}
+
+// Accepted pairs of a tile pair listed for the first-owner check, at most
+// this many per wave (more: each lane checks its own, one by one).
+constexpr uint32_t kPend = 256;
+
 // --- vector screen --------------------------------------------------------
 // Lane l holds point a_l of tile a in registers and tests it against every
 // point b_j of tile b, read from LDS by broadcast: FP32 squared differences
@@ -1224,6 +1240,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs_gram(
   __shared__ uint32_t sAi[kWaves][kPairTile];
   __shared__ uint32_t sBi[kWaves][kPairTile];
   __shared__ uint64_t sOut[kWaves][kOutBuf];
+  __shared__ uint16_t sPend[kWaves][kPend];  // accepted (row << 6 | col) codes
 
   const uint32_t lane = lane_id();
   const uint32_t l32 = lane & 31u, h = lane >> 5;
@@ -1421,32 +1438,72 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs_gram(
       }
 
       // First owner: drop a pair that an earlier grid put in one cell.  The
-      // B rows are in registers by now: their space takes the B words.
-      if (V.nw && ballot(acc != 0ull)) {
+      // B rows are in registers by now: their space takes the B words.  The
+      // accepted pairs are listed in LDS and checked one per lane, so that
+      // the check takes ceil(count / 64) rounds rather than the most any
+      // one lane holds.
+      const uint32_t cnt = (uint32_t)__popcll(acc);
+      const uint32_t incl = wave_inclusive_scan(cnt);
+      const uint32_t total = lane_value(incl, 63);
+      if (V.nw && total) {
         wave_lds_sync();
 #pragma unroll
         for (int q = 0; q < kSigWords; ++q) sBw[q][lane] = bsw[q];
-        wave_lds_sync();
-        uint64_t m = acc;
-        while (m) {
-          const int b = __builtin_ctzll(m);
-          m &= m - 1;
-          const uint32_t row = gram_row(b, lane), col = gram_col(b, lane);
-          uint64_t aq[kSigWords], bq[kSigWords];
-#pragma unroll
-          for (int q = 0; q < kSigWords; ++q) {
-            aq[q] = sAw[q][row];
-            bq[q] = sBw[q][col];
+        if (total <= kPend) {
+          uint32_t pos = incl - cnt;
+          uint64_t m = acc;
+          while (m) {
+            const int b = __builtin_ctzll(m);
+            m &= m - 1;
+            sPend[w][pos++] = (uint16_t)((gram_row(b, lane) << 6) | gram_col(b, lane));
           }
-          if (shared_earlier_cell(aq, bq, V.tcell, pa0 + row, sAi[w][row], pb0 + col,
-                                  sBi[w][col], P))
-            acc &= ~(1ull << b);
+          wave_lds_sync();
+          for (uint32_t e0 = 0; e0 < total; e0 += 64) {
+            const uint32_t e = e0 + lane;
+            bool keep = e < total;
+            uint64_t pair = 0;
+            if (keep) {
+              const uint32_t code = sPend[w][e];
+              const uint32_t row = code >> 6, col = code & 63u;
+              uint64_t aq[kSigWords], bq[kSigWords];
+#pragma unroll
+              for (int q = 0; q < kSigWords; ++q) {
+                aq[q] = sAw[q][row];
+                bq[q] = sBw[q][col];
+              }
+              keep = !shared_earlier_cell(aq, bq, V.tcell, pa0 + row, sAi[w][row], pb0 + col,
+                                          sBi[w][col], P);
+              pair = pack_pair(sAi[w][row], sBi[w][col], T.pair_bits);
+            }
+            append_pair(P, O, lane, keep, pair);
+          }
+          wave_lds_sync();  // sPend is rewritten by the next tile pair
+        } else {
+          wave_lds_sync();
+          uint64_t m = acc;
+          while (m) {
+            const int b = __builtin_ctzll(m);
+            m &= m - 1;
+            const uint32_t row = gram_row(b, lane), col = gram_col(b, lane);
+            uint64_t aq[kSigWords], bq[kSigWords];
+#pragma unroll
+            for (int q = 0; q < kSigWords; ++q) {
+              aq[q] = sAw[q][row];
+              bq[q] = sBw[q][col];
+            }
+            if (shared_earlier_cell(aq, bq, V.tcell, pa0 + row, sAi[w][row], pb0 + col,
+                                    sBi[w][col], P))
+              acc &= ~(1ull << b);
+          }
+          emit_pairs(P, O, lane, acc, [&](int b) {
+            return pack_pair(sAi[w][gram_row(b, lane)], sBi[w][gram_col(b, lane)], T.pair_bits);
+          });
         }
+      } else if (total) {
+        emit_pairs(P, O, lane, acc, [&](int b) {
+          return pack_pair(sAi[w][gram_row(b, lane)], sBi[w][gram_col(b, lane)], T.pair_bits);
+        });
       }
-
-      emit_pairs(P, O, lane, acc, [&](int b) {
-        return pack_pair(sAi[w][gram_row(b, lane)], sBi[w][gram_col(b, lane)], T.pair_bits);
-      });
       cur = nxt;
     }
     }

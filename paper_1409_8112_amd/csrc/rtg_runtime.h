@@ -195,6 +195,9 @@ struct Ctx {
   uint32_t cell_unit_tiles = 1;  // cells of at most this many tiles: one work unit
   uint32_t pair_blocks = 0;      // pair-kernel grid cap (0: default)
   bool balanced_units = true;    // pair-kernel waves take equal shares of the tile pairs
+  // partition blocks of the neighbour-list build (each writes its own run of
+  // every bucket; more blocks keep more waves waiting on LDS atomics at once)
+  uint32_t bucket_blocks = 256;
   Lane main;          // the caller's stream: blocking calls
   rtg_stats stats{};  // of the last blocking call
   std::mutex mu;      // one blocking call at a time

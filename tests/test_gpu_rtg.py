@@ -344,6 +344,38 @@ def test_dense_rows_contiguous_in_index_order(ctx):
         other.close()
 
 
+@pytest.mark.parametrize("env", [{"RTG_UNITS": "roundrobin"}, {"RTG_PAIR_BLOCKS": "7"},
+                                 {"RTG_PAIR_BLOCKS": "60000"},
+                                 {"RTG_PAIR_BLOCKS": "3", "RTG_PAIRS": "vector"}])
+def test_wave_work_assignment(env):
+    """Pair-kernel waves dealt units round-robin, a tiny grid (long runs of
+    units per wave) and a grid far larger than the work (many empty runs):
+    the same lists as the oracle."""
+    from paper_1409_8112_amd import rtg
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        other = rtg.Context(0, arena_bytes=4 << 30)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
+    try:
+        cases = [(workloads.uniform_points(3000, 6, seed=41), 6, 0.3),
+                 (workloads.clustered_points(5000, 3, seed=42), 3, 0.05),
+                 (workloads.uniform_points(700, 2, seed=43), 2, 0.08)]
+        for p, d, r in cases:
+            print(f"work assignment {env}: n={len(p)} d={d}", flush=True)
+            res = other.all_pairs(_dev(p), r, 5, 2.0, 3)
+            rp, col = res.to_numpy()
+            res.release()
+            _assert_same(rp, col, oracle.rtg(p, r, 5, 2.0, 3))
+    finally:
+        other.close()
+
+
 def test_release_and_determinism(ctx):
     from paper_1409_8112_amd import rtg
     p = workloads.uniform_points(20000, 4, seed=2)
