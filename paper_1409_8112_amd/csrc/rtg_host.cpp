@@ -1244,8 +1244,12 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     // copy puts them after the earlier passes' pairs in cand.
     const uint32_t nseg = kCandSegments;
     unsigned long long* segcnt = counters + 4;
-    const uint64_t guess =
-        std::min<uint64_t>(tests_total, std::max<uint64_t>(1u << 20, tests_total / 16));
+    // The guess: a sixteenth of the tests, but at most 16 pairs per (point,
+    // grid) key -- where few tested pairs lie within r (high d, wide cells)
+    // the tests overstate the pairs a thousandfold.
+    const uint64_t guess = std::min<uint64_t>(
+        tests_total,
+        std::max<uint64_t>(1u << 20, std::min<uint64_t>(tests_total / 16, 16ull * N)));
     uint64_t seg_cap = guess / nseg + guess / (4 * nseg) + 1024;
     for (int attempt = 0; attempt < 2; ++attempt) {
       uint64_t* sbuf = S.get<uint64_t>((size_t)nseg * seg_cap);
