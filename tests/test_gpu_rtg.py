@@ -376,6 +376,29 @@ def test_wave_work_assignment(env):
         other.close()
 
 
+def test_sparse_acceptance_fits_a_small_budget():
+    """At d = 12 with cells as wide as the cube, about 1e10 pairs are tested
+    for about 1e7 within r: the room first taken for the pairs must follow
+    the points, not the tests, or a 4 GB context cannot run it."""
+    from paper_1409_8112_amd import rtg
+    c = rtg.Context(0, arena_bytes=4 << 30)
+    try:
+        n, r = 1_000_000, 0.45
+        p = workloads.uniform_points(n, 12, seed=12)
+        print("sparse acceptance: n=1e6 d=12", flush=True)
+        res = c.all_pairs(_dev(p), r, 8, 2.0, 4)
+        st = c.stats()
+        rp, col = res.to_numpy()
+        res.release()
+        assert st["tests"] > 1000 * st["unique_pairs"] > 0
+        R, u = oracle.make_transforms(4, 8, 12)
+        rows = np.random.default_rng(5).choice(n, size=24, replace=False)
+        for s_i, row in zip(range(len(rows)), oracle.rtg_rows(p, r, 2.0, R, u, rows)):
+            assert np.array_equal(col[rp[rows[s_i]]:rp[rows[s_i] + 1]], row)
+    finally:
+        c.close()
+
+
 def test_release_and_determinism(ctx):
     from paper_1409_8112_amd import rtg
     p = workloads.uniform_points(20000, 4, seed=2)
