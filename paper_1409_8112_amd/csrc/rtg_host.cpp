@@ -651,6 +651,25 @@ class Uploads {
   size_t total_ = 0;
 };
 
+// The tile table of a segmented key sort: segment q holds keys
+// [off[q], off[q] + len[q]); tiles stay inside segments and the histogram
+// table runs segment by segment (see rtgk::SortTile).
+std::vector<SortTile> segment_tiles(const std::vector<uint64_t>& off,
+                                    const std::vector<uint64_t>& len) {
+  std::vector<SortTile> tab;
+  uint64_t slot = 0;
+  for (size_t q = 0; q < off.size(); ++q) {
+    const uint32_t nts = (uint32_t)((len[q] + kTile - 1) / kTile);
+    for (uint32_t t = 0; t < nts; ++t) {
+      const uint64_t st0 = (uint64_t)t * kTile;
+      tab.push_back(SortTile{off[q] + st0, (uint32_t)std::min<uint64_t>(kTile, len[q] - st0),
+                             (uint32_t)(slot + t), nts, 0u});
+    }
+    slot += (uint64_t)256 * nts;
+  }
+  return tab;
+}
+
 // Frees every arena block taken through it when it goes out of scope.
 // Blocks are returned only after the lane's stream has drained, so that
 // another lane cannot reuse memory a kernel of this one still touches.
@@ -1007,7 +1026,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     if (rc) return rc;
   }
   st.key_bits = std::max(st.key_bits, P.key_bits);
-  st.key_passes = std::max(st.key_passes, (P.key_bits + kRadixBits - 1) / kRadixBits);
+
   st.pair_bits = 2 * pair_bits;
   st.transforms_per_sort = P.tb;
 
@@ -1049,7 +1068,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   uint32_t* vals = idx_bits ? nullptr : S.get<uint32_t>(NB);
   uint32_t* vals_alt = idx_bits ? nullptr : S.get<uint32_t>(NB);
   const size_t ntiles = (NB + kTile - 1) / kTile;
-  void* sort_scr = S.get<char>(radix_scratch_bytes(NB, 0, P.key_bits));
+  void* sort_scr = S.get<char>(radix_scratch_bytes(NB, 0, P.key_bits, (size_t)S_total));
   uint32_t* run_scr = S.get<uint32_t>(2 * ntiles + 8 + scan_scratch_elems(ntiles));
   const size_t max_cells = NB / 2 + 1;
   const size_t max_units = max_cells + NB / kPairTile + 1;
@@ -1142,9 +1161,32 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     kend(RTG_K_KEYS, 4.0 * (double)pass_pts * d + (idx_bits ? 8.0 : 12.0) * (double)N +
                          (sig ? 16.0 * (double)pass_pts * sig_W : 0.0));
     mark(2);
-    const int where = radix_sort(keys, vals, keys_alt, vals_alt, N, idx_bits, idx_bits + key_bits,
-                                 sort_scr, err, stream, &tm, RTG_K_KEY_HIST, RTG_K_KEY_SCATTER,
-                                 ctx->sort_algo);
+    // Several segments in the pass: sort within segments (tiles that stay
+    // inside one segment), so only the cell bits take passes; the segment
+    // bits above them are already in order.
+    const bool segmented = seg_bits > 0 && ctx->sort_algo == kSortReduceScan;
+    uint32_t ntab = 0;
+    SortTile* tab_d = nullptr;
+    if (segmented) {
+      std::vector<uint64_t> soff, slen;
+      for (int32_t sg = sa; sg < sb; ++sg) {
+        soff.push_back((uint64_t)segs[sg].key_off);
+        slen.push_back((uint64_t)jobs[segs[sg].inst]->n);
+      }
+      const std::vector<SortTile> tab = segment_tiles(soff, slen);
+      ntab = (uint32_t)tab.size();
+      Uploads Ut(*this);
+      const size_t o_tab = Ut.add(tab.data(), sizeof(SortTile) * tab.size());
+      char* tab_mem = S.get<char>(Ut.total());
+      if (!tab_mem) return RTG_ENOMEM;
+      tab_d = reinterpret_cast<SortTile*>(tab_mem + o_tab);
+      if ((rc = Ut.send(tab_mem))) return rc;
+    }
+    const int sort_end = idx_bits + (segmented ? P.layout.cell_bits : key_bits);
+    const int where = radix_sort(keys, vals, keys_alt, vals_alt, N, idx_bits, sort_end, sort_scr,
+                                 err, stream, &tm, RTG_K_KEY_HIST, RTG_K_KEY_SCATTER,
+                                 ctx->sort_algo, tab_d, ntab);
+    st.key_passes = std::max(st.key_passes, (sort_end - idx_bits + kRadixBits - 1) / kRadixBits);
     const uint64_t* skeys = where ? keys_alt : keys;
     const uint32_t* sidx = idx_bits ? nullptr : (where ? vals_alt : vals);
     mark(3);
@@ -1849,13 +1891,33 @@ int Lane::build_index(const float* points, int64_t n, int32_t d, double r, int32
     uint64_t* keys_alt = static_cast<uint64_t*>(own(sizeof(uint64_t) * N));
     uint32_t* vals = idx_bits ? nullptr : static_cast<uint32_t*>(own(sizeof(uint32_t) * N));
     uint32_t* vals_alt = idx_bits ? nullptr : static_cast<uint32_t*>(own(sizeof(uint32_t) * N));
-    void* scr = S.get<char>(radix_scratch_bytes(N, 0, key_bits));
+    void* scr = S.get<char>(radix_scratch_bytes(N, 0, key_bits, (size_t)(sb - sa)));
     if (!keys || !keys_alt || (!idx_bits && (!vals || !vals_alt)) || !scr) return RTG_ENOMEM;
     KeysArgs ka{inst_d, 1, nblk, d, n, soa, sa, sb, segs_d, I.R, I.u, I.klo, I.layout,
                 keys, vals, err, I.sig, I.sig_W, I.sig_b, I.sig_gpw, idx_bits};
     launch_keys(ka, stream);
-    const int where = radix_sort(keys, vals, keys_alt, vals_alt, N, idx_bits, idx_bits + key_bits,
-                                 scr, err, stream, nullptr, 0, 0, ctx->sort_algo);
+    // several grids in the sort: within grids, on the cell bits only
+    const bool segmented = seg_bits > 0 && ctx->sort_algo == kSortReduceScan;
+    SortTile* tab_d = nullptr;
+    uint32_t ntab = 0;
+    if (segmented) {
+      std::vector<uint64_t> soff, slen;
+      for (int32_t t = sa; t < sb; ++t) {
+        soff.push_back((uint64_t)(t - sa) * (uint64_t)n);
+        slen.push_back((uint64_t)n);
+      }
+      const std::vector<SortTile> tab = segment_tiles(soff, slen);
+      ntab = (uint32_t)tab.size();
+      Uploads Ut(*this);
+      const size_t o_tab = Ut.add(tab.data(), sizeof(SortTile) * tab.size());
+      char* tab_mem = S.get<char>(Ut.total());
+      if (!tab_mem) return RTG_ENOMEM;
+      tab_d = reinterpret_cast<SortTile*>(tab_mem + o_tab);
+      if ((rc = Ut.send(tab_mem))) return rc;
+    }
+    const int sort_end = idx_bits + (segmented ? I.P.layout.cell_bits : key_bits);
+    const int where = radix_sort(keys, vals, keys_alt, vals_alt, N, idx_bits, sort_end, scr, err,
+                                 stream, nullptr, 0, 0, ctx->sort_algo, tab_d, ntab);
     uint64_t* sorted = where ? keys_alt : keys;
     uint32_t* sorted_idx = idx_bits ? nullptr : (where ? vals_alt : vals);
     if ((rc = sync())) return rc;  // the other buffers go back below

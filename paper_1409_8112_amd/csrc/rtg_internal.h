@@ -141,12 +141,28 @@ void scan_exclusive_u64(const uint64_t* in, uint64_t* out, size_t count, uint64_
 // algorithm).  *err |= 2 if a look-back wait gave up (the output is then
 // wrong but every write stays in bounds).  timer (optional) sees the
 // histogram launches as kid_hist and each digit pass as kid_scatter.
+//
+// Segmented sorts (reduce-then-scan only): with a tile table, each tile
+// covers keys [start, start + len) of one segment (len <= kTile) and its
+// digit counts go to slot + digit * stride of a histogram table laid out
+// segment by segment, digit by digit, tile by tile; the scan of that table
+// then keeps every key inside its segment, so bits above end_bit (the
+// segment id) need no pass.  ntiles_table tiles; the scratch needs
+// radix_scratch_bytes(count, ..., ntiles_table - tiles_for(count)).
 enum { kSortOnesweep = 0, kSortReduceScan = 1 };
-size_t radix_scratch_bytes(size_t count, int begin_bit, int end_bit);
+struct SortTile {
+  uint64_t start;
+  uint32_t len;
+  uint32_t slot;    // histogram index of digit 0
+  uint32_t stride;  // distance between digits (the segment's tiles)
+  uint32_t pad;
+};
+size_t radix_scratch_bytes(size_t count, int begin_bit, int end_bit, size_t extra_tiles = 0);
 int radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
                size_t count, int begin_bit, int end_bit, void* scratch, uint32_t* err,
                hipStream_t s, const LaunchTimer* timer = nullptr, int kid_hist = 0,
-               int kid_scatter = 0, int algo = kSortOnesweep);
+               int kid_scatter = 0, int algo = kSortOnesweep, const SortTile* tiles = nullptr,
+               uint32_t ntiles_table = 0);
 
 // --- cells ----------------------------------------------------------------
 // Runs of equal keys >> shift with length >= 2 in a sorted key array: per

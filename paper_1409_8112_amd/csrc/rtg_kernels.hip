@@ -406,8 +406,8 @@ struct TileLds {
 // the call wcnt[w][dg] holds wave w's count of digit dg.
 template <bool HAS_VAL>
 __device__ __forceinline__ void tile_rank(TileLds<HAS_VAL>& S, const uint64_t* __restrict__ kin,
-                                          const uint32_t* __restrict__ vin, size_t count,
-                                          size_t tile, int shift, int nbits, uint64_t* k_,
+                                          const uint32_t* __restrict__ vin, size_t tile_base,
+                                          size_t tile_end, int shift, int nbits, uint64_t* k_,
                                           uint32_t* v_, uint32_t* r_) {
   const uint32_t lane = lane_id();
   const int w = threadIdx.x >> 6;
@@ -415,12 +415,12 @@ __device__ __forceinline__ void tile_rank(TileLds<HAS_VAL>& S, const uint64_t* _
 #pragma unroll
   for (int q = 0; q < kWaves; ++q) S.wcnt[q][threadIdx.x] = 0u;
   __syncthreads();
-  const size_t wave_base = tile * kTile + (size_t)w * (kTile / kWaves);
+  const size_t wave_base = tile_base + (size_t)w * (kTile / kWaves);
   const uint64_t lt = (1ull << lane) - 1ull;
 #pragma unroll
   for (int q = 0; q < kKeysPerThread; ++q) {
     const size_t e = wave_base + (size_t)q * 64 + lane;
-    const bool valid = e < count;
+    const bool valid = e < tile_end;
     const uint64_t key = valid ? kin[e] : ~0ull;
     k_[q] = key;
     if (HAS_VAL) v_[q] = valid ? vin[e] : 0u;
@@ -469,17 +469,17 @@ __device__ __forceinline__ uint32_t tile_layout(TileLds<HAS_VAL>& S) {
 template <bool HAS_VAL>
 __device__ __forceinline__ void tile_scatter(TileLds<HAS_VAL>& S, uint64_t* __restrict__ kout,
                                              uint32_t* __restrict__ vout, size_t count,
-                                             size_t tile, int shift, int nbits, const uint64_t* k_,
-                                             const uint32_t* v_, const uint32_t* r_) {
+                                             size_t tile_base, size_t tile_end, int shift,
+                                             int nbits, const uint64_t* k_, const uint32_t* v_,
+                                             const uint32_t* r_) {
   const uint32_t lane = lane_id();
   const int w = threadIdx.x >> 6;
   const uint32_t mask = (1u << nbits) - 1u;
-  const size_t tile_base = tile * kTile;
   const size_t wave_base = tile_base + (size_t)w * (kTile / kWaves);
 #pragma unroll
   for (int q = 0; q < kKeysPerThread; ++q) {
     const size_t e = wave_base + (size_t)q * 64 + lane;
-    if (e < count) {
+    if (e < tile_end) {
       const uint32_t dg = (uint32_t)(k_[q] >> shift) & mask;
       const uint32_t pos = S.wcnt[w][dg] + r_[q];
       S.key[pos] = k_[q];
@@ -487,7 +487,7 @@ __device__ __forceinline__ void tile_scatter(TileLds<HAS_VAL>& S, uint64_t* __re
     }
   }
   __syncthreads();
-  const size_t rem = count - tile_base;
+  const size_t rem = tile_end - tile_base;
   const uint32_t tile_count = rem < (size_t)kTile ? (uint32_t)rem : (uint32_t)kTile;
 #pragma unroll 4
   for (int q = 0; q < kKeysPerThread; ++q) {
@@ -506,38 +506,67 @@ __device__ __forceinline__ void tile_scatter(TileLds<HAS_VAL>& S, uint64_t* __re
 
 // --- reduce-then-scan ---------------------------------------------------------
 
+// Tile b of a sort: its keys [start, start + len) and the place of its
+// digit counts in the histogram table, slot + digit * stride.  Without a
+// table, tile b is keys [b kTile, ...) with slot b and stride ntiles; with
+// one, tiles stay inside segments and the table is segment-major, so its
+// exclusive scan orders by segment, then digit, then tile.
+struct TileSpan {
+  size_t start, end;
+  size_t slot, stride;
+};
+__device__ __forceinline__ TileSpan tile_span(const SortTile* tiles, size_t count,
+                                              uint32_t ntiles, uint32_t b) {
+  TileSpan t;
+  if (tiles) {
+    const SortTile d = tiles[b];
+    t.start = d.start;
+    t.end = d.start + d.len;
+    t.slot = d.slot;
+    t.stride = d.stride;
+  } else {
+    t.start = (size_t)b * kTile;
+    t.end = min(count, t.start + (size_t)kTile);
+    t.slot = b;
+    t.stride = ntiles;
+  }
+  return t;
+}
+
 __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t* __restrict__ keys,
                                                        size_t count, int shift, int nbits,
                                                        uint32_t* __restrict__ tile_hist,
-                                                       uint32_t ntiles) {
+                                                       uint32_t ntiles,
+                                                       const SortTile* __restrict__ tiles) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0u;
   __syncthreads();
   const uint32_t mask = (1u << nbits) - 1u;
-  const size_t base = (size_t)blockIdx.x * kTile;
+  const TileSpan t = tile_span(tiles, count, ntiles, blockIdx.x);
 #pragma unroll 4
   for (int q = 0; q < kKeysPerThread; ++q) {
-    size_t e = base + (size_t)q * kBlock + threadIdx.x;
-    if (e < count) atomicAdd(&h[(uint32_t)(keys[e] >> shift) & mask], 1u);
+    size_t e = t.start + (size_t)q * kBlock + threadIdx.x;
+    if (e < t.end) atomicAdd(&h[(uint32_t)(keys[e] >> shift) & mask], 1u);
   }
   __syncthreads();
-  tile_hist[(size_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+  tile_hist[t.slot + (size_t)threadIdx.x * t.stride] = h[threadIdx.x];
 }
 
 template <bool HAS_VAL>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
     uint32_t* __restrict__ vout, size_t count, int shift, int nbits,
-    const uint32_t* __restrict__ tile_off, uint32_t ntiles) {
+    const uint32_t* __restrict__ tile_off, uint32_t ntiles, const SortTile* __restrict__ tiles) {
   __shared__ TileLds<HAS_VAL> S;
   uint64_t k_[kKeysPerThread];
   uint32_t v_[kKeysPerThread];
   uint32_t r_[kKeysPerThread];
-  tile_rank<HAS_VAL>(S, kin, vin, count, blockIdx.x, shift, nbits, k_, v_, r_);
+  const TileSpan t = tile_span(tiles, count, ntiles, blockIdx.x);
+  tile_rank<HAS_VAL>(S, kin, vin, t.start, t.end, shift, nbits, k_, v_, r_);
   tile_layout<HAS_VAL>(S);
-  S.goff[threadIdx.x] = tile_off[(size_t)threadIdx.x * ntiles + blockIdx.x];
+  S.goff[threadIdx.x] = tile_off[t.slot + (size_t)threadIdx.x * t.stride];
   __syncthreads();
-  tile_scatter<HAS_VAL>(S, kout, vout, count, blockIdx.x, shift, nbits, k_, v_, r_);
+  tile_scatter<HAS_VAL>(S, kout, vout, count, t.start, t.end, shift, nbits, k_, v_, r_);
 }
 
 // --- onesweep -------------------------------------------------------------------
@@ -611,7 +640,9 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(
   uint64_t k_[kKeysPerThread];
   uint32_t v_[kKeysPerThread];
   uint32_t r_[kKeysPerThread];
-  tile_rank<HAS_VAL>(S, kin, vin, count, tile, shift, nbits, k_, v_, r_);
+  const size_t tile_base = tile * kTile;
+  const size_t tile_end = min(count, tile_base + (size_t)kTile);
+  tile_rank<HAS_VAL>(S, kin, vin, tile_base, tile_end, shift, nbits, k_, v_, r_);
   const uint32_t tot = tile_layout<HAS_VAL>(S);
   const uint32_t dg = threadIdx.x;
   if (dg < (1u << nbits)) {
@@ -637,7 +668,7 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(
     S.goff[dg] = digit_off[dg] + excl;
   }
   __syncthreads();
-  tile_scatter<HAS_VAL>(S, kout, vout, count, tile, shift, nbits, k_, v_, r_);
+  tile_scatter<HAS_VAL>(S, kout, vout, count, tile_base, tile_end, shift, nbits, k_, v_, r_);
 }
 
 // ---------------------------------------------------------------------------
@@ -2436,9 +2467,9 @@ void scan_exclusive_u64(const uint64_t* in, uint64_t* out, size_t count, uint64_
   scan_rec<uint64_t>(in, out, count, total, scratch, s);
 }
 
-size_t radix_scratch_bytes(size_t count, int begin_bit, int end_bit) {
+size_t radix_scratch_bytes(size_t count, int begin_bit, int end_bit, size_t extra_tiles) {
   auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  const size_t ntiles = tiles_for(count);
+  const size_t ntiles = tiles_for(count) + extra_tiles;
   const int npass = std::max(1, (end_bit - begin_bit + kRadixBits - 1) / kRadixBits);
   const size_t nbh = (count + (size_t)kHistBlockTiles * kTile - 1) / ((size_t)kHistBlockTiles * kTile);
   const size_t onesweep = up(nbh * npass * 256 * 4) + up((size_t)npass * 256 * 8) +
@@ -2450,7 +2481,8 @@ size_t radix_scratch_bytes(size_t count, int begin_bit, int end_bit) {
 
 int radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
                size_t count, int begin_bit, int end_bit, void* scratch, uint32_t* err,
-               hipStream_t s, const LaunchTimer* timer, int kid_hist, int kid_scatter, int algo) {
+               hipStream_t s, const LaunchTimer* timer, int kid_hist, int kid_scatter, int algo,
+               const SortTile* tiles, uint32_t ntiles_table) {
   const LaunchTimer none;
   const LaunchTimer& tm = timer ? *timer : none;
   const double elem = vals ? 12.0 : 8.0;
@@ -2498,23 +2530,25 @@ int radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* val
     }
     return where;
   }
+  const unsigned nt = tiles ? ntiles_table : ntiles;
+  if (nt == 0) return 0;
   uint32_t* hist = reinterpret_cast<uint32_t*>(base);
-  uint32_t* sscr = hist + (size_t)256 * ntiles;
+  uint32_t* sscr = hist + (size_t)256 * nt;
   for (int b = begin_bit; b < end_bit; b += kRadixBits) {
     const int nbits = (end_bit - b) < kRadixBits ? (end_bit - b) : kRadixBits;
     tm.on_begin(kid_hist);
-    hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kBlock), 0, s, kin, count, b, nbits, hist,
-                       ntiles);
+    hipLaunchKernelGGL(k_radix_hist, dim3(nt), dim3(kBlock), 0, s, kin, count, b, nbits, hist, nt,
+                       tiles);
     tm.on_end(kid_hist, 8.0 * (double)count);
-    scan_rec<uint32_t>(hist, hist, (size_t)256 * ntiles, (uint32_t*)nullptr, sscr, s);
+    scan_rec<uint32_t>(hist, hist, (size_t)256 * nt, (uint32_t*)nullptr, sscr, s);
     tm.on_begin(kid_scatter);
     if (vals)
-      hipLaunchKernelGGL(k_radix_scatter<true>, dim3(ntiles), dim3(kBlock), 0, s, kin, vin, kout,
-                         vout, count, b, nbits, hist, ntiles);
+      hipLaunchKernelGGL(k_radix_scatter<true>, dim3(nt), dim3(kBlock), 0, s, kin, vin, kout,
+                         vout, count, b, nbits, hist, nt, tiles);
     else
-      hipLaunchKernelGGL(k_radix_scatter<false>, dim3(ntiles), dim3(kBlock), 0, s, kin,
+      hipLaunchKernelGGL(k_radix_scatter<false>, dim3(nt), dim3(kBlock), 0, s, kin,
                          (const uint32_t*)nullptr, kout, (uint32_t*)nullptr, count, b, nbits, hist,
-                         ntiles);
+                         nt, tiles);
     tm.on_end(kid_scatter, 2.0 * elem * (double)count);
     std::swap(kin, kout);
     std::swap(vin, vout);
