@@ -191,17 +191,31 @@ __global__ __launch_bounds__(kBlock) void k_stage(const InstDesc* __restrict__ i
 }
 
 // One block per instance: bbox[q][2j] = min over its blocks, [2j+1] = max.
+// bbox of every instance to the identities of min and max (bits of the
+// order-preserving encoding).
+__global__ void k_bbox_init(uint32_t* __restrict__ bbox, uint32_t count) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) bbox[e] = (e & 1u) ? 0u : 0xFFFFFFFFu;
+}
+
+// Block (q, y) folds slice y of instance q's per-block boxes into bbox with
+// atomic min / max (one per axis and block): one instance spreads over up
+// to kBboxBlocks blocks.
+constexpr uint32_t kBboxBlocks = 64;
 __global__ __launch_bounds__(kBlock) void k_bbox_reduce(const InstDesc* __restrict__ inst, int d,
                                                         const uint32_t* __restrict__ part,
                                                         uint32_t* __restrict__ bbox) {
   const uint32_t q = blockIdx.x;
   const uint32_t b0 = inst[q].blk_first;
   const uint32_t nb = (uint32_t)((inst[q].n + kBlock - 1) / kBlock);
+  const uint32_t per = (nb + gridDim.y - 1) / gridDim.y;
+  const uint32_t lo_b = blockIdx.y * per, hi_b = min(nb, lo_b + per);
+  if (lo_b >= hi_b) return;
   const int w = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
   for (int l = w; l < d; l += kWaves) {
     uint32_t lo = 0xFFFFFFFFu, hi = 0u;
-    for (uint32_t b = lane; b < nb; b += 64) {
+    for (uint32_t b = lo_b + lane; b < hi_b; b += 64) {
       lo = min(lo, part[(size_t)(b0 + b) * 2 * d + 2 * l]);
       hi = max(hi, part[(size_t)(b0 + b) * 2 * d + 2 * l + 1]);
     }
@@ -211,8 +225,8 @@ __global__ __launch_bounds__(kBlock) void k_bbox_reduce(const InstDesc* __restri
       hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
     }
     if (lane == 0) {
-      bbox[(size_t)q * 2 * d + 2 * l] = lo;
-      bbox[(size_t)q * 2 * d + 2 * l + 1] = hi;
+      atomicMin(&bbox[(size_t)q * 2 * d + 2 * l], lo);
+      atomicMax(&bbox[(size_t)q * 2 * d + 2 * l + 1], hi);
     }
   }
 }
@@ -769,10 +783,20 @@ __global__ __launch_bounds__(kBlock) void k_cell_work(const uint32_t* __restrict
     units[c] = nt <= cell_unit_tiles ? 1u : nt;
     tests[c] = L * (L - 1) / 2;
   }
+  // one atomic per block: a single counter's device-scope atomics serialise
+  // across the XCDs
+  __shared__ unsigned long long wm[kWaves];
   unsigned long long m = L;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m += __shfl_xor(m, o, 64);
-  if (lane_id() == 0 && m) atomicAdd(members, m);
+  if (lane_id() == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long all = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) all += wm[q];
+    if (all) atomicAdd(members, all);
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_unique_count(const uint64_t* __restrict__ keys,
@@ -2374,7 +2398,13 @@ void launch_stage(const InstDesc* inst, uint32_t m, uint32_t nblocks, int d, int
   hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(64), 0, s, bad, 0u, (size_t)1);
   hipLaunchKernelGGL(k_stage, dim3(nblocks), dim3(kBlock), 0, s, inst, m, d, npts, soa, aos, bad,
                      part);
-  hipLaunchKernelGGL(k_bbox_reduce, dim3(m), dim3(kBlock), 0, s, inst, d, part, bbox);
+  const uint32_t nbox = m * 2u * (uint32_t)d;
+  hipLaunchKernelGGL(k_bbox_init, dim3((nbox + kBlock - 1) / kBlock), dim3(kBlock), 0, s, bbox,
+                     nbox);
+  // blocks per instance: about 64 per-block boxes each, at most kBboxBlocks
+  uint32_t gy = (uint32_t)std::min<uint64_t>(kBboxBlocks, (nblocks / m + 63) / 64);
+  if (gy < 1) gy = 1;
+  hipLaunchKernelGGL(k_bbox_reduce, dim3(m, gy), dim3(kBlock), 0, s, inst, d, part, bbox);
 }
 
 template <int D>
