@@ -96,23 +96,37 @@ Arena::Arena(char* base, size_t bytes) {
   const uintptr_t a = (b + kAlign - 1) & ~(uintptr_t)(kAlign - 1);
   base_ = reinterpret_cast<char*>(a);
   size_ = bytes > (a - b) ? (bytes - (a - b)) & ~(size_t)(kAlign - 1) : 0;
-  if (size_) free_[0] = size_;
+  if (size_) add_free(0, size_);
+}
+
+void Arena::add_free(size_t off, size_t len) {
+  free_[off] = len;
+  by_size_.emplace(len, off);
+}
+
+void Arena::drop_free(std::map<size_t, size_t>::iterator it) {
+  auto range = by_size_.equal_range(it->second);
+  for (auto s = range.first; s != range.second; ++s)
+    if (s->second == it->first) {
+      by_size_.erase(s);
+      break;
+    }
+  free_.erase(it);
 }
 
 void* Arena::alloc(size_t bytes) {
   bytes = std::max<size_t>(bytes, 1);
   bytes = (bytes + kAlign - 1) & ~(size_t)(kAlign - 1);
-  for (auto it = free_.begin(); it != free_.end(); ++it) {
-    if (it->second < bytes) continue;
-    const size_t off = it->first, rem = it->second - bytes;
-    free_.erase(it);
-    if (rem) free_[off + bytes] = rem;
-    used_[off] = bytes;
-    in_use_ += bytes;
-    peak_ = std::max(peak_, in_use_);
-    return base_ + off;
-  }
-  return nullptr;
+  auto s = by_size_.lower_bound(bytes);  // the smallest free block that fits
+  if (s == by_size_.end()) return nullptr;
+  const size_t off = s->second, len = s->first;
+  by_size_.erase(s);
+  free_.erase(off);
+  if (len > bytes) add_free(off + bytes, len - bytes);
+  used_[off] = bytes;
+  in_use_ += bytes;
+  peak_ = std::max(peak_, in_use_);
+  return base_ + off;
 }
 
 void Arena::release(void* p) {
@@ -126,7 +140,7 @@ void Arena::release(void* p) {
   auto next = free_.lower_bound(start);
   if (next != free_.end() && start + len == next->first) {
     len += next->second;
-    free_.erase(next);
+    drop_free(next);
   }
   auto prev = free_.lower_bound(start);
   if (prev != free_.begin()) {
@@ -134,17 +148,13 @@ void Arena::release(void* p) {
     if (prev->first + prev->second == start) {
       start = prev->first;
       len += prev->second;
-      free_.erase(prev);
+      drop_free(prev);
     }
   }
-  free_[start] = len;
+  add_free(start, len);
 }
 
-size_t Arena::largest_free() const {
-  size_t m = 0;
-  for (auto& f : free_) m = std::max(m, f.second);
-  return m;
-}
+size_t Arena::largest_free() const { return by_size_.empty() ? 0 : by_size_.rbegin()->first; }
 
 // ---------------------------------------------------------------------------
 // helpers
@@ -186,6 +196,14 @@ PairTest make_pair_test(double r2, int pair_bits) {
 double mr_screen_r2(double r) {
   const double x = (r * r) * (1.0 + 0x1p-40);
   return std::nextafter(x, INFINITY);
+}
+
+// The volume of the d-ball of radius r over that of the cube of side
+// alpha r: no more than this share of the pairs of points that share a cell
+// lie within r of each other (the cube's edges only lower the share).
+double ball_share(int d, double alpha) {
+  const double v = std::pow(M_PI, 0.5 * d) / std::tgamma(0.5 * d + 1.0);
+  return std::min(1.0, v / std::pow(alpha, d));
 }
 
 // Whether the matrix-core pair screen suits an instance: its band, relative
@@ -1286,15 +1304,30 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     // copy puts them after the earlier passes' pairs in cand.
     const uint32_t nseg = kCandSegments;
     unsigned long long* segcnt = counters + 4;
-    // The guess: a sixteenth of the tests, but at most 16 pairs per (point,
-    // grid) key -- where few tested pairs lie within r (high d, wide cells)
-    // the tests overstate the pairs a thousandfold.
-    const uint64_t guess = std::min<uint64_t>(
-        tests_total,
-        std::max<uint64_t>(1u << 20, std::min<uint64_t>(tests_total / 16, 16ull * N)));
+    // The guess: the tests times the share of a cell's pairs that can lie
+    // within r -- for two points of one cube of side alpha r at most the
+    // unit ball's volume over alpha^d (the cube's edges only lower it), with a
+    // quarter to spare and a sixteenth as the floor -- but at most 16 pairs
+    // per (point, grid) key: where few tested pairs lie within r (high d,
+    // clustered points) the tests overstate the pairs a thousandfold.
+    double share = 1.0 / 16;
+    for (int32_t sg = sa; sg < sb; ++sg)
+      share = std::max(share, 1.25 * ball_share(d, jobs[segs[sg].inst]->alpha));
+    // Where that would take more than a quarter of the free memory, or
+    // cannot be had, a sixteenth of the tests: an overflow then costs one
+    // more pair pass.
+    const uint64_t lean = std::min<uint64_t>(
+        tests_total, std::max<uint64_t>(1u << 20, std::min<uint64_t>(tests_total / 16, 16ull * N)));
+    const uint64_t guess = std::max<uint64_t>(
+        lean, std::min<uint64_t>({tests_total, (uint64_t)(share * (double)tests_total), 16ull * N,
+                                  ctx->largest_free() / 40}));
     uint64_t seg_cap = guess / nseg + guess / (4 * nseg) + 1024;
     for (int attempt = 0; attempt < 2; ++attempt) {
       uint64_t* sbuf = S.get<uint64_t>((size_t)nseg * seg_cap);
+      if (!sbuf && attempt == 0 && lean < guess) {
+        seg_cap = lean / nseg + lean / (4 * nseg) + 1024;
+        sbuf = S.get<uint64_t>((size_t)nseg * seg_cap);
+      }
       if (!sbuf) return RTG_ENOMEM;
       launch_fill_u64(reinterpret_cast<uint64_t*>(segcnt), 0ull, nseg, stream);
       pa.cand = sbuf;
@@ -1488,14 +1521,12 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   } else {
     std::vector<int64_t> at(m + 1);
     int64_t* at_d = S.get<int64_t>(m + 1);
-    int64_t** rp_tab = S.get<int64_t*>(m);
-    int32_t** col_tab = S.get<int32_t*>(m);
-    if (!at_d || !rp_tab || !col_tab) {
+    if (!at_d) {
       dfree(res);
       return RTG_ENOMEM;
     }
     launch_rowptr_at(inst_d, m, row_ptr, npts, at_d, stream);
-    if ((rc = download(at.data(), at_d, sizeof(int64_t) * (m + 1)))) {
+    if ((rc = read_back(at_d, sizeof(int64_t) * (m + 1), at.data()))) {
       dfree(res);
       return rc;
     }
@@ -1506,10 +1537,19 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
       const size_t nq = (size_t)((q + 1 < m ? at[q + 1] : at[m]) - at[q]);
       rc = alloc_result(*this, jobs[q]->n, nq, &mem[q], &rps[q], &cols[q]);
     }
-    if (!rc) rc = upload(rp_tab, rps.data(), sizeof(int64_t*) * m);
-    if (!rc) rc = upload(col_tab, cols.data(), sizeof(int32_t*) * m);
+    // both pointer tables in one copy from pinned memory
+    Uploads Ul(*this);
+    const size_t o_rp = Ul.add(rps.data(), sizeof(int64_t*) * m);
+    const size_t o_col = Ul.add(cols.data(), sizeof(int32_t*) * m);
+    char* tabs = rc ? nullptr : S.get<char>(Ul.total());
+    if (!rc && !tabs) rc = RTG_ENOMEM;
+    int64_t** rp_tab = tabs ? reinterpret_cast<int64_t**>(tabs + o_rp) : nullptr;
+    int32_t** col_tab = tabs ? reinterpret_cast<int32_t**>(tabs + o_col) : nullptr;
+    if (!rc) rc = Ul.send(tabs);
     if (!rc) {
-      launch_localize(inst_d, m, nblk, row_ptr, col, rp_tab, col_tab, stream);
+      kbegin(RTG_K_CSR);
+      launch_localize(inst_d, m, nblk, row_ptr, col, at_d, at[m], rp_tab, col_tab, stream);
+      kend(RTG_K_CSR, 16.0 * (double)(npts + m) + 8.0 * (double)at[m]);
       rc = sync();
     }
     dfree(res);

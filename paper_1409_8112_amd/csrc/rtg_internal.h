@@ -412,9 +412,10 @@ void launch_u32_to_u64(const uint32_t* src, size_t count, uint64_t* dst, hipStre
 void launch_rowptr_at(const InstDesc* inst, uint32_t m, const int64_t* row_ptr, int64_t npts,
                       int64_t* out, hipStream_t s);
 // Instance q's rows of the batch lists into out_rp[q] (n+1) / out_col[q],
-// with column indices local to the instance (device pointer tables).
+// with row starts and column indices local to the instance (device pointer
+// tables); at = launch_rowptr_at's output, total = at[m] entries.
 void launch_localize(const InstDesc* inst, uint32_t m, uint32_t nblocks, const int64_t* row_ptr,
-                     const int32_t* col, int64_t* const* out_rp, int32_t* const* out_col,
-                     hipStream_t s);
+                     const int32_t* col, const int64_t* at, int64_t total, int64_t* const* out_rp,
+                     int32_t* const* out_col, hipStream_t s);
 
 }  // namespace rtgk

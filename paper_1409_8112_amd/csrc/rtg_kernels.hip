@@ -2342,27 +2342,60 @@ __global__ void k_rowptr_at(const InstDesc* __restrict__ inst, uint32_t m,
   if (q == m) out[m] = row_ptr[npts];
 }
 
-// One thread per batch point (point blocks as in the stage): copies the
-// point's row of the batch lists into its instance's own lists, with
-// indices local to the instance.
-__global__ __launch_bounds__(kBlock) void k_localize(const InstDesc* __restrict__ inst, uint32_t m,
-                                                     const int64_t* __restrict__ row_ptr,
-                                                     const int32_t* __restrict__ col,
-                                                     int64_t* const* __restrict__ out_rp,
-                                                     int32_t* const* __restrict__ out_col) {
+// One thread per batch point (point blocks as in the stage): the point's
+// row start in its instance's own row_ptr, relative to the instance.
+__global__ __launch_bounds__(kBlock) void k_localize_rows(const InstDesc* __restrict__ inst,
+                                                          uint32_t m,
+                                                          const int64_t* __restrict__ row_ptr,
+                                                          int64_t* const* __restrict__ out_rp) {
   const uint32_t q = block_instance(inst, m, blockIdx.x);
   const int64_t n = inst[q].n;
   const int64_t i = (int64_t)(blockIdx.x - (uint32_t)inst[q].blk_first) * kBlock + threadIdx.x;
   if (i >= n) return;
   const int64_t off = inst[q].pt_off;
-  const int64_t g = off + i;
   const int64_t base = row_ptr[off];
-  const int64_t a = row_ptr[g], b = row_ptr[g + 1];
   int64_t* rp = out_rp[q];
-  rp[i] = a - base;
-  if (i == n - 1) rp[n] = b - base;
-  int32_t* c = out_col[q];
-  for (int64_t e = a; e < b; ++e) c[e - base] = col[e] - (int32_t)off;
+  rp[i] = row_ptr[off + i] - base;
+  if (i == n - 1) rp[n] = row_ptr[off + n] - base;
+}
+
+constexpr int kLocalizePer = 16;  // entries per thread of the column copy
+
+// The batch's col copied into the instances' own col arrays, indices made
+// local: each block a contiguous run of kLocalizePer * kBlock entries (loads
+// and stores coalesced); at[q] is instance q's first entry, at[m] the total.
+// Each thread finds the instance of its first entry by bisection and steps
+// forward past instance ends (several instances may share a run).
+__global__ __launch_bounds__(kBlock) void k_localize_cols(const InstDesc* __restrict__ inst,
+                                                          uint32_t m,
+                                                          const int64_t* __restrict__ at,
+                                                          const int32_t* __restrict__ col,
+                                                          int32_t* const* __restrict__ out_col) {
+  const int64_t total = at[m];
+  const int64_t e0 = (int64_t)blockIdx.x * (kLocalizePer * kBlock) + threadIdx.x;
+  if (e0 >= total) return;
+  uint32_t lo = 0, hi = m - 1;  // the last q with at[q] <= e0
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (at[mid] <= e0) lo = mid; else hi = mid - 1;
+  }
+  uint32_t q = lo;
+  int64_t q_end = at[q + 1], q_begin = at[q];
+  int32_t* dst = out_col[q];
+  int32_t off = (int32_t)inst[q].pt_off;
+#pragma unroll 4
+  for (int j = 0; j < kLocalizePer; ++j) {
+    const int64_t e = e0 + (int64_t)j * kBlock;
+    if (e >= total) break;
+    while (e >= q_end) {
+      ++q;
+      q_begin = q_end;
+      q_end = at[q + 1];
+      dst = out_col[q];
+      off = (int32_t)inst[q].pt_off;
+    }
+    dst[e - q_begin] = col[e] - off;
+  }
 }
 
 inline unsigned grid_for(size_t count, unsigned block = kBlock) {
@@ -2894,11 +2927,15 @@ void launch_rowptr_at(const InstDesc* inst, uint32_t m, const int64_t* row_ptr, 
 }
 
 void launch_localize(const InstDesc* inst, uint32_t m, uint32_t nblocks, const int64_t* row_ptr,
-                     const int32_t* col, int64_t* const* out_rp, int32_t* const* out_col,
-                     hipStream_t s) {
-  if (!nblocks) return;
-  hipLaunchKernelGGL(k_localize, dim3(nblocks), dim3(kBlock), 0, s, inst, m, row_ptr, col, out_rp,
-                     out_col);
+                     const int32_t* col, const int64_t* at, int64_t total, int64_t* const* out_rp,
+                     int32_t* const* out_col, hipStream_t s) {
+  if (nblocks)
+    hipLaunchKernelGGL(k_localize_rows, dim3(nblocks), dim3(kBlock), 0, s, inst, m, row_ptr,
+                       out_rp);
+  if (total > 0 && m > 0)
+    hipLaunchKernelGGL(k_localize_cols,
+                       dim3((unsigned)((total + kLocalizePer * kBlock - 1) / (kLocalizePer * kBlock))),
+                       dim3(kBlock), 0, s, inst, m, at, col, out_col);
 }
 
 }  // namespace rtgk

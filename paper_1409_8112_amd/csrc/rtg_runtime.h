@@ -19,8 +19,9 @@
 
 namespace rtg {
 
-// First-fit sub-allocator over one device buffer (the context's memory
-// budget).  Host-side bookkeeping only; blocks are 256-byte aligned.
+// Best-fit sub-allocator over one device buffer (the context's memory
+// budget): free blocks indexed by offset (for coalescing) and by length
+// (for the search).  Host-side bookkeeping only; blocks are 256-byte aligned.
 class Arena {
  public:
   static constexpr size_t kAlign = 256;
@@ -35,8 +36,11 @@ class Arena {
  private:
   char* base_ = nullptr;
   size_t size_ = 0, in_use_ = 0, peak_ = 0;
-  std::map<size_t, size_t> free_;  // offset -> length
-  std::map<size_t, size_t> used_;  // offset -> length
+  std::map<size_t, size_t> free_;            // offset -> length
+  std::multimap<size_t, size_t> by_size_;    // length -> offset (the same free blocks)
+  std::map<size_t, size_t> used_;            // offset -> length
+  void add_free(size_t off, size_t len);
+  void drop_free(std::map<size_t, size_t>::iterator it);
 };
 
 // How cell vectors are packed into the sort key for one query.

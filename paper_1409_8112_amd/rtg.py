@@ -14,7 +14,6 @@ from __future__ import annotations
 import ctypes
 import os
 import threading
-from dataclasses import dataclass
 
 import numpy as np
 
@@ -159,17 +158,32 @@ def model_recall(d: int, k: int, alpha: float, flags: int = 0) -> float:
     return float(rc.value)
 
 
-@dataclass
 class Result:
-    """A device-resident neighbour list (views into the context's arena)."""
-    ctx: "Context"
-    handle: int
-    n: int
-    nnz: int
-    pairs: int
-    row_ptr: "object"  # torch.int64 [n+1], cuda
-    col: "object"      # torch.int32 [nnz], cuda
-    released: bool = False
+    """A device-resident neighbour list: row_ptr (torch.int64 [n+1]) and col
+    (torch.int32 [nnz]) are views into the context's arena, made on first
+    use, valid until release()."""
+
+    __slots__ = ("ctx", "handle", "n", "nnz", "pairs", "released", "_rp_ptr", "_col_ptr",
+                 "_row_ptr", "_col")
+
+    def __init__(self, ctx: "Context", handle: int, n: int, nnz: int, pairs: int,
+                 rp_ptr: int, col_ptr: int):
+        self.ctx, self.handle, self.n, self.nnz, self.pairs = ctx, handle, n, nnz, pairs
+        self.released = False
+        self._rp_ptr, self._col_ptr = rp_ptr, col_ptr
+        self._row_ptr = self._col = None
+
+    @property
+    def row_ptr(self):
+        if self._row_ptr is None:
+            self._row_ptr = self.ctx._view(self._rp_ptr, self.n + 1, self.ctx.torch.int64)
+        return self._row_ptr
+
+    @property
+    def col(self):
+        if self._col is None:
+            self._col = self.ctx._view(self._col_ptr, self.nnz, self.ctx.torch.int32)
+        return self._col
 
     def to_numpy(self):
         return self.row_ptr.cpu().numpy().copy(), self.col.cpu().numpy().copy()
@@ -234,10 +248,8 @@ class Context:
         return self.arena[off:off + nbytes].view(dtype)
 
     def _result(self, c: rtg_csr) -> Result:
-        t = self.torch
-        return Result(self, int(c.handle), int(c.n), int(c.nnz), int(c.pairs),
-                      self._view(c.row_ptr, int(c.n) + 1, t.int64),
-                      self._view(c.col or 0, int(c.nnz), t.int32))
+        return Result(self, int(c.handle), int(c.n), int(c.nnz), int(c.pairs), int(c.row_ptr),
+                      int(c.col or 0))
 
     def _points(self, points):
         if points.dtype != self.torch.float32:
@@ -274,13 +286,21 @@ class Context:
     def rtg_all_pairs_batched(self, queries) -> list[Result]:
         """queries: list of dicts with points, r, k, alpha, seed, flags."""
         nq = len(queries)
-        qs = (rtg_query * max(nq, 1))()
-        for i, q in enumerate(queries):
-            p = self._points(q["points"])
-            qs[i] = rtg_query(p.data_ptr(), p.shape[0], p.shape[1], float(q["r"]), int(q["k"]),
-                              float(q["alpha"]), q.get("seed", 0) & (2**64 - 1), q.get("flags", 0))
+        # the query table filled column by column (one numpy write per field)
+        qs = np.zeros(max(nq, 1), dtype=np.dtype(rtg_query))
+        pts = [self._points(q["points"]) for q in queries]
+        if nq:
+            qs["points"][:nq] = [p.data_ptr() for p in pts]
+            qs["n"][:nq] = [p.shape[0] for p in pts]
+            qs["d"][:nq] = [p.shape[1] for p in pts]
+            qs["r"][:nq] = [q["r"] for q in queries]
+            qs["k"][:nq] = [q["k"] for q in queries]
+            qs["alpha"][:nq] = [q["alpha"] for q in queries]
+            qs["seed"][:nq] = [q.get("seed", 0) & (2**64 - 1) for q in queries]
+            qs["flags"][:nq] = [q.get("flags", 0) for q in queries]
         outs = (rtg_csr * max(nq, 1))()
-        _check(lib().rtg_all_pairs_batched(self.h, qs, nq, outs), "rtg_all_pairs_batched")
+        _check(lib().rtg_all_pairs_batched(self.h, qs.ctypes.data_as(ctypes.POINTER(rtg_query)),
+                                           nq, outs), "rtg_all_pairs_batched")
         return [self._result(outs[i]) for i in range(nq)]
 
     def rtg_submit(self, points, r: float, k: int, alpha: float, seed: int,
