@@ -128,3 +128,40 @@ def test_invalid_query_fails_the_batch_and_keeps_nothing(ctx):
     # the context still works
     ok = _queries(7, 3)
     _check(ok, _run(ctx, ok))
+
+
+def test_instances_without_pairs_between_others(ctx):
+    """Copying a batch's lists into per-instance results: instances with no
+    pairs (a radius too small for any) at the start, the end and in runs in
+    the middle, many small instances sharing one run of the copy and large
+    ones spanning several -- every result equals the oracle's."""
+    qs = []
+    for q in range(30):
+        none = q in (0, 1, 7, 8, 9, 15, 28, 29)
+        n = 3 if q % 5 == 4 else (40 + 13 * q if q % 3 else 2500 + 400 * q)
+        p = workloads.uniform_points(n, 3, seed=900 + q)
+        r = 1e-7 if none else workloads.prm_radius(max(n, 3), 3, 1.2)
+        qs.append(dict(points=p, r=r, k=3, alpha=2.0, seed=q, flags=(0, 1)[q % 2]))
+    got = _run(ctx, qs)
+    _check(qs, got)
+    assert sum(len(col) for _, col in got) > 200_000  # several runs of the copy
+    assert all(len(got[q][1]) == 0 for q in (0, 1, 7, 8, 9, 15, 28, 29))
+
+
+def test_result_views_made_on_first_use(ctx):
+    """row_ptr and col are device views into the arena, made on first access
+    and equal to the copied-out lists."""
+    import torch
+    qs = _queries(8, 5, dims=(3,), n_lo=200, n_hi=2000)
+    res = ctx.all_pairs_batched([dict(q, points=_dev(q["points"])) for q in qs])
+    try:
+        for q, r in zip(qs, res):
+            ref = oracle.rtg(q["points"], q["r"], q["k"], q["alpha"], q["seed"], q["flags"] & 3)
+            assert r.row_ptr.is_cuda and r.row_ptr.dtype == torch.int64
+            assert r.col.dtype == torch.int32 and r.row_ptr.shape[0] == r.n + 1
+            assert r.col.shape[0] == r.nnz == len(ref.col)
+            assert np.array_equal(r.row_ptr.cpu().numpy(), ref.row_ptr)
+            assert np.array_equal(r.col.cpu().numpy(), ref.col)
+    finally:
+        for r in res:
+            r.release()
