@@ -967,22 +967,35 @@ __device__ __forceinline__ uint32_t tile_len(const UnitView& V, uint32_t t) {
   return min((uint32_t)kPairTile, V.L - t * kPairTile);
 }
 
-// Loads the tile after (ta, tb) in the wave's stream of tile pairs: the next
-// B tile of the row, else the next row's diagonal tile, else the first tile
-// of the next unit Vn (nothing when the stream ends).
+// A row's tile pairs (ta, tb): its diagonal first, then its B tiles from the
+// last down to ta + 1, so that a row ends on the next row's own tile.
+__device__ __forceinline__ uint32_t row_step_tile(const UnitView& V, uint32_t ta, uint32_t s) {
+  return s == 0 ? ta : V.nt - s;
+}
+
+// Loads the tile after (ta, tb) in the wave's stream of tile pairs: the
+// row's next B tile, else -- the row ending on tile ta + 1 -- that tile again
+// (kept from R_cur, not loaded) for the next row, else the first tile of the
+// next unit Vn (nothing when the stream ends).
 template <int D>
 __device__ __forceinline__ void load_next(const PairsArgs& P, const UnitView& V,
                                           const UnitView& Vn, uint32_t ta, uint32_t tb,
-                                          uint32_t lane, TileRegs<D>& R) {
+                                          uint32_t lane, const TileRegs<D>& R_cur,
+                                          TileRegs<D>& R) {
+  uint32_t t = ~0u;  // the unit's next tile to load
+  if (tb == ta) {
+    if (V.nt > ta + 1) t = V.nt - 1;
+  } else if (tb > ta + 1) {
+    t = tb - 1;
+  } else if (ta + 1 < V.ta_end) {
+    R = R_cur;  // tb = ta + 1: the next row's tile, in registers already
+    return;
+  }
   uint32_t p0 = 0, n = 0;
   int nw = 0;
-  if (tb + 1 < V.nt) {
-    p0 = V.s0 + (tb + 1) * kPairTile;
-    n = tile_len(V, tb + 1);
-    nw = V.nw;
-  } else if (ta + 1 < V.ta_end) {
-    p0 = V.s0 + (ta + 1) * kPairTile;
-    n = tile_len(V, ta + 1);
+  if (t != ~0u) {
+    p0 = V.s0 + t * kPairTile;
+    n = tile_len(V, t);
     nw = V.nw;
   } else if (Vn.ok) {
     p0 = Vn.s0 + Vn.ta_begin * kPairTile;
@@ -1122,7 +1135,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs(const PairsArgs P) {
       const uint32_t pa0 = V.s0 + ta * kPairTile;
       const bool rowok = lane < nA;
       const TileRegs<D> A = cur;  // the row's tile, also its diagonal B tile
-      for (uint32_t tb = ta; tb < V.nt; ++tb) {
+      for (uint32_t s = 0; s < V.nt - ta; ++s) {
+      const uint32_t tb = row_step_tile(V, ta, s);
       const uint32_t pb0 = V.s0 + tb * kPairTile;
       const uint32_t nB = tile_len(V, tb);
       wave_lds_sync();
@@ -1134,7 +1148,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs(const PairsArgs P) {
         for (int q = 0; q < kSigWords; ++q) sBw[w][q][lane] = cur.sw[q];
       }
       wave_lds_sync();
-      load_next<D>(P, V, Vn, ta, tb, lane, nxt);
+      load_next<D>(P, V, Vn, ta, tb, lane, cur, nxt);
 
       // lane l tests j only when j > lim: every pair once in a diagonal tile
       const int lim = rowok ? (ta == tb ? (int)lane : -1) : 64;
@@ -1278,8 +1292,12 @@ __device__ __forceinline__ uint32_t gram_col(int b, uint32_t lane) {
   return 32u * (((uint32_t)b >> 4) & 1u) + (lane & 31u);
 }
 
+// Four waves per SIMD up to D = 9 (at most 128 registers: a few spills at
+// D = 9 cost less than the lost wave); three above, where the registers the
+// wider rows need would spill more.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_cell_pairs_gram(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(D <= 9 ? 4 : 3))) void
+k_cell_pairs_gram(
     const PairsArgs P) {
   constexpr int KA = (D + 3) & ~1;  // augmented row length, even
   constexpr int KS = KA / 2;        // MFMA steps per block
@@ -1376,7 +1394,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs_gram(
       for (int q = 0; q < kSigWords; ++q) sAw[q][lane] = cur.sw[q];
     }
 
-    for (uint32_t tb = ta; tb < V.nt; ++tb) {
+    for (uint32_t s = 0; s < V.nt - ta; ++s) {
+      const uint32_t tb = row_step_tile(V, ta, s);
       const uint32_t pb0 = V.s0 + tb * kPairTile;
       const uint32_t nB = min((uint32_t)kPairTile, V.L - tb * kPairTile);
       wave_lds_sync();
@@ -1418,7 +1437,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_pairs_gram(
 #pragma unroll
       for (int l = 0; l < KA; ++l) sB[lane][l] = row[l];
       wave_lds_sync();
-      load_next<D>(P, V, Vn, ta, tb, lane, nxt);
+      load_next<D>(P, V, Vn, ta, tb, lane, cur, nxt);
 
       float breg[2][KS];
 #pragma unroll
