@@ -125,6 +125,59 @@ def bench_batched(ctx, count: int, reps: int = 3) -> dict:
             "same_pairs_as_plain": pairs == pairs_plain}
 
 
+def brute_force_rows(points: np.ndarray, r: float, rows: np.ndarray, chunk: int = 16384) -> list:
+    """Every point within r of each sampled row by direct search, the row
+    itself excluded: a Gram-expansion screen with a wide margin, then the
+    exact FP64 decision (squared differences summed axis by axis)."""
+    p = points.astype(np.float64)
+    q = p[rows]
+    r2 = r * r
+    qn = (q * q).sum(1)
+    found = [[] for _ in range(len(rows))]
+    t_last = time.perf_counter()
+    for s0 in range(0, len(p), chunk):
+        if time.perf_counter() - t_last > 20.0:
+            print(f"#   brute force: {s0} of {len(p)} points", file=sys.stderr, flush=True)
+            t_last = time.perf_counter()
+        b = p[s0:s0 + chunk]
+        approx = qn[:, None] + (b * b).sum(1)[None, :] - 2.0 * (q @ b.T)
+        qi, bj = np.nonzero(approx <= r2 * (1.0 + 1e-6) + 1e-9)
+        if len(qi) == 0:
+            continue
+        diff = q[qi] - b[bj]
+        acc = np.zeros(len(qi))
+        for l in range(p.shape[1]):
+            acc = acc + diff[:, l] * diff[:, l]
+        j = bj + s0
+        keep = (acc <= r2) & (j != rows[qi])
+        for a, c in zip(qi[keep].tolist(), j[keep].tolist()):
+            found[a].append(c)
+    return found
+
+
+def measure_recall(ctx, pts, pts_host, wl, nrows: int) -> dict:
+    """Recall of the GPU's neighbour lists against brute force on sampled
+    rows (all rows when nrows >= n), and the count of listed neighbours
+    farther than r (zero by construction)."""
+    rows = np.arange(wl.n) if nrows >= wl.n else np.sort(
+        np.random.default_rng(12345).choice(wl.n, size=nrows, replace=False))
+    res = ctx.all_pairs(pts, wl.r, wl.k, wl.alpha, wl.seed)
+    rp, col = res.to_numpy()
+    res.release()
+    t0 = time.perf_counter()
+    bf = brute_force_rows(pts_host, wl.r, rows)
+    hit = want = outside = 0
+    for a, row in enumerate(rows.tolist()):
+        got = set(col[rp[row]:rp[row + 1]].tolist())
+        truth = set(bf[a])
+        hit += len(got & truth)
+        want += len(truth)
+        outside += len(got - truth)
+    return {"rows": int(len(rows)), "neighbours_brute_force": want, "found": hit,
+            "recall": hit / max(want, 1), "listed_beyond_r": outside,
+            "brute_force_s": time.perf_counter() - t0}
+
+
 def bench_auto(ctx, pts, wl, target: float, mean_neighbours: float, reps: int = 10) -> dict:
     """The workload with (k, alpha) chosen by the library for a target recall
     (modelled), against its fixed parameters' modelled recall."""
@@ -310,6 +363,8 @@ def main(argv=None) -> int:
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (a known-size "
                          "kernel for scaling hardware byte counters)")
+    ap.add_argument("--recall-rows", type=int, default=0,
+                    help="recall against brute force on this many sampled rows (0: skip)")
     ap.add_argument("--batched-count", type=int, default=4096)
     ap.add_argument("--serving-requests", type=int, default=1000)
     ap.add_argument("--serving-rate", type=float, default=1000.0)
@@ -427,6 +482,9 @@ def main(argv=None) -> int:
         "probe_kernel_ms": {name: probe["kernel_ms"][i] for i, name in enumerate(rtg.KERNELS)},
         "roofline": roof,
     }
+    if args.recall_rows > 0:
+        print(f"# recall on {args.recall_rows} sampled rows", file=sys.stderr, flush=True)
+        out["recall"] = measure_recall(ctx, pts, pts_host, wl, args.recall_rows)
     if not args.no_auto and args.workload == "uniform_d6":
         print("# parameters chosen for recall 0.98", file=sys.stderr, flush=True)
         out["auto_params"] = bench_auto(ctx, pts, wl, 0.98, 20.0)
