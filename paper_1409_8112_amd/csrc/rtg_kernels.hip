@@ -297,7 +297,8 @@ __global__ __launch_bounds__(kBlock) void k_keys(const InstDesc* __restrict__ in
       double y = cell_y<D>(Rt + (size_t)j * d, p, soa, npts, g, d, inv_c, ut[j]);
       bool ok = fabs(y) < 2147483648.0;
       bad |= !ok;
-      int64_t kap = ok ? (int64_t)floor(y) : 0;
+      // |y| < 2^31: the floor fits 32 bits, and one native conversion takes it
+      int64_t kap = ok ? (int64_t)(int32_t)floor(y) : 0;
       uint64_t mask = (1ull << layout->bits[j]) - 1ull;
       cell |= ((uint64_t)(kap - kl[j]) & mask) << layout->shift[j];
       grp |= ((uint64_t)(kap - kl[j]) & bmask) << (j * sig_b);
@@ -344,7 +345,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_coords(const float* __restrict_
     double y = cell_y<D>(R + (size_t)j * d, p, soa, n, i, d, inv_c, u[j]);
     bool ok = fabs(y) < 2147483648.0;
     bad |= !ok;
-    kappa[i * d + j] = ok ? (int64_t)floor(y) : 0;
+    kappa[i * d + j] = ok ? (int64_t)(int32_t)floor(y) : 0;
   }
   if (bad) atomicOr(err, 1u);
 }
@@ -354,6 +355,9 @@ __global__ __launch_bounds__(kBlock) void k_cell_coords(const float* __restrict_
 
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kBlock * kScanItems;
+// Up to this many tile sums, every apply block adds up its predecessors' sums
+// itself (at most 8 KB read per block).
+constexpr int kFusedScanSums = 2048;
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const T* __restrict__ in, size_t count,
@@ -369,10 +373,19 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const T* __restrict__ in
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-template <typename T>
+// Scans each block's tile and adds its offset: offsets[block] (already
+// scanned), or with FROM_SUMS the sum of the earlier blocks' tile sums, added
+// up by the block itself (no separate scan of the sums; for few blocks).
+template <typename T, bool FROM_SUMS = false>
 __global__ __launch_bounds__(kBlock) void k_scan_apply(const T* in, T* out, size_t count,
                                                        const T* __restrict__ offsets, T* total) {
   __shared__ T wsum[kWaves];
+  T from_sums = 0;
+  if (FROM_SUMS) {
+    T part = 0;
+    for (uint32_t p = threadIdx.x; p < blockIdx.x; p += kBlock) part += offsets[p];
+    block_exclusive_scan<T>(part, wsum, from_sums);
+  }
   const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
   T v[kScanItems];
   T s = 0;
@@ -383,7 +396,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const T* in, T* out, size
   }
   T tile_total;
   T run = block_exclusive_scan<T>(s, wsum, tile_total);
-  const T off = offsets ? offsets[blockIdx.x] : (T)0;
+  const T off = FROM_SUMS ? from_sums : (offsets ? offsets[blockIdx.x] : (T)0);
   run += off;
 #pragma unroll
   for (int q = 0; q < kScanItems; ++q) {
@@ -1637,7 +1650,7 @@ __global__ __launch_bounds__(kBlock) void k_query_keys(const QueryArgs A) {
       const double y = z * A.inv_c + ut[j];
       const bool ok = fabs(y) < 2147483648.0;
       bad |= !ok;
-      const int64_t kap = ok ? (int64_t)floor(y) : 0;
+      const int64_t kap = ok ? (int64_t)(int32_t)floor(y) : 0;
       const uint64_t mask = (1ull << A.layout->bits[j]) - 1ull;
       cell |= ((uint64_t)(kap - kl[j]) & mask) << A.layout->shift[j];
       grp |= ((uint64_t)(kap - kl[j]) & bmask) << (j * A.sig_b);
@@ -2534,6 +2547,12 @@ static void scan_rec(const T* in, T* out, size_t count, T* total, T* scratch, hi
   const size_t nb = (count + kScanTile - 1) / kScanTile;
   T* sums = scratch;
   hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(kBlock), 0, s, in, count, sums);
+  if (nb <= (size_t)kFusedScanSums) {
+    // each block adds up the sums before it: two launches instead of three
+    hipLaunchKernelGGL((k_scan_apply<T, true>), dim3((unsigned)nb), dim3(kBlock), 0, s, in, out,
+                       count, (const T*)sums, total);
+    return;
+  }
   scan_rec<T>(sums, sums, nb, (T*)nullptr, scratch + nb, s);
   hipLaunchKernelGGL(k_scan_apply<T>, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, count,
                      (const T*)sums, total);
