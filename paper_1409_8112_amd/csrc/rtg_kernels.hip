@@ -418,10 +418,12 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const T* in, T* out, size
 //     the scatter (one more read of the keys per pass).
 
 // LDS of one tile: staged keys/values and the per-wave digit counters.
+// (Values are staged in key[] too, after the keys have gone out: the tile
+// needs no separate value area, so a sort with values keeps the occupancy of
+// one without.)
 template <bool HAS_VAL>
 struct TileLds {
   uint64_t key[kTile];
-  uint32_t val[HAS_VAL ? kTile : 1];
   uint32_t wcnt[kWaves][256];
   uint32_t dstart[256];
   uint64_t goff[256];
@@ -503,6 +505,7 @@ __device__ __forceinline__ void tile_scatter(TileLds<HAS_VAL>& S, uint64_t* __re
   const int w = threadIdx.x >> 6;
   const uint32_t mask = (1u << nbits) - 1u;
   const size_t wave_base = tile_base + (size_t)w * (kTile / kWaves);
+  uint32_t pos_[HAS_VAL ? kKeysPerThread : 1];
 #pragma unroll
   for (int q = 0; q < kKeysPerThread; ++q) {
     const size_t e = wave_base + (size_t)q * 64 + lane;
@@ -510,12 +513,14 @@ __device__ __forceinline__ void tile_scatter(TileLds<HAS_VAL>& S, uint64_t* __re
       const uint32_t dg = (uint32_t)(k_[q] >> shift) & mask;
       const uint32_t pos = S.wcnt[w][dg] + r_[q];
       S.key[pos] = k_[q];
-      if (HAS_VAL) S.val[pos] = v_[q];
+      if (HAS_VAL) pos_[q] = pos;
     }
   }
   __syncthreads();
   const size_t rem = tile_end - tile_base;
   const uint32_t tile_count = rem < (size_t)kTile ? (uint32_t)rem : (uint32_t)kTile;
+  // the digit of each slot this thread writes out, a byte each, for the values
+  uint32_t dg4[HAS_VAL ? kKeysPerThread / 4 : 1] = {};
 #pragma unroll 4
   for (int q = 0; q < kKeysPerThread; ++q) {
     const uint32_t s = (uint32_t)q * kBlock + threadIdx.x;
@@ -523,9 +528,27 @@ __device__ __forceinline__ void tile_scatter(TileLds<HAS_VAL>& S, uint64_t* __re
       const uint64_t key = S.key[s];
       const uint32_t dg = (uint32_t)(key >> shift) & mask;
       const uint64_t g = S.goff[dg] + (s - S.dstart[dg]);
-      if (g < count) {  // always true when the offsets are right
-        kout[g] = key;
-        if (HAS_VAL) vout[g] = S.val[s];
+      if (g < count) kout[g] = key;  // always in range when the offsets are right
+      if (HAS_VAL) dg4[q / 4] |= dg << (8 * (q % 4));
+    }
+  }
+  if (HAS_VAL) {
+    // the values through the same slots, once every key has been read out
+    __syncthreads();
+    uint32_t* sval = reinterpret_cast<uint32_t*>(S.key);
+#pragma unroll
+    for (int q = 0; q < kKeysPerThread; ++q) {
+      const size_t e = wave_base + (size_t)q * 64 + lane;
+      if (e < tile_end) sval[pos_[q]] = v_[q];
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int q = 0; q < kKeysPerThread; ++q) {
+      const uint32_t s = (uint32_t)q * kBlock + threadIdx.x;
+      if (s < tile_count) {
+        const uint32_t dg = (dg4[q / 4] >> (8 * (q % 4))) & 0xFFu;
+        const uint64_t g = S.goff[dg] + (s - S.dstart[dg]);
+        if (g < count) vout[g] = sval[s];
       }
     }
   }
