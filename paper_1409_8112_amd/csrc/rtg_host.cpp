@@ -739,14 +739,16 @@ int csr_by_buckets(Lane& c, Scratch& S, const uint64_t* pairs, size_t count, int
   hipStream_t s = c.stream;
   int rc;
   const size_t E = both ? 2 * count : count;
-  // at most 2^14 buckets of at most 2^10 rows; up to about 8k entries per
-  // bucket, half of what one block holds in LDS (two blocks share a CU),
-  // so that each partition block writes runs of entries per bucket
+  // at most 2^14 buckets of at most 2^10 rows, as few as keep the mean
+  // bucket within 7/8 of what one block holds in LDS (the rest is headroom
+  // for uneven buckets; one that overflows takes the global sort): fewer,
+  // larger buckets give the partition blocks longer runs to write and the
+  // per-bucket blocks more entries per fixed step
   int rb = std::max(0, ceil_log2((uint64_t)n) - 14);
   if ((1 << rb) > kBucketMaxRows) return RTG_ENOMEM;  // callers keep n <= 2^22
   const double per_row = (double)E / (double)n;
   while ((2 << rb) <= kBucketMaxRows && rb + 1 + pb <= 32 &&
-         per_row * (double)(1u << (rb + 1)) <= 8192.0)
+         per_row * (double)(1u << (rb + 1)) <= (double)(kBucketMaxEntries / 8 * 7))
     ++rb;
   const uint32_t nbuckets = (uint32_t)((n + ((int64_t)1 << rb) - 1) >> rb);
   const uint32_t nblocks =
