@@ -1011,8 +1011,9 @@ __device__ __forceinline__ uint32_t row_step_tile(const UnitView& V, uint32_t ta
 
 // Loads the tile after (ta, tb) in the wave's stream of tile pairs: the
 // row's next B tile, else -- the row ending on tile ta + 1 -- that tile again
-// (kept from R_cur, not loaded) for the next row, else the first tile of the
-// next unit Vn (nothing when the stream ends).
+// (kept from R_cur, not loaded) for the next row, in this unit or in the next
+// one when that is the same cell's next row, else the first tile of the next
+// unit Vn (nothing when the stream ends).
 template <int D>
 __device__ __forceinline__ void load_next(const PairsArgs& P, const UnitView& V,
                                           const UnitView& Vn, uint32_t ta, uint32_t tb,
@@ -1023,7 +1024,7 @@ __device__ __forceinline__ void load_next(const PairsArgs& P, const UnitView& V,
     if (V.nt > ta + 1) t = V.nt - 1;
   } else if (tb > ta + 1) {
     t = tb - 1;
-  } else if (ta + 1 < V.ta_end) {
+  } else if (ta + 1 < V.ta_end || (Vn.ok && Vn.s0 == V.s0 && Vn.ta_begin == ta + 1)) {
     R = R_cur;  // tb = ta + 1: the next row's tile, in registers already
     return;
   }
