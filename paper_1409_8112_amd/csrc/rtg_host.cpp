@@ -364,6 +364,7 @@ Ctx::Ctx(int dev) : device(dev) {
   const char* bc = std::getenv("RTG_BUCKET_CAP");
   if (const char* e = std::getenv("RTG_BUCKET_BLOCKS"))
     bucket_blocks = (uint32_t)std::max(1, std::min(4096, std::atoi(e)));
+  if (const char* e = std::getenv("RTG_BATCH_LANES")) batch_lanes = std::atoi(e) > 1 ? 2 : 1;
   if (const char* e = std::getenv("RTG_UNITS"))
     balanced_units = std::strcmp(e, "roundrobin") != 0;
   bucket_cap = kBucketMaxEntries;
@@ -375,6 +376,8 @@ Ctx::Ctx(int dev) : device(dev) {
 
 Ctx::~Ctx() {
   stop_server();
+  if (side) side->fini();
+  if (side_ready) (void)hipEventDestroy(side_ready);
   main.fini();
   if (own_arena && arena_mem) (void)hipFree(arena_mem);
 }
@@ -1612,6 +1615,52 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   return RTG_OK;
 }
 
+// The second lane of the batched call, made with this context's device
+// current (as the request loop's lanes are).
+int Ctx::side_lane() {
+  if (side) return RTG_OK;
+  if (hipSetDevice(device) != hipSuccess) return RTG_EDEVICE;
+  std::unique_ptr<Lane> L(new (std::nothrow) Lane());
+  if (!L) return RTG_ENOMEM;
+  int rc = L->init(this, nullptr, true);
+  if (!rc && hipEventCreateWithFlags(&side_ready, hipEventDisableTiming) != hipSuccess)
+    rc = RTG_EDEVICE;
+  if (rc) {
+    L->fini();
+    return rc;
+  }
+  side = std::move(L);
+  return RTG_OK;
+}
+
+// Adds the counts and times of b to a (widths: the larger).
+static void add_stats(rtg_stats& a, const rtg_stats& b) {
+  a.cells += b.cells;
+  a.tests += b.tests;
+  a.candidates += b.candidates;
+  a.band_rechecks += b.band_rechecks;
+  a.unique_pairs += b.unique_pairs;
+  a.key_bits = std::max(a.key_bits, b.key_bits);
+  a.key_passes = std::max(a.key_passes, b.key_passes);
+  a.pair_bits = std::max(a.pair_bits, b.pair_bits);
+  a.transforms_per_sort = std::max(a.transforms_per_sort, b.transforms_per_sort);
+  a.ms_stage += b.ms_stage;
+  a.ms_keys += b.ms_keys;
+  a.ms_key_sort += b.ms_key_sort;
+  a.ms_cells += b.ms_cells;
+  a.ms_pairs += b.ms_pairs;
+  a.ms_pair_sort += b.ms_pair_sort;
+  a.ms_unique += b.ms_unique;
+  a.ms_csr += b.ms_csr;
+  a.ms_total += b.ms_total;
+  for (int i = 0; i < RTG_NKERNELS; ++i) {
+    a.kernel_launches[i] += b.kernel_launches[i];
+    a.kernel_bytes[i] += b.kernel_bytes[i];
+    a.kernel_ms[i] += b.kernel_ms[i];
+  }
+  a.matrix_screen_launches += b.matrix_screen_launches;
+}
+
 // Many queries: grouped by dimension and list flags, each group split into
 // batches of at most batch_points points (an instance larger than that runs
 // alone), every batch one pass of run_batch.
@@ -1650,6 +1699,7 @@ int Ctx::batched(const rtg_query* q, int32_t nq, rtg_csr* outs) {
                   R[i].data(), u[i].data(), &res[i], 0};
     groups[{q[i].d, q[i].flags & kListFlags}].push_back(i);
   }
+  std::vector<std::vector<Job*>> batches;
   for (auto& g : groups) {
     size_t b = 0;
     while (b < g.second.size()) {
@@ -1661,9 +1711,47 @@ int Ctx::batched(const rtg_query* q, int32_t nq, rtg_csr* outs) {
         batch.push_back(&jobs[g.second[b]]);
         ++b;
       }
-      if ((rc = main.run_batch(batch, st))) return undo(rc);
-      for (Job* j : batch) done[j->out - res.data()] = 1;
+      batches.push_back(std::move(batch));
     }
+  }
+  // Several batches: two lanes take them in turn.  A batch that runs out of
+  // memory beside the other lane's pass runs again alone afterwards.
+  constexpr int kNotRun = 1 << 20;
+  std::vector<int> brc(batches.size(), kNotRun);
+  if (batches.size() >= 2 && batch_lanes > 1 && side_lane() == RTG_OK) {
+    if ((rc = hip_fail(hipEventRecord(side_ready, main.stream), "hipEventRecord")) ||
+        (rc = hip_fail(hipStreamWaitEvent(side->stream, side_ready, 0), "hipStreamWaitEvent")))
+      return undo(rc);
+    side->timing_mask = main.timing_mask;
+    std::atomic<size_t> next{0};
+    std::atomic<bool> failed{false};
+    auto work = [&](Lane& L, rtg_stats& s) {
+      for (;;) {
+        if (failed) return;
+        const size_t b = next++;
+        if (b >= batches.size()) return;
+        brc[b] = L.run_batch(batches[b], s);
+        if (brc[b] == RTG_OK)
+          for (Job* j : batches[b]) done[j->out - res.data()] = 1;
+        else if (brc[b] != RTG_ENOMEM)
+          failed = true;
+      }
+    };
+    rtg_stats st2{};
+    std::thread t([&] {
+      (void)hipSetDevice(device);
+      work(*side, st2);
+    });
+    work(main, st);
+    t.join();
+    add_stats(st, st2);
+    for (int r : brc)
+      if (r != RTG_OK && r != RTG_ENOMEM && r != kNotRun) return undo(r);
+  }
+  for (size_t b = 0; b < batches.size(); ++b) {
+    if (brc[b] == RTG_OK) continue;
+    if ((rc = main.run_batch(batches[b], st))) return undo(rc);
+    for (Job* j : batches[b]) done[j->out - res.data()] = 1;
   }
   for (int32_t i = 0; i < nq; ++i) outs[i] = res[i];
   st.d = nq ? q[0].d : 0;

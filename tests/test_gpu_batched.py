@@ -165,3 +165,45 @@ def test_result_views_made_on_first_use(ctx):
     finally:
         for r in res:
             r.release()
+
+
+def test_two_lanes_in_a_small_budget():
+    """Batches run two at a time; in a budget that holds about two passes a
+    pass may run out of memory beside the other and runs again alone. Every
+    result equals the oracle's, and equals one lane's."""
+    qs = []
+    for q in range(6):
+        n = 40000 - 1500 * q
+        p = workloads.uniform_points(n, 3, seed=700 + q)
+        qs.append(dict(points=p, r=workloads.prm_radius(n, 3, 0.6), k=4, alpha=2.0, seed=q,
+                       flags=0))
+    small = _small_ctx(48 << 20, RTG_BATCH_POINTS=40000)
+    try:
+        got = _run(small, qs)
+    finally:
+        small.close()
+    one = _small_ctx(48 << 20, RTG_BATCH_POINTS=40000, RTG_BATCH_LANES=1)
+    try:
+        alone = _run(one, qs)
+    finally:
+        one.close()
+    _check(qs, got)
+    for (a, b), (x, y) in zip(got, alone):
+        assert np.array_equal(a, x) and np.array_equal(b, y)
+
+
+def _small_ctx(arena_bytes, **env):
+    import torch
+    from paper_1409_8112_amd import rtg
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update({k: str(v) for k, v in env.items()})
+    try:
+        return rtg.Context(0, arena_bytes=arena_bytes)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
