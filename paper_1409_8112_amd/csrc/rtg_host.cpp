@@ -492,7 +492,7 @@ void Lane::fini() {
 }
 
 int Lane::hip_fail(hipError_t e, const char* what) { return ctx->hip_fail(e, what); }
-void* Lane::dalloc(size_t bytes) { return ctx->dalloc(bytes); }
+
 void Lane::dfree(void* p) { ctx->dfree(p); }
 
 int Lane::sync() { return hip_fail(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
@@ -696,26 +696,54 @@ std::vector<SortTile> segment_tiles(const std::vector<uint64_t>& off,
 // another lane cannot reuse memory a kernel of this one still touches.
 struct Scratch {
   Lane& c;
-  std::vector<void*> held;
-  explicit Scratch(Lane& lane) : c(lane) {}
+  void* outer;                                    // the lane's Scratch before this one
+  std::vector<std::pair<void*, size_t>> held;     // in use
+  // Dropped blocks.  Their last use is queued on this lane's stream, so the
+  // lane's later work may take them at once (stream order); the arena, and
+  // so the other lanes, gets them back only once the stream has drained.
+  std::vector<std::pair<void*, size_t>> pool;
+  explicit Scratch(Lane& lane) : c(lane), outer(lane.scratch) { lane.scratch = this; }
   ~Scratch() {
-    if (held.empty()) return;
+    c.scratch = outer;
+    if (held.empty() && pool.empty()) return;
     (void)hipStreamSynchronize(c.stream);
-    for (void* p : held) c.dfree(p);
+    for (auto& b : held) c.dfree(b.first);
+    for (auto& b : pool) c.dfree(b.first);
   }
   template <class T>
   T* get(size_t count) {
-    void* p = c.dalloc(std::max<size_t>(count, 1) * sizeof(T));
-    if (p) held.push_back(p);
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    // a dropped block that fits without wasting more than its request
+    size_t best = pool.size();
+    for (size_t i = 0; i < pool.size(); ++i)
+      if (pool[i].second >= bytes && pool[i].second <= 2 * bytes + 4096 &&
+          (best == pool.size() || pool[i].second < pool[best].second))
+        best = i;
+    if (best < pool.size()) {
+      held.push_back(pool[best]);
+      pool.erase(pool.begin() + (std::ptrdiff_t)best);
+      return static_cast<T*>(held.back().first);
+    }
+    void* p = c.dalloc(bytes);
+    if (p) held.push_back({p, bytes});
     return static_cast<T*>(p);
   }
   void drop(void* p) {
-    auto it = std::find(held.begin(), held.end(), p);
-    if (it != held.end()) {
-      (void)hipStreamSynchronize(c.stream);
-      c.dfree(p);
-      held.erase(it);
-    }
+    for (size_t i = 0; i < held.size(); ++i)
+      if (held[i].first == p) {
+        pool.push_back(held[i]);
+        held.erase(held.begin() + (std::ptrdiff_t)i);
+        return;
+      }
+  }
+  // Gives the dropped blocks back to the arena (after the stream drains);
+  // false if there were none.
+  bool flush() {
+    if (pool.empty()) return false;
+    (void)hipStreamSynchronize(c.stream);
+    for (auto& b : pool) c.ctx->dfree(b.first);
+    pool.clear();
+    return true;
   }
 };
 
@@ -870,6 +898,15 @@ int csr_from_sorted(Lane& c, Scratch& S, const uint64_t* uniq, size_t U, int64_t
 
 
 }  // namespace
+
+// Device memory from the arena; when it has none to give, the dropped blocks
+// of this lane's open Scratch objects go back to it first.
+void* Lane::dalloc(size_t bytes) {
+  void* p = ctx->dalloc(bytes);
+  for (Scratch* s = static_cast<Scratch*>(scratch); !p && s; s = static_cast<Scratch*>(s->outer))
+    if (s->flush()) p = ctx->dalloc(bytes);
+  return p;
+}
 
 int Lane::make_empty_result(int64_t n, rtg_csr* out, uint64_t handle) {
   void* mem = dalloc(sizeof(int64_t) * (size_t)(n + 1));
@@ -1363,7 +1400,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
       if (most <= seg_cap) {
         if (cand_total + total > cap) {
           const uint64_t want = cand_total + total;
-          uint64_t* grown = static_cast<uint64_t*>(dalloc(sizeof(uint64_t) * std::max<uint64_t>(want, 1)));
+          uint64_t* grown = S.get<uint64_t>(std::max<uint64_t>(want, 1));
           if (!grown) return RTG_ENOMEM;
           if (cand && cand_total)
             if ((rc = hip_fail(hipMemcpyAsync(grown, cand, sizeof(uint64_t) * cand_total,
@@ -1371,7 +1408,6 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
                                "grow candidates")))
               return rc;
           if (cand) S.drop(cand);
-          S.held.push_back(grown);
           cand = grown;
           cap = want;
         }

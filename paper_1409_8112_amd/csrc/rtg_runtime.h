@@ -138,6 +138,7 @@ struct Lane {
   Ctx* ctx = nullptr;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  void* scratch = nullptr;     // the innermost open scratch set of this lane (rtg_host.cpp)
   void* host_stage = nullptr;  // pinned staging for read-backs
   size_t host_stage_bytes = 0;
   void* host_up = nullptr;     // pinned staging for batched uploads
