@@ -92,8 +92,7 @@ def bench_batched(ctx, count: int, reps: int = 3) -> dict:
     def batched_once():
         res = ctx.all_pairs_batched(queries)
         pairs = sum(r.pairs for r in res)
-        for r in res:
-            r.release()
+        ctx.release_many(res)
         return pairs
 
     batched_once()  # warm-up

@@ -216,6 +216,12 @@ int rtg_poll(rtg_ctx *ctx, uint64_t ticket, rtg_csr *out);
 /* Free a result's or an index's device memory.  Errors: RTG_ENOENT. */
 int rtg_release(rtg_ctx *ctx, uint64_t handle);
 
+/* rtg_release for handles[0..count) (host array, read only) in one call,
+ * e.g. the results of one rtg_all_pairs_batched.  Every known handle is
+ * released; RTG_ENOENT if any was unknown.  Errors: RTG_EINVAL (ctx NULL,
+ * count < 0, or handles NULL with count > 0), RTG_ENOENT. */
+int rtg_release_many(rtg_ctx *ctx, const uint64_t *handles, int32_t count);
+
 /* Query mode (an r-NN index of one point set; Sec. V suggests answering
  * queries from the grids).  rtg_index_build sorts the k grids of `points`
  * once -- the transforms, cell keys and sort of rtg_all_pairs -- and keeps

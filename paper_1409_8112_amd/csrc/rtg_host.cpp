@@ -422,6 +422,27 @@ uint64_t Ctx::keep_result(uint64_t h, void* mem, int64_t n, int64_t nnz, int64_t
   return h;
 }
 
+int Ctx::release_many(const uint64_t* handles, int32_t count) {
+  int rc = RTG_OK;
+  std::lock_guard<std::mutex> lk(amu);
+  for (int32_t i = 0; i < count; ++i) {
+    auto it = results.find(handles[i]);
+    if (it != results.end()) {
+      arena->release(it->second.mem);
+      results.erase(it);
+      continue;
+    }
+    auto ix = indexes.find(handles[i]);
+    if (ix == indexes.end()) {
+      rc = RTG_ENOENT;
+      continue;
+    }
+    for (void* p : ix->second->blocks) arena->release(p);
+    indexes.erase(ix);
+  }
+  return rc;
+}
+
 int Ctx::release(uint64_t h) {
   std::lock_guard<std::mutex> lk(amu);
   auto it = results.find(h);
@@ -2315,6 +2336,11 @@ int rtg_all_pairs_with_transforms(rtg_ctx* ctx, const float* points, int64_t n, 
 int rtg_release(rtg_ctx* ctx, uint64_t handle) {
   if (!ctx) return RTG_EINVAL;
   return reinterpret_cast<Ctx*>(ctx)->release(handle);
+}
+
+int rtg_release_many(rtg_ctx* ctx, const uint64_t* handles, int32_t count) {
+  if (!ctx || count < 0 || (count > 0 && !handles)) return RTG_EINVAL;
+  return reinterpret_cast<Ctx*>(ctx)->release_many(handles, count);
 }
 
 int rtg_index_build(rtg_ctx* ctx, const float* points, int64_t n, int32_t d, double r, int32_t k,

@@ -229,6 +229,7 @@ struct Ctx {
   uint64_t keep_result(uint64_t h, void* mem, int64_t n, int64_t nnz, int64_t pairs,
                        int64_t* row_ptr, int32_t* col);
   int release(uint64_t handle);
+  int release_many(const uint64_t* handles, int32_t count);
   bool find_result(uint64_t handle, rtg_csr* out);
 
   int all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha,

@@ -99,6 +99,7 @@ def lib() -> ctypes.CDLL:
                 "rtg_submit": [vp, ctypes.POINTER(rtg_query), ctypes.POINTER(u64)],
                 "rtg_poll": [vp, u64, ctypes.POINTER(rtg_csr)],
                 "rtg_release": [vp, u64],
+                "rtg_release_many": [vp, ctypes.POINTER(u64), i32],
                 "rtg_make_transforms": [u64, i32, i32, u32, vp, vp],
                 "rtg_choose_params": [i32, f64, f64, u32, ctypes.POINTER(i32),
                                       ctypes.POINTER(f64), ctypes.POINTER(f64)],
@@ -301,7 +302,12 @@ class Context:
         outs = (rtg_csr * max(nq, 1))()
         _check(lib().rtg_all_pairs_batched(self.h, qs.ctypes.data_as(ctypes.POINTER(rtg_query)),
                                            nq, outs), "rtg_all_pairs_batched")
-        return [self._result(outs[i]) for i in range(nq)]
+        if nq == 0:
+            return []
+        # the output table read column by column (one numpy pass per field)
+        arr = np.frombuffer(outs, dtype=np.dtype(rtg_csr), count=nq)
+        cols = [arr[f].tolist() for f in ("handle", "n", "nnz", "pairs", "row_ptr", "col")]
+        return [Result(self, *t) for t in zip(*cols)]
 
     def rtg_submit(self, points, r: float, k: int, alpha: float, seed: int,
                    flags: int = 0) -> int | None:
@@ -340,6 +346,18 @@ class Context:
 
     def rtg_release(self, handle: int) -> None:
         _check(lib().rtg_release(self.h, handle), "rtg_release")
+
+    def rtg_release_many(self, results) -> None:
+        """Release every not yet released Result of the list in one call."""
+        todo = [r for r in results if not r.released]
+        if not todo:
+            return
+        hs = np.array([r.handle for r in todo], dtype=np.uint64)
+        rc = lib().rtg_release_many(self.h, hs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                    len(hs))
+        for r in todo:
+            r.released = True
+        _check(rc, "rtg_release_many")
 
     def rtg_index_build(self, points, r: float, k: int, alpha: float, seed: int,
                         flags: int = 0) -> int:
@@ -387,6 +405,7 @@ class Context:
     all_pairs = rtg_all_pairs
     all_pairs_with_transforms = rtg_all_pairs_with_transforms
     all_pairs_batched = rtg_all_pairs_batched
+    release_many = rtg_release_many
     submit = rtg_submit
     poll = rtg_poll
     release = rtg_release

@@ -61,6 +61,7 @@ def test_create_rejects_bad_arguments_without_touching_a_device():
     assert rtg.lib().rtg_create(None, 0, None, 1 << 30, None) == rtg.EINVAL
     assert rtg.lib().rtg_create(ctypes.byref(h), 0, None, 1024, None) == rtg.EINVAL
     assert rtg.lib().rtg_all_pairs(None, None, 0, 3, 0.1, 1, 2.0, 0, 0, None) == rtg.EINVAL
+    assert rtg.lib().rtg_release_many(None, None, 0) == rtg.EINVAL
 
 
 def test_binding_refuses_to_run_without_a_gpu():

@@ -207,3 +207,23 @@ def _small_ctx(arena_bytes, **env):
                 del os.environ[k]
             else:
                 os.environ[k] = v
+
+
+def test_release_many(ctx):
+    """One call releases a batch's results; releasing them again is
+    RTG_ENOENT, and a negative count or a missing array is RTG_EINVAL."""
+    import ctypes
+    from paper_1409_8112_amd import rtg
+    qs = _queries(9, 12, dims=(3, 6), n_lo=100, n_hi=3000)
+    res = ctx.all_pairs_batched([dict(q, points=_dev(q["points"])) for q in qs])
+    handles = np.array([r.handle for r in res], dtype=np.uint64)
+    ctx.release_many(res)
+    assert all(r.released for r in res)
+    ctx.release_many(res)  # nothing left to release: no call
+    ptr = handles.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    assert rtg.lib().rtg_release_many(ctx.h, ptr, len(handles)) == rtg.ENOENT
+    assert rtg.lib().rtg_release_many(ctx.h, ptr, -1) == rtg.EINVAL
+    assert rtg.lib().rtg_release_many(ctx.h, None, 3) == rtg.EINVAL
+    assert rtg.lib().rtg_release_many(ctx.h, None, 0) == rtg.OK
+    # the context still works and the memory came back
+    _check(qs[:4], _run(ctx, qs[:4]))
