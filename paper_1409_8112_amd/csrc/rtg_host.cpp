@@ -364,7 +364,7 @@ Ctx::Ctx(int dev) : device(dev) {
   const char* bc = std::getenv("RTG_BUCKET_CAP");
   if (const char* e = std::getenv("RTG_BUCKET_BLOCKS"))
     bucket_blocks = (uint32_t)std::max(1, std::min(4096, std::atoi(e)));
-  if (const char* e = std::getenv("RTG_BATCH_LANES")) batch_lanes = std::atoi(e) > 1 ? 2 : 1;
+  if (const char* e = std::getenv("RTG_BATCH_LANES")) batch_lanes = std::max(1, std::min(3, std::atoi(e)));
   if (const char* e = std::getenv("RTG_UNITS"))
     balanced_units = std::strcmp(e, "roundrobin") != 0;
   bucket_cap = kBucketMaxEntries;
@@ -376,7 +376,7 @@ Ctx::Ctx(int dev) : device(dev) {
 
 Ctx::~Ctx() {
   stop_server();
-  if (side) side->fini();
+  for (auto& L : side) L->fini();
   if (side_ready) (void)hipEventDestroy(side_ready);
   main.fini();
   if (own_arena && arena_mem) (void)hipFree(arena_mem);
@@ -1672,21 +1672,23 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   return RTG_OK;
 }
 
-// The second lane of the batched call, made with this context's device
-// current (as the request loop's lanes are).
-int Ctx::side_lane() {
-  if (side) return RTG_OK;
+// The extra lanes of the batched call (count of them), made with this
+// context's device current (as the request loop's lanes are).
+int Ctx::side_lanes(int count) {
+  if ((int)side.size() >= count) return RTG_OK;
   if (hipSetDevice(device) != hipSuccess) return RTG_EDEVICE;
-  std::unique_ptr<Lane> L(new (std::nothrow) Lane());
-  if (!L) return RTG_ENOMEM;
-  int rc = L->init(this, nullptr, true);
-  if (!rc && hipEventCreateWithFlags(&side_ready, hipEventDisableTiming) != hipSuccess)
-    rc = RTG_EDEVICE;
-  if (rc) {
-    L->fini();
-    return rc;
+  if (!side_ready && hipEventCreateWithFlags(&side_ready, hipEventDisableTiming) != hipSuccess)
+    return RTG_EDEVICE;
+  while ((int)side.size() < count) {
+    std::unique_ptr<Lane> L(new (std::nothrow) Lane());
+    if (!L) return RTG_ENOMEM;
+    const int rc = L->init(this, nullptr, true);
+    if (rc) {
+      L->fini();
+      return rc;
+    }
+    side.push_back(std::move(L));
   }
-  side = std::move(L);
   return RTG_OK;
 }
 
@@ -1775,11 +1777,14 @@ int Ctx::batched(const rtg_query* q, int32_t nq, rtg_csr* outs) {
   // memory beside the other lane's pass runs again alone afterwards.
   constexpr int kNotRun = 1 << 20;
   std::vector<int> brc(batches.size(), kNotRun);
-  if (batches.size() >= 2 && batch_lanes > 1 && side_lane() == RTG_OK) {
-    if ((rc = hip_fail(hipEventRecord(side_ready, main.stream), "hipEventRecord")) ||
-        (rc = hip_fail(hipStreamWaitEvent(side->stream, side_ready, 0), "hipStreamWaitEvent")))
-      return undo(rc);
-    side->timing_mask = main.timing_mask;
+  const int extra = (int)std::min<size_t>(batch_lanes - 1, batches.size() - 1);
+  if (batches.size() >= 2 && extra > 0 && side_lanes(extra) == RTG_OK) {
+    if ((rc = hip_fail(hipEventRecord(side_ready, main.stream), "hipEventRecord"))) return undo(rc);
+    for (int l = 0; l < extra; ++l) {
+      if ((rc = hip_fail(hipStreamWaitEvent(side[l]->stream, side_ready, 0), "hipStreamWaitEvent")))
+        return undo(rc);
+      side[l]->timing_mask = main.timing_mask;
+    }
     std::atomic<size_t> next{0};
     std::atomic<bool> failed{false};
     auto work = [&](Lane& L, rtg_stats& s) {
@@ -1794,14 +1799,16 @@ int Ctx::batched(const rtg_query* q, int32_t nq, rtg_csr* outs) {
           failed = true;
       }
     };
-    rtg_stats st2{};
-    std::thread t([&] {
-      (void)hipSetDevice(device);
-      work(*side, st2);
-    });
+    std::vector<rtg_stats> sst(extra, rtg_stats{});
+    std::vector<std::thread> threads;
+    for (int l = 0; l < extra; ++l)
+      threads.emplace_back([&, l] {
+        (void)hipSetDevice(device);
+        work(*side[l], sst[l]);
+      });
     work(main, st);
-    t.join();
-    add_stats(st, st2);
+    for (auto& t : threads) t.join();
+    for (const auto& s2 : sst) add_stats(st, s2);
     for (int r : brc)
       if (r != RTG_OK && r != RTG_ENOMEM && r != kNotRun) return undo(r);
   }

@@ -204,13 +204,14 @@ struct Ctx {
   // every bucket; more blocks keep more waves waiting on LDS atomics at once)
   uint32_t bucket_blocks = 256;
   Lane main;          // the caller's stream: blocking calls
-  // A second lane for rtg_all_pairs_batched: two batches run at once, so one
-  // pass's host work and waits overlap the other's kernels (RTG_BATCH_LANES=1:
-  // one at a time).  Made on first use.
-  int batch_lanes = 2;
-  std::unique_ptr<Lane> side;
+  // More lanes for rtg_all_pairs_batched: batches run batch_lanes at a time
+  // (the caller's lane and batch_lanes - 1 more), so one pass's host work and
+  // waits overlap the others' kernels (RTG_BATCH_LANES, 1 to 3).  Made on
+  // first use.
+  int batch_lanes = 3;
+  std::vector<std::unique_ptr<Lane>> side;
   hipEvent_t side_ready = nullptr;  // the caller's stream reached the call
-  int side_lane();
+  int side_lanes(int count);
   rtg_stats stats{};  // of the last blocking call
   std::mutex mu;      // one blocking call at a time
   std::mutex amu;     // arena, results, handles

@@ -168,9 +168,9 @@ def test_result_views_made_on_first_use(ctx):
 
 
 def test_two_lanes_in_a_small_budget():
-    """Batches run two at a time; in a budget that holds about two passes a
-    pass may run out of memory beside the other and runs again alone. Every
-    result equals the oracle's, and equals one lane's."""
+    """Batches run several at a time; in a budget that holds about two passes
+    a pass may run out of memory beside the others and runs again alone.
+    Every result equals the oracle's, and equals one lane's."""
     qs = []
     for q in range(6):
         n = 40000 - 1500 * q
