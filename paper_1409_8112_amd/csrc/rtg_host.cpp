@@ -752,7 +752,12 @@ struct Scratch {
   void drop(void* p) {
     for (size_t i = 0; i < held.size(); ++i)
       if (held[i].first == p) {
-        pool.push_back(held[i]);
+        if (c.keep_drops) {
+          pool.push_back(held[i]);
+        } else {
+          (void)hipStreamSynchronize(c.stream);
+          c.dfree(p);
+        }
         held.erase(held.begin() + (std::ptrdiff_t)i);
         return;
       }

@@ -139,6 +139,10 @@ struct Lane {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   void* scratch = nullptr;     // the innermost open scratch set of this lane (rtg_host.cpp)
+  // Blocks a pass drops are kept for the pass's own later allocations (no
+  // wait); off for the request loop's lanes, whose admission reads the
+  // arena's free bytes and needs them back at once.
+  bool keep_drops = true;
   void* host_stage = nullptr;  // pinned staging for read-backs
   size_t host_stage_bytes = 0;
   void* host_up = nullptr;     // pinned staging for batched uploads

@@ -92,6 +92,7 @@ int Server::start(int nlanes) {
   for (int i = 0; i < nlanes; ++i) {
     lanes.emplace_back(new Lane());
     if ((rc = lanes.back()->init(&c, nullptr, true))) return rc;
+    lanes.back()->keep_drops = false;  // admission reads the free bytes
   }
   reserved.assign(nlanes, 0);
   for (int i = 0; i < nlanes; ++i) workers.emplace_back(&Server::work, this, i);
