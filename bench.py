@@ -370,9 +370,9 @@ def main(argv=None) -> int:
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(instances and requests shard across GPUs without communication; see the design "
-              "notes)", file=sys.stderr)
+        print(f"bench.py: measures one GPU; --gpus {args.gpus} is not supported "
+              "(instances and requests would shard across GPUs without communication)",
+              file=sys.stderr)
         return 2
 
     import torch

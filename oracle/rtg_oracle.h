@@ -26,8 +26,7 @@
  * Parameter names: the paper's m (number of grids) is `k` here and its
  * cell-size factor c~ is `alpha`; the grid cell side is alpha * r.
  *
- * Readings where the paper is silent (each one is listed in the design notes
- * of the repository):
+ * Readings where the paper is silent:
  *   - "at most r" is taken literally: a pair is reported iff d^2 <= r*r, with
  *     d^2 summed in FP64 from the FP32 coordinates in axis order, no FMA;
  *   - a cell is half-open: kappa_j = floor(y_j);
