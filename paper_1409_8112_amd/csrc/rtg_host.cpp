@@ -1284,9 +1284,16 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     uint32_t* sscr = run_scr + 2 * nt + 2;
     kbegin(RTG_K_CELLS);
     launch_run_count(skeys, N, idx_bits, hcnt, tcnt, stream);
-    scan_exclusive_u32(hcnt, hcnt, nt, tot, sscr, stream);
-    scan_exclusive_u32(tcnt, tcnt, nt, tot + 1, sscr, stream);
-    launch_run_write(skeys, N, idx_bits, hcnt, tcnt, cstart, cend, stream);
+    // up to 8192 tiles the writing kernel adds up the earlier tiles' counts
+    // itself (and clears the member counter of the cell-work kernel)
+    const bool counts_direct = nt >= 1 && nt <= 8192;
+    if (counts_direct) {
+      launch_run_write(skeys, N, idx_bits, hcnt, tcnt, cstart, cend, tot, counters + 3, stream);
+    } else {
+      scan_exclusive_u32(hcnt, hcnt, nt, tot, sscr, stream);
+      scan_exclusive_u32(tcnt, tcnt, nt, tot + 1, sscr, stream);
+      launch_run_write(skeys, N, idx_bits, hcnt, tcnt, cstart, cend, nullptr, nullptr, stream);
+    }
     kend(RTG_K_CELLS, 16.0 * (double)N);
     uint64_t got[8];
     Gather g1;
@@ -1302,7 +1309,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     uint32_t units_total = 0;
     if (ncells_h) {
       kbegin(RTG_K_CELLS);
-      launch_fill_u64(reinterpret_cast<uint64_t*>(counters) + 3, 0ull, 1, stream);
+      if (!counts_direct) launch_fill_u64(reinterpret_cast<uint64_t*>(counters) + 3, 0ull, 1, stream);
       launch_cell_work(cstart, cend, ncells_h, ctx->cell_unit_tiles, units, tests_c,
                        counters + 3, stream);
       scan_exclusive_u32(units, units, ncells_h, scan32 + s64, scan32, stream);

@@ -170,9 +170,12 @@ int radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* val
 void launch_run_count(const uint64_t* keys, size_t count, int shift, uint32_t* head_cnt,
                       uint32_t* tail_cnt, hipStream_t s);
 // Writes start[c] / end[c] of run c (ordered by position) given the scanned
-// per-tile offsets.
+// per-tile offsets; or, with tot, given the raw per-tile counts (the kernel
+// adds up the earlier tiles' counts itself, writes tot[0] = runs (heads),
+// tot[1] = tails, and clears *zero if given).
 void launch_run_write(const uint64_t* keys, size_t count, int shift, const uint32_t* head_off,
-                      const uint32_t* tail_off, uint32_t* start, uint32_t* end, hipStream_t s);
+                      const uint32_t* tail_off, uint32_t* start, uint32_t* end, uint32_t* tot,
+                      unsigned long long* zero, hipStream_t s);
 // units[c] = work units of run c (see UnitDesc), tests[c] = L(L-1)/2, and
 // *members += sum of L, for c < ncells.
 void launch_cell_work(const uint32_t* start, const uint32_t* end, uint32_t ncells,

@@ -765,13 +765,20 @@ __global__ __launch_bounds__(kBlock) void k_run_count(const uint64_t* __restrict
   }
 }
 
+// head_off / tail_off: each tile's scanned offsets, or with FROM_COUNTS the
+// raw per-tile counts, which each block then adds up for the tiles before it
+// itself (the last block writes the totals to tot; block 0 clears *zero).
+template <bool FROM_COUNTS>
 __global__ __launch_bounds__(kBlock) void k_run_write(const uint64_t* __restrict__ keys,
                                                       size_t count, int shift,
                                                       const uint32_t* __restrict__ head_off,
                                                       const uint32_t* __restrict__ tail_off,
                                                       uint32_t* __restrict__ start,
-                                                      uint32_t* __restrict__ end) {
+                                                      uint32_t* __restrict__ end,
+                                                      uint32_t* __restrict__ tot,
+                                                      unsigned long long* __restrict__ zero) {
   __shared__ uint32_t sh[kWaves], st[kWaves];
+  __shared__ uint32_t wsum[kWaves];
   const uint32_t lane = lane_id();
   const int w = threadIdx.x >> 6;
   const size_t wave_base = (size_t)blockIdx.x * kTile + (size_t)w * (kTile / kWaves);
@@ -789,7 +796,29 @@ __global__ __launch_bounds__(kBlock) void k_run_write(const uint64_t* __restrict
     st[w] = tc;
   }
   __syncthreads();
-  uint32_t hbase = head_off[blockIdx.x], tbase = tail_off[blockIdx.x];
+  uint32_t hbase, tbase;
+  if (FROM_COUNTS) {
+    uint32_t ph = 0, pt = 0;
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kBlock) {
+      ph += head_off[b];
+      pt += tail_off[b];
+    }
+    block_exclusive_scan<uint32_t>(ph, wsum, hbase);
+    block_exclusive_scan<uint32_t>(pt, wsum, tbase);
+    if (threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) {
+      uint32_t a = 0, b = 0;
+      for (int q = 0; q < kWaves; ++q) {
+        a += sh[q];
+        b += st[q];
+      }
+      tot[0] = hbase + a;
+      tot[1] = tbase + b;
+    }
+    if (zero && threadIdx.x == 0 && blockIdx.x == 0) *zero = 0ull;
+  } else {
+    hbase = head_off[blockIdx.x];
+    tbase = tail_off[blockIdx.x];
+  }
   for (int q = 0; q < w; ++q) {
     hbase += sh[q];
     tbase += st[q];
@@ -2690,10 +2719,16 @@ void launch_run_count(const uint64_t* keys, size_t count, int shift, uint32_t* h
 }
 
 void launch_run_write(const uint64_t* keys, size_t count, int shift, const uint32_t* head_off,
-                      const uint32_t* tail_off, uint32_t* start, uint32_t* end, hipStream_t s) {
+                      const uint32_t* tail_off, uint32_t* start, uint32_t* end, uint32_t* tot,
+                      unsigned long long* zero, hipStream_t s) {
   if (!count) return;
-  hipLaunchKernelGGL(k_run_write, dim3(tiles_for(count)), dim3(kBlock), 0, s, keys, count, shift,
-                     head_off, tail_off, start, end);
+  if (tot)
+    hipLaunchKernelGGL(k_run_write<true>, dim3(tiles_for(count)), dim3(kBlock), 0, s, keys, count,
+                       shift, head_off, tail_off, start, end, tot, zero);
+  else
+    hipLaunchKernelGGL(k_run_write<false>, dim3(tiles_for(count)), dim3(kBlock), 0, s, keys, count,
+                       shift, head_off, tail_off, start, end, (uint32_t*)nullptr,
+                       (unsigned long long*)nullptr);
 }
 
 void launch_cell_work(const uint32_t* start, const uint32_t* end, uint32_t ncells,
