@@ -1820,6 +1820,10 @@ int Ctx::batched(const rtg_query* q, int32_t nq, rtg_csr* outs) {
       });
     work(main, st);
     for (auto& t : threads) t.join();
+    // The extra lanes go with the call: their streams would otherwise keep
+    // hardware queues (a few per process) that the request loop's lanes need.
+    for (auto& L : side) L->fini();
+    side.clear();
     for (const auto& s2 : sst) add_stats(st, s2);
     for (int r : brc)
       if (r != RTG_OK && r != RTG_ENOMEM && r != kNotRun) return undo(r);

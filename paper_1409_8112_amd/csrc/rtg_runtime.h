@@ -210,8 +210,8 @@ struct Ctx {
   Lane main;          // the caller's stream: blocking calls
   // More lanes for rtg_all_pairs_batched: batches run batch_lanes at a time
   // (the caller's lane and batch_lanes - 1 more), so one pass's host work and
-  // waits overlap the others' kernels (RTG_BATCH_LANES, 1 to 3).  Made on
-  // first use.
+  // waits overlap the others' kernels (RTG_BATCH_LANES, 1 to 3).  Made for
+  // each call that has several batches and released at its end.
   int batch_lanes = 3;
   std::vector<std::unique_ptr<Lane>> side;
   hipEvent_t side_ready = nullptr;  // the caller's stream reached the call
