@@ -1284,9 +1284,10 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     uint32_t* sscr = run_scr + 2 * nt + 2;
     kbegin(RTG_K_CELLS);
     launch_run_count(skeys, N, idx_bits, hcnt, tcnt, stream);
-    // up to 8192 tiles the writing kernel adds up the earlier tiles' counts
-    // itself (and clears the member counter of the cell-work kernel)
-    const bool counts_direct = nt >= 1 && nt <= 8192;
+    // up to 2048 tiles the writing kernel adds up the earlier tiles' counts
+    // itself (and clears the member counter of the cell-work kernel); its
+    // reads grow as the square of the tiles, so more take the scans
+    const bool counts_direct = nt >= 1 && nt <= 2048;
     if (counts_direct) {
       launch_run_write(skeys, N, idx_bits, hcnt, tcnt, cstart, cend, tot, counters + 3, stream);
     } else {
