@@ -56,6 +56,9 @@ struct Gather {
   }
 };
 void launch_gather(const Gather& g, uint64_t* dst, hipStream_t s);
+// rec[i][0..d) = rows[i][0..d), rec[i][d..rs) = 0 (padding, then the
+// signature word in the last two floats), for i < n.
+void launch_records(const float* rows, int64_t n, int d, int rs, float* rec, hipStream_t s);
 
 // --- batches ------------------------------------------------------------------
 // A batch is a set of instances (queries) of the same dimension d run through
@@ -113,7 +116,7 @@ struct KeysArgs {
   uint32_t* vals;
   uint32_t* err;
   uint64_t* sig;     // neighbourhood signatures (see PairFilter), or null
-  int sig_W, sig_b, sig_gpw;
+  int sig_stride, sig_b, sig_gpw;  // sig_stride: words from one point's signature to the next
   int idx_bits;
 };
 void launch_keys(const KeysArgs& a, hipStream_t s);
@@ -232,6 +235,9 @@ struct PairsArgs {
   const uint32_t* sidx;    // sorted point indices (null when in skeys)
   int idx_bits;            // > 0: point index in the low idx_bits of skeys
   const float* pts;        // batch points, row-major [npts][d] (FP64 band re-test)
+  const float* rows;       // tile loads (direct): point i's coordinates at rows + i row_stride
+  int row_stride;
+  int sig_stride;          // words from point i's signature (sigp) to point i + 1's
   int d;
   const PairTest* tests;   // per instance
   int W, g, gpw;           // signature layout

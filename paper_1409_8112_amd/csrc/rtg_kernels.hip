@@ -265,7 +265,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(const InstDesc* __restrict__ in
                                                  const KeyLayout* __restrict__ layout,
                                                  uint64_t* __restrict__ keys,
                                                  uint32_t* __restrict__ vals, uint32_t* err,
-                                                 uint64_t* __restrict__ sig, int sig_W,
+                                                 uint64_t* __restrict__ sig, int sig_stride,
                                                  int sig_b, int sig_gpw, int idx_bits) {
   const int d = D > 0 ? D : d_rt;
   const uint32_t q = block_instance(inst, m, blockIdx.x);
@@ -307,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(const InstDesc* __restrict__ in
       // the point owns its row: earlier passes' bits are read back and kept
       const int w = t / sig_gpw;
       if (w != sw) {
-        if (sw >= 0) sig[(size_t)g * sig_W + sw] |= sword;
+        if (sw >= 0) sig[(size_t)g * sig_stride + sw] |= sword;
         sword = 0;
         sw = w;
       }
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(const InstDesc* __restrict__ in
       vals[pos] = (uint32_t)g;
     }
   }
-  if (sig && sw >= 0) sig[(size_t)g * sig_W + sw] |= sword;
+  if (sig && sw >= 0) sig[(size_t)g * sig_stride + sw] |= sword;
   if (bad) atomicOr(err, 1u);
 }
 
@@ -938,7 +938,7 @@ __device__ __forceinline__ bool zero_group(uint64_t x, int n, const PairsArgs& P
 
 // Signature word q of the point at sorted position p with index i.
 __device__ __forceinline__ uint64_t sig_word(const PairsArgs& P, int q, uint32_t p, uint32_t i) {
-  return P.direct ? P.sigp[(size_t)i * P.W + q] : P.ssig[(size_t)q * P.N + p];
+  return P.direct ? P.sigp[(size_t)i * P.sig_stride + q] : P.ssig[(size_t)q * P.N + p];
 }
 
 // Whether two points within r shared a cell under a grid t < tcell; word q of
@@ -986,12 +986,12 @@ __device__ __forceinline__ void load_tile(const PairsArgs& P, uint32_t p0, uint3
   const uint32_t p = p0 + lane;
   R.idx = ok ? point_at(P, p) : 0u;
   if (P.direct) {
-    const float* row = P.pts + (size_t)R.idx * P.d;
+    const float* row = P.rows + (size_t)R.idx * P.row_stride;
 #pragma unroll
     for (int l = 0; l < D; ++l) R.c[l] = (ok && l < P.d) ? row[l] : 0.0f;
 #pragma unroll
     for (int q = 0; q < kSigWords; ++q)
-      R.sw[q] = (ok && q < nw) ? P.sigp[(size_t)R.idx * P.W + q] : 0ull;
+      R.sw[q] = (ok && q < nw) ? P.sigp[(size_t)R.idx * P.sig_stride + q] : 0ull;
   } else {
 #pragma unroll
     for (int l = 0; l < D; ++l) R.c[l] = (ok && l < P.d) ? P.spts[(size_t)l * P.N + p] : 0.0f;
@@ -2418,6 +2418,17 @@ __global__ void k_gather(Gather g, uint64_t* __restrict__ dst) {
                            : (uint64_t)*static_cast<const uint32_t*>(g.src[q]);
 }
 
+// Point records for tile loads: the coordinates, then zeros up to rs floats
+// (the last two hold the point's signature word, written by the key kernel).
+__global__ void k_records(const float* __restrict__ rows, int64_t n, int d, int rs,
+                          float* __restrict__ rec) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float* r = rec + (size_t)i * rs;
+  for (int l = 0; l < d; ++l) r[l] = rows[(size_t)i * d + l];
+  for (int l = d; l < rs; ++l) r[l] = 0.0f;
+}
+
 // out[q] = row_ptr[first point of instance q] for q < m, out[m] = row_ptr[npts].
 __global__ void k_rowptr_at(const InstDesc* __restrict__ inst, uint32_t m,
                             const int64_t* __restrict__ row_ptr, int64_t npts,
@@ -2529,7 +2540,7 @@ template <int D>
 static void keys_dispatch(const KeysArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_keys<D>, dim3(a.nblocks), dim3(kBlock), 0, s, a.inst, a.m, a.d, a.npts,
                      a.soa, a.sa, a.sb, a.segs, a.R, a.u, a.klo, a.layout, a.keys, a.vals, a.err,
-                     a.sig, a.sig_W, a.sig_b, a.sig_gpw, a.idx_bits);
+                     a.sig, a.sig_stride, a.sig_b, a.sig_gpw, a.idx_bits);
 }
 
 void launch_keys(const KeysArgs& a, hipStream_t s) {
@@ -3015,6 +3026,12 @@ void launch_u32_to_u64(const uint32_t* src, size_t count, uint64_t* dst, hipStre
 void launch_gather(const Gather& g, uint64_t* dst, hipStream_t s) {
   if (g.count <= 0) return;
   hipLaunchKernelGGL(k_gather, dim3(1), dim3(64), 0, s, g, dst);
+}
+
+void launch_records(const float* rows, int64_t n, int d, int rs, float* rec, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_records, dim3(grid_for((size_t)n)), dim3(kBlock), 0, s, rows, n, d, rs,
+                     rec);
 }
 
 void launch_rowptr_at(const InstDesc* inst, uint32_t m, const int64_t* row_ptr, int64_t npts,
