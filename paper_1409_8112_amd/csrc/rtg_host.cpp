@@ -1360,7 +1360,9 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
                         : (uint32_t)std::min<uint64_t>(
                               kMaxPairBlocks,
                               std::max<uint64_t>(2048, tests_total / (90000ull * kWaves) + 1));
-    if (balanced) {
+    // (with no more units than waves every wave takes at most one either way,
+    // and the every-n-th dealing needs no ranges)
+    if (balanced && units_total > pair_waves(pa)) {
       // each wave takes a contiguous run of units with an equal share of the
       // tile pairs, so that no wave (and no block) runs far longer than the rest
       scan_exclusive_u64(uwork, uwork, units_total, uscan + su, uscan, stream);
