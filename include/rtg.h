@@ -208,8 +208,12 @@ int rtg_all_pairs_batched(rtg_ctx *ctx, const rtg_query *queries, int32_t nq, rt
  * memory fits the budget and runs every admitted request in the next pass of
  * the batched pipeline.  rtg_poll returns RTG_OK with the result once done
  * (the result then belongs to the caller's handle), RTG_EAGAIN while pending,
- * or the request's error.  Errors: RTG_EINVAL, RTG_ENOMEM (larger than the
- * whole budget), RTG_ENOENT (unknown ticket). */
+ * or the request's error.  Finished results count against the budget until
+ * released: a request that does not fit beside them stays pending until the
+ * caller releases some (or other requests' staged points are dropped), and
+ * fails with RTG_ENOMEM only when it does not fit with nothing else held.
+ * Errors: RTG_EINVAL, RTG_ENOMEM (its working-set bound plus its points
+ * exceed the whole budget), RTG_ENOENT (unknown ticket). */
 int rtg_submit(rtg_ctx *ctx, const rtg_query *query, uint64_t *ticket);
 int rtg_poll(rtg_ctx *ctx, uint64_t ticket, rtg_csr *out);
 

@@ -237,6 +237,40 @@ int min_field_bits(double alpha) {
   return 33;
 }
 
+uint64_t cand_per_key(uint32_t flags) {
+  // First owner: every pair once, about nu / (2k) per key at nu neighbours.
+  // Sort-unique and bitmap keep every grid's repeats until the union.
+  return (flags & (RTG_DEDUP_SORT | RTG_DEDUP_BITMAP)) ? 8 : 4;
+}
+
+size_t Ctx::pass_bytes_bound(int64_t n, int32_t d, int32_t k, double alpha, uint32_t flags) const {
+  const double N = (double)n * (double)k;
+  const int b = std::min(32, min_field_bits(alpha));
+  const int g = d * b;
+  const int gpw = g <= 64 ? 64 / g : 1;
+  const double W = (double)((k + gpw - 1) / gpw);
+  const double rs = (double)((d + 2 + 3) & ~3);
+  // per point: SoA and concatenated rows, bounding-box partials, point
+  // records or signature rows
+  double bytes = (double)n * (8.0 * d + d / 32.0 + std::max(4.0 * rs, 8.0 * W) + 16.0);
+  // per key: two key buffers and two value buffers (worst case), cell
+  // starts / ends / unit counts (6), unit descriptors (16.5), cell tests (4),
+  // unit work and its scan (4.2 + 0.1), sort and scan scratch (1)
+  bytes += N * (16.0 + 8.0 + 6.0 + 16.5 + 4.0 + 4.3 + 1.0);
+  if (!gather_direct) bytes += N * (4.0 * d + 8.0 * W);
+  // candidates: the pair kernels' segments (a quarter to spare) and the
+  // compacted copy, then the list build (entries and the result) after the
+  // key buffers are gone -- the larger of the two phases
+  const double C = (double)cand_per_key(flags) * N;
+  bytes += std::max(8.0 * 1.25 * C + 8.0 * kCandSegments * 1024 + 8.0 * C,
+                    8.0 * C + 8.0 * C + 12.0 * 2.0 * C + 8.0 * (double)n);
+  if (flags & RTG_DEDUP_BITMAP)
+    bytes += std::min((double)kBitmapMaxBytes, (double)n * (double)(n - 1) / 16.0);
+  // transforms, descriptors, tables, alignment
+  bytes += 8.0 * k * d * (d + 2) + (double)(2 << 20);
+  return (size_t)bytes;
+}
+
 int plan_batch(int d, uint32_t m, const int64_t* k, const int64_t* n, const double* R,
                const double* u, const double* inv_c, const double* alpha, const float* lo,
                const float* hi, size_t budget_bytes, Packing& P) {
@@ -424,38 +458,36 @@ uint64_t Ctx::keep_result(uint64_t h, void* mem, int64_t n, int64_t nnz, int64_t
 
 int Ctx::release_many(const uint64_t* handles, int32_t count) {
   int rc = RTG_OK;
-  std::lock_guard<std::mutex> lk(amu);
-  for (int32_t i = 0; i < count; ++i) {
-    auto it = results.find(handles[i]);
-    if (it != results.end()) {
-      arena->release(it->second.mem);
-      results.erase(it);
-      continue;
+  bool any = false;
+  {
+    std::lock_guard<std::mutex> lk(amu);
+    for (int32_t i = 0; i < count; ++i) {
+      auto it = results.find(handles[i]);
+      if (it != results.end()) {
+        arena->release(it->second.mem);
+        results.erase(it);
+        any = true;
+        continue;
+      }
+      auto ix = indexes.find(handles[i]);
+      if (ix == indexes.end()) {
+        rc = RTG_ENOENT;
+        continue;
+      }
+      for (void* p : ix->second->blocks) arena->release(p);
+      indexes.erase(ix);
+      any = true;
     }
-    auto ix = indexes.find(handles[i]);
-    if (ix == indexes.end()) {
-      rc = RTG_ENOENT;
-      continue;
-    }
-    for (void* p : ix->second->blocks) arena->release(p);
-    indexes.erase(ix);
   }
+  if (any) wake_server();
   return rc;
 }
 
-int Ctx::release(uint64_t h) {
+int Ctx::release(uint64_t h) { return release_many(&h, 1); }
+
+bool Ctx::holds_results() {
   std::lock_guard<std::mutex> lk(amu);
-  auto it = results.find(h);
-  if (it != results.end()) {
-    arena->release(it->second.mem);
-    results.erase(it);
-    return RTG_OK;
-  }
-  auto ix = indexes.find(h);
-  if (ix == indexes.end()) return RTG_ENOENT;
-  for (void* p : ix->second->blocks) arena->release(p);
-  indexes.erase(ix);
-  return RTG_OK;
+  return !results.empty() || !indexes.empty();
 }
 
 bool Ctx::find_result(uint64_t h, rtg_csr* out) {
@@ -1162,7 +1194,8 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   uint32_t* cend = S.get<uint32_t>(max_cells);
   uint32_t* units = S.get<uint32_t>(max_cells);
   UnitDesc* udesc = S.get<UnitDesc>(max_units);
-  float* spts = S.get<float>((size_t)d * NB);  // unit points by sorted position
+  // unit points by sorted position: only when the pair kernels read a gathered copy
+  float* spts = ctx->gather_direct ? nullptr : S.get<float>((size_t)d * NB);
   uint64_t* tests_c = S.get<uint64_t>(max_cells);
   const size_t s64 = scan_scratch_elems(max_cells);
   uint64_t* scan64 = S.get<uint64_t>(s64 + 4);
@@ -1175,7 +1208,8 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   const size_t max_waves = (size_t)std::max<uint32_t>(ctx->pair_blocks, kMaxPairBlocks) * kWaves;
   uint32_t* wfirst = balanced ? S.get<uint32_t>(max_waves + 1) : nullptr;
   if (!keys || !keys_alt || (!idx_bits && (!vals || !vals_alt)) || !sort_scr || !run_scr ||
-      !cstart || !cend || !units || !udesc || !spts || !tests_c || !scan64 || !scan32 ||
+      !cstart || !cend || !units || !udesc || (!ctx->gather_direct && !spts) || !tests_c ||
+      !scan64 || !scan32 ||
       (balanced && (!uwork || !uscan || !wfirst)))
     return RTG_ENOMEM;
 
@@ -1217,16 +1251,20 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   float* rec = nullptr;
   int sig_stride = sig_W;
   if (first_owner) {
-    ssig = S.get<uint64_t>((size_t)sig_W * NB);
+    // signature words by sorted position: only for the gathered copy
+    if (!ctx->gather_direct) {
+      ssig = S.get<uint64_t>((size_t)sig_W * NB);
+      if (!ssig) return RTG_ENOMEM;
+    }
     if (sig_W == 1 && ctx->gather_direct && d <= 6) {
       rec = S.get<float>((size_t)npts * rs);
-      if (!rec || !ssig) return RTG_ENOMEM;
+      if (!rec) return RTG_ENOMEM;
       launch_records(pts_rows, npts, d, rs, rec, stream);
       sig = reinterpret_cast<uint64_t*>(rec + rs - 2);
       sig_stride = rs / 2;
     } else {
       sig = S.get<uint64_t>((size_t)npts * sig_W);
-      if (!sig || !ssig) return RTG_ENOMEM;
+      if (!sig) return RTG_ENOMEM;
       launch_fill_u64(sig, 0ull, (size_t)npts * sig_W, stream);
     }
   }
@@ -1351,6 +1389,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     pa.total_units = units_total;
     pa.spts = spts;
     pa.ssig = first_owner ? ssig : nullptr;
+    pa.first_owner = first_owner ? 1 : 0;
     pa.N = NB;
     pa.direct = ctx->gather_direct ? 1 : 0;
     // about 90k pair tests per wave: enough work to hide a wave's start, and
@@ -1404,20 +1443,20 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     // The guess: the tests times the share of a cell's pairs that can lie
     // within r -- for two points of one cube of side alpha r at most the
     // unit ball's volume over alpha^d (the cube's edges only lower it), with a
-    // quarter to spare and a sixteenth as the floor -- but at most 16 pairs
-    // per (point, grid) key: where few tested pairs lie within r (high d,
-    // clustered points) the tests overstate the pairs a thousandfold.
+    // quarter to spare and a sixteenth as the floor -- but at most
+    // cand_per_key pairs per (point, grid) key: where few tested pairs lie
+    // within r (high d, clustered points) the tests overstate the pairs a
+    // thousandfold.  The cap keeps the pass inside pass_bytes_bound.
     double share = 1.0 / 16;
     for (int32_t sg = sa; sg < sb; ++sg)
       share = std::max(share, 1.25 * ball_share(d, jobs[segs[sg].inst]->alpha));
-    // Where that would take more than a quarter of the free memory, or
-    // cannot be had, a sixteenth of the tests: an overflow then costs one
+    const uint64_t per_key = cand_per_key(flags);
+    const uint64_t guess = std::min<uint64_t>(
+        {tests_total, std::max<uint64_t>(1u << 16, (uint64_t)(share * (double)tests_total)),
+         per_key * N});
+    // Where that cannot be had, a quarter of it: an overflow then costs one
     // more pair pass.
-    const uint64_t lean = std::min<uint64_t>(
-        tests_total, std::max<uint64_t>(1u << 20, std::min<uint64_t>(tests_total / 16, 16ull * N)));
-    const uint64_t guess = std::max<uint64_t>(
-        lean, std::min<uint64_t>({tests_total, (uint64_t)(share * (double)tests_total), 16ull * N,
-                                  ctx->largest_free() / 40}));
+    const uint64_t lean = std::max<uint64_t>(1, guess / 4);
     uint64_t seg_cap = guess / nseg + guess / (4 * nseg) + 1024;
     for (int attempt = 0; attempt < 2; ++attempt) {
       uint64_t* sbuf = S.get<uint64_t>((size_t)nseg * seg_cap);

@@ -226,8 +226,9 @@ void launch_unit_fill(const uint32_t* start, const uint32_t* end, const uint32_t
 struct PairsArgs {
   const UnitDesc* units;
   uint32_t total_units;
-  const float* spts;       // [d][N] unit points' coordinates by sorted position
-  const uint64_t* ssig;    // [W][N] their signature words (null: no first-owner rule)
+  const float* spts;       // [d][N] unit points' coordinates by sorted position (direct == 0)
+  const uint64_t* ssig;    // [W][N] their signature words (direct == 0 and first_owner)
+  int first_owner;         // 1: keep a pair only under the first grid whose cell holds both
   size_t N;                // plane stride of spts / ssig
   int direct;              // 1: read rows by point index from pts / sigp instead
   const uint64_t* sigp;    // [npts][W] signature words by point (direct reads)
@@ -415,6 +416,7 @@ void launch_over_emit(const uint64_t* keys, uint32_t tot, const uint32_t* ids,
                       int rb, int64_t n, int64_t* row_ptr, int32_t* col, hipStream_t s);
 
 void launch_u32_to_u64(const uint32_t* src, size_t count, uint64_t* dst, hipStream_t s);
+
 
 // --- per-instance lists of a batch ------------------------------------------
 // out[q] = row_ptr[first batch point of instance q], out[m] = row_ptr[npts].

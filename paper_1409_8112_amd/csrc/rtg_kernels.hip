@@ -1024,7 +1024,7 @@ __device__ __forceinline__ UnitView unit_view(const PairsArgs& P, uint32_t u, ui
   v.tcell = (int)uniform(U.t);
   v.inst = uniform(U.inst);
   v.nt = (v.L + kPairTile - 1) / kPairTile;
-  v.nw = (P.ssig && v.tcell > 0) ? (v.tcell - 1) / P.gpw + 1 : 0;
+  v.nw = (P.first_owner && v.tcell > 0) ? (v.tcell - 1) / P.gpw + 1 : 0;
   return v;
 }
 

@@ -58,6 +58,9 @@ int model_recall(int32_t d, int32_t k, double alpha, uint32_t flags, double* rec
 int choose_params(int32_t d, double target, double nu, uint32_t flags, int32_t* k_out,
                   double* alpha_out, double* recall_out);
 int min_field_bits(double alpha);
+// Candidate pairs a pass makes room for per (point, grid) key before it
+// learns the exact count (a pass that needs more runs its pair kernel again).
+uint64_t cand_per_key(uint32_t flags);
 int validate_query(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha);
 // Flags that shape a pass's output (instances batched together share them).
 constexpr uint32_t kListFlags = RTG_UPPER_ONLY | RTG_DEDUP_SORT | RTG_DEDUP_BITMAP;
@@ -228,6 +231,9 @@ struct Ctx {
   int hip_fail(hipError_t e, const char* what);
   void* dalloc(size_t bytes);
   void dfree(void* p);
+  // Device bytes one pass of the pipeline takes for an instance (points
+  // excluded), while its candidates stay within cand_per_key per key.
+  size_t pass_bytes_bound(int64_t n, int32_t d, int32_t k, double alpha, uint32_t flags) const;
   size_t largest_free();
   size_t free_bytes();
   uint64_t new_handle();
@@ -249,6 +255,8 @@ struct Ctx {
   int submit(const rtg_query& q, uint64_t* ticket);
   int poll(uint64_t ticket, rtg_csr* out);
   void stop_server();
+  void wake_server();   // memory came back: requests waiting for it may run
+  bool holds_results();  // results or indexes held in the arena
   std::atomic<int64_t> served_requests{0}, served_batches{0};
 };
 

@@ -9,33 +9,28 @@
 // tickets.  Queries that arrive while a pass runs join the next pass on a
 // free lane, so passes of different lanes overlap on the device.
 //
-// Admission is by device memory: a pass starts when its planning estimate
-// fits the arena's free bytes less the estimates of the passes already
-// running (the head of the queue always starts on an idle device).  A pass
-// that still runs out of memory, or fails on one of its queries, is split:
-// its queries go back to the front of the queue to run alone, on an idle
-// device, so each query gets its own result or error.  A query's result
-// never depends on its batch-mates: no step of a pass mixes instances.
+// Admission is by device memory: a pass starts when its working-set bound
+// (Ctx::pass_bytes_bound) fits the arena's free bytes -- which already count
+// the finished results the caller has not released -- less the bounds of
+// the passes already running (the head of the queue always starts on an
+// idle device).  A pass that still runs out of memory, or fails on one of
+// its queries, is split: its queries go back to the front of the queue to
+// run alone, on an idle device, so each query gets its own result or error.
+// A query that runs out of memory alone while other requests' points or
+// unreleased results hold part of the budget waits until memory comes back
+// (a release, or a pass that ends) and runs again; it fails with ENOMEM
+// only when nothing else holds memory.  A query's result never depends on
+// its batch-mates: no step of a pass mixes instances.
 #include "../../include/rtg.h"
 #include "rtg_runtime.h"
 
+#include <algorithm>
 #include <cstdlib>
 #include <vector>
 
 namespace rtg {
 
 namespace {
-
-// Planning bound on the device bytes one pass needs for a query beyond its
-// staged points: staged coordinates (SoA and rows), keys and their sort
-// buffers, per-point cell signatures, cell tables, candidate pairs and the
-// neighbour lists, at generous per-point rates.  Not a promise: a pass that
-// exceeds it is retried alone.
-size_t estimate_bytes(int64_t n, int32_t d, int32_t k) {
-  const double N = (double)n * (double)k;
-  const double b = (double)n * (8.0 * d + 256.0) + 48.0 * N + (double)(1 << 20);
-  return (size_t)b;
-}
 
 enum { kQueued = 0, kRunning = 1, kDone = 2 };
 
@@ -48,6 +43,11 @@ struct Request {
   int state = kQueued;
   int rc = RTG_OK;
   bool solo = false;      // run alone on an idle device
+  // Ran alone and ran out of memory while other requests' points or results
+  // held part of the budget: waits until some memory is given back (the
+  // server's release count passes wait_gen).
+  bool waiting = false;
+  uint64_t wait_gen = 0;
   rtg_csr out{};
 };
 
@@ -71,6 +71,7 @@ struct Server {
   int running = 0;
   bool solo_running = false;
   bool stop = false;
+  uint64_t gen = 0;  // device memory given back (results released, points dropped)
 
   std::mutex copy_mu;  // the copy lane: staging of submitted points
   Lane copy;
@@ -82,6 +83,15 @@ struct Server {
   int poll(uint64_t ticket, rtg_csr* out);
   bool pick(std::vector<Request*>& batch, size_t& est);
   void work(int li);
+  // Called when the caller releases a result or an index: a request waiting
+  // for memory may run again.
+  void wake() {
+    {
+      std::lock_guard<std::mutex> lk(m);
+      ++gen;
+    }
+    cv.notify_all();
+  }
 };
 
 int Server::start(int nlanes) {
@@ -125,7 +135,7 @@ int Server::submit(const rtg_query& q, uint64_t* ticket) {
   int rc = make_transforms(q.seed, q.k, q.d, q.flags, req->R.data(), req->u.data());
   if (rc) return rc;
   const size_t pts_bytes = sizeof(float) * (size_t)q.n * (size_t)q.d;
-  req->est = estimate_bytes(q.n, q.d, q.k);
+  req->est = c.pass_bytes_bound(q.n, q.d, q.k, q.alpha, q.flags);
   if (req->est + pts_bytes > c.arena->size()) return RTG_ENOMEM;
   const uint64_t t = c.new_handle();
   req->ticket = t;
@@ -183,11 +193,19 @@ int Server::poll(uint64_t t, rtg_csr* out) {
   return rc;
 }
 
-// Under m: the next pass for an idle lane, or false to wait.
+// Under m: the next pass for an idle lane, or false to wait.  The pass
+// starts with the first queued request that is not waiting for memory.
 bool Server::pick(std::vector<Request*>& batch, size_t& est) {
   batch.clear();
   if (queue.empty() || solo_running) return false;
-  Request* h = queue.front();
+  Request* h = nullptr;
+  for (Request* r : queue) {
+    if (r->waiting && r->wait_gen == gen) continue;
+    r->waiting = false;
+    h = r;
+    break;
+  }
+  if (!h) return false;
   if (h->solo && running > 0) return false;
   size_t others = 0;
   for (size_t v : reserved) others += v;
@@ -199,9 +217,9 @@ bool Server::pick(std::vector<Request*>& batch, size_t& est) {
   int64_t pts = h->q.n;
   if (!h->solo) {
     const uint32_t g = group_of(h->q);
-    for (size_t i = 1; i < queue.size(); ++i) {
+    for (size_t i = 0; i < queue.size(); ++i) {
       Request* r = queue[i];
-      if (r->solo || group_of(r->q) != g) continue;
+      if (r == h || r->solo || r->waiting || group_of(r->q) != g) continue;
       if (pts + r->q.n > c.batch_points || est + r->est > avail) continue;
       batch.push_back(r);
       est += r->est;
@@ -209,14 +227,8 @@ bool Server::pick(std::vector<Request*>& batch, size_t& est) {
     }
   }
   std::deque<Request*> rest;
-  size_t b = 0;
-  for (Request* r : queue) {
-    if (b < batch.size() && r == batch[b]) {
-      ++b;
-      continue;
-    }
-    rest.push_back(r);
-  }
+  for (Request* r : queue)
+    if (std::find(batch.begin(), batch.end(), r) == batch.end()) rest.push_back(r);
   queue.swap(rest);
   return true;
 }
@@ -252,11 +264,25 @@ void Server::work(int li) {
     --running;
     reserved[li] = 0;
     if (solo) solo_running = false;
-    if (rc != RTG_OK && rc != RTG_EDEVICE && (batch.size() > 1 || (rc == RTG_ENOMEM && !solo))) {
+    // A request that ran alone on an idle device and still ran out of
+    // memory: if other requests' points or finished results hold part of the
+    // budget it waits for some of it to come back; only with nothing else
+    // held is the budget too small for it.
+    bool others_hold = false;
+    if (rc == RTG_ENOMEM && solo) {
+      others_hold = running > 0 || c.holds_results();
+      for (Request* r : queue) others_hold = others_hold || r->pts_mem != nullptr;
+    }
+    if (rc != RTG_OK && rc != RTG_EDEVICE &&
+        (batch.size() > 1 || (rc == RTG_ENOMEM && (!solo || others_hold)))) {
       // split: every query runs alone, in its original order, at the front
       for (size_t i = batch.size(); i-- > 0;) {
         batch[i]->state = kQueued;
         batch[i]->solo = true;
+        if (solo) {
+          batch[i]->waiting = true;
+          batch[i]->wait_gen = gen;
+        }
         queue.push_front(batch[i]);
       }
     } else {
@@ -266,6 +292,7 @@ void Server::work(int li) {
         c.dfree(r->pts_mem);
         r->pts_mem = nullptr;
       }
+      ++gen;  // their staged points are back
       c.served_requests += (int64_t)batch.size();
       c.served_batches += 1;
     }
@@ -303,6 +330,11 @@ int Ctx::poll(uint64_t ticket, rtg_csr* out) {
   }
   if (!s) return find_result(ticket, out) ? RTG_OK : RTG_ENOENT;
   return s->poll(ticket, out);
+}
+
+void Ctx::wake_server() {
+  std::lock_guard<std::mutex> lk(server_mu);
+  if (server) server->wake();
 }
 
 void Ctx::stop_server() {

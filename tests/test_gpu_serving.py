@@ -150,17 +150,15 @@ def test_bad_request_fails_alone(ctx):
 def test_admission_by_memory_budget():
     """With a budget that holds about one request's working set at a time,
     requests run one after another and every result is still right; a
-    request larger than the whole budget is refused at submit.  (Radii are
-    small enough that the finished results, which stay in the budget until
-    they are collected, fit beside one working set: otherwise a request
-    retried alone after the others have finished could still not fit.)"""
+    request larger than the whole budget is refused at submit.  Finished
+    results count against the budget until they are released, and a request
+    that does not fit beside them waits for the release rather than fail."""
     from paper_1409_8112_amd import rtg
     c = _context(96 << 20)
     try:
         reqs = _requests(4, 6, dims=(3,), n_lo=60000, n_hi=80000)
         for q in reqs:
             q["k"] = 4
-            q["r"] *= 0.6
         got = _serve(c, reqs)
         for q, (rp, col) in zip(reqs, got):
             ref = _oracle(q)
