@@ -146,3 +146,40 @@ def batched_instances(count: int = 4096, seed: int = 0, n_lo: int = 1000, n_hi: 
         r = prm_radius(n, d, gammas[d])
         out.append(Workload(f"batched[{q}]", n, d, r, k, alpha, seed=q, point_seed=1_000_000 + q))
     return out
+
+
+@dataclass
+class ServingMix:
+    """A request stream: Poisson arrival times (seconds from the start) and
+    one uniform all-pairs instance per request."""
+    arrivals: np.ndarray
+    requests: list
+
+    def replay_sample(self, frac: float = 0.01, seed: int = 2024) -> np.ndarray:
+        """Indices of a seeded sample of the requests (frac of them, at least
+        one), ascending: the requests whose results are checked in full."""
+        m = max(1, int(round(frac * len(self.requests))))
+        rng = np.random.default_rng(seed)
+        return np.sort(rng.choice(len(self.requests), size=m, replace=False))
+
+
+def serving_mix(count: int = 1000, rate: float = 1000.0, seed: int = 0, n_lo: int = 500,
+                n_hi: int = 2_000_000, dims=(3, 6, 12), target_neighbours: float = 15.0,
+                k: int = 8, alpha: float = 2.0) -> ServingMix:
+    """Poisson arrivals at `rate` per second; request i has n log-uniform in
+    [n_lo, n_hi], d drawn from dims, points uniform in [0,1)^d (point seed
+    2_000_000 + i), radius gamma_d (ln n / n)^(1/d) with gamma_d set for
+    ~target_neighbours mean neighbours at the geometric-mean n; RTG seed i."""
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    ns = np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), size=count)).round().astype(np.int64)
+    ds = rng.choice(list(dims), size=count)
+    n_mid = int(round(math.sqrt(n_lo * n_hi)))
+    gammas = {int(d): calibrate_radius_uniform(n_mid, int(d), target_neighbours)
+              / (math.log(n_mid) / n_mid) ** (1.0 / d) for d in dims}
+    reqs = []
+    for i in range(count):
+        n, d = int(ns[i]), int(ds[i])
+        reqs.append(Workload(f"served[{i}]", n, d, prm_radius(n, d, gammas[d]), k, alpha,
+                             seed=i, point_seed=2_000_000 + i))
+    return ServingMix(arrivals, reqs)
