@@ -12,8 +12,15 @@ alpha = 2, r for ~20 mean neighbours, seed 0.
 Prints one JSON line.  Besides throughput it carries:
   roofline      the dominant kernel's algorithmic bytes (or flops) per launch
                 over its average launch time, timed live with HIP events on
-                the library's stream during the timed steps;
-  cpu_baseline  the CPU oracle on the same workload, single-threaded.
+                the library's stream during the timed steps; the pair kernel
+                counts 2d FP32 flops per tested pair (a difference, a square
+                and a sum per coordinate, the square and sum fused);
+  phases        per pipeline phase (key, key sort, cells, pairs, lists):
+                algorithmic bytes, device time and the fraction of HBM peak;
+  configs       the small d3 and the clustered d12 workloads, each timed the
+                same way (ms, pairs/s, pair-kernel roofline, phases);
+  cpu_baseline  the CPU oracle on the same workload, single-threaded, and on
+                a sample of the batched instances over every host core.
 """
 from __future__ import annotations
 
@@ -39,12 +46,12 @@ SINGLE_KERNELS = {"keys": "k_keys", "key_hist": "k_radix_hist", "key_scatter": "
                   "gather": "k_gather_units", "compact": "k_seg_compact"}
 
 
-def measured_traffic(kernel_name: str):
+def measured_traffic(kernel_name: str, summary: str = "k_cell_pairs_uniform_n1e6_d6_traffic.txt"):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary, or None when it is missing, names another kernel, or the kernel
     source changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_cell_pairs_uniform_n1e6_d6_traffic.txt")
+    path = os.path.join(ROOT, "profiles", summary)
     src = os.path.join(ROOT, "paper_1409_8112_amd", "csrc", "rtg_kernels.hip")
     try:
         kv = {}
@@ -76,6 +83,36 @@ def cpu_baseline(points, wl, budget_s: float):
     pairs = len(res.col) // 2
     return {"value": pairs / dt, "unit": "pairs/s", "cores": 1, "kind": "oracle",
             "sample": f"the whole workload ({wl.name}), single-threaded C oracle, {dt:.1f} s",
+            "seconds": dt, "pairs": pairs}
+
+
+def _oracle_pairs(wl):
+    """Pairs the oracle reports for one batched instance (a pool worker)."""
+    import oracle
+    pts = wl.points()
+    t0 = time.perf_counter()
+    res = oracle.rtg(pts, wl.r, wl.k, wl.alpha, wl.seed)
+    return len(res.col) // 2, time.perf_counter() - t0
+
+
+def cpu_baseline_all_cores(count: int = 4096, sample: int = 512) -> dict:
+    """The oracle on every host core: the first `sample` of the batched
+    instances, one instance per task over a process pool (instances are
+    independent, so nothing is merged)."""
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_1409_8112_amd import workloads
+    cores = max(1, min(16, os.cpu_count() or 1))
+    specs = workloads.batched_instances(count)[:sample]
+    import multiprocessing
+    with ProcessPoolExecutor(max_workers=cores, mp_context=multiprocessing.get_context("fork")) as ex:
+        list(ex.map(_oracle_pairs, specs[:cores]))  # workers up, oracle loaded
+        t0 = time.perf_counter()
+        got = list(ex.map(_oracle_pairs, specs))
+        dt = time.perf_counter() - t0
+    pairs = sum(p for p, _ in got)
+    return {"value": pairs / dt, "unit": "pairs/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {sample} of the {count} batched instances, one process per core, "
+                      f"{dt:.1f} s wall ({sum(t for _, t in got):.1f} s of oracle time)",
             "seconds": dt, "pairs": pairs}
 
 
@@ -276,26 +313,24 @@ def bench_query(ctx, pts, wl, m: int = 1_000_000, reps: int = 5) -> dict:
             "neighbours_per_s": found / t, "index_build_ms": build_ms}
 
 
-def bench_serving(ctx, count: int, rate: float, seed: int = 0) -> dict:
-    """Poisson arrivals through rtg_submit / rtg_poll.  Latency runs from a
-    request's scheduled arrival to the poll that sees it done."""
+def serving_points(count: int):
+    """The request mix's points, on the device (workloads.serving_mix)."""
     import torch
     from paper_1409_8112_amd import workloads
-    rng = np.random.default_rng(seed)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=count))
-    ns = np.exp(rng.uniform(np.log(500), np.log(2_000_000), size=count)).round().astype(np.int64)
-    dims = rng.choice([3, 6, 12], size=count)
-    n_mid = int(round(np.sqrt(500 * 2_000_000)))
-    gamma = {int(d): workloads.calibrate_radius_uniform(n_mid, int(d), 15.0)
-             / (np.log(n_mid) / n_mid) ** (1.0 / d) for d in (3, 6, 12)}
-    gen = torch.Generator(device="cuda:0")
-    gen.manual_seed(seed)
-    reqs = []
-    for i in range(count):
-        n, d = int(ns[i]), int(dims[i])
-        p = torch.rand((n, d), generator=gen, device="cuda:0", dtype=torch.float32)
-        reqs.append((p, workloads.prm_radius(n, d, gamma[d]), i))
+    mix = workloads.serving_mix(count)
+    pts = [torch.from_numpy(w.points()).to("cuda:0") for w in mix.requests]
     torch.cuda.synchronize()
+    return mix, pts
+
+
+def bench_serving(ctx, mix, pts, rate: float) -> dict:
+    """Poisson arrivals through rtg_submit / rtg_poll: the mix's requests at
+    its arrival times rescaled to `rate`.  Latency runs from a request's
+    scheduled arrival to the poll that sees it done."""
+    count = len(mix.requests)
+    arrivals = mix.arrivals * (1000.0 / rate)  # the mix is drawn at 1000 requests/s
+    reqs = [(p, w.r, w.seed) for p, w in zip(pts, mix.requests)]
+    ns = np.array([w.n for w in mix.requests])
     before = ctx.stats()
 
     lat, pairs = [], 0
@@ -307,7 +342,7 @@ def bench_serving(ctx, count: int, rate: float, seed: int = 0) -> dict:
         now = time.perf_counter() - t0
         while i < count and arrivals[i] <= now:
             p, r, s = reqs[i]
-            t = ctx.submit(p, r, 8, 2.0, s)
+            t = ctx.submit(p, r, mix.requests[i].k, mix.requests[i].alpha, s)
             if t is None:
                 break  # no room to stage it yet
             pending[t] = arrivals[i]
@@ -332,12 +367,106 @@ def bench_serving(ctx, count: int, rate: float, seed: int = 0) -> dict:
     passes = after["served_batches"] - before["served_batches"]
     return {"workload": f"{count} requests, Poisson {rate:g}/s, n log-uniform [500, 2e6] "
                         f"(sum {int(ns.sum())}), d in {{3,6,12}}, uniform, ~15 nb, k=8, alpha=2",
+            "rate_per_s": rate,
             "value": pairs / span, "unit": "pairs/s", "pairs": pairs,
             "latency_ms": {"p50": float(np.percentile(lat, 50)),
                            "p99": float(np.percentile(lat, 99)),
                            "max": float(np.max(lat))},
             "offered_s": float(arrivals[-1]), "span_s": span,
             "requests_per_pass": served / max(passes, 1)}
+
+
+# Phases of one query: kernel ids whose launches they group (rtg.KERNELS).
+PHASES = {"stage": ["stage"], "key": ["keys"], "key_sort": ["key_hist", "key_scatter"],
+          "cells": ["cells"], "pairs": ["pairs"], "compact": ["compact"],
+          "lists": ["csr"], "scans": ["scan"]}
+
+
+def phase_block(stats_sum: dict, steps: int) -> dict:
+    """Per phase: the library's algorithmic bytes (what its kernels must read
+    and write), device time (HIP events around each launch) and the rate as a
+    fraction of HBM peak, per query."""
+    from paper_1409_8112_amd import rtg
+    out = {}
+    for name, kids in PHASES.items():
+        ix = [rtg.KERNELS.index(k) for k in kids]
+        by = sum(stats_sum["kernel_bytes"][i] for i in ix) / steps
+        ms = sum(stats_sum["kernel_ms"][i] for i in ix) / steps
+        la = sum(stats_sum["kernel_launches"][i] for i in ix) / steps
+        gbs = by / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+        out[name] = {"bytes": by, "us": ms * 1e3, "launch_groups": la, "GB/s": gbs,
+                     "frac_hbm": gbs / HBM_PEAK_GBS}
+    return out
+
+
+def _sum_stats(acc, st):
+    if acc is None:
+        return {k: (list(v) if isinstance(v, list) else v) for k, v in st.items()}
+    for k in ("kernel_bytes", "kernel_ms", "kernel_launches"):
+        acc[k] = [a + b for a, b in zip(acc[k], st[k])]
+    return acc
+
+
+def probe_steps(ctx, step, steps: int):
+    """steps queries with every kernel id timed: summed stats."""
+    from paper_1409_8112_amd import rtg
+    ctx.set_timing((1 << rtg.NKERNELS) - 1)
+    acc = None
+    for _ in range(steps):
+        step()
+        acc = _sum_stats(acc, ctx.stats())
+    ctx.set_timing(0)
+    return acc
+
+
+def pair_roofline(d: int, tests: float, pair_ms: float, matrix: bool) -> dict:
+    """The pair kernel against FP32 peak: 2d flops per tested pair."""
+    achieved = 2.0 * d * tests / (pair_ms / 1e3) / 1e12
+    return {"bound": "mfma" if matrix else "alu", "achieved": achieved,
+            "peak": FP32_VEC_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_VEC_PEAK_TFLOPS, "avg_launch_ms": pair_ms,
+            "flops_per_test": 2 * d, "tests": tests,
+            "kernel": "k_cell_pairs_gram" if matrix else "k_cell_pairs"}
+
+
+def bench_config(ctx, wl, steps: int, warmup: int, probes: int = 3) -> dict:
+    """One workload: ms per query (wall clock, points resident), pairs/s,
+    the pair kernel's roofline and the phases."""
+    import torch
+    from paper_1409_8112_amd import rtg
+    pts = torch.from_numpy(wl.points()).to("cuda:0")
+    torch.cuda.synchronize()
+
+    def step():
+        res = ctx.all_pairs(pts, wl.r, wl.k, wl.alpha, wl.seed)
+        pairs = res.pairs
+        res.release()
+        return pairs
+
+    for _ in range(warmup):
+        step()
+    acc = probe_steps(ctx, step, probes)
+    st = ctx.stats()
+    pk = rtg.KERNELS.index("pairs")
+    pair_ms = acc["kernel_ms"][pk] / max(acc["kernel_launches"][pk], 1)
+    lat = []
+    pairs = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        pairs = step()
+        lat.append((time.perf_counter() - s0) * 1e3)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    del pts
+    return {"workload": wl.name, "n": wl.n, "d": wl.d, "k": wl.k, "alpha": wl.alpha, "r": wl.r,
+            "steps": steps, "ms": ms, "pairs": pairs, "pairs_per_s": pairs / (ms / 1e3),
+            "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                           "p99": float(np.percentile(lat, 99))},
+            "pair_kernel": pair_roofline(wl.d, st["tests"], pair_ms,
+                                         st["matrix_screen_launches"] > 0),
+            "phases": phase_block(acc, probes)}
 
 
 def main(argv=None) -> int:
@@ -350,6 +479,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=60.0)
     ap.add_argument("--arena-gb", type=float, default=48.0)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the small d3 and clustered d12 workloads")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-instances measurement")
     ap.add_argument("--no-serving", action="store_true",
@@ -366,7 +497,8 @@ def main(argv=None) -> int:
                     help="recall against brute force on this many sampled rows (0: skip)")
     ap.add_argument("--batched-count", type=int, default=4096)
     ap.add_argument("--serving-requests", type=int, default=1000)
-    ap.add_argument("--serving-rate", type=float, default=1000.0)
+    ap.add_argument("--serving-rates", default="1000,500",
+                    help="arrival rates (requests/s) of the request-loop runs")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -374,6 +506,12 @@ def main(argv=None) -> int:
               "(instances and requests would shard across GPUs without communication)",
               file=sys.stderr)
         return 2
+
+    all_cores = None
+    if not args.no_cpu_baseline:
+        # before anything touches the GPU: the pool forks plain CPU workers
+        print("# cpu baseline, all cores (oracle)", file=sys.stderr, flush=True)
+        all_cores = cpu_baseline_all_cores(args.batched_count)
 
     import torch
     from paper_1409_8112_amd import rtg
@@ -402,10 +540,9 @@ def main(argv=None) -> int:
     for _ in range(args.warmup):
         step()
 
-    # One untimed step with every kernel timed picks the dominant single kernel.
-    ctx.set_timing((1 << rtg.NKERNELS) - 1)
-    step()
-    probe = ctx.stats()
+    # Untimed steps with every kernel timed: the phases, and the dominant
+    # single kernel for the roofline.
+    probe = probe_steps(ctx, step, 3)
     ms_by = {name: probe["kernel_ms"][rtg.KERNELS.index(name)] for name in SINGLE_KERNELS}
     dominant = max(ms_by, key=ms_by.get)
     kid = rtg.KERNELS.index(dominant)
@@ -415,6 +552,7 @@ def main(argv=None) -> int:
     lat = []
     k_ms = k_bytes = 0.0
     k_launch = 0
+    tests = 0
     pairs = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -426,6 +564,7 @@ def main(argv=None) -> int:
         k_ms += st["kernel_ms"][kid]
         k_bytes += st["kernel_bytes"][kid]
         k_launch += st["kernel_launches"][kid]
+        tests += st["tests"]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.set_timing(0)
@@ -436,25 +575,19 @@ def main(argv=None) -> int:
 
     avg_ms = k_ms / max(k_launch, 1)
     if dominant == "pairs":
-        # ALU bound: FP32 flops of the screen, 3 per coordinate (sub, mul, add)
-        flops = 3.0 * wl.d * st["tests"] * args.steps / max(k_launch, 1)
-        achieved = flops / (avg_ms / 1e3) / 1e12
-        traffic = (measured_traffic("k_cell_pairs")
-                   if args.workload == "uniform_d6" and st["matrix_screen_launches"] else None)
-        # the matrix-core screen is an FP32 contraction (Gram blocks): its
-        # peak is the FP32 matrix rate, the same figure as FP32 vector
-        bound = "mfma" if st["matrix_screen_launches"] else "alu"
-        roof = {"bound": bound, "achieved": achieved, "peak": FP32_VEC_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP32_VEC_PEAK_TFLOPS, "traffic": traffic}
+        roof = pair_roofline(wl.d, tests / max(k_launch, 1), avg_ms,
+                             st["matrix_screen_launches"] > 0)
+        roof["traffic"] = (measured_traffic("k_cell_pairs")
+                           if args.workload == "uniform_d6" and st["matrix_screen_launches"]
+                           else None)
     else:
         per_launch = k_bytes / max(k_launch, 1)
         achieved = per_launch / (avg_ms / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
-    if dominant == "pairs" and st["matrix_screen_launches"]:
-        roof["kernel"] = "k_cell_pairs_gram"
-    roof.update({"kernel": roof.get("kernel", SINGLE_KERNELS[dominant]), "kernel_id": dominant,
-                 "avg_launch_ms": avg_ms, "launches_per_step": k_launch / args.steps,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": SINGLE_KERNELS[dominant]}
+    roof.update({"kernel_id": dominant, "avg_launch_ms": avg_ms,
+                 "launches_per_step": k_launch / args.steps,
                  "algorithmic_bytes_per_launch": k_bytes / max(k_launch, 1)})
 
     out = {
@@ -478,9 +611,19 @@ def main(argv=None) -> int:
         "stats": {k: st[k] for k in ("cells", "tests", "candidates", "band_rechecks",
                                      "unique_pairs", "key_bits", "key_passes", "pair_bits",
                                      "transforms_per_sort")},
-        "probe_kernel_ms": {name: probe["kernel_ms"][i] for i, name in enumerate(rtg.KERNELS)},
         "roofline": roof,
+        "phases": phase_block(probe, 3),
+        "probe_kernel_ms": {name: probe["kernel_ms"][i] / 3 for i, name in enumerate(rtg.KERNELS)},
     }
+    del pts
+    if not args.no_configs and args.workload == "uniform_d6":
+        from paper_1409_8112_amd import workloads
+        out["configs"] = {}
+        for name, w, steps in (("small_d3", workloads.small_uniform_d3(), 50),
+                               ("clustered_d12", workloads.skewed_clustered_d12(), 10)):
+            print(f"# config {w.name}", file=sys.stderr, flush=True)
+            out["configs"][name] = bench_config(ctx, w, steps, 3)
+    pts = torch.from_numpy(pts_host).to("cuda:0")
     if args.recall_rows > 0:
         print(f"# recall on {args.recall_rows} sampled rows", file=sys.stderr, flush=True)
         out["recall"] = measure_recall(ctx, pts, pts_host, wl, args.recall_rows)
@@ -493,17 +636,23 @@ def main(argv=None) -> int:
     if not args.no_variants and args.workload == "uniform_d6":
         print("# dedup rules and metric variants", file=sys.stderr, flush=True)
         out["variants"] = bench_variants(ctx, pts, wl)
+    del pts
     if not args.no_batched:
         print(f"# batched: {args.batched_count} instances", file=sys.stderr, flush=True)
         out["batched"] = bench_batched(ctx, args.batched_count)
     if not args.no_serving:
-        print(f"# serving: {args.serving_requests} requests at {args.serving_rate}/s",
-              file=sys.stderr, flush=True)
-        out["serving"] = bench_serving(ctx, args.serving_requests, args.serving_rate)
+        mix, spts = serving_points(args.serving_requests)
+        out["serving"] = []
+        for rate in (float(x) for x in args.serving_rates.split(",")):
+            print(f"# serving: {args.serving_requests} requests at {rate}/s",
+                  file=sys.stderr, flush=True)
+            out["serving"].append(bench_serving(ctx, mix, spts, rate))
+        del spts
     ctx.close()
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(pts_host, wl, args.cpu_budget)
+        out["cpu_baseline_all_cores"] = all_cores
     print(json.dumps(out), flush=True)
     return 0
 
