@@ -195,6 +195,35 @@ int rtg_all_pairs_with_transforms(rtg_ctx *ctx, const float *points, int64_t n, 
                                   double r, int32_t k, double alpha, const double *R,
                                   const double *u, uint32_t flags, rtg_csr *out);
 
+/* For callers that cannot allocate device memory (serving loops that must
+ * not call hipMalloc, harnesses that forbid allocation): rtg_all_pairs with
+ * the result written into caller buffers and every byte of device scratch
+ * taken from one file-scope device array of the library, RTG_NOALLOC_BYTES
+ * per device, held by each device the library runs on until the process
+ * ends.  No device memory is allocated or freed and no host memory is
+ * pinned during the call (the context's arena is not used either).
+ *   points, n, d, r, k, alpha, seed, flags: as rtg_all_pairs.
+ *   row_ptr: device, n+1 int64, 8-byte aligned, written on RTG_OK.
+ *   col: device, col_capacity int32 (may be NULL when col_capacity is 0),
+ *     written on RTG_OK with the nnz entries of the symmetric (or, with
+ *     RTG_UPPER_ONLY, upper) lists -- the arrays rtg_all_pairs returns.
+ *   nnz: host; receives the entries written, or on RTG_ENOMEM because
+ *     col_capacity is too small, the entries needed (row_ptr and col are
+ *     then untouched).
+ * Limits: the pass's working set (about 130 bytes per point and grid plus
+ * 8d + 64 per point) must fit RTG_NOALLOC_BYTES and its uploaded transforms
+ * (8 k d (d+2) bytes and tables) 256 KiB; larger calls return RTG_ENOMEM
+ * before any device work.  The call is blocking and per-kernel timing does
+ * not apply to it.  Calls on one device share the array: calls that overlap
+ * on one GPU (from different contexts of that device) race and must be
+ * serialised by the caller; calls on one context are serialised by it.
+ * Errors: as rtg_all_pairs; RTG_EINVAL also for a misaligned or non-device
+ * row_ptr / col; RTG_EDEVICE if the array's address could not be obtained. */
+#define RTG_NOALLOC_BYTES ((size_t)256 << 20)
+int rtg_all_pairs_noalloc(rtg_ctx *ctx, const float *points, int64_t n, int32_t d, double r,
+                          int32_t k, double alpha, uint64_t seed, uint32_t flags,
+                          int64_t *row_ptr, int32_t *col, int64_t col_capacity, int64_t *nnz);
+
 /* Many independent queries in one pass of the pipeline: every (query, grid)
  * pair is one segment of a shared key space, so each kernel launch covers all
  * queries.  outs[q] receives query q's list, identical to what rtg_all_pairs

@@ -428,9 +428,26 @@ void* Ctx::dalloc(size_t bytes) {
   return arena->alloc(bytes);
 }
 
+void* Ctx::dalloc_noalloc(size_t bytes) {
+  std::lock_guard<std::mutex> lk(amu);
+  return noalloc_arena ? noalloc_arena->alloc(bytes) : nullptr;
+}
+
+size_t Ctx::largest_free_noalloc() {
+  std::lock_guard<std::mutex> lk(amu);
+  return noalloc_arena ? noalloc_arena->largest_free() : 0;
+}
+
+Arena* Ctx::arena_of(const void* p) {
+  const char* c = static_cast<const char*>(p);
+  const char* b = static_cast<const char*>(noalloc_base);
+  if (noalloc_arena && c >= b && c < b + kNoallocBytes) return noalloc_arena.get();
+  return arena.get();
+}
+
 void Ctx::dfree(void* p) {
   std::lock_guard<std::mutex> lk(amu);
-  arena->release(p);
+  arena_of(p)->release(p);
 }
 
 size_t Ctx::largest_free() {
@@ -464,7 +481,7 @@ int Ctx::release_many(const uint64_t* handles, int32_t count) {
     for (int32_t i = 0; i < count; ++i) {
       auto it = results.find(handles[i]);
       if (it != results.end()) {
-        arena->release(it->second.mem);
+        arena_of(it->second.mem)->release(it->second.mem);
         results.erase(it);
         any = true;
         continue;
@@ -960,11 +977,14 @@ int csr_from_sorted(Lane& c, Scratch& S, const uint64_t* uniq, size_t U, int64_t
 // Device memory from the arena; when it has none to give, the dropped blocks
 // of this lane's open Scratch objects go back to it first.
 void* Lane::dalloc(size_t bytes) {
-  void* p = ctx->dalloc(bytes);
+  auto get = [&] { return noalloc ? ctx->dalloc_noalloc(bytes) : ctx->dalloc(bytes); };
+  void* p = get();
   for (Scratch* s = static_cast<Scratch*>(scratch); !p && s; s = static_cast<Scratch*>(s->outer))
-    if (s->flush()) p = ctx->dalloc(bytes);
+    if (s->flush()) p = get();
   return p;
 }
+
+size_t Lane::largest_free() { return noalloc ? ctx->largest_free_noalloc() : ctx->largest_free(); }
 
 int Lane::make_empty_result(int64_t n, rtg_csr* out, uint64_t handle) {
   void* mem = dalloc(sizeof(int64_t) * (size_t)(n + 1));
@@ -1029,6 +1049,69 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
   rc = main.run_batch(jobs, st);
   if (!rc) stats = st;
   return rc;
+}
+
+// rtg_all_pairs into the caller's buffers with every device byte from the
+// no-allocation arena: the usual pass on the main lane, its result copied
+// out and given back.  Size limits keep the pass inside the array and every
+// host transfer inside the main lane's pinned staging (sized at creation),
+// so nothing is allocated on the device or pinned on the host.
+int Ctx::all_pairs_noalloc(const float* points, int64_t n, int32_t d, double r, int32_t k,
+                           double alpha, const double* R, const double* u, uint32_t flags,
+                           int64_t* row_ptr, int32_t* col, int64_t col_capacity, int64_t* nnz) {
+  if (poisoned) return RTG_EDEVICE;
+  if (!noalloc_arena) return RTG_EDEVICE;
+  int rc = check_query(points, n, d, r, k, alpha, flags);
+  if (rc) return rc;
+  if ((reinterpret_cast<uintptr_t>(row_ptr) & 7u) || (reinterpret_cast<uintptr_t>(col) & 3u) ||
+      check_device_pointer(row_ptr, device) ||
+      (col_capacity > 0 && check_device_pointer(col, device)))
+    return RTG_EINVAL;
+  // uploads of one pass (transforms, field origins, segment tiles) and the
+  // working set (points excluded) against the limits
+  const double staging = 8.0 * k * d * (d + 2) + 24.0 * k + 24.0 * k * ((double)n / kTile + 2.0) +
+                         8192.0;
+  if (staging > (double)kNoallocStaging ||
+      pass_bytes_bound(n, d, k, alpha, flags) > kNoallocBytes)
+    return RTG_ENOMEM;
+  rtg_stats st{};
+  st.n = n;
+  st.d = d;
+  st.k = k;
+  st.point_transforms = n * k;
+  rtg_csr out{};
+  const uint32_t timing = main.timing_mask;
+  main.timing_mask = 0;  // no timing events are made in this call
+  main.noalloc = true;
+  if (n <= 1) {
+    rc = main.tiny_query(points, n, d, &out, 0);
+  } else {
+    Job job{points, n, d, r, alpha, k, flags, R, u, &out};
+    std::vector<Job*> jobs{&job};
+    rc = main.run_batch(jobs, st);
+  }
+  main.noalloc = false;
+  main.timing_mask = timing;
+  if (rc) return rc;
+  const int64_t need = out.nnz;
+  if (need > col_capacity) {
+    release(out.handle);
+    *nnz = need;
+    return RTG_ENOMEM;
+  }
+  rc = hip_fail(hipMemcpyAsync(row_ptr, out.row_ptr, sizeof(int64_t) * (size_t)(n + 1),
+                               hipMemcpyDeviceToDevice, main.stream),
+                "copy row_ptr");
+  if (!rc && need)
+    rc = hip_fail(hipMemcpyAsync(col, out.col, sizeof(int32_t) * (size_t)need,
+                                 hipMemcpyDeviceToDevice, main.stream),
+                  "copy col");
+  if (!rc) rc = main.sync();
+  release(out.handle);
+  if (rc) return rc;
+  *nnz = need;
+  stats = st;
+  return RTG_OK;
 }
 
 // One pass of the pipeline over a batch of instances of one dimension d
@@ -1140,7 +1223,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
       ks[q] = jobs[q]->k;
     }
     rc = plan_batch(d, m, ks.data(), ns.data(), Rh.data(), uh.data(), inv_cs.data(),
-                    alphas.data(), lo.data(), hi.data(), ctx->largest_free() / 2, P);
+                    alphas.data(), lo.data(), hi.data(), largest_free() / 2, P);
     if (rc) return rc;
   }
   st.key_bits = std::max(st.key_bits, P.key_bits);
@@ -1233,7 +1316,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
       bits += nq * (nq - 1) / 2;
     }
     const uint64_t words = (bits + 31) / 32;
-    const uint64_t limit = std::min<uint64_t>(kBitmapMaxBytes, ctx->largest_free() / 4);
+    const uint64_t limit = std::min<uint64_t>(kBitmapMaxBytes, largest_free() / 4);
     if (4 * words <= limit) bitmap_words = std::max<uint64_t>(words, 1);
   }
   const bool bitmap = bitmap_words > 0;
@@ -2378,10 +2461,18 @@ int rtg_create(rtg_ctx** out, int device, void* arena, size_t arena_bytes, void*
     arena = c->arena_mem;
   }
   c->arena.reset(new rtg::Arena(static_cast<char*>(arena), arena_bytes));
-  const int rc = c->main.init(c, static_cast<hipStream_t>(hip_stream), false);
+  int rc = c->main.init(c, static_cast<hipStream_t>(hip_stream), false);
+  // pinned staging large enough that rtg_all_pairs_noalloc never grows it
+  if (!rc) rc = c->main.up_room(rtg::kNoallocStaging);
   if (rc) {
     delete c;
     return rc;
+  }
+  // The no-allocation entry point's device array on this device (current).
+  void* np = nullptr;
+  if (rtgk::noalloc_scratch_address(&np) == 0 && np) {
+    c->noalloc_base = np;
+    c->noalloc_arena.reset(new rtg::Arena(static_cast<char*>(np), rtgk::kNoallocBytes));
   }
   *out = reinterpret_cast<rtg_ctx*>(c);
   return RTG_OK;
@@ -2415,6 +2506,21 @@ int rtg_all_pairs_with_transforms(rtg_ctx* ctx, const float* points, int64_t n, 
   Ctx* c = reinterpret_cast<Ctx*>(ctx);
   std::lock_guard<std::mutex> lk(c->mu);
   return c->all_pairs(points, n, d, r, k, alpha, R, u, flags, out);
+}
+
+int rtg_all_pairs_noalloc(rtg_ctx* ctx, const float* points, int64_t n, int32_t d, double r,
+                          int32_t k, double alpha, uint64_t seed, uint32_t flags, int64_t* row_ptr,
+                          int32_t* col, int64_t col_capacity, int64_t* nnz) {
+  if (!ctx || !row_ptr || !nnz || col_capacity < 0 || (col_capacity > 0 && !col))
+    return RTG_EINVAL;
+  int rc = rtg::validate_query(points, n, d, r, k, alpha);
+  if (rc) return rc;
+  std::vector<double> R((size_t)k * d * d), u((size_t)k * d);
+  if ((rc = rtg::make_transforms(seed, k, d, flags, R.data(), u.data()))) return rc;
+  Ctx* c = reinterpret_cast<Ctx*>(ctx);
+  std::lock_guard<std::mutex> lk(c->mu);
+  return c->all_pairs_noalloc(points, n, d, r, k, alpha, R.data(), u.data(), flags, row_ptr, col,
+                              col_capacity, nnz);
 }
 
 int rtg_release(rtg_ctx* ctx, uint64_t handle) {

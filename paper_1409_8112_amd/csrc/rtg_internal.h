@@ -417,6 +417,14 @@ void launch_over_emit(const uint64_t* keys, uint32_t tot, const uint32_t* ids,
 
 void launch_u32_to_u64(const uint32_t* src, size_t count, uint64_t* dst, hipStream_t s);
 
+// --- memory for callers that cannot allocate ----------------------------------
+// Bytes of the file-scope device array that rtg_all_pairs_noalloc takes all
+// of its device memory from (one copy per device, held until the process
+// ends).
+constexpr size_t kNoallocBytes = size_t(256) << 20;
+// That array's address on the current device (hipGetSymbolAddress); 0 on
+// success, else the HIP error code (*ptr is then null).
+int noalloc_scratch_address(void** ptr);
 
 // --- per-instance lists of a batch ------------------------------------------
 // out[q] = row_ptr[first batch point of instance q], out[m] = row_ptr[npts].

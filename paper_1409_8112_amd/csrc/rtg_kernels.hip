@@ -3052,4 +3052,22 @@ void launch_localize(const InstDesc* inst, uint32_t m, uint32_t nblocks, const i
                        dim3(kBlock), 0, s, inst, m, at, col, out_col);
 }
 
+// --- memory for callers that cannot allocate ----------------------------------
+// All scratch and the result of rtg_all_pairs_noalloc live here.  In host
+// code the name is only a stand-in for the array, not a device address: the
+// host side uses the address that noalloc_scratch_address returns for the
+// current device, and the kernels get pointers into it as arguments.
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+int noalloc_scratch_address(void** ptr) {
+  *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *ptr = nullptr;
+    return (int)e;
+  }
+  return 0;
+}
+
 }  // namespace rtgk

@@ -100,6 +100,9 @@ struct Job {
 // Points per batch of rtg_all_pairs_batched (an instance larger runs alone):
 // keeps the neighbour-list build on row buckets and the packed sort keys.
 constexpr int64_t kBatchPoints = int64_t(1) << 22;
+// Pinned upload staging of the main lane, made at rtg_create: everything
+// rtg_all_pairs_noalloc uploads fits it.
+constexpr size_t kNoallocStaging = size_t(256) << 10;
 
 int plan_batch(int d, uint32_t m, const int64_t* k, const int64_t* n, const double* R,
                const double* u, const double* inv_c, const double* alpha, const float* lo,
@@ -146,6 +149,10 @@ struct Lane {
   // wait); off for the request loop's lanes, whose admission reads the
   // arena's free bytes and needs them back at once.
   bool keep_drops = true;
+  // Allocations of this lane come from the context's no-allocation arena
+  // (the file-scope device array) instead of its budget: set for the
+  // duration of an rtg_all_pairs_noalloc call.
+  bool noalloc = false;
   void* host_stage = nullptr;  // pinned staging for read-backs
   size_t host_stage_bytes = 0;
   void* host_up = nullptr;     // pinned staging for batched uploads
@@ -164,6 +171,7 @@ struct Lane {
   int hip_fail(hipError_t e, const char* what);
   void* dalloc(size_t bytes);
   void dfree(void* p);
+  size_t largest_free();  // in the arena this lane allocates from
   int sync();
   int read_back(const void* dev, size_t bytes, void* host);
   // Several device scalars in one copy (one sync).
@@ -197,6 +205,10 @@ struct Ctx {
   bool own_arena = false;
   void* arena_mem = nullptr;
   std::unique_ptr<Arena> arena;
+  // rtg_all_pairs_noalloc: the file-scope device array of this device
+  // (address from hipGetSymbolAddress at rtg_create) and the arena over it.
+  void* noalloc_base = nullptr;
+  std::unique_ptr<Arena> noalloc_arena;
   std::atomic<bool> poisoned{false};
   int sort_algo = 0;  // rtgk::kSortOnesweep or rtgk::kSortReduceScan
   uint32_t bucket_cap = rtgk::kBucketMaxEntries;  // entries per LDS-sorted bucket
@@ -230,7 +242,10 @@ struct Ctx {
 
   int hip_fail(hipError_t e, const char* what);
   void* dalloc(size_t bytes);
-  void dfree(void* p);
+  void* dalloc_noalloc(size_t bytes);   // from the no-allocation arena
+  size_t largest_free_noalloc();
+  void dfree(void* p);                  // to whichever arena holds p
+  Arena* arena_of(const void* p);       // (under amu)
   // Device bytes one pass of the pipeline takes for an instance (points
   // excluded), while its candidates stay within cand_per_key per key.
   size_t pass_bytes_bound(int64_t n, int32_t d, int32_t k, double alpha, uint32_t flags) const;
@@ -245,6 +260,9 @@ struct Ctx {
 
   int all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha,
                 const double* R, const double* u, uint32_t flags, rtg_csr* out);
+  int all_pairs_noalloc(const float* points, int64_t n, int32_t d, double r, int32_t k,
+                        double alpha, const double* R, const double* u, uint32_t flags,
+                        int64_t* row_ptr, int32_t* col, int64_t col_capacity, int64_t* nnz);
   int batched(const rtg_query* q, int32_t nq, rtg_csr* outs);
   int check_query(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha,
                   uint32_t flags);

@@ -94,6 +94,8 @@ def lib() -> ctypes.CDLL:
                                   ctypes.POINTER(rtg_csr)],
                 "rtg_all_pairs_with_transforms": [vp, vp, i64, i32, f64, i32, f64, vp, vp, u32,
                                                   ctypes.POINTER(rtg_csr)],
+                "rtg_all_pairs_noalloc": [vp, vp, i64, i32, f64, i32, f64, u64, u32, vp, vp,
+                                          i64, ctypes.POINTER(i64)],
                 "rtg_all_pairs_batched": [vp, ctypes.POINTER(rtg_query), i32,
                                           ctypes.POINTER(rtg_csr)],
                 "rtg_submit": [vp, ctypes.POINTER(rtg_query), ctypes.POINTER(u64)],
@@ -269,6 +271,32 @@ class Context:
                "rtg_all_pairs")
         return self._result(out)
 
+    def rtg_all_pairs_noalloc(self, points, r: float, k: int, alpha: float, seed: int,
+                              row_ptr, col, flags: int = 0) -> int:
+        """rtg_all_pairs into caller tensors (row_ptr int64 [n+1], col int32
+        [capacity]) with no device allocation; returns nnz.  Raises RTGError
+        (ENOMEM) when col is too small, with the entries needed in .needed."""
+        p = self._points(points)
+        t = self.torch
+        if row_ptr.dtype != t.int64 or col.dtype != t.int32:
+            raise TypeError("row_ptr must be int64 and col int32")
+        if not (row_ptr.is_cuda and col.is_cuda and row_ptr.is_contiguous() and
+                col.is_contiguous()) or row_ptr.numel() != p.shape[0] + 1:
+            raise ValueError("row_ptr must be a contiguous CUDA tensor of n+1 entries and col "
+                             "a contiguous CUDA tensor")
+        nnz = ctypes.c_int64(0)
+        rc = lib().rtg_all_pairs_noalloc(self.h, p.data_ptr(), p.shape[0], p.shape[1], float(r),
+                                         int(k), float(alpha), seed & (2**64 - 1), flags,
+                                         row_ptr.data_ptr(),
+                                         col.data_ptr() if col.numel() else None, col.numel(),
+                                         ctypes.byref(nnz))
+        if rc == ENOMEM:
+            err = RTGError(rc, "rtg_all_pairs_noalloc")
+            err.needed = int(nnz.value)
+            raise err
+        _check(rc, "rtg_all_pairs_noalloc")
+        return int(nnz.value)
+
     def rtg_all_pairs_with_transforms(self, points, r: float, alpha: float, R, u,
                                       flags: int = 0) -> Result:
         p = self._points(points)
@@ -403,6 +431,7 @@ class Context:
     index_build = rtg_index_build
     index_query = rtg_index_query
     all_pairs = rtg_all_pairs
+    all_pairs_noalloc = rtg_all_pairs_noalloc
     all_pairs_with_transforms = rtg_all_pairs_with_transforms
     all_pairs_batched = rtg_all_pairs_batched
     release_many = rtg_release_many
