@@ -284,6 +284,56 @@ def bench_variants(ctx, pts, wl, reps: int = 10) -> dict:
                        "mr_2_robots_ms": mr_ms, "mr_2_robots_pairs": mr_pairs}}
 
 
+def bench_param_study(ctx, reps: int = 3) -> dict:
+    """The paper's parameter study (Sec. IV-A) on the GPU path: n = 102400
+    points uniform in [0,1]^9, radius of Eq. r_FMT* (eta = 0).  Success rate
+    = reported pairs over the oracle's brute-force pairs (RTG reports a
+    subset of them), and the time of one all-pairs call (points resident,
+    median of reps):
+      vs_m      m = 5..60 grids at c~ = 1.1,
+      vs_c      c~ = 1.0..2.0 at m = 20,
+      table_ii  Table II's rule over a (m, c~) grid: the fastest pair with
+                success >= 0.98,
+      model     the library's modelled choice for 0.98 (rtg_choose_params),
+                measured the same way."""
+    import torch
+    from paper_1409_8112_amd import rtg, workloads
+    with open(os.path.join(ROOT, "tests", "golden", "bruteforce_fmt_uniform.json")) as fh:
+        case = [c for c in json.load(fh)["cases"] if (c["n"], c["d"]) == (102400, 9)][0]
+    n, d, r, truth = case["n"], case["d"], case["r"], case["pairs"]
+    pts = torch.from_numpy(workloads.uniform_points(n, d, case["point_seed"])).to("cuda:0")
+    torch.cuda.synchronize()
+
+    def run(k, alpha):
+        times, pairs = [], 0
+        for i in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = ctx.all_pairs(pts, r, k, alpha, 0)
+            pairs = res.pairs
+            res.release()
+            torch.cuda.synchronize()
+            if i:
+                times.append(time.perf_counter() - t0)
+        return {"k": k, "alpha": alpha, "ms": float(np.median(times)) * 1e3, "pairs": pairs,
+                "success": pairs / truth}
+
+    vs_m = [run(k, 1.1) for k in (5, 10, 15, 20, 25, 30, 35, 40, 45, 50, 60)]
+    vs_c = [run(20, round(c, 3)) for c in np.arange(1.0, 2.0001, 0.1)]
+    grid = [run(k, round(c, 3)) for k in range(10, 61, 5) for c in np.arange(1.0, 1.6001, 0.05)]
+    ok = [g for g in grid if g["success"] >= 0.98]
+    best = min(ok, key=lambda g: g["ms"]) if ok else None
+    nu = 2.0 * truth / n
+    k_m, a_m, rec_m = rtg.choose_params(d, 0.98, nu)
+    model = run(k_m, a_m)
+    model["model_recall"] = rec_m
+    del pts
+    return {"workload": f"n={n} uniform in [0,1]^{d}, r={r:.4f} (Eq. r_FMT*, eta=0), "
+                        f"{truth} brute-force pairs (oracle), {nu:.1f} mean neighbours",
+            "vs_m_at_c1.1": vs_m, "vs_c_at_m20": vs_c, "grid_points": len(grid),
+            "table_ii_choice": best, "model_choice": model}
+
+
 def bench_query(ctx, pts, wl, m: int = 1_000_000, reps: int = 5) -> dict:
     """Query mode: an index of the workload's points (its k sorted grids),
     then m uniform query points per call."""
@@ -490,6 +540,8 @@ def main(argv=None) -> int:
                     help="skip the dedup-rule and metric-variant measurements")
     ap.add_argument("--no-auto", action="store_true",
                     help="skip the run with parameters chosen for a target recall")
+    ap.add_argument("--no-param-study", action="store_true",
+                    help="skip the parameter study (success rate and time vs m and c~)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (a known-size "
                          "kernel for scaling hardware byte counters)")
@@ -630,6 +682,9 @@ def main(argv=None) -> int:
     if not args.no_auto and args.workload == "uniform_d6":
         print("# parameters chosen for recall 0.98", file=sys.stderr, flush=True)
         out["auto_params"] = bench_auto(ctx, pts, wl, 0.98, 20.0)
+    if not args.no_param_study and args.workload == "uniform_d6":
+        print("# parameter study (n=102400, d=9)", file=sys.stderr, flush=True)
+        out["param_study"] = bench_param_study(ctx)
     if not args.no_query and args.workload == "uniform_d6":
         print("# query mode", file=sys.stderr, flush=True)
         out["query"] = bench_query(ctx, pts, wl)
