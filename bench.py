@@ -132,16 +132,26 @@ def bench_batched(ctx, count: int, reps: int = 3) -> dict:
         ctx.release_many(res)
         return pairs
 
+    def timed():
+        times, got = [], 0
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            got = batched_once()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        return float(np.median(times)), got
+
     batched_once()  # warm-up
-    times = []
-    pairs = 0
-    for _ in range(reps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        pairs = batched_once()
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-    t_b = float(np.median(times))
+    t_default, _ = timed()
+    # the autotuner, one dimension at a time (its entries cover the passes of
+    # that dimension), then the batch again with the tuned settings
+    tuned = []
+    t0 = time.perf_counter()
+    for d in sorted({w.d for w in wls}):
+        tuned.append(ctx.autotune([q for q, w in zip(queries, wls) if w.d == d], reps=2))
+    tune_s = time.perf_counter() - t0
+    t_b, pairs = timed()
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -158,7 +168,8 @@ def bench_batched(ctx, count: int, reps: int = 3) -> dict:
             "value": pairs / t_b, "unit": "pairs/s", "ms": t_b * 1e3, "pairs": pairs,
             "plain_value": pairs_plain / t_p, "plain_ms": t_p * 1e3,
             "plain_pairs": pairs_plain, "speedup_vs_plain": t_p / t_b,
-            "same_pairs_as_plain": pairs == pairs_plain}
+            "same_pairs_as_plain": pairs == pairs_plain,
+            "default_settings_ms": t_default * 1e3, "tuning_s": tune_s, "tuned": tuned}
 
 
 def brute_force_rows(points: np.ndarray, r: float, rows: np.ndarray, chunk: int = 16384) -> list:
@@ -295,7 +306,10 @@ def bench_param_study(ctx, reps: int = 3) -> dict:
       table_ii  Table II's rule over a (m, c~) grid: the fastest pair with
                 success >= 0.98,
       model     the library's modelled choice for 0.98 (rtg_choose_params),
-                measured the same way."""
+                measured the same way,
+      tuned     the library's measured choice (rtg_tune_params: modelled
+                recall >= 0.98, fastest measured time), measured the same
+                way."""
     import torch
     from paper_1409_8112_amd import rtg, workloads
     with open(os.path.join(ROOT, "tests", "golden", "bruteforce_fmt_uniform.json")) as fh:
@@ -327,11 +341,15 @@ def bench_param_study(ctx, reps: int = 3) -> dict:
     k_m, a_m, rec_m = rtg.choose_params(d, 0.98, nu)
     model = run(k_m, a_m)
     model["model_recall"] = rec_m
+    # modelled recall, measured time: the library's own Table II rule
+    k_t, a_t, rec_t, _ms = ctx.tune_params(pts, r, 0.98, reps=2)
+    tuned = run(k_t, a_t)
+    tuned["model_recall"] = rec_t
     del pts
     return {"workload": f"n={n} uniform in [0,1]^{d}, r={r:.4f} (Eq. r_FMT*, eta=0), "
                         f"{truth} brute-force pairs (oracle), {nu:.1f} mean neighbours",
             "vs_m_at_c1.1": vs_m, "vs_c_at_m20": vs_c, "grid_points": len(grid),
-            "table_ii_choice": best, "model_choice": model}
+            "table_ii_choice": best, "model_choice": model, "tuned_choice": tuned}
 
 
 def bench_query(ctx, pts, wl, m: int = 1_000_000, reps: int = 5) -> dict:

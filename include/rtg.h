@@ -311,6 +311,62 @@ int rtg_choose_params(int32_t d, double target_recall, double mean_neighbours, u
 /* The modelled recall of (k, alpha) (see rtg_choose_params).  Host only. */
 int rtg_model_recall(int32_t d, int32_t k, double alpha, uint32_t flags, double *recall);
 
+/* Parameters for a target recall by measurement: the rule of the paper's
+ * parameter study (Sec. IV-A, Table II: among the (m, c~) that reach the
+ * success rate, the one with the fastest run), with the modelled recall of
+ * rtg_choose_params in place of a brute-force count.  For every alpha in
+ * {1.0, 1.05, ..., 2.5} the least k <= 128 whose modelled recall reaches
+ * target_recall is timed on the caller's points (device, row-major [n][d],
+ * n >= 2; median of reps calls of rtg_all_pairs with seed 0 and flags); the
+ * fastest (k, alpha) is returned with its modelled recall and time in
+ * milliseconds.  Errors: as rtg_all_pairs; RTG_EINVAL (target outside
+ * (0, 1), reps outside [1, 100]); RTG_ERANGE (no candidate ran). */
+int rtg_tune_params(rtg_ctx *ctx, const float *points, int64_t n, int32_t d, double r,
+                    double target_recall, uint32_t flags, int32_t reps, int32_t *k,
+                    double *alpha, double *recall, double *ms);
+
+/* Launch settings of one pass of the pipeline, for passes of dimension d
+ * whose points number in (2^(log2_points - 1), 2^log2_points].  A pass uses
+ * the entry the context holds for its dimension and size, else the defaults
+ * (the RTG_* environment settings read at rtg_create). */
+typedef struct rtg_tuning {
+  int32_t d;
+  int32_t log2_points;
+  int32_t tests_per_wave; /* pair kernels: a grid of about this many pair tests
+                             per wavefront (1000 .. 10^7)                     */
+  int32_t unit_tiles;     /* cells of at most this many 64-point tiles are one
+                             work unit of the pair kernels (1 .. 64)          */
+  int32_t part_threads;   /* block size of the neighbour-list partition (256 or
+                             1024)                                            */
+  int32_t bucket_blocks;  /* partition blocks of the neighbour-list build
+                             (1 .. 4096)                                      */
+  int32_t bucket_entries; /* target mean entries of a neighbour-list bucket
+                             (256 .. 16384)                                   */
+  int32_t sort;           /* radix sort: 0 onesweep, 1 reduce-then-scan       */
+  double ms;              /* rtg_autotune: median time of the tuned workload */
+} rtg_tuning;
+
+/* The autotuner.  Times the given queries (all of one dimension d; run as
+ * rtg_all_pairs_batched runs them, results released) under each candidate
+ * value of each setting in turn, starting from the entry their passes use
+ * now, keeps a value only when it is faster by more than 2%, and installs
+ * the result for passes of that size (the points of one pass: the queries'
+ * total, at most the batch size).  reps: timed calls per candidate (median),
+ * 1 .. 100.  *out receives the entry.  Errors: RTG_EINVAL (mixed d, nq < 1,
+ * reps out of range), and those of rtg_all_pairs_batched. */
+int rtg_autotune(rtg_ctx *ctx, const rtg_query *queries, int32_t nq, int32_t reps,
+                 rtg_tuning *out);
+/* Install an entry (RTG_EINVAL if a field is out of range; ms is ignored). */
+int rtg_set_tuning(rtg_ctx *ctx, const rtg_tuning *tuning);
+/* The settings a pass of `points` points of dimension d would use. */
+int rtg_get_tuning(rtg_ctx *ctx, int32_t d, int64_t points, rtg_tuning *out);
+/* Write every installed entry to a JSON file, or install the entries of one
+ * (rtg_create also loads the file named by RTG_TUNING_FILE).  Errors:
+ * RTG_EINVAL (unwritable path, malformed file or field out of range: then
+ * nothing is installed), RTG_ENOENT (no such file). */
+int rtg_save_tuning(rtg_ctx *ctx, const char *path);
+int rtg_load_tuning(rtg_ctx *ctx, const char *path);
+
 /* Device timing with HIP events on the context's stream: bit i of `mask`
  * times every launch of kernel id i (RTG_K_*), RTG_TIME_PHASES times the
  * pipeline phases; 0 turns timing off.  Events add a few microseconds per

@@ -365,7 +365,7 @@ Ctx::Ctx(int dev) : device(dev) {
   // histogram + scan + scatter beat onesweep, whose look-back reads cross
   // the XCDs' L2s.  RTG_SORT=onesweep selects onesweep.
   const char* e = std::getenv("RTG_SORT");
-  sort_algo = (e && std::strcmp(e, "onesweep") == 0) ? kSortOnesweep : kSortReduceScan;
+  defaults.sort_algo = (e && std::strcmp(e, "onesweep") == 0) ? kSortOnesweep : kSortReduceScan;
   // RTG_BATCH_POINTS lowers the points per batch of rtg_all_pairs_batched
   // and of the request loop (tests use it to split small batches).
   const char* bp = std::getenv("RTG_BATCH_POINTS");
@@ -386,7 +386,7 @@ Ctx::Ctx(int dev) : device(dev) {
   // RTG_UNIT_TILES: cells of at most this many 64-point tiles are one work
   // unit of the pair kernels (larger cells: one unit per tile).
   if (const char* e = std::getenv("RTG_UNIT_TILES"))
-    cell_unit_tiles = (uint32_t)std::max(1, std::min(64, std::atoi(e)));
+    defaults.unit_tiles = (uint32_t)std::max(1, std::min(64, std::atoi(e)));
   // RTG_PAIR_BLOCKS: grid size of the pair kernels (default: from the work).
   if (const char* e = std::getenv("RTG_PAIR_BLOCKS"))
     pair_blocks = (uint32_t)std::max(1, std::min(1 << 20, std::atoi(e)));
@@ -397,8 +397,11 @@ Ctx::Ctx(int dev) : device(dev) {
   // LDS (tests use it to send buckets down the global-sort fallback).
   const char* bc = std::getenv("RTG_BUCKET_CAP");
   if (const char* e = std::getenv("RTG_BUCKET_BLOCKS"))
-    bucket_blocks = (uint32_t)std::max(1, std::min(4096, std::atoi(e)));
+    defaults.bucket_blocks = (uint32_t)std::max(1, std::min(4096, std::atoi(e)));
   if (const char* e = std::getenv("RTG_BATCH_LANES")) batch_lanes = std::max(1, std::min(3, std::atoi(e)));
+  // RTG_PART_THREADS: block size of the neighbour-list partition kernels
+  if (const char* e = std::getenv("RTG_PART_THREADS"))
+    defaults.part_threads = std::atoi(e) >= 1024 ? 1024 : 256;
   if (const char* e = std::getenv("RTG_UNITS"))
     balanced_units = std::strcmp(e, "roundrobin") != 0;
   bucket_cap = kBucketMaxEntries;
@@ -406,6 +409,12 @@ Ctx::Ctx(int dev) : device(dev) {
     const long v = std::strtol(bc, nullptr, 10);
     if (v >= 1 && v < kBucketMaxEntries) bucket_cap = (uint32_t)v;
   }
+}
+
+Tuning Ctx::tuning_for(int d, int64_t npts) {
+  std::lock_guard<std::mutex> lk(tmu);
+  auto it = tuned.find({d, ceil_log2((uint64_t)std::max<int64_t>(npts, 1))});
+  return it == tuned.end() ? defaults : it->second;
 }
 
 Ctx::~Ctx() {
@@ -837,9 +846,9 @@ int alloc_result(Lane& c, int64_t n, size_t nnz, void** res, int64_t** row_ptr, 
 // directed entries of the unique pairs into buckets of 2^rb rows, then put
 // each bucket in (row, col) order in LDS and write col and row_ptr; buckets
 // too large for LDS go through the global radix sort.
-int csr_by_buckets(Lane& c, Scratch& S, const uint64_t* pairs, size_t count, int64_t n, int pb,
-                   bool both, uint32_t* err, const LaunchTimer* tm, void** res, int64_t** row_ptr,
-                   int32_t** col, size_t* nnz_out, uint32_t* err_host = nullptr,
+int csr_by_buckets(Lane& c, Scratch& S, const Tuning& T, const uint64_t* pairs, size_t count,
+                   int64_t n, int pb, bool both, uint32_t* err, const LaunchTimer* tm, void** res,
+                   int64_t** row_ptr, int32_t** col, size_t* nnz_out, uint32_t* err_host = nullptr,
                    bool* drained = nullptr) {
   if (drained) *drained = false;
   hipStream_t s = c.stream;
@@ -854,11 +863,11 @@ int csr_by_buckets(Lane& c, Scratch& S, const uint64_t* pairs, size_t count, int
   if ((1 << rb) > kBucketMaxRows) return RTG_ENOMEM;  // callers keep n <= 2^22
   const double per_row = (double)E / (double)n;
   while ((2 << rb) <= kBucketMaxRows && rb + 1 + pb <= 32 &&
-         per_row * (double)(1u << (rb + 1)) <= (double)(kBucketMaxEntries / 8 * 7))
+         per_row * (double)(1u << (rb + 1)) <= (double)T.bucket_entries)
     ++rb;
   const uint32_t nbuckets = (uint32_t)((n + ((int64_t)1 << rb) - 1) >> rb);
   const uint32_t nblocks =
-      (uint32_t)std::min<size_t>(c.ctx->bucket_blocks, (count + 4095) / 4096);
+      (uint32_t)std::min<size_t>(T.bucket_blocks, (count + 4095) / 4096);
   const uint32_t chunk = (uint32_t)((count + nblocks - 1) / nblocks);
   const size_t np = (size_t)nbuckets * nblocks;
   uint32_t* part = S.get<uint32_t>(np + 1);
@@ -868,10 +877,11 @@ int csr_by_buckets(Lane& c, Scratch& S, const uint64_t* pairs, size_t count, int
   if (!part || !pscr || !entries || !over) return RTG_ENOMEM;
   if ((rc = alloc_result(c, n, E, res, row_ptr, col))) return rc;
   if (tm) tm->on_begin(RTG_K_CSR);
-  launch_bucket_hist(pairs, count, pb, rb, both ? 1 : 0, nbuckets, chunk, nblocks, part, s);
+  const int pt = (int)T.part_threads;
+  launch_bucket_hist(pairs, count, pb, rb, both ? 1 : 0, nbuckets, chunk, nblocks, pt, part, s);
   scan_exclusive_u32(part, part, np, part + np, pscr, s);
-  launch_bucket_scatter(pairs, count, pb, rb, both ? 1 : 0, nbuckets, chunk, nblocks, part, entries,
-                        s);
+  launch_bucket_scatter(pairs, count, pb, rb, both ? 1 : 0, nbuckets, chunk, nblocks, pt, part,
+                        entries, s);
   launch_fill_u32(over, 0u, 1, s);
   launch_bucket_csr(entries, part, nbuckets, nblocks, part + np, over + 1, over, c.ctx->bucket_cap, pb,
                     rb, n, *row_ptr, *col, s);
@@ -931,8 +941,8 @@ int csr_by_buckets(Lane& c, Scratch& S, const uint64_t* pairs, size_t count, int
 
 // Neighbour lists from pairs sorted by (i, j): upper rows are runs of the
 // sorted list; lower rows come from a second sort of the swapped pairs.
-int csr_from_sorted(Lane& c, Scratch& S, const uint64_t* uniq, size_t U, int64_t n, int pb,
-                    bool both, uint32_t* err, int64_t* row_ptr, int32_t* col) {
+int csr_from_sorted(Lane& c, Scratch& S, const Tuning& T, const uint64_t* uniq, size_t U,
+                    int64_t n, int pb, bool both, uint32_t* err, int64_t* row_ptr, int32_t* col) {
   hipStream_t s = c.stream;
   uint32_t* up_s = S.get<uint32_t>((size_t)n);
   uint32_t* up_e = S.get<uint32_t>((size_t)n);
@@ -957,7 +967,7 @@ int csr_from_sorted(Lane& c, Scratch& S, const uint64_t* uniq, size_t U, int64_t
     if (!sw || !sw_alt || !scr) return RTG_ENOMEM;
     launch_swap_pairs(uniq, U, pb, sw, s);
     const int where = radix_sort(sw, nullptr, sw_alt, nullptr, U, 0, 2 * pb, scr, err, s, nullptr,
-                                 0, 0, c.ctx->sort_algo);
+                                 0, 0, T.sort_algo);
     lower = where ? sw_alt : sw;
     launch_row_runs(lower, U, pb, lo_s, lo_e, s);
   }
@@ -1158,6 +1168,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     kmax = std::max(kmax, j.k);
   }
   if (npts >= (int64_t(1) << 31)) return RTG_ENOMEM;
+  const Tuning T = ctx->tuning_for(d, npts);
   const int pair_bits = std::max(1, ceil_log2((uint64_t)npts));
   std::vector<PairTest> tests(m);
   std::vector<int> sub(m);  // MR-metric axes per robot (0: Euclidean)
@@ -1387,7 +1398,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     // Several segments in the pass: sort within segments (tiles that stay
     // inside one segment), so only the cell bits take passes; the segment
     // bits above them are already in order.
-    const bool segmented = seg_bits > 0 && ctx->sort_algo == kSortReduceScan;
+    const bool segmented = seg_bits > 0 && T.sort_algo == kSortReduceScan;
     uint32_t ntab = 0;
     SortTile* tab_d = nullptr;
     if (segmented) {
@@ -1408,7 +1419,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     const int sort_end = idx_bits + (segmented ? P.layout.cell_bits : key_bits);
     const int where = radix_sort(keys, vals, keys_alt, vals_alt, N, idx_bits, sort_end, sort_scr,
                                  err, stream, &tm, RTG_K_KEY_HIST, RTG_K_KEY_SCATTER,
-                                 ctx->sort_algo, tab_d, ntab);
+                                 T.sort_algo, tab_d, ntab);
     st.key_passes = std::max(st.key_passes, (sort_end - idx_bits + kRadixBits - 1) / kRadixBits);
     const uint64_t* skeys = where ? keys_alt : keys;
     const uint32_t* sidx = idx_bits ? nullptr : (where ? vals_alt : vals);
@@ -1448,11 +1459,11 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     if (ncells_h) {
       kbegin(RTG_K_CELLS);
       if (!counts_direct) launch_fill_u64(reinterpret_cast<uint64_t*>(counters) + 3, 0ull, 1, stream);
-      launch_cell_work(cstart, cend, ncells_h, ctx->cell_unit_tiles, units, tests_c,
+      launch_cell_work(cstart, cend, ncells_h, T.unit_tiles, units, tests_c,
                        counters + 3, stream);
       scan_exclusive_u32(units, units, ncells_h, scan32 + s64, scan32, stream);
       scan_exclusive_u64(tests_c, tests_c, ncells_h, scan64 + s64, scan64, stream);
-      launch_unit_fill(cstart, cend, units, ncells_h, ctx->cell_unit_tiles, skeys,
+      launch_unit_fill(cstart, cend, units, ncells_h, T.unit_tiles, skeys,
                        seg_bits > 0 ? idx_bits + P.layout.cell_bits : 64, sa, segs_d, udesc,
                        uwork, stream);
       kend(RTG_K_CELLS, 24.0 * (double)ncells_h);
@@ -1481,7 +1492,8 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
                         ? ctx->pair_blocks
                         : (uint32_t)std::min<uint64_t>(
                               kMaxPairBlocks,
-                              std::max<uint64_t>(2048, tests_total / (90000ull * kWaves) + 1));
+                              std::max<uint64_t>(2048, tests_total / ((uint64_t)T.tests_per_wave *
+                                                                      kWaves) + 1));
     // (with no more units than waves every wave takes at most one either way,
     // and the every-n-th dealing needs no ranges)
     if (balanced && units_total > pair_waves(pa)) {
@@ -1676,7 +1688,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
         static_cast<void*>(S.get<char>(radix_scratch_bytes(C, 0, 2 * pair_bits))));
     if (!cand_alt || !scr) return RTG_ENOMEM;
     const int where = radix_sort(cand, nullptr, cand_alt, nullptr, C, 0, 2 * pair_bits, scr, err,
-                                 stream, &tm, RTG_K_PAIR_HIST, RTG_K_PAIR_SCATTER, ctx->sort_algo);
+                                 stream, &tm, RTG_K_PAIR_HIST, RTG_K_PAIR_SCATTER, T.sort_algo);
     const uint64_t* sc = where ? cand_alt : cand;
     uint64_t* dst = where ? cand : cand_alt;
     mark(6);
@@ -1714,13 +1726,13 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     if ((rc = alloc_result(*this, npts, 0, &res, &row_ptr, &col))) return rc;
     launch_fill_u64(reinterpret_cast<uint64_t*>(row_ptr), 0ull, (size_t)(npts + 1), stream);
   } else if (bucket_ok) {
-    rc = csr_by_buckets(*this, S, pairs, npairs, npts, pair_bits, both, err, &tm, &res, &row_ptr,
+    rc = csr_by_buckets(*this, S, T, pairs, npairs, npts, pair_bits, both, err, &tm, &res, &row_ptr,
                         &col, &nnz, &err_seen, &drained);
     if (rc) return rc;
   } else {
     nnz = both ? 2 * npairs : npairs;
     if ((rc = alloc_result(*this, npts, nnz, &res, &row_ptr, &col))) return rc;
-    rc = csr_from_sorted(*this, S, pairs, npairs, npts, pair_bits, both, err, row_ptr, col);
+    rc = csr_from_sorted(*this, S, T, pairs, npairs, npts, pair_bits, both, err, row_ptr, col);
     if (rc) {
       dfree(res);
       return rc;
@@ -2107,6 +2119,25 @@ int model_recall(int32_t d, int32_t k, double alpha, uint32_t flags, double* rec
   return RTG_OK;
 }
 
+int least_grids(int32_t d, double alpha, double target, uint32_t flags, int32_t kmax,
+                int32_t* k_out, double* recall_out) {
+  if (d < 1 || d > kMaxDim || !(alpha > 0.0) || !(target > 0.0 && target < 1.0) || kmax < 1)
+    return RTG_EINVAL;
+  const bool rotate = !(flags & RTG_NO_ROTATE);
+  RecallModel M(d);
+  const std::vector<double> p = M.probs(alpha, rotate);
+  if (RecallModel::recall_of(p, kmax, rotate) < target) return RTG_ERANGE;
+  int lo = 1, hi = kmax;
+  while (lo < hi) {
+    const int mid = (lo + hi) / 2;
+    if (RecallModel::recall_of(p, mid, rotate) >= target) hi = mid;
+    else lo = mid + 1;
+  }
+  *k_out = lo;
+  *recall_out = RecallModel::recall_of(p, lo, rotate);
+  return RTG_OK;
+}
+
 int choose_params(int32_t d, double target, double nu, uint32_t flags, int32_t* k_out,
                   double* alpha_out, double* recall_out) {
   if (d < 1 || d > kMaxDim || !(target > 0.0 && target < 1.0) || !(nu > 0.0) ||
@@ -2251,7 +2282,7 @@ int Lane::build_index(const float* points, int64_t n, int32_t d, double r, int32
                 keys, vals, err, I.sig, I.sig_W, I.sig_b, I.sig_gpw, idx_bits};
     launch_keys(ka, stream);
     // several grids in the sort: within grids, on the cell bits only
-    const bool segmented = seg_bits > 0 && ctx->sort_algo == kSortReduceScan;
+    const bool segmented = seg_bits > 0 && ctx->defaults.sort_algo == kSortReduceScan;
     SortTile* tab_d = nullptr;
     uint32_t ntab = 0;
     if (segmented) {
@@ -2271,7 +2302,7 @@ int Lane::build_index(const float* points, int64_t n, int32_t d, double r, int32
     }
     const int sort_end = idx_bits + (segmented ? I.P.layout.cell_bits : key_bits);
     const int where = radix_sort(keys, vals, keys_alt, vals_alt, N, idx_bits, sort_end, scr, err,
-                                 stream, nullptr, 0, 0, ctx->sort_algo, tab_d, ntab);
+                                 stream, nullptr, 0, 0, ctx->defaults.sort_algo, tab_d, ntab);
     uint64_t* sorted = where ? keys_alt : keys;
     uint32_t* sorted_idx = idx_bits ? nullptr : (where ? vals_alt : vals);
     if ((rc = sync())) return rc;  // the other buffers go back below
@@ -2404,8 +2435,8 @@ int Lane::query_index(const Index& I, const float* queries, int64_t m, rtg_stats
     if ((rc = alloc_result(*this, m, 0, &res, &row_ptr, &col))) return rc;
     launch_fill_u64(reinterpret_cast<uint64_t*>(row_ptr), 0ull, (size_t)(m + 1), stream);
   } else if (bucket_ok) {
-    if ((rc = csr_by_buckets(*this, S, cand, C, m, pb, false, err + 1, nullptr, &res, &row_ptr,
-                             &col, &nnz)))
+    if ((rc = csr_by_buckets(*this, S, ctx->defaults, cand, C, m, pb, false, err + 1, nullptr,
+                             &res, &row_ptr, &col, &nnz)))
       return rc;
   } else {
     uint64_t* alt = S.get<uint64_t>(C);
@@ -2413,11 +2444,11 @@ int Lane::query_index(const Index& I, const float* queries, int64_t m, rtg_stats
     if (!alt || !scr) return RTG_ENOMEM;
     launch_fill_u32(err + 1, 0u, 1, stream);
     const int where = radix_sort(cand, nullptr, alt, nullptr, C, 0, 2 * pb, scr, err + 1, stream,
-                                 nullptr, 0, 0, ctx->sort_algo);
+                                 nullptr, 0, 0, ctx->defaults.sort_algo);
     nnz = C;
     if ((rc = alloc_result(*this, m, nnz, &res, &row_ptr, &col))) return rc;
-    if ((rc = csr_from_sorted(*this, S, where ? alt : cand, C, m, pb, false, err + 1, row_ptr,
-                              col))) {
+    if ((rc = csr_from_sorted(*this, S, ctx->defaults, where ? alt : cand, C, m, pb, false,
+                              err + 1, row_ptr, col))) {
       dfree(res);
       return rc;
     }
@@ -2461,6 +2492,7 @@ int rtg_create(rtg_ctx** out, int device, void* arena, size_t arena_bytes, void*
     arena = c->arena_mem;
   }
   c->arena.reset(new rtg::Arena(static_cast<char*>(arena), arena_bytes));
+  c->load_tuning_from_env();
   int rc = c->main.init(c, static_cast<hipStream_t>(hip_stream), false);
   // pinned staging large enough that rtg_all_pairs_noalloc never grows it
   if (!rc) rc = c->main.up_room(rtg::kNoallocStaging);

@@ -385,11 +385,12 @@ void launch_csr_fill_lower(const uint64_t* lo, size_t count, int pair_bits, cons
 // [nbuckets][nblocks] counts / their exclusive scan (bucket-major).
 constexpr int kBucketMaxEntries = 16384;  // entries one block holds in LDS
 constexpr int kBucketMaxRows = 1024;      // rows per bucket (rb <= 10)
+// threads: block size of the two partition kernels (256 or 1024).
 void launch_bucket_hist(const uint64_t* pairs, size_t count, int pb, int rb, int both,
-                        uint32_t nbuckets, uint32_t chunk, uint32_t nblocks, uint32_t* part,
-                        hipStream_t s);
+                        uint32_t nbuckets, uint32_t chunk, uint32_t nblocks, int threads,
+                        uint32_t* part, hipStream_t s);
 void launch_bucket_scatter(const uint64_t* pairs, size_t count, int pb, int rb, int both,
-                           uint32_t nbuckets, uint32_t chunk, uint32_t nblocks,
+                           uint32_t nbuckets, uint32_t chunk, uint32_t nblocks, int threads,
                            const uint32_t* offs, uint32_t* entries, hipStream_t s);
 // Writes col and row_ptr (all but row_ptr[n]) for every bucket of at most
 // cap (<= kBucketMaxEntries) entries: entries of unique pairs, so a bucket's

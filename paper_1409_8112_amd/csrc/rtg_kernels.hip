@@ -2102,23 +2102,24 @@ __global__ void k_csr_fill_lower(const uint64_t* __restrict__ lo, size_t count, 
 // bucket's slice of row_ptr.  The order of entries inside a bucket before the
 // local sort does not matter: the sort makes it canonical.
 
-__global__ __launch_bounds__(kBlock) void k_bucket_hist(const uint64_t* __restrict__ pairs,
-                                                        size_t count, int pb, int rb, int both,
-                                                        uint32_t nbuckets, uint32_t chunk,
-                                                        uint32_t nblocks,
-                                                        uint32_t* __restrict__ part) {
+template <int TH>
+__global__ __launch_bounds__(TH) void k_bucket_hist(const uint64_t* __restrict__ pairs,
+                                                    size_t count, int pb, int rb, int both,
+                                                    uint32_t nbuckets, uint32_t chunk,
+                                                    uint32_t nblocks,
+                                                    uint32_t* __restrict__ part) {
   extern __shared__ uint32_t h[];
-  for (uint32_t b = threadIdx.x; b < nbuckets; b += kBlock) h[b] = 0u;
+  for (uint32_t b = threadIdx.x; b < nbuckets; b += TH) h[b] = 0u;
   __syncthreads();
   const size_t base = (size_t)blockIdx.x * chunk;
   const size_t end = min(count, base + chunk);
   const uint64_t cmask = (1ull << pb) - 1ull;
   // eight loads in flight per thread, then their atomics
-  for (size_t q0 = base; q0 < end; q0 += 8 * kBlock) {
+  for (size_t q0 = base; q0 < end; q0 += 8 * TH) {
     uint64_t k8[8];
 #pragma unroll
     for (int x = 0; x < 8; ++x) {
-      const size_t q = q0 + (size_t)x * kBlock + threadIdx.x;
+      const size_t q = q0 + (size_t)x * TH + threadIdx.x;
       k8[x] = q < end ? pairs[q] : ~0ull;
     }
 #pragma unroll
@@ -2129,29 +2130,30 @@ __global__ __launch_bounds__(kBlock) void k_bucket_hist(const uint64_t* __restri
     }
   }
   __syncthreads();
-  for (uint32_t b = threadIdx.x; b < nbuckets; b += kBlock)
+  for (uint32_t b = threadIdx.x; b < nbuckets; b += TH)
     part[(size_t)b * nblocks + blockIdx.x] = h[b];
 }
 
-__global__ __launch_bounds__(kBlock) void k_bucket_scatter(const uint64_t* __restrict__ pairs,
-                                                           size_t count, int pb, int rb, int both,
-                                                           uint32_t nbuckets, uint32_t chunk,
-                                                           uint32_t nblocks,
-                                                           const uint32_t* __restrict__ offs,
-                                                           uint32_t* __restrict__ entries) {
+template <int TH>
+__global__ __launch_bounds__(TH) void k_bucket_scatter(const uint64_t* __restrict__ pairs,
+                                                       size_t count, int pb, int rb, int both,
+                                                       uint32_t nbuckets, uint32_t chunk,
+                                                       uint32_t nblocks,
+                                                       const uint32_t* __restrict__ offs,
+                                                       uint32_t* __restrict__ entries) {
   extern __shared__ uint32_t cur[];
-  for (uint32_t b = threadIdx.x; b < nbuckets; b += kBlock)
+  for (uint32_t b = threadIdx.x; b < nbuckets; b += TH)
     cur[b] = offs[(size_t)b * nblocks + blockIdx.x];
   __syncthreads();
   const size_t base = (size_t)blockIdx.x * chunk;
   const size_t end = min(count, base + chunk);
   const uint64_t cmask = (1ull << pb) - 1ull;
   const uint32_t rmask = (1u << rb) - 1u;
-  for (size_t q0 = base; q0 < end; q0 += 8 * kBlock) {
+  for (size_t q0 = base; q0 < end; q0 += 8 * TH) {
     uint64_t k8[8];
 #pragma unroll
     for (int x = 0; x < 8; ++x) {
-      const size_t q = q0 + (size_t)x * kBlock + threadIdx.x;
+      const size_t q = q0 + (size_t)x * TH + threadIdx.x;
       k8[x] = q < end ? pairs[q] : ~0ull;
     }
 #pragma unroll
@@ -2970,19 +2972,29 @@ void launch_csr_fill_lower(const uint64_t* lo, size_t count, int pair_bits, cons
 // --- row buckets ------------------------------------------------------------
 
 void launch_bucket_hist(const uint64_t* pairs, size_t count, int pb, int rb, int both,
-                        uint32_t nbuckets, uint32_t chunk, uint32_t nblocks, uint32_t* part,
-                        hipStream_t s) {
+                        uint32_t nbuckets, uint32_t chunk, uint32_t nblocks, int threads,
+                        uint32_t* part, hipStream_t s) {
   if (!nblocks) return;
-  hipLaunchKernelGGL(k_bucket_hist, dim3(nblocks), dim3(kBlock), nbuckets * sizeof(uint32_t), s,
-                     pairs, count, pb, rb, both, nbuckets, chunk, nblocks, part);
+  const size_t lds = nbuckets * sizeof(uint32_t);
+  if (threads >= 1024)
+    hipLaunchKernelGGL(k_bucket_hist<1024>, dim3(nblocks), dim3(1024), lds, s, pairs, count, pb,
+                       rb, both, nbuckets, chunk, nblocks, part);
+  else
+    hipLaunchKernelGGL(k_bucket_hist<kBlock>, dim3(nblocks), dim3(kBlock), lds, s, pairs, count,
+                       pb, rb, both, nbuckets, chunk, nblocks, part);
 }
 
 void launch_bucket_scatter(const uint64_t* pairs, size_t count, int pb, int rb, int both,
-                           uint32_t nbuckets, uint32_t chunk, uint32_t nblocks,
+                           uint32_t nbuckets, uint32_t chunk, uint32_t nblocks, int threads,
                            const uint32_t* offs, uint32_t* entries, hipStream_t s) {
   if (!nblocks) return;
-  hipLaunchKernelGGL(k_bucket_scatter, dim3(nblocks), dim3(kBlock), nbuckets * sizeof(uint32_t), s,
-                     pairs, count, pb, rb, both, nbuckets, chunk, nblocks, offs, entries);
+  const size_t lds = nbuckets * sizeof(uint32_t);
+  if (threads >= 1024)
+    hipLaunchKernelGGL(k_bucket_scatter<1024>, dim3(nblocks), dim3(1024), lds, s, pairs, count,
+                       pb, rb, both, nbuckets, chunk, nblocks, offs, entries);
+  else
+    hipLaunchKernelGGL(k_bucket_scatter<kBlock>, dim3(nblocks), dim3(kBlock), lds, s, pairs,
+                       count, pb, rb, both, nbuckets, chunk, nblocks, offs, entries);
 }
 
 void launch_bucket_csr(const uint32_t* entries, const uint32_t* offs, uint32_t nbuckets,

@@ -57,6 +57,10 @@ int make_transforms(uint64_t seed, int32_t k, int32_t d, uint32_t flags, double*
 int model_recall(int32_t d, int32_t k, double alpha, uint32_t flags, double* recall);
 int choose_params(int32_t d, double target, double nu, uint32_t flags, int32_t* k_out,
                   double* alpha_out, double* recall_out);
+// The least k <= kmax whose modelled recall at cell factor alpha reaches
+// target (RTG_ERANGE if none does), and that recall.
+int least_grids(int32_t d, double alpha, double target, uint32_t flags, int32_t kmax,
+                int32_t* k_out, double* recall_out);
 int min_field_bits(double alpha);
 // Candidate pairs a pass makes room for per (point, grid) key before it
 // learns the exact count (a pass that needs more runs its pair kernel again).
@@ -131,6 +135,17 @@ struct Index {
   rtgk::KeyLayout* layout = nullptr;
   rtgk::QueryGrid* grids = nullptr;  // device [k]
   std::vector<void*> blocks;         // arena blocks the index owns
+};
+
+// Launch settings of one pass (rtg_tuning in rtg.h): the context's
+// defaults, or what the autotuner found for the pass's dimension and size.
+struct Tuning {
+  uint32_t tests_per_wave = 90000;  // pair kernels: grid of about this many tests per wave
+  uint32_t unit_tiles = 1;          // cells of at most this many tiles are one unit
+  uint32_t part_threads = 256;      // neighbour-list partition block size (256 or 1024)
+  uint32_t bucket_blocks = 256;     // neighbour-list partition blocks
+  uint32_t bucket_entries = rtgk::kBucketMaxEntries / 8 * 7;  // target entries per bucket
+  int sort_algo = rtgk::kSortReduceScan;
 };
 
 struct Ctx;
@@ -210,18 +225,28 @@ struct Ctx {
   void* noalloc_base = nullptr;
   std::unique_ptr<Arena> noalloc_arena;
   std::atomic<bool> poisoned{false};
-  int sort_algo = 0;  // rtgk::kSortOnesweep or rtgk::kSortReduceScan
   uint32_t bucket_cap = rtgk::kBucketMaxEntries;  // entries per LDS-sorted bucket
   int64_t batch_points = kBatchPoints;             // points per batch
   int server_lanes = 2;  // passes of the request loop that may run at once
   int pair_screen = 0;   // 0 auto, 1 vector, 2 matrix cores (d <= 16)
   bool gather_direct = true;  // pair kernels read rows by point index
-  uint32_t cell_unit_tiles = 1;  // cells of at most this many tiles: one work unit
-  uint32_t pair_blocks = 0;      // pair-kernel grid cap (0: default)
+  uint32_t pair_blocks = 0;      // pair-kernel grid (0: from the tuning's tests per wave)
   bool balanced_units = true;    // pair-kernel waves take equal shares of the tile pairs
-  // partition blocks of the neighbour-list build (each writes its own run of
-  // every bucket; more blocks keep more waves waiting on LDS atomics at once)
-  uint32_t bucket_blocks = 256;
+  // Launch settings: the defaults (environment), and the autotuner's entries
+  // by (dimension, log2 of the points of a pass), under tmu.
+  Tuning defaults;
+  std::map<std::pair<int, int>, Tuning> tuned;
+  std::mutex tmu;
+  Tuning tuning_for(int d, int64_t npts);
+  // the autotuner (rtg_tune.cpp)
+  int autotune(const rtg_query* q, int32_t nq, int32_t reps, rtg_tuning* out);
+  int set_tuning(const rtg_tuning& t);
+  int save_tuning(const char* path);
+  int load_tuning(const char* path);
+  void load_tuning_from_env();
+  int tune_params(const float* points, int64_t n, int32_t d, double r, double target,
+                  uint32_t flags, int32_t reps, int32_t* k, double* alpha, double* recall,
+                  double* ms);
   Lane main;          // the caller's stream: blocking calls
   // More lanes for rtg_all_pairs_batched: batches run batch_lanes at a time
   // (the caller's lane and batch_lanes - 1 more), so one pass's host work and

@@ -55,6 +55,15 @@ class rtg_query(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32)]
 
 
+class rtg_tuning(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int32) for name in (
+        "d", "log2_points", "tests_per_wave", "unit_tiles", "part_threads", "bucket_blocks",
+        "bucket_entries", "sort")] + [("ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class rtg_stats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n", "d", "k", "point_transforms", "cells", "tests", "candidates", "band_rechecks",
@@ -109,6 +118,14 @@ def lib() -> ctypes.CDLL:
                 "rtg_index_build": [vp, vp, i64, i32, f64, i32, f64, u64, u32,
                                     ctypes.POINTER(u64)],
                 "rtg_index_query": [vp, u64, vp, i64, ctypes.POINTER(rtg_csr)],
+                "rtg_autotune": [vp, ctypes.POINTER(rtg_query), i32, i32,
+                                 ctypes.POINTER(rtg_tuning)],
+                "rtg_set_tuning": [vp, ctypes.POINTER(rtg_tuning)],
+                "rtg_get_tuning": [vp, i32, i64, ctypes.POINTER(rtg_tuning)],
+                "rtg_save_tuning": [vp, ctypes.c_char_p],
+                "rtg_load_tuning": [vp, ctypes.c_char_p],
+                "rtg_tune_params": [vp, vp, i64, i32, f64, f64, u32, i32, ctypes.POINTER(i32),
+                                    ctypes.POINTER(f64), ctypes.POINTER(f64), ctypes.POINTER(f64)],
                 "rtg_set_timing": [vp, u32],
                 "rtg_get_stats": [vp, ctypes.POINTER(rtg_stats)],
                 "rtg_debug_cell_coords": [vp, vp, i64, i32, f64, f64, vp, vp, vp],
@@ -312,6 +329,58 @@ class Context:
                "rtg_all_pairs_with_transforms")
         return self._result(out)
 
+    def _query_table(self, queries):
+        nq = len(queries)
+        qs = np.zeros(max(nq, 1), dtype=np.dtype(rtg_query))
+        pts = [self._points(q["points"]) for q in queries]
+        if nq:
+            qs["points"][:nq] = [p.data_ptr() for p in pts]
+            qs["n"][:nq] = [p.shape[0] for p in pts]
+            qs["d"][:nq] = [p.shape[1] for p in pts]
+            qs["r"][:nq] = [q["r"] for q in queries]
+            qs["k"][:nq] = [q["k"] for q in queries]
+            qs["alpha"][:nq] = [q["alpha"] for q in queries]
+            qs["seed"][:nq] = [q.get("seed", 0) & (2**64 - 1) for q in queries]
+            qs["flags"][:nq] = [q.get("flags", 0) for q in queries]
+        return qs, pts
+
+    def rtg_autotune(self, queries, reps: int = 3) -> dict:
+        """Tunes the launch settings for these queries (one dimension) and
+        installs them; returns the entry (rtg_tuning) as a dict."""
+        qs, _pts = self._query_table(queries)
+        out = rtg_tuning()
+        _check(lib().rtg_autotune(self.h, qs.ctypes.data_as(ctypes.POINTER(rtg_query)),
+                                  len(queries), int(reps), ctypes.byref(out)), "rtg_autotune")
+        return out.as_dict()
+
+    def rtg_set_tuning(self, entry: dict) -> None:
+        t = rtg_tuning(**{k: v for k, v in entry.items() if k in dict(rtg_tuning._fields_)})
+        _check(lib().rtg_set_tuning(self.h, ctypes.byref(t)), "rtg_set_tuning")
+
+    def rtg_get_tuning(self, d: int, points: int) -> dict:
+        out = rtg_tuning()
+        _check(lib().rtg_get_tuning(self.h, int(d), int(points), ctypes.byref(out)),
+               "rtg_get_tuning")
+        return out.as_dict()
+
+    def rtg_save_tuning(self, path: str) -> None:
+        _check(lib().rtg_save_tuning(self.h, os.fsencode(path)), "rtg_save_tuning")
+
+    def rtg_load_tuning(self, path: str) -> None:
+        _check(lib().rtg_load_tuning(self.h, os.fsencode(path)), "rtg_load_tuning")
+
+    def rtg_tune_params(self, points, r: float, target_recall: float, flags: int = 0,
+                        reps: int = 2):
+        """(k, alpha, modelled recall, ms): the fastest measured parameters
+        whose modelled recall reaches the target."""
+        p = self._points(points)
+        k, a, rec, ms = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().rtg_tune_params(self.h, p.data_ptr(), p.shape[0], p.shape[1], float(r),
+                                     float(target_recall), flags, int(reps), ctypes.byref(k),
+                                     ctypes.byref(a), ctypes.byref(rec), ctypes.byref(ms)),
+               "rtg_tune_params")
+        return int(k.value), float(a.value), float(rec.value), float(ms.value)
+
     def rtg_all_pairs_batched(self, queries) -> list[Result]:
         """queries: list of dicts with points, r, k, alpha, seed, flags."""
         nq = len(queries)
@@ -432,6 +501,12 @@ class Context:
     index_query = rtg_index_query
     all_pairs = rtg_all_pairs
     all_pairs_noalloc = rtg_all_pairs_noalloc
+    autotune = rtg_autotune
+    set_tuning = rtg_set_tuning
+    get_tuning = rtg_get_tuning
+    save_tuning = rtg_save_tuning
+    load_tuning = rtg_load_tuning
+    tune_params = rtg_tune_params
     all_pairs_with_transforms = rtg_all_pairs_with_transforms
     all_pairs_batched = rtg_all_pairs_batched
     release_many = rtg_release_many

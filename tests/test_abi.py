@@ -73,7 +73,7 @@ def test_binding_refuses_to_run_without_a_gpu():
 
 
 def test_binding_structs_match_the_header(tmp_path):
-    """The ctypes mirrors of rtg_csr, rtg_query and rtg_stats have the C
+    """The ctypes mirrors of rtg_csr, rtg_query, rtg_stats and rtg_tuning have the C
     layout of include/rtg.h (sizes and field offsets, compiled with gcc)."""
     import shutil
     import subprocess
@@ -83,7 +83,8 @@ def test_binding_structs_match_the_header(tmp_path):
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     fields = {"rtg_csr": [f for f, _ in rtg.rtg_csr._fields_],
               "rtg_query": [f for f, _ in rtg.rtg_query._fields_],
-              "rtg_stats": [f for f, _ in rtg.rtg_stats._fields_]}
+              "rtg_stats": [f for f, _ in rtg.rtg_stats._fields_],
+              "rtg_tuning": [f for f, _ in rtg.rtg_tuning._fields_]}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rtg.h"', "int main(void) {"]
     for st, fs in fields.items():
         lines.append(f'  printf("{st} %zu\\n", sizeof({st}));')
