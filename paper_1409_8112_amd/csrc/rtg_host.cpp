@@ -6,6 +6,7 @@
 #include "rtg_runtime.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -545,6 +546,8 @@ int Lane::init(Ctx* c, hipStream_t s, bool create_stream) {
   if (hipHostMalloc(&host_up, 65536) != hipSuccess) return RTG_EDEVICE;
   host_up_bytes = 65536;
   if (hipEventCreateWithFlags(&up_done, hipEventDisableTiming) != hipSuccess) return RTG_EDEVICE;
+  if (hipHostMalloc((void**)&mail, kMailBytes + 256) != hipSuccess) return RTG_EDEVICE;
+  mail[0] = 0;
   gather_dev = c->dalloc(64);
   if (!gather_dev) return RTG_ENOMEM;
   for (auto& e : ev)
@@ -558,6 +561,8 @@ void Lane::fini() {
   host_stage = nullptr;
   if (host_up) (void)hipHostFree(host_up);
   host_up = nullptr;
+  if (mail) (void)hipHostFree(mail);
+  mail = nullptr;
   if (up_done) (void)hipEventDestroy(up_done);
   up_done = nullptr;
   for (auto& e : ev)
@@ -576,7 +581,39 @@ void Lane::dfree(void* p) { ctx->dfree(p); }
 
 int Lane::sync() { return hip_fail(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
 
+// Read-backs go through the pinned mailbox: a one-block kernel copies the
+// values and then posts a sequence number, which the host waits for by
+// spinning -- no stream synchronisation and its wake-up latency on the
+// critical path.  A wait longer than kMailSpinUs (a long pass queued before
+// the read) synchronises the stream instead.
+constexpr double kMailSpinUs = 20000.0;
+
+int Lane::wait_mail(uint64_t seq) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    if (__atomic_load_n(&mail[0], __ATOMIC_ACQUIRE) == seq) return RTG_OK;
+    const double us = std::chrono::duration<double, std::micro>(
+                          std::chrono::steady_clock::now() - t0).count();
+    if (us > kMailSpinUs) break;
+  }
+  int rc = sync();
+  if (rc) return rc;
+  return __atomic_load_n(&mail[0], __ATOMIC_ACQUIRE) == seq
+             ? RTG_OK
+             : hip_fail(hipErrorUnknown, "read-back mailbox");
+}
+
 int Lane::read_back(const void* dev, size_t bytes, void* host) {
+  if (bytes <= kMailBytes && bytes % 4 == 0 && !(reinterpret_cast<uintptr_t>(dev) & 3u)) {
+    const uint64_t seq = ++mail_seq;
+    launch_mailbox(static_cast<const uint32_t*>(dev), (uint32_t)(bytes / 4), nullptr,
+                   reinterpret_cast<uint32_t*>(mail + 32), mail, seq, stream);
+    int rc = hip_fail(hipGetLastError(), "read-back launch");
+    if (!rc) rc = wait_mail(seq);
+    if (rc) return rc;
+    std::memcpy(host, mail + 32, bytes);
+    return RTG_OK;
+  }
   if (bytes > host_stage_bytes) {
     // every earlier read-back has completed (each one waits)
     const size_t grown = std::max(bytes, 2 * host_stage_bytes);
@@ -595,8 +632,13 @@ int Lane::read_back(const void* dev, size_t bytes, void* host) {
 }
 
 int Lane::gather_back(const rtgk::Gather& g, uint64_t* host) {
-  rtgk::launch_gather(g, static_cast<uint64_t*>(gather_dev), stream);
-  return read_back(gather_dev, sizeof(uint64_t) * g.count, host);
+  const uint64_t seq = ++mail_seq;
+  launch_mailbox(nullptr, 0, &g, reinterpret_cast<uint32_t*>(mail + 32), mail, seq, stream);
+  int rc = hip_fail(hipGetLastError(), "read-back launch");
+  if (!rc) rc = wait_mail(seq);
+  if (rc) return rc;
+  std::memcpy(host, mail + 32, sizeof(uint64_t) * (size_t)g.count);
+  return RTG_OK;
 }
 
 int Lane::download(void* host, const void* dev, size_t bytes) {
@@ -1444,36 +1486,35 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
       launch_run_write(skeys, N, idx_bits, hcnt, tcnt, cstart, cend, nullptr, nullptr, stream);
     }
     kend(RTG_K_CELLS, 16.0 * (double)N);
+    // Cell work, unit counts and their scans and the unit descriptors run on
+    // the device's own cell count (tot[0]; the host knows only the bound
+    // max_cells), so one read-back after them serves the whole cell stage.
+    kbegin(RTG_K_CELLS);
+    if (!counts_direct) launch_fill_u64(reinterpret_cast<uint64_t*>(counters) + 3, 0ull, 1, stream);
+    const uint32_t cell_bound = (uint32_t)std::min<size_t>(max_cells, N / 2 + 1);
+    launch_cell_work(cstart, cend, cell_bound, tot, T.unit_tiles, units, tests_c, counters + 3,
+                     stream);
+    scan_exclusive_u32(units, units, cell_bound, scan32 + s64, scan32, stream, tot);
+    scan_exclusive_u64(tests_c, tests_c, cell_bound, scan64 + s64, scan64, stream, tot);
+    launch_unit_fill(cstart, cend, units, cell_bound, tot, T.unit_tiles, skeys,
+                     seg_bits > 0 ? idx_bits + P.layout.cell_bits : 64, sa, segs_d, udesc, uwork,
+                     stream);
+    kend(RTG_K_CELLS, 0.0);
     uint64_t got[8];
     Gather g1;
     g1.add(tot, 4);
     g1.add(err, 4);
+    g1.add(scan64 + s64, 8);
+    g1.add(scan32 + s64, 4);
     if ((rc = gather_back(g1, got))) return rc;
     const uint32_t ncells_h = (uint32_t)got[0], errh0 = (uint32_t)got[1];
     // A cell coordinate out of range makes the grouping meaningless: stop
     // before the pair kernel sees it.
     if (errh0 & 1u) return RTG_ERANGE;
     if (errh0) return hip_fail(hipErrorUnknown, "radix sort look-back");
-    uint64_t tests_total = 0;
-    uint32_t units_total = 0;
-    if (ncells_h) {
-      kbegin(RTG_K_CELLS);
-      if (!counts_direct) launch_fill_u64(reinterpret_cast<uint64_t*>(counters) + 3, 0ull, 1, stream);
-      launch_cell_work(cstart, cend, ncells_h, T.unit_tiles, units, tests_c,
-                       counters + 3, stream);
-      scan_exclusive_u32(units, units, ncells_h, scan32 + s64, scan32, stream);
-      scan_exclusive_u64(tests_c, tests_c, ncells_h, scan64 + s64, scan64, stream);
-      launch_unit_fill(cstart, cend, units, ncells_h, T.unit_tiles, skeys,
-                       seg_bits > 0 ? idx_bits + P.layout.cell_bits : 64, sa, segs_d, udesc,
-                       uwork, stream);
-      kend(RTG_K_CELLS, 24.0 * (double)ncells_h);
-      Gather g2;
-      g2.add(scan64 + s64, 8);
-      g2.add(scan32 + s64, 4);
-      if ((rc = gather_back(g2, got))) return rc;
-      tests_total = got[0];
-      units_total = (uint32_t)got[1];
-    }
+    const uint64_t tests_total = ncells_h ? got[2] : 0;
+    const uint32_t units_total = ncells_h ? (uint32_t)got[3] : 0u;
+    st.kernel_bytes[RTG_K_CELLS] += 24.0 * (double)ncells_h;
     mark(4);
     st.cells += ncells_h;
     st.tests += (int64_t)tests_total;

@@ -56,6 +56,11 @@ struct Gather {
   }
 };
 void launch_gather(const Gather& g, uint64_t* dst, hipStream_t s);
+// Writes words 32-bit words of src (or, with src null, the scalars of *g as
+// u64) to pinned host memory at host, then seq to *host_seq with a
+// system-scope release once every value is visible (one block).
+void launch_mailbox(const uint32_t* src, uint32_t words, const Gather* g, uint32_t* host,
+                    uint64_t* host_seq, uint64_t seq, hipStream_t s);
 // rec[i][0..d) = rows[i][0..d), rec[i][d..rs) = 0 (padding, then the
 // signature word in the last two floats), for i < n.
 void launch_records(const float* rows, int64_t n, int d, int rs, float* rec, hipStream_t s);
@@ -129,12 +134,14 @@ void launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s);
 void launch_fill_u64(uint64_t* p, uint64_t v, size_t count, hipStream_t s);
 
 // Exclusive prefix sum of count elements; total (device, optional) receives
-// the sum.  scratch must hold scan_scratch_elems(count) elements.
+// the sum.  scratch must hold scan_scratch_elems(count) elements.  With
+// dcount (device) the elements are the first min(count, *dcount): count is
+// then only the host's bound.
 size_t scan_scratch_elems(size_t count);
 void scan_exclusive_u32(const uint32_t* in, uint32_t* out, size_t count, uint32_t* total,
-                        uint32_t* scratch, hipStream_t s);
+                        uint32_t* scratch, hipStream_t s, const uint32_t* dcount = nullptr);
 void scan_exclusive_u64(const uint64_t* in, uint64_t* out, size_t count, uint64_t* total,
-                        uint64_t* scratch, hipStream_t s);
+                        uint64_t* scratch, hipStream_t s, const uint32_t* dcount = nullptr);
 
 // --- radix sort -----------------------------------------------------------
 // Stable LSD sort of count 64-bit keys (and optional u32 values) on bits
@@ -180,10 +187,11 @@ void launch_run_write(const uint64_t* keys, size_t count, int shift, const uint3
                       const uint32_t* tail_off, uint32_t* start, uint32_t* end, uint32_t* tot,
                       unsigned long long* zero, hipStream_t s);
 // units[c] = work units of run c (see UnitDesc), tests[c] = L(L-1)/2, and
-// *members += sum of L, for c < ncells.
+// *members += sum of L, for c < ncells (c < min(ncells, *dcells) when the
+// device count dcells is given; ncells is then the host's bound).
 void launch_cell_work(const uint32_t* start, const uint32_t* end, uint32_t ncells,
-                      uint32_t cell_unit_tiles, uint32_t* units, uint64_t* tests,
-                      unsigned long long* members, hipStream_t s);
+                      const uint32_t* dcells, uint32_t cell_unit_tiles, uint32_t* units,
+                      uint64_t* tests, unsigned long long* members, hipStream_t s);
 // A work unit of the pair kernels: the 64-point tiles ta in [ta_begin,
 // ta_end) of a cell, each tested against the cell's tiles tb >= ta.  A cell
 // of at most cell_unit_tiles tiles is one unit; a larger cell has one unit
@@ -201,9 +209,9 @@ struct UnitDesc {
 // sa + (its key >> seg_shift) (sa when seg_shift >= 64).
 // work (optional) receives each unit's tile pairs.
 void launch_unit_fill(const uint32_t* start, const uint32_t* end, const uint32_t* unit_off,
-                      uint32_t ncells, uint32_t cell_unit_tiles, const uint64_t* skeys,
-                      int seg_shift, int sa, const SegDesc* segs, UnitDesc* desc, uint64_t* work,
-                      hipStream_t s);
+                      uint32_t ncells, const uint32_t* dcells, uint32_t cell_unit_tiles,
+                      const uint64_t* skeys, int seg_shift, int sa, const SegDesc* segs,
+                      UnitDesc* desc, uint64_t* work, hipStream_t s);
 
 // --- cell pairs -----------------------------------------------------------
 // Neighbourhood signatures for the first-owner rule, which keeps a pair

@@ -359,10 +359,14 @@ constexpr int kScanTile = kBlock * kScanItems;
 // itself (at most 8 KB read per block).
 constexpr int kFusedScanSums = 2048;
 
+// With dcount the element count is min(count, *dcount): count is then the
+// grid's capacity and the elements beyond the device count read as zero.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const T* __restrict__ in, size_t count,
-                                                        T* __restrict__ sums) {
+                                                        T* __restrict__ sums,
+                                                        const uint32_t* __restrict__ dcount) {
   __shared__ T wsum[kWaves];
+  if (dcount) count = min(count, (size_t)*dcount);
   const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
   T s = 0;
 #pragma unroll
@@ -378,8 +382,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const T* __restrict__ in
 // up by the block itself (no separate scan of the sums; for few blocks).
 template <typename T, bool FROM_SUMS = false>
 __global__ __launch_bounds__(kBlock) void k_scan_apply(const T* in, T* out, size_t count,
-                                                       const T* __restrict__ offsets, T* total) {
+                                                       const T* __restrict__ offsets, T* total,
+                                                       const uint32_t* __restrict__ dcount) {
   __shared__ T wsum[kWaves];
+  if (dcount) count = min(count, (size_t)*dcount);
   T from_sums = 0;
   if (FROM_SUMS) {
     T part = 0;
@@ -836,17 +842,22 @@ __global__ __launch_bounds__(kBlock) void k_run_write(const uint64_t* __restrict
 
 __global__ __launch_bounds__(kBlock) void k_cell_work(const uint32_t* __restrict__ start,
                                                       const uint32_t* __restrict__ end,
-                                                      uint32_t ncells, uint32_t cell_unit_tiles,
+                                                      uint32_t ncells,
+                                                      const uint32_t* __restrict__ dcells,
+                                                      uint32_t cell_unit_tiles,
                                                       uint32_t* __restrict__ units,
                                                       uint64_t* __restrict__ tests,
                                                       unsigned long long* members) {
-  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  // cells [0, ncells), or [0, min(ncells, *dcells)) with the device count
+  if (dcells) ncells = min(ncells, *dcells);
   uint64_t L = 0;
-  if (c < ncells) {
-    L = end[c] - start[c];
-    const uint32_t nt = (uint32_t)((L + kPairTile - 1) / kPairTile);
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncells;
+       c += gridDim.x * blockDim.x) {
+    const uint64_t Lc = end[c] - start[c];
+    const uint32_t nt = (uint32_t)((Lc + kPairTile - 1) / kPairTile);
     units[c] = nt <= cell_unit_tiles ? 1u : nt;
-    tests[c] = L * (L - 1) / 2;
+    tests[c] = Lc * (Lc - 1) / 2;
+    L += Lc;
   }
   // one atomic per block: a single counter's device-scope atomics serialise
   // across the XCDs
@@ -1945,12 +1956,13 @@ __global__ __launch_bounds__(kBlock) void k_seg_compact(const uint64_t* __restri
 // Unit descriptors of cell c: the whole cell, or one unit per tile.
 __global__ void k_unit_fill(const uint32_t* __restrict__ start, const uint32_t* __restrict__ end,
                             const uint32_t* __restrict__ unit_off, uint32_t ncells,
-                            uint32_t cell_unit_tiles, const uint64_t* __restrict__ skeys,
-                            int seg_shift, int sa,
+                            const uint32_t* __restrict__ dcells, uint32_t cell_unit_tiles,
+                            const uint64_t* __restrict__ skeys, int seg_shift, int sa,
                             const SegDesc* __restrict__ segs, UnitDesc* __restrict__ desc,
                             uint64_t* __restrict__ work) {
-  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncells) return;
+  if (dcells) ncells = min(ncells, *dcells);
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncells;
+       c += gridDim.x * blockDim.x) {
   const uint32_t s0 = start[c], L = end[c] - s0;
   const uint32_t nt = (L + kPairTile - 1) / kPairTile;
   const int seg = sa + (seg_shift >= 64 ? 0 : (int)(skeys[s0] >> seg_shift));
@@ -1973,6 +1985,7 @@ __global__ void k_unit_fill(const uint32_t* __restrict__ start, const uint32_t* 
       desc[o + q] = D;
       if (work) work[o + q] = nt - q;
     }
+  }
   }
 }
 
@@ -2420,6 +2433,28 @@ __global__ void k_gather(Gather g, uint64_t* __restrict__ dst) {
                            : (uint64_t)*static_cast<const uint32_t*>(g.src[q]);
 }
 
+// Read-backs into pinned host memory: the values (words of a device buffer,
+// or the scalars of a Gather), then -- after every thread's stores are
+// visible at system scope -- the sequence number the host waits for.
+__global__ __launch_bounds__(kBlock) void k_mailbox(const uint32_t* __restrict__ src,
+                                                    uint32_t words, Gather g,
+                                                    uint32_t* __restrict__ host,
+                                                    uint64_t* __restrict__ host_seq,
+                                                    uint64_t seq) {
+  if (src) {
+    for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) host[i] = src[i];
+  } else if (threadIdx.x < (unsigned)g.count) {
+    const int q = threadIdx.x;
+    const uint64_t v = g.bytes[q] == 8 ? *static_cast<const uint64_t*>(g.src[q])
+                                       : (uint64_t)*static_cast<const uint32_t*>(g.src[q]);
+    reinterpret_cast<uint64_t*>(host)[q] = v;
+  }
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_store(host_seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Point records for tile loads: the coordinates, then zeros up to rs floats
 // (the last two hold the point's signature word, written by the key kernel).
 __global__ void k_records(const float* __restrict__ rows, int64_t n, int d, int rs,
@@ -2600,38 +2635,40 @@ size_t scan_scratch_elems(size_t count) {
 }
 
 template <typename T>
-static void scan_rec(const T* in, T* out, size_t count, T* total, T* scratch, hipStream_t s) {
+static void scan_rec(const T* in, T* out, size_t count, T* total, T* scratch, hipStream_t s,
+                     const uint32_t* dcount = nullptr) {
   if (count == 0) {
     if (total) hipLaunchKernelGGL(k_fill<T>, dim3(1), dim3(64), 0, s, total, (T)0, (size_t)1);
     return;
   }
   if (count <= (size_t)kScanTile) {
     hipLaunchKernelGGL(k_scan_apply<T>, dim3(1), dim3(kBlock), 0, s, in, out, count,
-                       (const T*)nullptr, total);
+                       (const T*)nullptr, total, dcount);
     return;
   }
   const size_t nb = (count + kScanTile - 1) / kScanTile;
   T* sums = scratch;
-  hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(kBlock), 0, s, in, count, sums);
+  hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(kBlock), 0, s, in, count, sums,
+                     dcount);
   if (nb <= (size_t)kFusedScanSums) {
     // each block adds up the sums before it: two launches instead of three
     hipLaunchKernelGGL((k_scan_apply<T, true>), dim3((unsigned)nb), dim3(kBlock), 0, s, in, out,
-                       count, (const T*)sums, total);
+                       count, (const T*)sums, total, dcount);
     return;
   }
   scan_rec<T>(sums, sums, nb, (T*)nullptr, scratch + nb, s);
   hipLaunchKernelGGL(k_scan_apply<T>, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, count,
-                     (const T*)sums, total);
+                     (const T*)sums, total, dcount);
 }
 
 void scan_exclusive_u32(const uint32_t* in, uint32_t* out, size_t count, uint32_t* total,
-                        uint32_t* scratch, hipStream_t s) {
-  scan_rec<uint32_t>(in, out, count, total, scratch, s);
+                        uint32_t* scratch, hipStream_t s, const uint32_t* dcount) {
+  scan_rec<uint32_t>(in, out, count, total, scratch, s, dcount);
 }
 
 void scan_exclusive_u64(const uint64_t* in, uint64_t* out, size_t count, uint64_t* total,
-                        uint64_t* scratch, hipStream_t s) {
-  scan_rec<uint64_t>(in, out, count, total, scratch, s);
+                        uint64_t* scratch, hipStream_t s, const uint32_t* dcount) {
+  scan_rec<uint64_t>(in, out, count, total, scratch, s, dcount);
 }
 
 size_t radix_scratch_bytes(size_t count, int begin_bit, int end_bit, size_t extra_tiles) {
@@ -2744,21 +2781,28 @@ void launch_run_write(const uint64_t* keys, size_t count, int shift, const uint3
                        (unsigned long long*)nullptr);
 }
 
+// Grid of the cell kernels: one thread per cell up to 2048 blocks, then
+// every thread takes more (with a device count the host knows only a bound).
+static unsigned cell_grid(uint32_t ncells) {
+  return (unsigned)std::min<size_t>(grid_for(ncells), 2048);
+}
+
 void launch_cell_work(const uint32_t* start, const uint32_t* end, uint32_t ncells,
-                      uint32_t cell_unit_tiles, uint32_t* units, uint64_t* tests,
-                      unsigned long long* members, hipStream_t s) {
+                      const uint32_t* dcells, uint32_t cell_unit_tiles, uint32_t* units,
+                      uint64_t* tests, unsigned long long* members, hipStream_t s) {
   if (!ncells) return;
-  hipLaunchKernelGGL(k_cell_work, dim3(grid_for(ncells)), dim3(kBlock), 0, s, start, end, ncells,
-                     cell_unit_tiles, units, tests, members);
+  hipLaunchKernelGGL(k_cell_work, dim3(cell_grid(ncells)), dim3(kBlock), 0, s, start, end, ncells,
+                     dcells, cell_unit_tiles, units, tests, members);
 }
 
 void launch_unit_fill(const uint32_t* start, const uint32_t* end, const uint32_t* unit_off,
-                      uint32_t ncells, uint32_t cell_unit_tiles, const uint64_t* skeys,
-                      int seg_shift, int sa, const SegDesc* segs, UnitDesc* desc, uint64_t* work,
-                      hipStream_t s) {
+                      uint32_t ncells, const uint32_t* dcells, uint32_t cell_unit_tiles,
+                      const uint64_t* skeys, int seg_shift, int sa, const SegDesc* segs,
+                      UnitDesc* desc, uint64_t* work, hipStream_t s) {
   if (!ncells) return;
-  hipLaunchKernelGGL(k_unit_fill, dim3(grid_for(ncells)), dim3(kBlock), 0, s, start, end, unit_off,
-                     ncells, cell_unit_tiles, skeys, seg_shift, sa, segs, desc, work);
+  hipLaunchKernelGGL(k_unit_fill, dim3(cell_grid(ncells)), dim3(kBlock), 0, s, start, end,
+                     unit_off, ncells, dcells, cell_unit_tiles, skeys, seg_shift, sa, segs, desc,
+                     work);
 }
 
 uint32_t pair_waves(const PairsArgs& a) {
@@ -3033,6 +3077,12 @@ void launch_over_emit(const uint64_t* keys, uint32_t tot, const uint32_t* ids,
 void launch_u32_to_u64(const uint32_t* src, size_t count, uint64_t* dst, hipStream_t s) {
   if (count == 0) return;
   hipLaunchKernelGGL(k_widen, dim3(grid_for(count)), dim3(kBlock), 0, s, src, count, dst);
+}
+
+void launch_mailbox(const uint32_t* src, uint32_t words, const Gather* g, uint32_t* host,
+                    uint64_t* host_seq, uint64_t seq, hipStream_t s) {
+  hipLaunchKernelGGL(k_mailbox, dim3(1), dim3(kBlock), 0, s, src, words, g ? *g : Gather{}, host,
+                     host_seq, seq);
 }
 
 void launch_gather(const Gather& g, uint64_t* dst, hipStream_t s) {

@@ -175,6 +175,14 @@ struct Lane {
   hipEvent_t up_done = nullptr;  // recorded after the last batched upload's copy
   bool up_pending = false;
   void* gather_dev = nullptr;  // 8 device u64 that gather_back fills
+  // Pinned mailbox of the read-backs: a sequence word, then kMailBytes of
+  // values (see wait_mail).
+  static constexpr size_t kMailBytes = 64 << 10;
+  uint64_t* mail = nullptr;
+  uint64_t mail_seq = 0;
+  // Waits for the mailbox kernel just queued to post seq: spins, then after
+  // a while synchronises the stream (which also reports a failed kernel).
+  int wait_mail(uint64_t seq);
   uint32_t timing_mask = 0;    // bit i: time kernel id i; RTG_TIME_PHASES: phases
   hipEvent_t ev[9] = {};
   std::vector<hipEvent_t> kev;                // pool of event pairs
