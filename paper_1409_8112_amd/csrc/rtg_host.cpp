@@ -888,7 +888,7 @@ int alloc_result(Lane& c, int64_t n, size_t nnz, void** res, int64_t** row_ptr, 
 // directed entries of the unique pairs into buckets of 2^rb rows, then put
 // each bucket in (row, col) order in LDS and write col and row_ptr; buckets
 // too large for LDS go through the global radix sort.
-int csr_by_buckets(Lane& c, Scratch& S, const Tuning& T, const uint64_t* pairs, size_t count,
+int csr_by_buckets(Lane& c, Scratch& S, const Tuning& T, const PairSource& pairs, size_t count,
                    int64_t n, int pb, bool both, uint32_t* err, const LaunchTimer* tm, void** res,
                    int64_t** row_ptr, int32_t** col, size_t* nnz_out, uint32_t* err_host = nullptr,
                    bool* drained = nullptr) {
@@ -908,8 +908,11 @@ int csr_by_buckets(Lane& c, Scratch& S, const Tuning& T, const uint64_t* pairs, 
          per_row * (double)(1u << (rb + 1)) <= (double)T.bucket_entries)
     ++rb;
   const uint32_t nbuckets = (uint32_t)((n + ((int64_t)1 << rb) - 1) >> rb);
-  const uint32_t nblocks =
-      (uint32_t)std::min<size_t>(T.bucket_blocks, (count + 4095) / 4096);
+  uint32_t nblocks = (uint32_t)std::max<size_t>(
+      1, std::min<size_t>(T.bucket_blocks, (count + 4095) / 4096));
+  // pairs still in output segments: every segment gets the same number of
+  // blocks
+  if (pairs.nseg) nblocks = (nblocks + pairs.nseg - 1) / pairs.nseg * pairs.nseg;
   const uint32_t chunk = (uint32_t)((count + nblocks - 1) / nblocks);
   const size_t np = (size_t)nbuckets * nblocks;
   uint32_t* part = S.get<uint32_t>(np + 1);
@@ -1249,10 +1252,54 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   if ((rc = U1.send(up1))) return rc;
   launch_fill_u64(reinterpret_cast<uint64_t*>(counters), 0ull, kCounterWords, stream);
 
+  // First-owner filter (default): each pair is emitted only by the first grid
+  // whose cell holds both points, so the union needs no de-duplication.  It
+  // compares neighbourhood signatures: per grid the low sig_b bits of every
+  // axis field, sig_b the widest minimum field width of the batch.  Groups
+  // wider than a word (small alpha at high d) take sort-unique instead.
+  int sig_b = 1;
+  for (uint32_t q = 0; q < m; ++q) sig_b = std::max(sig_b, min_field_bits(jobs[q]->alpha));
+  const int sig_g = d * sig_b;
+  // Bitmaps of every instance's unordered pairs, when asked for and small
+  // enough; otherwise the first-owner rule where the signatures fit.
+  uint64_t bitmap_words = 0;
+  std::vector<BitmapInst> bmi;
+  if (flags & RTG_DEDUP_BITMAP) {
+    uint64_t bits = 0;
+    for (uint32_t q = 0; q < m; ++q) {
+      bmi.push_back(BitmapInst{inst[q].pt_off, (int64_t)bits});
+      const uint64_t nq = (uint64_t)inst[q].n;
+      bits += nq * (nq - 1) / 2;
+    }
+    const uint64_t words = (bits + 31) / 32;
+    const uint64_t limit = std::min<uint64_t>(kBitmapMaxBytes, largest_free() / 4);
+    if (4 * words <= limit) bitmap_words = std::max<uint64_t>(words, 1);
+  }
+  const bool bitmap = bitmap_words > 0;
+  const bool first_owner = !(flags & RTG_DEDUP_SORT) && !bitmap && sig_g <= 64;
+  const int sig_gpw = sig_g <= 64 ? 64 / sig_g : 1;
+  const int sig_W = (kmax + sig_gpw - 1) / sig_gpw;
+  uint64_t* sig = nullptr;   // [npts][W], or in the point records
+  uint64_t* ssig = nullptr;  // [W][NB] by sorted position (gathered copy)
+  // With one signature word, tile loads by point index and d <= 6, every
+  // point gets a 32-byte record (coordinates, padding, then the signature
+  // word in the last 8 bytes): a tile load reads one aligned run per lane
+  // instead of a row and a word apart (uniform d6 pair kernel about 1.5%
+  // faster; wider records at d = 12 cost more than they saved).  The stage
+  // kernel writes them while it reads the points.
+  const int rs = (d + 2 + 3) & ~3;
+  float* rec = nullptr;
+  int sig_stride = sig_W;
+  if (first_owner && sig_W == 1 && ctx->gather_direct && d <= 6) {
+    rec = S.get<float>((size_t)npts * rs);
+    if (!rec) return RTG_ENOMEM;
+    sig = reinterpret_cast<uint64_t*>(rec + rs - 2);
+    sig_stride = rs / 2;
+  }
   // --- stage: SoA copy (+ concatenated rows), finiteness, bounding boxes -------
   kbegin(RTG_K_STAGE);
-  launch_stage(inst_d, m, nblk, d, npts, soa, aos, bad, bbox, part, stream);
-  kend(RTG_K_STAGE, (aos ? 12.0 : 8.0) * (double)npts * d);
+  launch_stage(inst_d, m, nblk, d, npts, soa, aos, bad, bbox, part, rec, rs, stream);
+  kend(RTG_K_STAGE, (aos ? 12.0 : 8.0) * (double)npts * d + (rec ? 4.0 * rs * (double)npts : 0.0));
   mark(1);
   std::vector<uint32_t> hb((size_t)m * 2 * d + 1);
   if ((rc = read_back(bbox, sizeof(uint32_t) * hb.size(), hb.data()))) return rc;
@@ -1349,65 +1396,30 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
       (balanced && (!uwork || !uscan || !wfirst)))
     return RTG_ENOMEM;
 
-  // First-owner filter (default): each pair is emitted only by the first grid
-  // whose cell holds both points, so the union needs no de-duplication.  It
-  // compares neighbourhood signatures: per grid the low sig_b bits of every
-  // axis field, sig_b the widest minimum field width of the batch.  Groups
-  // wider than a word (small alpha at high d) take sort-unique instead.
-  int sig_b = 1;
-  for (uint32_t q = 0; q < m; ++q) sig_b = std::max(sig_b, min_field_bits(jobs[q]->alpha));
-  const int sig_g = d * sig_b;
-  // Bitmaps of every instance's unordered pairs, when asked for and small
-  // enough; otherwise the first-owner rule where the signatures fit.
-  uint64_t bitmap_words = 0;
-  std::vector<BitmapInst> bmi;
-  if (flags & RTG_DEDUP_BITMAP) {
-    uint64_t bits = 0;
-    for (uint32_t q = 0; q < m; ++q) {
-      bmi.push_back(BitmapInst{inst[q].pt_off, (int64_t)bits});
-      const uint64_t nq = (uint64_t)inst[q].n;
-      bits += nq * (nq - 1) / 2;
-    }
-    const uint64_t words = (bits + 31) / 32;
-    const uint64_t limit = std::min<uint64_t>(kBitmapMaxBytes, largest_free() / 4);
-    if (4 * words <= limit) bitmap_words = std::max<uint64_t>(words, 1);
-  }
-  const bool bitmap = bitmap_words > 0;
-  const bool first_owner = !(flags & RTG_DEDUP_SORT) && !bitmap && sig_g <= 64;
-  const int sig_gpw = sig_g <= 64 ? 64 / sig_g : 1;
-  const int sig_W = (kmax + sig_gpw - 1) / sig_gpw;
-  uint64_t* sig = nullptr;   // [npts][W], or in the point records
-  uint64_t* ssig = nullptr;  // [W][NB] by sorted position
-  // With one signature word, tile loads by point index and d <= 6, every
-  // point gets a 32-byte record (coordinates, padding, then the signature
-  // word in the last 8 bytes): a tile load reads one aligned run per lane
-  // instead of a row and a word apart (uniform d6 pair kernel about 1.5%
-  // faster; wider records at d = 12 cost more than they saved).
-  const int rs = (d + 2 + 3) & ~3;
-  float* rec = nullptr;
-  int sig_stride = sig_W;
   if (first_owner) {
     // signature words by sorted position: only for the gathered copy
     if (!ctx->gather_direct) {
       ssig = S.get<uint64_t>((size_t)sig_W * NB);
       if (!ssig) return RTG_ENOMEM;
     }
-    if (sig_W == 1 && ctx->gather_direct && d <= 6) {
-      rec = S.get<float>((size_t)npts * rs);
-      if (!rec) return RTG_ENOMEM;
-      launch_records(pts_rows, npts, d, rs, rec, stream);
-      sig = reinterpret_cast<uint64_t*>(rec + rs - 2);
-      sig_stride = rs / 2;
-    } else {
+    if (!rec) {
       sig = S.get<uint64_t>((size_t)npts * sig_W);
       if (!sig) return RTG_ENOMEM;
-      launch_fill_u64(sig, 0ull, (size_t)npts * sig_W, stream);
+      // the key kernel ORs into the words when its passes split the grids
+      if (P.tb < S_total) launch_fill_u64(sig, 0ull, (size_t)npts * sig_W, stream);
     }
   }
 
   uint64_t cap = 0;
   uint64_t* cand = nullptr;
   uint64_t cand_total = 0;  // exact number of candidates so far
+  // One pass whose first-owner pairs go straight to the row-bucket lists: the
+  // list build reads the pair kernel's output segments as they are, so they
+  // are not first copied into one array.
+  const bool lists_from_segments = P.tb >= S_total && first_owner && !any_mr &&
+                                   pair_bits <= 24 && ceil_log2((uint64_t)npts) <= 22 &&
+                                   ceil_log2((uint64_t)npts) - 14 + pair_bits <= 32;
+  PairSource seg_src{nullptr};
   uint64_t rechecks_seen = 0;
 
   // Pair screen: matrix cores when every instance suits them.  Their Gram
@@ -1431,7 +1443,8 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     const int seg_bits = (sb - sa) > 1 ? ceil_log2((uint64_t)(sb - sa)) : 0;
     const int key_bits = seg_bits + P.layout.cell_bits;
     KeysArgs ka{inst_d, m, nblk, d, npts, soa, sa, sb, segs_d, Rd, ud, klo_d, layout_d,
-                keys, vals, err, sig, sig_stride, sig_b, sig_gpw, idx_bits};
+                keys, vals, err, sig, sig_stride, sig_b, sig_gpw, idx_bits,
+                P.tb >= S_total ? 1 : 0};
     kbegin(RTG_K_KEYS);
     launch_keys(ka, stream);
     kend(RTG_K_KEYS, 4.0 * (double)pass_pts * d + (idx_bits ? 8.0 : 12.0) * (double)N +
@@ -1627,6 +1640,11 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
       if (attempt == 0 && !pa.direct)  // the gather: index, row, words in; row, words out
         st.kernel_bytes[RTG_K_GATHER] +=
             (8.0 + 8.0 * d + (first_owner ? 16.0 * sig_W : 0.0)) * (double)cnt[3];
+      if (most <= seg_cap && lists_from_segments && 2 * total < (1ull << 32)) {
+        seg_src = PairSource{sbuf, segcnt, seg_cap, nseg};
+        cand_total += total;
+        break;
+      }
       if (most <= seg_cap) {
         if (cand_total + total > cap) {
           const uint64_t want = cand_total + total;
@@ -1722,6 +1740,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   const uint64_t* pairs = cand;  // pairs for the neighbour-list build
   size_t npairs = C;
   if (C > 0 && (!unique_pairs || !bucket_ok)) {
+    if (seg_src.pairs) return hip_fail(hipErrorUnknown, "pair segments without a row-bucket build");
     // Global sort of the packed pairs; with RTG_DEDUP_SORT also drop repeats
     // (sort-unique over every grid's candidates).
     uint64_t* cand_alt = S.get<uint64_t>(C);
@@ -1767,7 +1786,8 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     if ((rc = alloc_result(*this, npts, 0, &res, &row_ptr, &col))) return rc;
     launch_fill_u64(reinterpret_cast<uint64_t*>(row_ptr), 0ull, (size_t)(npts + 1), stream);
   } else if (bucket_ok) {
-    rc = csr_by_buckets(*this, S, T, pairs, npairs, npts, pair_bits, both, err, &tm, &res, &row_ptr,
+    const PairSource psrc = seg_src.pairs ? seg_src : PairSource{pairs};
+    rc = csr_by_buckets(*this, S, T, psrc, npairs, npts, pair_bits, both, err, &tm, &res, &row_ptr,
                         &col, &nnz, &err_seen, &drained);
     if (rc) return rc;
   } else {
@@ -2063,7 +2083,8 @@ int Ctx::debug_cell_coords(const float* points, int64_t n, int32_t d, double r, 
   one.n = n;
   if ((rc = L.upload(inst_d, &one, sizeof(one)))) return rc;
   launch_fill_u32(flags_dev + 1, 0u, 1, L.stream);
-  launch_stage(inst_d, 1, nblk, d, n, soa, nullptr, flags_dev, flags_dev + 2, stage_part, L.stream);
+  launch_stage(inst_d, 1, nblk, d, n, soa, nullptr, flags_dev, flags_dev + 2, stage_part, nullptr,
+               0, L.stream);
   launch_cell_coords(soa, n, d, Rd, ud, 1.0 / (alpha * r), kap, flags_dev + 1, L.stream);
   uint32_t fl[2];
   if ((rc = L.read_back(flags_dev, sizeof(fl), fl))) return rc;
@@ -2268,7 +2289,7 @@ int Lane::build_index(const float* points, int64_t n, int32_t d, double r, int32
   uint32_t* err = bad + 1;
   if ((rc = upload(inst_d, &one, sizeof(one)))) return rc;
   launch_fill_u32(err, 0u, 1, stream);
-  launch_stage(inst_d, 1, nblk, d, n, soa, nullptr, bad, bbox, part, stream);
+  launch_stage(inst_d, 1, nblk, d, n, soa, nullptr, bad, bbox, part, nullptr, 0, stream);
   std::vector<uint32_t> hb((size_t)2 * d + 1);
   if ((rc = download(hb.data(), bbox, sizeof(uint32_t) * hb.size()))) return rc;
   if (hb[(size_t)2 * d]) return RTG_EINVAL;
@@ -2476,8 +2497,8 @@ int Lane::query_index(const Index& I, const float* queries, int64_t m, rtg_stats
     if ((rc = alloc_result(*this, m, 0, &res, &row_ptr, &col))) return rc;
     launch_fill_u64(reinterpret_cast<uint64_t*>(row_ptr), 0ull, (size_t)(m + 1), stream);
   } else if (bucket_ok) {
-    if ((rc = csr_by_buckets(*this, S, ctx->defaults, cand, C, m, pb, false, err + 1, nullptr,
-                             &res, &row_ptr, &col, &nnz)))
+    if ((rc = csr_by_buckets(*this, S, ctx->defaults, PairSource{cand}, C, m, pb, false, err + 1,
+                             nullptr, &res, &row_ptr, &col, &nnz)))
       return rc;
   } else {
     uint64_t* alt = S.get<uint64_t>(C);

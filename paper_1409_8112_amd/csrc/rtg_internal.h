@@ -93,10 +93,13 @@ struct SegDesc {
 // row-major aos [npts][d] when aos is not null), *bad = 1 if a value is not
 // finite (else 0), and per-axis min/max as order-preserving uint32
 // encodings in bbox[q][2d] (min at 2j, max at 2j+1).  nblocks = the
-// instances' point blocks; part holds nblocks * 2d elements.
+// instances' point blocks; part holds nblocks * 2d elements.  With rec, also
+// the point records of the pair kernels' tile loads: rec[i][0..d) = the
+// point, rec[i][d..rs) = 0 (the signature word, in the last two floats, is
+// filled by the key kernel).
 void launch_stage(const InstDesc* inst, uint32_t m, uint32_t nblocks, int d, int64_t npts,
                   float* soa, float* aos, uint32_t* bad, uint32_t* bbox, uint32_t* part,
-                  hipStream_t s);
+                  float* rec, int rs, hipStream_t s);
 
 // --- cell keys ------------------------------------------------------------
 // For every batch point and each of its instance's segments in [sa, sb):
@@ -123,6 +126,7 @@ struct KeysArgs {
   uint64_t* sig;     // neighbourhood signatures (see PairFilter), or null
   int sig_stride, sig_b, sig_gpw;  // sig_stride: words from one point's signature to the next
   int idx_bits;
+  int sig_fresh;     // 1: this pass covers every grid, so signature words are stored, not ORed
 };
 void launch_keys(const KeysArgs& a, hipStream_t s);
 // kappa [n][d] = floor(y) for one transform (stage check).
@@ -393,11 +397,21 @@ void launch_csr_fill_lower(const uint64_t* lo, size_t count, int pair_bits, cons
 // [nbuckets][nblocks] counts / their exclusive scan (bucket-major).
 constexpr int kBucketMaxEntries = 16384;  // entries one block holds in LDS
 constexpr int kBucketMaxRows = 1024;      // rows per bucket (rb <= 10)
-// threads: block size of the two partition kernels (256 or 1024).
-void launch_bucket_hist(const uint64_t* pairs, size_t count, int pb, int rb, int both,
+// threads: block size of the two partition kernels (256 or 1024).  The
+// pairs are one array of count entries (nseg = 0), or the pair kernels' nseg
+// output segments as they left them (segment s at pairs + s seg_cap with
+// seg_cnt[s] entries on the device; count their total, nblocks a multiple of
+// nseg).
+struct PairSource {
+  const uint64_t* pairs;
+  const unsigned long long* seg_cnt = nullptr;
+  uint64_t seg_cap = 0;
+  uint32_t nseg = 0;
+};
+void launch_bucket_hist(const PairSource& src, size_t count, int pb, int rb, int both,
                         uint32_t nbuckets, uint32_t chunk, uint32_t nblocks, int threads,
                         uint32_t* part, hipStream_t s);
-void launch_bucket_scatter(const uint64_t* pairs, size_t count, int pb, int rb, int both,
+void launch_bucket_scatter(const PairSource& src, size_t count, int pb, int rb, int both,
                            uint32_t nbuckets, uint32_t chunk, uint32_t nblocks, int threads,
                            const uint32_t* offs, uint32_t* entries, hipStream_t s);
 // Writes col and row_ptr (all but row_ptr[n]) for every bucket of at most

@@ -148,7 +148,8 @@ __device__ __forceinline__ uint32_t block_instance(const InstDesc* __restrict__ 
 __global__ __launch_bounds__(kBlock) void k_stage(const InstDesc* __restrict__ inst, uint32_t m,
                                                   int d, int64_t npts, float* __restrict__ soa,
                                                   float* __restrict__ aos, uint32_t* bad,
-                                                  uint32_t* __restrict__ part) {
+                                                  uint32_t* __restrict__ part,
+                                                  float* __restrict__ rec, int rs) {
   __shared__ uint32_t smin[kWaves][kMaxDim], smax[kWaves][kMaxDim];
   const uint32_t q = block_instance(inst, m, blockIdx.x);
   const float* pts = inst[q].pts;
@@ -163,6 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_stage(const InstDesc* __restrict__ i
     if (live) {
       soa[(int64_t)l * npts + g] = v;
       if (aos) aos[g * d + l] = v;
+      if (rec) rec[g * rs + l] = v;
       if (!isfinite(v)) nonfinite = true;
       else lo = hi = float_order(v);
     }
@@ -177,6 +179,8 @@ __global__ __launch_bounds__(kBlock) void k_stage(const InstDesc* __restrict__ i
     }
   }
   if (ballot(nonfinite) && lane_id() == 0) atomicOr(bad, 1u);
+  if (rec && live)
+    for (int l = d; l < rs; ++l) rec[g * rs + l] = 0.0f;  // padding, then the signature word
   __syncthreads();
   if (threadIdx.x < (unsigned)d) {
     uint32_t lo = 0xFFFFFFFFu, hi = 0u;
@@ -266,7 +270,8 @@ __global__ __launch_bounds__(kBlock) void k_keys(const InstDesc* __restrict__ in
                                                  uint64_t* __restrict__ keys,
                                                  uint32_t* __restrict__ vals, uint32_t* err,
                                                  uint64_t* __restrict__ sig, int sig_stride,
-                                                 int sig_b, int sig_gpw, int idx_bits) {
+                                                 int sig_b, int sig_gpw, int idx_bits,
+                                                 int sig_fresh) {
   const int d = D > 0 ? D : d_rt;
   const uint32_t q = block_instance(inst, m, blockIdx.x);
   const int64_t i = (int64_t)(blockIdx.x - (uint32_t)inst[q].blk_first) * kBlock + threadIdx.x;
@@ -307,7 +312,10 @@ __global__ __launch_bounds__(kBlock) void k_keys(const InstDesc* __restrict__ in
       // the point owns its row: earlier passes' bits are read back and kept
       const int w = t / sig_gpw;
       if (w != sw) {
-        if (sw >= 0) sig[(size_t)g * sig_stride + sw] |= sword;
+        if (sw >= 0) {
+          uint64_t* dst = sig + (size_t)g * sig_stride + sw;
+          *dst = sig_fresh ? sword : (*dst | sword);
+        }
         sword = 0;
         sw = w;
       }
@@ -322,7 +330,10 @@ __global__ __launch_bounds__(kBlock) void k_keys(const InstDesc* __restrict__ in
       vals[pos] = (uint32_t)g;
     }
   }
-  if (sig && sw >= 0) sig[(size_t)g * sig_stride + sw] |= sword;
+  if (sig && sw >= 0) {
+    uint64_t* dst = sig + (size_t)g * sig_stride + sw;
+    *dst = sig_fresh ? sword : (*dst | sword);
+  }
   if (bad) atomicOr(err, 1u);
 }
 
@@ -2115,17 +2126,48 @@ __global__ void k_csr_fill_lower(const uint64_t* __restrict__ lo, size_t count, 
 // bucket's slice of row_ptr.  The order of entries inside a bucket before the
 // local sort does not matter: the sort makes it canonical.
 
+// The pairs a partition block reads: a chunk of one array, or -- when the
+// pairs are still in the pair kernels' nseg output segments (segment s at
+// pairs + s seg_cap, seg_cnt[s] entries) -- an equal share of one segment
+// (block b takes segment b % nseg; nblocks is a multiple of nseg).
+struct PairRange {
+  const uint64_t* src;
+  size_t base, end;
+};
+__device__ __forceinline__ PairRange pair_range(const uint64_t* pairs, size_t count,
+                                                uint32_t chunk, uint32_t nblocks,
+                                                const unsigned long long* seg_cnt,
+                                                uint64_t seg_cap, uint32_t nseg) {
+  PairRange r;
+  if (nseg) {
+    const uint32_t seg = blockIdx.x % nseg, bps = nblocks / nseg, part = blockIdx.x / nseg;
+    const size_t cnt = (size_t)min((unsigned long long)seg_cap, seg_cnt[seg]);
+    const size_t ch = (cnt + bps - 1) / bps;
+    r.src = pairs + (size_t)seg * seg_cap;
+    r.base = min(cnt, (size_t)part * ch);
+    r.end = min(cnt, r.base + ch);
+  } else {
+    r.src = pairs;
+    r.base = (size_t)blockIdx.x * chunk;
+    r.end = min(count, r.base + chunk);
+  }
+  return r;
+}
+
 template <int TH>
 __global__ __launch_bounds__(TH) void k_bucket_hist(const uint64_t* __restrict__ pairs,
                                                     size_t count, int pb, int rb, int both,
                                                     uint32_t nbuckets, uint32_t chunk,
                                                     uint32_t nblocks,
+                                                    const unsigned long long* __restrict__ seg_cnt,
+                                                    uint64_t seg_cap, uint32_t nseg,
                                                     uint32_t* __restrict__ part) {
   extern __shared__ uint32_t h[];
   for (uint32_t b = threadIdx.x; b < nbuckets; b += TH) h[b] = 0u;
   __syncthreads();
-  const size_t base = (size_t)blockIdx.x * chunk;
-  const size_t end = min(count, base + chunk);
+  const PairRange pr = pair_range(pairs, count, chunk, nblocks, seg_cnt, seg_cap, nseg);
+  const uint64_t* __restrict__ src = pr.src;
+  const size_t base = pr.base, end = pr.end;
   const uint64_t cmask = (1ull << pb) - 1ull;
   // eight loads in flight per thread, then their atomics
   for (size_t q0 = base; q0 < end; q0 += 8 * TH) {
@@ -2133,7 +2175,7 @@ __global__ __launch_bounds__(TH) void k_bucket_hist(const uint64_t* __restrict__
 #pragma unroll
     for (int x = 0; x < 8; ++x) {
       const size_t q = q0 + (size_t)x * TH + threadIdx.x;
-      k8[x] = q < end ? pairs[q] : ~0ull;
+      k8[x] = q < end ? src[q] : ~0ull;
     }
 #pragma unroll
     for (int x = 0; x < 8; ++x) {
@@ -2152,14 +2194,17 @@ __global__ __launch_bounds__(TH) void k_bucket_scatter(const uint64_t* __restric
                                                        size_t count, int pb, int rb, int both,
                                                        uint32_t nbuckets, uint32_t chunk,
                                                        uint32_t nblocks,
+                                                       const unsigned long long* __restrict__ seg_cnt,
+                                                       uint64_t seg_cap, uint32_t nseg,
                                                        const uint32_t* __restrict__ offs,
                                                        uint32_t* __restrict__ entries) {
   extern __shared__ uint32_t cur[];
   for (uint32_t b = threadIdx.x; b < nbuckets; b += TH)
     cur[b] = offs[(size_t)b * nblocks + blockIdx.x];
   __syncthreads();
-  const size_t base = (size_t)blockIdx.x * chunk;
-  const size_t end = min(count, base + chunk);
+  const PairRange pr = pair_range(pairs, count, chunk, nblocks, seg_cnt, seg_cap, nseg);
+  const uint64_t* __restrict__ src = pr.src;
+  const size_t base = pr.base, end = pr.end;
   const uint64_t cmask = (1ull << pb) - 1ull;
   const uint32_t rmask = (1u << rb) - 1u;
   for (size_t q0 = base; q0 < end; q0 += 8 * TH) {
@@ -2167,7 +2212,7 @@ __global__ __launch_bounds__(TH) void k_bucket_scatter(const uint64_t* __restric
 #pragma unroll
     for (int x = 0; x < 8; ++x) {
       const size_t q = q0 + (size_t)x * TH + threadIdx.x;
-      k8[x] = q < end ? pairs[q] : ~0ull;
+      k8[x] = q < end ? src[q] : ~0ull;
     }
 #pragma unroll
     for (int x = 0; x < 8; ++x) {
@@ -2334,8 +2379,14 @@ __global__ __launch_bounds__(kCsrThreads) void k_bucket_csr(
       const uint32_t lo = rstart[r], hi = rcur[r];
       if (hi - lo <= kShortRow) {
         const uint32_t c = e_[q] & cmask;
-        uint32_t rank = 0;
-        for (uint32_t x = lo; x < hi; ++x) rank += (s[x] & cmask) < c ? 1u : 0u;
+        // the rank of c among its row: four independent LDS reads per step
+        uint32_t rank = 0, x = lo;
+        for (; x + 4 <= hi; x += 4) {
+          const uint32_t a0 = s[x], a1 = s[x + 1], a2 = s[x + 2], a3 = s[x + 3];
+          rank += ((a0 & cmask) < c ? 1u : 0u) + ((a1 & cmask) < c ? 1u : 0u) +
+                  ((a2 & cmask) < c ? 1u : 0u) + ((a3 & cmask) < c ? 1u : 0u);
+        }
+        for (; x < hi; ++x) rank += (s[x] & cmask) < c ? 1u : 0u;
         col[(size_t)start + lo + rank] = (int32_t)c;
       }
     }
@@ -2559,11 +2610,11 @@ void launch_fill_u64(uint64_t* p, uint64_t v, size_t count, hipStream_t s) {
 
 void launch_stage(const InstDesc* inst, uint32_t m, uint32_t nblocks, int d, int64_t npts,
                   float* soa, float* aos, uint32_t* bad, uint32_t* bbox, uint32_t* part,
-                  hipStream_t s) {
+                  float* rec, int rs, hipStream_t s) {
   if (!nblocks) return;
   hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(64), 0, s, bad, 0u, (size_t)1);
   hipLaunchKernelGGL(k_stage, dim3(nblocks), dim3(kBlock), 0, s, inst, m, d, npts, soa, aos, bad,
-                     part);
+                     part, rec, rs);
   const uint32_t nbox = m * 2u * (uint32_t)d;
   hipLaunchKernelGGL(k_bbox_init, dim3((nbox + kBlock - 1) / kBlock), dim3(kBlock), 0, s, bbox,
                      nbox);
@@ -2577,7 +2628,7 @@ template <int D>
 static void keys_dispatch(const KeysArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_keys<D>, dim3(a.nblocks), dim3(kBlock), 0, s, a.inst, a.m, a.d, a.npts,
                      a.soa, a.sa, a.sb, a.segs, a.R, a.u, a.klo, a.layout, a.keys, a.vals, a.err,
-                     a.sig, a.sig_stride, a.sig_b, a.sig_gpw, a.idx_bits);
+                     a.sig, a.sig_stride, a.sig_b, a.sig_gpw, a.idx_bits, a.sig_fresh);
 }
 
 void launch_keys(const KeysArgs& a, hipStream_t s) {
@@ -3015,30 +3066,34 @@ void launch_csr_fill_lower(const uint64_t* lo, size_t count, int pair_bits, cons
 
 // --- row buckets ------------------------------------------------------------
 
-void launch_bucket_hist(const uint64_t* pairs, size_t count, int pb, int rb, int both,
+void launch_bucket_hist(const PairSource& src, size_t count, int pb, int rb, int both,
                         uint32_t nbuckets, uint32_t chunk, uint32_t nblocks, int threads,
                         uint32_t* part, hipStream_t s) {
   if (!nblocks) return;
   const size_t lds = nbuckets * sizeof(uint32_t);
   if (threads >= 1024)
-    hipLaunchKernelGGL(k_bucket_hist<1024>, dim3(nblocks), dim3(1024), lds, s, pairs, count, pb,
-                       rb, both, nbuckets, chunk, nblocks, part);
+    hipLaunchKernelGGL(k_bucket_hist<1024>, dim3(nblocks), dim3(1024), lds, s, src.pairs, count,
+                       pb, rb, both, nbuckets, chunk, nblocks, src.seg_cnt, src.seg_cap,
+                       src.nseg, part);
   else
-    hipLaunchKernelGGL(k_bucket_hist<kBlock>, dim3(nblocks), dim3(kBlock), lds, s, pairs, count,
-                       pb, rb, both, nbuckets, chunk, nblocks, part);
+    hipLaunchKernelGGL(k_bucket_hist<kBlock>, dim3(nblocks), dim3(kBlock), lds, s, src.pairs,
+                       count, pb, rb, both, nbuckets, chunk, nblocks, src.seg_cnt, src.seg_cap,
+                       src.nseg, part);
 }
 
-void launch_bucket_scatter(const uint64_t* pairs, size_t count, int pb, int rb, int both,
+void launch_bucket_scatter(const PairSource& src, size_t count, int pb, int rb, int both,
                            uint32_t nbuckets, uint32_t chunk, uint32_t nblocks, int threads,
                            const uint32_t* offs, uint32_t* entries, hipStream_t s) {
   if (!nblocks) return;
   const size_t lds = nbuckets * sizeof(uint32_t);
   if (threads >= 1024)
-    hipLaunchKernelGGL(k_bucket_scatter<1024>, dim3(nblocks), dim3(1024), lds, s, pairs, count,
-                       pb, rb, both, nbuckets, chunk, nblocks, offs, entries);
+    hipLaunchKernelGGL(k_bucket_scatter<1024>, dim3(nblocks), dim3(1024), lds, s, src.pairs,
+                       count, pb, rb, both, nbuckets, chunk, nblocks, src.seg_cnt, src.seg_cap,
+                       src.nseg, offs, entries);
   else
-    hipLaunchKernelGGL(k_bucket_scatter<kBlock>, dim3(nblocks), dim3(kBlock), lds, s, pairs,
-                       count, pb, rb, both, nbuckets, chunk, nblocks, offs, entries);
+    hipLaunchKernelGGL(k_bucket_scatter<kBlock>, dim3(nblocks), dim3(kBlock), lds, s, src.pairs,
+                       count, pb, rb, both, nbuckets, chunk, nblocks, src.seg_cnt, src.seg_cap,
+                       src.nseg, offs, entries);
 }
 
 void launch_bucket_csr(const uint32_t* entries, const uint32_t* offs, uint32_t nbuckets,
