@@ -152,6 +152,7 @@ def bench_batched(ctx, count: int, reps: int = 3) -> dict:
         tuned.append(ctx.autotune([q for q, w in zip(queries, wls) if w.d == d], reps=2))
     tune_s = time.perf_counter() - t0
     t_b, pairs = timed()
+    plan = bench_plan(ctx, queries, reps)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -169,7 +170,8 @@ def bench_batched(ctx, count: int, reps: int = 3) -> dict:
             "plain_value": pairs_plain / t_p, "plain_ms": t_p * 1e3,
             "plain_pairs": pairs_plain, "speedup_vs_plain": t_p / t_b,
             "same_pairs_as_plain": pairs == pairs_plain,
-            "default_settings_ms": t_default * 1e3, "tuning_s": tune_s, "tuned": tuned}
+            "default_settings_ms": t_default * 1e3, "tuning_s": tune_s, "tuned": tuned,
+            "plan": plan}
 
 
 def brute_force_rows(points: np.ndarray, r: float, rows: np.ndarray, chunk: int = 16384) -> list:
@@ -497,6 +499,28 @@ def pair_roofline(d: int, tests: float, pair_ms: float, matrix: bool) -> dict:
             "kernel": "k_cell_pairs_gram" if matrix else "k_cell_pairs"}
 
 
+def bench_plan(ctx, queries, steps: int) -> dict:
+    """The same queries run as a plan (rtg_plan_*): two runs size the
+    workspaces and capture the graphs, then steps timed runs replay them."""
+    import torch
+    plan = ctx.plan_create(queries)
+    try:
+        for _ in range(2):
+            ctx.release_many(plan.run(queries))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pairs = 0
+        for _ in range(steps):
+            res = plan.run(queries)
+            pairs = sum(r.pairs for r in res)
+            ctx.release_many(res)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        return {"ms": ms, "pairs": pairs, "pairs_per_s": pairs / (ms / 1e3), **plan.info()}
+    finally:
+        plan.destroy()
+
+
 def bench_config(ctx, wl, steps: int, warmup: int, probes: int = 3) -> dict:
     """One workload: ms per query (wall clock, points resident), pairs/s,
     the pair kernel's roofline and the phases."""
@@ -527,9 +551,11 @@ def bench_config(ctx, wl, steps: int, warmup: int, probes: int = 3) -> dict:
         lat.append((time.perf_counter() - s0) * 1e3)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
+    plan = bench_plan(ctx, [dict(points=pts, r=wl.r, k=wl.k, alpha=wl.alpha, seed=wl.seed)], steps)
     del pts
     return {"workload": wl.name, "n": wl.n, "d": wl.d, "k": wl.k, "alpha": wl.alpha, "r": wl.r,
             "steps": steps, "ms": ms, "pairs": pairs, "pairs_per_s": pairs / (ms / 1e3),
+            "plan": plan,
             "latency_ms": {"p50": float(np.percentile(lat, 50)),
                            "p99": float(np.percentile(lat, 99))},
             "pair_kernel": pair_roofline(wl.d, st["tests"], pair_ms,
@@ -684,6 +710,9 @@ def main(argv=None) -> int:
         "roofline": roof,
         "phases": phase_block(probe, 3),
         "probe_kernel_ms": {name: probe["kernel_ms"][i] / 3 for i, name in enumerate(rtg.KERNELS)},
+        # the same step through a plan (graph replay of the device-sized stretch)
+        "plan": bench_plan(ctx, [dict(points=pts, r=wl.r, k=wl.k, alpha=wl.alpha, seed=wl.seed)],
+                           args.steps),
     }
     del pts
     if not args.no_configs and args.workload == "uniform_d6":

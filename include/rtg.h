@@ -231,6 +231,32 @@ int rtg_all_pairs_noalloc(rtg_ctx *ctx, const float *points, int64_t n, int32_t 
  * rtg_all_pairs, for any query. */
 int rtg_all_pairs_batched(rtg_ctx *ctx, const rtg_query *queries, int32_t nq, rtg_csr *outs);
 
+/* Plans: rtg_all_pairs_batched repeated over queries of one fixed shape (a
+ * stream of many small problems of the same sizes, each the all-pairs r-NN
+ * problem of Sec. II).  rtg_plan_create records the shape of queries[0..nq)
+ * -- each query's n, d, k and flags -- and validates them as
+ * rtg_all_pairs_batched does; it runs nothing.  rtg_plan_run takes queries
+ * of that shape (points, r, alpha and seed may differ) and returns, in
+ * outs[0..nq), exactly what rtg_all_pairs_batched returns for them.  Its
+ * first run gives each batch of the call a device workspace (held by the
+ * plan, counted against the context's budget until rtg_plan_destroy); from
+ * the second run on the pass's device-sized stretch, from the cell keys to
+ * the unit descriptors, is launched as one HIP graph captured on the
+ * context's stream, recaptured when a launch argument changes (another
+ * cell-key layout for new data).  Per-kernel timing of those kernels
+ * (rtg_set_timing) runs them as ordinary launches instead.  Runs are
+ * blocking and serialised with the context's other calls.  rtg_plan_info
+ * reports the graphs captured and replayed so far and the workspace bytes
+ * held.  A plan belongs to its context: destroy it before the context.
+ * Errors: RTG_EINVAL (NULL arguments, nq < 0, or for rtg_plan_run a shape
+ * other than the plan's), and those of rtg_all_pairs_batched. */
+typedef struct rtg_plan rtg_plan;
+int rtg_plan_create(rtg_ctx *ctx, const rtg_query *queries, int32_t nq, rtg_plan **plan);
+int rtg_plan_run(rtg_plan *plan, const rtg_query *queries, int32_t nq, rtg_csr *outs);
+int rtg_plan_info(const rtg_plan *plan, int64_t *captures, int64_t *replays,
+                  int64_t *workspace_bytes);
+int rtg_plan_destroy(rtg_plan *plan);
+
 /* Request loop (continuous batching).  rtg_submit copies the query's points
  * into the context before it returns (the caller may reuse its buffer) and
  * hands back a ticket; a scheduler thread admits requests while their device

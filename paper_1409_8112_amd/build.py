@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "librtg.so")
 SOURCES = [os.path.join(CSRC, f)
-           for f in ("rtg_kernels.hip", "rtg_host.cpp", "rtg_server.cpp", "rtg_tune.cpp")]
+           for f in ("rtg_kernels.hip", "rtg_host.cpp", "rtg_server.cpp", "rtg_tune.cpp",
+                     "rtg_plan.cpp")]
 HEADERS = [os.path.join(CSRC, f) for f in ("rtg_internal.h", "rtg_runtime.h")] + [
     os.path.join(os.path.dirname(HERE), "include", "rtg.h")]
 

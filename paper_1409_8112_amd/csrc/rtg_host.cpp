@@ -573,6 +573,8 @@ void Lane::fini() {
   gather_dev = nullptr;
   if (own_stream) (void)hipStreamDestroy(stream);
   own_stream = false;
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  cap_stream = nullptr;
 }
 
 int Lane::hip_fail(hipError_t e, const char* what) { return ctx->hip_fail(e, what); }
@@ -823,6 +825,16 @@ struct Scratch {
   // lane's later work may take them at once (stream order); the arena, and
   // so the other lanes, gets them back only once the stream has drained.
   std::vector<std::pair<void*, size_t>> pool;
+  // A plan's workspace (the same addresses on every run, which its captured
+  // graph needs): while carve is set, requests are cut from [carve, carve +
+  // carve_left) in order and never given back one by one; if it runs short
+  // the rest come from the arena (carve_short).  With record set, the sizes
+  // such requests would take are summed in recorded.
+  char* carve = nullptr;
+  size_t carve_left = 0;
+  bool carve_short = false;
+  bool record = false;
+  size_t recorded = 0;
   explicit Scratch(Lane& lane) : c(lane), outer(lane.scratch) { lane.scratch = this; }
   ~Scratch() {
     c.scratch = outer;
@@ -834,6 +846,18 @@ struct Scratch {
   template <class T>
   T* get(size_t count) {
     const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    const size_t cut = (bytes + Arena::kAlign - 1) & ~(size_t)(Arena::kAlign - 1);
+    if (record) recorded += cut;
+    if (carve) {
+      if (cut <= carve_left) {
+        void* p = carve;
+        carve += cut;
+        carve_left -= cut;
+        return static_cast<T*>(p);
+      }
+      carve = nullptr;
+      carve_short = true;
+    }
     // a dropped block that fits without wasting more than its request
     size_t best = pool.size();
     for (size_t i = 0; i < pool.size(); ++i)
@@ -1172,7 +1196,7 @@ int Ctx::all_pairs_noalloc(const float* points, int64_t n, int32_t d, double r, 
 // One pass of the pipeline over a batch of instances of one dimension d
 // sharing the RTG_UPPER_ONLY / RTG_DEDUP_SORT flags (every instance has
 // n >= 2 and passed check_query).  On success each job's out is filled.
-int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
+int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st, PassPlan* pp) {
   const uint32_t m = (uint32_t)jobs.size();
   const int d = jobs[0]->d;
   const uint32_t flags = jobs[0]->flags;
@@ -1190,6 +1214,12 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
   } detach{*this};
   const LaunchTimer tm = timer();
   Scratch S(*this);
+  if (pp && pp->ws) {
+    S.carve = static_cast<char*>(pp->ws);
+    S.carve_left = pp->head_bytes;
+  } else if (pp) {
+    S.record = true;  // the first run sizes the plan's workspace
+  }
   mark(0);
 
   // --- the batch's instances and segments (host) -----------------------------
@@ -1442,14 +1472,6 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     }
     const int seg_bits = (sb - sa) > 1 ? ceil_log2((uint64_t)(sb - sa)) : 0;
     const int key_bits = seg_bits + P.layout.cell_bits;
-    KeysArgs ka{inst_d, m, nblk, d, npts, soa, sa, sb, segs_d, Rd, ud, klo_d, layout_d,
-                keys, vals, err, sig, sig_stride, sig_b, sig_gpw, idx_bits,
-                P.tb >= S_total ? 1 : 0};
-    kbegin(RTG_K_KEYS);
-    launch_keys(ka, stream);
-    kend(RTG_K_KEYS, 4.0 * (double)pass_pts * d + (idx_bits ? 8.0 : 12.0) * (double)N +
-                         (sig ? 16.0 * (double)pass_pts * sig_W : 0.0));
-    mark(2);
     // Several segments in the pass: sort within segments (tiles that stay
     // inside one segment), so only the cell bits take passes; the segment
     // bits above them are already in order.
@@ -1472,47 +1494,139 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
       if ((rc = Ut.send(tab_mem))) return rc;
     }
     const int sort_end = idx_bits + (segmented ? P.layout.cell_bits : key_bits);
-    const int where = radix_sort(keys, vals, keys_alt, vals_alt, N, idx_bits, sort_end, sort_scr,
-                                 err, stream, &tm, RTG_K_KEY_HIST, RTG_K_KEY_SCATTER,
-                                 T.sort_algo, tab_d, ntab);
-    st.key_passes = std::max(st.key_passes, (sort_end - idx_bits + kRadixBits - 1) / kRadixBits);
-    const uint64_t* skeys = where ? keys_alt : keys;
-    const uint32_t* sidx = idx_bits ? nullptr : (where ? vals_alt : vals);
-    mark(3);
-    // cells with >= 2 points
     const size_t nt = (N + kTile - 1) / kTile;
     uint32_t* hcnt = run_scr;
     uint32_t* tcnt = run_scr + nt;
     uint32_t* tot = run_scr + 2 * nt;  // [0] heads, [1] tails
     uint32_t* sscr = run_scr + 2 * nt + 2;
-    kbegin(RTG_K_CELLS);
-    launch_run_count(skeys, N, idx_bits, hcnt, tcnt, stream);
     // up to 2048 tiles the writing kernel adds up the earlier tiles' counts
     // itself (and clears the member counter of the cell-work kernel); its
     // reads grow as the square of the tiles, so more take the scans
     const bool counts_direct = nt >= 1 && nt <= 2048;
-    if (counts_direct) {
-      launch_run_write(skeys, N, idx_bits, hcnt, tcnt, cstart, cend, tot, counters + 3, stream);
-    } else {
-      scan_exclusive_u32(hcnt, hcnt, nt, tot, sscr, stream);
-      scan_exclusive_u32(tcnt, tcnt, nt, tot + 1, sscr, stream);
-      launch_run_write(skeys, N, idx_bits, hcnt, tcnt, cstart, cend, nullptr, nullptr, stream);
-    }
-    kend(RTG_K_CELLS, 16.0 * (double)N);
-    // Cell work, unit counts and their scans and the unit descriptors run on
-    // the device's own cell count (tot[0]; the host knows only the bound
-    // max_cells), so one read-back after them serves the whole cell stage.
-    kbegin(RTG_K_CELLS);
-    if (!counts_direct) launch_fill_u64(reinterpret_cast<uint64_t*>(counters) + 3, 0ull, 1, stream);
     const uint32_t cell_bound = (uint32_t)std::min<size_t>(max_cells, N / 2 + 1);
-    launch_cell_work(cstart, cend, cell_bound, tot, T.unit_tiles, units, tests_c, counters + 3,
-                     stream);
-    scan_exclusive_u32(units, units, cell_bound, scan32 + s64, scan32, stream, tot);
-    scan_exclusive_u64(tests_c, tests_c, cell_bound, scan64 + s64, scan64, stream, tot);
-    launch_unit_fill(cstart, cend, units, cell_bound, tot, T.unit_tiles, skeys,
-                     seg_bits > 0 ? idx_bits + P.layout.cell_bits : 64, sa, segs_d, udesc, uwork,
-                     stream);
-    kend(RTG_K_CELLS, 0.0);
+    int where = 0;
+    // From the key kernel to the unit descriptors every size is on the
+    // device: the stretch a plan captures as a graph.
+    auto stretch = [&]() {
+      KeysArgs ka{inst_d, m, nblk, d, npts, soa, sa, sb, segs_d, Rd, ud, klo_d, layout_d,
+                  keys, vals, err, sig, sig_stride, sig_b, sig_gpw, idx_bits,
+                  P.tb >= S_total ? 1 : 0};
+      kbegin(RTG_K_KEYS);
+      launch_keys(ka, stream);
+      kend(RTG_K_KEYS, 4.0 * (double)pass_pts * d + (idx_bits ? 8.0 : 12.0) * (double)N +
+                           (sig ? 16.0 * (double)pass_pts * sig_W : 0.0));
+      mark(2);
+      where = radix_sort(keys, vals, keys_alt, vals_alt, N, idx_bits, sort_end, sort_scr,
+                                   err, stream, &tm, RTG_K_KEY_HIST, RTG_K_KEY_SCATTER,
+                                   T.sort_algo, tab_d, ntab);
+      st.key_passes = std::max(st.key_passes, (sort_end - idx_bits + kRadixBits - 1) / kRadixBits);
+      const uint64_t* skeys = where ? keys_alt : keys;
+      mark(3);
+      // cells with >= 2 points
+      kbegin(RTG_K_CELLS);
+      launch_run_count(skeys, N, idx_bits, hcnt, tcnt, stream);
+      if (counts_direct) {
+        launch_run_write(skeys, N, idx_bits, hcnt, tcnt, cstart, cend, tot, counters + 3, stream);
+      } else {
+        scan_exclusive_u32(hcnt, hcnt, nt, tot, sscr, stream);
+        scan_exclusive_u32(tcnt, tcnt, nt, tot + 1, sscr, stream);
+        launch_run_write(skeys, N, idx_bits, hcnt, tcnt, cstart, cend, nullptr, nullptr, stream);
+      }
+      kend(RTG_K_CELLS, 16.0 * (double)N);
+      // Cell work, unit counts and their scans and the unit descriptors run on
+      // the device's own cell count (tot[0]; the host knows only the bound
+      // max_cells), so one read-back after them serves the whole cell stage.
+      kbegin(RTG_K_CELLS);
+      if (!counts_direct) launch_fill_u64(reinterpret_cast<uint64_t*>(counters) + 3, 0ull, 1, stream);
+      launch_cell_work(cstart, cend, cell_bound, tot, T.unit_tiles, units, tests_c, counters + 3,
+                       stream);
+      scan_exclusive_u32(units, units, cell_bound, scan32 + s64, scan32, stream, tot);
+      scan_exclusive_u64(tests_c, tests_c, cell_bound, scan64 + s64, scan64, stream, tot);
+      launch_unit_fill(cstart, cend, units, cell_bound, tot, T.unit_tiles, skeys,
+                       seg_bits > 0 ? idx_bits + P.layout.cell_bits : 64, sa, segs_d, udesc, uwork,
+                       stream);
+      kend(RTG_K_CELLS, 0.0);
+    };
+    // A plan's single-pass stretch is captured once and then replayed:
+    // its arguments (workspace addresses and sizes) must match the capture.
+    constexpr uint32_t kStretchTimed = (1u << RTG_K_KEYS) | (1u << RTG_K_KEY_HIST) |
+                                       (1u << RTG_K_KEY_SCATTER) | (1u << RTG_K_CELLS) |
+                                       (1u << RTG_K_SCAN) | RTG_TIME_PHASES;
+    const bool graph = pp && pp->ws && !S.carve_short && P.tb >= S_total &&
+                       !(timing_mask & kStretchTimed);
+    std::vector<int64_t> shape;
+    if (graph) {
+      for (const void* ptr : {(const void*)inst_d, (const void*)soa, (const void*)segs_d,
+                              (const void*)Rd, (const void*)ud, (const void*)klo_d,
+                              (const void*)layout_d, (const void*)keys, (const void*)keys_alt,
+                              (const void*)vals, (const void*)vals_alt, (const void*)err,
+                              (const void*)sig, (const void*)sort_scr, (const void*)tab_d,
+                              (const void*)run_scr, (const void*)cstart, (const void*)cend,
+                              (const void*)units, (const void*)tests_c, (const void*)scan32,
+                              (const void*)scan64, (const void*)udesc, (const void*)uwork,
+                              (const void*)counters})
+        shape.push_back((int64_t)reinterpret_cast<uintptr_t>(ptr));
+      for (int64_t v : {(int64_t)m, (int64_t)nblk, (int64_t)d, npts, (int64_t)sa, (int64_t)sb,
+                        (int64_t)N, (int64_t)pass_pts, (int64_t)idx_bits, (int64_t)key_bits,
+                        (int64_t)P.layout.cell_bits, (int64_t)sort_end, (int64_t)ntab,
+                        (int64_t)T.sort_algo, (int64_t)T.unit_tiles, (int64_t)sig_stride,
+                        (int64_t)sig_b, (int64_t)sig_gpw, (int64_t)cell_bound,
+                        (int64_t)counts_direct, (int64_t)seg_bits, (int64_t)NB,
+                        (int64_t)max_cells})
+        shape.push_back(v);
+    }
+    if (graph && pp->exec && shape == pp->shape) {
+      if ((rc = hip_fail(hipGraphLaunch(pp->exec, stream), "hipGraphLaunch"))) return rc;
+      where = pp->where;  // the buffer the sort's last pass wrote
+      for (int q = 0; q < RTG_NKERNELS; ++q) {
+        st.kernel_launches[q] += pp->launches[q];
+        st.kernel_bytes[q] += pp->bytes[q];
+      }
+      st.key_passes = std::max(st.key_passes, pp->key_passes);
+      ++pp->replays;
+    } else if (graph) {
+      if (pp->exec) (void)hipGraphExecDestroy(pp->exec);
+      pp->exec = nullptr;
+      rtg_stats before = st;
+      hipGraph_t g = nullptr;
+      // the stretch's launches go to the capturing stream while it records
+      if (!own_stream && !cap_stream)
+        (void)hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
+      const hipStream_t lane_stream = stream;
+      const hipStream_t cs = own_stream ? stream : cap_stream;
+      bool captured =
+          cs && hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) == hipSuccess;
+      if (captured) {
+        stream = cs;
+        stretch();
+        stream = lane_stream;
+        captured = hipStreamEndCapture(cs, &g) == hipSuccess && g != nullptr;
+        if (captured)
+          captured = hipGraphInstantiate(&pp->exec, g, nullptr, nullptr, 0) == hipSuccess;
+        if (g) (void)hipGraphDestroy(g);
+      }
+      if (!captured) (void)hipGetLastError();  // the failed capture's error
+      if (captured) {
+        for (int q = 0; q < RTG_NKERNELS; ++q) {
+          pp->launches[q] = st.kernel_launches[q] - before.kernel_launches[q];
+          pp->bytes[q] = st.kernel_bytes[q] - before.kernel_bytes[q];
+        }
+        pp->key_passes = st.key_passes;
+        pp->where = where;
+        pp->shape = shape;
+        ++pp->captures;
+        if ((rc = hip_fail(hipGraphLaunch(pp->exec, stream), "hipGraphLaunch"))) return rc;
+      } else {
+        // no graph: the stretch runs as ordinary launches
+        pp->exec = nullptr;
+        st = before;
+        stretch();
+      }
+    } else {
+      stretch();
+    }
+    const uint64_t* skeys = where ? keys_alt : keys;
+    const uint32_t* sidx = idx_bits ? nullptr : (where ? vals_alt : vals);
     uint64_t got[8];
     Gather g1;
     g1.add(tot, 4);
@@ -1529,6 +1643,9 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     const uint32_t units_total = ncells_h ? (uint32_t)got[3] : 0u;
     st.kernel_bytes[RTG_K_CELLS] += 24.0 * (double)ncells_h;
     mark(4);
+    // a plan's workspace ends here: what follows is sized by the pass's pairs
+    S.carve = nullptr;
+    S.record = false;
     st.cells += ncells_h;
     st.tests += (int64_t)tests_total;
     if (units_total == 0) continue;
@@ -1898,6 +2015,14 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st) {
     jobs[0]->out->handle =
         ctx->keep_result(jobs[0]->handle, res, jobs[0]->n, (int64_t)nnz, jobs[0]->out->pairs,
                          row_ptr, col);
+  // A plan's first run leaves it a workspace of the sizes the run took up to
+  // the cell stage; its later runs cut those buffers from it, at the same
+  // addresses each time.  Without room the plan runs as before and tries
+  // again next time.
+  if (pp && !pp->ws && S.recorded) {
+    pp->ws = ctx->dalloc(S.recorded);
+    if (pp->ws) pp->head_bytes = S.recorded;
+  }
   return RTG_OK;
 }
 
@@ -1952,7 +2077,29 @@ static void add_stats(rtg_stats& a, const rtg_stats& b) {
 // Many queries: grouped by dimension and list flags, each group split into
 // batches of at most batch_points points (an instance larger than that runs
 // alone), every batch one pass of run_batch.
-int Ctx::batched(const rtg_query* q, int32_t nq, rtg_csr* outs) {
+std::vector<std::vector<int32_t>> Ctx::batch_groups(const rtg_query* q, int32_t nq) {
+  std::map<std::pair<int, uint32_t>, std::vector<int32_t>> groups;
+  for (int32_t i = 0; i < nq; ++i)
+    if (q[i].n > 1) groups[{q[i].d, q[i].flags & kListFlags}].push_back(i);
+  std::vector<std::vector<int32_t>> batches;
+  for (auto& g : groups) {
+    size_t b = 0;
+    while (b < g.second.size()) {
+      std::vector<int32_t> batch;
+      int64_t pts = 0;
+      while (b < g.second.size() && (batch.empty() || pts + q[g.second[b]].n <= batch_points)) {
+        pts += q[g.second[b]].n;
+        batch.push_back(g.second[b]);
+        ++b;
+      }
+      batches.push_back(std::move(batch));
+    }
+  }
+  return batches;
+}
+
+int Ctx::batched(const rtg_query* q, int32_t nq, rtg_csr* outs,
+                 std::vector<std::unique_ptr<PassPlan>>* plan) {
   if (poisoned) return RTG_EDEVICE;
   int rc;
   for (int32_t i = 0; i < nq; ++i)
@@ -1965,6 +2112,12 @@ int Ctx::batched(const rtg_query* q, int32_t nq, rtg_csr* outs) {
     if ((rc = make_transforms(q[i].seed, q[i].k, q[i].d, q[i].flags, R[i].data(), u[i].data())))
       return rc;
   }
+  const std::vector<std::vector<int32_t>> groups = batch_groups(q, nq);
+  if (plan) {
+    if (plan->empty())
+      for (size_t b = 0; b < groups.size(); ++b) plan->emplace_back(new PassPlan);
+    if (plan->size() != groups.size()) return RTG_EINVAL;
+  }
   std::vector<rtg_csr> res(nq);
   std::vector<char> done(nq, 0);
   auto undo = [&](int code) {
@@ -1974,7 +2127,6 @@ int Ctx::batched(const rtg_query* q, int32_t nq, rtg_csr* outs) {
   };
   rtg_stats st{};
   std::vector<Job> jobs(nq);
-  std::map<std::pair<int, uint32_t>, std::vector<int32_t>> groups;
   for (int32_t i = 0; i < nq; ++i) {
     st.n += q[i].n;
     st.point_transforms += q[i].n * q[i].k;
@@ -1985,23 +2137,13 @@ int Ctx::batched(const rtg_query* q, int32_t nq, rtg_csr* outs) {
     }
     jobs[i] = Job{q[i].points, q[i].n, q[i].d, q[i].r, q[i].alpha, q[i].k, q[i].flags,
                   R[i].data(), u[i].data(), &res[i], 0};
-    groups[{q[i].d, q[i].flags & kListFlags}].push_back(i);
   }
   std::vector<std::vector<Job*>> batches;
-  for (auto& g : groups) {
-    size_t b = 0;
-    while (b < g.second.size()) {
-      std::vector<Job*> batch;
-      int64_t pts = 0;
-      while (b < g.second.size() &&
-             (batch.empty() || pts + jobs[g.second[b]].n <= batch_points)) {
-        pts += jobs[g.second[b]].n;
-        batch.push_back(&jobs[g.second[b]]);
-        ++b;
-      }
-      batches.push_back(std::move(batch));
-    }
+  for (const auto& g : groups) {
+    batches.emplace_back();
+    for (int32_t i : g) batches.back().push_back(&jobs[i]);
   }
+  auto pass_plan = [&](size_t b) { return plan ? (*plan)[b].get() : nullptr; };
   // Several batches: two lanes take them in turn.  A batch that runs out of
   // memory beside the other lane's pass runs again alone afterwards.
   constexpr int kNotRun = 1 << 20;
@@ -2021,7 +2163,7 @@ int Ctx::batched(const rtg_query* q, int32_t nq, rtg_csr* outs) {
         if (failed) return;
         const size_t b = next++;
         if (b >= batches.size()) return;
-        brc[b] = L.run_batch(batches[b], s);
+        brc[b] = L.run_batch(batches[b], s, pass_plan(b));
         if (brc[b] == RTG_OK)
           for (Job* j : batches[b]) done[j->out - res.data()] = 1;
         else if (brc[b] != RTG_ENOMEM)
@@ -2047,7 +2189,7 @@ int Ctx::batched(const rtg_query* q, int32_t nq, rtg_csr* outs) {
   }
   for (size_t b = 0; b < batches.size(); ++b) {
     if (brc[b] == RTG_OK) continue;
-    if ((rc = main.run_batch(batches[b], st))) return undo(rc);
+    if ((rc = main.run_batch(batches[b], st, pass_plan(b)))) return undo(rc);
     for (Job* j : batches[b]) done[j->out - res.data()] = 1;
   }
   for (int32_t i = 0; i < nq; ++i) outs[i] = res[i];

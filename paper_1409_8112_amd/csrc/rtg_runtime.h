@@ -148,6 +148,23 @@ struct Tuning {
   int sort_algo = rtgk::kSortReduceScan;
 };
 
+// One batch pass that a plan (rtg_plan) runs again and again with the same
+// shape: the pass's leading allocations come from the plan's workspace, so
+// their addresses repeat from run to run, and the stretch from the key
+// kernel to the unit descriptors -- whose sizes are all on the device -- is
+// captured once as a HIP graph and replayed.
+struct PassPlan {
+  void* ws = nullptr;            // workspace (an arena block of head_bytes)
+  size_t head_bytes = 0;
+  std::vector<int64_t> shape;    // launch arguments of the captured stretch
+  hipGraphExec_t exec = nullptr;
+  int64_t launches[RTG_NKERNELS] = {};  // the stretch's launches and bytes (stats)
+  double bytes[RTG_NKERNELS] = {};
+  int key_passes = 0;
+  int where = 0;                 // which key buffer holds the sorted keys
+  int64_t captures = 0, replays = 0;
+};
+
 struct Ctx;
 struct Server;
 
@@ -159,6 +176,10 @@ struct Lane {
   Ctx* ctx = nullptr;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // A stream that only records graphs (made on first use) for a lane whose
+  // stream cannot be captured (the caller's, possibly the null stream); the
+  // graphs are launched on the lane's stream.
+  hipStream_t cap_stream = nullptr;
   void* scratch = nullptr;     // the innermost open scratch set of this lane (rtg_host.cpp)
   // Blocks a pass drops are kept for the pass's own later allocations (no
   // wait); off for the request loop's lanes, whose admission reads the
@@ -216,8 +237,9 @@ struct Lane {
   int query_index(const Index& I, const float* queries, int64_t m, rtg_stats& st,
                   rtg_csr* out);
   int tiny_query(const float* points, int64_t n, int32_t d, rtg_csr* out, uint64_t handle);
-  // One pass of the pipeline over a batch of instances of one dimension.
-  int run_batch(std::vector<Job*>& jobs, rtg_stats& st);
+  // One pass of the pipeline over a batch of instances of one dimension
+  // (pp: the pass of a plan, or null).
+  int run_batch(std::vector<Job*>& jobs, rtg_stats& st, PassPlan* pp = nullptr);
 };
 
 struct Ctx {
@@ -296,7 +318,12 @@ struct Ctx {
   int all_pairs_noalloc(const float* points, int64_t n, int32_t d, double r, int32_t k,
                         double alpha, const double* R, const double* u, uint32_t flags,
                         int64_t* row_ptr, int32_t* col, int64_t col_capacity, int64_t* nnz);
-  int batched(const rtg_query* q, int32_t nq, rtg_csr* outs);
+  // Many queries: one pass per batch; with plan, batch b runs as plan[b].
+  int batched(const rtg_query* q, int32_t nq, rtg_csr* outs,
+              std::vector<std::unique_ptr<PassPlan>>* plan = nullptr);
+  // The batches batched() forms: query indices, grouped by dimension and
+  // list flags, at most batch_points points each.
+  std::vector<std::vector<int32_t>> batch_groups(const rtg_query* q, int32_t nq);
   int check_query(const float* points, int64_t n, int32_t d, double r, int32_t k, double alpha,
                   uint32_t flags);
   int debug_cell_coords(const float* points, int64_t n, int32_t d, double r, double alpha,

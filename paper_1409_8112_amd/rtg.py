@@ -107,6 +107,11 @@ def lib() -> ctypes.CDLL:
                                           i64, ctypes.POINTER(i64)],
                 "rtg_all_pairs_batched": [vp, ctypes.POINTER(rtg_query), i32,
                                           ctypes.POINTER(rtg_csr)],
+                "rtg_plan_create": [vp, ctypes.POINTER(rtg_query), i32, ctypes.POINTER(vp)],
+                "rtg_plan_run": [vp, ctypes.POINTER(rtg_query), i32, ctypes.POINTER(rtg_csr)],
+                "rtg_plan_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                  ctypes.POINTER(i64)],
+                "rtg_plan_destroy": [vp],
                 "rtg_submit": [vp, ctypes.POINTER(rtg_query), ctypes.POINTER(u64)],
                 "rtg_poll": [vp, u64, ctypes.POINTER(rtg_csr)],
                 "rtg_release": [vp, u64],
@@ -214,6 +219,41 @@ class Result:
             self.released = True
 
 
+class Plan:
+    """A plan of one context (rtg_plan_*): run() returns what
+    rtg_all_pairs_batched returns for the same queries."""
+
+    def __init__(self, ctx: "Context", handle, nq: int):
+        self.ctx, self.h, self.nq = ctx, handle, nq
+
+    def run(self, queries) -> list[Result]:
+        if self.h is None:
+            raise RTGError(EINVAL, "plan destroyed")
+        nq = len(queries)
+        qs, _pts = self.ctx._query_table(queries)
+        outs = (rtg_csr * max(nq, 1))()
+        _check(lib().rtg_plan_run(self.h, qs.ctypes.data_as(ctypes.POINTER(rtg_query)), nq, outs),
+               "rtg_plan_run")
+        return self.ctx._results(outs, nq)
+
+    def info(self) -> dict:
+        c, r, w = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().rtg_plan_info(self.h, ctypes.byref(c), ctypes.byref(r), ctypes.byref(w)),
+               "rtg_plan_info")
+        return {"captures": c.value, "replays": r.value, "workspace_bytes": w.value}
+
+    def destroy(self) -> None:
+        if self.h is not None and self.ctx.h.value:
+            _check(lib().rtg_plan_destroy(self.h), "rtg_plan_destroy")
+        self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+
 class Context:
     """An RTG context on one GPU: an arena of `arena_bytes` device memory from
     torch and torch's current HIP stream."""
@@ -241,6 +281,8 @@ class Context:
     # -- lifetime --------------------------------------------------------------
     def close(self) -> None:
         if getattr(self, "h", None) and self.h.value:
+            for p in getattr(self, "_plans", []):
+                p.destroy()  # a plan goes before its context
             lib().rtg_destroy(self.h)
             self.h = ctypes.c_void_p()
 
@@ -381,30 +423,36 @@ class Context:
                "rtg_tune_params")
         return int(k.value), float(a.value), float(rec.value), float(ms.value)
 
-    def rtg_all_pairs_batched(self, queries) -> list[Result]:
-        """queries: list of dicts with points, r, k, alpha, seed, flags."""
-        nq = len(queries)
-        # the query table filled column by column (one numpy write per field)
-        qs = np.zeros(max(nq, 1), dtype=np.dtype(rtg_query))
-        pts = [self._points(q["points"]) for q in queries]
-        if nq:
-            qs["points"][:nq] = [p.data_ptr() for p in pts]
-            qs["n"][:nq] = [p.shape[0] for p in pts]
-            qs["d"][:nq] = [p.shape[1] for p in pts]
-            qs["r"][:nq] = [q["r"] for q in queries]
-            qs["k"][:nq] = [q["k"] for q in queries]
-            qs["alpha"][:nq] = [q["alpha"] for q in queries]
-            qs["seed"][:nq] = [q.get("seed", 0) & (2**64 - 1) for q in queries]
-            qs["flags"][:nq] = [q.get("flags", 0) for q in queries]
-        outs = (rtg_csr * max(nq, 1))()
-        _check(lib().rtg_all_pairs_batched(self.h, qs.ctypes.data_as(ctypes.POINTER(rtg_query)),
-                                           nq, outs), "rtg_all_pairs_batched")
+    def _results(self, outs, nq: int) -> list[Result]:
         if nq == 0:
             return []
         # the output table read column by column (one numpy pass per field)
         arr = np.frombuffer(outs, dtype=np.dtype(rtg_csr), count=nq)
         cols = [arr[f].tolist() for f in ("handle", "n", "nnz", "pairs", "row_ptr", "col")]
         return [Result(self, *t) for t in zip(*cols)]
+
+    def rtg_all_pairs_batched(self, queries) -> list[Result]:
+        """queries: list of dicts with points, r, k, alpha, seed, flags."""
+        nq = len(queries)
+        # the query table filled column by column (one numpy write per field)
+        qs, _pts = self._query_table(queries)
+        outs = (rtg_csr * max(nq, 1))()
+        _check(lib().rtg_all_pairs_batched(self.h, qs.ctypes.data_as(ctypes.POINTER(rtg_query)),
+                                           nq, outs), "rtg_all_pairs_batched")
+        return self._results(outs, nq)
+
+    def rtg_plan_create(self, queries) -> "Plan":
+        """A plan for repeated batched calls of these queries' shape (each
+        query's n, d, k and flags)."""
+        qs, _pts = self._query_table(queries)
+        h = ctypes.c_void_p()
+        _check(lib().rtg_plan_create(self.h, qs.ctypes.data_as(ctypes.POINTER(rtg_query)),
+                                     len(queries), ctypes.byref(h)), "rtg_plan_create")
+        plan = Plan(self, h, len(queries))
+        if not hasattr(self, "_plans"):
+            self._plans = []
+        self._plans.append(plan)
+        return plan
 
     def rtg_submit(self, points, r: float, k: int, alpha: float, seed: int,
                    flags: int = 0) -> int | None:
@@ -509,6 +557,7 @@ class Context:
     tune_params = rtg_tune_params
     all_pairs_with_transforms = rtg_all_pairs_with_transforms
     all_pairs_batched = rtg_all_pairs_batched
+    plan_create = rtg_plan_create
     release_many = rtg_release_many
     submit = rtg_submit
     poll = rtg_poll
