@@ -173,8 +173,16 @@ int ceil_log2(uint64_t x) {
 // (d + 2) 2^-24 < 2^-17.9 of the exact value, and the FP64 sum within
 // (d + 2) 2^-53, so a value at or below lo is within r in FP64 and a value
 // above hi is not; only the band between is re-tested in FP64.
-PairTest make_pair_test(double r2, int pair_bits) {
+//
+// s_bound: two points of one cell of side c lie within its diagonal, so
+// |a - b|^2 <= d c^2 (the cell coordinates floor(R p / c + u) agree; R is
+// orthogonal and the FP64 rounding of R p / c + u is far below the 2^-10
+// margin, which also covers the FP32 centring and norms).  With o a point
+// of the cell, |a - o|^2 + |b - o|^2 <= 2 d c^2.
+PairTest make_pair_test(double r2, int pair_bits, int d, double cell_side) {
   PairTest t;
+  const double sb = 2.0 * d * cell_side * cell_side * (1.0 + 0x1p-10);
+  t.s_bound = (sb < 0x1p100) ? (float)sb : 0.0f;
   const double lo_d = r2 * (1.0 - 0x1p-16);
   float lo = (float)lo_d;
   if ((double)lo > lo_d) lo = std::nextafter(lo, -INFINITY);
@@ -283,6 +291,7 @@ int plan_batch(int d, uint32_t m, const int64_t* k, const int64_t* n, const doub
   }
   std::vector<int> need(d, 1);
   P.klo.assign((size_t)S_total * d, 0);
+  P.wrapped = false;
   int bmin = 1;
   int64_t tr = 0;
   for (uint32_t q = 0; q < m; ++q) {
@@ -307,6 +316,8 @@ int plan_batch(int d, uint32_t m, const int64_t* k, const int64_t* n, const doub
           klo = (int64_t)std::floor(ylo) - 1;
           const int64_t khi = (int64_t)std::floor(yhi) + 1;
           bits = std::max(1, ceil_log2((uint64_t)(khi - klo + 1)));
+        } else {
+          P.wrapped = true;  // 32-bit fields of cell coordinates beyond 2^31
         }
         P.klo[(size_t)tr * d + j] = klo;
         need[j] = std::max(need[j], std::min(bits, 32));
@@ -381,6 +392,10 @@ Ctx::Ctx(int dev) : device(dev) {
     if (std::strcmp(e, "vector") == 0) pair_screen = 1;
     if (std::strcmp(e, "matrix") == 0) pair_screen = 2;
   }
+  // RTG_BAND: "tile" makes the matrix-core screen bound its FP32 band by each
+  // tile pair's largest norms instead of the cell diagonal (narrower band,
+  // fewer FP64 re-tests, two wave reductions per tile pair).
+  if (const char* e = std::getenv("RTG_BAND")) unit_band = std::strcmp(e, "tile") != 0;
   // RTG_GATHER: "sorted" makes the pair kernels read a copy of the cell
   // members' rows gathered in sorted order instead of the rows by index.
   if (const char* e = std::getenv("RTG_GATHER")) gather_direct = std::strcmp(e, "sorted") != 0;
@@ -1252,7 +1267,8 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st, PassPlan* pp) {
   for (uint32_t q = 0; q < m; ++q) {
     const Job& j = *jobs[q];
     sub[q] = axes_per_robot(d, j.flags);
-    tests[q] = make_pair_test(sub[q] ? mr_screen_r2(j.r) : j.r * j.r, pair_bits);
+    tests[q] = make_pair_test(sub[q] ? mr_screen_r2(j.r) : j.r * j.r, pair_bits, d,
+                              j.alpha * j.r);
     any_mr = any_mr || sub[q] > 0;
     std::memcpy(&Rh[(size_t)inst[q].tr_off * d * d], j.R, sizeof(double) * (size_t)j.k * d * d);
     std::memcpy(&uh[(size_t)inst[q].tr_off * d], j.u, sizeof(double) * (size_t)j.k * d);
@@ -1685,6 +1701,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st, PassPlan* pp) {
     pa.d = d;
     pa.tests = tests_d;
     pa.gram = use_gram ? 1 : 0;
+    pa.unit_band = (ctx->unit_band && !P.truncated && !P.wrapped) ? 1 : 0;
     if (first_owner) {
       pa.W = sig_W;
       pa.g = sig_g;

@@ -29,6 +29,10 @@ struct PairTest {
   float hi;      // reject if d2_f32 >  hi  (hi >= r2 (1 + 2^-16))
   double r2;     // FP64 decision in between: s <= r2
   int32_t pair_bits;  // bits of one index in a packed (i,j) pair
+  // An FP32 bound on |a - o|^2 + |b - o|^2 for three points a, b, o of one
+  // grid cell (twice the squared cell diagonal, with margin), used by the
+  // matrix-core screen when the cell keys are exact; 0: none.
+  float s_bound;
 };
 
 // Optional hook around kernel launches (HIP-event timing, byte accounting).
@@ -260,6 +264,9 @@ struct PairsArgs {
   unsigned long long *cand_count, *rechecks;  // cand_count: [nseg]
   uint32_t nseg;           // output segments (0 or 1: one)
   int gram;                // 1: matrix-core screen (d <= 16), 0: vector screen
+  // 1: every unit holds the points of one grid cell (no two cells share a
+  // key), so the matrix-core screen may take its band from tests[].s_bound
+  int unit_band;
   uint32_t max_blocks;     // grid size cap (0: default)
   // [pair_waves + 1]: wave w takes units [wave_first[w], wave_first[w + 1])
   // (launch_wave_ranges); null: every pair_waves-th unit from its own index

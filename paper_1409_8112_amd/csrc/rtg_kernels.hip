@@ -1380,6 +1380,27 @@ __device__ __forceinline__ uint32_t gram_col(int b, uint32_t lane) {
   return 32u * (((uint32_t)b >> 4) & 1u) + (lane & 31u);
 }
 
+// The screen's band for S = max |a'|^2 + max |b'|^2 (or a bound on it).  The
+// products carry lo into the sums (the B rows hold |b'|^2 - lo), so each
+// output is x = v - lo: x < 0 accepts, x > W rejects, anything between is
+// decided in FP64.  E bounds the rounding of x, including the lo term; a
+// band that reaches 0 (cells far wider than r) is decided in FP64 throughout.
+struct GramBand {
+  float lo;
+  uint32_t Wu;    // W as bits: x <= W for x >= 0
+  bool all_fp64;
+};
+__device__ __forceinline__ GramBand gram_band(float S, float r2f, float gain) {
+  constexpr float kU = 0x1p-24f;
+  const float E = (S + r2f) * gain + r2f * (4.0f * kU) + 1e-36f;
+  GramBand b;
+  b.all_fp64 = !(E < r2f);
+  b.lo = b.all_fp64 ? 0.0f : (r2f - E) * (1.0f - 0x1p-20f);
+  const float hi = (r2f + E) * (1.0f + 0x1p-20f);
+  b.Wu = __float_as_uint(next_up(hi - b.lo));
+  return b;
+}
+
 // Four waves per SIMD up to D = 9 (at most 128 registers: a few spills at
 // D = 9 cost less than the lost wave); three above, where the registers the
 // wider rows need would spill more.
@@ -1390,8 +1411,7 @@ k_cell_pairs_gram(
   constexpr int KA = (D + 3) & ~1;  // augmented row length, even
   constexpr int KS = KA / 2;        // MFMA steps per block
   constexpr int KP = KA + 1;        // LDS row stride, odd: conflict-free column reads
-  constexpr float kU = 0x1p-24f;
-  constexpr float kGain = 1.5f * (float)(2 * KA + D + 8) * kU;
+  constexpr float kGain = 1.5f * (float)(2 * KA + D + 8) * 0x1p-24f;
   // A tile rows, then (once they are in registers) the A signature words;
   // the same for B.
   constexpr int kRegion = (kPairTile * KP > 2 * kSigWords * kPairTile) ? kPairTile * KP
@@ -1401,7 +1421,7 @@ k_cell_pairs_gram(
   __shared__ uint32_t sAi[kWaves][kPairTile];
   __shared__ uint32_t sBi[kWaves][kPairTile];
   __shared__ uint64_t sOut[kWaves][kOutBuf];
-  __shared__ uint16_t sPend[kWaves][kPend];  // accepted (row << 6 | col) codes
+  __shared__ uint16_t sPend[kWaves][kPend];  // accepted (lane << 6 | bit) codes
 
   const uint32_t lane = lane_id();
   const uint32_t l32 = lane & 31u, h = lane >> 5;
@@ -1433,6 +1453,12 @@ k_cell_pairs_gram(
     const UnitView Vn = unit_view(P, u + step, u_end);
     const PairTest T = P.tests[V.inst];
     const float r2f = (float)T.r2;
+    // When every unit is one grid cell, S <= s_bound for all of the unit's
+    // tile pairs: one band for the unit, no per-tile maxima.
+    const float s_bound =
+        __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(T.s_bound)));
+    const bool unit_band = P.unit_band && s_bound > 0.0f;
+    const GramBand ub = gram_band(s_bound, r2f, kGain);
     // origin: the first point of the unit's first tile (lane 0; wave-uniform)
     float o[D];
 #pragma unroll
@@ -1468,7 +1494,7 @@ k_cell_pairs_gram(
 #pragma unroll
       for (int l = 0; l < KA; ++l) sA[lane][l] = row[l];
     }
-    const float amax = wave_max_f(na);
+    const float amax = unit_band ? 0.0f : wave_max_f(na);
     wave_lds_sync();
     float areg[2][KS];
 #pragma unroll
@@ -1508,18 +1534,12 @@ k_cell_pairs_gram(
       for (int l = D + 2; l < KA; ++l) row[l] = 0.0f;
 #pragma unroll
       for (int q = 0; q < kSigWords; ++q) bsw[q] = cur.sw[q];
-      const float bmax = wave_max_f(nb);
-
-      // The tile pair's band.  The products carry lo into the sums (the B
-      // rows hold |b'|^2 - lo), so each output is x = v - lo: x < 0 accepts,
-      // x > W rejects, anything between is decided in FP64.  E bounds the
-      // rounding of x, including the lo term; a pair whose band reaches 0
-      // (cells far wider than r) is decided in FP64 throughout.
-      const float E = (amax + bmax + r2f) * kGain + r2f * (4.0f * kU) + 1e-36f;
-      const bool all_fp64 = !(E < r2f);
-      const float lo = all_fp64 ? 0.0f : (r2f - E) * (1.0f - 0x1p-20f);
-      const float hi = (r2f + E) * (1.0f + 0x1p-20f);
-      const uint32_t Wu = __float_as_uint(next_up(hi - lo));  // x <= W, as bits (x >= 0)
+      // the tile pair's band: the unit's, else from this pair's maxima
+      GramBand bd = ub;
+      if (!unit_band) bd = gram_band(amax + wave_max_f(nb), r2f, kGain);
+      const bool all_fp64 = bd.all_fp64;
+      const float lo = bd.lo;
+      const uint32_t Wu = bd.Wu;
       row[D + 1] = lane < nB ? nb - lo : 1e30f;
       sBi[w][lane] = cur.idx;
 #pragma unroll
@@ -1563,8 +1583,18 @@ k_cell_pairs_gram(
 #pragma unroll
             for (int i = 0; i < 16; ++i)
               cm = __builtin_amdgcn_alignbit(cm, __float_as_uint(v[i]) - (Wu + 1u), 31);
-            cm = all_fp64 ? 0xFFFFu : cm;
-            am = all_fp64 ? 0u : am;
+            if (all_fp64) {
+              // every pair of real points is decided in FP64; the padding
+              // rows and columns of a short tile hold no points
+              const bool col_in = 32u * (uint32_t)C + l32 < nB;
+              uint32_t in = 0u;
+#pragma unroll
+              for (int i = 0; i < 16; ++i)
+                in = (in << 1) |
+                     ((col_in && 32u * (uint32_t)R + mfma32_row((uint32_t)i, lane) < nA) ? 1u : 0u);
+              cm = in;
+              am = 0u;
+            }
           }
           uint32_t valid = 0xFFFFu;
           if (diag && R == C) {
@@ -1601,46 +1631,55 @@ k_cell_pairs_gram(
 
       // First owner: drop a pair that an earlier grid put in one cell.  The
       // B rows are in registers by now: their space takes the B words.  The
-      // accepted pairs are listed in LDS and checked one per lane, so that
-      // the check takes ceil(count / 64) rounds rather than the most any
-      // one lane holds.
+      // accepted bits are listed in LDS as (lane, bit) codes, each lane
+      // writing its own in turn, and are then worked one per lane -- the
+      // pair's row and column, the check, the packed pair -- so the per-pair
+      // work takes ceil(count / 64) rounds rather than the most any one lane
+      // holds.
       const uint32_t cnt = (uint32_t)__popcll(acc);
       const uint32_t incl = wave_inclusive_scan(cnt);
       const uint32_t total = lane_value(incl, 63);
-      if (V.nw && total) {
+      const bool check = V.nw != 0;
+      if (total && check) {
         wave_lds_sync();
 #pragma unroll
         for (int q = 0; q < kSigWords; ++q) sBw[q][lane] = bsw[q];
-        if (total <= kPend) {
-          uint32_t pos = incl - cnt;
-          uint64_t m = acc;
-          while (m) {
-            const int b = __builtin_ctzll(m);
-            m &= m - 1;
-            sPend[w][pos++] = (uint16_t)((gram_row(b, lane) << 6) | gram_col(b, lane));
-          }
-          wave_lds_sync();
-          for (uint32_t e0 = 0; e0 < total; e0 += 64) {
-            const uint32_t e = e0 + lane;
-            bool keep = e < total;
-            uint64_t pair = 0;
-            if (keep) {
-              const uint32_t code = sPend[w][e];
-              const uint32_t row = code >> 6, col = code & 63u;
+      }
+      if (total && total <= kPend) {
+        uint32_t pos = incl - cnt;
+        uint64_t m = acc;
+        while (m) {
+          const int b = __builtin_ctzll(m);
+          m &= m - 1;
+          sPend[w][pos++] = (uint16_t)((lane << 6) | (uint32_t)b);
+        }
+        wave_lds_sync();
+        for (uint32_t e0 = 0; e0 < total; e0 += 64) {
+          const uint32_t e = e0 + lane;
+          bool keep = e < total;
+          uint64_t pair = 0;
+          if (keep) {
+            const uint32_t code = sPend[w][e];
+            const int b = (int)(code & 63u);
+            const uint32_t row = gram_row(b, code >> 6), col = gram_col(b, code >> 6);
+            const uint32_t ia = sAi[w][row], ib = sBi[w][col];
+            if (check) {
               uint64_t aq[kSigWords], bq[kSigWords];
 #pragma unroll
               for (int q = 0; q < kSigWords; ++q) {
                 aq[q] = sAw[q][row];
                 bq[q] = sBw[q][col];
               }
-              keep = !shared_earlier_cell(aq, bq, V.tcell, pa0 + row, sAi[w][row], pb0 + col,
-                                          sBi[w][col], P);
-              pair = pack_pair(sAi[w][row], sBi[w][col], T.pair_bits);
+              keep = !shared_earlier_cell(aq, bq, V.tcell, pa0 + row, ia, pb0 + col, ib, P);
             }
-            append_pair(P, O, lane, keep, pair);
+            pair = pack_pair(ia, ib, T.pair_bits);
           }
-          wave_lds_sync();  // sPend is rewritten by the next tile pair
-        } else {
+          append_pair(P, O, lane, keep, pair);
+        }
+        wave_lds_sync();  // sPend is rewritten by the next tile pair
+      } else if (total) {
+        // more than the list holds: each lane checks and writes its own
+        if (check) {
           wave_lds_sync();
           uint64_t m = acc;
           while (m) {
@@ -1657,11 +1696,7 @@ k_cell_pairs_gram(
                                     sBi[w][col], P))
               acc &= ~(1ull << b);
           }
-          emit_pairs(P, O, lane, acc, [&](int b) {
-            return pack_pair(sAi[w][gram_row(b, lane)], sBi[w][gram_col(b, lane)], T.pair_bits);
-          });
         }
-      } else if (total) {
         emit_pairs(P, O, lane, acc, [&](int b) {
           return pack_pair(sAi[w][gram_row(b, lane)], sBi[w][gram_col(b, lane)], T.pair_bits);
         });
@@ -2372,22 +2407,25 @@ __global__ __launch_bounds__(kCsrThreads) void k_bucket_csr(
   for (int q = 0; q < kCsrItems; ++q)
     if (threadIdx.x + (uint32_t)q * kCsrThreads < cnt) s[atomicAdd(&rcur[e_[q] >> pb], 1u)] = e_[q];
   __syncthreads();
+  // Short rows: thread t takes the entries at positions t, t + 1024, ... of
+  // the row-ordered array, so the lanes of a wave cover a few whole rows and
+  // read the same row element at each step (broadcast reads, no bank
+  // conflicts).  Each entry's place is the number of smaller columns in its
+  // row (the row bits are equal, so whole entries compare as columns).
 #pragma unroll
   for (int q = 0; q < kCsrItems; ++q) {
-    if (threadIdx.x + (uint32_t)q * kCsrThreads < cnt) {
-      const uint32_t r = e_[q] >> pb;
+    const uint32_t x = threadIdx.x + (uint32_t)q * kCsrThreads;
+    if (x < cnt) {
+      const uint32_t e = s[x];
+      const uint32_t r = e >> pb;
       const uint32_t lo = rstart[r], hi = rcur[r];
       if (hi - lo <= kShortRow) {
-        const uint32_t c = e_[q] & cmask;
-        // the rank of c among its row: four independent LDS reads per step
-        uint32_t rank = 0, x = lo;
-        for (; x + 4 <= hi; x += 4) {
-          const uint32_t a0 = s[x], a1 = s[x + 1], a2 = s[x + 2], a3 = s[x + 3];
-          rank += ((a0 & cmask) < c ? 1u : 0u) + ((a1 & cmask) < c ? 1u : 0u) +
-                  ((a2 & cmask) < c ? 1u : 0u) + ((a3 & cmask) < c ? 1u : 0u);
-        }
-        for (; x < hi; ++x) rank += (s[x] & cmask) < c ? 1u : 0u;
-        col[(size_t)start + lo + rank] = (int32_t)c;
+        uint32_t rank = 0, y = lo;
+        for (; y + 4 <= hi; y += 4)
+          rank += (s[y] < e ? 1u : 0u) + (s[y + 1] < e ? 1u : 0u) + (s[y + 2] < e ? 1u : 0u) +
+                  (s[y + 3] < e ? 1u : 0u);
+        for (; y < hi; ++y) rank += s[y] < e ? 1u : 0u;
+        col[(size_t)start + lo + rank] = (int32_t)(e & cmask);
       }
     }
   }
@@ -2590,6 +2628,7 @@ inline unsigned grid_for(size_t count, unsigned block = kBlock) {
 inline unsigned tiles_for(size_t count) { return (unsigned)((count + kTile - 1) / kTile); }
 
 }  // namespace
+
 
 // ===========================================================================
 // launchers

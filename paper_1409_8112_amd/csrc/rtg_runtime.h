@@ -51,6 +51,7 @@ struct Packing {
   int seg_bits = 0;          // bits of the grid id above the cell fields
   int key_bits = 0;          // seg_bits + cell_bits
   bool truncated = false;    // some field narrower than its span (aliasing)
+  bool wrapped = false;      // some field's span beyond 32 bits (aliasing)
 };
 
 int make_transforms(uint64_t seed, int32_t k, int32_t d, uint32_t flags, double* R, double* u);
@@ -259,6 +260,7 @@ struct Ctx {
   int64_t batch_points = kBatchPoints;             // points per batch
   int server_lanes = 2;  // passes of the request loop that may run at once
   int pair_screen = 0;   // 0 auto, 1 vector, 2 matrix cores (d <= 16)
+  bool unit_band = true;  // matrix-core band from the cell diagonal where keys are exact
   bool gather_direct = true;  // pair kernels read rows by point index
   uint32_t pair_blocks = 0;      // pair-kernel grid (0: from the tuning's tests per wave)
   bool balanced_units = true;    // pair-kernel waves take equal shares of the tile pairs

@@ -215,3 +215,51 @@ def test_band_covers_the_model_bound():
                 model = U * S * (2 * KA + D + 7) + U * r2f * (KA + 2)
                 model += (KA + D + 3) ** 2 * U * U * (S + r2f)
                 assert E >= model, (D, float(r2), mult)
+
+
+def _haar(rng, d):
+    q, r = np.linalg.qr(rng.normal(size=(d, d)))
+    return q * np.sign(np.diag(r))
+
+
+def _norms32(P, o):
+    """|fl(p - o)|^2 for each row p, in FP32 as the screen forms it (centred
+    coordinates rounded to FP32, squares summed by an FMA chain)."""
+    c = (P.astype(np.float32) - o.astype(np.float32)).astype(np.float32)
+    acc = np.zeros(len(P), dtype=np.float32)
+    for l in range(P.shape[1]):
+        x = c[:, l].astype(np.float64)
+        acc = (x * x + acc.astype(np.float64)).astype(np.float32)
+    return acc
+
+
+@pytest.mark.parametrize("d,side,offset", [(2, 0.3, 0.0), (3, 1.7, 5e3), (6, 0.26, 0.0),
+                                           (6, 0.26, 3e4), (9, 0.9, 1e2), (12, 2.0, 7e5),
+                                           (16, 0.05, 1e1)])
+def test_cell_diagonal_bounds_the_band_norms(d, side, offset):
+    """The unit-wide band takes S <= s_bound = 2 d c^2 (1 + 2^-10) (rounded
+    to FP32) for any three points a, b, o of one grid cell.  Points of one
+    cell -- its corners and random interior points, mapped back through the
+    grid's rotation and shift, rounded to FP32, kept only if their FP64 cell
+    is still that cell -- all have |fl(p - o)|^2 <= s_bound / 2 for every
+    origin o among them."""
+    rng = np.random.default_rng(d * 7 + int(offset) % 13)
+    R = _haar(rng, d)
+    u = rng.random(d)
+    kappa = np.floor(rng.normal(size=d) * 3 + offset / side)
+    # corners pulled in by more than the FP32 spacing of the coordinates, so
+    # that rounding keeps them in the cell
+    m = max(1e-3, 4.0 * (abs(offset) + 10.0) * 2.0 ** -23 / side)
+    bits = rng.random((32, d)) < 0.5
+    corners = np.concatenate([np.where(bits, 1 - m, m), np.where(bits, m, 1 - m)])
+    y = np.concatenate([kappa + corners, kappa + rng.random((200, d))])
+    P = ((y - u) * side) @ R                       # R^T applied row-wise
+    P32 = P.astype(np.float32)
+    cell = np.floor((P32.astype(np.float64) @ R.T) / side + u)
+    P32 = P32[(cell == kappa).all(axis=1)]
+    assert len(P32) > 150
+    s_bound = np.float32(2.0 * d * side * side * (1.0 + 2.0 ** -10))
+    worst = max(float(_norms32(P32, o).max()) for o in P32[:40])
+    assert 2 * worst <= float(s_bound), (worst, float(s_bound))
+    # and the bound is not loose: opposite corners (both kept) come near it
+    assert 2 * worst >= 0.9 * (1 - 2 * m) ** 2 * float(s_bound)

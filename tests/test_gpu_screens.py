@@ -93,6 +93,26 @@ def test_one_huge_cell(screen):
     _check(mode, ctx, res, oracle.bruteforce(p, r))
 
 
+def test_huge_cell_far_wider_than_r(screen):
+    """One cell whose points spread a few hundred r apart: the screen's band
+    reaches 0 and every pair of real points is decided in FP64 (the short
+    tiles' padding rows and columns must not be taken for points)."""
+    mode, ctx = screen
+    rng = np.random.default_rng(23)
+    centres = rng.random((30, 3)) * 200.0
+    p = (np.repeat(centres, 50, axis=0) + rng.normal(size=(1500, 3)) * 0.05).astype(np.float32)
+    p = p[:1477]  # ragged last tile
+    r = 0.08
+    R, u = oracle.make_transforms(0, 64, 3)
+    # the points' rotated coordinates span under 0.05 cells: a shift away
+    # from the faces keeps them in one cell
+    t = next(t for t in range(64) if np.all((u[t] > 0.1) & (u[t] < 0.9)))
+    res = ctx.all_pairs_with_transforms(_dev(p), r, 1e5, R[t:t + 1], u[t:t + 1])
+    ref = oracle.bruteforce(p, r)
+    assert len(ref.col) > 1000
+    _check(mode, ctx, res, ref)
+
+
 def test_coincident_points(screen):
     p = np.repeat(workloads.uniform_points(40, 4, seed=2), 9, axis=0)
     _run(screen, p, 0.05, 3, 2.0, 5)
