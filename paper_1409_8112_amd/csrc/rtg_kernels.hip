@@ -194,6 +194,87 @@ __global__ __launch_bounds__(kBlock) void k_stage(const InstDesc* __restrict__ i
   }
 }
 
+// The minimum and maximum of lo / hi over the wave (every lane active), in
+// every lane: quads, half rows and rows by DPP, then the four rows' values.
+__device__ __forceinline__ void wave_minmax_u32(uint32_t& lo, uint32_t& hi) {
+  auto step = [&](auto ctrl) {
+    constexpr int C = decltype(ctrl)::value;
+    lo = min(lo, dpp_u32<C>(lo, lo));
+    hi = max(hi, dpp_u32<C>(hi, hi));
+  };
+  step(std::integral_constant<int, 0xB1>{});
+  step(std::integral_constant<int, 0x4E>{});
+  step(std::integral_constant<int, 0x141>{});
+  step(std::integral_constant<int, 0x140>{});
+  lo = min(min(lane_value(lo, 0), lane_value(lo, 16)), min(lane_value(lo, 32), lane_value(lo, 48)));
+  hi = max(max(lane_value(hi, 0), lane_value(hi, 16)), max(lane_value(hi, 32), lane_value(hi, 48)));
+}
+
+// k_stage for d = D <= 16: every coordinate of the thread's point loaded at
+// once, wave minima and maxima by DPP, and the point record (when asked
+// for: the coordinates, then zeros -- padding and the signature word the
+// key kernel writes) stored 16 bytes at a time.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_stage_d(const InstDesc* __restrict__ inst, uint32_t m,
+                                                    int64_t npts, float* __restrict__ soa,
+                                                    float* __restrict__ aos, uint32_t* bad,
+                                                    uint32_t* __restrict__ part,
+                                                    float* __restrict__ rec) {
+  constexpr int RS = (D + 2 + 3) & ~3;  // record floats (used for D <= 6)
+  __shared__ uint32_t smin[kWaves][D], smax[kWaves][D];
+  const uint32_t q = block_instance(inst, m, blockIdx.x);
+  const float* pts = inst[q].pts;
+  const int64_t i = (int64_t)(blockIdx.x - (uint32_t)inst[q].blk_first) * kBlock + threadIdx.x;
+  const bool live = i < inst[q].n;
+  const int64_t g = inst[q].pt_off + i;
+  const int w = threadIdx.x >> 6;
+  float v[D];
+#pragma unroll
+  for (int l = 0; l < D; ++l) v[l] = live ? pts[i * D + l] : 0.0f;
+  bool nonfinite = false;
+#pragma unroll
+  for (int l = 0; l < D; ++l) {
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    if (live) {
+      soa[(int64_t)l * npts + g] = v[l];
+      if (aos) aos[g * D + l] = v[l];
+      if (!isfinite(v[l])) nonfinite = true;
+      else lo = hi = float_order(v[l]);
+    }
+    wave_minmax_u32(lo, hi);
+    if (lane_id() == 0) {
+      smin[w][l] = lo;
+      smax[w][l] = hi;
+    }
+  }
+  if (ballot(nonfinite) && lane_id() == 0) atomicOr(bad, 1u);
+  if constexpr (D <= 6) {
+    if (rec && live) {
+      float4* r4 = reinterpret_cast<float4*>(rec + g * RS);
+#pragma unroll
+      for (int c4 = 0; c4 < RS / 4; ++c4) {
+        float4 x;
+        x.x = 4 * c4 + 0 < D ? v[4 * c4 + 0] : 0.0f;
+        x.y = 4 * c4 + 1 < D ? v[4 * c4 + 1] : 0.0f;
+        x.z = 4 * c4 + 2 < D ? v[4 * c4 + 2] : 0.0f;
+        x.w = 4 * c4 + 3 < D ? v[4 * c4 + 3] : 0.0f;
+        r4[c4] = x;
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < (unsigned)D) {
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+#pragma unroll
+    for (int q2 = 0; q2 < kWaves; ++q2) {
+      lo = min(lo, smin[q2][threadIdx.x]);
+      hi = max(hi, smax[q2][threadIdx.x]);
+    }
+    part[(size_t)blockIdx.x * 2 * D + 2 * threadIdx.x] = lo;
+    part[(size_t)blockIdx.x * 2 * D + 2 * threadIdx.x + 1] = hi;
+  }
+}
+
 // One block per instance: bbox[q][2j] = min over its blocks, [2j+1] = max.
 // bbox of every instance to the identities of min and max (bits of the
 // order-preserving encoding).
@@ -2652,8 +2733,32 @@ void launch_stage(const InstDesc* inst, uint32_t m, uint32_t nblocks, int d, int
                   float* rec, int rs, hipStream_t s) {
   if (!nblocks) return;
   hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(64), 0, s, bad, 0u, (size_t)1);
-  hipLaunchKernelGGL(k_stage, dim3(nblocks), dim3(kBlock), 0, s, inst, m, d, npts, soa, aos, bad,
-                     part, rec, rs);
+#define RTG_STAGE(DD)                                                                         \
+  hipLaunchKernelGGL(k_stage_d<DD>, dim3(nblocks), dim3(kBlock), 0, s, inst, m, npts, soa, aos, \
+                     bad, part, rec)
+  // records are made for d <= 6 only, rs = (d + 5) & ~3 as k_stage_d assumes
+  switch (d) {
+    case 1: RTG_STAGE(1); break;
+    case 2: RTG_STAGE(2); break;
+    case 3: RTG_STAGE(3); break;
+    case 4: RTG_STAGE(4); break;
+    case 5: RTG_STAGE(5); break;
+    case 6: RTG_STAGE(6); break;
+    case 7: RTG_STAGE(7); break;
+    case 8: RTG_STAGE(8); break;
+    case 9: RTG_STAGE(9); break;
+    case 10: RTG_STAGE(10); break;
+    case 11: RTG_STAGE(11); break;
+    case 12: RTG_STAGE(12); break;
+    case 13: RTG_STAGE(13); break;
+    case 14: RTG_STAGE(14); break;
+    case 15: RTG_STAGE(15); break;
+    case 16: RTG_STAGE(16); break;
+    default:
+      hipLaunchKernelGGL(k_stage, dim3(nblocks), dim3(kBlock), 0, s, inst, m, d, npts, soa, aos,
+                         bad, part, rec, rs);
+  }
+#undef RTG_STAGE
   const uint32_t nbox = m * 2u * (uint32_t)d;
   hipLaunchKernelGGL(k_bbox_init, dim3((nbox + kBlock - 1) / kBlock), dim3(kBlock), 0, s, bbox,
                      nbox);
