@@ -264,8 +264,9 @@ size_t Ctx::pass_bytes_bound(int64_t n, int32_t d, int32_t k, double alpha, uint
   double bytes = (double)n * (8.0 * d + d / 32.0 + std::max(4.0 * rs, 8.0 * W) + 16.0);
   // per key: two key buffers and two value buffers (worst case), cell
   // starts / ends / unit counts (6), unit descriptors (16.5), cell tests (4),
-  // unit work and its scan (4.2 + 0.1), sort and scan scratch (1)
-  bytes += N * (16.0 + 8.0 + 6.0 + 16.5 + 4.0 + 4.3 + 1.0);
+  // unit work and its scan (4.2 + 0.1), cell head and tail bits (0.25),
+  // sort and scan scratch (1)
+  bytes += N * (16.0 + 8.0 + 6.0 + 16.5 + 4.0 + 4.3 + 0.25 + 1.0);
   if (!gather_direct) bytes += N * (4.0 * d + 8.0 * W);
   // candidates: the pair kernels' segments (a quarter to spare) and the
   // compacted copy, then the list build (entries and the result) after the
@@ -1417,6 +1418,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st, PassPlan* pp) {
   const size_t ntiles = (NB + kTile - 1) / kTile;
   void* sort_scr = S.get<char>(radix_scratch_bytes(NB, 0, P.key_bits, (size_t)S_total));
   uint32_t* run_scr = S.get<uint32_t>(2 * ntiles + 8 + scan_scratch_elems(ntiles));
+  uint64_t* run_masks = S.get<uint64_t>(run_mask_words(NB));  // cell heads and tails
   const size_t max_cells = NB / 2 + 1;
   const size_t max_units = max_cells + NB / kPairTile + 1;
   uint32_t* cstart = S.get<uint32_t>(max_cells);
@@ -1437,6 +1439,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st, PassPlan* pp) {
   const size_t max_waves = (size_t)std::max<uint32_t>(ctx->pair_blocks, kMaxPairBlocks) * kWaves;
   uint32_t* wfirst = balanced ? S.get<uint32_t>(max_waves + 1) : nullptr;
   if (!keys || !keys_alt || (!idx_bits && (!vals || !vals_alt)) || !sort_scr || !run_scr ||
+      !run_masks ||
       !cstart || !cend || !units || !udesc || (!ctx->gather_direct && !spts) || !tests_c ||
       !scan64 || !scan32 ||
       (balanced && (!uwork || !uscan || !wfirst)))
@@ -1540,15 +1543,15 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st, PassPlan* pp) {
       mark(3);
       // cells with >= 2 points
       kbegin(RTG_K_CELLS);
-      launch_run_count(skeys, N, idx_bits, hcnt, tcnt, stream);
+      launch_run_count(skeys, N, idx_bits, hcnt, tcnt, run_masks, stream);
       if (counts_direct) {
-        launch_run_write(skeys, N, idx_bits, hcnt, tcnt, cstart, cend, tot, counters + 3, stream);
+        launch_run_write(run_masks, N, hcnt, tcnt, cstart, cend, tot, counters + 3, stream);
       } else {
         scan_exclusive_u32(hcnt, hcnt, nt, tot, sscr, stream);
         scan_exclusive_u32(tcnt, tcnt, nt, tot + 1, sscr, stream);
-        launch_run_write(skeys, N, idx_bits, hcnt, tcnt, cstart, cend, nullptr, nullptr, stream);
+        launch_run_write(run_masks, N, hcnt, tcnt, cstart, cend, nullptr, nullptr, stream);
       }
-      kend(RTG_K_CELLS, 16.0 * (double)N);
+      kend(RTG_K_CELLS, 8.5 * (double)N);  // keys once, head and tail bits out and back
       // Cell work, unit counts and their scans and the unit descriptors run on
       // the device's own cell count (tot[0]; the host knows only the bound
       // max_cells), so one read-back after them serves the whole cell stage.
@@ -1580,7 +1583,7 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st, PassPlan* pp) {
                               (const void*)run_scr, (const void*)cstart, (const void*)cend,
                               (const void*)units, (const void*)tests_c, (const void*)scan32,
                               (const void*)scan64, (const void*)udesc, (const void*)uwork,
-                              (const void*)counters})
+                              (const void*)counters, (const void*)run_masks})
         shape.push_back((int64_t)reinterpret_cast<uintptr_t>(ptr));
       for (int64_t v : {(int64_t)m, (int64_t)nblk, (int64_t)d, npts, (int64_t)sa, (int64_t)sb,
                         (int64_t)N, (int64_t)pass_pts, (int64_t)idx_bits, (int64_t)key_bits,

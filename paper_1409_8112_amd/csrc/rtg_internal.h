@@ -184,14 +184,17 @@ int radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* val
 
 // --- cells ----------------------------------------------------------------
 // Runs of equal keys >> shift with length >= 2 in a sorted key array: per
-// tile counts of run heads and run tails (u32 each, ntiles entries).
+// tile counts of run heads and run tails (u32 each, ntiles entries), and the
+// head and tail bits themselves, masks[2 g] and masks[2 g + 1] for the keys
+// [64 g, 64 g + 64) (run_mask_words(count) words).
 void launch_run_count(const uint64_t* keys, size_t count, int shift, uint32_t* head_cnt,
-                      uint32_t* tail_cnt, hipStream_t s);
-// Writes start[c] / end[c] of run c (ordered by position) given the scanned
-// per-tile offsets; or, with tot, given the raw per-tile counts (the kernel
-// adds up the earlier tiles' counts itself, writes tot[0] = runs (heads),
-// tot[1] = tails, and clears *zero if given).
-void launch_run_write(const uint64_t* keys, size_t count, int shift, const uint32_t* head_off,
+                      uint32_t* tail_cnt, uint64_t* masks, hipStream_t s);
+size_t run_mask_words(size_t count);
+// Writes start[c] / end[c] of run c (ordered by position) from the masks
+// given the scanned per-tile offsets; or, with tot, given the raw per-tile
+// counts (the kernel adds up the earlier tiles' counts itself, writes tot[0]
+// = runs (heads), tot[1] = tails, and clears *zero if given).
+void launch_run_write(const uint64_t* masks, size_t count, const uint32_t* head_off,
                       const uint32_t* tail_off, uint32_t* start, uint32_t* end, uint32_t* tot,
                       unsigned long long* zero, hipStream_t s);
 // units[c] = work units of run c (see UnitDesc), tests[c] = L(L-1)/2, and

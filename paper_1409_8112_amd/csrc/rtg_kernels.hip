@@ -835,17 +835,23 @@ __device__ __forceinline__ void run_flags(const uint64_t* __restrict__ keys, siz
 
 __global__ __launch_bounds__(kBlock) void k_run_count(const uint64_t* __restrict__ keys,
                                                       size_t count, int shift, uint32_t* head_cnt,
-                                                      uint32_t* tail_cnt) {
+                                                      uint32_t* tail_cnt,
+                                                      uint64_t* __restrict__ masks) {
   __shared__ uint32_t sh[kWaves], st[kWaves];
   const uint32_t lane = lane_id();
   const int w = threadIdx.x >> 6;
   const size_t wave_base = (size_t)blockIdx.x * kTile + (size_t)w * (kTile / kWaves);
+  const size_t ngroups = (count + 63) / 64;
   uint32_t hc = 0, tc = 0;
   for (int q = 0; q < kKeysPerThread; ++q) {
     bool h, t;
     run_flags(keys, count, wave_base + (size_t)q * 64 + lane, shift, h, t);
-    hc += (uint32_t)__popcll(ballot(h));
-    tc += (uint32_t)__popcll(ballot(t));
+    const uint64_t hb = ballot(h), tb = ballot(t);
+    hc += (uint32_t)__popcll(hb);
+    tc += (uint32_t)__popcll(tb);
+    // the writing kernel reads these bits instead of the keys again
+    const size_t g = (wave_base >> 6) + (size_t)q;
+    if (g < ngroups && lane < 2) masks[2 * g + lane] = lane ? tb : hb;
   }
   if (lane == 0) {
     sh[w] = hc;
@@ -867,8 +873,8 @@ __global__ __launch_bounds__(kBlock) void k_run_count(const uint64_t* __restrict
 // raw per-tile counts, which each block then adds up for the tiles before it
 // itself (the last block writes the totals to tot; block 0 clears *zero).
 template <bool FROM_COUNTS>
-__global__ __launch_bounds__(kBlock) void k_run_write(const uint64_t* __restrict__ keys,
-                                                      size_t count, int shift,
+__global__ __launch_bounds__(kBlock) void k_run_write(const uint64_t* __restrict__ masks,
+                                                      size_t count,
                                                       const uint32_t* __restrict__ head_off,
                                                       const uint32_t* __restrict__ tail_off,
                                                       uint32_t* __restrict__ start,
@@ -880,14 +886,19 @@ __global__ __launch_bounds__(kBlock) void k_run_write(const uint64_t* __restrict
   const uint32_t lane = lane_id();
   const int w = threadIdx.x >> 6;
   const size_t wave_base = (size_t)blockIdx.x * kTile + (size_t)w * (kTile / kWaves);
+  const size_t ngroups = (count + 63) / 64;
   uint32_t hmask = 0, tmask = 0, hc = 0, tc = 0;
   for (int q = 0; q < kKeysPerThread; ++q) {
-    bool h, t;
-    run_flags(keys, count, wave_base + (size_t)q * 64 + lane, shift, h, t);
-    hmask |= (uint32_t)h << q;
-    tmask |= (uint32_t)t << q;
-    hc += (uint32_t)__popcll(ballot(h));
-    tc += (uint32_t)__popcll(ballot(t));
+    const size_t g = (wave_base >> 6) + (size_t)q;
+    uint64_t hb = 0, tb = 0;
+    if (g < ngroups) {
+      hb = masks[2 * g];
+      tb = masks[2 * g + 1];
+    }
+    hmask |= (uint32_t)((hb >> lane) & 1ull) << q;
+    tmask |= (uint32_t)((tb >> lane) & 1ull) << q;
+    hc += (uint32_t)__popcll(hb);
+    tc += (uint32_t)__popcll(tb);
   }
   if (lane == 0) {
     sh[w] = hc;
@@ -2956,23 +2967,25 @@ int radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* val
   return where;
 }
 
+size_t run_mask_words(size_t count) { return 2 * ((count + 63) / 64); }
+
 void launch_run_count(const uint64_t* keys, size_t count, int shift, uint32_t* head_cnt,
-                      uint32_t* tail_cnt, hipStream_t s) {
+                      uint32_t* tail_cnt, uint64_t* masks, hipStream_t s) {
   if (!count) return;
   hipLaunchKernelGGL(k_run_count, dim3(tiles_for(count)), dim3(kBlock), 0, s, keys, count, shift,
-                     head_cnt, tail_cnt);
+                     head_cnt, tail_cnt, masks);
 }
 
-void launch_run_write(const uint64_t* keys, size_t count, int shift, const uint32_t* head_off,
+void launch_run_write(const uint64_t* masks, size_t count, const uint32_t* head_off,
                       const uint32_t* tail_off, uint32_t* start, uint32_t* end, uint32_t* tot,
                       unsigned long long* zero, hipStream_t s) {
   if (!count) return;
   if (tot)
-    hipLaunchKernelGGL(k_run_write<true>, dim3(tiles_for(count)), dim3(kBlock), 0, s, keys, count,
-                       shift, head_off, tail_off, start, end, tot, zero);
+    hipLaunchKernelGGL(k_run_write<true>, dim3(tiles_for(count)), dim3(kBlock), 0, s, masks, count,
+                       head_off, tail_off, start, end, tot, zero);
   else
-    hipLaunchKernelGGL(k_run_write<false>, dim3(tiles_for(count)), dim3(kBlock), 0, s, keys, count,
-                       shift, head_off, tail_off, start, end, (uint32_t*)nullptr,
+    hipLaunchKernelGGL(k_run_write<false>, dim3(tiles_for(count)), dim3(kBlock), 0, s, masks,
+                       count, head_off, tail_off, start, end, (uint32_t*)nullptr,
                        (unsigned long long*)nullptr);
 }
 

@@ -1,8 +1,10 @@
 """Both pair screens, forced: the vector screen (FP32 differences on the
-vector units) and the matrix-core screen (FP32 Gram blocks with a per-tile
-error band), each bit-exact to the oracle on the cases that stress them:
-ragged tiles, every d it serves, one huge cell, coincident points, pairs
-at r exactly and one ulp either side, aliased keys, clustered cells."""
+vector units) and the matrix-core screen (FP32 Gram blocks with an error
+band, from the cell diagonal where keys are exact or -- matrix-tile mode --
+from each tile pair's largest norms), each bit-exact to the oracle on the
+cases that stress them: ragged tiles, every d it serves, one huge cell,
+coincident points, pairs at r exactly and one ulp either side, aliased
+keys, clustered cells."""
 import os
 
 import numpy as np
@@ -13,7 +15,10 @@ from paper_1409_8112_amd import workloads
 
 pytestmark = pytest.mark.gpu
 
-MODES = ["vector", "matrix"]
+MODES = ["vector", "matrix", "matrix-tile"]
+# the environment each mode's context is made under
+ENV = {"vector": {"RTG_PAIRS": "vector"}, "matrix": {"RTG_PAIRS": "matrix"},
+       "matrix-tile": {"RTG_PAIRS": "matrix", "RTG_BAND": "tile"}}
 
 
 @pytest.fixture(scope="module", params=MODES)
@@ -22,15 +27,17 @@ def screen(request):
     from paper_1409_8112_amd import rtg
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    old = os.environ.get("RTG_PAIRS")
-    os.environ["RTG_PAIRS"] = request.param
+    env = ENV[request.param]
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
     try:
         c = rtg.Context(0, arena_bytes=8 << 30)
     finally:
-        if old is None:
-            del os.environ["RTG_PAIRS"]
-        else:
-            os.environ["RTG_PAIRS"] = old
+        for k, v in old.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
     yield request.param, c
     c.close()
 
@@ -47,7 +54,7 @@ def _check(mode, ctx, res, ref):
     st = ctx.stats()
     if st["tests"] > 0 and st["d"] <= 16:
         used = st["matrix_screen_launches"] > 0
-        assert used == (mode == "matrix"), st["matrix_screen_launches"]
+        assert used == mode.startswith("matrix"), st["matrix_screen_launches"]
 
 
 def _run(screen, p, r, k, alpha, seed, flags=0):
