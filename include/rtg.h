@@ -183,8 +183,16 @@ int rtg_destroy(rtg_ctx *ctx);
  *   seed selects the k transforms (see rtg_make_transforms).
  *   flags: RTG_NO_ROTATE, RTG_UPPER_ONLY, RTG_DEDUP_SORT or RTG_DEDUP_BITMAP,
  *   RTG_ROBOTS(b).
- * n <= 1 gives an empty list.  Errors: RTG_EINVAL (also for NaN/Inf
- * coordinates), RTG_ERANGE, RTG_ENOMEM, RTG_EDEVICE. */
+ * n <= 1 gives an empty list.  Small Euclidean instances (n <= 4096,
+ * d <= 8, n d <= 12288, k n <= 12288, k d (d + 1) <= 2048) run in two
+ * launches -- one workgroup per grid finds its cells, tests their pairs and
+ * keeps the first grid's, then the lists are built -- and take the general
+ * pipeline when their keys, pairs (131072) or rows (128) exceed what those
+ * launches hold; the lists are the same either way, and the stats count
+ * both launches under RTG_K_PAIRS with candidates = unique_pairs.  The
+ * environment setting RTG_SMALL=0 turns the small path off.  Errors:
+ * RTG_EINVAL (also for NaN/Inf coordinates), RTG_ERANGE, RTG_ENOMEM,
+ * RTG_EDEVICE. */
 int rtg_all_pairs(rtg_ctx *ctx, const float *points, int64_t n, int32_t d, double r, int32_t k,
                   double alpha, uint64_t seed, uint32_t flags, rtg_csr *out);
 

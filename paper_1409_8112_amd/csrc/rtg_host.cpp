@@ -155,6 +155,25 @@ void Arena::release(void* p) {
   add_free(start, len);
 }
 
+void Arena::shrink(void* p, size_t bytes) {
+  if (!p) return;
+  const size_t off = (size_t)(static_cast<char*>(p) - base_);
+  auto u = used_.find(off);
+  if (u == used_.end()) return;
+  bytes = (std::max<size_t>(bytes, 1) + kAlign - 1) & ~(size_t)(kAlign - 1);
+  if (bytes >= u->second) return;
+  const size_t tail = u->second - bytes;
+  u->second = bytes;
+  in_use_ -= tail;
+  size_t start = off + bytes, len = tail;
+  auto next = free_.lower_bound(start);
+  if (next != free_.end() && start + len == next->first) {
+    len += next->second;
+    drop_free(next);
+  }
+  add_free(start, len);
+}
+
 size_t Arena::largest_free() const { return by_size_.empty() ? 0 : by_size_.rbegin()->first; }
 
 // ---------------------------------------------------------------------------
@@ -397,6 +416,8 @@ Ctx::Ctx(int dev) : device(dev) {
   // tile pair's largest norms instead of the cell diagonal (narrower band,
   // fewer FP64 re-tests, two wave reductions per tile pair).
   if (const char* e = std::getenv("RTG_BAND")) unit_band = std::strcmp(e, "tile") != 0;
+  // RTG_SMALL=0: small instances take the general pipeline too.
+  if (const char* e = std::getenv("RTG_SMALL")) small_path = std::strcmp(e, "0") != 0;
   // RTG_GATHER: "sorted" makes the pair kernels read a copy of the cell
   // members' rows gathered in sorted order instead of the rows by index.
   if (const char* e = std::getenv("RTG_GATHER")) gather_direct = std::strcmp(e, "sorted") != 0;
@@ -474,6 +495,11 @@ Arena* Ctx::arena_of(const void* p) {
 void Ctx::dfree(void* p) {
   std::lock_guard<std::mutex> lk(amu);
   arena_of(p)->release(p);
+}
+
+void Ctx::dshrink(void* p, size_t bytes) {
+  std::lock_guard<std::mutex> lk(amu);
+  arena_of(p)->shrink(p, bytes);
 }
 
 size_t Ctx::largest_free() {
@@ -1140,10 +1166,120 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
     return rc;
   }
   Job job{points, n, d, r, alpha, k, flags, R, u, out};
+  if (small_path && n <= kTinyPoints && n * d <= kTinyFloats && d <= 8 &&
+      (int64_t)k * n <= kTinyCells && (int64_t)k * d * (d + 1) <= kTinyTransform &&
+      axes_per_robot(d, flags) == 0) {
+    rc = main.run_tiny(job, st);
+    if (rc != Lane::kTinyFallback) {
+      if (!rc) stats = st;
+      return rc;
+    }
+  }
   std::vector<Job*> jobs{&job};
   rc = main.run_batch(jobs, st);
   if (!rc) stats = st;
   return rc;
+}
+
+// One small instance: k workgroups find each grid's cells and test their
+// pairs (first grid only), one builds the lists into a result block sized
+// for the most pairs the small path takes, which then gives back its tail.
+// One read-back for the counts.
+int Lane::run_tiny(Job& j, rtg_stats& st) {
+  const int d = j.d;
+  int rc;
+  kstats = &st;
+  kpending.clear();
+  struct Detach {
+    Lane& c;
+    ~Detach() {
+      c.kpending.clear();
+      c.kstats = nullptr;
+    }
+  } detach{*this};
+  Scratch S(*this);
+  mark(0);
+  Uploads U(*this);
+  const size_t o_R = U.add(j.R, sizeof(double) * (size_t)j.k * d * d);
+  const size_t o_u = U.add(j.u, sizeof(double) * (size_t)j.k * d);
+  char* up = S.get<char>(U.total());
+  uint64_t* pairs = S.get<uint64_t>(kTinyPairCap);
+  int32_t* stage = S.get<int32_t>(2 * kTinyPairCap);
+  unsigned long long* cnt = S.get<unsigned long long>(8);  // [0..3] counts, [4] error bits
+  if (!up || !pairs || !stage || !cnt) return RTG_ENOMEM;
+  if ((rc = U.send(up))) return rc;
+  void* res = nullptr;
+  int64_t* row_ptr = nullptr;
+  int32_t* col = nullptr;
+  if ((rc = alloc_result(*this, j.n, 2 * kTinyPairCap, &res, &row_ptr, &col))) return rc;
+  launch_fill_u64(reinterpret_cast<uint64_t*>(cnt), 0ull, 8, stream);
+  TinyArgs a{};
+  a.pts = j.pts;
+  a.n = (int)j.n;
+  a.r2 = j.r * j.r;
+  a.inv_c = 1.0 / (j.alpha * j.r);
+  a.R = reinterpret_cast<const double*>(up + o_R);
+  a.u = reinterpret_cast<const double*>(up + o_u);
+  a.k = j.k;
+  a.pairs = pairs;
+  a.cap = kTinyPairCap;
+  a.count = cnt;
+  a.err = reinterpret_cast<uint32_t*>(cnt + 4);
+  a.upper = (j.flags & RTG_UPPER_ONLY) ? 1 : 0;
+  a.row_ptr = row_ptr;
+  a.col = col;
+  a.stage = stage;
+  kbegin(RTG_K_PAIRS);
+  launch_tiny(a, d, j.k, stream);
+  // points read per grid and pair; pairs, lists and row offsets written
+  kend(RTG_K_PAIRS, 4.0 * (double)j.n * d * j.k);
+  if ((rc = hip_fail(hipGetLastError(), "kernel launch"))) {
+    dfree(res);
+    return rc;
+  }
+  uint64_t got[8];
+  Gather g;
+  g.add(cnt, 8);
+  g.add(cnt + 1, 8);
+  g.add(cnt + 2, 8);
+  g.add(cnt + 3, 8);
+  g.add(cnt + 4, 4);
+  if ((rc = gather_back(g, got))) {
+    dfree(res);
+    return rc;
+  }
+  const uint64_t npairs = got[0], nnz = got[3];
+  const uint32_t err = (uint32_t)got[4];
+  kfinish();
+  if (err & 1u) {
+    dfree(res);
+    return RTG_EINVAL;
+  }
+  if (err & 2u) {
+    dfree(res);
+    return RTG_ERANGE;
+  }
+  if (err || npairs > kTinyPairCap) {
+    dfree(res);
+    return kTinyFallback;
+  }
+  const size_t rp = ((sizeof(int64_t) * (size_t)(j.n + 1)) + Arena::kAlign - 1) &
+                    ~(size_t)(Arena::kAlign - 1);
+  ctx->dshrink(res, rp + sizeof(int32_t) * std::max<uint64_t>(nnz, 1));
+  const bool both = !(j.flags & RTG_UPPER_ONLY);
+  st.cells = (int64_t)got[2];
+  st.tests = (int64_t)got[1];
+  st.candidates = (int64_t)npairs;
+  st.unique_pairs = (int64_t)npairs;
+  st.transforms_per_sort = 1;
+  j.out->n = j.n;
+  j.out->nnz = (int64_t)nnz;
+  j.out->row_ptr = row_ptr;
+  j.out->col = nnz ? col : nullptr;
+  j.out->pairs = (int64_t)(both ? nnz / 2 : nnz);
+  j.out->handle = ctx->keep_result(j.handle, res, j.n, (int64_t)nnz, j.out->pairs, row_ptr, col);
+  mark(8);
+  return RTG_OK;
 }
 
 // rtg_all_pairs into the caller's buffers with every device byte from the

@@ -373,6 +373,41 @@ void launch_query_pairs(const QueryArgs& a, hipStream_t s);
 void launch_gather_units(const PairsArgs& a, const uint64_t* sig, float* spts, uint64_t* ssig,
                          hipStream_t s);
 void launch_cell_pairs(const PairsArgs& a, hipStream_t s);
+
+// --- small instances --------------------------------------------------------
+// One instance of n <= kTinyPoints points (d <= 8, n d <= kTinyFloats,
+// k n <= kTinyCells, k d (d + 1) <= kTinyTransform) in two launches: k
+// workgroups, one per grid, find the cells (32-bit keys, sorted in LDS),
+// test their pairs in FP64 and append the pairs of the first grid that
+// holds both points to pairs; workgroups of 512 rows each build
+// the CSR lists from them.
+constexpr int kTinyPoints = 4096;
+constexpr int kTinyFloats = 12288;    // n d at most (the points are staged in LDS)
+constexpr int kTinyTransform = 2048;  // k d (d + 1) at most (the transforms too)
+constexpr int kTinyCells = 12288;     // k n at most (every grid's packed cells)
+constexpr int kTinyBinBits = 12;      // counting sort up to 2^12 cells, else bitonic
+constexpr int kTinyBins = 1 << kTinyBinBits;
+constexpr int kTinyListLds = 32768;   // list entries built in LDS (more: in stage)
+constexpr uint64_t kTinyPairCap = 131072;
+constexpr uint32_t kTinyMaxDeg = 128;
+struct TinyArgs {
+  const float* pts;           // [n][d] FP32
+  int n;
+  double r2, inv_c;           // r^2; 1 / (alpha r)
+  const double* R;            // [k][d][d]
+  const double* u;            // [k][d]
+  int k;
+  uint64_t* pairs;            // [cap]: (min << 32) | max
+  uint64_t cap;
+  unsigned long long* count;  // [0] pairs, [1] tests, [2] cells, [3] entries written
+  uint32_t* err;              // bits: 1 non-finite point, 2 cell out of range,
+                              // 4 key wider than 31 bits, 8 row over kTinyMaxDeg
+  int upper;                  // 1: one orientation
+  int64_t* row_ptr;           // [n + 1]
+  int32_t* col;               // [2 cap]
+  int32_t* stage;             // [2 cap]: the entries before their rows are ordered
+};
+void launch_tiny(const TinyArgs& a, int d, int k, hipStream_t s);
 // dst[0, sum cnt) = the segments' entries in segment order: segment s holds
 // src[s seg_cap, s seg_cap + cnt[s]).  dst must not overlap src.
 void launch_seg_compact(const uint64_t* src, uint64_t seg_cap, const unsigned long long* cnt,

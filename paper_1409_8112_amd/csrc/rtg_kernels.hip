@@ -2719,6 +2719,467 @@ inline unsigned grid_for(size_t count, unsigned block = kBlock) {
 
 inline unsigned tiles_for(size_t count) { return (unsigned)((count + kTile - 1) / kTile); }
 
+// ---------------------------------------------------------------------------
+// Small instances in two launches.  For n <= kTinyPoints (and d <= 8) the
+// whole pipeline fits one workgroup per grid: block t computes every
+// point's cell under grids 0..t (the FP64 formula of k_keys) and packs each
+// cell's fields into 32 bits (field widths from the block's own minimum and
+// maximum), sorts grid t's keys -- cell and point index -- in LDS (counting
+// sort over few cells, else bitonic), tests every pair of each cell in FP64
+// in the definition's order, keeps a pair within r only if no earlier
+// grid's packed cells of the two points are equal, and appends it to one
+// pair list.  A second launch turns the list into the CSR lists.
+// Anything outside these limits -- wider keys, more pairs than the lists
+// hold in LDS, a row longer than kTinyMaxDeg -- is flagged and the caller
+// runs the general pipeline instead.
+
+constexpr int kTinyThreads = 512;
+constexpr int kTinyWaves = kTinyThreads / 64;
+constexpr int kTinyPer = kTinyPoints / kTinyThreads;
+
+__device__ __forceinline__ uint32_t tiny_block_scan(uint32_t v, uint32_t* wsum, uint32_t& total) {
+  const uint32_t lane = lane_id();
+  const int w = threadIdx.x >> 6;
+  const uint32_t inc = wave_inclusive_scan(v);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (int q = 0; q < kTinyWaves; ++q) {
+    const uint32_t x = wsum[q];
+    if (q < w) before += x;
+    all += x;
+  }
+  __syncthreads();
+  total = all;
+  return before + inc - v;
+}
+
+// The wave's staged pairs (kTinyOut per wave) go to the list in one block
+// of slots; every lane of the wave takes part.
+constexpr uint32_t kTinyOut = 256;
+struct TinyOut {
+  uint64_t* buf;
+  uint32_t n;
+};
+__device__ __forceinline__ void tiny_flush(const TinyArgs& A, TinyOut& O, uint32_t lane) {
+  wave_lds_sync();
+  if (O.n) {
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(A.count, (unsigned long long)O.n);
+    base = lane_value(base, 0);
+    for (uint32_t e = lane; e < O.n; e += 64)
+      if (base + e < A.cap) A.pairs[base + e] = O.buf[e];
+    O.n = 0;
+  }
+  wave_lds_sync();
+}
+__device__ __forceinline__ void tiny_append(const TinyArgs& A, TinyOut& O, uint32_t lane,
+                                            bool keep, uint64_t val) {
+  const uint64_t m = ballot(keep);
+  const uint32_t c = (uint32_t)__popcll(m);
+  if (!c) return;
+  if (O.n + c > kTinyOut) tiny_flush(A, O, lane);
+  if (keep) O.buf[O.n + rank_below(m)] = val;
+  O.n += c;
+}
+
+template <int D>
+__global__ __launch_bounds__(kTinyThreads) void k_tiny_grids(const TinyArgs A) {
+  __shared__ float sp[kTinyFloats];         // the points, [n][D]
+  __shared__ double sT[kTinyTransform];     // R then u of every grid
+  __shared__ uint32_t sC[kTinyCells];       // packed cells of grids 0..t, [g][n]
+  __shared__ uint32_t skey[kTinyPoints];    // (cell << idx_bits) | point, sorted
+  __shared__ union {
+    uint32_t hist[kTinyBins];                // the counting sort's bins
+    uint64_t out[kTinyWaves][kTinyOut];      // then each wave's staged pairs
+  } sU;
+  __shared__ int32_t wlo[kTinyWaves][D], whi[kTinyWaves][D];
+  __shared__ uint32_t wsum[kTinyWaves];
+  __shared__ uint32_t sflag;
+  const int t = blockIdx.x;
+  const int n = A.n;
+  const uint32_t lane = lane_id();
+  const int w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) sflag = 0u;
+  uint32_t bad = 0u;
+  for (int e = (int)threadIdx.x; e < n * D; e += kTinyThreads) {
+    const float v = A.pts[e];
+    if (!isfinite(v)) bad |= 1u;
+    sp[e] = v;
+  }
+  const int nR = A.k * D * D;
+  for (int e = (int)threadIdx.x; e < nR + A.k * D; e += kTinyThreads)
+    sT[e] = e < nR ? A.R[e] : A.u[e - nR];
+  if (bad) atomicOr(&sflag, bad);
+  __syncthreads();
+  int idx_bits = 1;
+  while ((1 << idx_bits) < n) ++idx_bits;
+
+  // The packed cell of every point under grids 0..t: the fields (the key
+  // kernel's FP64 formula) less their minimum over the instance, side by
+  // side.  Grid t's cells key the sort; the earlier grids' decide, by one
+  // comparison, whether a pair was already some earlier grid's.
+  int cell_bits = 0;
+  for (int g = 0; g <= t; ++g) {
+    const double* Rg = sT + (size_t)g * D * D;
+    const double* ug = sT + nR + (size_t)g * D;
+    int32_t lo[D], hi[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      lo[j] = INT32_MAX;
+      hi[j] = INT32_MIN;
+    }
+    bad = 0u;
+    for (int i = (int)threadIdx.x; i < n; i += kTinyThreads) {
+      float p[D];
+#pragma unroll
+      for (int l = 0; l < D; ++l) p[l] = sp[i * D + l];
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const double y = cell_y<D>(Rg + (size_t)j * D, p, nullptr, 0, 0, D, A.inv_c, ug[j]);
+        const bool ok = fabs(y) < 2147483648.0;
+        const int32_t kj = ok ? (int32_t)floor(y) : 0;
+        if (!ok) bad |= 2u;
+        lo[j] = min(lo[j], kj);
+        hi[j] = max(hi[j], kj);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        lo[j] = min(lo[j], __shfl_xor(lo[j], o, 64));
+        hi[j] = max(hi[j], __shfl_xor(hi[j], o, 64));
+      }
+      if (lane == 0) {
+        wlo[w][j] = lo[j];
+        whi[w][j] = hi[j];
+      }
+    }
+    if (bad) atomicOr(&sflag, bad);
+    __syncthreads();
+    int shift[D], total = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      lo[j] = wlo[0][j];
+      hi[j] = whi[0][j];
+#pragma unroll
+      for (int q = 1; q < kTinyWaves; ++q) {
+        lo[j] = min(lo[j], wlo[q][j]);
+        hi[j] = max(hi[j], whi[q][j]);
+      }
+      int b = 0;
+      while (b < 32 && ((int64_t)1 << b) < (int64_t)hi[j] - (int64_t)lo[j] + 1) ++b;
+      shift[j] = total;
+      total += b;
+    }
+    uint32_t flag = sflag;
+    // grid t's key holds the point index too (and must not match the
+    // bitonic sort's padding); the earlier grids' cells only need 32 bits
+    if (g == t ? total + idx_bits > 31 : total > 32) flag |= 4u;
+    if (flag) {
+      if (threadIdx.x == 0) atomicOr(A.err, flag);
+      return;  // uniform: every thread read the same flag
+    }
+    cell_bits = total;
+    for (int i = (int)threadIdx.x; i < n; i += kTinyThreads) {
+      float p[D];
+#pragma unroll
+      for (int l = 0; l < D; ++l) p[l] = sp[i * D + l];
+      uint32_t cell = 0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const double y = cell_y<D>(Rg + (size_t)j * D, p, nullptr, 0, 0, D, A.inv_c, ug[j]);
+        cell |= (uint32_t)((int32_t)floor(y) - lo[j]) << shift[j];
+      }
+      sC[(size_t)g * n + i] = cell;
+    }
+    __syncthreads();  // wlo / whi are reused by the next grid
+  }
+  const uint32_t* cur = sC + (size_t)t * n;
+
+  // Grid t's keys in cell order: a counting sort over the cells when they
+  // are few, else a bitonic sort of the whole keys.
+  if (cell_bits <= kTinyBinBits) {
+    const int nb = 1 << cell_bits;
+    for (int c = (int)threadIdx.x; c < nb; c += kTinyThreads) sU.hist[c] = 0u;
+    __syncthreads();
+    for (int i = (int)threadIdx.x; i < n; i += kTinyThreads) atomicAdd(&sU.hist[cur[i]], 1u);
+    __syncthreads();
+    constexpr int per = kTinyBins / kTinyThreads;
+    uint32_t mine = 0;
+#pragma unroll
+    for (int e = 0; e < per; ++e) {
+      const int c = (int)threadIdx.x * per + e;
+      if (c < nb) mine += sU.hist[c];
+    }
+    uint32_t all;
+    uint32_t run = tiny_block_scan(mine, wsum, all);
+#pragma unroll
+    for (int e = 0; e < per; ++e) {
+      const int c = (int)threadIdx.x * per + e;
+      if (c < nb) {
+        const uint32_t h = sU.hist[c];
+        sU.hist[c] = run;
+        run += h;
+      }
+    }
+    __syncthreads();
+    for (int i = (int)threadIdx.x; i < n; i += kTinyThreads) {
+      const uint32_t c = cur[i];
+      skey[atomicAdd(&sU.hist[c], 1u)] = (c << idx_bits) | (uint32_t)i;
+    }
+    __syncthreads();
+  } else {
+    int np2 = 1;
+    while (np2 < n) np2 <<= 1;
+    for (int i = (int)threadIdx.x; i < np2; i += kTinyThreads)
+      skey[i] = i < n ? (cur[i] << idx_bits) | (uint32_t)i : 0xFFFFFFFFu;
+    __syncthreads();
+    for (int size = 2; size <= np2; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int x = (int)threadIdx.x; x < np2 / 2; x += kTinyThreads) {
+          const int a = 2 * stride * (x / stride) + (x % stride), b = a + stride;
+          const bool up = (a & size) == 0;
+          const uint32_t ka = skey[a], kb = skey[b];
+          if ((ka > kb) == up) {
+            skey[a] = kb;
+            skey[b] = ka;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+
+  // Pairs per sorted position: c_p = the positions after p in p's cell
+  // (the cell's end: the counting sort's cursor, else found by bisection);
+  // their exclusive prefix goes where grid t's cells were (no longer read).
+  const uint32_t imask = (1u << idx_bits) - 1u;
+  uint32_t* pre = sC + (size_t)t * n;
+  uint32_t cnt[kTinyPer];
+  uint32_t mine = 0, cells = 0;
+#pragma unroll
+  for (int e = 0; e < kTinyPer; ++e) {
+    const int p = (int)threadIdx.x * kTinyPer + e;
+    cnt[e] = 0;
+    if (p < n) {
+      const uint32_t cp = skey[p] >> idx_bits;
+      int lo = p + 1, hi = n;  // the first position past p's cell
+      if (cell_bits <= kTinyBinBits) {
+        lo = (int)sU.hist[cp];
+      } else {
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if ((skey[mid] >> idx_bits) == cp) lo = mid + 1; else hi = mid;
+        }
+      }
+      cnt[e] = (uint32_t)(lo - p - 1);
+      if (cnt[e] && (p == 0 || (skey[p - 1] >> idx_bits) != cp)) ++cells;
+      mine += cnt[e];
+    }
+  }
+  uint32_t T;
+  uint32_t run = tiny_block_scan(mine, wsum, T);  // barriers: every c_p is read
+#pragma unroll
+  for (int e = 0; e < kTinyPer; ++e) {
+    const int p = (int)threadIdx.x * kTinyPer + e;
+    if (p < n) {
+      pre[p] = run;
+      run += cnt[e];
+    }
+  }
+  __syncthreads();
+
+  // Each thread tests one contiguous run of the block's T pairs (p, q),
+  // p < q in one cell, in position order: its first p by bisection of pre,
+  // then q steps to the cell's end and p on to the next position with pairs.
+  const uint32_t chunk = (T + kTinyThreads - 1) / kTinyThreads;
+  uint32_t e = threadIdx.x * chunk;
+  const uint32_t e_end = min(T, e + chunk);
+  int p = 0, q = 0;
+  uint32_t pend = 0;  // pre of the position after p
+  uint32_t a = 0;
+  float pa[D];
+  if (e < e_end) {
+    int lo = 0, hi = n - 1;  // the last position with pre <= e
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pre[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    p = lo;
+    q = p + 1 + (int)(e - pre[p]);
+    pend = p + 1 < n ? pre[p + 1] : T;
+    a = skey[p] & imask;
+#pragma unroll
+    for (int l = 0; l < D; ++l) pa[l] = sp[a * D + l];
+  }
+  TinyOut O{sU.out[w], 0u};
+  // sU.hist was last read before the prefix scan's barriers
+  for (uint32_t round = 0; round < chunk; ++round, ++e) {
+    bool keep = false;
+    uint64_t val = 0;
+    if (e < e_end) {
+      if (e == pend) {  // on to the next position that has pairs
+        do {
+          ++p;
+          pend = p + 1 < n ? pre[p + 1] : T;
+        } while (pend == pre[p]);
+        q = p + 1;
+        a = skey[p] & imask;
+#pragma unroll
+        for (int l = 0; l < D; ++l) pa[l] = sp[a * D + l];
+      }
+      const uint32_t b = skey[q] & imask;
+      double s2 = 0.0;
+#pragma unroll
+      for (int l = 0; l < D; ++l) {
+        const double dl = (double)pa[l] - (double)sp[b * D + l];
+        s2 = s2 + dl * dl;
+      }
+      keep = s2 <= A.r2;
+      // first owner: no earlier grid with both points in one cell
+      for (int g = 0; keep && g < t; ++g)
+        if (sC[(size_t)g * n + a] == sC[(size_t)g * n + b]) keep = false;
+      val = ((uint64_t)min(a, b) << 32) | (uint64_t)max(a, b);
+      ++q;
+    }
+    tiny_append(A, O, lane, keep, val);
+  }
+  tiny_flush(A, O, lane);
+  // the block's cells (tests: T)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cells += __shfl_xor(cells, o, 64);
+  if (lane == 0 && cells) atomicAdd(A.count + 2, (unsigned long long)cells);
+  if (threadIdx.x == 0 && T) atomicAdd(A.count + 1, (unsigned long long)T);
+}
+
+// The pair list to CSR lists, the rows split over the workgroups
+// (kTinyThreads rows each): every workgroup counts every row's degree and
+// takes the offsets of all of them, places the entries of its own rows --
+// in LDS when they fit, else in A.stage -- and writes each at its rank
+// within its row (rows of at most kTinyMaxDeg entries).  count[3] receives
+// the entries written.
+__global__ __launch_bounds__(kTinyThreads) void k_tiny_lists(const TinyArgs A) {
+  __shared__ uint32_t cur[kTinyPoints];
+  __shared__ int32_t scol[kTinyListLds];
+  __shared__ uint32_t wsum[kTinyWaves];
+  __shared__ uint32_t smax, sbase, send;
+  constexpr int kB = 8;  // pairs in flight per thread
+  const uint64_t P = A.count[0];
+  if (P > A.cap || *A.err) return;  // uniform: the caller reruns or fails
+  const int n = A.n;
+  const uint32_t r0 = blockIdx.x * kTinyThreads, r1 = min((uint32_t)n, r0 + kTinyThreads);
+  for (int i = (int)threadIdx.x; i < n; i += kTinyThreads) cur[i] = 0u;
+  if (threadIdx.x == 0) smax = 0u;
+  __syncthreads();
+  for (uint32_t base = 0; base < (uint32_t)P; base += kB * kTinyThreads) {
+    uint64_t v[kB];
+#pragma unroll
+    for (int e = 0; e < kB; ++e) {
+      const uint32_t x = base + e * kTinyThreads + threadIdx.x;
+      v[e] = x < P ? A.pairs[x] : ~0ull;
+    }
+#pragma unroll
+    for (int e = 0; e < kB; ++e) {
+      if (v[e] == ~0ull) continue;
+      atomicAdd(&cur[(uint32_t)(v[e] >> 32)], 1u);
+      if (!A.upper) atomicAdd(&cur[(uint32_t)v[e]], 1u);
+    }
+  }
+  __syncthreads();
+  // row offsets: thread t takes the rows [t kTinyPer, (t + 1) kTinyPer);
+  // cur becomes the placement cursor of the workgroup's rows and the end
+  // of every other row (so a row's start is always its predecessor's cur)
+  uint32_t dg[kTinyPer];
+  uint32_t mine = 0, mx = 0;
+#pragma unroll
+  for (int e = 0; e < kTinyPer; ++e) {
+    const int i = (int)threadIdx.x * kTinyPer + e;
+    dg[e] = i < n ? cur[i] : 0u;
+    mine += dg[e];
+    mx = max(mx, dg[e]);
+  }
+  atomicMax(&smax, mx);
+  uint32_t all;
+  uint32_t run = tiny_block_scan(mine, wsum, all);
+  if (smax > kTinyMaxDeg) {
+    if (threadIdx.x == 0) atomicOr(A.err, 8u);
+    return;  // uniform after the scan's barriers
+  }
+#pragma unroll
+  for (int e = 0; e < kTinyPer; ++e) {
+    const uint32_t i = threadIdx.x * kTinyPer + e;
+    if (i < (uint32_t)n) {
+      const bool own = i >= r0 && i < r1;
+      if (own) A.row_ptr[i] = (int64_t)run;
+      cur[i] = own ? run : run + dg[e];
+      if (i == r0) sbase = run;
+      if (i + 1 == r1) send = run + dg[e];
+    }
+    run += dg[e];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    A.row_ptr[n] = (int64_t)all;
+    A.count[3] = all;
+  }
+  __syncthreads();
+  const uint32_t base = sbase;
+  const bool in_lds = send - base <= (uint32_t)kTinyListLds;
+  // entry at list position x: scol[x - base] or A.stage[x]
+  int32_t* stage = in_lds ? scol : A.stage;
+  const uint32_t off = in_lds ? base : 0u;
+  for (uint32_t b0 = 0; b0 < (uint32_t)P; b0 += kB * kTinyThreads) {
+    uint64_t v[kB];
+#pragma unroll
+    for (int e = 0; e < kB; ++e) {
+      const uint32_t x = b0 + e * kTinyThreads + threadIdx.x;
+      v[e] = x < P ? A.pairs[x] : ~0ull;
+    }
+#pragma unroll
+    for (int e = 0; e < kB; ++e) {
+      if (v[e] == ~0ull) continue;
+      const uint32_t a = (uint32_t)(v[e] >> 32), b = (uint32_t)v[e];
+      if (a >= r0 && a < r1) stage[atomicAdd(&cur[a], 1u) - off] = (int32_t)b;
+      if (!A.upper && b >= r0 && b < r1) stage[atomicAdd(&cur[b], 1u) - off] = (int32_t)a;
+    }
+  }
+  // the workgroup's own stores to A.stage are visible after the barrier
+  __threadfence_block();
+  __syncthreads();
+  // A row's entries are distinct, so each one's rank within the row is its
+  // place: kR entries at a time are held in registers and compared with
+  // every entry of the row, read kR at a time (INT32_MAX past the row's
+  // end counts below none).  One row per thread.
+  constexpr int kR = 16;
+  const uint32_t i = r0 + threadIdx.x;
+  if (i >= r1) return;
+  const uint32_t s = i ? cur[i - 1] : 0u, len = cur[i] - s;
+  const int32_t* row = stage + (s - off);
+  for (uint32_t x0 = 0; x0 < len; x0 += kR) {
+    int32_t v[kR];
+    uint32_t rank[kR];
+#pragma unroll
+    for (int x = 0; x < kR; ++x) {
+      v[x] = x0 + x < len ? row[x0 + x] : INT32_MAX;
+      rank[x] = 0;
+    }
+    for (uint32_t y0 = 0; y0 < len; y0 += kR) {
+      int32_t wv[kR];
+#pragma unroll
+      for (int y = 0; y < kR; ++y) wv[y] = y0 + y < len ? row[y0 + y] : INT32_MAX;
+#pragma unroll
+      for (int y = 0; y < kR; ++y)
+#pragma unroll
+        for (int x = 0; x < kR; ++x) rank[x] += wv[y] < v[x] ? 1u : 0u;
+    }
+#pragma unroll
+    for (int x = 0; x < kR; ++x)
+      if (x0 + x < len) A.col[s + rank[x]] = v[x];
+  }
+}
+
 }  // namespace
 
 
@@ -3138,6 +3599,25 @@ static void pairs_dispatch(const PairsArgs& a, hipStream_t s) {
     }
   }
   hipLaunchKernelGGL((k_cell_pairs<D>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+}
+
+void launch_tiny(const TinyArgs& a, int d, int k, hipStream_t s) {
+#define RTG_TINY(DD) \
+  hipLaunchKernelGGL(k_tiny_grids<DD>, dim3(k), dim3(kTinyThreads), 0, s, a)
+  switch (d) {
+    case 1: RTG_TINY(1); break;
+    case 2: RTG_TINY(2); break;
+    case 3: RTG_TINY(3); break;
+    case 4: RTG_TINY(4); break;
+    case 5: RTG_TINY(5); break;
+    case 6: RTG_TINY(6); break;
+    case 7: RTG_TINY(7); break;
+    case 8: RTG_TINY(8); break;
+    default: return;
+  }
+#undef RTG_TINY
+  hipLaunchKernelGGL(k_tiny_lists, dim3((a.n + kTinyThreads - 1) / kTinyThreads),
+                     dim3(kTinyThreads), 0, s, a);
 }
 
 void launch_cell_pairs(const PairsArgs& a, hipStream_t s) {

@@ -28,6 +28,7 @@ class Arena {
   Arena(char* base, size_t bytes);
   void* alloc(size_t bytes);  // nullptr when no free block is large enough
   void release(void* p);
+  void shrink(void* p, size_t bytes);  // gives back the tail of a block past bytes
   size_t largest_free() const;
   size_t size() const { return size_; }
   size_t in_use() const { return in_use_; }
@@ -241,6 +242,10 @@ struct Lane {
   // One pass of the pipeline over a batch of instances of one dimension
   // (pp: the pass of a plan, or null).
   int run_batch(std::vector<Job*>& jobs, rtg_stats& st, PassPlan* pp = nullptr);
+  // One small instance in two launches (kTinyPoints, d <= 8, Euclidean);
+  // kTinyFallback when it is outside the small path's limits.
+  static constexpr int kTinyFallback = 1000;
+  int run_tiny(Job& job, rtg_stats& st);
 };
 
 struct Ctx {
@@ -261,6 +266,7 @@ struct Ctx {
   int server_lanes = 2;  // passes of the request loop that may run at once
   int pair_screen = 0;   // 0 auto, 1 vector, 2 matrix cores (d <= 16)
   bool unit_band = true;  // matrix-core band from the cell diagonal where keys are exact
+  bool small_path = true;  // one small instance in two launches (Lane::run_tiny)
   bool gather_direct = true;  // pair kernels read rows by point index
   uint32_t pair_blocks = 0;      // pair-kernel grid (0: from the tuning's tests per wave)
   bool balanced_units = true;    // pair-kernel waves take equal shares of the tile pairs
@@ -302,6 +308,7 @@ struct Ctx {
   void* dalloc_noalloc(size_t bytes);   // from the no-allocation arena
   size_t largest_free_noalloc();
   void dfree(void* p);                  // to whichever arena holds p
+  void dshrink(void* p, size_t bytes);  // a block's tail back to its arena
   Arena* arena_of(const void* p);       // (under amu)
   // Device bytes one pass of the pipeline takes for an instance (points
   // excluded), while its candidates stay within cand_per_key per key.

@@ -16,11 +16,22 @@ K_PAIR_HIST, K_UNIQUE = 6, 8
 
 @pytest.fixture(scope="module")
 def ctx():
+    """Small instances through the general pipeline too (the de-duplication
+    kernels are its steps; the two-launch small path has its own tests)."""
+    import os
     import torch
     from paper_1409_8112_amd import rtg
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    c = rtg.Context(0, arena_bytes=24 << 30)
+    old = os.environ.get("RTG_SMALL")
+    os.environ["RTG_SMALL"] = "0"
+    try:
+        c = rtg.Context(0, arena_bytes=24 << 30)
+    finally:
+        if old is None:
+            del os.environ["RTG_SMALL"]
+        else:
+            os.environ["RTG_SMALL"] = old
     yield c
     c.close()
 

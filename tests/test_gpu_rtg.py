@@ -21,11 +21,21 @@ pytestmark = pytest.mark.gpu
 
 @pytest.fixture(scope="module")
 def ctx():
+    """A context whose small instances also take the general pipeline (the
+    two-launch small path has its own tests, test_gpu_small.py)."""
     import torch
     from paper_1409_8112_amd import rtg
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    c = rtg.Context(0, arena_bytes=24 << 30)
+    old = os.environ.get("RTG_SMALL")
+    os.environ["RTG_SMALL"] = "0"
+    try:
+        c = rtg.Context(0, arena_bytes=24 << 30)
+    finally:
+        if old is None:
+            del os.environ["RTG_SMALL"]
+        else:
+            os.environ["RTG_SMALL"] = old
     yield c
     c.close()
 

@@ -17,8 +17,9 @@ pytestmark = pytest.mark.gpu
 
 MODES = ["vector", "matrix", "matrix-tile"]
 # the environment each mode's context is made under
-ENV = {"vector": {"RTG_PAIRS": "vector"}, "matrix": {"RTG_PAIRS": "matrix"},
-       "matrix-tile": {"RTG_PAIRS": "matrix", "RTG_BAND": "tile"}}
+ENV = {"vector": {"RTG_PAIRS": "vector", "RTG_SMALL": "0"},
+       "matrix": {"RTG_PAIRS": "matrix", "RTG_SMALL": "0"},
+       "matrix-tile": {"RTG_PAIRS": "matrix", "RTG_BAND": "tile", "RTG_SMALL": "0"}}
 
 
 @pytest.fixture(scope="module", params=MODES)
