@@ -235,8 +235,9 @@ int rtg_all_pairs_noalloc(rtg_ctx *ctx, const float *points, int64_t n, int32_t 
 /* Many independent queries in one pass of the pipeline: every (query, grid)
  * pair is one segment of a shared key space, so each kernel launch covers all
  * queries.  outs[q] receives query q's list, identical to what rtg_all_pairs
- * returns for it alone.  On error no result is kept.  Errors as
- * rtg_all_pairs, for any query. */
+ * returns for it alone.  One query within the small-instance limits of
+ * rtg_all_pairs takes its two-launch path, as there.  On error no result is
+ * kept.  Errors as rtg_all_pairs, for any query. */
 int rtg_all_pairs_batched(rtg_ctx *ctx, const rtg_query *queries, int32_t nq, rtg_csr *outs);
 
 /* Plans: rtg_all_pairs_batched repeated over queries of one fixed shape (a
@@ -255,7 +256,8 @@ int rtg_all_pairs_batched(rtg_ctx *ctx, const rtg_query *queries, int32_t nq, rt
  * (rtg_set_timing) runs them as ordinary launches instead.  Runs are
  * blocking and serialised with the context's other calls.  rtg_plan_info
  * reports the graphs captured and replayed so far and the workspace bytes
- * held.  A plan belongs to its context: destroy it before the context.
+ * held (a plan of one small instance runs the two-launch path of
+ * rtg_all_pairs, which needs no graph: it captures nothing).  A plan belongs to its context: destroy it before the context.
  * Errors: RTG_EINVAL (NULL arguments, nq < 0, or for rtg_plan_run a shape
  * other than the plan's), and those of rtg_all_pairs_batched. */
 typedef struct rtg_plan rtg_plan;

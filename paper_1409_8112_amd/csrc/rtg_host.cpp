@@ -1139,6 +1139,13 @@ int Ctx::check_query(const float* points, int64_t n, int32_t d, double r, int32_
   return RTG_OK;
 }
 
+// Whether an instance is within the two-launch small path's limits.
+bool Ctx::small_fits(int64_t n, int32_t d, int32_t k, uint32_t flags) const {
+  return small_path && n > 1 && n <= kTinyPoints && n * d <= kTinyFloats && d <= 8 &&
+         (int64_t)k * n <= kTinyCells && (int64_t)k * d * (d + 1) <= kTinyTransform &&
+         axes_per_robot(d, flags) == 0;
+}
+
 // Lists for a query of n <= 1 points: empty, after the finiteness check.
 int Lane::tiny_query(const float* points, int64_t n, int32_t d, rtg_csr* out, uint64_t handle) {
   if (n == 1) {
@@ -1166,9 +1173,7 @@ int Ctx::all_pairs(const float* points, int64_t n, int32_t d, double r, int32_t 
     return rc;
   }
   Job job{points, n, d, r, alpha, k, flags, R, u, out};
-  if (small_path && n <= kTinyPoints && n * d <= kTinyFloats && d <= 8 &&
-      (int64_t)k * n <= kTinyCells && (int64_t)k * d * (d + 1) <= kTinyTransform &&
-      axes_per_robot(d, flags) == 0) {
+  if (small_fits(n, d, k, flags)) {
     rc = main.run_tiny(job, st);
     if (rc != Lane::kTinyFallback) {
       if (!rc) stats = st;
@@ -2293,6 +2298,19 @@ int Ctx::batched(const rtg_query* q, int32_t nq, rtg_csr* outs,
     }
     jobs[i] = Job{q[i].points, q[i].n, q[i].d, q[i].r, q[i].alpha, q[i].k, q[i].flags,
                   R[i].data(), u[i].data(), &res[i], 0};
+  }
+  // One small instance: the two-launch path, as rtg_all_pairs takes it
+  // (nothing is captured for it)
+  if (nq == 1 && small_fits(q[0].n, q[0].d, q[0].k, q[0].flags)) {
+    rc = main.run_tiny(jobs[0], st);
+    if (rc != Lane::kTinyFallback) {
+      if (rc) return rc;
+      outs[0] = res[0];
+      st.d = q[0].d;
+      st.k = q[0].k;
+      stats = st;
+      return RTG_OK;
+    }
   }
   std::vector<std::vector<Job*>> batches;
   for (const auto& g : groups) {

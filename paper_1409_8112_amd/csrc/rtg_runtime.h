@@ -267,6 +267,7 @@ struct Ctx {
   int pair_screen = 0;   // 0 auto, 1 vector, 2 matrix cores (d <= 16)
   bool unit_band = true;  // matrix-core band from the cell diagonal where keys are exact
   bool small_path = true;  // one small instance in two launches (Lane::run_tiny)
+  bool small_fits(int64_t n, int32_t d, int32_t k, uint32_t flags) const;
   bool gather_direct = true;  // pair kernels read rows by point index
   uint32_t pair_blocks = 0;      // pair-kernel grid (0: from the tuning's tests per wave)
   bool balanced_units = true;    // pair-kernel waves take equal shares of the tile pairs

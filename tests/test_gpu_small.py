@@ -179,3 +179,28 @@ def test_results_released_and_repeated(ctx):
         res.release()
     for rp, col in outs[1:]:
         assert np.array_equal(rp, outs[0][0]) and np.array_equal(col, outs[0][1])
+
+
+def test_one_query_batches_and_plans(ctx):
+    """A batch of one small query and a plan of one small instance take the
+    two-launch path too (a plan then captures nothing) with the same lists."""
+    from paper_1409_8112_amd import rtg
+    p = workloads.uniform_points(1800, 4, seed=44)
+    r = workloads.prm_radius(1800, 4, 1.0)
+    q = dict(points=_dev(p), r=r, k=3, alpha=2.0, seed=9)
+    ref = oracle.rtg(p, r, 3, 2.0, 9, 0)
+    res = ctx.all_pairs_batched([q])
+    rp, col = res[0].to_numpy()
+    ctx.release_many(res)
+    assert np.array_equal(rp, ref.row_ptr) and np.array_equal(col, ref.col)
+    assert ctx.stats()["kernel_launches"][rtg.KERNELS.index("keys")] == 0
+    plan = ctx.plan_create([q])
+    try:
+        for _ in range(3):
+            res = plan.run([q])
+            rp, col = res[0].to_numpy()
+            ctx.release_many(res)
+            assert np.array_equal(rp, ref.row_ptr) and np.array_equal(col, ref.col)
+        assert plan.info()["captures"] == 0 and plan.info()["replays"] == 0
+    finally:
+        plan.destroy()
