@@ -160,6 +160,9 @@ typedef struct rtg_stats {
   /* Pair-kernel launches of the last call that screened on the matrix cores
    * (the rest used the vector screen). */
   int64_t matrix_screen_launches;
+  /* Requests the request loop ran on the two-launch small-instance path
+   * (since rtg_create). */
+  int64_t served_small;
 } rtg_stats;
 
 /* Create a context on HIP device `device`.

@@ -1146,6 +1146,16 @@ bool Ctx::small_fits(int64_t n, int32_t d, int32_t k, uint32_t flags) const {
          axes_per_robot(d, flags) == 0;
 }
 
+// Device bytes the small path takes at most for an instance: the uploaded
+// transforms, the pair list, the list staging, the counts and the result
+// block before it gives back its tail (with room for alignment).
+size_t Ctx::small_bytes(int64_t n, int32_t d, int32_t k) const {
+  auto up = [](size_t b) { return (b + Arena::kAlign - 1) / Arena::kAlign * Arena::kAlign; };
+  return up(sizeof(double) * (size_t)k * d * (d + 1)) + up(sizeof(uint64_t) * kTinyPairCap) +
+         up(sizeof(int32_t) * 2 * kTinyPairCap) + up(64) + up(sizeof(int64_t) * (size_t)(n + 1)) +
+         up(sizeof(int32_t) * 2 * kTinyPairCap) + (64u << 10);
+}
+
 // Lists for a query of n <= 1 points: empty, after the finiteness check.
 int Lane::tiny_query(const float* points, int64_t n, int32_t d, rtg_csr* out, uint64_t handle) {
   if (n == 1) {
@@ -3027,6 +3037,7 @@ int rtg_get_stats(rtg_ctx* ctx, rtg_stats* out) {
   }
   out->served_requests = c->served_requests;
   out->served_batches = c->served_batches;
+  out->served_small = c->served_small;
   return RTG_OK;
 }
 

@@ -268,6 +268,7 @@ struct Ctx {
   bool unit_band = true;  // matrix-core band from the cell diagonal where keys are exact
   bool small_path = true;  // one small instance in two launches (Lane::run_tiny)
   bool small_fits(int64_t n, int32_t d, int32_t k, uint32_t flags) const;
+  size_t small_bytes(int64_t n, int32_t d, int32_t k) const;  // device bytes it takes at most
   bool gather_direct = true;  // pair kernels read rows by point index
   uint32_t pair_blocks = 0;      // pair-kernel grid (0: from the tuning's tests per wave)
   bool balanced_units = true;    // pair-kernel waves take equal shares of the tile pairs
@@ -345,7 +346,7 @@ struct Ctx {
   void stop_server();
   void wake_server();   // memory came back: requests waiting for it may run
   bool holds_results();  // results or indexes held in the arena
-  std::atomic<int64_t> served_requests{0}, served_batches{0};
+  std::atomic<int64_t> served_requests{0}, served_batches{0}, served_small{0};
 };
 
 }  // namespace rtg

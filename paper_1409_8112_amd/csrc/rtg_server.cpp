@@ -21,6 +21,12 @@
 // (a release, or a pass that ends) and runs again; it fails with ENOMEM
 // only when nothing else holds memory.  A query's result never depends on
 // its batch-mates: no step of a pass mixes instances.
+//
+// A query within the small-instance limits of rtg_all_pairs that reaches
+// the head of the queue while the device is idle runs alone on that path's
+// two launches, and no other pass starts meanwhile: its workgroups take a
+// CU's LDS each and would otherwise wait for another pass's kernels to
+// drain.  On a busy device it heads or joins a batch pass like any other.
 #include "../../include/rtg.h"
 #include "rtg_runtime.h"
 
@@ -43,6 +49,8 @@ struct Request {
   int state = kQueued;
   int rc = RTG_OK;
   bool solo = false;      // run alone on an idle device
+  bool small = false;     // within the small path's limits
+  bool tiny_run = false;  // picked to run alone on the small path
   // Ran alone and ran out of memory while other requests' points or results
   // held part of the budget: waits until some memory is given back (the
   // server's release count passes wait_gen).
@@ -136,6 +144,8 @@ int Server::submit(const rtg_query& q, uint64_t* ticket) {
   if (rc) return rc;
   const size_t pts_bytes = sizeof(float) * (size_t)q.n * (size_t)q.d;
   req->est = c.pass_bytes_bound(q.n, q.d, q.k, q.alpha, q.flags);
+  req->small = c.small_fits(q.n, q.d, q.k, q.flags);
+  if (req->small) req->est = std::max(req->est, c.small_bytes(q.n, q.d, q.k));
   if (req->est + pts_bytes > c.arena->size()) return RTG_ENOMEM;
   const uint64_t t = c.new_handle();
   req->ticket = t;
@@ -215,7 +225,8 @@ bool Server::pick(std::vector<Request*>& batch, size_t& est) {
   batch.push_back(h);
   est = h->est;
   int64_t pts = h->q.n;
-  if (!h->solo) {
+  h->tiny_run = h->small && running == 0;
+  if (!h->solo && !h->tiny_run) {
     const uint32_t g = group_of(h->q);
     for (size_t i = 0; i < queue.size(); ++i) {
       Request* r = queue[i];
@@ -242,7 +253,7 @@ void Server::work(int li) {
     size_t est = 0;
     while (!stop && !pick(batch, est)) cv.wait(lk);
     if (stop) return;
-    const bool solo = batch.size() == 1 && batch[0]->solo;
+    const bool solo = batch.size() == 1 && (batch[0]->solo || batch[0]->tiny_run);
     for (Request* r : batch) r->state = kRunning;
     reserved[li] = est;
     ++running;
@@ -258,7 +269,15 @@ void Server::work(int li) {
       ptrs[i] = &jobs[i];
     }
     rtg_stats st{};
-    const int rc = c.poisoned ? RTG_EDEVICE : L.run_batch(ptrs, st);
+    int rc = RTG_EDEVICE;
+    if (!c.poisoned) {
+      rc = Lane::kTinyFallback;
+      if (batch.size() == 1 && batch[0]->tiny_run) {
+        rc = L.run_tiny(jobs[0], st);
+        if (rc == RTG_OK) c.served_small += 1;
+      }
+      if (rc == Lane::kTinyFallback) rc = L.run_batch(ptrs, st);
+    }
 
     lk.lock();
     --running;

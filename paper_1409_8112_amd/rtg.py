@@ -76,7 +76,7 @@ class rtg_stats(ctypes.Structure):
         ("kernel_bytes", ctypes.c_double * NKERNELS),
         ("kernel_ms", ctypes.c_double * NKERNELS),
         ("served_requests", ctypes.c_int64), ("served_batches", ctypes.c_int64),
-        ("matrix_screen_launches", ctypes.c_int64)]
+        ("matrix_screen_launches", ctypes.c_int64), ("served_small", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         out = {}

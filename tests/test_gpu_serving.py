@@ -1,7 +1,8 @@
 """The request loop (rtg_submit / rtg_poll): every served result equals the
 oracle's and the lone call's, whatever it was batched with; requests are
 batched; the loop admits work by device memory; errors stay with their
-request."""
+request; a small request that finds the device idle runs alone on the
+two-launch small path."""
 import os
 
 import numpy as np
@@ -32,7 +33,9 @@ def _context(arena_bytes, **env):
 
 @pytest.fixture(scope="module")
 def ctx():
-    c = _context(8 << 30)
+    """Small requests batched too (RTG_SMALL=0): the batching tests below
+    take sizes the small path would otherwise run alone."""
+    c = _context(8 << 30, RTG_SMALL=0)
     yield c
     c.close()
 
@@ -94,6 +97,35 @@ def test_served_results_equal_oracle_and_lone_calls(ctx):
     tiny = sum(len(q["points"]) <= 1 for q in reqs)
     assert served == len(reqs) - tiny
     assert passes < served, "requests submitted together were never batched"
+
+
+def test_small_requests_on_an_idle_device_take_the_small_path():
+    c = _context(8 << 30)
+    try:
+        # one at a time: each finds the device idle and runs on the small path
+        small = _requests(11, 10, dims=(3, 6), n_lo=50, n_hi=1500)
+        before = c.stats()
+        for q in small:
+            (rp, col), = _serve(c, [q])
+            ref = _oracle(q)
+            assert np.array_equal(rp, ref.row_ptr) and np.array_equal(col, ref.col)
+        after = c.stats()
+        assert after["served_small"] - before["served_small"] == len(small)
+        # submitted together with larger ones: whichever path each takes,
+        # the lists are the oracle's
+        large = _requests(12, 12, dims=(12,), n_lo=500, n_hi=4000)
+        more = _requests(13, 24, dims=(3, 6), n_lo=50, n_hi=1500)
+        reqs = []
+        for i, q in enumerate(more):
+            reqs.append(q)
+            if i % 2:
+                reqs.append(large[i // 2])
+        got = _serve(c, reqs)
+        for q, (rp, col) in zip(reqs, got):
+            ref = _oracle(q)
+            assert np.array_equal(rp, ref.row_ptr) and np.array_equal(col, ref.col)
+    finally:
+        c.close()
 
 
 def test_submit_copies_the_points(ctx):
