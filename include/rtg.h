@@ -280,6 +280,8 @@ int rtg_plan_destroy(rtg_plan *plan);
  * released: a request that does not fit beside them stays pending until the
  * caller releases some (or other requests' staged points are dropped), and
  * fails with RTG_ENOMEM only when it does not fit with nothing else held.
+ * A request within rtg_all_pairs' small-instance limits that finds no pass
+ * running runs alone on that two-launch path (rtg_stats.served_small).
  * Errors: RTG_EINVAL, RTG_ENOMEM (its working-set bound plus its points
  * exceed the whole budget), RTG_ENOENT (unknown ticket). */
 int rtg_submit(rtg_ctx *ctx, const rtg_query *query, uint64_t *ticket);
