@@ -2729,9 +2729,9 @@ inline unsigned tiles_for(size_t count) { return (unsigned)((count + kTile - 1) 
 // in the definition's order, keeps a pair within r only if no earlier
 // grid's packed cells of the two points are equal, and appends it to one
 // pair list.  A second launch turns the list into the CSR lists.
-// Anything outside these limits -- wider keys, more pairs than the lists
-// hold in LDS, a row longer than kTinyMaxDeg -- is flagged and the caller
-// runs the general pipeline instead.
+// Anything outside these limits -- wider keys, more pairs than the list
+// holds (kTinyPairCap), a row longer than kTinyMaxDeg -- is flagged and the
+// caller runs the general pipeline instead.
 
 constexpr int kTinyThreads = 512;
 constexpr int kTinyWaves = kTinyThreads / 64;
