@@ -877,11 +877,14 @@ struct Scratch {
   bool carve_short = false;
   bool record = false;
   size_t recorded = 0;
+  // Set by a caller whose last stream operation was a read-back that waited
+  // for every kernel before it: the blocks go back without a stream wait.
+  bool drained = false;
   explicit Scratch(Lane& lane) : c(lane), outer(lane.scratch) { lane.scratch = this; }
   ~Scratch() {
     c.scratch = outer;
     if (held.empty() && pool.empty()) return;
-    (void)hipStreamSynchronize(c.stream);
+    if (!drained) (void)hipStreamSynchronize(c.stream);
     for (auto& b : held) c.dfree(b.first);
     for (auto& b : pool) c.dfree(b.first);
   }
@@ -1294,6 +1297,7 @@ int Lane::run_tiny(Job& j, rtg_stats& st) {
   j.out->pairs = (int64_t)(both ? nnz / 2 : nnz);
   j.out->handle = ctx->keep_result(j.handle, res, j.n, (int64_t)nnz, j.out->pairs, row_ptr, col);
   mark(8);
+  S.drained = true;  // the counts' read-back came after both launches
   return RTG_OK;
 }
 
@@ -2194,6 +2198,9 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st, PassPlan* pp) {
     pp->ws = ctx->dalloc(S.recorded);
     if (pp->ws) pp->head_bytes = S.recorded;
   }
+  // The pass's last stream operation was a read-back after its last kernel
+  // (the list build's, the error bits' or the localization's wait).
+  S.drained = true;
   return RTG_OK;
 }
 
