@@ -1452,7 +1452,6 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st, PassPlan* pp) {
   uint32_t* bad = bbox + (size_t)m * 2 * d;
   uint32_t* err = reinterpret_cast<uint32_t*>(counters + kErrWord);
   if ((rc = U1.send(up1))) return rc;
-  launch_fill_u64(reinterpret_cast<uint64_t*>(counters), 0ull, kCounterWords, stream);
 
   // First-owner filter (default): each pair is emitted only by the first grid
   // whose cell holds both points, so the union needs no de-duplication.  It
@@ -1500,7 +1499,9 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st, PassPlan* pp) {
   }
   // --- stage: SoA copy (+ concatenated rows), finiteness, bounding boxes -------
   kbegin(RTG_K_STAGE);
-  launch_stage(inst_d, m, nblk, d, npts, soa, aos, bad, bbox, part, rec, rs, stream);
+  // (its first launch also clears the pass's counters)
+  launch_stage(inst_d, m, nblk, d, npts, soa, aos, bad, bbox, part, rec, rs, stream,
+               reinterpret_cast<uint64_t*>(counters), kCounterWords);
   kend(RTG_K_STAGE, (aos ? 12.0 : 8.0) * (double)npts * d + (rec ? 4.0 * rs * (double)npts : 0.0));
   mark(1);
   std::vector<uint32_t> hb((size_t)m * 2 * d + 1);
@@ -1552,10 +1553,28 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st, PassPlan* pp) {
       }
     NB = std::max(NB, (size_t)off);
   }
+  // Each pass of several segments sorts within them (reduce-then-scan):
+  // its table of sort tiles goes up with the layout, in one copy.
+  std::vector<std::vector<SortTile>> pass_tabs;
+  for (int32_t sa = 0; sa < S_total; sa += P.tb) {
+    const int32_t sb = std::min(S_total, sa + P.tb);
+    pass_tabs.emplace_back();
+    if (sb - sa > 1 && T.sort_algo == kSortReduceScan) {
+      std::vector<uint64_t> soff, slen;
+      for (int32_t sg = sa; sg < sb; ++sg) {
+        soff.push_back((uint64_t)segs[sg].key_off);
+        slen.push_back((uint64_t)jobs[segs[sg].inst]->n);
+      }
+      pass_tabs.back() = segment_tiles(soff, slen);
+    }
+  }
   Uploads U2(*this);
   const size_t o_layout = U2.add(&P.layout, sizeof(KeyLayout));
   const size_t o_klo = U2.add(P.klo.data(), sizeof(int64_t) * P.klo.size());
   const size_t o_segs = U2.add(segs.data(), sizeof(SegDesc) * segs.size());
+  std::vector<size_t> o_tabs;
+  for (const auto& tab : pass_tabs)
+    o_tabs.push_back(U2.add(tab.data(), sizeof(SortTile) * tab.size()));
   char* up2 = S.get<char>(U2.total());
   if (!up2) return RTG_ENOMEM;
   KeyLayout* layout_d = reinterpret_cast<KeyLayout*>(up2 + o_layout);
@@ -1653,19 +1672,9 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st, PassPlan* pp) {
     uint32_t ntab = 0;
     SortTile* tab_d = nullptr;
     if (segmented) {
-      std::vector<uint64_t> soff, slen;
-      for (int32_t sg = sa; sg < sb; ++sg) {
-        soff.push_back((uint64_t)segs[sg].key_off);
-        slen.push_back((uint64_t)jobs[segs[sg].inst]->n);
-      }
-      const std::vector<SortTile> tab = segment_tiles(soff, slen);
-      ntab = (uint32_t)tab.size();
-      Uploads Ut(*this);
-      const size_t o_tab = Ut.add(tab.data(), sizeof(SortTile) * tab.size());
-      char* tab_mem = S.get<char>(Ut.total());
-      if (!tab_mem) return RTG_ENOMEM;
-      tab_d = reinterpret_cast<SortTile*>(tab_mem + o_tab);
-      if ((rc = Ut.send(tab_mem))) return rc;
+      const size_t pass = (size_t)(sa / P.tb);
+      ntab = (uint32_t)pass_tabs[pass].size();
+      tab_d = reinterpret_cast<SortTile*>(up2 + o_tabs[pass]);
     }
     const int sort_end = idx_bits + (segmented ? P.layout.cell_bits : key_bits);
     const size_t nt = (N + kTile - 1) / kTile;
@@ -1906,7 +1915,9 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st, PassPlan* pp) {
         sbuf = S.get<uint64_t>((size_t)nseg * seg_cap);
       }
       if (!sbuf) return RTG_ENOMEM;
-      launch_fill_u64(reinterpret_cast<uint64_t*>(segcnt), 0ull, nseg, stream);
+      // the stage's first launch cleared them for the first pair launch
+      if (sa > 0 || attempt > 0)
+        launch_fill_u64(reinterpret_cast<uint64_t*>(segcnt), 0ull, nseg, stream);
       pa.cand = sbuf;
       pa.cap = seg_cap;
       pa.cand_count = segcnt;

@@ -100,10 +100,12 @@ struct SegDesc {
 // instances' point blocks; part holds nblocks * 2d elements.  With rec, also
 // the point records of the pair kernels' tile loads: rec[i][0..d) = the
 // point, rec[i][d..rs) = 0 (the signature word, in the last two floats, is
-// filled by the key kernel).
+// filled by the key kernel).  zero64[0, nzero), if given, is cleared first
+// in the same launch as bbox and bad.
 void launch_stage(const InstDesc* inst, uint32_t m, uint32_t nblocks, int d, int64_t npts,
                   float* soa, float* aos, uint32_t* bad, uint32_t* bbox, uint32_t* part,
-                  float* rec, int rs, hipStream_t s);
+                  float* rec, int rs, hipStream_t s, uint64_t* zero64 = nullptr,
+                  uint32_t nzero = 0);
 
 // --- cell keys ------------------------------------------------------------
 // For every batch point and each of its instance's segments in [sa, sb):

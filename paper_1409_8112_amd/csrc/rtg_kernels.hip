@@ -275,12 +275,15 @@ __global__ __launch_bounds__(kBlock) void k_stage_d(const InstDesc* __restrict__
   }
 }
 
-// One block per instance: bbox[q][2j] = min over its blocks, [2j+1] = max.
-// bbox of every instance to the identities of min and max (bits of the
-// order-preserving encoding).
-__global__ void k_bbox_init(uint32_t* __restrict__ bbox, uint32_t count) {
+// Before the stage: bbox of every instance to the identities of min and
+// max (bits of the order-preserving encoding), *bad to 0, and the caller's
+// zero64[0, nzero) to 0 (counters of the pass), in one launch.
+__global__ void k_stage_init(uint32_t* __restrict__ bbox, uint32_t count, uint32_t* bad,
+                             uint64_t* __restrict__ zero64, uint32_t nzero) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < count) bbox[e] = (e & 1u) ? 0u : 0xFFFFFFFFu;
+  if (e < nzero) zero64[e] = 0ull;
+  if (e == 0) *bad = 0u;
 }
 
 // Block (q, y) folds slice y of instance q's per-block boxes into bbox with
@@ -3202,9 +3205,11 @@ void launch_fill_u64(uint64_t* p, uint64_t v, size_t count, hipStream_t s) {
 
 void launch_stage(const InstDesc* inst, uint32_t m, uint32_t nblocks, int d, int64_t npts,
                   float* soa, float* aos, uint32_t* bad, uint32_t* bbox, uint32_t* part,
-                  float* rec, int rs, hipStream_t s) {
+                  float* rec, int rs, hipStream_t s, uint64_t* zero64, uint32_t nzero) {
+  const uint32_t nbox = m * 2u * (uint32_t)d;
+  hipLaunchKernelGGL(k_stage_init, dim3(grid_for(std::max(nbox, nzero))), dim3(kBlock), 0, s,
+                     bbox, nbox, bad, zero64, nzero);
   if (!nblocks) return;
-  hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(64), 0, s, bad, 0u, (size_t)1);
 #define RTG_STAGE(DD)                                                                         \
   hipLaunchKernelGGL(k_stage_d<DD>, dim3(nblocks), dim3(kBlock), 0, s, inst, m, npts, soa, aos, \
                      bad, part, rec)
@@ -3231,9 +3236,6 @@ void launch_stage(const InstDesc* inst, uint32_t m, uint32_t nblocks, int d, int
                          bad, part, rec, rs);
   }
 #undef RTG_STAGE
-  const uint32_t nbox = m * 2u * (uint32_t)d;
-  hipLaunchKernelGGL(k_bbox_init, dim3((nbox + kBlock - 1) / kBlock), dim3(kBlock), 0, s, bbox,
-                     nbox);
   // blocks per instance: about 64 per-block boxes each, at most kBboxBlocks
   uint32_t gy = (uint32_t)std::min<uint64_t>(kBboxBlocks, (nblocks / m + 63) / 64);
   if (gy < 1) gy = 1;
