@@ -146,13 +146,24 @@ def bench_batched(ctx, count: int, reps: int = 3) -> dict:
     batched_once()  # warm-up
     t_default, _ = timed()
     # the autotuner, one dimension at a time (its entries cover the passes of
-    # that dimension), then the batch again with the tuned settings
+    # that dimension), then the batch again with the tuned settings.  Each
+    # dimension is tuned alone while the whole batch runs its dimensions'
+    # passes on several lanes at once, so the tuned entries are kept only if
+    # the whole batch is faster with them (else the entries in use before
+    # are put back and the batch timed again).
+    dims = sorted({w.d for w in wls})
+    before = {d: ctx.get_tuning(d, 1 << 22) for d in dims}
     tuned = []
     t0 = time.perf_counter()
-    for d in sorted({w.d for w in wls}):
+    for d in dims:
         tuned.append(ctx.autotune([q for q, w in zip(queries, wls) if w.d == d], reps=2))
     tune_s = time.perf_counter() - t0
     t_b, pairs = timed()
+    t_tuned, kept = t_b, t_b <= t_default
+    if not kept:
+        for e in tuned:
+            ctx.set_tuning({**before[e["d"]], "d": e["d"], "log2_points": e["log2_points"]})
+        t_b, pairs = timed()
     plan = bench_plan(ctx, queries, reps)
 
     torch.cuda.synchronize()
@@ -172,6 +183,7 @@ def bench_batched(ctx, count: int, reps: int = 3) -> dict:
             "plain_pairs": pairs_plain, "speedup_vs_plain": t_p / t_b,
             "same_pairs_as_plain": pairs == pairs_plain,
             "default_settings_ms": t_default * 1e3, "tuning_s": tune_s, "tuned": tuned,
+            "tuned_ms": t_tuned * 1e3, "tuned_kept": kept,
             "plan": plan}
 
 
