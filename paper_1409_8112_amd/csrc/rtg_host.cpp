@@ -1239,6 +1239,9 @@ int Lane::run_tiny(Job& j, rtg_stats& st) {
   a.R = reinterpret_cast<const double*>(up + o_R);
   a.u = reinterpret_cast<const double*>(up + o_u);
   a.k = j.k;
+  // up to 8 workgroups per grid (each finds the grid's cells, then tests
+  // its slice of the pairs), no more than 256 in all unless k is larger
+  a.parts = (uint32_t)std::max(1, std::min(8, 256 / std::max(1, j.k)));
   a.pairs = pairs;
   a.cap = kTinyPairCap;
   a.count = cnt;

@@ -378,11 +378,11 @@ void launch_cell_pairs(const PairsArgs& a, hipStream_t s);
 
 // --- small instances --------------------------------------------------------
 // One instance of n <= kTinyPoints points (d <= 8, n d <= kTinyFloats,
-// k n <= kTinyCells, k d (d + 1) <= kTinyTransform) in two launches: k
-// workgroups, one per grid, find the cells (32-bit keys, sorted in LDS),
-// test their pairs in FP64 and append the pairs of the first grid that
-// holds both points to pairs; workgroups of 512 rows each build
-// the CSR lists from them.
+// k n <= kTinyCells, k d (d + 1) <= kTinyTransform) in two launches:
+// TinyArgs::parts workgroups per grid each find the grid's cells (32-bit
+// keys, sorted in LDS), test their share of its pairs in FP64 and append
+// the pairs of the first grid that holds both points to pairs; workgroups
+// of 512 rows each build the CSR lists from them.
 constexpr int kTinyPoints = 4096;
 constexpr int kTinyFloats = 12288;    // n d at most (the points are staged in LDS)
 constexpr int kTinyTransform = 2048;  // k d (d + 1) at most (the transforms too)
@@ -399,6 +399,7 @@ struct TinyArgs {
   const double* R;            // [k][d][d]
   const double* u;            // [k][d]
   int k;
+  uint32_t parts;             // workgroups per grid, each testing a slice of its pairs
   uint64_t* pairs;            // [cap]: (min << 32) | max
   uint64_t cap;
   unsigned long long* count;  // [0] pairs, [1] tests, [2] cells, [3] entries written

@@ -2724,12 +2724,13 @@ inline unsigned tiles_for(size_t count) { return (unsigned)((count + kTile - 1) 
 
 // ---------------------------------------------------------------------------
 // Small instances in two launches.  For n <= kTinyPoints (and d <= 8) the
-// whole pipeline fits one workgroup per grid: block t computes every
-// point's cell under grids 0..t (the FP64 formula of k_keys) and packs each
-// cell's fields into 32 bits (field widths from the block's own minimum and
-// maximum), sorts grid t's keys -- cell and point index -- in LDS (counting
-// sort over few cells, else bitonic), tests every pair of each cell in FP64
-// in the definition's order, keeps a pair within r only if no earlier
+// whole pipeline fits a few workgroups per grid: block (t, part) computes
+// every point's cell under grids 0..t (the FP64 formula of k_keys) and
+// packs each cell's fields into 32 bits (field widths from the block's own
+// minimum and maximum), sorts grid t's keys -- cell and point index -- in
+// LDS (counting sort over few cells, else bitonic), tests its slice of the
+// pairs of the cells in FP64 in the definition's order, keeps a pair within
+// r only if no earlier
 // grid's packed cells of the two points are equal, and appends it to one
 // pair list.  A second launch turns the list into the CSR lists.
 // Anything outside these limits -- wider keys, more pairs than the list
@@ -2800,7 +2801,10 @@ __global__ __launch_bounds__(kTinyThreads) void k_tiny_grids(const TinyArgs A) {
   __shared__ int32_t wlo[kTinyWaves][D], whi[kTinyWaves][D];
   __shared__ uint32_t wsum[kTinyWaves];
   __shared__ uint32_t sflag;
-  const int t = blockIdx.x;
+  // k parts workgroups: workgroup (t, part) tests slice part of grid t's
+  // pairs (every part finds the grid's cells itself)
+  const int t = (int)(blockIdx.x / A.parts);
+  const uint32_t part = blockIdx.x % A.parts;
   const int n = A.n;
   const uint32_t lane = lane_id();
   const int w = threadIdx.x >> 6;
@@ -2995,12 +2999,34 @@ __global__ __launch_bounds__(kTinyThreads) void k_tiny_grids(const TinyArgs A) {
   }
   __syncthreads();
 
-  // Each thread tests one contiguous run of the block's T pairs (p, q),
-  // p < q in one cell, in position order: its first p by bisection of pre,
-  // then q steps to the cell's end and p on to the next position with pairs.
-  const uint32_t chunk = (T + kTinyThreads - 1) / kTinyThreads;
-  uint32_t e = threadIdx.x * chunk;
-  const uint32_t e_end = min(T, e + chunk);
+  // The workgroup's slice [s0, s1) of the grid's T pairs (p, q), p < q in
+  // one cell, in position order, in one contiguous run per thread: its
+  // first p by bisection of pre, then q steps to the cell's end and p on to
+  // the next position with pairs.  The order of a cell's points may differ
+  // between the parts (the counting sort's scatter is atomic), so slices
+  // hold whole cells: a nominal bound T * part / parts moves down to the
+  // first pair of the cell that holds it, a value every part finds alike.
+  auto cell_bound = [&](uint32_t part_i) -> uint32_t {
+    const uint32_t s = (uint32_t)((uint64_t)T * part_i / A.parts);
+    if (s >= T) return T;
+    int lo = 0, hi = n - 1;  // the position whose pairs hold index s
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pre[mid] <= s) lo = mid; else hi = mid - 1;
+    }
+    const uint32_t c = skey[lo] >> idx_bits;
+    int a0 = 0, a1 = lo;  // the first position of that cell
+    while (a0 < a1) {
+      const int mid = (a0 + a1) >> 1;
+      if ((skey[mid] >> idx_bits) < c) a0 = mid + 1; else a1 = mid;
+    }
+    return pre[a0];
+  };
+  const uint32_t s0 = cell_bound(part);
+  const uint32_t s1 = cell_bound(part + 1);
+  const uint32_t chunk = (s1 - s0 + kTinyThreads - 1) / kTinyThreads;
+  uint32_t e = s0 + threadIdx.x * chunk;
+  const uint32_t e_end = min(s1, e + chunk);
   int p = 0, q = 0;
   uint32_t pend = 0;  // pre of the position after p
   uint32_t a = 0;
@@ -3051,11 +3077,13 @@ __global__ __launch_bounds__(kTinyThreads) void k_tiny_grids(const TinyArgs A) {
     tiny_append(A, O, lane, keep, val);
   }
   tiny_flush(A, O, lane);
-  // the block's cells (tests: T)
+  // the grid's cells and tests (T), counted by its first part
+  if (part == 0) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) cells += __shfl_xor(cells, o, 64);
-  if (lane == 0 && cells) atomicAdd(A.count + 2, (unsigned long long)cells);
-  if (threadIdx.x == 0 && T) atomicAdd(A.count + 1, (unsigned long long)T);
+    for (int o = 32; o > 0; o >>= 1) cells += __shfl_xor(cells, o, 64);
+    if (lane == 0 && cells) atomicAdd(A.count + 2, (unsigned long long)cells);
+    if (threadIdx.x == 0 && T) atomicAdd(A.count + 1, (unsigned long long)T);
+  }
 }
 
 // The pair list to CSR lists, the rows split over the workgroups
@@ -3605,7 +3633,7 @@ static void pairs_dispatch(const PairsArgs& a, hipStream_t s) {
 
 void launch_tiny(const TinyArgs& a, int d, int k, hipStream_t s) {
 #define RTG_TINY(DD) \
-  hipLaunchKernelGGL(k_tiny_grids<DD>, dim3(k), dim3(kTinyThreads), 0, s, a)
+  hipLaunchKernelGGL(k_tiny_grids<DD>, dim3(k * a.parts), dim3(kTinyThreads), 0, s, a)
   switch (d) {
     case 1: RTG_TINY(1); break;
     case 2: RTG_TINY(2); break;
