@@ -992,14 +992,15 @@ int csr_by_buckets(Lane& c, Scratch& S, const Tuning& T, const PairSource& pairs
   if ((rc = alloc_result(c, n, E, res, row_ptr, col))) return rc;
   if (tm) tm->on_begin(RTG_K_CSR);
   const int pt = (int)T.part_threads;
-  launch_bucket_hist(pairs, count, pb, rb, both ? 1 : 0, nbuckets, chunk, nblocks, pt, part, s);
+  // the histogram launch also clears the oversized count; the CSR launch
+  // also writes row_ptr[n]
+  launch_bucket_hist(pairs, count, pb, rb, both ? 1 : 0, nbuckets, chunk, nblocks, pt, part, over,
+                     s);
   scan_exclusive_u32(part, part, np, part + np, pscr, s);
   launch_bucket_scatter(pairs, count, pb, rb, both ? 1 : 0, nbuckets, chunk, nblocks, pt, part,
                         entries, s);
-  launch_fill_u32(over, 0u, 1, s);
   launch_bucket_csr(entries, part, nbuckets, nblocks, part + np, over + 1, over, c.ctx->bucket_cap, pb,
-                    rb, n, *row_ptr, *col, s);
-  launch_fill_u64(reinterpret_cast<uint64_t*>(*row_ptr + n), (uint64_t)E, 1, s);
+                    rb, n, (int64_t)E, *row_ptr, *col, s);
   // read the pairs twice, write and read the entries, write col and row_ptr
   if (tm) tm->on_end(RTG_K_CSR, 16.0 * (double)count + 8.0 * (double)E + 4.0 * (double)E +
                                     8.0 * (double)(n + 1));

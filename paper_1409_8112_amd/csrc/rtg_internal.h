@@ -456,21 +456,22 @@ struct PairSource {
   uint64_t seg_cap = 0;
   uint32_t nseg = 0;
 };
+// Also clears *zero_word (when given): the oversized count of the CSR step.
 void launch_bucket_hist(const PairSource& src, size_t count, int pb, int rb, int both,
                         uint32_t nbuckets, uint32_t chunk, uint32_t nblocks, int threads,
-                        uint32_t* part, hipStream_t s);
+                        uint32_t* part, uint32_t* zero_word, hipStream_t s);
 void launch_bucket_scatter(const PairSource& src, size_t count, int pb, int rb, int both,
                            uint32_t nbuckets, uint32_t chunk, uint32_t nblocks, int threads,
                            const uint32_t* offs, uint32_t* entries, hipStream_t s);
-// Writes col and row_ptr (all but row_ptr[n]) for every bucket of at most
+// Writes col and row_ptr (row_ptr[n] = nnz) for every bucket of at most
 // cap (<= kBucketMaxEntries) entries: entries of unique pairs, so a bucket's
 // start in the entry array is its start in col.  Larger buckets, and
 // buckets with a row of more than 1024 entries, are listed in oversized[]
-// (count in *n_oversized) for the caller.
+// (count in *n_oversized, cleared beforehand) for the caller.
 void launch_bucket_csr(const uint32_t* entries, const uint32_t* offs, uint32_t nbuckets,
                        uint32_t nblocks, const uint32_t* total, uint32_t* oversized,
                        uint32_t* n_oversized, uint32_t cap, int pb, int rb, int64_t n,
-                       int64_t* row_ptr, int32_t* col, hipStream_t s);
+                       int64_t nnz, int64_t* row_ptr, int32_t* col, hipStream_t s);
 // Every oversized bucket at once: ids[q] (q < nover) are their bucket ids.
 // launch_over_extent gives each one's first entry and entry count (part is
 // the scanned partition table, part[np] its total); with off the exclusive

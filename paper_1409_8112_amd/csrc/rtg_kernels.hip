@@ -2291,8 +2291,10 @@ __global__ __launch_bounds__(TH) void k_bucket_hist(const uint64_t* __restrict__
                                                     uint32_t nblocks,
                                                     const unsigned long long* __restrict__ seg_cnt,
                                                     uint64_t seg_cap, uint32_t nseg,
-                                                    uint32_t* __restrict__ part) {
+                                                    uint32_t* __restrict__ part,
+                                                    uint32_t* __restrict__ zero_word) {
   extern __shared__ uint32_t h[];
+  if (zero_word && blockIdx.x == 0 && threadIdx.x == 0) *zero_word = 0u;
   for (uint32_t b = threadIdx.x; b < nbuckets; b += TH) h[b] = 0u;
   __syncthreads();
   const PairRange pr = pair_range(pairs, count, chunk, nblocks, seg_cnt, seg_cap, nseg);
@@ -2438,7 +2440,7 @@ __device__ __forceinline__ uint32_t csr_block_exclusive_scan(uint32_t v, uint32_
 __global__ __launch_bounds__(kCsrThreads) void k_bucket_csr(
     const uint32_t* __restrict__ entries, const uint32_t* __restrict__ offs, uint32_t nbuckets,
     uint32_t nblocks, const uint32_t* __restrict__ total_p, uint32_t* __restrict__ oversized,
-    uint32_t* __restrict__ n_oversized, uint32_t cap, int pb, int rb, int64_t n,
+    uint32_t* __restrict__ n_oversized, uint32_t cap, int pb, int rb, int64_t n, int64_t nnz,
     int64_t* __restrict__ row_ptr, int32_t* __restrict__ col) {
   __shared__ uint32_t s[kBucketMaxEntries];
   __shared__ uint32_t rstart[kBucketMaxRows], rcur[kBucketMaxRows];
@@ -2446,6 +2448,7 @@ __global__ __launch_bounds__(kCsrThreads) void k_bucket_csr(
   __shared__ uint32_t s_long, s_nlong;
   __shared__ uint32_t s_longrows[kMaxLongRows];
   const uint32_t b = blockIdx.x;
+  if (b == 0 && threadIdx.x == 0) row_ptr[n] = nnz;
   uint32_t start, cnt;
   bucket_range(offs, b, nbuckets, nblocks, *total_p, start, cnt);
   if (cnt > cap) {
@@ -3735,17 +3738,20 @@ void launch_csr_fill_lower(const uint64_t* lo, size_t count, int pair_bits, cons
 
 void launch_bucket_hist(const PairSource& src, size_t count, int pb, int rb, int both,
                         uint32_t nbuckets, uint32_t chunk, uint32_t nblocks, int threads,
-                        uint32_t* part, hipStream_t s) {
-  if (!nblocks) return;
+                        uint32_t* part, uint32_t* zero_word, hipStream_t s) {
+  if (!nblocks) {
+    if (zero_word) launch_fill_u32(zero_word, 0u, 1, s);
+    return;
+  }
   const size_t lds = nbuckets * sizeof(uint32_t);
   if (threads >= 1024)
     hipLaunchKernelGGL(k_bucket_hist<1024>, dim3(nblocks), dim3(1024), lds, s, src.pairs, count,
                        pb, rb, both, nbuckets, chunk, nblocks, src.seg_cnt, src.seg_cap,
-                       src.nseg, part);
+                       src.nseg, part, zero_word);
   else
     hipLaunchKernelGGL(k_bucket_hist<kBlock>, dim3(nblocks), dim3(kBlock), lds, s, src.pairs,
                        count, pb, rb, both, nbuckets, chunk, nblocks, src.seg_cnt, src.seg_cap,
-                       src.nseg, part);
+                       src.nseg, part, zero_word);
 }
 
 void launch_bucket_scatter(const PairSource& src, size_t count, int pb, int rb, int both,
@@ -3766,11 +3772,15 @@ void launch_bucket_scatter(const PairSource& src, size_t count, int pb, int rb, 
 void launch_bucket_csr(const uint32_t* entries, const uint32_t* offs, uint32_t nbuckets,
                        uint32_t nblocks, const uint32_t* total, uint32_t* oversized,
                        uint32_t* n_oversized, uint32_t cap, int pb, int rb, int64_t n,
-                       int64_t* row_ptr, int32_t* col, hipStream_t s) {
-  if (!nbuckets) return;
+                       int64_t nnz, int64_t* row_ptr, int32_t* col, hipStream_t s) {
+  if (!nbuckets) {
+    launch_fill_u64(reinterpret_cast<uint64_t*>(row_ptr + n), (uint64_t)nnz, 1, s);
+    return;
+  }
   if (cap > (uint32_t)kBucketMaxEntries) cap = kBucketMaxEntries;
   hipLaunchKernelGGL(k_bucket_csr, dim3(nbuckets), dim3(kCsrThreads), 0, s, entries, offs,
-                     nbuckets, nblocks, total, oversized, n_oversized, cap, pb, rb, n, row_ptr, col);
+                     nbuckets, nblocks, total, oversized, n_oversized, cap, pb, rb, n, nnz, row_ptr,
+                     col);
 }
 
 void launch_over_extent(const uint32_t* ids, uint32_t nover, const uint32_t* part,
