@@ -1,8 +1,9 @@
 """The two-launch path for small instances (n <= 4096, n d <= 12288,
 k n <= 12288, d <= 8, Euclidean): its lists equal the oracle's bit for bit
 across dimensions, sizes, flags, both in-LDS sorts (counting over few
-cells, bitonic over many), coincident points and pairs at r exactly and one
-ulp either side; it is the path that ran (no key kernel); and whatever it
+cells, bitonic over many), one to eight workgroups per grid (slices cut at
+cell boundaries, with cells larger than a slice), coincident points and
+pairs at r exactly and one ulp either side; it is the path that ran (no key kernel); and whatever it
 cannot take -- keys wider than 31 bits, more pairs than its list holds
 (131072), rows longer than 128 -- falls back to the general pipeline with
 the same result, while bad points and out-of-range cells give the general
@@ -67,6 +68,31 @@ def test_many_cells_bitonic_sort(ctx):
     p = workloads.uniform_points(2000, 3, seed=21)
     small, st = _run(ctx, p, 0.02, 4, 1.5, 5)
     assert small and st["cells"] > 0
+
+
+def test_pairs_split_at_cell_boundaries(ctx):
+    # With few grids each grid's pair tests are split over several
+    # workgroups at cell boundaries.  One cell holding every point (all
+    # slices but the last are empty), clusters larger than a slice, cells of
+    # every size in between, and enough grids that each has one workgroup.
+    rng = np.random.default_rng(44)
+    one = (0.5 + rng.random((120, 3)) * 1e-4).astype(np.float32)
+    small, st = _run(ctx, one, 0.01, 2, 2.0, 3)
+    assert small and st["unique_pairs"] == 120 * 119 // 2
+    centres = rng.random((10, 3))
+    clusters = np.concatenate([c + rng.normal(size=(100, 3)) * 4e-3 for c in centres])
+    small, _ = _run(ctx, clusters.astype(np.float32), 0.05, 4, 2.0, 8)
+    assert small
+    # k n <= 12288: fewer points as k grows (k > 32: fewer parts per grid;
+    # k = 200: one workgroup per grid)
+    for n, ks in ((1200, (1, 3, 8)), (180, (40, 64)), (90, (128,))):
+        mixed = np.concatenate([workloads.uniform_points(n, 2, seed=45),
+                                (0.3 + rng.random((n // 20, 2)) * 2e-3)]).astype(np.float32)
+        for k in ks:
+            small, _ = _run(ctx, mixed, 0.02 * (1200 / n) ** 0.5, k, 2.5, k)
+            assert small
+    small, _ = _run(ctx, workloads.uniform_points(50, 1, seed=46), 0.03, 200, 2.0, 5)
+    assert small
 
 
 def test_rows_under_the_limit(ctx):
