@@ -511,12 +511,15 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const T* in, T* out, size
 // radix sort: tiles of 4096 elements; element e of a tile is held by wave
 // e / 1024, round (e % 1024) / 64, lane e % 64, so every load is one
 // contiguous 64-element run.  Two drivers share the tile code:
-//   onesweep (default): one histogram read for all digit passes, then per
-//     pass one kernel in which each tile takes the next tile id, publishes
-//     its digit counts and looks back over earlier tiles' published counts
-//     (decoupled look-back) to find where its digits start;
-//   reduce-then-scan: per pass, tile histograms, a device-wide scan, then
-//     the scatter (one more read of the keys per pass).
+//   reduce-then-scan (the default): per pass, tile histograms, a
+//     device-wide scan, then the scatter (one more read of the keys per
+//     pass); it can sort within segments, leaving their bits out of the
+//     passes;
+//   onesweep: one histogram read for all digit passes, then per pass one
+//     kernel in which each tile takes the next tile id, publishes its digit
+//     counts and looks back over earlier tiles' published counts (decoupled
+//     look-back) to find where its digits start; its look-back reads cross
+//     the XCDs' L2s, and it measured slower.
 
 // LDS of one tile: staged keys/values and the per-wave digit counters.
 // (Values are staged in key[] too, after the keys have gone out: the tile
