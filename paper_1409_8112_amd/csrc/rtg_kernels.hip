@@ -1499,6 +1499,24 @@ __device__ __forceinline__ GramBand gram_band(float S, float r2f, float gain) {
   return b;
 }
 
+// The matrix cores' operands of a tile from its rows, one row per lane:
+// block X (rows 32 X .. 32 X + 31) takes, in lane l, element 2 q + (l >> 5)
+// of row 32 X + (l & 31).  Lanes 0-31 of block 0 keep their own even
+// elements and lanes 32-63 need the odd elements of lanes 0-31; block 1
+// the reverse.  Swapping the upper half of row[2 q] with the lower half of
+// row[2 q + 1] across the wave (v_permlane32_swap) leaves block 0's
+// operand in the first and block 1's in the second: no trip through LDS.
+template <int KS>
+__device__ __forceinline__ void gram_operands(const float* row, float (&op)[2][KS]) {
+#pragma unroll
+  for (int q = 0; q < KS; ++q) {
+    const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(row[2 * q]),
+                                                     __float_as_uint(row[2 * q + 1]), false, false);
+    op[0][q] = __uint_as_float(sw[0]);
+    op[1][q] = __uint_as_float(sw[1]);
+  }
+}
+
 // Four waves per SIMD up to D = 9 (at most 128 registers: a few spills at
 // D = 9 cost less than the lost wave); three above, where the registers the
 // wider rows need would spill more.
@@ -1508,12 +1526,9 @@ k_cell_pairs_gram(
     const PairsArgs P) {
   constexpr int KA = (D + 3) & ~1;  // augmented row length, even
   constexpr int KS = KA / 2;        // MFMA steps per block
-  constexpr int KP = KA + 1;        // LDS row stride, odd: conflict-free column reads
   constexpr float kGain = 1.5f * (float)(2 * KA + D + 8) * 0x1p-24f;
-  // A tile rows, then (once they are in registers) the A signature words;
-  // the same for B.
-  constexpr int kRegion = (kPairTile * KP > 2 * kSigWords * kPairTile) ? kPairTile * KP
-                                                                       : 2 * kSigWords * kPairTile;
+  // the A and B tiles' signature words
+  constexpr int kRegion = 2 * kSigWords * kPairTile;
   __shared__ __attribute__((aligned(16))) float sAreg[kWaves][kRegion];
   __shared__ __attribute__((aligned(16))) float sBreg[kWaves][kRegion];
   __shared__ uint32_t sAi[kWaves][kPairTile];
@@ -1524,8 +1539,6 @@ k_cell_pairs_gram(
   const uint32_t lane = lane_id();
   const uint32_t l32 = lane & 31u, h = lane >> 5;
   const int w = threadIdx.x >> 6;
-  float (*sA)[KP] = reinterpret_cast<float (*)[KP]>(sAreg[w]);
-  float (*sB)[KP] = reinterpret_cast<float (*)[KP]>(sBreg[w]);
   uint64_t (*sAw)[kPairTile] = reinterpret_cast<uint64_t (*)[kPairTile]>(sAreg[w]);
   uint64_t (*sBw)[kPairTile] = reinterpret_cast<uint64_t (*)[kPairTile]>(sBreg[w]);
   unsigned long long nre = 0;
@@ -1568,6 +1581,7 @@ k_cell_pairs_gram(
     // tile a: centred rows, norms; invalid rows get a huge norm (rejected)
     wave_lds_sync();
     float na = 0.0f;
+    float areg[2][KS];
     {
       float row[KA];
       if (lane < nA) {
@@ -1589,22 +1603,14 @@ k_cell_pairs_gram(
 #pragma unroll
       for (int l = D + 2; l < KA; ++l) row[l] = 0.0f;
       sAi[w][lane] = cur.idx;
-#pragma unroll
-      for (int l = 0; l < KA; ++l) sA[lane][l] = row[l];
+      gram_operands<KS>(row, areg);
     }
     const float amax = unit_band ? 0.0f : wave_max_f(na);
-    wave_lds_sync();
-    float areg[2][KS];
-#pragma unroll
-    for (int R = 0; R < 2; ++R)
-#pragma unroll
-      for (int q = 0; q < KS; ++q) areg[R][q] = sA[32 * R + l32][2 * q + h];
     if (V.nw) {
-      // the A rows are in registers: their space takes the A signature words
-      wave_lds_sync();
 #pragma unroll
       for (int q = 0; q < kSigWords; ++q) sAw[q][lane] = cur.sw[q];
     }
+    wave_lds_sync();  // the A indices and words, before lanes read each other's
 
     for (uint32_t s = 0; s < V.nt - ta; ++s) {
       const uint32_t tb = row_step_tile(V, ta, s);
@@ -1640,16 +1646,10 @@ k_cell_pairs_gram(
       const uint32_t Wu = bd.Wu;
       row[D + 1] = lane < nB ? nb - lo : 1e30f;
       sBi[w][lane] = cur.idx;
-#pragma unroll
-      for (int l = 0; l < KA; ++l) sB[lane][l] = row[l];
-      wave_lds_sync();
-      load_next<D>(P, V, Vn, ta, tb, lane, cur, nxt);
-
       float breg[2][KS];
-#pragma unroll
-      for (int C = 0; C < 2; ++C)
-#pragma unroll
-        for (int q = 0; q < KS; ++q) breg[C][q] = sB[32 * C + l32][2 * q + h];
+      gram_operands<KS>(row, breg);
+      wave_lds_sync();  // the B indices, before lanes read each other's
+      load_next<D>(P, V, Vn, ta, tb, lane, cur, nxt);
 
       const bool diag = (ta == tb);
       uint64_t acc = 0ull, band = 0ull;
