@@ -1218,20 +1218,23 @@ int Lane::run_tiny(Job& j, rtg_stats& st) {
   } detach{*this};
   Scratch S(*this);
   mark(0);
+  // the transforms and the zeroed counters ([0..3] counts, [4] error
+  // bits) go up in one copy: no separate launch clears the counters
+  static const unsigned long long kZeroCounts[8] = {};
   Uploads U(*this);
   const size_t o_R = U.add(j.R, sizeof(double) * (size_t)j.k * d * d);
   const size_t o_u = U.add(j.u, sizeof(double) * (size_t)j.k * d);
+  const size_t o_cnt = U.add(kZeroCounts, sizeof(kZeroCounts));
   char* up = S.get<char>(U.total());
   uint64_t* pairs = S.get<uint64_t>(kTinyPairCap);
   int32_t* stage = S.get<int32_t>(2 * kTinyPairCap);
-  unsigned long long* cnt = S.get<unsigned long long>(8);  // [0..3] counts, [4] error bits
-  if (!up || !pairs || !stage || !cnt) return RTG_ENOMEM;
+  if (!up || !pairs || !stage) return RTG_ENOMEM;
+  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(up + o_cnt);
   if ((rc = U.send(up))) return rc;
   void* res = nullptr;
   int64_t* row_ptr = nullptr;
   int32_t* col = nullptr;
   if ((rc = alloc_result(*this, j.n, 2 * kTinyPairCap, &res, &row_ptr, &col))) return rc;
-  launch_fill_u64(reinterpret_cast<uint64_t*>(cnt), 0ull, 8, stream);
   TinyArgs a{};
   a.pts = j.pts;
   a.n = (int)j.n;
