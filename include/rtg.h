@@ -188,10 +188,11 @@ int rtg_destroy(rtg_ctx *ctx);
  *   RTG_ROBOTS(b).
  * n <= 1 gives an empty list.  Small Euclidean instances (n <= 4096,
  * d <= 8, n d <= 12288, k n <= 12288, k d (d + 1) <= 2048) run in two
- * launches -- one workgroup per grid finds its cells, tests their pairs and
- * keeps the first grid's, then the lists are built -- and take the general
- * pipeline when their keys, pairs (131072) or rows (128) exceed what those
- * launches hold; the lists are the same either way, and the stats count
+ * launches -- up to eight workgroups per grid find its cells, test their
+ * share of its pairs and keep the first grid's, then the lists are built --
+ * and take the general pipeline when their keys, pairs (131072) or rows
+ * (128) exceed what those launches hold; the lists are the same either
+ * way, and the stats count
  * both launches under RTG_K_PAIRS with candidates = unique_pairs.  The
  * environment setting RTG_SMALL=0 turns the small path off.  Errors:
  * RTG_EINVAL (also for NaN/Inf coordinates), RTG_ERANGE, RTG_ENOMEM,
