@@ -828,13 +828,20 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(
 // ---------------------------------------------------------------------------
 // runs of equal keys (cells with >= 2 points), unique keys.
 
+// Whether element e begins or ends a run of at least two equal keys.  The
+// wave's lanes hold 64 consecutive elements (e = 64-aligned base + lane):
+// each loads its own key, takes its neighbours' from the adjacent lanes, and
+// only the first and last lanes load the keys beyond the wave's ends.
 __device__ __forceinline__ void run_flags(const uint64_t* __restrict__ keys, size_t count, size_t e,
-                                          int shift, bool& head, bool& tail) {
-  head = tail = false;
-  if (e >= count) return;
-  const uint64_t k = keys[e] >> shift;
-  const bool prev_same = e > 0 && (keys[e - 1] >> shift) == k;
-  const bool next_same = e + 1 < count && (keys[e + 1] >> shift) == k;
+                                          uint32_t lane, int shift, bool& head, bool& tail) {
+  const bool in = e < count;
+  const uint64_t k = in ? keys[e] >> shift : 0ull;
+  uint64_t kp = __shfl_up(k, 1, 64);
+  uint64_t kn = __shfl_down(k, 1, 64);
+  if (lane == 0 && in && e > 0) kp = keys[e - 1] >> shift;
+  if (lane == 63 && e + 1 < count) kn = keys[e + 1] >> shift;
+  const bool prev_same = in && e > 0 && kp == k;
+  const bool next_same = in && e + 1 < count && kn == k;
   head = !prev_same && next_same;
   tail = prev_same && !next_same;
 }
@@ -851,7 +858,7 @@ __global__ __launch_bounds__(kBlock) void k_run_count(const uint64_t* __restrict
   uint32_t hc = 0, tc = 0;
   for (int q = 0; q < kKeysPerThread; ++q) {
     bool h, t;
-    run_flags(keys, count, wave_base + (size_t)q * 64 + lane, shift, h, t);
+    run_flags(keys, count, wave_base + (size_t)q * 64 + lane, lane, shift, h, t);
     const uint64_t hb = ballot(h), tb = ballot(t);
     hc += (uint32_t)__popcll(hb);
     tc += (uint32_t)__popcll(tb);
