@@ -1728,10 +1728,14 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st, PassPlan* pp) {
       // max_cells), so one read-back after them serves the whole cell stage.
       kbegin(RTG_K_CELLS);
       if (!counts_direct) launch_fill_u64(reinterpret_cast<uint64_t*>(counters) + 3, 0ull, 1, stream);
-      launch_cell_work(cstart, cend, cell_bound, tot, T.unit_tiles, units, tests_c, counters + 3,
-                       stream);
-      scan_exclusive_u32(units, units, cell_bound, scan32 + s64, scan32, stream, tot);
-      scan_exclusive_u64(tests_c, tests_c, cell_bound, scan64 + s64, scan64, stream, tot);
+      if (!launch_cell_work_scanned(cstart, cend, cell_bound, tot, T.unit_tiles, units, tests_c,
+                                    counters + 3, scan32, scan32 + s64, scan64, scan64 + s64,
+                                    stream)) {
+        launch_cell_work(cstart, cend, cell_bound, tot, T.unit_tiles, units, tests_c, counters + 3,
+                         stream);
+        scan_exclusive_u32(units, units, cell_bound, scan32 + s64, scan32, stream, tot);
+        scan_exclusive_u64(tests_c, tests_c, cell_bound, scan64 + s64, scan64, stream, tot);
+      }
       launch_unit_fill(cstart, cend, units, cell_bound, tot, T.unit_tiles, skeys,
                        seg_bits > 0 ? idx_bits + P.layout.cell_bits : 64, sa, segs_d, udesc, uwork,
                        stream);

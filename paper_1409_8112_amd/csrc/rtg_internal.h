@@ -205,6 +205,14 @@ void launch_run_write(const uint64_t* masks, size_t count, const uint32_t* head_
 void launch_cell_work(const uint32_t* start, const uint32_t* end, uint32_t ncells,
                       const uint32_t* dcells, uint32_t cell_unit_tiles, uint32_t* units,
                       uint64_t* tests, unsigned long long* members, hipStream_t s);
+// launch_cell_work followed by the in-place exclusive scans of units and
+// tests (totals to *utotal, *ttotal; usums / tsums hold one sum per 2048
+// cells), in three launches, when ncells needs at most 2048 such sums;
+// returns false, having launched nothing, otherwise.
+bool launch_cell_work_scanned(const uint32_t* start, const uint32_t* end, uint32_t ncells,
+                              const uint32_t* dcells, uint32_t cell_unit_tiles, uint32_t* units,
+                              uint64_t* tests, unsigned long long* members, uint32_t* usums,
+                              uint32_t* utotal, uint64_t* tsums, uint64_t* ttotal, hipStream_t s);
 // A work unit of the pair kernels: the 64-point tiles ta in [ta_begin,
 // ta_end) of a cell, each tested against the cell's tiles tb >= ta.  A cell
 // of at most cell_unit_tiles tiles is one unit; a larger cell has one unit

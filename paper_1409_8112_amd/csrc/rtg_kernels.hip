@@ -991,6 +991,64 @@ __global__ __launch_bounds__(kBlock) void k_cell_work(const uint32_t* __restrict
   }
 }
 
+// k_cell_work by scan tiles: block b takes cells [b kScanTile, (b + 1)
+// kScanTile), kScanItems consecutive cells per thread as the scan kernels
+// hold them, and also writes the tile's sums of units and tests, so that
+// the two scans need only their apply launches (each block adds up the
+// sums before its own tile).
+__global__ __launch_bounds__(kBlock) void k_cell_work_tiles(
+    const uint32_t* __restrict__ start, const uint32_t* __restrict__ end, uint32_t ncells,
+    const uint32_t* __restrict__ dcells, uint32_t cell_unit_tiles, uint32_t* __restrict__ units,
+    uint64_t* __restrict__ tests, unsigned long long* members, uint32_t* __restrict__ usums,
+    uint64_t* __restrict__ tsums) {
+  if (dcells) ncells = min(ncells, *dcells);
+  const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
+  uint64_t L = 0, tt = 0;
+  uint32_t uu = 0;
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) {
+    const size_t c = base + q;
+    if (c < ncells) {
+      const uint64_t Lc = end[c] - start[c];
+      const uint32_t nt = (uint32_t)((Lc + kPairTile - 1) / kPairTile);
+      const uint32_t u = nt <= cell_unit_tiles ? 1u : nt;
+      const uint64_t t = Lc * (Lc - 1) / 2;
+      units[c] = u;
+      tests[c] = t;
+      uu += u;
+      tt += t;
+      L += Lc;
+    }
+  }
+  __shared__ unsigned long long wl[kWaves], wt[kWaves];
+  __shared__ uint32_t wu[kWaves];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    L += __shfl_xor(L, o, 64);
+    tt += __shfl_xor(tt, o, 64);
+    uu += __shfl_xor(uu, o, 64);
+  }
+  if (lane_id() == 0) {
+    wl[threadIdx.x >> 6] = L;
+    wt[threadIdx.x >> 6] = tt;
+    wu[threadIdx.x >> 6] = uu;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long all = 0, tall = 0;
+    uint32_t uall = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) {
+      all += wl[q];
+      tall += wt[q];
+      uall += wu[q];
+    }
+    usums[blockIdx.x] = uall;
+    tsums[blockIdx.x] = tall;
+    if (all) atomicAdd(members, all);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_unique_count(const uint64_t* __restrict__ keys,
                                                          size_t count, uint32_t* tile_cnt) {
   __shared__ uint32_t sh[kWaves];
@@ -3505,6 +3563,21 @@ void launch_cell_work(const uint32_t* start, const uint32_t* end, uint32_t ncell
   if (!ncells) return;
   hipLaunchKernelGGL(k_cell_work, dim3(cell_grid(ncells)), dim3(kBlock), 0, s, start, end, ncells,
                      dcells, cell_unit_tiles, units, tests, members);
+}
+
+bool launch_cell_work_scanned(const uint32_t* start, const uint32_t* end, uint32_t ncells,
+                              const uint32_t* dcells, uint32_t cell_unit_tiles, uint32_t* units,
+                              uint64_t* tests, unsigned long long* members, uint32_t* usums,
+                              uint32_t* utotal, uint64_t* tsums, uint64_t* ttotal, hipStream_t s) {
+  const size_t nb = ((size_t)ncells + kScanTile - 1) / kScanTile;
+  if (!ncells || nb > (size_t)kFusedScanSums) return false;
+  hipLaunchKernelGGL(k_cell_work_tiles, dim3((unsigned)nb), dim3(kBlock), 0, s, start, end, ncells,
+                     dcells, cell_unit_tiles, units, tests, members, usums, tsums);
+  hipLaunchKernelGGL((k_scan_apply<uint32_t, true>), dim3((unsigned)nb), dim3(kBlock), 0, s, units,
+                     units, (size_t)ncells, (const uint32_t*)usums, utotal, dcells);
+  hipLaunchKernelGGL((k_scan_apply<uint64_t, true>), dim3((unsigned)nb), dim3(kBlock), 0, s, tests,
+                     tests, (size_t)ncells, (const uint64_t*)tsums, ttotal, dcells);
+  return true;
 }
 
 void launch_unit_fill(const uint32_t* start, const uint32_t* end, const uint32_t* unit_off,
