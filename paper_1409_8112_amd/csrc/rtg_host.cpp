@@ -1442,6 +1442,20 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st, PassPlan* pp) {
   const size_t o_tests = U1.add(tests.data(), sizeof(PairTest) * m);
   const size_t o_R = U1.add(Rh.data(), sizeof(double) * Rh.size());
   const size_t o_u = U1.add(uh.data(), sizeof(double) * uh.size());
+  // A few boxes: their identities, *bad and the pass's counters go up with
+  // the descriptors (cleared by the copy, not by a launch).
+  const size_t nbox = (size_t)m * 2 * d;
+  const bool box_up = nbox <= 1024;
+  std::vector<uint32_t> box_init;
+  static const unsigned long long kZeroCounters[kCounterWords] = {};
+  size_t o_box = 0, o_cnt = 0;
+  if (box_up) {
+    box_init.resize(nbox + 1);
+    for (size_t e = 0; e < nbox; ++e) box_init[e] = (e & 1) ? 0u : 0xFFFFFFFFu;
+    box_init[nbox] = 0u;  // bad
+    o_box = U1.add(box_init.data(), sizeof(uint32_t) * box_init.size());
+    o_cnt = U1.add(kZeroCounters, sizeof(kZeroCounters));
+  }
   char* up1 = S.get<char>(U1.total());
   if (!up1) return RTG_ENOMEM;
   InstDesc* inst_d = reinterpret_cast<InstDesc*>(up1 + o_inst);
@@ -1451,10 +1465,13 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st, PassPlan* pp) {
   float* soa = S.get<float>((size_t)npts * d);
   float* aos = m > 1 ? S.get<float>((size_t)npts * d) : nullptr;
   uint32_t* part = S.get<uint32_t>((size_t)nblk * 2 * d);
-  uint32_t* bbox = S.get<uint32_t>((size_t)m * 2 * d + 1);  // + [bad]
+  uint32_t* bbox = box_up ? reinterpret_cast<uint32_t*>(up1 + o_box)
+                         : S.get<uint32_t>((size_t)m * 2 * d + 1);  // + [bad]
   // -, rechecks, filter count, members, the pair-output segments' counts,
   // then err (read back with them after each pass's pair kernel)
-  unsigned long long* counters = S.get<unsigned long long>(kCounterWords);
+  unsigned long long* counters =
+      box_up ? reinterpret_cast<unsigned long long*>(up1 + o_cnt)
+             : S.get<unsigned long long>(kCounterWords);
   if (!soa || (m > 1 && !aos) || !part || !bbox || !counters) return RTG_ENOMEM;
   uint32_t* bad = bbox + (size_t)m * 2 * d;
   uint32_t* err = reinterpret_cast<uint32_t*>(counters + kErrWord);
@@ -1506,9 +1523,9 @@ int Lane::run_batch(std::vector<Job*>& jobs, rtg_stats& st, PassPlan* pp) {
   }
   // --- stage: SoA copy (+ concatenated rows), finiteness, bounding boxes -------
   kbegin(RTG_K_STAGE);
-  // (its first launch also clears the pass's counters)
+  // (its first launch also clears the boxes and the pass's counters, unless the upload did)
   launch_stage(inst_d, m, nblk, d, npts, soa, aos, bad, bbox, part, rec, rs, stream,
-               reinterpret_cast<uint64_t*>(counters), kCounterWords);
+               reinterpret_cast<uint64_t*>(counters), kCounterWords, box_up);
   kend(RTG_K_STAGE, (aos ? 12.0 : 8.0) * (double)npts * d + (rec ? 4.0 * rs * (double)npts : 0.0));
   mark(1);
   std::vector<uint32_t> hb((size_t)m * 2 * d + 1);

@@ -105,7 +105,7 @@ struct SegDesc {
 void launch_stage(const InstDesc* inst, uint32_t m, uint32_t nblocks, int d, int64_t npts,
                   float* soa, float* aos, uint32_t* bad, uint32_t* bbox, uint32_t* part,
                   float* rec, int rs, hipStream_t s, uint64_t* zero64 = nullptr,
-                  uint32_t nzero = 0);
+                  uint32_t nzero = 0, bool cleared = false);
 
 // --- cell keys ------------------------------------------------------------
 // For every batch point and each of its instance's segments in [sa, sb):

@@ -3304,10 +3304,12 @@ void launch_fill_u64(uint64_t* p, uint64_t v, size_t count, hipStream_t s) {
 
 void launch_stage(const InstDesc* inst, uint32_t m, uint32_t nblocks, int d, int64_t npts,
                   float* soa, float* aos, uint32_t* bad, uint32_t* bbox, uint32_t* part,
-                  float* rec, int rs, hipStream_t s, uint64_t* zero64, uint32_t nzero) {
+                  float* rec, int rs, hipStream_t s, uint64_t* zero64, uint32_t nzero,
+                  bool cleared) {
   const uint32_t nbox = m * 2u * (uint32_t)d;
-  hipLaunchKernelGGL(k_stage_init, dim3(grid_for(std::max(nbox, nzero))), dim3(kBlock), 0, s,
-                     bbox, nbox, bad, zero64, nzero);
+  if (!cleared)
+    hipLaunchKernelGGL(k_stage_init, dim3(grid_for(std::max(nbox, nzero))), dim3(kBlock), 0, s,
+                       bbox, nbox, bad, zero64, nzero);
   if (!nblocks) return;
 #define RTG_STAGE(DD)                                                                         \
   hipLaunchKernelGGL(k_stage_d<DD>, dim3(nblocks), dim3(kBlock), 0, s, inst, m, npts, soa, aos, \
@@ -3335,8 +3337,9 @@ void launch_stage(const InstDesc* inst, uint32_t m, uint32_t nblocks, int d, int
                          bad, part, rec, rs);
   }
 #undef RTG_STAGE
-  // blocks per instance: about 64 per-block boxes each, at most kBboxBlocks
-  uint32_t gy = (uint32_t)std::min<uint64_t>(kBboxBlocks, (nblocks / m + 63) / 64);
+  // blocks per instance: about 256 per-block boxes each (four per lane), at
+  // most kBboxBlocks
+  uint32_t gy = (uint32_t)std::min<uint64_t>(kBboxBlocks, (nblocks / m + 255) / 256);
   if (gy < 1) gy = 1;
   hipLaunchKernelGGL(k_bbox_reduce, dim3(m, gy), dim3(kBlock), 0, s, inst, d, part, bbox);
 }
